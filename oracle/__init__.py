@@ -1,0 +1,18 @@
+"""CPU oracle for the DDA hot path -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously-correct double-precision implementation of what the
+GPU library computes: lattice sites, frames, incident field, polarizabilities,
+the dense interaction matrix (LU solve), a direct O(N^2) matvec (C + OpenMP)
+inside the oracle's own BiCGstab, cross sections, scattering amplitudes,
+Mueller matrix, angular quadrature, and Mie theory for spheres.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product (``paper_1002_1505_amd``)
+never imports it, and it never imports the product.
+
+Functions whose parity is unpinned (no test fixes them against the paper or
+mathematics independent of the oracle): the numerical values of the LDR
+coefficients b1, b2, b3 (recalled from Draine & Goodman 1993, not printed in
+the guide).  Everything else is pinned by ``tests/test_oracle_*.py``.
+"""
+from . import dda, mie, scatter  # noqa: F401

@@ -1,0 +1,392 @@
+"""CPU oracle for the discrete dipole approximation (test infrastructure only).
+
+Plain, slow, double-precision reference for everything the GPU library
+computes.  It shares no code with the GPU path: only ``tests/``, the smoke
+check and the benchmark's CPU-baseline leg may import it.
+
+The DDSCAT 7.1 guide states the system to solve (section "Choice of Iterative
+Algorithm", eq. AP=E), the target description, orientation and polarization
+conventions, and the scattering-amplitude and Mueller-matrix relations; it
+cites but does not print the interaction tensor, the polarizabilities and the
+cross-section sums.  For those the oracle writes out the standard definitions
+from the cited literature (Draine 1988; Draine & Goodman 1993), and says so
+at each function.
+
+Units: lattice spacing d = 1, incident amplitude |E0| = 1, Gaussian units,
+time dependence exp(-i omega t).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+# Lattice-dispersion-relation coefficients of Draine & Goodman (1993), the
+# reference the guide cites for the LATTDR polarizability (section "Dipole
+# Polarizabilities").  The guide does not print them: parity unpinned.
+LDR_B1 = -1.8915316
+LDR_B2 = 0.1648469
+LDR_B3 = -1.7700004
+
+ALPHA_CM = "cm"        # Clausius-Mossotti, no radiative reaction
+ALPHA_CM_RR = "cm_rr"  # Clausius-Mossotti with the radiative-reaction term
+ALPHA_LDR = "ldr"      # lattice dispersion relation (LATTDR)
+
+
+# ---------------------------------------------------------------------------
+# Target: occupied lattice sites
+# ---------------------------------------------------------------------------
+
+def sites_from_occupancy(occ: np.ndarray, origin=None):
+    """Occupied sites of an occupancy grid (shape (n3, n2, n1), x fastest).
+
+    Returns (r, comp, idx): r (N, 3) float64 site coordinates relative to the
+    target-frame origin, comp (N,) int composition ids (>= 1), idx (N, 3) int
+    lattice indices (ix, iy, iz).  Sites are listed in increasing linear box
+    index ix + n1 (iy + n2 iz).  The origin defaults to the centroid of the
+    occupied sites (the guide's ELLIPSOID entry puts the target-frame origin
+    at the centroid).
+    """
+    occ = np.asarray(occ)
+    iz, iy, ix = np.nonzero(occ)  # C order => sorted by linear index
+    idx = np.stack([ix, iy, iz], axis=1).astype(np.int64)
+    comp = occ[iz, iy, ix].astype(np.int64)
+    if origin is None:
+        origin = idx.mean(axis=0) if len(idx) else np.zeros(3)
+    r = idx.astype(np.float64) - np.asarray(origin, dtype=np.float64)[None, :]
+    return r, comp, idx
+
+
+def effective_radius(n_dipoles: int) -> float:
+    """a_eff = (3 V / 4 pi)^(1/3) with V = N d^3 (section "Applicability of the DDA")."""
+    return (3.0 * n_dipoles / (4.0 * np.pi)) ** (1.0 / 3.0)
+
+
+# ---------------------------------------------------------------------------
+# Frames (section "Target Orientation")
+# ---------------------------------------------------------------------------
+
+def lab_axes_in_target_frame(beta, theta, phi, a1=(1.0, 0.0, 0.0), a2=(0.0, 1.0, 0.0)):
+    """Target-frame components of the lab axes x_LF, y_LF, z_LF.
+
+    Follows the expansion of x_LF, y_LF, z_LF over the target axes a1, a2,
+    a3 = a1 x a2 given in "Orientation of the Target in the Lab Frame".
+    Angles in radians.  Returns a (3, 3) array whose rows are x_LF, y_LF, z_LF.
+    """
+    a1 = np.asarray(a1, dtype=np.float64)
+    a2 = np.asarray(a2, dtype=np.float64)
+    a1 = a1 / np.linalg.norm(a1)
+    a2 = a2 / np.linalg.norm(a2)
+    a3 = np.cross(a1, a2)
+    cb, sb = np.cos(beta), np.sin(beta)
+    ct, st = np.cos(theta), np.sin(theta)
+    cp, sp = np.cos(phi), np.sin(phi)
+    xl = a1 * ct - a2 * st * cb + a3 * st * sb
+    yl = a1 * st * cp + a2 * (ct * cb * cp - sb * sp) - a3 * (ct * sb * cp + cb * sp)
+    zl = a1 * st * sp + a2 * (ct * cb * sp + sb * cp) - a3 * (ct * sb * sp - cb * cp)
+    return np.stack([xl, yl, zl])
+
+
+def target_axes_in_lab_frame(beta, theta, phi):
+    """Lab-frame components of a1, a2, a3 (same section, first set of equations)."""
+    cb, sb = np.cos(beta), np.sin(beta)
+    ct, st = np.cos(theta), np.sin(theta)
+    cp, sp = np.cos(phi), np.sin(phi)
+    a1 = np.array([ct, st * cp, st * sp])
+    a2 = np.array([-st * cb, ct * cb * cp - sb * sp, ct * cb * sp + sb * cp])
+    a3 = np.array([st * sb, -(ct * sb * cp + cb * sp), -(ct * sb * sp - cb * cp)])
+    return np.stack([a1, a2, a3])
+
+
+def incident_polarizations(e01_lab=(0, 1, 0)):
+    """Normalized e01 and e02 = x_LF x conj(e01), lab-frame components.
+
+    Section "Incident Polarization State": the user's e01 is normalized and
+    the second state is built as x_LF cross e01*.
+    """
+    e01 = np.asarray(e01_lab, dtype=np.complex128)
+    e01 = e01 / np.sqrt(np.vdot(e01, e01).real)
+    xhat = np.array([1.0, 0.0, 0.0], dtype=np.complex128)
+    e02 = np.cross(xhat, np.conj(e01))
+    return e01, e02
+
+
+def waves_for_orientation(beta, theta, phi, e01_lab=(0, 1, 0), a1=(1, 0, 0), a2=(0, 1, 0)):
+    """Target-frame incidence direction and the two polarization vectors.
+
+    Returns (khat_tf (3,), [e1_tf, e2_tf] complex (2, 3), lab_axes (3, 3)).
+    """
+    L = lab_axes_in_target_frame(beta, theta, phi, a1, a2)
+    e01, e02 = incident_polarizations(e01_lab)
+    khat = L[0].copy()
+    e1 = e01[0] * L[0] + e01[1] * L[1] + e01[2] * L[2]
+    e2 = e02[0] * L[0] + e02[1] * L[1] + e02[2] * L[2]
+    return khat, np.stack([e1, e2]), L
+
+
+# ---------------------------------------------------------------------------
+# Incident field and polarizability
+# ---------------------------------------------------------------------------
+
+def incident_field(r, k, khat, e):
+    """E_j = e exp(i k khat . r_j) at every site; (N, 3) complex."""
+    ph = np.exp(1j * k * (r @ np.asarray(khat, dtype=np.float64)))
+    return ph[:, None] * np.asarray(e, dtype=np.complex128)[None, :]
+
+
+def clausius_mossotti(m):
+    """alpha_CM = (3 / 4 pi) (eps - 1) / (eps + 2), eps = m^2, d = 1."""
+    eps = np.asarray(m, dtype=np.complex128) ** 2
+    return (3.0 / (4.0 * np.pi)) * (eps - 1.0) / (eps + 2.0)
+
+
+def inverse_polarizability(m, k, kind=ALPHA_LDR, khat=None, e=None):
+    """1/alpha for refractive index m (per composition) at wavenumber k (d = 1).
+
+    CM:    1/alpha_CM.
+    CM_RR: 1/alpha_CM - (2/3) i k^3 (radiative reaction).
+    LDR:   1/alpha_CM + (b1 + eps b2 + eps b3 S) k^2 - (2/3) i k^3, with
+           S = sum_j (khat_j e_j)^2 (Draine & Goodman 1993); for complex e the
+           reading S = sum_j khat_j^2 |e_j|^2 is taken.
+    """
+    m = np.asarray(m, dtype=np.complex128)
+    eps = m ** 2
+    inv = 1.0 / clausius_mossotti(m)
+    if kind == ALPHA_CM:
+        return inv
+    if kind == ALPHA_CM_RR:
+        return inv - (2.0 / 3.0) * 1j * k ** 3
+    if kind == ALPHA_LDR:
+        kh = np.asarray(khat, dtype=np.float64)
+        ev = np.asarray(e, dtype=np.complex128)
+        S = float(np.sum(kh ** 2 * np.abs(ev) ** 2))
+        return inv + (LDR_B1 + eps * LDR_B2 + eps * LDR_B3 * S) * k ** 2 - (2.0 / 3.0) * 1j * k ** 3
+    raise ValueError(kind)
+
+
+def site_inverse_polarizability(comp, m_list, k, kind=ALPHA_LDR, khat=None, e=None):
+    """Per-site 1/alpha (N,) from composition ids (1-based) and m per composition."""
+    table = np.array([inverse_polarizability(mm, k, kind, khat, e) for mm in m_list])
+    return table[np.asarray(comp) - 1]
+
+
+# ---------------------------------------------------------------------------
+# Interaction matrix (dense) and its action
+# ---------------------------------------------------------------------------
+
+def interaction_block(rvec, k):
+    """A(r) for one nonzero separation r = r_j - r_l (3-vector): the 3x3 block
+
+        exp(i k r)/r [ k^2 (n n - I) + (i k r - 1)/r^2 (3 n n - I) ],
+
+    i.e. minus the dipole field tensor (Draine 1988; the guide cites it in
+    its introduction and in "Choice of Iterative Algorithm")."""
+    rr = float(np.sqrt(np.dot(rvec, rvec)))
+    n = np.asarray(rvec, dtype=np.float64) / rr
+    nn = np.outer(n, n)
+    I3 = np.eye(3)
+    return np.exp(1j * k * rr) / rr * (k * k * (nn - I3) + (1j * k * rr - 1.0) / rr ** 2 * (3.0 * nn - I3))
+
+
+def dense_matrix(r, k, ainv):
+    """The 3N x 3N matrix A of eq. AP=E, site-major (row 3 j + a)."""
+    r = np.asarray(r, dtype=np.float64)
+    n = len(r)
+    A = np.zeros((3 * n, 3 * n), dtype=np.complex128)
+    d = r[:, None, :] - r[None, :, :]
+    rr = np.sqrt((d ** 2).sum(-1))
+    np.fill_diagonal(rr, 1.0)
+    nv = d / rr[..., None]
+    ph = np.exp(1j * k * rr) / rr
+    c1 = k * k
+    c2 = (1j * k * rr - 1.0) / rr ** 2
+    for a in range(3):
+        for b in range(3):
+            nn = nv[..., a] * nv[..., b]
+            delta = 1.0 if a == b else 0.0
+            blk = ph * (c1 * (nn - delta) + c2 * (3.0 * nn - delta))
+            np.fill_diagonal(blk, 0.0)
+            A[a::3, b::3] = blk
+    idx = np.arange(n)
+    for a in range(3):
+        A[3 * idx + a, 3 * idx + a] = ainv
+    return A
+
+
+def solve_dense(r, k, ainv, E):
+    """P from LAPACK's LU solve of the dense system; E, P are (N, 3)."""
+    A = dense_matrix(r, k, ainv)
+    P = np.linalg.solve(A, np.asarray(E, dtype=np.complex128).reshape(-1))
+    return P.reshape(-1, 3)
+
+
+_LIB = None
+
+
+def _direct_lib():
+    global _LIB
+    if _LIB is None:
+        from . import build as _b
+
+        path = _b.LIB
+        if not os.path.exists(path):
+            _b.build()
+        lib = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        lib.oracle_matvec.argtypes = [ctypes.c_int64, P, ctypes.c_double, P, P, P]
+        lib.oracle_matvec.restype = None
+        lib.oracle_matvec_rows.argtypes = [ctypes.c_int64, P, ctypes.c_double, P, P,
+                                           ctypes.c_int64, P, P]
+        lib.oracle_matvec_rows.restype = None
+        _LIB = lib
+    return _LIB
+
+
+def matvec_direct(r, k, ainv, x):
+    """y = A x by the direct O(N^2) pair sum (C + OpenMP); x, y are (N, 3)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    ainv = np.ascontiguousarray(np.broadcast_to(ainv, (len(r),)), dtype=np.complex128)
+    x = np.ascontiguousarray(x, dtype=np.complex128).reshape(len(r), 3)
+    y = np.empty_like(x)
+    _direct_lib().oracle_matvec(len(r), r.ctypes.data, float(k), ainv.ctypes.data,
+                                x.ctypes.data, y.ctypes.data)
+    return y
+
+
+def matvec_rows(r, k, ainv, x, rows):
+    """(A x) at the listed sites only: (len(rows), 3)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    ainv = np.ascontiguousarray(np.broadcast_to(ainv, (len(r),)), dtype=np.complex128)
+    x = np.ascontiguousarray(x, dtype=np.complex128).reshape(len(r), 3)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    y = np.empty((len(rows), 3), dtype=np.complex128)
+    _direct_lib().oracle_matvec_rows(len(r), r.ctypes.data, float(k), ainv.ctypes.data,
+                                     x.ctypes.data, len(rows), rows.ctypes.data, y.ctypes.data)
+    return y
+
+
+# ---------------------------------------------------------------------------
+# Iterative solve (the oracle's own BiCGstab, van der Vorst 1992)
+# ---------------------------------------------------------------------------
+
+def bicgstab(matvec, b, x0=None, tol=1e-10, max_iter=10000):
+    """Unpreconditioned BiCGstab for a general complex system A x = b.
+
+    Stops when ||b - A x|| / ||b|| <= tol (residual recomputed at the end).
+    Returns (x, info) with info = {iters, matvecs, rel_resid}.
+    """
+    b = np.asarray(b, dtype=np.complex128).reshape(-1)
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.complex128).reshape(-1).copy()
+    nb = np.linalg.norm(b)
+    if nb == 0:
+        return x, {"iters": 0, "matvecs": 0, "rel_resid": 0.0}
+    r = b - matvec(x)
+    nmv = 1
+    rhat = r.copy()
+    rho_old = alpha = omega = 1.0 + 0j
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    it = 0
+    while np.linalg.norm(r) / nb > tol and it < max_iter:
+        rho = np.vdot(rhat, r)
+        if it == 0:
+            p = r.copy()
+        else:
+            beta = (rho / rho_old) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+        v = matvec(p)
+        alpha = rho / np.vdot(rhat, v)
+        s = r - alpha * v
+        t = matvec(s)
+        nmv += 2
+        tt = np.vdot(t, t).real
+        omega = np.vdot(t, s) / tt if tt > 0 else 0.0
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rho_old = rho
+        it += 1
+    r_true = b - matvec(x)
+    nmv += 1
+    return x, {"iters": it, "matvecs": nmv, "rel_resid": float(np.linalg.norm(r_true) / nb)}
+
+
+def solve_iterative(r, k, ainv, E, tol=1e-10, x0=None, max_iter=10000):
+    """P from BiCGstab over the direct matvec; E, P are (N, 3)."""
+    n = len(r)
+    mv = lambda v: matvec_direct(r, k, ainv, v.reshape(n, 3)).reshape(-1)
+    x, info = bicgstab(mv, np.asarray(E).reshape(-1), None if x0 is None else np.asarray(x0).reshape(-1),
+                       tol=tol, max_iter=max_iter)
+    return x.reshape(n, 3), info
+
+
+def residual_norms(r, k, ainv, E, P):
+    """(||E - A P|| / ||E||, the guide's eq. err_tol value ||A^H A P - A^H E|| / ||A^H E||).
+
+    A^H v is evaluated as conj(A conj(v)), valid because A is symmetric.
+    """
+    E = np.asarray(E, dtype=np.complex128)
+    AP = matvec_direct(r, k, ainv, P)
+    rvec = E - AP
+    rel = np.linalg.norm(rvec) / np.linalg.norm(E)
+    AH = lambda v: np.conj(matvec_direct(r, k, ainv, np.conj(v)))
+    num = AH(rvec)
+    den = AH(E)
+    return float(rel), float(np.linalg.norm(num) / np.linalg.norm(den))
+
+
+# ---------------------------------------------------------------------------
+# Cross sections (Draine 1988 sums; Q = C / (pi a_eff^2), section
+# "What Does It Calculate?")
+# ---------------------------------------------------------------------------
+
+def cross_sections(k, E, P, ainv, n_dipoles=None):
+    """(Q_ext, Q_abs, Q_sca) with Q_sca = Q_ext - Q_abs.
+
+    C_ext = 4 pi k sum_j Im(E_j^* . P_j)
+    C_abs = 4 pi k sum_j [ Im(P_j . conj(1/alpha_j) P_j^*) - (2/3) k^3 |P_j|^2 ]
+    """
+    E = np.asarray(E, dtype=np.complex128)
+    P = np.asarray(P, dtype=np.complex128)
+    n = len(P) if n_dipoles is None else n_dipoles
+    cext = 4.0 * np.pi * k * np.sum(np.imag(np.conj(E) * P))
+    p2 = np.sum(np.abs(P) ** 2, axis=1)
+    cabs = 4.0 * np.pi * k * np.sum(np.imag(np.conj(ainv)) * p2 - (2.0 / 3.0) * k ** 3 * p2)
+    area = np.pi * effective_radius(n) ** 2
+    qext, qabs = cext / area, cabs / area
+    return float(qext), float(qabs), float(qext - qabs)
+
+
+def scattering_double_sum(r, k, P):
+    """C_sca / (pi a_eff^2) from the exact double sum over site pairs,
+
+        C_sca = 4 pi k sum_j sum_l P_j^H Im[G(r_j - r_l)] P_l,
+
+    with G = -A off the diagonal and Im G(0) = (2/3) k^3 I.  Equals
+    k^4 times the integral of |sum_j (P_j - n (n . P_j)) exp(-i k n . r_j)|^2
+    over directions; an identity only for a solution of A P = E when
+    compared with Q_ext - Q_abs (optical theorem)."""
+    r = np.asarray(r, dtype=np.float64)
+    P = np.asarray(P, dtype=np.complex128)
+    n = len(r)
+    total = (2.0 / 3.0) * k ** 3 * np.sum(np.abs(P) ** 2)
+    for j in range(n):
+        d = r[j][None, :] - r
+        rr = np.sqrt((d ** 2).sum(-1))
+        mask = np.arange(n) != j
+        d, rr, Pl = d[mask], rr[mask], P[mask]
+        nv = d / rr[:, None]
+        ph = np.exp(1j * k * rr) / rr
+        nP = np.sum(nv * Pl, axis=1)
+        # G P_l = -(A P_l) = ph [ k^2 (P - n (n.P)) + (1 - ikr)/r^2 (3 n (n.P) - P) ]
+        GP = ph[:, None] * (k * k * (Pl - nv * nP[:, None])
+                            + ((1.0 - 1j * k * rr) / rr ** 2)[:, None] * (3.0 * nv * nP[:, None] - Pl))
+        # P_j^H Im[G] P_l with Im taken elementwise: Im G is real symmetric, so
+        # sum_l P_j^H ImG P_l = Re over the pair sum of conj(P_j) . ImG P_l after
+        # symmetrisation; compute Im G P_l as (G P_l - conj(G) P_l)/(2 i).
+        GcP = np.conj(ph)[:, None] * (k * k * (Pl - nv * nP[:, None])
+                                      + ((1.0 + 1j * k * rr) / rr ** 2)[:, None] * (3.0 * nv * nP[:, None] - Pl))
+        ImGP = (GP - GcP) / 2j
+        total += np.real(np.sum(np.conj(P[j])[None, :] * ImGP))
+    csca = 4.0 * np.pi * k * total
+    return float(csca / (np.pi * effective_radius(n) ** 2))
