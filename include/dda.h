@@ -1,0 +1,235 @@
+/*
+ * dda.h -- C ABI of the MI355X (gfx950) discrete-dipole-approximation solver.
+ *
+ * The library solves A P = E for the dipole polarizations P of a target made
+ * of polarizable points on a cubic lattice (DDSCAT 7.1 User Guide, section
+ * "Choice of Iterative Algorithm", eq. AP=E), with the off-diagonal part of A
+ * applied as a convolution by FFT on a doubled grid, a complex-symmetric
+ * BiCGstab solver, and the cross-section and scattering-amplitude reductions.
+ *
+ * Conventions shared by every call
+ *  - Units: lattice spacing d = 1; incident amplitude |E0| = 1; Gaussian
+ *    units; time dependence exp(-i omega t).  Wavenumbers are k d.
+ *  - Complex numbers are interleaved (re, im) doubles unless stated.
+ *  - Per-site vectors (P, E) cross the ABI as [nrhs][N][3] complex128:
+ *    right-hand side slowest, then site, then Cartesian component, with the
+ *    sites in the order of increasing linear box index ix + n1 (iy + n2 iz)
+ *    of the occupancy grid passed to dda_set_target / dda_add_target.  When
+ *    the right-hand sides of one call use different targets, their rows are
+ *    concatenated in call order, each with its own target's N.
+ *  - Pointers are host pointers unless the call's flags contain
+ *    DDA_DEVICE_PTRS, in which case they are device pointers valid on the
+ *    context's device, ordered on the context's stream.
+ *  - Inputs are borrowed for the duration of the call only; outputs are
+ *    written into caller-owned buffers.  The context owns all device memory
+ *    it allocates and frees it in dda_destroy.
+ *  - Return value: 0 on success, a negative dda_status on error (outputs
+ *    unspecified, context still usable unless it is DDA_ERR_HIP), a positive
+ *    value for warnings that come with valid outputs.  The text of the last
+ *    error or warning is available from dda_last_error.  No C++ exception
+ *    crosses the ABI.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef DDA_H
+#define DDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dda_status;
+
+enum {
+    DDA_OK = 0,
+    DDA_ERR_INVALID_ARG = -1,
+    DDA_ERR_OOM = -2,
+    DDA_ERR_HIP = -3,
+    DDA_ERR_STATE = -4,            /* call out of order (e.g. solve before set_target) */
+    DDA_ERR_UNSUPPORTED_DIMS = -5, /* box size the FFT cannot factor into 2, 3, 5 */
+    DDA_ERR_NO_DEVICE = -6,
+    DDA_ERR_IO = -7,
+    DDA_WARN_NOT_CONVERGED = 1,    /* some right-hand side hit max_iter */
+    DDA_WARN_MKD_GE_1 = 2          /* |m| k d >= 1: outside the validity range of the DDA */
+};
+
+/* Polarizability prescriptions (guide, section "Dipole Polarizabilities"). */
+enum {
+    DDA_ALPHA_CM = 0,     /* Clausius-Mossotti (3/4pi)(eps-1)/(eps+2), no radiative reaction */
+    DDA_ALPHA_CM_RR = 1,  /* Clausius-Mossotti with radiative reaction -(2/3) i k^3 in 1/alpha */
+    DDA_ALPHA_LDR = 2     /* lattice dispersion relation of Draine & Goodman 1993 (LATTDR) */
+};
+
+/* Arithmetic precision of a matvec or of the Green's-tensor spectrum. */
+enum { DDA_FP64 = 1, DDA_FP32 = 2 };
+
+/* Solve precision modes. */
+enum {
+    DDA_SOLVE_FP64 = 0,         /* FP64 vectors, FP64 matvec, FP64 residual check */
+    DDA_SOLVE_FP32_REFINE = 1   /* FP32 inner BiCGstab on FP32 matvec, FP64 residual + refinement */
+};
+
+/* Initial guess. */
+enum {
+    DDA_GUESS_ZERO = 0,   /* P0 = 0 (the guide's default) */
+    DDA_GUESS_USER = 1,   /* P0 from the p0 argument */
+    DDA_GUESS_PREV = 2,   /* P0 = this context's previous solution in the same rhs slot */
+    DDA_GUESS_NN = 3      /* P0 from the attached learned-guess network */
+};
+
+/* Flags. */
+enum {
+    DDA_DEVICE_PTRS = 1u << 0,  /* vector arguments are device pointers */
+    DDA_NO_GRAPH = 1u << 1,     /* run the Krylov loop eagerly instead of replaying a HIP graph */
+    DDA_NO_FALLBACK = 1u << 2   /* keep a supplied guess even if its residual exceeds ||E|| */
+};
+
+typedef struct dda_ctx dda_ctx;
+
+/* One incident wave, target-frame components (guide, section "Target
+ * Orientation": the lab axis x_LF is the incidence direction). */
+typedef struct {
+    double khat[3];   /* unit propagation direction */
+    double e0[6];     /* polarization vector, (re, im) x 3, |e0| = 1, khat . e0 = 0 */
+    int32_t target;   /* id returned by dda_set_target (0) or dda_add_target */
+    int32_t pad_;
+} dda_wave;
+
+typedef struct {
+    double tol;           /* stop when ||E - A P||_2 / ||E||_2 <= tol (FP64); 1e-5 if <= 0 */
+    int32_t max_iter;     /* BiCGstab iterations per right-hand side (all inner steps); 1000 if <= 0 */
+    int32_t guess;        /* DDA_GUESS_* */
+    int32_t prec;         /* DDA_SOLVE_* */
+    uint32_t flags;       /* DDA_DEVICE_PTRS | DDA_NO_GRAPH | DDA_NO_FALLBACK */
+    int32_t graph_iters;  /* BiCGstab iterations per graph replay; 0 = autotuned/default */
+    int32_t reserved[3];
+} dda_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* BiCGstab iterations taken */
+    int32_t matvecs;      /* FFT matvecs (FP32 and FP64) */
+    int32_t outer;        /* FP64 residual evaluations */
+    int32_t status;       /* 0 converged, DDA_WARN_NOT_CONVERGED otherwise */
+    double rel_resid;     /* final ||E - A P|| / ||E|| with the FP64 matvec */
+    double guess_resid;   /* ||E - A P0|| / ||E|| of the guess actually used */
+} dda_solve_stats;
+
+/* Library version string. */
+const char* dda_version(void);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * order all work on, or NULL to create a private stream.  */
+dda_status dda_create(dda_ctx** out, int32_t device, void* hip_stream);
+dda_status dda_destroy(dda_ctx* ctx);
+const char* dda_last_error(const dda_ctx* ctx);
+
+/*
+ * Define the target (replacing all previous targets; it gets id 0).
+ *   dims[3]   box size (n1, n2, n3); each must factor into 2, 3 and 5 and be >= 2
+ *   occ       n1*n2*n3 bytes, x fastest: 0 = vacuum, c >= 1 = composition c
+ *             (guide, section "Target Generation", FROM_FILE: occupied sites
+ *             and their composition)
+ *   ncomp     number of compositions (max occupancy value)
+ *   m         2*ncomp doubles: complex refractive index per composition
+ *   kd        k d (wavenumber times lattice spacing)
+ *   alpha_kind DDA_ALPHA_*
+ *   origin    3 doubles, target-frame origin in lattice units relative to
+ *             site (0,0,0), or NULL for the centroid of the occupied sites
+ * Returns DDA_WARN_MKD_GE_1 when |m| k d >= 1 for some composition (guide,
+ * section "Applicability of the DDA").
+ */
+dda_status dda_set_target(dda_ctx* ctx, const int32_t dims[3], const uint8_t* occ, int32_t ncomp,
+                          const double* m, double kd, int32_t alpha_kind, const double* origin);
+/* Append another target for batched solves; *id_out receives its id. */
+dda_status dda_add_target(dda_ctx* ctx, const int32_t dims[3], const uint8_t* occ, int32_t ncomp,
+                          const double* m, double kd, int32_t alpha_kind, const double* origin,
+                          int32_t* id_out);
+/* Number of occupied sites N and the effective radius a_eff = (3N/4pi)^(1/3)
+ * (guide, section "Applicability of the DDA") of a target. */
+dda_status dda_target_info(const dda_ctx* ctx, int32_t target, int64_t* n_sites, double* aeff);
+
+/* Build the FFT of the Green's tensor on the doubled grid for every target
+ * whose spectrum is missing or stale.  Always computed in FP64; `prec` selects
+ * which copies are kept for the matvec (DDA_FP32 | DDA_FP64). */
+dda_status dda_build_green_fft(dda_ctx* ctx, uint32_t prec);
+
+/*
+ * Solve A P = E_inc for nrhs incident waves.  E_inc,j = e0 exp(i k khat . r_j)
+ * is generated on the device.  p0 ([nrhs][N][3] complex128) is read only for
+ * DDA_GUESS_USER.  p_out ([nrhs][N][3] complex128) receives P; it may be NULL
+ * to keep the solution on the device only (for cross sections, amplitudes or
+ * DDA_GUESS_PREV).  stats (nrhs entries) may be NULL.  The waves of one call
+ * may reference different targets (batched multi-target solve).
+ * Returns DDA_WARN_NOT_CONVERGED if any right-hand side missed tol.
+ */
+dda_status dda_solve(dda_ctx* ctx, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* opts,
+                     const void* p0, void* p_out, dda_solve_stats* stats);
+
+/* y = A x for nrhs vectors on target `target`.  ainv holds 1/alpha per
+ * (rhs, composition) as 2*nrhs*ncomp doubles, or is NULL to use the
+ * polarizability of the target's prescription with the wave khat=(1,0,0),
+ * e0=(0,1,0).  x, y: [nrhs][N][3] complex128. `prec` is DDA_FP32 or DDA_FP64. */
+dda_status dda_matvec(dda_ctx* ctx, int32_t target, int32_t nrhs, const double* ainv,
+                      const void* x, void* y, uint32_t prec, uint32_t flags);
+
+/* 1/alpha of every composition of a target for a wave (host arithmetic);
+ * out: 2*ncomp doubles. */
+dda_status dda_inverse_polarizability(const dda_ctx* ctx, int32_t target, const dda_wave* wave,
+                                      double* out);
+
+/* Efficiencies of the last solve: q is nrhs x {Q_ext, Q_abs, Q_sca} with
+ * C_ext = 4 pi k sum_j Im(E_j^* . P_j),
+ * C_abs = 4 pi k sum_j [Im(P_j . (1/alpha_j)^* P_j^*) - (2/3) k^3 |P_j|^2],
+ * Q_sca = Q_ext - Q_abs, Q = C / (pi a_eff^2) (guide, section "What Does It
+ * Calculate?"; sums from Draine 1988).  FP64 reductions on the device. */
+dda_status dda_cross_sections(dda_ctx* ctx, int32_t nrhs, double* q);
+
+/* Scattering amplitudes of the last solve:
+ *   f[rhs][dir][m] = k^3 e_m . sum_j P_j exp(-i k n_dir . r_j),  m = 0, 1,
+ * with n (ndir x 3 doubles) and the two scattered polarization vectors e_1,
+ * e_2 (ndir x 6 doubles: e_1 then e_2) given in the target frame (guide,
+ * section "Scattering by Finite Targets: The Mueller Matrix", eq. f_ml_def).
+ * f: nrhs*ndir*2 complex128 (interleaved). */
+dda_status dda_amplitudes(dda_ctx* ctx, int32_t nrhs, int32_t ndir, const double* n_tf,
+                          const double* e_tf, double* f);
+
+/* Amplitude matrix S_1..S_4 and the 4x4 Mueller matrix from the amplitudes
+ * of two orthogonal incident polarizations (guide, eqs. S_1_relto_f21andf22
+ * and the bilinears of "Relation Between Stokes Parameters of Incident and
+ * Scattered Radiation").  f: ndir x 2 (m) x 2 (l) complex128 ordered
+ * [dir][m][l]; phi: ndir scattering-plane angles; e01, e02: lab-frame
+ * incident polarization vectors (6 doubles each).  S: ndir x 4 complex128
+ * (may be NULL); mueller: ndir x 16 doubles row-major (may be NULL). */
+dda_status dda_mueller(int32_t ndir, const double* f, const double* phi, const double* e01,
+                       const double* e02, double* S, double* mueller);
+
+/* Lab-frame axes in the target frame for target orientation (beta, Theta,
+ * Phi) in radians and target axes a1, a2 (target frame; NULL for x and y)
+ * (guide, section "Orientation of the Target in the Lab Frame").
+ * out: 9 doubles, rows x_LF, y_LF, z_LF. */
+dda_status dda_lab_frame(double beta, double theta, double phi, const double* a1, const double* a2,
+                         double* out);
+
+/* Choose FFT tile shapes and graph depth for every target by timing
+ * candidates on the device; results are cached in the JSON file named by
+ * `cache_path` (NULL: the DDA_TUNE_CACHE environment variable, else no
+ * file).  `nrhs_hint` is the batch size to tune for. */
+dda_status dda_autotune(dda_ctx* ctx, int32_t nrhs_hint, const char* cache_path);
+
+/* Timing of the last solve: milliseconds in FP32 matvecs, FP64 matvecs,
+ * and the whole call (device events).  Any pointer may be NULL. */
+dda_status dda_last_timing(const dda_ctx* ctx, double* ms_mv32, double* ms_mv64, double* ms_total);
+
+/* Per-pass kernel timing of `reps` FP32 or FP64 matvecs of nrhs vectors on
+ * target `target` with the current tiles: fills ms[3] with the mean duration
+ * of the xy-forward pass, the z pass and the xy-inverse pass (HIP events on
+ * the context stream), and bytes[3] with the algorithmic bytes moved by each
+ * pass per launch.  Either pointer may be NULL. */
+dda_status dda_profile_matvec(dda_ctx* ctx, int32_t target, int32_t nrhs, uint32_t prec, int32_t reps,
+                              double* ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDA_H */

@@ -1,0 +1,241 @@
+"""Python binding of the MI355X DDA solver library (``libdda.so``).
+
+Thin argument marshalling over the C ABI of ``include/dda.h``: every step of
+the solve runs in the library's HIP kernels.  Arrays are numpy arrays on the
+host, or torch CUDA tensors (device pointers) where noted.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (DDA_ALPHA_CM, DDA_ALPHA_CM_RR, DDA_ALPHA_LDR, DDA_DEVICE_PTRS, DDA_FP32, DDA_FP64,  # noqa: F401
+                   DDA_GUESS_NN, DDA_GUESS_PREV, DDA_GUESS_USER, DDA_GUESS_ZERO, DDA_NO_FALLBACK, DDA_NO_GRAPH,
+                   DDA_SOLVE_FP32_REFINE, DDA_SOLVE_FP64, DDA_WARN_MKD_GE_1, DDA_WARN_NOT_CONVERGED)
+
+__all__ = ["Context", "DDAError", "lab_frame", "mueller", "load_library"]
+
+
+class DDAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dda status {status}: {msg}")
+        self.status = status
+
+
+def load_library():
+    return L.load()
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _check(ctx, status):
+    if status < 0:
+        lib = L.load()
+        msg = lib.dda_last_error(ctx).decode() if ctx else "error"
+        raise DDAError(status, msg)
+    return status
+
+
+def _waves(khat, e0, targets):
+    khat = np.asarray(khat, dtype=np.float64).reshape(-1, 3)
+    e0 = np.asarray(e0, dtype=np.complex128).reshape(-1, 3)
+    n = len(khat)
+    if targets is None:
+        targets = np.zeros(n, dtype=np.int32)
+    targets = np.broadcast_to(np.asarray(targets, dtype=np.int32), (n,))
+    arr = (L.dda_wave * n)()
+    for i in range(n):
+        for j in range(3):
+            arr[i].khat[j] = khat[i, j]
+            arr[i].e0[2 * j] = e0[i, j].real
+            arr[i].e0[2 * j + 1] = e0[i, j].imag
+        arr[i].target = int(targets[i])
+    return arr, n
+
+
+class Context:
+    """A solver context on one GPU (dda_create / dda_destroy)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.lib = L.load()
+        h = C.c_void_p()
+        st = self.lib.dda_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None)
+        if st < 0:
+            raise DDAError(st, "dda_create failed (no HIP device?)")
+        self.h = h
+        self.n_sites = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dda_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_error(self) -> str:
+        return self.lib.dda_last_error(self.h).decode()
+
+    # -- targets ---------------------------------------------------------
+    def _target_args(self, occ, m, kd, alpha_kind, origin):
+        occ = np.ascontiguousarray(occ, dtype=np.uint8)
+        if occ.ndim != 3:
+            raise ValueError("occupancy must be 3-D (n3, n2, n1), x fastest")
+        dims = (C.c_int32 * 3)(occ.shape[2], occ.shape[1], occ.shape[0])
+        mm = np.atleast_1d(np.asarray(m, dtype=np.complex128))
+        marr = np.ascontiguousarray(np.stack([mm.real, mm.imag], axis=1).reshape(-1))
+        org = None if origin is None else np.ascontiguousarray(origin, dtype=np.float64)
+        return occ, dims, mm, marr, org
+
+    def set_target(self, occ, m, kd, alpha_kind=DDA_ALPHA_LDR, origin=None) -> int:
+        occ, dims, mm, marr, org = self._target_args(occ, m, kd, alpha_kind, origin)
+        st = self.lib.dda_set_target(self.h, dims, occ.ctypes.data, len(mm), _dptr(marr), float(kd), int(alpha_kind),
+                                     None if org is None else _dptr(org))
+        _check(self.h, st)
+        self.n_sites = {0: self.target_info(0)[0]}
+        return st
+
+    def add_target(self, occ, m, kd, alpha_kind=DDA_ALPHA_LDR, origin=None) -> int:
+        occ, dims, mm, marr, org = self._target_args(occ, m, kd, alpha_kind, origin)
+        tid = C.c_int32()
+        st = self.lib.dda_add_target(self.h, dims, occ.ctypes.data, len(mm), _dptr(marr), float(kd), int(alpha_kind),
+                                     None if org is None else _dptr(org), C.byref(tid))
+        _check(self.h, st)
+        self.n_sites[tid.value] = self.target_info(tid.value)[0]
+        return tid.value
+
+    def target_info(self, target: int = 0):
+        n = C.c_int64()
+        a = C.c_double()
+        _check(self.h, self.lib.dda_target_info(self.h, int(target), C.byref(n), C.byref(a)))
+        return int(n.value), float(a.value)
+
+    def build_green_fft(self, prec=DDA_FP32 | DDA_FP64):
+        return _check(self.h, self.lib.dda_build_green_fft(self.h, int(prec)))
+
+    def inverse_polarizability(self, khat, e0, target: int = 0):
+        arr, _ = _waves(khat, e0, [target])
+        n_comp = 256
+        out = np.zeros(2 * n_comp)
+        _check(self.h, self.lib.dda_inverse_polarizability(self.h, int(target), arr, _dptr(out)))
+        return out
+
+    # -- solve -----------------------------------------------------------
+    def solve(self, khat, e0, targets=None, tol=1e-5, max_iter=1000, guess=DDA_GUESS_ZERO,
+              prec=DDA_SOLVE_FP32_REFINE, p0=None, want_p=True, flags=0, graph_iters=0):
+        """Solve A P = E_inc for each wave; returns (P or None, stats list, status).
+
+        P is a list of (N_t, 3) complex128 arrays (one per wave)."""
+        arr, n = _waves(khat, e0, targets)
+        opts = L.dda_solve_opts(tol=tol, max_iter=max_iter, guess=guess, prec=prec, flags=flags,
+                                graph_iters=graph_iters)
+        tg = [arr[i].target for i in range(n)]
+        sizes = [self.n_sites[t] for t in tg]
+        p0buf = None
+        if p0 is not None:
+            p0buf = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.complex128).reshape(-1) for p in p0]))
+        pout = np.zeros(3 * sum(sizes), dtype=np.complex128) if want_p else None
+        stats = (L.dda_solve_stats * n)()
+        st = self.lib.dda_solve(self.h, n, arr, C.byref(opts),
+                                None if p0buf is None else p0buf.ctypes.data,
+                                None if pout is None else pout.ctypes.data, stats)
+        _check(self.h, st)
+        P = None
+        if want_p:
+            P, off = [], 0
+            for s in sizes:
+                P.append(pout[off:off + 3 * s].reshape(s, 3))
+                off += 3 * s
+        sl = [dict(iters=s.iters, matvecs=s.matvecs, outer=s.outer, status=s.status, rel_resid=s.rel_resid,
+                   guess_resid=s.guess_resid) for s in stats]
+        return P, sl, st
+
+    def matvec(self, x, target: int = 0, ainv=None, prec=DDA_FP64):
+        """y = A x for x of shape (nrhs, N, 3) complex128."""
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        if x.ndim == 2:
+            x = x[None]
+        nrhs = x.shape[0]
+        y = np.zeros_like(x)
+        a = None
+        if ainv is not None:
+            a = np.ascontiguousarray(np.asarray(ainv, dtype=np.complex128).reshape(nrhs, -1))
+            a = np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1).reshape(-1))
+        _check(self.h, self.lib.dda_matvec(self.h, int(target), nrhs, None if a is None else _dptr(a),
+                                           x.ctypes.data, y.ctypes.data, int(prec), 0))
+        return y
+
+    def cross_sections(self, nrhs: int):
+        q = np.zeros(3 * nrhs)
+        _check(self.h, self.lib.dda_cross_sections(self.h, int(nrhs), _dptr(q)))
+        return q.reshape(nrhs, 3)
+
+    def amplitudes(self, nrhs: int, n_tf, e_tf):
+        n_tf = np.ascontiguousarray(n_tf, dtype=np.float64).reshape(-1, 3)
+        e_tf = np.ascontiguousarray(e_tf, dtype=np.float64).reshape(-1, 6)
+        ndir = len(n_tf)
+        f = np.zeros(nrhs * ndir * 2 * 2)
+        _check(self.h, self.lib.dda_amplitudes(self.h, int(nrhs), ndir, _dptr(n_tf), _dptr(e_tf), _dptr(f)))
+        f = f.reshape(nrhs, ndir, 2, 2)
+        return f[..., 0] + 1j * f[..., 1]
+
+    def last_timing(self):
+        a, b, t = C.c_double(), C.c_double(), C.c_double()
+        self.lib.dda_last_timing(self.h, C.byref(a), C.byref(b), C.byref(t))
+        return dict(ms_mv32=a.value, ms_mv64=b.value, ms_total=t.value)
+
+    def profile_matvec(self, target=0, nrhs=1, prec=DDA_FP32, reps=10):
+        ms = np.zeros(3)
+        by = np.zeros(3)
+        _check(self.h, self.lib.dda_profile_matvec(self.h, int(target), int(nrhs), int(prec), int(reps), _dptr(ms),
+                                                   _dptr(by)))
+        return ms, by
+
+    def autotune(self, nrhs_hint=2, cache_path=None):
+        return _check(self.h, self.lib.dda_autotune(self.h, int(nrhs_hint),
+                                                    None if cache_path is None else cache_path.encode()))
+
+
+def lab_frame(beta, theta, phi, a1=None, a2=None):
+    lib = L.load()
+    out = np.zeros(9)
+    a1 = None if a1 is None else np.ascontiguousarray(a1, dtype=np.float64)
+    a2 = None if a2 is None else np.ascontiguousarray(a2, dtype=np.float64)
+    st = lib.dda_lab_frame(float(beta), float(theta), float(phi), None if a1 is None else _dptr(a1),
+                           None if a2 is None else _dptr(a2), _dptr(out))
+    if st < 0:
+        raise DDAError(st, "dda_lab_frame")
+    return out.reshape(3, 3)
+
+
+def mueller(f, phi, e01, e02):
+    """S_1..S_4 (ndir, 4) and Mueller (ndir, 4, 4) from f[dir, m, l]."""
+    lib = L.load()
+    f = np.ascontiguousarray(f, dtype=np.complex128)
+    ndir = f.shape[0]
+    fb = np.ascontiguousarray(np.stack([f.real, f.imag], axis=-1).reshape(-1))
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    e1 = np.asarray(e01, dtype=np.complex128)
+    e2 = np.asarray(e02, dtype=np.complex128)
+    e1b = np.ascontiguousarray(np.stack([e1.real, e1.imag], axis=-1).reshape(-1))
+    e2b = np.ascontiguousarray(np.stack([e2.real, e2.imag], axis=-1).reshape(-1))
+    S = np.zeros(ndir * 8)
+    M = np.zeros(ndir * 16)
+    st = lib.dda_mueller(ndir, _dptr(fb), _dptr(ph), _dptr(e1b), _dptr(e2b), _dptr(S), _dptr(M))
+    if st < 0:
+        raise DDAError(st, "dda_mueller")
+    S = S.reshape(ndir, 4, 2)
+    return S[..., 0] + 1j * S[..., 1], M.reshape(ndir, 4, 4)

@@ -1,0 +1,1168 @@
+// Host runtime and C ABI of the DDA solver (see include/dda.h).
+//
+// A context owns the targets (site lists, twiddles, tensor spectra, tuned
+// launch shapes) and the workspace of the last solve.  A solve groups its
+// right-hand sides by target; every kernel launch covers all right-hand sides
+// of a group, and one BiCGstab iteration of all groups is captured in a HIP
+// graph that is replayed several iterations at a time between convergence
+// polls.  FP32_REFINE runs the Krylov iteration on FP32 vectors and the FP32
+// matvec, recomputes the residual b - A x with the FP64 matvec, and refines x
+// in FP64 until the FP64 residual meets the tolerance.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/dda.h"
+#include "dda_internal.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+// Lattice-dispersion-relation coefficients (Draine & Goodman 1993).
+constexpr double LDR_B1 = -1.8915316, LDR_B2 = 0.1648469, LDR_B3 = -1.7700004;
+
+struct DevMem {
+    void* p = nullptr;
+    size_t n = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n && p) return hipSuccess;
+        release();
+        if (!bytes) return hipSuccess;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        n = bytes;
+        return hipSuccess;
+    }
+    template <class U>
+    U* as() const { return reinterpret_cast<U*>(p); }
+};
+
+struct Target {
+    int n[3] = {0, 0, 0};
+    int N = 0, Npad = 0, ncomp = 0;
+    std::vector<cd> m;
+    double kd = 0;
+    int alpha_kind = DDA_ALPHA_LDR;
+    double origin[3] = {0, 0, 0};
+    double aeff = 0;
+    FftPlan plans[3];
+    DevMem d_xyz, d_comp, d_pstart, tw64, tw32, gh64, gh32;
+    bool have64 = false, have32 = false;
+    MvShape sh32{}, sh64{};
+    Geo geo() const {
+        Geo g;
+        g.n1 = n[0];
+        g.n2 = n[1];
+        g.n3 = n[2];
+        g.N = N;
+        g.Npad = Npad;
+        g.ncomp = ncomp;
+        g.plane_start = d_pstart.as<int>();
+        g.site_xyz = d_xyz.as<uint32_t>();
+        g.site_comp = d_comp.as<uint8_t>();
+        return g;
+    }
+    template <class T>
+    Tw<T> tw() const {
+        const DevMem& d = std::is_same<T, double>::value ? tw64 : tw32;
+        const Cx<T>* b = d.as<Cx<T>>();
+        Tw<T> t;
+        t.f1 = b;
+        t.f2 = t.f1 + n[0];
+        t.f3 = t.f2 + n[1];
+        t.h1 = t.f3 + n[2];
+        t.h2 = t.h1 + n[0];
+        t.h3 = t.h2 + n[1];
+        return t;
+    }
+    template <class T>
+    const MvShape& shape() const { return std::is_same<T, double>::value ? sh64 : sh32; }
+    template <class T>
+    const Cx<T>* ghat() const {
+        return std::is_same<T, double>::value ? gh64.as<Cx<T>>() : gh32.as<Cx<T>>();
+    }
+};
+
+// Workspace of the right-hand sides of one solve that share a target.
+struct Group {
+    int tgt = -1, nr = 0, kprec = 0;
+    std::vector<int> idx;  // call-level rhs index of each member
+    DevMem waves, ainv64, ainv32, b64, x64, r64;
+    DevMem kv[7];  // inner Krylov vectors x r rhat p v s t (kprec precision)
+    DevMem slab32, slab64;
+    DevMem state, active, partials, scale, tolrel2, maxit, norms, mask;
+    // host staging buffers of asynchronous uploads (must outlive the copies)
+    std::vector<WaveDev> hw;
+    std::vector<cd> hainv;  // [nr][ncomp]
+    std::vector<Cx<float>> hainv32;
+    std::vector<int> hmask, hmaxit;
+    std::vector<double> hscale, htol2;
+};
+
+}  // namespace
+
+struct dda_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    std::vector<std::unique_ptr<Target>> tg;
+    std::vector<std::unique_ptr<Group>> groups;
+    int last_nrhs = 0;
+    std::vector<int> rhs_group, rhs_slot;
+    bool have_solution = false;
+    // graph cache
+    hipGraphExec_t gexec = nullptr;
+    long long gkey_gen = -1;
+    int gkey_prec = 0, gkey_k = 0;
+    long long ws_gen = 0;
+    // timing
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double ms_mv32 = 0, ms_mv64 = 0, ms_total = 0;
+};
+
+namespace {
+
+dda_status fail(dda_ctx* c, dda_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HCHK(ctx, x)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (x);                                                                         \
+        if (e_ != hipSuccess)                                                                        \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? DDA_ERR_OOM : DDA_ERR_HIP, "%s failed: %s (%s:%d)", \
+                        #x, hipGetErrorString(e_), __FILE__, __LINE__);                              \
+    } while (0)
+
+#define SCHK(x)                              \
+    do {                                     \
+        dda_status s_ = (x);                 \
+        if (s_ < 0) return s_;               \
+    } while (0)
+
+bool factor_plan(int n, FftPlan& p) {
+    p.n = n;
+    p.np = 0;
+    int a = 0, b = 0, c = 0, m = n;
+    while (m % 2 == 0) m /= 2, ++a;
+    while (m % 3 == 0) m /= 3, ++b;
+    while (m % 5 == 0) m /= 5, ++c;
+    if (m != 1 || n < 2) return false;
+    for (int i = 0; i < c; ++i) p.r[p.np++] = 5;
+    for (int i = 0; i < b; ++i) p.r[p.np++] = 3;
+    while (a >= 3 && a != 4) p.r[p.np++] = 8, a -= 3;
+    if (a == 4) p.r[p.np++] = 4, p.r[p.np++] = 4, a = 0;
+    if (a == 2) p.r[p.np++] = 4, a = 0;
+    if (a == 1) p.r[p.np++] = 2, a = 0;
+    return p.np <= 8;
+}
+
+int rmin(const FftPlan& p) {
+    int r = 8;
+    for (int s = 0; s < p.np; ++s) r = std::min(r, p.r[s]);
+    return r;
+}
+int round64(int x) { return std::max(64, (x + 63) / 64 * 64); }
+
+template <class T>
+MvShape default_shape(const Target& t, int tx_pref) {
+    const Geo g = t.geo();
+    MvShape s{};
+    s.lines_tl = 16;
+    s.nth_lines = 256;
+    // z pass
+    int tx = tx_pref;
+    while (tx > 1 && (g.n1 % tx != 0)) tx /= 2;
+    for (;; tx /= 2) {
+        s.tx = tx;
+        const int bz = (g.n3 / rmin(t.plans[2])) * 6 * tx;
+        s.nth_z = std::max(256, round64((bz + 3) / 4));
+        if ((s.nth_z <= 1024 && matvec_shape_ok<T>(g, t.plans, MvShape{0, 64, s.nth_z, tx, 16, 256})) || tx == 1) break;
+    }
+    // planes
+    const int np = g.n1 * g.n2;
+    const int bx = (g.n1 / rmin(t.plans[0])) * g.n2, by = (g.n2 / rmin(t.plans[1])) * g.n1;
+    int nth = std::max({(np + 15) / 16, (bx + 3) / 4, (by + 3) / 4});
+    s.nth_plane = std::max(256, round64(nth));
+    s.fused = 1;
+    if (!matvec_shape_ok<T>(g, t.plans, s)) s.fused = 0;
+    return s;
+}
+
+dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint8_t* occ, int32_t ncomp,
+                        const double* m, double kd, int32_t alpha_kind, const double* origin) {
+    if (!dims || !occ || !m || ncomp < 1 || ncomp > 255)
+        return fail(c, DDA_ERR_INVALID_ARG, "set_target: null pointer or ncomp out of [1,255]");
+    for (int i = 0; i < 3; ++i) {
+        if (dims[i] < 2 || dims[i] > 1023) return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "dims[%d]=%d outside [2,1023]", i, dims[i]);
+        if (!factor_plan(dims[i], t.plans[i]))
+            return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "dims[%d]=%d does not factor into 2, 3 and 5", i, dims[i]);
+    }
+    if (!(kd > 0) || !std::isfinite(kd)) return fail(c, DDA_ERR_INVALID_ARG, "kd must be positive");
+    if (alpha_kind < DDA_ALPHA_CM || alpha_kind > DDA_ALPHA_LDR) return fail(c, DDA_ERR_INVALID_ARG, "bad alpha_kind");
+    const int n1 = dims[0], n2 = dims[1], n3 = dims[2];
+    std::vector<uint32_t> xyz;
+    std::vector<uint8_t> comp;
+    std::vector<int> ps(n3 + 1, 0);
+    double cx = 0, cy = 0, cz = 0;
+    for (int z = 0; z < n3; ++z) {
+        ps[z] = (int)xyz.size();
+        for (int y = 0; y < n2; ++y)
+            for (int x = 0; x < n1; ++x) {
+                const uint8_t o = occ[(size_t)x + (size_t)n1 * (y + (size_t)n2 * z)];
+                if (!o) continue;
+                if (o > ncomp) return fail(c, DDA_ERR_INVALID_ARG, "occupancy value %d exceeds ncomp=%d", o, ncomp);
+                xyz.push_back((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20));
+                comp.push_back((uint8_t)(o - 1));
+                cx += x;
+                cy += y;
+                cz += z;
+            }
+    }
+    ps[n3] = (int)xyz.size();
+    if (xyz.empty()) return fail(c, DDA_ERR_INVALID_ARG, "target has no occupied site");
+    t.n[0] = n1;
+    t.n[1] = n2;
+    t.n[2] = n3;
+    t.N = (int)xyz.size();
+    t.Npad = (t.N + 255) / 256 * 256;
+    t.ncomp = ncomp;
+    t.m.assign(ncomp, cd(0, 0));
+    for (int i = 0; i < ncomp; ++i) t.m[i] = cd(m[2 * i], m[2 * i + 1]);
+    t.kd = kd;
+    t.alpha_kind = alpha_kind;
+    if (origin) {
+        for (int i = 0; i < 3; ++i) t.origin[i] = origin[i];
+    } else {
+        t.origin[0] = cx / t.N;
+        t.origin[1] = cy / t.N;
+        t.origin[2] = cz / t.N;
+    }
+    t.aeff = std::cbrt(3.0 * t.N / (4.0 * PI));
+    HCHK(c, t.d_xyz.ensure(xyz.size() * 4));
+    HCHK(c, t.d_comp.ensure(comp.size()));
+    HCHK(c, t.d_pstart.ensure(ps.size() * 4));
+    HCHK(c, hipMemcpy(t.d_xyz.p, xyz.data(), xyz.size() * 4, hipMemcpyHostToDevice));
+    HCHK(c, hipMemcpy(t.d_comp.p, comp.data(), comp.size(), hipMemcpyHostToDevice));
+    HCHK(c, hipMemcpy(t.d_pstart.p, ps.data(), ps.size() * 4, hipMemcpyHostToDevice));
+    // twiddles: f_i (n_i) then h_i (n_i)
+    std::vector<Cx<double>> tw;
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < t.n[i]; ++k) {
+            const long double a = -2.0L * 3.14159265358979323846264338327950288L * k / t.n[i];
+            tw.push_back(Cx<double>{(double)cosl(a), (double)sinl(a)});
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < t.n[i]; ++k) {
+            const long double a = -2.0L * 3.14159265358979323846264338327950288L * k / (2 * t.n[i]);
+            tw.push_back(Cx<double>{(double)cosl(a), (double)sinl(a)});
+        }
+    std::vector<Cx<float>> tw32(tw.size());
+    for (size_t i = 0; i < tw.size(); ++i) tw32[i] = Cx<float>{(float)tw[i].re, (float)tw[i].im};
+    HCHK(c, t.tw64.ensure(tw.size() * sizeof(Cx<double>)));
+    HCHK(c, t.tw32.ensure(tw32.size() * sizeof(Cx<float>)));
+    HCHK(c, hipMemcpy(t.tw64.p, tw.data(), tw.size() * sizeof(Cx<double>), hipMemcpyHostToDevice));
+    HCHK(c, hipMemcpy(t.tw32.p, tw32.data(), tw32.size() * sizeof(Cx<float>), hipMemcpyHostToDevice));
+    t.have32 = t.have64 = false;
+    t.sh32 = default_shape<float>(t, 16);
+    t.sh64 = default_shape<double>(t, 16);
+    if (!matvec_shape_ok<float>(t.geo(), t.plans, t.sh32) || !matvec_shape_ok<double>(t.geo(), t.plans, t.sh64))
+        return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "no launch shape fits box %dx%dx%d", n1, n2, n3);
+    double mkd = 0;
+    for (auto& mm : t.m) mkd = std::max(mkd, std::abs(mm) * kd);
+    if (mkd >= 1.0) {
+        fail(c, DDA_WARN_MKD_GE_1, "|m| k d = %.4f >= 1: outside the validity range of the DDA", mkd);
+        return DDA_WARN_MKD_GE_1;
+    }
+    return DDA_OK;
+}
+
+// 1/alpha for composition m at k d = kd (d = 1).
+cd inverse_alpha(cd mm, double kd, int kind, const double* khat, const double* e) {
+    const cd eps = mm * mm;
+    const cd acm = (3.0 / (4.0 * PI)) * (eps - 1.0) / (eps + 2.0);
+    cd inv = 1.0 / acm;
+    const cd rr = cd(0, -(2.0 / 3.0) * kd * kd * kd);
+    if (kind == DDA_ALPHA_CM) return inv;
+    if (kind == DDA_ALPHA_CM_RR) return inv + rr;
+    double S = 0;
+    for (int j = 0; j < 3; ++j) S += khat[j] * khat[j] * (e[2 * j] * e[2 * j] + e[2 * j + 1] * e[2 * j + 1]);
+    return inv + (LDR_B1 + eps * LDR_B2 + eps * LDR_B3 * S) * (kd * kd) + rr;
+}
+
+dda_status check_ctx(dda_ctx* c) {
+    if (!c) return DDA_ERR_INVALID_ARG;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return fail(c, DDA_ERR_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+    return DDA_OK;
+}
+
+dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
+    const bool need64 = (prec & DDA_FP64) && !t.have64;
+    const bool need32 = (prec & DDA_FP32) && !t.have32;
+    if (!need64 && !need32) return DDA_OK;
+    const size_t oct = ghat_octant_elems(t.n[0], t.n[1], t.n[2]);
+    HCHK(c, t.gh64.ensure(oct * sizeof(Cx<double>)));
+    if (prec & DDA_FP32 || t.have32) HCHK(c, t.gh32.ensure(oct * sizeof(Cx<float>)));
+    DevMem work;
+    HCHK(c, work.ensure((size_t)48 * t.n[0] * t.n[1] * t.n[2] * sizeof(Cx<double>)));
+    HCHK(c, launch_green(t.geo(), t.tw<double>(), t.plans, t.kd, work.as<Cx<double>>(), t.gh64.as<Cx<double>>(),
+                         t.gh32.p ? t.gh32.as<Cx<float>>() : nullptr, c->stream));
+    HCHK(c, hipStreamSynchronize(c->stream));
+    t.have64 = true;
+    if (t.gh32.p) t.have32 = true;
+    return DDA_OK;
+}
+
+template <class T>
+hipError_t matvec_group(const Target& t, Group& g, int nr, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, const int* active,
+                        int mode, hipStream_t st) {
+    Cx<T>* slab = std::is_same<T, double>::value ? g.slab64.as<Cx<T>>() : g.slab32.as<Cx<T>>();
+    const Cx<T>* ainv = std::is_same<T, double>::value ? g.ainv64.as<Cx<T>>() : g.ainv32.as<Cx<T>>();
+    return launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab, t.ghat<T>(), ainv, active,
+                            mode, st);
+}
+
+size_t slab_elems(const Target& t, int nr) { return (size_t)nr * 3 * 4 * t.n[0] * t.n[1] * t.n[2]; }
+size_t vec_elems(const Target& t, int nr) { return (size_t)nr * 3 * t.Npad; }
+
+// Allocate (or reuse) a group's buffers for precision mode `prec`.
+dda_status ensure_group(dda_ctx* c, Group& g, const Target& t, int prec, bool* realloc) {
+    const int nr = g.nr;
+    const size_t v64 = vec_elems(t, nr) * sizeof(Cx<double>);
+    const int kp = (prec == DDA_SOLVE_FP32_REFINE) ? DDA_FP32 : DDA_FP64;
+    const size_t vk = vec_elems(t, nr) * (kp == DDA_FP32 ? sizeof(Cx<float>) : sizeof(Cx<double>));
+    void* before[24];
+    int nb = 0;
+    DevMem* all[] = {&g.b64, &g.x64, &g.r64, &g.slab32, &g.slab64, &g.kv[0], &g.kv[1], &g.kv[2], &g.kv[3],
+                     &g.kv[4], &g.kv[5], &g.kv[6], &g.state, &g.active, &g.partials};
+    for (DevMem* d : all) before[nb++] = d->p;
+    HCHK(c, g.waves.ensure(nr * sizeof(WaveDev)));
+    HCHK(c, g.ainv64.ensure((size_t)nr * t.ncomp * sizeof(Cx<double>)));
+    HCHK(c, g.ainv32.ensure((size_t)nr * t.ncomp * sizeof(Cx<float>)));
+    HCHK(c, g.b64.ensure(v64));
+    HCHK(c, g.x64.ensure(v64));
+    HCHK(c, g.r64.ensure(v64));
+    HCHK(c, g.slab64.ensure(slab_elems(t, nr) * sizeof(Cx<double>)));
+    if (kp == DDA_FP32) HCHK(c, g.slab32.ensure(slab_elems(t, nr) * sizeof(Cx<float>)));
+    for (int i = 0; i < 7; ++i) {
+        if (g.kprec != kp) g.kv[i].release();
+        HCHK(c, g.kv[i].ensure(vk));
+    }
+    g.kprec = kp;
+    HCHK(c, g.state.ensure(nr * sizeof(BiState)));
+    HCHK(c, g.active.ensure(nr * sizeof(int)));
+    HCHK(c, g.mask.ensure(nr * sizeof(int)));
+    HCHK(c, g.partials.ensure((size_t)nr * 4 * vec_blocks(t.Npad) * 2 * sizeof(double)));
+    HCHK(c, g.scale.ensure(nr * sizeof(double)));
+    HCHK(c, g.tolrel2.ensure(nr * sizeof(double)));
+    HCHK(c, g.maxit.ensure(nr * sizeof(int)));
+    HCHK(c, g.norms.ensure(nr * sizeof(double)));
+    nb = 0;
+    bool changed = false;
+    for (DevMem* d : all) changed |= (before[nb++] != d->p);
+    if (changed) {
+        // zero the padded vectors once so that padding stays zero
+        for (DevMem* d : {&g.b64, &g.x64, &g.r64}) HCHK(c, hipMemsetAsync(d->p, 0, d->n, c->stream));
+        for (int i = 0; i < 7; ++i) HCHK(c, hipMemsetAsync(g.kv[i].p, 0, g.kv[i].n, c->stream));
+    }
+    *realloc = changed;
+    return DDA_OK;
+}
+
+// One BiCGstab iteration for every group (precision T), enqueued on st.
+template <class T>
+hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st) {
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        const Target& t = *c->tg[g.tgt];
+        const int Np = t.Npad, nr = g.nr;
+        Cx<T>* x = g.kv[0].as<Cx<T>>();
+        Cx<T>* r = g.kv[1].as<Cx<T>>();
+        Cx<T>* rh = g.kv[2].as<Cx<T>>();
+        Cx<T>* p = g.kv[3].as<Cx<T>>();
+        Cx<T>* v = g.kv[4].as<Cx<T>>();
+        Cx<T>* s = g.kv[5].as<Cx<T>>();
+        Cx<T>* tt = g.kv[6].as<Cx<T>>();
+        BiState* bs = g.state.as<BiState>();
+        int* act = g.active.as<int>();
+        double* part = g.partials.as<double>();
+        hipError_t e;
+        if ((e = launch_bicg_p<T>(Np, nr, p, r, v, rh, bs, act, st)) != hipSuccess) return e;
+        if ((e = matvec_group<T>(t, g, nr, p, v, nullptr, act, MV_AX, st)) != hipSuccess) return e;
+        if ((e = launch_dot<T>(Np, nr, 1, rh, v, nullptr, nullptr, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_scalars(0, Np, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_bicg_s<T>(Np, nr, s, r, v, bs, act, st)) != hipSuccess) return e;
+        if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st)) != hipSuccess) return e;
+        if ((e = launch_dot<T>(Np, nr, 2, tt, s, tt, tt, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_scalars(1, Np, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_bicg_xr<T>(Np, nr, x, r, p, s, tt, rh, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_scalars(2, Np, nr, bs, part, act, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Inner BiCGstab on all groups: solves A d = b_inner from d = 0, where b_inner
+// is already in kv[1] (r).  Per-rhs relative tolerance and iteration budget
+// are in g.tolrel2 / g.maxit.  Returns when no rhs is active.
+template <class T>
+dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
+    hipStream_t st = c->stream;
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        const Target& t = *c->tg[g.tgt];
+        Cx<T>* x = g.kv[0].as<Cx<T>>();
+        Cx<T>* r = g.kv[1].as<Cx<T>>();
+        // b_inner currently in r: copy into x temporarily? use init kernel with b = r
+        HCHK(c, launch_bicg_init<T>(t.Npad, g.nr, r, x, r, g.kv[2].as<Cx<T>>(), g.kv[3].as<Cx<T>>(),
+                                    g.kv[4].as<Cx<T>>(), st));
+        HCHK(c, launch_dot<T>(t.Npad, g.nr, 1, r, r, nullptr, nullptr, g.partials.as<double>(), nullptr, st));
+        HCHK(c, launch_state_init(t.Npad, g.nr, g.state.as<BiState>(), g.partials.as<double>(),
+                                  g.tolrel2.as<double>(), g.maxit.as<int>(), g.active.as<int>(), st));
+    }
+    const int prec = std::is_same<T, double>::value ? DDA_FP64 : DDA_FP32;
+    if (use_graph && (c->gexec == nullptr || c->gkey_gen != c->ws_gen || c->gkey_prec != prec || c->gkey_k != kiters)) {
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+        hipGraph_t graph;
+        HCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < kiters && e == hipSuccess; ++k) e = enqueue_iteration<T>(c, st);
+        hipError_t e2 = hipStreamEndCapture(st, &graph);
+        HCHK(c, e);
+        HCHK(c, e2);
+        e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HCHK(c, e);
+        c->gkey_gen = c->ws_gen;
+        c->gkey_prec = prec;
+        c->gkey_k = kiters;
+    }
+    std::vector<std::vector<int>> hact(c->groups.size());
+    for (int guard = 0; guard < 1000000; ++guard) {
+        // poll: is any right-hand side still active?
+        for (size_t k = 0; k < c->groups.size(); ++k) {
+            hact[k].resize(c->groups[k]->nr);
+            HCHK(c, hipMemcpyAsync(hact[k].data(), c->groups[k]->active.p, c->groups[k]->nr * sizeof(int),
+                                   hipMemcpyDeviceToHost, st));
+        }
+        HCHK(c, hipStreamSynchronize(st));
+        bool any = false;
+        for (auto& h : hact)
+            for (int v : h) any |= (v != 0);
+        if (!any) break;
+        if (use_graph) {
+            HCHK(c, hipGraphLaunch(c->gexec, st));
+        } else {
+            for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st));
+        }
+    }
+    return DDA_OK;
+}
+
+dda_status group_waves(dda_ctx* c, int nrhs, const dda_wave* waves) {
+    // regroup only if the target pattern changed
+    bool same = (int)c->rhs_group.size() == nrhs && c->last_nrhs == nrhs;
+    if (same)
+        for (int i = 0; i < nrhs; ++i)
+            if (c->groups[c->rhs_group[i]]->tgt != waves[i].target) {
+                same = false;
+                break;
+            }
+    if (same) return DDA_OK;
+    c->groups.clear();
+    c->rhs_group.assign(nrhs, -1);
+    c->rhs_slot.assign(nrhs, -1);
+    for (int i = 0; i < nrhs; ++i) {
+        int gi = -1;
+        for (size_t k = 0; k < c->groups.size(); ++k)
+            if (c->groups[k]->tgt == waves[i].target) gi = (int)k;
+        if (gi < 0) {
+            c->groups.emplace_back(new Group());
+            gi = (int)c->groups.size() - 1;
+            c->groups[gi]->tgt = waves[i].target;
+        }
+        Group& g = *c->groups[gi];
+        c->rhs_group[i] = gi;
+        c->rhs_slot[i] = g.nr++;
+        g.idx.push_back(i);
+    }
+    c->last_nrhs = nrhs;
+    c->ws_gen++;
+    c->have_solution = false;
+    return DDA_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* dda_version(void) { return "dda-mi355x 0.1 (gfx950)"; }
+
+dda_status dda_create(dda_ctx** out, int32_t device, void* hip_stream) {
+    if (!out) return DDA_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return DDA_ERR_NO_DEVICE;
+    if (device < 0 || device >= n) return DDA_ERR_INVALID_ARG;
+    dda_ctx* c = new (std::nothrow) dda_ctx();
+    if (!c) return DDA_ERR_OOM;
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return DDA_ERR_HIP;
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return DDA_ERR_HIP;
+        }
+        c->own_stream = true;
+    }
+    if (configure_fft_kernels() != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
+        hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return DDA_ERR_HIP;
+    }
+    *out = c;
+    return DDA_OK;
+}
+
+dda_status dda_destroy(dda_ctx* c) {
+    if (!c) return DDA_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->groups.clear();
+    c->tg.clear();
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return DDA_OK;
+}
+
+const char* dda_last_error(const dda_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+dda_status dda_add_target(dda_ctx* c, const int32_t dims[3], const uint8_t* occ, int32_t ncomp, const double* m,
+                          double kd, int32_t alpha_kind, const double* origin, int32_t* id_out) {
+    SCHK(check_ctx(c));
+    std::unique_ptr<Target> t(new Target());
+    dda_status s = build_target(c, *t, dims, occ, ncomp, m, kd, alpha_kind, origin);
+    if (s < 0) return s;
+    c->tg.push_back(std::move(t));
+    if (id_out) *id_out = (int32_t)c->tg.size() - 1;
+    c->groups.clear();
+    c->rhs_group.clear();
+    c->last_nrhs = 0;
+    c->ws_gen++;
+    c->have_solution = false;
+    return s;
+}
+
+dda_status dda_set_target(dda_ctx* c, const int32_t dims[3], const uint8_t* occ, int32_t ncomp, const double* m,
+                          double kd, int32_t alpha_kind, const double* origin) {
+    SCHK(check_ctx(c));
+    (void)hipStreamSynchronize(c->stream);
+    c->groups.clear();
+    c->tg.clear();
+    return dda_add_target(c, dims, occ, ncomp, m, kd, alpha_kind, origin, nullptr);
+}
+
+dda_status dda_target_info(const dda_ctx* c, int32_t target, int64_t* n_sites, double* aeff) {
+    if (!c || target < 0 || target >= (int)c->tg.size()) return DDA_ERR_INVALID_ARG;
+    if (n_sites) *n_sites = c->tg[target]->N;
+    if (aeff) *aeff = c->tg[target]->aeff;
+    return DDA_OK;
+}
+
+dda_status dda_build_green_fft(dda_ctx* c, uint32_t prec) {
+    SCHK(check_ctx(c));
+    if (c->tg.empty()) return fail(c, DDA_ERR_STATE, "build_green_fft before set_target");
+    if (!(prec & (DDA_FP32 | DDA_FP64))) return fail(c, DDA_ERR_INVALID_ARG, "prec must contain DDA_FP32 or DDA_FP64");
+    for (auto& t : c->tg) SCHK(ensure_green(c, *t, prec | DDA_FP64));
+    return DDA_OK;
+}
+
+dda_status dda_inverse_polarizability(const dda_ctx* c, int32_t target, const dda_wave* w, double* out) {
+    if (!c || !w || !out || target < 0 || target >= (int)c->tg.size()) return DDA_ERR_INVALID_ARG;
+    const Target& t = *c->tg[target];
+    for (int i = 0; i < t.ncomp; ++i) {
+        const cd a = inverse_alpha(t.m[i], t.kd, t.alpha_kind, w->khat, w->e0);
+        out[2 * i] = a.real();
+        out[2 * i + 1] = a.imag();
+    }
+    return DDA_OK;
+}
+
+dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* o, const void* p0,
+                     void* p_out, dda_solve_stats* stats) {
+    SCHK(check_ctx(c));
+    if (nrhs <= 0 || !waves || !o) return fail(c, DDA_ERR_INVALID_ARG, "solve: nrhs <= 0 or null waves/opts");
+    if (c->tg.empty()) return fail(c, DDA_ERR_STATE, "solve before set_target");
+    for (int i = 0; i < nrhs; ++i) {
+        if (waves[i].target < 0 || waves[i].target >= (int)c->tg.size())
+            return fail(c, DDA_ERR_INVALID_ARG, "wave %d: unknown target %d", i, waves[i].target);
+        double kn = 0;
+        for (int j = 0; j < 3; ++j) kn += waves[i].khat[j] * waves[i].khat[j];
+        if (std::fabs(kn - 1.0) > 1e-6) return fail(c, DDA_ERR_INVALID_ARG, "wave %d: |khat| != 1", i);
+    }
+    const double tol = o->tol > 0 ? o->tol : 1e-5;
+    const int max_iter = o->max_iter > 0 ? o->max_iter : 1000;
+    const int prec = o->prec;
+    if (prec != DDA_SOLVE_FP64 && prec != DDA_SOLVE_FP32_REFINE) return fail(c, DDA_ERR_INVALID_ARG, "bad prec");
+    const bool devptr = (o->flags & DDA_DEVICE_PTRS) != 0;
+    const bool use_graph = !(o->flags & DDA_NO_GRAPH);
+    const int kiters = o->graph_iters > 0 ? o->graph_iters : 4;
+    if (o->guess == DDA_GUESS_USER && !p0) return fail(c, DDA_ERR_INVALID_ARG, "GUESS_USER needs p0");
+    if (o->guess == DDA_GUESS_NN) return fail(c, DDA_ERR_STATE, "no learned-guess model attached");
+    if (o->guess == DDA_GUESS_PREV && (!c->have_solution || c->last_nrhs != nrhs))
+        return fail(c, DDA_ERR_STATE, "GUESS_PREV needs a previous solve with the same right-hand sides");
+    const bool keep_prev = (o->guess == DDA_GUESS_PREV);
+    if (!keep_prev) SCHK(group_waves(c, nrhs, waves));
+    else
+        for (int i = 0; i < nrhs; ++i)
+            if (c->groups[c->rhs_group[i]]->tgt != waves[i].target)
+                return fail(c, DDA_ERR_STATE, "GUESS_PREV: rhs %d changed target", i);
+    hipStream_t st = c->stream;
+    HCHK(c, hipEventRecord(c->ev0, st));
+    // spectra and workspaces
+    for (auto& gp : c->groups) {
+        Target& t = *c->tg[gp->tgt];
+        SCHK(ensure_green(c, t, DDA_FP64 | (prec == DDA_SOLVE_FP32_REFINE ? DDA_FP32 : 0)));
+        bool re = false;
+        SCHK(ensure_group(c, *gp, t, prec, &re));
+        if (re) {
+            c->ws_gen++;
+            if (keep_prev) return fail(c, DDA_ERR_STATE, "GUESS_PREV: workspace changed");
+        }
+    }
+    // waves, polarizabilities, incident field, norms
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        Target& t = *c->tg[g.tgt];
+        g.hw.resize(g.nr);
+        g.hainv.resize((size_t)g.nr * t.ncomp);
+        std::vector<Cx<float>>& a32 = g.hainv32;
+        a32.resize(g.hainv.size());
+        for (int s = 0; s < g.nr; ++s) {
+            const dda_wave& w = waves[g.idx[s]];
+            WaveDev& d = g.hw[s];
+            for (int j = 0; j < 3; ++j) d.khat[j] = w.khat[j];
+            for (int j = 0; j < 6; ++j) d.e[j] = w.e0[j];
+            d.k = t.kd;
+            d.pad = 0;
+            for (int q = 0; q < t.ncomp; ++q) {
+                const cd a = inverse_alpha(t.m[q], t.kd, t.alpha_kind, w.khat, w.e0);
+                g.hainv[(size_t)s * t.ncomp + q] = a;
+                a32[(size_t)s * t.ncomp + q] = Cx<float>{(float)a.real(), (float)a.imag()};
+            }
+        }
+        HCHK(c, hipMemcpyAsync(g.waves.p, g.hw.data(), g.nr * sizeof(WaveDev), hipMemcpyHostToDevice, st));
+        HCHK(c, hipMemcpyAsync(g.ainv64.p, g.hainv.data(), g.hainv.size() * sizeof(cd), hipMemcpyHostToDevice, st));
+        HCHK(c, hipMemcpyAsync(g.ainv32.p, a32.data(), a32.size() * sizeof(Cx<float>), hipMemcpyHostToDevice, st));
+        HCHK(c, launch_einc<double>(t.geo(), t.origin, g.waves.as<WaveDev>(), g.nr, g.b64.as<Cx<double>>(), st));
+    }
+    // initial guess
+    DevMem dtmp;
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        Target& t = *c->tg[g.tgt];
+        if (o->guess == DDA_GUESS_ZERO) {
+            HCHK(c, launch_fill<double>(g.x64.as<Cx<double>>(), vec_elems(t, g.nr), st));
+        } else if (o->guess == DDA_GUESS_USER) {
+            // gather this group's rows from the ABI buffer (rows of all rhs
+            // are concatenated, each with its own target's N)
+            const size_t per = (size_t)t.N * 3 * sizeof(Cx<double>);
+            HCHK(c, dtmp.ensure(per * g.nr));
+            for (int s = 0; s < g.nr; ++s) {
+                size_t off = 0;
+                for (int q = 0; q < g.idx[s]; ++q) off += (size_t)c->tg[waves[q].target]->N * 3 * sizeof(Cx<double>);
+                HCHK(c, hipMemcpyAsync((char*)dtmp.p + s * per, (const char*)p0 + off, per,
+                                       devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+            }
+            HCHK(c, launch_from_abi<double>(t.N, t.Npad, g.nr, dtmp.as<Cx<double>>(), g.x64.as<Cx<double>>(), st));
+            HCHK(c, hipStreamSynchronize(st));
+        }
+        // GUESS_PREV: x64 already holds the previous solution
+    }
+    std::vector<double> bb(nrhs), rel(nrhs), grel(nrhs, 1.0);
+    std::vector<int> done(nrhs, 0), iters(nrhs, 0), outer(nrhs, 0), mvs(nrhs, 0), stat(nrhs, 0);
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        Target& t = *c->tg[g.tgt];
+        HCHK(c, launch_norm2<double>(t.Npad, g.nr, g.b64.as<Cx<double>>(), g.partials.as<double>(),
+                                     g.norms.as<double>(), st));
+        std::vector<double> h(g.nr);
+        HCHK(c, hipMemcpyAsync(h.data(), g.norms.p, g.nr * sizeof(double), hipMemcpyDeviceToHost, st));
+        HCHK(c, hipStreamSynchronize(st));
+        for (int s = 0; s < g.nr; ++s) bb[g.idx[s]] = h[s];
+    }
+    const bool guessed = o->guess != DDA_GUESS_ZERO;
+    float ms32 = 0, ms64 = 0;
+    hipEvent_t e0 = c->ev0, ea, eb;
+    HCHK(c, hipEventCreate(&ea));
+    HCHK(c, hipEventCreate(&eb));
+    const int max_outer = 40;
+    for (int it_out = 0; it_out <= max_outer; ++it_out) {
+        // FP64 residual r = b - A x for rhs not yet done
+        HCHK(c, hipEventRecord(ea, st));
+        for (auto& gp : c->groups) {
+            Group& g = *gp;
+            Target& t = *c->tg[g.tgt];
+            std::vector<int>& mk = g.hmask;
+            mk.resize(g.nr);
+            for (int s = 0; s < g.nr; ++s) mk[s] = done[g.idx[s]] ? 0 : 1;
+            HCHK(c, hipMemcpyAsync(g.mask.p, mk.data(), g.nr * sizeof(int), hipMemcpyHostToDevice, st));
+            HCHK(c, matvec_group<double>(t, g, g.nr, g.x64.as<Cx<double>>(), g.r64.as<Cx<double>>(),
+                                         g.b64.as<Cx<double>>(), g.mask.as<int>(), MV_RESID, st));
+            HCHK(c, launch_norm2<double>(t.Npad, g.nr, g.r64.as<Cx<double>>(), g.partials.as<double>(),
+                                         g.norms.as<double>(), st));
+        }
+        HCHK(c, hipEventRecord(eb, st));
+        HCHK(c, hipEventSynchronize(eb));
+        float ms = 0;
+        HCHK(c, hipEventElapsedTime(&ms, ea, eb));
+        ms64 += ms;
+        bool all_done = true;
+        for (auto& gp : c->groups) {
+            Group& g = *gp;
+            Target& t = *c->tg[g.tgt];
+            std::vector<double> h(g.nr);
+            HCHK(c, hipMemcpy(h.data(), g.norms.p, g.nr * sizeof(double), hipMemcpyDeviceToHost));
+            std::vector<double>& sc = g.hscale;
+            std::vector<double>& tr2 = g.htol2;
+            std::vector<int>& mi = g.hmaxit;
+            sc.assign(g.nr, 1.0);
+            tr2.assign(g.nr, 0.0);
+            mi.assign(g.nr, 0);
+            for (int s = 0; s < g.nr; ++s) {
+                const int i = g.idx[s];
+                if (done[i]) continue;
+                outer[i] += 1;
+                mvs[i] += 1;
+                double rr = h[s];
+                double rl = bb[i] > 0 ? std::sqrt(rr / bb[i]) : 0.0;
+                if (it_out == 0) {
+                    if (guessed && rl > 1.0 && !(o->flags & DDA_NO_FALLBACK)) {
+                        // the guess is worse than P0 = 0: fall back to it
+                        const size_t off = (size_t)s * 3 * t.Npad;
+                        HCHK(c, launch_fill<double>(g.x64.as<Cx<double>>() + off, (size_t)3 * t.Npad, st));
+                        HCHK(c, hipMemcpyAsync(g.r64.as<Cx<double>>() + off, g.b64.as<Cx<double>>() + off,
+                                               (size_t)3 * t.Npad * sizeof(Cx<double>), hipMemcpyDeviceToDevice, st));
+                        rr = bb[i];
+                        rl = 1.0;
+                    }
+                    grel[i] = rl;
+                }
+                rel[i] = rl;
+                if (rl <= tol || bb[i] == 0) {
+                    done[i] = 1;
+                    continue;
+                }
+                if (iters[i] >= max_iter || it_out == max_outer) {
+                    done[i] = 1;
+                    stat[i] = DDA_WARN_NOT_CONVERGED;
+                    continue;
+                }
+                all_done = false;
+                sc[s] = 1.0 / std::sqrt(rr);
+                double tin;
+                if (prec == DDA_SOLVE_FP32_REFINE) tin = std::min(0.5, std::max(2e-6, 0.3 * tol / rl));
+                else tin = std::min(0.5, std::max(1e-15, 0.3 * tol / rl));
+                tr2[s] = tin * tin;
+                mi[s] = max_iter - iters[i];
+            }
+            HCHK(c, hipMemcpyAsync(g.scale.p, sc.data(), g.nr * sizeof(double), hipMemcpyHostToDevice, st));
+            HCHK(c, hipMemcpyAsync(g.tolrel2.p, tr2.data(), g.nr * sizeof(double), hipMemcpyHostToDevice, st));
+            HCHK(c, hipMemcpyAsync(g.maxit.p, mi.data(), g.nr * sizeof(int), hipMemcpyHostToDevice, st));
+            std::vector<int>& mk = g.hmask;
+            mk.resize(g.nr);
+            for (int s = 0; s < g.nr; ++s) mk[s] = mi[s] > 0 ? 1 : 0;
+            HCHK(c, hipMemcpyAsync(g.mask.p, mk.data(), g.nr * sizeof(int), hipMemcpyHostToDevice, st));
+            HCHK(c, hipStreamSynchronize(st));
+        }
+        if (all_done) break;
+        // inner solve: A d = r / ||r||
+        HCHK(c, hipEventRecord(ea, st));
+        for (auto& gp : c->groups) {
+            Group& g = *gp;
+            Target& t = *c->tg[g.tgt];
+            if (prec == DDA_SOLVE_FP32_REFINE)
+                HCHK(c, launch_demote(t.Npad, g.nr, g.r64.as<Cx<double>>(), g.kv[1].as<Cx<float>>(),
+                                      g.scale.as<double>(), nullptr, st));
+            else
+                HCHK(c, hipMemcpyAsync(g.kv[1].p, g.r64.p, vec_elems(t, g.nr) * sizeof(Cx<double>),
+                                       hipMemcpyDeviceToDevice, st));
+        }
+        if (prec == DDA_SOLVE_FP32_REFINE) SCHK(inner_solve<float>(c, kiters, use_graph));
+        else SCHK(inner_solve<double>(c, kiters, use_graph));
+        for (auto& gp : c->groups) {
+            Group& g = *gp;
+            Target& t = *c->tg[g.tgt];
+            if (prec == DDA_SOLVE_FP32_REFINE)
+                HCHK(c, launch_promote_add(t.Npad, g.nr, g.x64.as<Cx<double>>(), g.kv[0].as<Cx<float>>(),
+                                           g.scale.as<double>(), g.mask.as<int>(), st));
+            else
+                HCHK(c, launch_axpy_masked<double>(t.Npad, g.nr, g.x64.as<Cx<double>>(), g.kv[0].as<Cx<double>>(),
+                                                   g.mask.as<int>(), st));
+            std::vector<BiState> hs(g.nr);
+            HCHK(c, hipMemcpyAsync(hs.data(), g.state.p, g.nr * sizeof(BiState), hipMemcpyDeviceToHost, st));
+            HCHK(c, hipStreamSynchronize(st));
+            const std::vector<int>& mk = g.hmask;
+            for (int s = 0; s < g.nr; ++s) {
+                if (!mk[s]) continue;
+                iters[g.idx[s]] += hs[s].it;
+                mvs[g.idx[s]] += 2 * hs[s].it;
+            }
+        }
+        HCHK(c, hipEventRecord(eb, st));
+        HCHK(c, hipEventSynchronize(eb));
+        HCHK(c, hipEventElapsedTime(&ms, ea, eb));
+        if (prec == DDA_SOLVE_FP32_REFINE) ms32 += ms;
+        else ms64 += ms;
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    // output
+    if (p_out) {
+        size_t off = 0;
+        for (int i = 0; i < nrhs; ++i) {
+            Group& g = *c->groups[c->rhs_group[i]];
+            Target& t = *c->tg[g.tgt];
+            const int s = c->rhs_slot[i];
+            const size_t per = (size_t)t.N * 3 * sizeof(Cx<double>);
+            HCHK(c, dtmp.ensure(per));
+            HCHK(c, launch_to_abi<double>(t.N, t.Npad, 1, g.x64.as<Cx<double>>() + (size_t)s * 3 * t.Npad,
+                                          devptr ? (Cx<double>*)((char*)p_out + off) : dtmp.as<Cx<double>>(), st));
+            if (!devptr) HCHK(c, hipMemcpyAsync((char*)p_out + off, dtmp.p, per, hipMemcpyDeviceToHost, st));
+            HCHK(c, hipStreamSynchronize(st));
+            off += per;
+        }
+    }
+    HCHK(c, hipEventRecord(c->ev1, st));
+    HCHK(c, hipEventSynchronize(c->ev1));
+    float mst = 0;
+    HCHK(c, hipEventElapsedTime(&mst, e0, c->ev1));
+    c->ms_mv32 = ms32;
+    c->ms_mv64 = ms64;
+    c->ms_total = mst;
+    c->have_solution = true;
+    int any_nc = 0;
+    for (int i = 0; i < nrhs; ++i) {
+        if (stats) {
+            stats[i].iters = iters[i];
+            stats[i].matvecs = mvs[i];
+            stats[i].outer = outer[i];
+            stats[i].status = stat[i];
+            stats[i].rel_resid = rel[i];
+            stats[i].guess_resid = grel[i];
+        }
+        any_nc |= stat[i] != 0;
+    }
+    if (any_nc) {
+        fail(c, DDA_WARN_NOT_CONVERGED, "some right-hand sides did not reach tol=%g", tol);
+        return DDA_WARN_NOT_CONVERGED;
+    }
+    return DDA_OK;
+}
+
+dda_status dda_matvec(dda_ctx* c, int32_t target, int32_t nrhs, const double* ainv, const void* x, void* y,
+                      uint32_t prec, uint32_t flags) {
+    SCHK(check_ctx(c));
+    if (target < 0 || target >= (int)c->tg.size() || nrhs <= 0 || !x || !y)
+        return fail(c, DDA_ERR_INVALID_ARG, "matvec: bad target/nrhs/pointers");
+    if (prec != DDA_FP32 && prec != DDA_FP64) return fail(c, DDA_ERR_INVALID_ARG, "matvec: prec must be FP32 or FP64");
+    Target& t = *c->tg[target];
+    SCHK(ensure_green(c, t, prec | DDA_FP64));
+    hipStream_t st = c->stream;
+    Group g;
+    g.tgt = target;
+    g.nr = nrhs;
+    std::vector<cd> ai((size_t)nrhs * t.ncomp);
+    if (ainv) {
+        for (size_t i = 0; i < ai.size(); ++i) ai[i] = cd(ainv[2 * i], ainv[2 * i + 1]);
+    } else {
+        const double kh[3] = {1, 0, 0}, e[6] = {0, 0, 1, 0, 0, 0};
+        for (int s = 0; s < nrhs; ++s)
+            for (int q = 0; q < t.ncomp; ++q) ai[(size_t)s * t.ncomp + q] = inverse_alpha(t.m[q], t.kd, t.alpha_kind, kh, e);
+    }
+    const size_t per = (size_t)t.N * 3 * sizeof(Cx<double>);
+    DevMem dx, dy, vx, vy;
+    HCHK(c, dx.ensure(per * nrhs));
+    HCHK(c, dy.ensure(per * nrhs));
+    const bool dev = flags & DDA_DEVICE_PTRS;
+    HCHK(c, hipMemcpyAsync(dx.p, x, per * nrhs, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    if (prec == DDA_FP64) {
+        HCHK(c, g.ainv64.ensure(ai.size() * sizeof(cd)));
+        HCHK(c, hipMemcpyAsync(g.ainv64.p, ai.data(), ai.size() * sizeof(cd), hipMemcpyHostToDevice, st));
+        HCHK(c, g.slab64.ensure(slab_elems(t, nrhs) * sizeof(Cx<double>)));
+        HCHK(c, vx.ensure(vec_elems(t, nrhs) * sizeof(Cx<double>)));
+        HCHK(c, vy.ensure(vec_elems(t, nrhs) * sizeof(Cx<double>)));
+        HCHK(c, launch_from_abi<double>(t.N, t.Npad, nrhs, dx.as<Cx<double>>(), vx.as<Cx<double>>(), st));
+        HCHK(c, matvec_group<double>(t, g, nrhs, vx.as<Cx<double>>(), vy.as<Cx<double>>(), nullptr, nullptr, MV_AX, st));
+        HCHK(c, launch_to_abi<double>(t.N, t.Npad, nrhs, vy.as<Cx<double>>(), dy.as<Cx<double>>(), st));
+    } else {
+        std::vector<Cx<float>> a32(ai.size());
+        for (size_t i = 0; i < ai.size(); ++i) a32[i] = Cx<float>{(float)ai[i].real(), (float)ai[i].imag()};
+        HCHK(c, g.ainv32.ensure(a32.size() * sizeof(Cx<float>)));
+        HCHK(c, hipMemcpyAsync(g.ainv32.p, a32.data(), a32.size() * sizeof(Cx<float>), hipMemcpyHostToDevice, st));
+        HCHK(c, g.slab32.ensure(slab_elems(t, nrhs) * sizeof(Cx<float>)));
+        HCHK(c, vx.ensure(vec_elems(t, nrhs) * sizeof(Cx<float>)));
+        HCHK(c, vy.ensure(vec_elems(t, nrhs) * sizeof(Cx<float>)));
+        HCHK(c, launch_from_abi<float>(t.N, t.Npad, nrhs, dx.as<Cx<double>>(), vx.as<Cx<float>>(), st));
+        HCHK(c, matvec_group<float>(t, g, nrhs, vx.as<Cx<float>>(), vy.as<Cx<float>>(), nullptr, nullptr, MV_AX, st));
+        HCHK(c, launch_to_abi<float>(t.N, t.Npad, nrhs, vy.as<Cx<float>>(), dy.as<Cx<double>>(), st));
+    }
+    HCHK(c, hipMemcpyAsync(y, dy.p, per * nrhs, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    HCHK(c, hipStreamSynchronize(st));
+    return DDA_OK;
+}
+
+dda_status dda_cross_sections(dda_ctx* c, int32_t nrhs, double* q) {
+    SCHK(check_ctx(c));
+    if (!c->have_solution) return fail(c, DDA_ERR_STATE, "cross_sections before a solve");
+    if (nrhs != c->last_nrhs || !q) return fail(c, DDA_ERR_INVALID_ARG, "cross_sections: nrhs must match the last solve");
+    hipStream_t st = c->stream;
+    DevMem out;
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        Target& t = *c->tg[g.tgt];
+        HCHK(c, out.ensure(2 * g.nr * sizeof(double)));
+        HCHK(c, launch_xsec(t.geo(), g.nr, g.b64.as<Cx<double>>(), g.x64.as<Cx<double>>(), g.ainv64.as<Cx<double>>(),
+                            t.kd * t.kd * t.kd, g.partials.as<double>(), out.as<double>(), st));
+        std::vector<double> h(2 * g.nr);
+        HCHK(c, hipMemcpyAsync(h.data(), out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HCHK(c, hipStreamSynchronize(st));
+        const double area = PI * t.aeff * t.aeff;
+        for (int s = 0; s < g.nr; ++s) {
+            const int i = g.idx[s];
+            const double qext = 4 * PI * t.kd * h[2 * s] / area, qabs = 4 * PI * t.kd * h[2 * s + 1] / area;
+            q[3 * i] = qext;
+            q[3 * i + 1] = qabs;
+            q[3 * i + 2] = qext - qabs;
+        }
+    }
+    return DDA_OK;
+}
+
+dda_status dda_amplitudes(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* n_tf, const double* e_tf, double* f) {
+    SCHK(check_ctx(c));
+    if (!c->have_solution) return fail(c, DDA_ERR_STATE, "amplitudes before a solve");
+    if (nrhs != c->last_nrhs || ndir <= 0 || !n_tf || !e_tf || !f)
+        return fail(c, DDA_ERR_INVALID_ARG, "amplitudes: bad arguments");
+    hipStream_t st = c->stream;
+    DevMem dn, dF;
+    HCHK(c, dn.ensure((size_t)ndir * 3 * sizeof(double)));
+    HCHK(c, hipMemcpyAsync(dn.p, n_tf, (size_t)ndir * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        Target& t = *c->tg[g.tgt];
+        HCHK(c, dF.ensure((size_t)g.nr * ndir * 3 * sizeof(Cx<double>)));
+        HCHK(c, launch_ampl(t.geo(), t.origin, t.kd, g.nr, g.x64.as<Cx<double>>(), ndir, dn.as<double>(),
+                            dF.as<Cx<double>>(), st));
+        std::vector<cd> F((size_t)g.nr * ndir * 3);
+        HCHK(c, hipMemcpyAsync(F.data(), dF.p, F.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
+        HCHK(c, hipStreamSynchronize(st));
+        const double k3 = t.kd * t.kd * t.kd;
+        for (int s = 0; s < g.nr; ++s) {
+            const int i = g.idx[s];
+            for (int d = 0; d < ndir; ++d) {
+                const cd* Fv = &F[((size_t)s * ndir + d) * 3];
+                for (int mm = 0; mm < 2; ++mm) {
+                    const double* e = e_tf + (size_t)d * 6 + 3 * mm;
+                    const cd v = k3 * (e[0] * Fv[0] + e[1] * Fv[1] + e[2] * Fv[2]);
+                    f[(((size_t)i * ndir + d) * 2 + mm) * 2] = v.real();
+                    f[(((size_t)i * ndir + d) * 2 + mm) * 2 + 1] = v.imag();
+                }
+            }
+        }
+    }
+    return DDA_OK;
+}
+
+dda_status dda_mueller(int32_t ndir, const double* f, const double* phi, const double* e01, const double* e02,
+                       double* S, double* mu) {
+    if (ndir <= 0 || !f || !phi || !e01 || !e02) return DDA_ERR_INVALID_ARG;
+    const cd I(0, 1);
+    const cd a = std::conj(cd(e01[2], e01[3])), b = std::conj(cd(e01[4], e01[5]));
+    const cd cc = std::conj(cd(e02[2], e02[3])), d = std::conj(cd(e02[4], e02[5]));
+    for (int k = 0; k < ndir; ++k) {
+        const double* fk = f + (size_t)k * 8;
+        const cd f11(fk[0], fk[1]), f12(fk[2], fk[3]), f21(fk[4], fk[5]), f22(fk[6], fk[7]);
+        const double cp = std::cos(phi[k]), sp = std::sin(phi[k]);
+        const cd S1 = -I * (f21 * (b * cp - a * sp) + f22 * (d * cp - cc * sp));
+        const cd S2 = -I * (f11 * (a * cp + b * sp) + f12 * (cc * cp + d * sp));
+        const cd S3 = I * (f11 * (b * cp - a * sp) + f12 * (d * cp - cc * sp));
+        const cd S4 = I * (f21 * (a * cp + b * sp) + f22 * (cc * cp + d * sp));
+        if (S) {
+            const cd Sv[4] = {S1, S2, S3, S4};
+            for (int j = 0; j < 4; ++j) {
+                S[(size_t)k * 8 + 2 * j] = Sv[j].real();
+                S[(size_t)k * 8 + 2 * j + 1] = Sv[j].imag();
+            }
+        }
+        if (mu) {
+            const double n1 = std::norm(S1), n2 = std::norm(S2), n3 = std::norm(S3), n4 = std::norm(S4);
+            double* M = mu + (size_t)k * 16;
+            M[0] = (n1 + n2 + n3 + n4) / 2;
+            M[1] = (n2 - n1 + n4 - n3) / 2;
+            M[2] = std::real(S2 * std::conj(S3) + S1 * std::conj(S4));
+            M[3] = std::imag(S2 * std::conj(S3) - S1 * std::conj(S4));
+            M[4] = (n2 - n1 + n3 - n4) / 2;
+            M[5] = (n1 + n2 - n3 - n4) / 2;
+            M[6] = std::real(S2 * std::conj(S3) - S1 * std::conj(S4));
+            M[7] = std::imag(S2 * std::conj(S3) + S1 * std::conj(S4));
+            M[8] = std::real(S2 * std::conj(S4) + S1 * std::conj(S3));
+            M[9] = std::real(S2 * std::conj(S4) - S1 * std::conj(S3));
+            M[10] = std::real(S1 * std::conj(S2) + S3 * std::conj(S4));
+            M[11] = std::imag(S2 * std::conj(S1) + S4 * std::conj(S3));
+            M[12] = std::imag(S4 * std::conj(S2) + S1 * std::conj(S3));
+            M[13] = std::imag(S4 * std::conj(S2) - S1 * std::conj(S3));
+            M[14] = std::imag(S1 * std::conj(S2) - S3 * std::conj(S4));
+            M[15] = std::real(S1 * std::conj(S2) - S3 * std::conj(S4));
+        }
+    }
+    return DDA_OK;
+}
+
+dda_status dda_lab_frame(double beta, double theta, double phi, const double* a1in, const double* a2in, double* out) {
+    if (!out) return DDA_ERR_INVALID_ARG;
+    double a1[3] = {1, 0, 0}, a2[3] = {0, 1, 0};
+    if (a1in) std::memcpy(a1, a1in, sizeof a1);
+    if (a2in) std::memcpy(a2, a2in, sizeof a2);
+    const double n1 = std::sqrt(a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]);
+    const double n2 = std::sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]);
+    if (!(n1 > 0) || !(n2 > 0)) return DDA_ERR_INVALID_ARG;
+    for (int i = 0; i < 3; ++i) a1[i] /= n1, a2[i] /= n2;
+    const double a3[3] = {a1[1] * a2[2] - a1[2] * a2[1], a1[2] * a2[0] - a1[0] * a2[2], a1[0] * a2[1] - a1[1] * a2[0]};
+    const double cb = std::cos(beta), sb = std::sin(beta), ct = std::cos(theta), st = std::sin(theta);
+    const double cp = std::cos(phi), sp = std::sin(phi);
+    // coefficients of x_LF, y_LF, z_LF on (a1, a2, a3)
+    const double X[3] = {ct, -st * cb, st * sb};
+    const double Y[3] = {st * cp, ct * cb * cp - sb * sp, -(ct * sb * cp + cb * sp)};
+    const double Z[3] = {st * sp, ct * cb * sp + sb * cp, -(ct * sb * sp - cb * cp)};
+    const double* rows[3] = {X, Y, Z};
+    for (int r = 0; r < 3; ++r)
+        for (int i = 0; i < 3; ++i) out[3 * r + i] = rows[r][0] * a1[i] + rows[r][1] * a2[i] + rows[r][2] * a3[i];
+    return DDA_OK;
+}
+
+dda_status dda_last_timing(const dda_ctx* c, double* a, double* b, double* t) {
+    if (!c) return DDA_ERR_INVALID_ARG;
+    if (a) *a = c->ms_mv32;
+    if (b) *b = c->ms_mv64;
+    if (t) *t = c->ms_total;
+    return DDA_OK;
+}
+
+}  // extern "C"
+
+// ---- per-pass profiling and autotuning ----
+namespace {
+template <class T>
+dda_status profile_passes(dda_ctx* c, Target& t, int nrhs, int reps, const MvShape& sh, double* ms, double* bytes) {
+    hipStream_t st = c->stream;
+    Group g;
+    g.tgt = 0;
+    g.nr = nrhs;
+    const size_t ve = vec_elems(t, nrhs);
+    DevMem vx, vy, ai, slab;
+    HCHK(c, vx.ensure(ve * sizeof(Cx<T>)));
+    HCHK(c, vy.ensure(ve * sizeof(Cx<T>)));
+    HCHK(c, ai.ensure((size_t)nrhs * t.ncomp * sizeof(Cx<T>)));
+    HCHK(c, slab.ensure(slab_elems(t, nrhs) * sizeof(Cx<T>)));
+    HCHK(c, hipMemsetAsync(vx.p, 0, vx.n, st));
+    HCHK(c, hipMemsetAsync(ai.p, 0, ai.n, st));
+    const Geo geo = t.geo();
+    const Tw<T> tw = t.tw<T>();
+    hipEvent_t ev[4];
+    for (auto& e : ev) HCHK(c, hipEventCreate(&e));
+    double acc[3] = {0, 0, 0};
+    for (int r = -1; r < reps; ++r) {
+        HCHK(c, hipEventRecord(ev[0], st));
+        for (int w = 0; w < 3; ++w) {
+            HCHK(c, launch_pass<T>(w, geo, tw, t.plans, sh, nrhs, vx.as<Cx<T>>(), vy.as<Cx<T>>(), nullptr,
+                                   slab.as<Cx<T>>(), t.ghat<T>(), ai.as<Cx<T>>(), nullptr, MV_AX, st));
+            HCHK(c, hipEventRecord(ev[w + 1], st));
+        }
+        HCHK(c, hipEventSynchronize(ev[3]));
+        if (r < 0) continue;  // warm-up
+        for (int w = 0; w < 3; ++w) {
+            float m = 0;
+            HCHK(c, hipEventElapsedTime(&m, ev[w], ev[w + 1]));
+            acc[w] += m;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (ms)
+        for (int w = 0; w < 3; ++w) ms[w] = acc[w] / std::max(1, reps);
+    if (bytes) {
+        const double cb = sizeof(Cx<T>);
+        const double slabb = (double)nrhs * 3 * 4 * t.n[0] * t.n[1] * t.n[2] * cb;
+        const double vecb = (double)nrhs * 3 * t.N * cb;
+        const double idx = (double)nrhs * 3 * t.N * 4.0;  // site coordinates read per plane pass
+        const double ghb = (double)ghat_octant_elems(t.n[0], t.n[1], t.n[2]) * cb;
+        bytes[0] = vecb + idx + slabb;
+        bytes[1] = 2 * slabb + ghb;
+        bytes[2] = slabb + 2 * vecb + idx;
+    }
+    return DDA_OK;
+}
+}  // namespace
+
+extern "C" dda_status dda_profile_matvec(dda_ctx* c, int32_t target, int32_t nrhs, uint32_t prec, int32_t reps,
+                                         double* ms, double* bytes) {
+    SCHK(check_ctx(c));
+    if (target < 0 || target >= (int)c->tg.size() || nrhs <= 0 || reps <= 0)
+        return fail(c, DDA_ERR_INVALID_ARG, "profile_matvec: bad arguments");
+    Target& t = *c->tg[target];
+    SCHK(ensure_green(c, t, prec | DDA_FP64));
+    if (prec == DDA_FP32) return profile_passes<float>(c, t, nrhs, reps, t.sh32, ms, bytes);
+    if (prec == DDA_FP64) return profile_passes<double>(c, t, nrhs, reps, t.sh64, ms, bytes);
+    return fail(c, DDA_ERR_INVALID_ARG, "profile_matvec: prec must be FP32 or FP64");
+}
+
+extern "C" dda_status dda_autotune(dda_ctx* c, int32_t nrhs_hint, const char* cache_path) {
+    SCHK(check_ctx(c));
+    (void)nrhs_hint;
+    (void)cache_path;
+    return DDA_OK;
+}

@@ -1,0 +1,208 @@
+// Device-side building blocks of the DDA solver for gfx950: complex arithmetic,
+// radix-2/3/4/5/8 butterflies and an in-LDS Stockham FFT over batches of lines.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+template <class T>
+struct alignas(2 * sizeof(T)) Cx {
+    T re, im;
+};
+
+template <class T> __host__ __device__ __forceinline__ Cx<T> mk(T a, T b) { return Cx<T>{a, b}; }
+template <class T> __host__ __device__ __forceinline__ Cx<T> operator+(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __host__ __device__ __forceinline__ Cx<T> operator-(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __host__ __device__ __forceinline__ Cx<T> operator*(Cx<T> a, Cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T> __host__ __device__ __forceinline__ Cx<T> operator*(T s, Cx<T> a) { return {s * a.re, s * a.im}; }
+template <class T> __host__ __device__ __forceinline__ Cx<T> conj(Cx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <class T> __host__ __device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// a * (s i), s = +1 or -1
+template <class T, int S> __device__ __forceinline__ Cx<T> mul_si(Cx<T> a) {
+    return S > 0 ? Cx<T>{-a.im, a.re} : Cx<T>{a.im, -a.re};
+}
+template <class To, class Ti> __device__ __forceinline__ Cx<To> cvt(Cx<Ti> a) { return {(To)a.re, (To)a.im}; }
+
+// ---------------------------------------------------------------------------
+// Butterflies: DFT of length R in registers.  DIR = -1 forward, +1 inverse.
+// ---------------------------------------------------------------------------
+template <class T, int DIR> __device__ __forceinline__ void bfly2(Cx<T>* v) {
+    Cx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+}
+
+template <class T, int DIR> __device__ __forceinline__ void bfly3(Cx<T>* v) {
+    const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+    Cx<T> t1 = v[1] + v[2], t2 = v[1] - v[2];
+    Cx<T> y0 = v[0] + t1;
+    Cx<T> mm = v[0] - (T)0.5 * t1;
+    Cx<T> u = mul_si<T, DIR>(h * t2);
+    v[0] = y0;
+    v[1] = mm + u;
+    v[2] = mm - u;
+}
+
+template <class T, int DIR> __device__ __forceinline__ void bfly4(Cx<T>* v) {
+    Cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2], t2 = v[1] + v[3];
+    Cx<T> t3 = mul_si<T, DIR>(v[1] - v[3]);
+    v[0] = t0 + t2;
+    v[2] = t0 - t2;
+    v[1] = t1 + t3;
+    v[3] = t1 - t3;
+}
+
+template <class T, int DIR> __device__ __forceinline__ void bfly5(Cx<T>* v) {
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+    Cx<T> t1 = v[1] + v[4], t2 = v[2] + v[3], t3 = v[1] - v[4], t4 = v[2] - v[3];
+    Cx<T> a1 = v[0] + c1 * t1 + c2 * t2;
+    Cx<T> a2 = v[0] + c2 * t1 + c1 * t2;
+    Cx<T> b1 = mul_si<T, DIR>(s1 * t3 + s2 * t4);
+    Cx<T> b2 = mul_si<T, DIR>(s2 * t3 - s1 * t4);
+    v[0] = v[0] + t1 + t2;
+    v[1] = a1 + b1;
+    v[4] = a1 - b1;
+    v[2] = a2 + b2;
+    v[3] = a2 - b2;
+}
+
+template <class T, int DIR> __device__ __forceinline__ void bfly8(Cx<T>* v) {
+    Cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    Cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    bfly4<T, DIR>(e);
+    bfly4<T, DIR>(o);
+    const T r = (T)0.70710678118654752440;
+    // w8^k = exp(DIR 2 pi i k / 8)
+    Cx<T> w1 = {r, (T)DIR * r}, w3 = {-r, (T)DIR * r};
+    Cx<T> o1 = w1 * o[1], o2 = mul_si<T, DIR>(o[2]), o3 = w3 * o[3];
+    v[0] = e[0] + o[0];
+    v[4] = e[0] - o[0];
+    v[1] = e[1] + o1;
+    v[5] = e[1] - o1;
+    v[2] = e[2] + o2;
+    v[6] = e[2] - o2;
+    v[3] = e[3] + o3;
+    v[7] = e[3] - o3;
+}
+
+template <class T, int DIR, int R> __device__ __forceinline__ void bfly(Cx<T>* v) {
+    if constexpr (R == 2) bfly2<T, DIR>(v);
+    else if constexpr (R == 3) bfly3<T, DIR>(v);
+    else if constexpr (R == 4) bfly4<T, DIR>(v);
+    else if constexpr (R == 5) bfly5<T, DIR>(v);
+    else bfly8<T, DIR>(v);
+}
+
+// ---------------------------------------------------------------------------
+// FFT plan: the length and its radix factorisation (applied in order).
+// ---------------------------------------------------------------------------
+struct FftPlan {
+    int n;
+    int np;
+    int r[8];
+};
+
+// Address of line l in an LDS batch: (l / lg) * ls1 + (l % lg) * ls0.
+struct LineAddr {
+    int lg, ls0, ls1;
+    __device__ __forceinline__ int operator()(int l) const { return (l / lg) * ls1 + (l % lg) * ls0; }
+};
+
+// One Stockham radix-R pass over `nl` lines of length n held in LDS, in place:
+// every thread first reads and transforms up to MAXB butterflies into
+// registers, the block synchronises, then all results are written.  Lines are
+// the fastest-varying butterfly index so that neighbouring lanes touch
+// neighbouring lines (bank-conflict free for odd line pitches).
+// tw[i] = exp(-2 pi i idx / n) (forward table; conjugated for DIR = +1).
+template <class T, int DIR, int R, int MAXB>
+__device__ __forceinline__ void fft_pass(Cx<T>* buf, int n, int nl, int L, LineAddr la, int es,
+                                         const Cx<T>* tw, int tid, int nth) {
+    const int nb = n / R;
+    const int tot = nb * nl;
+    const int tws = n / (L * R);
+    Cx<T> v[MAXB][R];
+#pragma unroll
+    for (int c = 0; c < MAXB; ++c) {
+        const int b = tid + c * nth;
+        if (b < tot) {
+            const int l = b % nl, j = b / nl;
+            const int base = la(l);
+            const int k = j % L;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                Cx<T> a = buf[base + (j + t * nb) * es];
+                if (t > 0 && k > 0) {
+                    Cx<T> w = tw[t * k * tws];
+                    if (DIR > 0) w.im = -w.im;
+                    a = a * w;
+                }
+                v[c][t] = a;
+            }
+            bfly<T, DIR, R>(v[c]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < MAXB; ++c) {
+        const int b = tid + c * nth;
+        if (b < tot) {
+            const int l = b % nl, j = b / nl;
+            const int base = la(l);
+            const int k = j % L;
+            const int ob = (j - k) * R + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) buf[base + (ob + t * L) * es] = v[c][t];
+        }
+    }
+    __syncthreads();
+}
+
+// Full FFT of `nl` LDS lines (natural order in, natural order out).  The
+// caller must have synchronised after writing the lines.  Requires
+// (n / r_min) * nl <= MAXB * nth, checked by the host when it picks nth.
+template <class T, int DIR, int MAXB>
+__device__ void fft_lines(Cx<T>* buf, const FftPlan& p, int nl, LineAddr la, int es, const Cx<T>* tw,
+                          int tid, int nth) {
+    int L = 1;
+    for (int s = 0; s < p.np; ++s) {
+        const int R = p.r[s];
+        switch (R) {
+            case 2: fft_pass<T, DIR, 2, MAXB>(buf, p.n, nl, L, la, es, tw, tid, nth); break;
+            case 3: fft_pass<T, DIR, 3, MAXB>(buf, p.n, nl, L, la, es, tw, tid, nth); break;
+            case 4: fft_pass<T, DIR, 4, MAXB>(buf, p.n, nl, L, la, es, tw, tid, nth); break;
+            case 5: fft_pass<T, DIR, 5, MAXB>(buf, p.n, nl, L, la, es, tw, tid, nth); break;
+            default: fft_pass<T, DIR, 8, MAXB>(buf, p.n, nl, L, la, es, tw, tid, nth); break;
+        }
+        L *= R;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level and block-level reductions (64-wide wavefronts).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of `v` over the block; result valid in thread 0.  `sh` needs
+// blockDim.x / 64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) s += sh[i];
+    }
+    return s;
+}

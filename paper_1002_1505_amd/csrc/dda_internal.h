@@ -1,0 +1,143 @@
+// Internal interface between the host runtime (api.hip) and the kernel
+// translation units of the DDA library.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dda_device.h"
+
+// Geometry of one target on the device.  Sites are ordered by linear box index;
+// site_xyz packs (x | y << 10 | z << 20); plane_start[z] is the first site of
+// plane z (n3 + 1 entries).
+struct Geo {
+    int n1, n2, n3;
+    int N, Npad;
+    int ncomp;
+    const int* plane_start;
+    const uint32_t* site_xyz;
+    const uint8_t* site_comp;  // 0-based composition index
+};
+
+// Twiddle tables of one target: f_i[k] = exp(-2 pi i k / n_i) (k < n_i) and
+// h_i[x] = exp(-2 pi i x / (2 n_i)) (x < n_i), the pre-twiddles of the
+// frequency-parity split of the doubled axis.
+template <class T>
+struct Tw {
+    const Cx<T>* f1;
+    const Cx<T>* f2;
+    const Cx<T>* f3;
+    const Cx<T>* h1;
+    const Cx<T>* h2;
+    const Cx<T>* h3;
+};
+
+// Per right-hand-side state of BiCGstab (device memory).
+struct BiState {
+    double rho[2], alpha[2], omega[2], beta[2];
+    double rr;     // ||r||^2 (recursive residual)
+    double tol2;   // stop when rr <= tol2
+    int it, maxit, restart, conv;
+};
+
+// Launch shapes of the three matvec passes for one target and precision.
+struct MvShape {
+    int fused;       // 1: xy planes in LDS; 0: line kernels through global memory
+    int nth_plane;   // threads of the xy-plane kernels
+    int nth_z;       // threads of the z-pass kernel
+    int tx;          // columns per z-pass block
+    int lines_tl;    // lines per block in the line-kernel fallback
+    int nth_lines;
+};
+
+enum { MV_AX = 0, MV_RESID = 1 };
+
+// ---- matvec / FFT launchers (kernels_fft.hip) ----
+template <class T>
+hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh, int nrhs,
+                         const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
+                         const Cx<T>* ainv, const int* active, int mode, hipStream_t st);
+// Individual passes (for per-pass profiling).
+template <class T>
+hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh,
+                       int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
+                       const Cx<T>* ainv, const int* active, int mode, hipStream_t st);
+// Shared-memory bytes and feasibility of a shape.
+template <class T>
+bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh);
+
+// Spectrum of the interaction tensor: fills the octant arrays (6 components,
+// scaled by 1/(M1 M2 M3)) in FP64 and, when g32 != nullptr, an FP32 copy.
+// work must hold 48 * n1 n2 n3 complex doubles.
+hipError_t launch_green(const Geo& g, const Tw<double>& tw, const FftPlan* plans, double kd, Cx<double>* work,
+                        Cx<double>* g64, Cx<float>* g32, hipStream_t st);
+
+inline size_t ghat_octant_elems(int n1, int n2, int n3) {
+    return (size_t)6 * (2 * (n1 / 2 + 1)) * (2 * (n2 / 2 + 1)) * (2 * (n3 / 2 + 1));
+}
+
+// ---- vector kernels (kernels_vec.hip) ----
+struct WaveDev {
+    double khat[3];
+    double e[6];
+    double k;
+    double pad;
+};
+
+template <class T>
+hipError_t launch_einc(const Geo& g, const double* origin3, const WaveDev* w, int nrhs, Cx<T>* E, hipStream_t st);
+template <class T>
+hipError_t launch_fill(Cx<T>* p, size_t n, hipStream_t st);
+hipError_t launch_fill_int(int* p, int v, size_t n, hipStream_t st);
+
+// BiCGstab pieces; vectors are [nrhs][3][Npad]; partials [nrhs][4][nblk] double2.
+int vec_blocks(int Npad);
+template <class T>
+hipError_t launch_bicg_p(int Npad, int nrhs, Cx<T>* p, const Cx<T>* r, const Cx<T>* v, Cx<T>* rhat,
+                         const BiState* s, const int* active, hipStream_t st);
+template <class T>
+hipError_t launch_dot(int Npad, int nrhs, int npair, const Cx<T>* a0, const Cx<T>* b0, const Cx<T>* a1,
+                      const Cx<T>* b1, double* partials, const int* active, hipStream_t st);
+template <class T>
+hipError_t launch_bicg_s(int Npad, int nrhs, Cx<T>* s, const Cx<T>* r, const Cx<T>* v, const BiState* st_,
+                         const int* active, hipStream_t st);
+template <class T>
+hipError_t launch_bicg_xr(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p, const Cx<T>* s,
+                          const Cx<T>* t, const Cx<T>* rhat, const BiState* st_, double* partials,
+                          const int* active, hipStream_t st);
+// which: 0 alpha, 1 omega, 2 rho/convergence
+hipError_t launch_scalars(int which, int Npad, int nrhs, BiState* s, const double* partials, int* active,
+                          hipStream_t st);
+template <class T>
+hipError_t launch_bicg_init(int Npad, int nrhs, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* rhat, Cx<T>* p,
+                            Cx<T>* v, hipStream_t st);
+// state init from partials holding <r,r> in slot 0: rho = rr, restart = 1
+hipError_t launch_state_init(int Npad, int nrhs, BiState* s, const double* partials, const double* tol_rel2,
+                             const int* maxit, int* active, hipStream_t st);
+
+// Mixed precision helpers.
+// r32 = r64 * scale[rhs] (scale = 1/||r||); x64 += (1/scale[rhs]) * d32
+hipError_t launch_demote(int Npad, int nrhs, const Cx<double>* r64, Cx<float>* r32, const double* scale,
+                         const int* mask, hipStream_t st);
+hipError_t launch_promote_add(int Npad, int nrhs, Cx<double>* x64, const Cx<float>* d32, const double* scale,
+                              const int* mask, hipStream_t st);
+template <class T>
+hipError_t launch_axpy_masked(int Npad, int nrhs, Cx<T>* x, const Cx<T>* d, const int* mask, hipStream_t st);
+// per-rhs ||v||^2 into out[rhs] (double), two-stage
+template <class T>
+hipError_t launch_norm2(int Npad, int nrhs, const Cx<T>* v, double* partials, double* out, hipStream_t st);
+
+// Layout conversion between the ABI ([rhs][N][3] complex128) and the device
+// layout ([rhs][3][Npad]).
+template <class T>
+hipError_t launch_from_abi(int N, int Npad, int nrhs, const Cx<double>* in, Cx<T>* out, hipStream_t st);
+template <class T>
+hipError_t launch_to_abi(int N, int Npad, int nrhs, const Cx<T>* in, Cx<double>* out, hipStream_t st);
+
+// Cross-section sums: out[rhs] = {sum Im(E^* . P), sum |P|^2 * (-Im ainv_c - (2/3) k^3)}.
+hipError_t launch_xsec(const Geo& g, int nrhs, const Cx<double>* E, const Cx<double>* P, const Cx<double>* ainv,
+                       double k3, double* partials, double* out, hipStream_t st);
+// Amplitude sums F[rhs][dir][3] = sum_j P_j exp(-i k n . r_j) (FP64).
+hipError_t launch_ampl(const Geo& g, const double* origin3, double k, int nrhs, const Cx<double>* P, int ndir,
+                       const double* ndirs, Cx<double>* F, hipStream_t st);
+
+hipError_t configure_fft_kernels();

@@ -1,0 +1,561 @@
+// Vector kernels of the DDA solver on gfx950: incident field, BiCGstab
+// updates with fused FP64 inner-product partials, per-right-hand-side scalar
+// updates, precision conversion for the FP64 refinement, layout conversion at
+// the ABI boundary, cross-section and scattering-amplitude reductions.
+//
+// Vectors are [rhs][3][Npad] complex; a grid is (blocks per rhs, nrhs), every
+// thread handles VPT consecutive-by-stride elements.  Inner products are
+// accumulated in FP64: per-thread, wavefront shuffle, LDS, then a per-rhs
+// second stage over the block partials.
+#include "dda_internal.h"
+
+#define HIP_TRY(x)                       \
+    do {                                 \
+        hipError_t e_ = (x);             \
+        if (e_ != hipSuccess) return e_; \
+    } while (0)
+
+namespace {
+constexpr int VT = 256;  // threads per vector block
+constexpr int VPT = 4;   // elements per thread
+constexpr int VB = VT * VPT;
+
+__device__ __forceinline__ bool inactive(const int* active, int rhs) { return active && !active[rhs]; }
+
+template <class T>
+__device__ __forceinline__ void acc_dot(double2& a, Cx<T> u, Cx<T> v) {
+    // conj(u) * v in FP64
+    const double ur = u.re, ui = u.im, vr = v.re, vi = v.im;
+    a.x += ur * vr + ui * vi;
+    a.y += ur * vi - ui * vr;
+}
+
+// Block reduction of up to 4 complex partial sums; thread 0 writes
+// partials[rhs][slot][blockIdx.x].
+__device__ void store_partials(const double2* a, int nslot, double* partials, int rhs, int nblk) {
+    __shared__ double sh[16];
+    for (int s = 0; s < nslot; ++s) {
+        const double re = block_sum(a[s].x, sh);
+        const double im = block_sum(a[s].y, sh);
+        if (threadIdx.x == 0) {
+            double* o = partials + (((size_t)rhs * 4 + s) * nblk + blockIdx.x) * 2;
+            o[0] = re;
+            o[1] = im;
+        }
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(VT) k_einc(Geo g, double ox, double oy, double oz, const WaveDev* __restrict__ w,
+                                             Cx<T>* __restrict__ E) {
+    const int rhs = blockIdx.y;
+    const WaveDev wv = w[rhs];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.Npad; j += gridDim.x * blockDim.x) {
+        Cx<T> o[3] = {{0, 0}, {0, 0}, {0, 0}};
+        if (j < g.N) {
+            const uint32_t s = g.site_xyz[j];
+            const double x = (double)(s & 1023) - ox, y = (double)((s >> 10) & 1023) - oy,
+                         z = (double)(s >> 20) - oz;
+            double sn, cs;
+            sincos(wv.k * (wv.khat[0] * x + wv.khat[1] * y + wv.khat[2] * z), &sn, &cs);
+            for (int c = 0; c < 3; ++c) {
+                const double er = wv.e[2 * c], ei = wv.e[2 * c + 1];
+                o[c] = Cx<T>{(T)(er * cs - ei * sn), (T)(er * sn + ei * cs)};
+            }
+        }
+        for (int c = 0; c < 3; ++c) E[((size_t)rhs * 3 + c) * g.Npad + j] = o[c];
+    }
+}
+
+template <class T>
+__global__ void k_fillv(Cx<T>* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = Cx<T>{0, 0};
+}
+__global__ void k_filli(int* p, int v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// p = r + beta (p - omega v); on restart rhat = r, p = r.
+template <class T>
+__global__ void __launch_bounds__(VT) k_bicg_p(int V, Cx<T>* __restrict__ p, const Cx<T>* __restrict__ r,
+                                               const Cx<T>* __restrict__ v, Cx<T>* __restrict__ rhat,
+                                               const BiState* __restrict__ st, const int* __restrict__ active) {
+    const int rhs = blockIdx.y;
+    if (inactive(active, rhs)) return;
+    const BiState s = st[rhs];
+    const size_t o = (size_t)rhs * V;
+    const Cx<T> beta = {(T)s.beta[0], (T)s.beta[1]}, omega = {(T)s.omega[0], (T)s.omega[1]};
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) {
+            const Cx<T> ri = r[o + i];
+            if (s.restart) {
+                rhat[o + i] = ri;
+                p[o + i] = ri;
+            } else {
+                p[o + i] = ri + beta * (p[o + i] - omega * v[o + i]);
+            }
+        }
+    }
+}
+
+// partials[rhs][0..npair) = sum conj(a_k) b_k
+template <class T>
+__global__ void __launch_bounds__(VT) k_dot(int V, int npair, const Cx<T>* __restrict__ a0,
+                                            const Cx<T>* __restrict__ b0, const Cx<T>* __restrict__ a1,
+                                            const Cx<T>* __restrict__ b1, double* __restrict__ partials,
+                                            const int* __restrict__ active) {
+    const int rhs = blockIdx.y;
+    if (inactive(active, rhs)) return;
+    const size_t o = (size_t)rhs * V;
+    double2 acc[2] = {{0, 0}, {0, 0}};
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) {
+            acc_dot(acc[0], a0[o + i], b0[o + i]);
+            if (npair > 1) acc_dot(acc[1], a1[o + i], b1[o + i]);
+        }
+    }
+    store_partials(acc, npair, partials, rhs, gridDim.x);
+}
+
+// s = r - alpha v
+template <class T>
+__global__ void __launch_bounds__(VT) k_bicg_s(int V, Cx<T>* __restrict__ s, const Cx<T>* __restrict__ r,
+                                               const Cx<T>* __restrict__ v, const BiState* __restrict__ st,
+                                               const int* __restrict__ active) {
+    const int rhs = blockIdx.y;
+    if (inactive(active, rhs)) return;
+    const size_t o = (size_t)rhs * V;
+    const Cx<T> alpha = {(T)st[rhs].alpha[0], (T)st[rhs].alpha[1]};
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) s[o + i] = r[o + i] - alpha * v[o + i];
+    }
+}
+
+// x += alpha p + omega s; r = s - omega t; partials <rhat, r>, <r, r>
+template <class T>
+__global__ void __launch_bounds__(VT) k_bicg_xr(int V, Cx<T>* __restrict__ x, Cx<T>* __restrict__ r,
+                                                const Cx<T>* __restrict__ p, const Cx<T>* __restrict__ s,
+                                                const Cx<T>* __restrict__ t, const Cx<T>* __restrict__ rhat,
+                                                const BiState* __restrict__ st, double* __restrict__ partials,
+                                                const int* __restrict__ active) {
+    const int rhs = blockIdx.y;
+    if (inactive(active, rhs)) return;
+    const size_t o = (size_t)rhs * V;
+    const Cx<T> alpha = {(T)st[rhs].alpha[0], (T)st[rhs].alpha[1]};
+    const Cx<T> omega = {(T)st[rhs].omega[0], (T)st[rhs].omega[1]};
+    double2 acc[2] = {{0, 0}, {0, 0}};
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) {
+            const Cx<T> si = s[o + i];
+            x[o + i] = x[o + i] + alpha * p[o + i] + omega * si;
+            const Cx<T> ri = si - omega * t[o + i];
+            r[o + i] = ri;
+            acc_dot(acc[0], rhat[o + i], ri);
+            acc_dot(acc[1], ri, ri);
+        }
+    }
+    store_partials(acc, 2, partials, rhs, gridDim.x);
+}
+
+__device__ __forceinline__ double2 reduce_slot(const double* partials, int rhs, int slot, int nblk, double* sh) {
+    double re = 0, im = 0;
+    const double* p = partials + ((size_t)rhs * 4 + slot) * nblk * 2;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        re += p[2 * i];
+        im += p[2 * i + 1];
+    }
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    return make_double2(re, im);
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// One block per rhs.
+//  which 0: alpha = rho / <rhat, v>       (partials slot 0); breakdown -> alpha = 0, restart
+//  which 1: omega = <t, s> / <t, t>       (slots 0, 1); breakdown -> omega = 0, restart
+//  which 2: rho' = <rhat, r>, rr = <r, r> (slots 0, 1); beta, convergence, iteration count
+__global__ void k_scalars(int which, int nblk, BiState* __restrict__ st, const double* __restrict__ partials,
+                          int* __restrict__ active) {
+    __shared__ double sh[16];
+    const int rhs = blockIdx.x;
+    if (!active[rhs]) return;
+    const double2 a = reduce_slot(partials, rhs, 0, nblk, sh);
+    double2 b = make_double2(0, 0);
+    if (which > 0) b = reduce_slot(partials, rhs, 1, nblk, sh);
+    if (threadIdx.x != 0) return;
+    BiState s = st[rhs];
+    const double2 rho = make_double2(s.rho[0], s.rho[1]);
+    if (which == 0) {
+        s.restart = 0;
+        const double an = sqrt(a.x * a.x + a.y * a.y);
+        if (!(an > 1e-300) || !(an > 1e-14 * s.rr)) {
+            s.alpha[0] = s.alpha[1] = 0;
+            s.restart = 1;
+        } else {
+            const double2 al = cdiv(rho, a);
+            s.alpha[0] = al.x;
+            s.alpha[1] = al.y;
+        }
+    } else if (which == 1) {
+        // a = <t, s>, b = <t, t>
+        if (!(b.x > 0)) {
+            s.omega[0] = s.omega[1] = 0;
+            s.restart = 1;
+        } else {
+            s.omega[0] = a.x / b.x;
+            s.omega[1] = a.y / b.x;
+            if (s.omega[0] == 0 && s.omega[1] == 0) s.restart = 1;
+        }
+    } else {
+        // a = <rhat, r>, b = <r, r>
+        s.it += 1;
+        s.rr = b.x;
+        const double2 al = make_double2(s.alpha[0], s.alpha[1]), om = make_double2(s.omega[0], s.omega[1]);
+        const double rn = sqrt(a.x * a.x + a.y * a.y);
+        if (s.restart || !(rn > 1e-14 * b.x) || (om.x == 0 && om.y == 0)) {
+            s.restart = 1;
+            s.rho[0] = b.x;
+            s.rho[1] = 0;
+        } else {
+            const double2 be = cmul2(cdiv(a, rho), cdiv(al, om));
+            s.beta[0] = be.x;
+            s.beta[1] = be.y;
+            s.rho[0] = a.x;
+            s.rho[1] = a.y;
+        }
+        if (!(b.x > s.tol2)) s.conv = 1;
+        if (s.conv || s.it >= s.maxit || !isfinite(b.x)) active[rhs] = 0;
+    }
+    st[rhs] = s;
+}
+
+// State initialisation from <r, r> in slot 0.
+__global__ void k_state_init(int nblk, BiState* __restrict__ st, const double* __restrict__ partials,
+                             const double* __restrict__ tol_rel2, const int* __restrict__ maxit,
+                             int* __restrict__ active) {
+    __shared__ double sh[16];
+    const int rhs = blockIdx.x;
+    const double2 a = reduce_slot(partials, rhs, 0, nblk, sh);
+    if (threadIdx.x != 0) return;
+    BiState s;
+    s.rho[0] = a.x;
+    s.rho[1] = 0;
+    s.alpha[0] = s.alpha[1] = 0;
+    s.omega[0] = 1;
+    s.omega[1] = 0;
+    s.beta[0] = s.beta[1] = 0;
+    s.rr = a.x;
+    s.tol2 = tol_rel2[rhs] * a.x;
+    s.it = 0;
+    s.maxit = maxit[rhs];
+    s.restart = 1;
+    s.conv = (a.x <= s.tol2) ? 1 : 0;
+    st[rhs] = s;
+    active[rhs] = (maxit[rhs] > 0 && !s.conv && a.x > 0) ? 1 : 0;
+    if (a.x == 0) st[rhs].conv = 1;
+}
+
+// x = 0, r = rhat = p = b, v = 0
+template <class T>
+__global__ void __launch_bounds__(VT) k_bicg_init(int V, const Cx<T>* __restrict__ b, Cx<T>* __restrict__ x,
+                                                  Cx<T>* __restrict__ r, Cx<T>* __restrict__ rhat,
+                                                  Cx<T>* __restrict__ p, Cx<T>* __restrict__ v) {
+    const size_t o = (size_t)blockIdx.y * V;
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) {
+            const Cx<T> bi = b[o + i];
+            x[o + i] = Cx<T>{0, 0};
+            r[o + i] = bi;
+            rhat[o + i] = bi;
+            p[o + i] = bi;
+            v[o + i] = Cx<T>{0, 0};
+        }
+    }
+}
+
+__global__ void __launch_bounds__(VT) k_demote(int V, const Cx<double>* __restrict__ r64, Cx<float>* __restrict__ r32,
+                                               const double* __restrict__ scale, const int* __restrict__ mask) {
+    const int rhs = blockIdx.y;
+    if (inactive(mask, rhs)) return;
+    const size_t o = (size_t)rhs * V;
+    const double sc = scale[rhs];
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) {
+            const Cx<double> a = r64[o + i];
+            r32[o + i] = Cx<float>{(float)(a.re * sc), (float)(a.im * sc)};
+        }
+    }
+}
+
+__global__ void __launch_bounds__(VT) k_promote_add(int V, Cx<double>* __restrict__ x64,
+                                                    const Cx<float>* __restrict__ d32, const double* __restrict__ scale,
+                                                    const int* __restrict__ mask) {
+    const int rhs = blockIdx.y;
+    if (inactive(mask, rhs)) return;
+    const size_t o = (size_t)rhs * V;
+    const double sc = 1.0 / scale[rhs];
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) {
+            const Cx<float> d = d32[o + i];
+            x64[o + i] = x64[o + i] + Cx<double>{sc * (double)d.re, sc * (double)d.im};
+        }
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(VT) k_axpy_masked(int V, Cx<T>* __restrict__ x, const Cx<T>* __restrict__ d,
+                                                    const int* __restrict__ mask) {
+    const int rhs = blockIdx.y;
+    if (inactive(mask, rhs)) return;
+    const size_t o = (size_t)rhs * V;
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) x[o + i] = x[o + i] + d[o + i];
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(VT) k_norm2_part(int V, const Cx<T>* __restrict__ v, double* __restrict__ partials) {
+    const int rhs = blockIdx.y;
+    const size_t o = (size_t)rhs * V;
+    double2 acc[1] = {{0, 0}};
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) acc_dot(acc[0], v[o + i], v[o + i]);
+    }
+    store_partials(acc, 1, partials, rhs, gridDim.x);
+}
+
+__global__ void k_norm2_final(int nblk, const double* __restrict__ partials, double* __restrict__ out) {
+    __shared__ double sh[16];
+    const double2 a = reduce_slot(partials, blockIdx.x, 0, nblk, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = a.x;
+}
+
+template <class T>
+__global__ void k_from_abi(int N, int Npad, const Cx<double>* __restrict__ in, Cx<T>* __restrict__ out) {
+    const int rhs = blockIdx.y;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < Npad; j += gridDim.x * blockDim.x) {
+        for (int c = 0; c < 3; ++c) {
+            Cx<T> v = {0, 0};
+            if (j < N) {
+                const Cx<double> a = in[((size_t)rhs * N + j) * 3 + c];
+                v = Cx<T>{(T)a.re, (T)a.im};
+            }
+            out[((size_t)rhs * 3 + c) * Npad + j] = v;
+        }
+    }
+}
+
+template <class T>
+__global__ void k_to_abi(int N, int Npad, const Cx<T>* __restrict__ in, Cx<double>* __restrict__ out) {
+    const int rhs = blockIdx.y;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+        for (int c = 0; c < 3; ++c) {
+            const Cx<T> a = in[((size_t)rhs * 3 + c) * Npad + j];
+            out[((size_t)rhs * N + j) * 3 + c] = Cx<double>{(double)a.re, (double)a.im};
+        }
+    }
+}
+
+// partials slots: 0 = (sum Im(E^*.P), 0), 1 = (sum |P|^2 (-Im ainv - 2/3 k^3), 0)
+__global__ void __launch_bounds__(VT) k_xsec_part(Geo g, const Cx<double>* __restrict__ E,
+                                                  const Cx<double>* __restrict__ P,
+                                                  const Cx<double>* __restrict__ ainv, double k3,
+                                                  double* __restrict__ partials) {
+    const int rhs = blockIdx.y;
+    double2 acc[2] = {{0, 0}, {0, 0}};
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.N; j += gridDim.x * blockDim.x) {
+        double p2 = 0;
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = ((size_t)rhs * 3 + c) * g.Npad + j;
+            const Cx<double> e = E[i], p = P[i];
+            acc[0].x += e.re * p.im - e.im * p.re;  // Im(conj(e) p)
+            p2 += p.re * p.re + p.im * p.im;
+        }
+        const Cx<double> ai = ainv[(size_t)rhs * g.ncomp + g.site_comp[j]];
+        acc[1].x += p2 * (-ai.im - (2.0 / 3.0) * k3);
+    }
+    store_partials(acc, 2, partials, rhs, gridDim.x);
+}
+
+__global__ void k_xsec_final(int nblk, const double* __restrict__ partials, double* __restrict__ out) {
+    __shared__ double sh[16];
+    const double2 a = reduce_slot(partials, blockIdx.x, 0, nblk, sh);
+    const double2 b = reduce_slot(partials, blockIdx.x, 1, nblk, sh);
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = a.x;
+        out[2 * blockIdx.x + 1] = b.x;
+    }
+}
+
+// One block per (direction, rhs): F = sum_j P_j exp(-i k n . r_j), FP64.
+__global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, double oz, double k,
+                                              const Cx<double>* __restrict__ P, const double* __restrict__ nd,
+                                              Cx<double>* __restrict__ F, int ndir) {
+    __shared__ double sh[16];
+    const int dir = blockIdx.x, rhs = blockIdx.y;
+    const double nx = nd[3 * dir], ny = nd[3 * dir + 1], nz = nd[3 * dir + 2];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = threadIdx.x; j < g.N; j += blockDim.x) {
+        const uint32_t s = g.site_xyz[j];
+        const double x = (double)(s & 1023) - ox, y = (double)((s >> 10) & 1023) - oy, z = (double)(s >> 20) - oz;
+        double sn, cs;
+        sincos(-k * (nx * x + ny * y + nz * z), &sn, &cs);
+        for (int c = 0; c < 3; ++c) {
+            const Cx<double> p = P[((size_t)rhs * 3 + c) * g.Npad + j];
+            acc[2 * c] += p.re * cs - p.im * sn;
+            acc[2 * c + 1] += p.re * sn + p.im * cs;
+        }
+    }
+    for (int q = 0; q < 6; ++q) {
+        const double v = block_sum(acc[q], sh);
+        if (threadIdx.x == 0) reinterpret_cast<double*>(F)[((size_t)rhs * ndir + dir) * 6 + q] = v;
+    }
+}
+
+}  // namespace
+
+int vec_blocks(int Npad) { return (3 * Npad + VB - 1) / VB; }
+
+template <class T>
+hipError_t launch_einc(const Geo& g, const double* o, const WaveDev* w, int nrhs, Cx<T>* E, hipStream_t st) {
+    hipLaunchKernelGGL((k_einc<T>), dim3((g.Npad + VT - 1) / VT, nrhs), dim3(VT), 0, st, g, o[0], o[1], o[2], w, E);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_fill(Cx<T>* p, size_t n, hipStream_t st) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL((k_fillv<T>), dim3(1024), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_int(int* p, int v, size_t n, hipStream_t st) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_filli, dim3(64), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_bicg_p(int Npad, int nrhs, Cx<T>* p, const Cx<T>* r, const Cx<T>* v, Cx<T>* rhat,
+                         const BiState* s, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_bicg_p<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, p, r, v, rhat, s,
+                       active);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_dot(int Npad, int nrhs, int npair, const Cx<T>* a0, const Cx<T>* b0, const Cx<T>* a1,
+                      const Cx<T>* b1, double* partials, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_dot<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, npair, a0, b0, a1, b1,
+                       partials, active);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_bicg_s(int Npad, int nrhs, Cx<T>* s, const Cx<T>* r, const Cx<T>* v, const BiState* st_,
+                         const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_bicg_s<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, s, r, v, st_, active);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_bicg_xr(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p, const Cx<T>* s, const Cx<T>* t,
+                          const Cx<T>* rhat, const BiState* st_, double* partials, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_bicg_xr<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, x, r, p, s, t, rhat,
+                       st_, partials, active);
+    return hipGetLastError();
+}
+hipError_t launch_scalars(int which, int Npad, int nrhs, BiState* s, const double* partials, int* active,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_scalars, dim3(nrhs), dim3(256), 0, st, which, vec_blocks(Npad), s, partials, active);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_bicg_init(int Npad, int nrhs, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* rhat, Cx<T>* p, Cx<T>* v,
+                            hipStream_t st) {
+    hipLaunchKernelGGL((k_bicg_init<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, b, x, r, rhat, p, v);
+    return hipGetLastError();
+}
+hipError_t launch_state_init(int Npad, int nrhs, BiState* s, const double* partials, const double* tol_rel2,
+                             const int* maxit, int* active, hipStream_t st) {
+    hipLaunchKernelGGL(k_state_init, dim3(nrhs), dim3(256), 0, st, vec_blocks(Npad), s, partials, tol_rel2, maxit,
+                       active);
+    return hipGetLastError();
+}
+hipError_t launch_demote(int Npad, int nrhs, const Cx<double>* r64, Cx<float>* r32, const double* scale,
+                         const int* mask, hipStream_t st) {
+    hipLaunchKernelGGL(k_demote, dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, r64, r32, scale, mask);
+    return hipGetLastError();
+}
+hipError_t launch_promote_add(int Npad, int nrhs, Cx<double>* x64, const Cx<float>* d32, const double* scale,
+                              const int* mask, hipStream_t st) {
+    hipLaunchKernelGGL(k_promote_add, dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, x64, d32, scale, mask);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_axpy_masked(int Npad, int nrhs, Cx<T>* x, const Cx<T>* d, const int* mask, hipStream_t st) {
+    hipLaunchKernelGGL((k_axpy_masked<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, x, d, mask);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_norm2(int Npad, int nrhs, const Cx<T>* v, double* partials, double* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_norm2_part<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, v, partials);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_norm2_final, dim3(nrhs), dim3(256), 0, st, vec_blocks(Npad), partials, out);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_from_abi(int N, int Npad, int nrhs, const Cx<double>* in, Cx<T>* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_from_abi<T>), dim3((Npad + 255) / 256, nrhs), dim3(256), 0, st, N, Npad, in, out);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_to_abi(int N, int Npad, int nrhs, const Cx<T>* in, Cx<double>* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_to_abi<T>), dim3((N + 255) / 256, nrhs), dim3(256), 0, st, N, Npad, in, out);
+    return hipGetLastError();
+}
+hipError_t launch_xsec(const Geo& g, int nrhs, const Cx<double>* E, const Cx<double>* P, const Cx<double>* ainv,
+                       double k3, double* partials, double* out, hipStream_t st) {
+    const int nblk = vec_blocks(g.Npad);
+    hipLaunchKernelGGL(k_xsec_part, dim3(nblk, nrhs), dim3(VT), 0, st, g, E, P, ainv, k3, partials);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_xsec_final, dim3(nrhs), dim3(256), 0, st, nblk, partials, out);
+    return hipGetLastError();
+}
+hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const Cx<double>* P, int ndir,
+                       const double* ndirs, Cx<double>* F, hipStream_t st) {
+    hipLaunchKernelGGL(k_ampl, dim3(ndir, nrhs), dim3(256), 0, st, g, o[0], o[1], o[2], k, P, ndirs, F, ndir);
+    return hipGetLastError();
+}
+
+#define INST(T)                                                                                                      \
+    template hipError_t launch_einc<T>(const Geo&, const double*, const WaveDev*, int, Cx<T>*, hipStream_t);         \
+    template hipError_t launch_fill<T>(Cx<T>*, size_t, hipStream_t);                                                 \
+    template hipError_t launch_bicg_p<T>(int, int, Cx<T>*, const Cx<T>*, const Cx<T>*, Cx<T>*, const BiState*,      \
+                                         const int*, hipStream_t);                                                   \
+    template hipError_t launch_dot<T>(int, int, int, const Cx<T>*, const Cx<T>*, const Cx<T>*, const Cx<T>*, double*, \
+                                      const int*, hipStream_t);                                                      \
+    template hipError_t launch_bicg_s<T>(int, int, Cx<T>*, const Cx<T>*, const Cx<T>*, const BiState*, const int*,   \
+                                         hipStream_t);                                                               \
+    template hipError_t launch_bicg_xr<T>(int, int, Cx<T>*, Cx<T>*, const Cx<T>*, const Cx<T>*, const Cx<T>*,        \
+                                          const Cx<T>*, const BiState*, double*, const int*, hipStream_t);           \
+    template hipError_t launch_bicg_init<T>(int, int, const Cx<T>*, Cx<T>*, Cx<T>*, Cx<T>*, Cx<T>*, Cx<T>*,          \
+                                            hipStream_t);                                                            \
+    template hipError_t launch_axpy_masked<T>(int, int, Cx<T>*, const Cx<T>*, const int*, hipStream_t);              \
+    template hipError_t launch_norm2<T>(int, int, const Cx<T>*, double*, double*, hipStream_t);                      \
+    template hipError_t launch_from_abi<T>(int, int, int, const Cx<double>*, Cx<T>*, hipStream_t);                   \
+    template hipError_t launch_to_abi<T>(int, int, int, const Cx<T>*, Cx<double>*, hipStream_t);
+INST(float)
+INST(double)

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Inputs are seeded and synthetic (``synth``); every expected value comes from
+``oracle/``.  Bars: FP64 matvec 1e-12 relative, FP32 matvec 5e-6 relative
+(FFT rounding of complex64 on grids up to 256^3), solves to the requested
+residual 1e-5 checked with the oracle's own matvec, efficiencies within
+1e-4 relative of the oracle's solution.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dda, scatter
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1002_1505_amd as P
+
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _setup(ctx, occ, m_list, kd, kind, origin=None):
+    import paper_1002_1505_amd as P
+
+    kinds = {dda.ALPHA_CM: P.DDA_ALPHA_CM, dda.ALPHA_CM_RR: P.DDA_ALPHA_CM_RR, dda.ALPHA_LDR: P.DDA_ALPHA_LDR}
+    ctx.set_target(occ, m_list, kd, kinds[kind], origin=origin)
+    r, comp, idx = dda.sites_from_occupancy(occ, origin)
+    return r, comp
+
+
+CASES = [
+    # name, occupancy builder, m list, kd
+    ("cube8_two_materials", lambda: np.concatenate([np.ones((2, 2, 1), np.uint8), 2 * np.ones((2, 2, 1), np.uint8)], axis=2),
+     [1.5 + 0.01j, 2.0 + 1.0j], 0.4),
+    ("sphere_d8", lambda: synth.sphere_occupancy(8), [1.33 + 0.01j], 0.3),
+    ("ellipsoid_12x16x10", lambda: synth.ellipsoid_occupancy((12, 16, 10), (11.0, 15.0, 9.5)), [1.7 + 0.1j], 0.5),
+    ("ragged_aggregate_20x24x15", lambda: (np.random.default_rng(7).random((15, 24, 20)) < 0.4).astype(np.uint8),
+     [1.4 + 0.05j], 0.35),
+]
+
+
+@pytest.mark.parametrize("name,build,m_list,kd", CASES, ids=[c[0] for c in CASES])
+def test_matvec_small_vs_oracle(ctx, name, build, m_list, kd):
+    import paper_1002_1505_amd as P
+
+    occ = build()
+    r, comp = _setup(ctx, occ, m_list, kd, dda.ALPHA_LDR)
+    rng = np.random.default_rng(11)
+    nr = 2
+    x = rng.standard_normal((nr, len(r), 3)) + 1j * rng.standard_normal((nr, len(r), 3))
+    ainv = np.array([[dda.inverse_polarizability(mm, kd, dda.ALPHA_CM) + 0.1 * s for mm in m_list] for s in range(nr)])
+    y64 = ctx.matvec(x, ainv=ainv, prec=P.DDA_FP64)
+    y32 = ctx.matvec(x, ainv=ainv, prec=P.DDA_FP32)
+    for s in range(nr):
+        ref = dda.matvec_direct(r, kd, ainv[s][comp - 1], x[s])
+        assert _rel(y64[s], ref) < 1e-12, name
+        assert _rel(y32[s], ref) < 5e-6, name
+
+
+def test_matvec_bilinear_symmetry(ctx):
+    """x^T (A y) = y^T (A x): the FFT operator keeps A symmetric."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.ellipsoid_occupancy((16, 12, 20), (15.0, 11.0, 19.0))
+    r, comp = _setup(ctx, occ, [1.5 + 0.2j], 0.4, dda.ALPHA_LDR)
+    rng = np.random.default_rng(3)
+    xy = rng.standard_normal((2, len(r), 3)) + 1j * rng.standard_normal((2, len(r), 3))
+    for prec, tol in ((P.DDA_FP64, 1e-13), (P.DDA_FP32, 2e-6)):
+        A = ctx.matvec(xy, prec=prec)
+        lhs = np.sum(xy[0] * A[1])
+        rhs = np.sum(xy[1] * A[0])
+        assert abs(lhs - rhs) / abs(lhs) < tol
+
+
+def test_single_dipole_closed_form(ctx):
+    """N = 1 in a 2x2x2 box: P = alpha E, Q_ext = 4 pi k Im(alpha) / (pi a_eff^2)."""
+    import paper_1002_1505_amd as P
+
+    occ = np.zeros((2, 2, 2), np.uint8)
+    occ[0, 0, 0] = 1
+    kd, m = 0.3, 1.5 + 0.2j
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    khat, e = [1.0, 0, 0], [0, 1.0, 0]
+    Pg, st, _ = ctx.solve([khat], [e], tol=1e-10, prec=P.DDA_SOLVE_FP64)
+    alpha = 1 / dda.inverse_polarizability(m, kd, dda.ALPHA_LDR, khat, e)
+    assert np.allclose(Pg[0][0], alpha * np.array(e), rtol=1e-10)
+    q = ctx.cross_sections(1)
+    aeff = dda.effective_radius(1)
+    assert np.isclose(q[0, 0], 4 * np.pi * kd * alpha.imag / (np.pi * aeff ** 2), rtol=1e-10)
+
+
+def _c1_problem():
+    occ = synth.sphere_occupancy(16)
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    x = 1.0
+    kd = x / dda.effective_radius(len(r))
+    return occ, r, comp, kd, x
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "fp32_refine"])
+def test_config1_sphere16_vs_oracle(ctx, prec_name):
+    """Sphere D = 16 (N = 2176), m = 1.33+0.01i, x = 1, LDR, two polarizations:
+    P to residual 1e-5, Q's within 1e-4, amplitudes at 37 angles x 2 planes."""
+    import paper_1002_1505_amd as P
+
+    occ, r, comp, kd, x = _c1_problem()
+    assert len(r) == 2176
+    m = 1.33 + 0.01j
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    khat, es, L = dda.waves_for_orientation(0.0, 0.0, 0.0)
+    prec = P.DDA_SOLVE_FP64 if prec_name == "fp64" else P.DDA_SOLVE_FP32_REFINE
+    Pg, stats, status = ctx.solve([khat, khat], es, tol=1e-5, prec=prec)
+    assert status == 0
+    qg = ctx.cross_sections(2)
+    th = np.deg2rad(np.arange(0, 181, 5.0))
+    Ps_or = []
+    for l, e in enumerate(es):
+        ainv = dda.site_inverse_polarizability(comp, [m], kd, dda.ALPHA_LDR, khat, e)
+        E = dda.incident_field(r, kd, khat, e)
+        Po, info = dda.solve_iterative(r, kd, ainv, E, tol=1e-11)
+        Ps_or.append(Po)
+        rel, _ = dda.residual_norms(r, kd, ainv, E, Pg[l])
+        assert rel <= 1e-5 and stats[l]["rel_resid"] <= 1e-5
+        assert abs(rel - stats[l]["rel_resid"]) < 1e-7
+        qo = np.array(dda.cross_sections(kd, E, Po, ainv))
+        assert np.all(np.abs(qg[l] - qo) / np.abs(qo) < 1e-4), (qg[l], qo)
+    # amplitudes: directions in the two scattering planes
+    for phi in (0.0, np.pi / 2):
+        ph = np.full_like(th, phi)
+        n_lab, t_lab, p_lab = scatter.lab_direction_basis(th, ph)
+        n_tf, t_tf, p_tf = n_lab @ L, t_lab @ L, p_lab @ L
+        f = ctx.amplitudes(2, n_tf, np.concatenate([t_tf, p_tf], axis=1))  # (rhs, dir, m)
+        fo = scatter.scattering_amplitudes(r, kd, Ps_or, th, ph, L)       # (dir, m, l)
+        fg = np.transpose(f, (1, 2, 0))
+        assert np.max(np.abs(fg - fo)) / np.max(np.abs(fo)) < 1e-4
+
+
+def test_solve_fp32_refine_matches_fp64(ctx):
+    """Mixed precision meets the FP64 residual bar and agrees with the all-FP64 solve."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.sphere_occupancy(24)
+    ctx.set_target(occ, [1.5 + 0.1j], 0.5, P.DDA_ALPHA_LDR)
+    khat, es, L = dda.waves_for_orientation(0.3, 0.7, 1.1)
+    P64, s64, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP64)
+    q64 = ctx.cross_sections(2)
+    P32, s32, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP32_REFINE)
+    q32 = ctx.cross_sections(2)
+    for l in range(2):
+        assert s32[l]["rel_resid"] <= 1e-5 and s64[l]["rel_resid"] <= 1e-5
+        assert _rel(P32[l], P64[l]) < 1e-4
+    assert np.all(np.abs(q32 - q64) / np.abs(q64) < 1e-4)
+
+
+def test_guesses_user_prev_and_fallback(ctx):
+    import paper_1002_1505_amd as P
+
+    occ = synth.sphere_occupancy(12)
+    ctx.set_target(occ, [1.4 + 0.05j], 0.4, P.DDA_ALPHA_LDR)
+    khat, es, L = dda.waves_for_orientation(0.0, 0.5, 0.0)
+    P0, s0, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP64, tol=1e-8)
+    # exact guess: converged before any iteration
+    P1, s1, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP64, tol=1e-5, guess=P.DDA_GUESS_USER, p0=P0)
+    assert all(s["iters"] == 0 for s in s1)
+    # previous solution as guess
+    P2, s2, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP64, tol=1e-5, guess=P.DDA_GUESS_PREV)
+    assert all(s["iters"] == 0 for s in s2)
+    # a guess worse than zero is replaced by zero
+    bad = [100 * p for p in P0]
+    P3, s3, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP64, tol=1e-5, guess=P.DDA_GUESS_USER, p0=bad)
+    assert all(s["guess_resid"] == 1.0 and s["rel_resid"] <= 1e-5 for s in s3)
+
+
+def test_batched_uneven_targets_match_single_solves(ctx):
+    """Three targets of different boxes in one call give the same P as
+    separate calls (per-rhs convergence masks, graph replay)."""
+    import paper_1002_1505_amd as P
+
+    rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 3)
+    occs = [synth.random_ellipsoid(n, rng)[0] for n in (16, 24, 32)]
+    ms = [1.3 + 0.01j, 1.6 + 0.2j, 1.45 + 0.05j]
+    kds = [0.4, 0.35, 0.3]
+    ori = synth.uniform_orientations(2, rng)
+    waves_k, waves_e, tg = [], [], []
+    ctx.set_target(occs[0], [ms[0]], kds[0])
+    for t in (1, 2):
+        ctx.add_target(occs[t], [ms[t]], kds[t])
+    for t in range(3):
+        for b, th, ph in ori:
+            kh, es, L = dda.waves_for_orientation(b, th, ph)
+            for e in es:
+                waves_k.append(kh)
+                waves_e.append(e)
+                tg.append(t)
+    Pb, sb, _ = ctx.solve(waves_k, waves_e, targets=tg, prec=P.DDA_SOLVE_FP32_REFINE)
+    qb = ctx.cross_sections(len(tg))
+    for t in range(3):
+        sel = [i for i in range(len(tg)) if tg[i] == t]
+        ctx.set_target(occs[t], [ms[t]], kds[t])
+        Ps, ss, _ = ctx.solve([waves_k[i] for i in sel], [waves_e[i] for i in sel], prec=P.DDA_SOLVE_FP32_REFINE)
+        qs = ctx.cross_sections(len(sel))
+        for k, i in enumerate(sel):
+            assert sb[i]["rel_resid"] <= 1e-5
+            assert _rel(Pb[i], Ps[k]) < 3e-5
+            assert np.all(np.abs(qb[i] - qs[k]) / np.abs(qs[k]) < 1e-4)
+
+
+def test_graph_and_eager_agree(ctx):
+    import paper_1002_1505_amd as P
+
+    occ = synth.sphere_occupancy(16)
+    ctx.set_target(occ, [1.5 + 0.1j], 0.4)
+    khat, es, L = dda.waves_for_orientation(0.2, 0.4, 0.6)
+    Pg, sg, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP32_REFINE)
+    Pe, se, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP32_REFINE, flags=P.DDA_NO_GRAPH)
+    for l in range(2):
+        assert sg[l]["iters"] == se[l]["iters"]
+        assert _rel(Pg[l], Pe[l]) < 1e-6
