@@ -215,6 +215,24 @@ dda_status dda_lab_frame(double beta, double theta, double phi, const double* a1
  * candidates on the device; results are cached in the JSON file named by
  * `cache_path` (NULL: the DDA_TUNE_CACHE environment variable, else no
  * file).  `nrhs_hint` is the batch size to tune for. */
+/* The two incident waves of orientation (beta, Theta, Phi): khat = x_LF, and
+ * the polarizations e01 (lab frame, 6 doubles, normalized here) and
+ * e02 = x_LF x conj(e01) (guide, sections "Target Orientation" and "Incident
+ * Polarization State"), all expressed in the target frame.  a1, a2: target
+ * axes in the target frame (NULL: x, y).  e01 NULL means y_LF.  out[0..1]
+ * receive the waves with target = `target`. */
+dda_status dda_orientation_waves(double beta, double theta, double phi, const double* a1, const double* a2,
+                                 const double* e01, int32_t target, dda_wave* out);
+
+/* Target-frame scattering directions and polarization basis for lab-frame
+ * scattering angles: n = x cos(theta) + y sin(theta) cos(phi) + z sin(theta)
+ * sin(phi) (guide, section "Scattering Directions", LFRAME), e_1 = theta_hat
+ * (parallel to the scattering plane) and e_2 = phi_hat (guide, section
+ * "Scattering by Finite Targets: The Mueller Matrix").  lab_axes: 9 doubles
+ * from dda_lab_frame.  n_tf: ndir x 3, e_tf: ndir x 6 (e_1 then e_2). */
+dda_status dda_scattering_frame(int32_t ndir, const double* theta, const double* phi, const double* lab_axes,
+                                double* n_tf, double* e_tf);
+
 dda_status dda_autotune(dda_ctx* ctx, int32_t nrhs_hint, const char* cache_path);
 
 /* Timing of the last solve: milliseconds in FP32 matvecs, FP64 matvecs,

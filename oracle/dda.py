@@ -239,6 +239,8 @@ def _direct_lib():
         lib.oracle_matvec_rows.argtypes = [ctypes.c_int64, P, ctypes.c_double, P, P,
                                            ctypes.c_int64, P, P]
         lib.oracle_matvec_rows.restype = None
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -252,6 +254,11 @@ def matvec_direct(r, k, ainv, x):
     _direct_lib().oracle_matvec(len(r), r.ctypes.data, float(k), ainv.ctypes.data,
                                 x.ctypes.data, y.ctypes.data)
     return y
+
+
+def threads() -> int:
+    """OpenMP threads used by the direct matvec."""
+    return int(_direct_lib().oracle_threads())
 
 
 def matvec_rows(r, k, ainv, x, rows):

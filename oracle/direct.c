@@ -90,3 +90,7 @@ void oracle_matvec_rows(int64_t n, const double* r, double k, const cplx* ainv,
         for (int a = 0; a < 3; ++a) y[3 * s + a] = acc[a] + ainv[j] * x[3 * j + a];
     }
 }
+
+/* Threads OpenMP will use for the loops above. */
+#include <omp.h>
+int oracle_threads(void) { return omp_get_max_threads(); }

@@ -15,7 +15,7 @@ from ._lib import (DDA_ALPHA_CM, DDA_ALPHA_CM_RR, DDA_ALPHA_LDR, DDA_DEVICE_PTRS
                    DDA_GUESS_NN, DDA_GUESS_PREV, DDA_GUESS_USER, DDA_GUESS_ZERO, DDA_NO_FALLBACK, DDA_NO_GRAPH,
                    DDA_SOLVE_FP32_REFINE, DDA_SOLVE_FP64, DDA_WARN_MKD_GE_1, DDA_WARN_NOT_CONVERGED)
 
-__all__ = ["Context", "DDAError", "lab_frame", "mueller", "load_library"]
+__all__ = ["Context", "DDAError", "lab_frame", "mueller", "orientation_waves", "scattering_frame", "load_library"]
 
 
 class DDAError(RuntimeError):
@@ -219,6 +219,40 @@ def lab_frame(beta, theta, phi, a1=None, a2=None):
     if st < 0:
         raise DDAError(st, "dda_lab_frame")
     return out.reshape(3, 3)
+
+
+def orientation_waves(beta, theta, phi, e01=None, a1=None, a2=None, target=0):
+    """(khat (2, 3), e0 (2, 3) complex) of the two incident polarizations of an
+    orientation, in the target frame (dda_orientation_waves)."""
+    lib = L.load()
+    out = (L.dda_wave * 2)()
+    e = None
+    if e01 is not None:
+        ev = np.asarray(e01, dtype=np.complex128)
+        e = np.ascontiguousarray(np.stack([ev.real, ev.imag], axis=1).reshape(-1))
+    a1 = None if a1 is None else np.ascontiguousarray(a1, dtype=np.float64)
+    a2 = None if a2 is None else np.ascontiguousarray(a2, dtype=np.float64)
+    st = lib.dda_orientation_waves(float(beta), float(theta), float(phi), None if a1 is None else _dptr(a1),
+                                   None if a2 is None else _dptr(a2), None if e is None else _dptr(e), int(target), out)
+    if st < 0:
+        raise DDAError(st, "dda_orientation_waves")
+    kh = np.array([[out[w].khat[i] for i in range(3)] for w in range(2)])
+    e0 = np.array([[out[w].e0[2 * i] + 1j * out[w].e0[2 * i + 1] for i in range(3)] for w in range(2)])
+    return kh, e0
+
+
+def scattering_frame(theta, phi, lab_axes):
+    """(n_tf (ndir, 3), e_tf (ndir, 6)) for lab-frame scattering angles (dda_scattering_frame)."""
+    lib = L.load()
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(-1)
+    ph = np.ascontiguousarray(np.broadcast_to(phi, th.shape), dtype=np.float64)
+    La = np.ascontiguousarray(lab_axes, dtype=np.float64).reshape(-1)
+    n = np.zeros((len(th), 3))
+    e = np.zeros((len(th), 6))
+    st = lib.dda_scattering_frame(len(th), _dptr(th), _dptr(ph), _dptr(La), _dptr(n), _dptr(e))
+    if st < 0:
+        raise DDAError(st, "dda_scattering_frame")
+    return n, e
 
 
 def mueller(f, phi, e01, e02):

@@ -77,6 +77,9 @@ SIGNATURES = {
     "dda_amplitudes": (C.c_int32, [P, C.c_int32, C.c_int32, D, D, D]),
     "dda_mueller": (C.c_int32, [C.c_int32, D, D, D, D, D, D]),
     "dda_lab_frame": (C.c_int32, [C.c_double, C.c_double, C.c_double, D, D, D]),
+    "dda_orientation_waves": (C.c_int32, [C.c_double, C.c_double, C.c_double, D, D, D, C.c_int32,
+                                          C.POINTER(dda_wave)]),
+    "dda_scattering_frame": (C.c_int32, [C.c_int32, D, D, D, D, D]),
     "dda_autotune": (C.c_int32, [P, C.c_int32, C.c_char_p]),
     "dda_last_timing": (C.c_int32, [P, D, D, D]),
     "dda_profile_matvec": (C.c_int32, [P, C.c_int32, C.c_int32, C.c_uint32, C.c_int32, D, D]),

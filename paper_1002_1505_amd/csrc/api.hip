@@ -1085,6 +1085,50 @@ dda_status dda_lab_frame(double beta, double theta, double phi, const double* a1
     return DDA_OK;
 }
 
+dda_status dda_orientation_waves(double beta, double theta, double phi, const double* a1, const double* a2,
+                                 const double* e01, int32_t target, dda_wave* out) {
+    if (!out) return DDA_ERR_INVALID_ARG;
+    double L[9];
+    dda_status s = dda_lab_frame(beta, theta, phi, a1, a2, L);
+    if (s < 0) return s;
+    cd e1[3] = {cd(0, 0), cd(1, 0), cd(0, 0)};
+    if (e01)
+        for (int j = 0; j < 3; ++j) e1[j] = cd(e01[2 * j], e01[2 * j + 1]);
+    const double nrm = std::sqrt(std::norm(e1[0]) + std::norm(e1[1]) + std::norm(e1[2]));
+    if (!(nrm > 0)) return DDA_ERR_INVALID_ARG;
+    for (auto& v : e1) v /= nrm;
+    // e02 = x_LF x conj(e01) in lab components
+    const cd c1[3] = {std::conj(e1[0]), std::conj(e1[1]), std::conj(e1[2])};
+    const cd e2[3] = {cd(0, 0), -c1[2], c1[1]};
+    const cd* es[2] = {e1, e2};
+    for (int w = 0; w < 2; ++w) {
+        for (int i = 0; i < 3; ++i) {
+            out[w].khat[i] = L[i];
+            cd v = es[w][0] * L[i] + es[w][1] * L[3 + i] + es[w][2] * L[6 + i];
+            out[w].e0[2 * i] = v.real();
+            out[w].e0[2 * i + 1] = v.imag();
+        }
+        out[w].target = target;
+        out[w].pad_ = 0;
+    }
+    return DDA_OK;
+}
+
+dda_status dda_scattering_frame(int32_t ndir, const double* theta, const double* phi, const double* L, double* n_tf,
+                                double* e_tf) {
+    if (ndir <= 0 || !theta || !phi || !L || !n_tf || !e_tf) return DDA_ERR_INVALID_ARG;
+    for (int d = 0; d < ndir; ++d) {
+        const double ct = std::cos(theta[d]), st = std::sin(theta[d]), cp = std::cos(phi[d]), sp = std::sin(phi[d]);
+        const double nl[3] = {ct, st * cp, st * sp}, tl[3] = {-st, ct * cp, ct * sp}, pl[3] = {0, -sp, cp};
+        for (int i = 0; i < 3; ++i) {
+            n_tf[3 * d + i] = nl[0] * L[i] + nl[1] * L[3 + i] + nl[2] * L[6 + i];
+            e_tf[6 * d + i] = tl[0] * L[i] + tl[1] * L[3 + i] + tl[2] * L[6 + i];
+            e_tf[6 * d + 3 + i] = pl[0] * L[i] + pl[1] * L[3 + i] + pl[2] * L[6 + i];
+        }
+    }
+    return DDA_OK;
+}
+
 dda_status dda_last_timing(const dda_ctx* c, double* a, double* b, double* t) {
     if (!c) return DDA_ERR_INVALID_ARG;
     if (a) *a = c->ms_mv32;
