@@ -207,7 +207,7 @@ MvShape default_shape(const Target& t, int tx_pref) {
         s.tx = tx;
         const int bz = (g.n3 / rmin(t.plans[2])) * 6 * tx;
         s.nth_z = std::max(256, round64((bz + 3) / 4));
-        if ((s.nth_z <= 1024 && matvec_shape_ok<T>(g, t.plans, MvShape{0, 64, s.nth_z, tx, 16, 256})) || tx == 1) break;
+        if ((s.nth_z <= 1024 && matvec_shape_ok<T>(g, t.plans, MvShape{0, 64, s.nth_z, tx, 16, 256, 0})) || tx == 1) break;
     }
     // planes
     const int np = g.n1 * g.n2;
@@ -215,7 +215,23 @@ MvShape default_shape(const Target& t, int tx_pref) {
     int nth = std::max({(np + 15) / 16, (bx + 3) / 4, (by + 3) / 4});
     s.nth_plane = std::max(256, round64(nth));
     s.fused = 1;
+    s.ct = 0;
     if (!matvec_shape_ok<T>(g, t.plans, s)) s.fused = 0;
+    if (ct_supported(g.n1, g.n2, g.n3)) {
+        // specialised kernels; z tile 16 columns unless only another fits
+        MvShape c = s;
+        for (int txc : {16, 32, 8}) {
+            c.tx = txc;
+            c.ct = ct_available<T>(g.n1, txc);
+            if ((c.ct & 2) && matvec_shape_ok<T>(g, t.plans, c)) break;
+        }
+        if (!(c.ct & 2)) {
+            c.tx = s.tx;
+            c.ct = ct_available<T>(g.n1, s.tx) & 1;
+        }
+        // a generic z pass needs its own thread count for the chosen tile
+        if (c.ct && matvec_shape_ok<T>(g, t.plans, c)) s = c;
+    }
     return s;
 }
 
@@ -556,7 +572,8 @@ dda_status dda_create(dda_ctx** out, int32_t device, void* hip_stream) {
         }
         c->own_stream = true;
     }
-    if (configure_fft_kernels() != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
+    if (configure_fft_kernels() != hipSuccess || configure_ct_kernels() != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess) {
         delete c;
         return DDA_ERR_HIP;

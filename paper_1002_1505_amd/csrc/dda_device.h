@@ -206,3 +206,72 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     }
     return s;
 }
+
+// ---------------------------------------------------------------------------
+// Compile-time FFT: line length, radix plan, number of lines, threads and
+// LDS addressing are template constants, so every index is a shift or a
+// multiply by a constant and the per-thread butterfly registers are sized
+// exactly.  Same Stockham scheme as fft_pass above.
+// ---------------------------------------------------------------------------
+template <int N> struct RadixPlan;
+template <> struct RadixPlan<2> { static constexpr int np = 1; static constexpr int r[1] = {2}; };
+template <> struct RadixPlan<4> { static constexpr int np = 1; static constexpr int r[1] = {4}; };
+template <> struct RadixPlan<8> { static constexpr int np = 1; static constexpr int r[1] = {8}; };
+template <> struct RadixPlan<16> { static constexpr int np = 2; static constexpr int r[2] = {4, 4}; };
+template <> struct RadixPlan<32> { static constexpr int np = 2; static constexpr int r[2] = {8, 4}; };
+template <> struct RadixPlan<48> { static constexpr int np = 3; static constexpr int r[3] = {3, 4, 4}; };
+template <> struct RadixPlan<64> { static constexpr int np = 2; static constexpr int r[2] = {8, 8}; };
+template <> struct RadixPlan<96> { static constexpr int np = 3; static constexpr int r[3] = {3, 8, 4}; };
+template <> struct RadixPlan<128> { static constexpr int np = 3; static constexpr int r[3] = {8, 4, 4}; };
+template <> struct RadixPlan<256> { static constexpr int np = 3; static constexpr int r[3] = {8, 8, 4}; };
+
+// Line l of the LDS batch starts at (l / LG) * LS1 + (l % LG) * LS0; its
+// elements are ES apart.
+template <class T, int DIR, int N, int R, int L, int NL, int NTH, int LG, int LS0, int LS1, int ES>
+__device__ __forceinline__ void ct_pass(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int tid) {
+    constexpr int NB = N / R, TOT = NB * NL, MB = (TOT + NTH - 1) / NTH, TWS = N / (L * R);
+    Cx<T> v[MB][R];
+#pragma unroll
+    for (int c = 0; c < MB; ++c) {
+        const int b = tid + c * NTH;
+        if ((TOT % NTH) == 0 || b < TOT) {
+            const int l = b % NL, j = b / NL;
+            const int base = (l / LG) * LS1 + (l % LG) * LS0;
+            const int k = j % L;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                Cx<T> a = buf[base + (j + t * NB) * ES];
+                if (L > 1 && t > 0) {
+                    Cx<T> w = tw[t * k * TWS];
+                    if (DIR > 0) w.im = -w.im;
+                    a = a * w;
+                }
+                v[c][t] = a;
+            }
+            bfly<T, DIR, R>(v[c]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < MB; ++c) {
+        const int b = tid + c * NTH;
+        if ((TOT % NTH) == 0 || b < TOT) {
+            const int l = b % NL, j = b / NL;
+            const int base = (l / LG) * LS1 + (l % LG) * LS0;
+            const int k = j % L;
+            const int ob = (j - k) * R + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) buf[base + (ob + t * L) * ES] = v[c][t];
+        }
+    }
+    __syncthreads();
+}
+
+template <class T, int DIR, int N, int NL, int NTH, int LG, int LS0, int LS1, int ES, int P = 0, int L = 1>
+__device__ __forceinline__ void ct_fft(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int tid) {
+    if constexpr (P < RadixPlan<N>::np) {
+        constexpr int R = RadixPlan<N>::r[P];
+        ct_pass<T, DIR, N, R, L, NL, NTH, LG, LS0, LS1, ES>(buf, tw, tid);
+        ct_fft<T, DIR, N, NL, NTH, LG, LS0, LS1, ES, P + 1, L * R>(buf, tw, tid);
+    }
+}

@@ -47,6 +47,7 @@ struct MvShape {
     int tx;          // columns per z-pass block
     int lines_tl;    // lines per block in the line-kernel fallback
     int nth_lines;
+    int ct;          // bit 0: specialised plane kernels, bit 1: specialised z pass (cubic boxes)
 };
 
 enum { MV_AX = 0, MV_RESID = 1 };
@@ -141,3 +142,13 @@ hipError_t launch_ampl(const Geo& g, const double* origin3, double k, int nrhs, 
                        const double* ndirs, Cx<double>* F, hipStream_t st);
 
 hipError_t configure_fft_kernels();
+
+// ---- compile-time specialised passes (kernels_ct.hip) ----
+bool ct_supported(int n1, int n2, int n3);
+template <class T>
+int ct_available(int n, int tx);
+template <class T>
+hipError_t launch_pass_ct(int which, int tx, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
+                          const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv, const int* active,
+                          int mode, hipStream_t st);
+hipError_t configure_ct_kernels();

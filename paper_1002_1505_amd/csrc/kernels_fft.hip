@@ -463,6 +463,12 @@ static int rmin_of(const FftPlan& p) {
 template <class T>
 bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh) {
     const size_t lds_max = 160 * 1024;
+    if (sh.ct) {
+        if (g.n1 != g.n2 || g.n2 != g.n3) return false;
+        const int av = ct_available<T>(g.n1, sh.tx);
+        if ((sh.ct & av) != sh.ct) return false;
+        if (sh.ct == 3) return true;
+    }
     if (sh.tx <= 0 || (g.n1 % sh.tx) != 0) return false;
     if (zpass_smem<T>(g, sh.tx) > lds_max) return false;
     const int bz = (g.n3 / rmin_of(plans[2])) * 6 * sh.tx;
@@ -485,6 +491,8 @@ hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* 
                        const int* active, int mode, hipStream_t st) {
     const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
     const long long np = (long long)n1 * n2;
+    if ((which == 1 && (sh.ct & 2)) || (which != 1 && (sh.ct & 1)))
+        return launch_pass_ct<T>(which, sh.tx, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, st);
     if (which == 0) {
         if (sh.fused) {
             const int nplanes = nrhs * 3 * n3;
