@@ -37,6 +37,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the CPU sample")
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--x", type=float, default=10.0)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--train-targets", type=int, default=8)
+    ap.add_argument("--train-orient", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--eval-targets", type=int, default=2)
+    ap.add_argument("--sweep", type=int, default=32)
     return ap.parse_args()
 
 
@@ -107,7 +113,13 @@ def main():
     q_rel = float(np.max(np.abs(q - q64) / np.abs(q64)))
     # per-pass matvec roofline (FP32, the solve's launch shapes, both rhs)
     ms, by = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP32, reps=20)
-    names = ["k_plane_fwd<float>", "k_zpass<float>", "k_plane_inv<float>"]
+    sh = ctx.get_shape(0, P.DDA_FP32)
+    if sh["ct"] & 1:
+        names = [f"k_pfwd_ct<float, {n}>",
+                 f"k_zpass2_ct<float, {n}, {sh['tx']}, 8>" if sh["zrb"] else f"k_zpass_ct<float, {n}, {sh['tx']}>",
+                 f"k_pinv_ct<float, {n}, 0, 1|2>"]
+    else:
+        names = ["k_plane_fwd<float>", "k_zpass<float>", "k_plane_inv<float, 0>"]
     dom = int(np.argmax(ms))
     gbs = by / (ms * 1e-3) / 1e9
     mv_ms = float(ms.sum())
@@ -143,6 +155,7 @@ def main():
             "traffic": None,
             "bytes_per_launch": float(by[dom]),
             "avg_launch_ms": round(float(ms[dom]), 5),
+            "shape": sh,
         },
         "matvec": {
             "nrhs": 2,
@@ -171,10 +184,94 @@ def main():
         },
         "setup_s": round(setup_s, 3),
     }
+    if not a.no_learned:
+        out["learned"] = learned_vs_plain(P, ctx, a)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(occ, kd, m, stats[-1], a.cpu_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def _aggregate_problem(synth, rng):
+    occ = synth.aggregate_occupancy(64, rng)
+    N = int(occ.sum())
+    aeff = (3.0 * N / (4.0 * np.pi)) ** (1.0 / 3.0)
+    x = rng.uniform(2.0, 10.0)
+    m = complex(rng.uniform(1.3, 1.7), rng.uniform(0.01, 0.1))
+    return occ, m, x / aeff
+
+
+def learned_vs_plain(P, ctx, a):
+    """Learned initial guess on porous aggregates in a 64^3 box (seeded
+    Gaussian-random-field targets, fill 0.3, m = U[1.3,1.7] + i U[0.01,0.1],
+    x = U[2,10]).  Training fields come from the solver on held-in targets
+    (orientation sweeps uniform in cos Theta); evaluation runs orientation
+    sweeps on held-out targets one orientation (2 polarizations) per solve,
+    with P0 = 0, P0 = previous orientation's P, and P0 from the network."""
+    import torch
+
+    import synth
+
+    rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 5)
+    net = P.Net(ctx, width=32, depth=6, seed=5)
+    t0 = time.perf_counter()
+    for _ in range(a.train_targets):
+        occ, m, kd = _aggregate_problem(synth, rng)
+        ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+        ori = synth.theta_sweep(a.train_orient, beta=rng.uniform(0, 2 * np.pi), phi=rng.uniform(0, 2 * np.pi))
+        kh, ee = [], []
+        for b, t, p in ori:
+            k2, e2 = P.orientation_waves(b, t, p)
+            kh += list(k2)
+            ee += list(e2)
+        ctx.solve(kh, ee, tol=1e-5, want_p=False)
+        net.record()
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss = net.train(epochs=a.epochs, batch=4, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    net.attach()
+    res = {"zero": [0, 0.0, 0], "prev": [0, 0.0, 0], "nn": [0, 0.0, 0]}  # iters, seconds, solves
+    guess_ms = 0.0
+    resid = {"zero": [], "prev": [], "nn": []}
+    for _ in range(a.eval_targets):
+        occ, m, kd = _aggregate_problem(synth, rng)
+        ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+        ori = synth.theta_sweep(a.sweep, beta=rng.uniform(0, 2 * np.pi), phi=rng.uniform(0, 2 * np.pi))
+        waves = [P.orientation_waves(b, t, p) for b, t, p in ori]
+        ctx.solve(waves[0][0], waves[0][1], want_p=False)  # warm-up (workspace, graph)
+        for mode, g in (("zero", P.DDA_GUESS_ZERO), ("prev", P.DDA_GUESS_PREV), ("nn", P.DDA_GUESS_NN)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for i, (kh, ee) in enumerate(waves):
+                gg = P.DDA_GUESS_ZERO if (mode == "prev" and i == 0) else g
+                _, st, _ = ctx.solve(kh, ee, tol=1e-5, guess=gg, want_p=False)
+                res[mode][0] += sum(s["iters"] for s in st)
+                res[mode][2] += sum(1 for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
+                resid[mode] += [s["guess_resid"] for s in st]
+                if mode == "nn":
+                    guess_ms += ctx.last_timing().get("ms_guess", 0.0)
+            torch.cuda.synchronize()
+            res[mode][1] += time.perf_counter() - t1
+    n_solves = 2 * a.sweep * a.eval_targets
+    out = {
+        "workload": f"porous aggregates in 64^3 box, {a.train_targets} training targets x {a.train_orient} "
+                    f"orientations x 2 pol ({net.num_samples} fields), {a.eval_targets} held-out targets x "
+                    f"{a.sweep}-orientation sweeps x 2 pol, one orientation per solve, tol 1e-5",
+        "params": net.num_params,
+        "train_loss": loss,
+        "gen_s": round(gen_s, 2),
+        "train_s": round(train_s, 2),
+    }
+    for mode in res:
+        it, sec, conv = res[mode]
+        out[mode] = {"solves_per_s": round(conv / sec, 3), "mean_iters": round(it / n_solves, 2),
+                     "converged": f"{conv}/{n_solves}", "mean_guess_resid": round(float(np.mean(resid[mode])), 4)}
+    out["nn_vs_zero"] = round(out["nn"]["solves_per_s"] / out["zero"]["solves_per_s"], 3)
+    out["nn_vs_prev"] = round(out["nn"]["solves_per_s"] / out["prev"]["solves_per_s"], 3)
+    net.close()
+    return out
 
 
 def cpu_baseline(occ, kd, m, stats, seconds):

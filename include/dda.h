@@ -235,6 +235,17 @@ dda_status dda_scattering_frame(int32_t ndir, const double* theta, const double*
 
 dda_status dda_autotune(dda_ctx* ctx, int32_t nrhs_hint, const char* cache_path);
 
+/* Milliseconds the last solve spent producing its learned initial guess. */
+dda_status dda_last_guess_ms(const dda_ctx* ctx, double* ms);
+
+/* Launch shape of a target's matvec passes for precision DDA_FP32 or
+ * DDA_FP64, as 8 integers: {planes in LDS, plane threads, z threads, z tile
+ * columns, fallback lines per block, fallback threads, specialised kernels
+ * bitmask, z pass over 8 rhs per block}.  dda_set_shape rejects shapes that do
+ * not fit the kernels' LDS or thread limits. */
+dda_status dda_get_shape(const dda_ctx* ctx, int32_t target, uint32_t prec, int32_t* out8);
+dda_status dda_set_shape(dda_ctx* ctx, int32_t target, uint32_t prec, const int32_t* in8);
+
 /* Timing of the last solve: milliseconds in FP32 matvecs, FP64 matvecs,
  * and the whole call (device events).  Any pointer may be NULL. */
 dda_status dda_last_timing(const dda_ctx* ctx, double* ms_mv32, double* ms_mv64, double* ms_total);
@@ -246,6 +257,59 @@ dda_status dda_last_timing(const dda_ctx* ctx, double* ms_mv32, double* ms_mv64,
  * pass per launch.  Either pointer may be NULL. */
 dda_status dda_profile_matvec(dda_ctx* ctx, int32_t target, int32_t nrhs, uint32_t prec, int32_t reps,
                               double* ms, double* bytes);
+
+/* ---- Learned initial guess ----
+ * A 3D convolutional network on the target's cubic box (side divisible by
+ * 16) predicts the local field E_loc = E_inc + net(features) at the occupied
+ * sites; the guess is P0 = E_loc / (1/alpha).  Features per voxel:
+ * occupancy, E_inc, (eps-1)/(eps+2), k d, khat.  3x3x3 convolutions with
+ * dilations 1, 2, 4, 8, ReLU; BF16 operands on MFMA with FP32 accumulation;
+ * FP32 master weights trained with Adam on fields the solver produced
+ * (dda_nn_record).  The network of zeros reproduces P0 = alpha E_inc.  A
+ * guess is used only if its FP64 residual is below ||E|| (else P0 = 0). */
+typedef struct dda_nn dda_nn;
+
+typedef struct {
+    int32_t width;      /* hidden channels: 16 or 32 */
+    int32_t depth;      /* number of convolution layers, >= 2 */
+    int32_t seed;       /* weight initialisation seed */
+    int32_t reserved;
+} dda_nn_config;
+
+typedef struct {
+    int32_t epochs;
+    int32_t batch;      /* samples per Adam step (<= 8) */
+    double lr;          /* Adam learning rate */
+    double weight_decay;
+    int32_t reserved[4];
+} dda_nn_train_opts;
+
+dda_status dda_nn_create(dda_ctx* ctx, const dda_nn_config* cfg, dda_nn** out);
+dda_status dda_nn_destroy(dda_nn* nn);
+int64_t dda_nn_num_params(const dda_nn* nn);
+int32_t dda_nn_num_samples(const dda_nn* nn);
+/* Layer shapes: depth x {cin, cout, dilation}. */
+dda_status dda_nn_layer_info(const dda_nn* nn, int32_t* out3);
+/* Flat FP32 parameters: per layer W[27][cin][cout] (offset index
+ * (dz+1)*9 + (dy+1)*3 + (dx+1)) then b[cout]. */
+dda_status dda_nn_get_params(const dda_nn* nn, float* out);
+dda_status dda_nn_set_params(dda_nn* nn, const float* in);
+/* Attach a network as the DDA_GUESS_NN model of the context (NULL detaches). */
+dda_status dda_set_guess_model(dda_ctx* ctx, dda_nn* nn);
+/* Record every solution of the last solve as a training sample. */
+dda_status dda_nn_record(dda_ctx* ctx, dda_nn* nn);
+/* Train on the recorded samples; mean loss of the last epoch in *loss. */
+dda_status dda_nn_train(dda_ctx* ctx, dda_nn* nn, const dda_nn_train_opts* opts, double* loss);
+dda_status dda_nn_save(const dda_nn* nn, const char* path);
+dda_status dda_nn_load(dda_nn* nn, const char* path);
+/* Test hook on dense host arrays over a D^3 box (D >= 16): x_in [ns][D^3][16],
+ * target [ns][D^3][16], mask [ns][D^3]; runs the forward pass (out, [ns][D^3][16],
+ * may be NULL) and, when target, mask and grads are given, the masked mean
+ * squared error over the first nout channels normalised per sample by the
+ * target's squared norm, averaged over samples, and its parameter gradients
+ * (flat, as dda_nn_get_params). */
+dda_status dda_nn_forward_backward(dda_nn* nn, int32_t ns, int32_t D, const float* x_in, const float* target,
+                                   const uint8_t* mask, int32_t nout, float* out, float* grads, double* loss);
 
 #ifdef __cplusplus
 }

@@ -15,4 +15,4 @@ mathematics independent of the oracle): the numerical values of the LDR
 coefficients b1, b2, b3 (recalled from Draine & Goodman 1993, not printed in
 the guide).  Everything else is pinned by ``tests/test_oracle_*.py``.
 """
-from . import dda, mie, scatter  # noqa: F401
+from . import dda, mie, nn, scatter  # noqa: F401

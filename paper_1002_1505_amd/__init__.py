@@ -65,7 +65,7 @@ class Context:
         h = C.c_void_p()
         st = self.lib.dda_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None)
         if st < 0:
-            raise DDAError(st, "dda_create failed (no HIP device?)")
+            raise DDAError(st, "dda_create failed: " + self.lib.dda_last_error(None).decode())
         self.h = h
         self.n_sites = {}
 
@@ -193,9 +193,10 @@ class Context:
         return f[..., 0] + 1j * f[..., 1]
 
     def last_timing(self):
-        a, b, t = C.c_double(), C.c_double(), C.c_double()
+        a, b, t, g = C.c_double(), C.c_double(), C.c_double(), C.c_double()
         self.lib.dda_last_timing(self.h, C.byref(a), C.byref(b), C.byref(t))
-        return dict(ms_mv32=a.value, ms_mv64=b.value, ms_total=t.value)
+        self.lib.dda_last_guess_ms(self.h, C.byref(g))
+        return dict(ms_mv32=a.value, ms_mv64=b.value, ms_total=t.value, ms_guess=g.value)
 
     def profile_matvec(self, target=0, nrhs=1, prec=DDA_FP32, reps=10):
         ms = np.zeros(3)
@@ -203,6 +204,17 @@ class Context:
         _check(self.h, self.lib.dda_profile_matvec(self.h, int(target), int(nrhs), int(prec), int(reps), _dptr(ms),
                                                    _dptr(by)))
         return ms, by
+
+    def get_shape(self, target=0, prec=DDA_FP32):
+        out = (C.c_int32 * 8)()
+        _check(self.h, self.lib.dda_get_shape(self.h, int(target), int(prec), out))
+        keys = ["fused", "nth_plane", "nth_z", "tx", "lines_tl", "nth_lines", "ct", "zrb"]
+        return dict(zip(keys, list(out)))
+
+    def set_shape(self, shape: dict, target=0, prec=DDA_FP32):
+        keys = ["fused", "nth_plane", "nth_z", "tx", "lines_tl", "nth_lines", "ct", "zrb"]
+        arr = (C.c_int32 * 8)(*[int(shape[k]) for k in keys])
+        _check(self.h, self.lib.dda_set_shape(self.h, int(target), int(prec), arr))
 
     def autotune(self, nrhs_hint=2, cache_path=None):
         return _check(self.h, self.lib.dda_autotune(self.h, int(nrhs_hint),
@@ -273,3 +285,96 @@ def mueller(f, phi, e01, e02):
         raise DDAError(st, "dda_mueller")
     S = S.reshape(ndir, 4, 2)
     return S[..., 0] + 1j * S[..., 1], M.reshape(ndir, 4, 4)
+
+
+class Net:
+    """Learned initial-guess network (dda_nn_*)."""
+
+    def __init__(self, ctx: Context, width=32, depth=6, seed=1):
+        self.lib = L.load()
+        self.ctx = ctx
+        h = C.c_void_p()
+        cfg = L.dda_nn_config(width=width, depth=depth, seed=seed)
+        st = self.lib.dda_nn_create(ctx.h, C.byref(cfg), C.byref(h))
+        if st < 0:
+            raise DDAError(st, "dda_nn_create failed")
+        self.h = h
+        self.depth = depth
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dda_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(self.lib.dda_nn_num_params(self.h))
+
+    @property
+    def num_samples(self) -> int:
+        return int(self.lib.dda_nn_num_samples(self.h))
+
+    def layers(self):
+        out = (C.c_int32 * (3 * self.depth))()
+        _check(None, self.lib.dda_nn_layer_info(self.h, out))
+        return [(out[3 * i], out[3 * i + 1], out[3 * i + 2]) for i in range(self.depth)]
+
+    def get_params(self):
+        flat = np.zeros(self.num_params, dtype=np.float32)
+        _check(None, self.lib.dda_nn_get_params(self.h, flat.ctypes.data_as(C.POINTER(C.c_float))))
+        return self._unflat(flat)
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(np.concatenate([np.concatenate([w.reshape(-1), b.reshape(-1)]) for w, b in params]),
+                                    dtype=np.float32)
+        assert flat.size == self.num_params
+        _check(None, self.lib.dda_nn_set_params(self.h, flat.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def _unflat(self, flat):
+        out, off = [], 0
+        for cin, cout, d in self.layers():
+            n = 27 * cin * cout
+            out.append((flat[off:off + n].reshape(27, cin, cout), flat[off + n:off + n + cout]))
+            off += n + cout
+        return out
+
+    def attach(self):
+        _check(self.ctx.h, self.lib.dda_set_guess_model(self.ctx.h, self.h))
+
+    def record(self):
+        _check(self.ctx.h, self.lib.dda_nn_record(self.ctx.h, self.h))
+
+    def train(self, epochs=1, batch=4, lr=1e-3, weight_decay=0.0):
+        o = L.dda_nn_train_opts(epochs=epochs, batch=batch, lr=lr, weight_decay=weight_decay)
+        loss = C.c_double()
+        _check(self.ctx.h, self.lib.dda_nn_train(self.ctx.h, self.h, C.byref(o), C.byref(loss)))
+        return loss.value
+
+    def save(self, path):
+        _check(None, self.lib.dda_nn_save(self.h, path.encode()))
+
+    def load(self, path):
+        _check(None, self.lib.dda_nn_load(self.h, path.encode()))
+
+    def forward_backward(self, x, target=None, mask=None, nout=6):
+        """x: (ns, D, D, D, 16) float32; returns (out, grads as [(dW, db)], loss)."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        ns, D = x.shape[0], x.shape[1]
+        out = np.zeros((ns, D, D, D, 16), dtype=np.float32)
+        fp = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))
+        if target is None:
+            _check(None, self.lib.dda_nn_forward_backward(self.h, ns, D, fp(x), None, None, nout, fp(out), None, None))
+            return out, None, None
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        g = np.zeros(self.num_params, dtype=np.float32)
+        loss = C.c_double()
+        _check(None, self.lib.dda_nn_forward_backward(self.h, ns, D, fp(x), fp(t), m.ctypes.data, nout, fp(out), fp(g),
+                                                      C.byref(loss)))
+        return out, self._unflat(g), loss.value

@@ -56,6 +56,15 @@ class dda_solve_stats(C.Structure):
                 ("rel_resid", C.c_double), ("guess_resid", C.c_double)]
 
 
+class dda_nn_config(C.Structure):
+    _fields_ = [("width", C.c_int32), ("depth", C.c_int32), ("seed", C.c_int32), ("reserved", C.c_int32)]
+
+
+class dda_nn_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("weight_decay", C.c_double),
+                ("reserved", C.c_int32 * 4)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/dda.h
 P = C.c_void_p
 D = C.POINTER(C.c_double)
@@ -82,7 +91,24 @@ SIGNATURES = {
     "dda_scattering_frame": (C.c_int32, [C.c_int32, D, D, D, D, D]),
     "dda_autotune": (C.c_int32, [P, C.c_int32, C.c_char_p]),
     "dda_last_timing": (C.c_int32, [P, D, D, D]),
+    "dda_last_guess_ms": (C.c_int32, [P, D]),
+    "dda_get_shape": (C.c_int32, [P, C.c_int32, C.c_uint32, C.POINTER(C.c_int32)]),
+    "dda_set_shape": (C.c_int32, [P, C.c_int32, C.c_uint32, C.POINTER(C.c_int32)]),
     "dda_profile_matvec": (C.c_int32, [P, C.c_int32, C.c_int32, C.c_uint32, C.c_int32, D, D]),
+    "dda_nn_create": (C.c_int32, [P, C.POINTER(dda_nn_config), C.POINTER(P)]),
+    "dda_nn_destroy": (C.c_int32, [P]),
+    "dda_nn_num_params": (C.c_int64, [P]),
+    "dda_nn_num_samples": (C.c_int32, [P]),
+    "dda_nn_layer_info": (C.c_int32, [P, C.POINTER(C.c_int32)]),
+    "dda_nn_get_params": (C.c_int32, [P, C.POINTER(C.c_float)]),
+    "dda_nn_set_params": (C.c_int32, [P, C.POINTER(C.c_float)]),
+    "dda_set_guess_model": (C.c_int32, [P, P]),
+    "dda_nn_record": (C.c_int32, [P, P]),
+    "dda_nn_train": (C.c_int32, [P, P, C.POINTER(dda_nn_train_opts), D]),
+    "dda_nn_save": (C.c_int32, [P, C.c_char_p]),
+    "dda_nn_load": (C.c_int32, [P, C.c_char_p]),
+    "dda_nn_forward_backward": (C.c_int32, [P, C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                            P, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float), D]),
 }
 
 _lib = None

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdda.so")
-SOURCES = ["kernels_fft.hip", "kernels_ct.hip", "kernels_vec.hip", "api.hip"]
+SOURCES = ["kernels_fft.hip", "kernels_ct.hip", "kernels_vec.hip", "api.hip", "nn.hip"]
 ARCH = os.environ.get("DDA_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -37,7 +37,7 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 5) -> str:
     hipcc = _hipcc()
     tmpdir = tempfile.mkdtemp(prefix="dda_build_")
     try:

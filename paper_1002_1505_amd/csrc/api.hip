@@ -26,6 +26,11 @@
 
 using cd = std::complex<double>;
 
+hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, const double* ainv,
+                         const Cx<double>* x64, hipStream_t st);
+hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves, const double* ainv, int nr,
+                          Cx<double>* x64, hipStream_t st);
+
 namespace {
 
 constexpr double PI = 3.14159265358979323846;
@@ -61,6 +66,7 @@ struct DevMem {
 };
 
 struct Target {
+    long long uid = 0;
     int n[3] = {0, 0, 0};
     int N = 0, Npad = 0, ncomp = 0;
     std::vector<cd> m;
@@ -139,6 +145,9 @@ struct dda_ctx {
     long long gkey_gen = -1;
     int gkey_prec = 0, gkey_k = 0;
     long long ws_gen = 0;
+    dda_nn* nn = nullptr;  // learned-guess model (not owned)
+    std::vector<dda_wave> last_waves;
+    double ms_guess = 0;
     // timing
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double ms_mv32 = 0, ms_mv64 = 0, ms_total = 0;
@@ -207,7 +216,7 @@ MvShape default_shape(const Target& t, int tx_pref) {
         s.tx = tx;
         const int bz = (g.n3 / rmin(t.plans[2])) * 6 * tx;
         s.nth_z = std::max(256, round64((bz + 3) / 4));
-        if ((s.nth_z <= 1024 && matvec_shape_ok<T>(g, t.plans, MvShape{0, 64, s.nth_z, tx, 16, 256, 0})) || tx == 1) break;
+        if ((s.nth_z <= 1024 && matvec_shape_ok<T>(g, t.plans, MvShape{0, 64, s.nth_z, tx, 16, 256, 0, 0})) || tx == 1) break;
     }
     // planes
     const int np = g.n1 * g.n2;
@@ -216,6 +225,7 @@ MvShape default_shape(const Target& t, int tx_pref) {
     s.nth_plane = std::max(256, round64(nth));
     s.fused = 1;
     s.ct = 0;
+    s.zrb = 0;
     if (!matvec_shape_ok<T>(g, t.plans, s)) s.fused = 0;
     if (ct_supported(g.n1, g.n2, g.n3)) {
         // specialised kernels; z tile 16 columns unless only another fits
@@ -230,6 +240,7 @@ MvShape default_shape(const Target& t, int tx_pref) {
             c.ct = ct_available<T>(g.n1, s.tx) & 1;
         }
         // a generic z pass needs its own thread count for the chosen tile
+        c.zrb = (c.ct & 2) ? 1 : 0;
         if (c.ct && matvec_shape_ok<T>(g, t.plans, c)) s = c;
     }
     return s;
@@ -285,6 +296,8 @@ dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint
         t.origin[2] = cz / t.N;
     }
     t.aeff = std::cbrt(3.0 * t.N / (4.0 * PI));
+    static long long next_uid = 1;
+    t.uid = next_uid++;
     HCHK(c, t.d_xyz.ensure(xyz.size() * 4));
     HCHK(c, t.d_comp.ensure(comp.size()));
     HCHK(c, t.d_pstart.ensure(ps.size() * 4));
@@ -343,6 +356,23 @@ dda_status check_ctx(dda_ctx* c) {
     return DDA_OK;
 }
 
+NnSiteView site_view(const Target& t) {
+    NnSiteView v;
+    v.uid = t.uid;
+    v.n1 = t.n[0];
+    v.n2 = t.n[1];
+    v.n3 = t.n[2];
+    v.N = t.N;
+    v.Npad = t.Npad;
+    v.ncomp = t.ncomp;
+    v.site_xyz = t.d_xyz.as<uint32_t>();
+    v.site_comp = t.d_comp.as<uint8_t>();
+    for (int i = 0; i < 3; ++i) v.origin[i] = t.origin[i];
+    v.kd = t.kd;
+    v.m = reinterpret_cast<const double*>(t.m.data());
+    return v;
+}
+
 dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
     const bool need64 = (prec & DDA_FP64) && !t.have64;
     const bool need32 = (prec & DDA_FP32) && !t.have32;
@@ -362,11 +392,11 @@ dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
 
 template <class T>
 hipError_t matvec_group(const Target& t, Group& g, int nr, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, const int* active,
-                        int mode, hipStream_t st) {
+                        int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr}) {
     Cx<T>* slab = std::is_same<T, double>::value ? g.slab64.as<Cx<T>>() : g.slab32.as<Cx<T>>();
     const Cx<T>* ainv = std::is_same<T, double>::value ? g.ainv64.as<Cx<T>>() : g.ainv32.as<Cx<T>>();
     return launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab, t.ghat<T>(), ainv, active,
-                            mode, st);
+                            mode, st, dot);
 }
 
 size_t slab_elems(const Target& t, int nr) { return (size_t)nr * 3 * 4 * t.n[0] * t.n[1] * t.n[2]; }
@@ -399,7 +429,7 @@ dda_status ensure_group(dda_ctx* c, Group& g, const Target& t, int prec, bool* r
     HCHK(c, g.state.ensure(nr * sizeof(BiState)));
     HCHK(c, g.active.ensure(nr * sizeof(int)));
     HCHK(c, g.mask.ensure(nr * sizeof(int)));
-    HCHK(c, g.partials.ensure((size_t)nr * 4 * vec_blocks(t.Npad) * 2 * sizeof(double)));
+    HCHK(c, g.partials.ensure((size_t)nr * 4 * std::max(vec_blocks(t.Npad), 12 * t.n[0]) * 2 * sizeof(double)));
     HCHK(c, g.scale.ensure(nr * sizeof(double)));
     HCHK(c, g.tolrel2.ensure(nr * sizeof(double)));
     HCHK(c, g.maxit.ensure(nr * sizeof(int)));
@@ -434,16 +464,27 @@ hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st) {
         int* act = g.active.as<int>();
         double* part = g.partials.as<double>();
         hipError_t e;
+        const bool fuse = (t.shape<T>().ct & 1) != 0;
+        const int nbv = vec_blocks(Np), nbp = fuse ? 12 * t.n[0] : nbv;
         if ((e = launch_bicg_p<T>(Np, nr, p, r, v, rh, bs, act, st)) != hipSuccess) return e;
-        if ((e = matvec_group<T>(t, g, nr, p, v, nullptr, act, MV_AX, st)) != hipSuccess) return e;
-        if ((e = launch_dot<T>(Np, nr, 1, rh, v, nullptr, nullptr, part, act, st)) != hipSuccess) return e;
-        if ((e = launch_scalars(0, Np, nr, bs, part, act, st)) != hipSuccess) return e;
+        if (fuse) {
+            if ((e = matvec_group<T>(t, g, nr, p, v, nullptr, act, MV_AX, st, MvDot{1, rh, part})) != hipSuccess) return e;
+        } else {
+            if ((e = matvec_group<T>(t, g, nr, p, v, nullptr, act, MV_AX, st)) != hipSuccess) return e;
+            if ((e = launch_dot<T>(Np, nr, 1, rh, v, nullptr, nullptr, part, act, st)) != hipSuccess) return e;
+        }
+        if ((e = launch_scalars(0, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
         if ((e = launch_bicg_s<T>(Np, nr, s, r, v, bs, act, st)) != hipSuccess) return e;
-        if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st)) != hipSuccess) return e;
-        if ((e = launch_dot<T>(Np, nr, 2, tt, s, tt, tt, part, act, st)) != hipSuccess) return e;
-        if ((e = launch_scalars(1, Np, nr, bs, part, act, st)) != hipSuccess) return e;
+        if (fuse) {
+            if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st, MvDot{2, nullptr, part})) != hipSuccess)
+                return e;
+        } else {
+            if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st)) != hipSuccess) return e;
+            if ((e = launch_dot<T>(Np, nr, 2, tt, s, tt, tt, part, act, st)) != hipSuccess) return e;
+        }
+        if ((e = launch_scalars(1, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
         if ((e = launch_bicg_xr<T>(Np, nr, x, r, p, s, tt, rh, bs, part, act, st)) != hipSuccess) return e;
-        if ((e = launch_scalars(2, Np, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_scalars(2, nbv, nr, bs, part, act, st)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -541,6 +582,9 @@ dda_status group_waves(dda_ctx* c, int nrhs, const dda_wave* waves) {
     return DDA_OK;
 }
 
+// error text of a failed dda_create (there is no context to hold it)
+thread_local std::string g_create_err = "no error";
+
 }  // namespace
 
 // ===========================================================================
@@ -572,9 +616,11 @@ dda_status dda_create(dda_ctx** out, int32_t device, void* hip_stream) {
         }
         c->own_stream = true;
     }
-    if (configure_fft_kernels() != hipSuccess || configure_ct_kernels() != hipSuccess ||
-        hipEventCreate(&c->ev0) != hipSuccess ||
+    hipError_t e1 = configure_fft_kernels(), e2 = configure_ct_kernels();
+    if (e1 != hipSuccess || e2 != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess) {
+        g_create_err = std::string("dda_create: kernel configuration failed: ") +
+                       hipGetErrorString(e1 != hipSuccess ? e1 : e2);
         delete c;
         return DDA_ERR_HIP;
     }
@@ -596,7 +642,7 @@ dda_status dda_destroy(dda_ctx* c) {
     return DDA_OK;
 }
 
-const char* dda_last_error(const dda_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* dda_last_error(const dda_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 dda_status dda_add_target(dda_ctx* c, const int32_t dims[3], const uint8_t* occ, int32_t ncomp, const double* m,
                           double kd, int32_t alpha_kind, const double* origin, int32_t* id_out) {
@@ -669,7 +715,7 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
     const bool use_graph = !(o->flags & DDA_NO_GRAPH);
     const int kiters = o->graph_iters > 0 ? o->graph_iters : 4;
     if (o->guess == DDA_GUESS_USER && !p0) return fail(c, DDA_ERR_INVALID_ARG, "GUESS_USER needs p0");
-    if (o->guess == DDA_GUESS_NN) return fail(c, DDA_ERR_STATE, "no learned-guess model attached");
+    if (o->guess == DDA_GUESS_NN && !c->nn) return fail(c, DDA_ERR_STATE, "no learned-guess model attached");
     if (o->guess == DDA_GUESS_PREV && (!c->have_solution || c->last_nrhs != nrhs))
         return fail(c, DDA_ERR_STATE, "GUESS_PREV needs a previous solve with the same right-hand sides");
     const bool keep_prev = (o->guess == DDA_GUESS_PREV);
@@ -739,6 +785,29 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
             HCHK(c, hipStreamSynchronize(st));
         }
         // GUESS_PREV: x64 already holds the previous solution
+    }
+    c->ms_guess = 0;
+    if (o->guess == DDA_GUESS_NN) {
+        HCHK(c, hipEventRecord(c->ev1, st));
+        for (auto& gp : c->groups) {
+            Group& g = *gp;
+            Target& t = *c->tg[g.tgt];
+            std::vector<dda_wave> gw(g.nr);
+            for (int s = 0; s < g.nr; ++s) gw[s] = waves[g.idx[s]];
+            hipError_t e = nn_guess_group(c->nn, site_view(t), gw.data(), reinterpret_cast<const double*>(g.hainv.data()),
+                                          g.nr, g.x64.as<Cx<double>>(), st);
+            if (e == hipErrorNotSupported)
+                return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "learned guess needs a cubic box with side divisible by 16");
+            HCHK(c, e);
+        }
+        hipEvent_t eg;
+        HCHK(c, hipEventCreate(&eg));
+        HCHK(c, hipEventRecord(eg, st));
+        HCHK(c, hipEventSynchronize(eg));
+        float mg = 0;
+        HCHK(c, hipEventElapsedTime(&mg, c->ev1, eg));
+        (void)hipEventDestroy(eg);
+        c->ms_guess = mg;
     }
     std::vector<double> bb(nrhs), rel(nrhs), grel(nrhs, 1.0);
     std::vector<int> done(nrhs, 0), iters(nrhs, 0), outer(nrhs, 0), mvs(nrhs, 0), stat(nrhs, 0);
@@ -902,6 +971,7 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
     c->ms_mv64 = ms64;
     c->ms_total = mst;
     c->have_solution = true;
+    c->last_waves.assign(waves, waves + nrhs);
     int any_nc = 0;
     for (int i = 0; i < nrhs; ++i) {
         if (stats) {
@@ -1146,6 +1216,37 @@ dda_status dda_scattering_frame(int32_t ndir, const double* theta, const double*
     return DDA_OK;
 }
 
+dda_status dda_set_guess_model(dda_ctx* c, dda_nn* nn) {
+    if (!c) return DDA_ERR_INVALID_ARG;
+    c->nn = nn;
+    return DDA_OK;
+}
+
+dda_status dda_nn_record(dda_ctx* c, dda_nn* nn) {
+    SCHK(check_ctx(c));
+    if (!nn) return fail(c, DDA_ERR_INVALID_ARG, "nn_record: null network");
+    if (!c->have_solution) return fail(c, DDA_ERR_STATE, "nn_record before a solve");
+    for (int i = 0; i < c->last_nrhs; ++i) {
+        Group& g = *c->groups[c->rhs_group[i]];
+        Target& t = *c->tg[g.tgt];
+        const int s = c->rhs_slot[i];
+        hipError_t e = nn_record_one(nn, site_view(t), c->last_waves[i],
+                                     reinterpret_cast<const double*>(g.hainv.data()) + (size_t)s * 2 * t.ncomp,
+                                     g.x64.as<Cx<double>>() + (size_t)s * 3 * t.Npad, c->stream);
+        if (e == hipErrorNotSupported)
+            return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "nn_record: needs a cubic box with side divisible by 16");
+        if (e == hipErrorInvalidValue) return fail(c, DDA_ERR_INVALID_ARG, "nn_record: all samples must share one box size");
+        HCHK(c, e);
+    }
+    return DDA_OK;
+}
+
+dda_status dda_last_guess_ms(const dda_ctx* c, double* ms) {
+    if (!c || !ms) return DDA_ERR_INVALID_ARG;
+    *ms = c->ms_guess;
+    return DDA_OK;
+}
+
 dda_status dda_last_timing(const dda_ctx* c, double* a, double* b, double* t) {
     if (!c) return DDA_ERR_INVALID_ARG;
     if (a) *a = c->ms_mv32;
@@ -1221,9 +1322,151 @@ extern "C" dda_status dda_profile_matvec(dda_ctx* c, int32_t target, int32_t nrh
     return fail(c, DDA_ERR_INVALID_ARG, "profile_matvec: prec must be FP32 or FP64");
 }
 
+namespace {
+// Candidate launch shapes of a target for precision T (all feasible).
+template <class T>
+std::vector<MvShape> shape_candidates(const Target& t) {
+    std::vector<MvShape> out;
+    const Geo g = t.geo();
+    const MvShape base = default_shape<T>(t, 16);
+    if (ct_supported(g.n1, g.n2, g.n3)) {
+        for (int tx : {8, 16, 32})
+            for (int zrb : {0, 1}) {
+                MvShape c = base;
+                c.tx = tx;
+                c.ct = ct_available<T>(g.n1, tx);
+                if (!(c.ct & 2)) continue;
+                c.zrb = zrb;
+                c.fused = 1;
+                if (matvec_shape_ok<T>(g, t.plans, c)) out.push_back(c);
+            }
+    }
+    for (int tx : {4, 8, 16, 32})
+        for (int fused : {1, 0}) {
+            if (g.n1 % tx) continue;
+            MvShape c = base;
+            c.ct = 0;
+            c.zrb = 0;
+            c.fused = fused;
+            c.tx = tx;
+            const int bz = (g.n3 / rmin(t.plans[2])) * 6 * tx;
+            c.nth_z = std::max(256, round64((bz + 3) / 4));
+            if (matvec_shape_ok<T>(g, t.plans, c)) out.push_back(c);
+        }
+    return out;
+}
+
+std::string shape_key(const Target& t, int prec, int nrhs, const std::string& arch) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%dx%dx%d/%s/rhs%d/%s", t.n[0], t.n[1], t.n[2], prec == DDA_FP64 ? "fp64" : "fp32",
+             nrhs, arch.c_str());
+    return buf;
+}
+
+// Cache file: one entry per line, {"key": [fused, nth_plane, nth_z, tx, lines_tl, nth_lines, ct, zrb, ms]}.
+std::vector<std::pair<std::string, std::vector<double>>> read_cache(const std::string& path) {
+    std::vector<std::pair<std::string, std::vector<double>>> out;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t a = line.find('"'), b = line.find('"', a + 1), l = line.find('['), r = line.find(']');
+        if (a == std::string::npos || b == std::string::npos || l == std::string::npos || r == std::string::npos)
+            continue;
+        std::vector<double> v;
+        std::stringstream ss(line.substr(l + 1, r - l - 1));
+        std::string tok;
+        while (std::getline(ss, tok, ',')) v.push_back(std::atof(tok.c_str()));
+        if (v.size() == 9) out.emplace_back(line.substr(a + 1, b - a - 1), v);
+    }
+    return out;
+}
+
+void write_cache(const std::string& path, const std::vector<std::pair<std::string, std::vector<double>>>& e) {
+    std::ofstream f(path + ".tmp");
+    f << "{\n";
+    for (size_t i = 0; i < e.size(); ++i) {
+        f << "  \"" << e[i].first << "\": [";
+        for (size_t j = 0; j < e[i].second.size(); ++j) f << (j ? ", " : "") << e[i].second[j];
+        f << "]" << (i + 1 < e.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+    f.close();
+    std::rename((path + ".tmp").c_str(), path.c_str());
+}
+
+template <class T>
+dda_status tune_target(dda_ctx* c, Target& t, int nrhs, const std::string& arch,
+                       std::vector<std::pair<std::string, std::vector<double>>>& cache, bool* changed) {
+    const int prec = std::is_same<T, double>::value ? DDA_FP64 : DDA_FP32;
+    const std::string key = shape_key(t, prec, nrhs, arch);
+    MvShape& dst = std::is_same<T, double>::value ? t.sh64 : t.sh32;
+    for (auto& kv : cache)
+        if (kv.first == key) {
+            const std::vector<double>& v = kv.second;
+            MvShape s{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], (int)v[6], (int)v[7]};
+            if (matvec_shape_ok<T>(t.geo(), t.plans, s)) {
+                dst = s;
+                return DDA_OK;
+            }
+        }
+    double best = 1e30;
+    MvShape bs = dst;
+    for (const MvShape& s : shape_candidates<T>(t)) {
+        double ms[3];
+        dda_status st = profile_passes<T>(c, t, nrhs, 5, s, ms, nullptr);
+        if (st < 0) return st;
+        const double tot = ms[0] + ms[1] + ms[2];
+        if (tot < best) {
+            best = tot;
+            bs = s;
+        }
+    }
+    dst = bs;
+    cache.emplace_back(key, std::vector<double>{(double)bs.fused, (double)bs.nth_plane, (double)bs.nth_z, (double)bs.tx,
+                                                (double)bs.lines_tl, (double)bs.nth_lines, (double)bs.ct, (double)bs.zrb,
+                                                best});
+    *changed = true;
+    return DDA_OK;
+}
+}  // namespace
+
 extern "C" dda_status dda_autotune(dda_ctx* c, int32_t nrhs_hint, const char* cache_path) {
     SCHK(check_ctx(c));
-    (void)nrhs_hint;
-    (void)cache_path;
+    if (c->tg.empty()) return fail(c, DDA_ERR_STATE, "autotune before set_target");
+    const int nrhs = nrhs_hint > 0 ? nrhs_hint : 2;
+    std::string path = cache_path ? cache_path : (std::getenv("DDA_TUNE_CACHE") ? std::getenv("DDA_TUNE_CACHE") : "");
+    hipDeviceProp_t prop;
+    HCHK(c, hipGetDeviceProperties(&prop, c->device));
+    const std::string arch = prop.gcnArchName;
+    auto cache = path.empty() ? std::vector<std::pair<std::string, std::vector<double>>>() : read_cache(path);
+    bool changed = false;
+    for (auto& t : c->tg) {
+        SCHK(ensure_green(c, *t, DDA_FP32 | DDA_FP64));
+        SCHK(tune_target<float>(c, *t, nrhs, arch, cache, &changed));
+        SCHK(tune_target<double>(c, *t, nrhs, arch, cache, &changed));
+    }
+    if (changed && !path.empty()) write_cache(path, cache);
+    c->ws_gen++;  // launch shapes are baked into captured graphs
+    return DDA_OK;
+}
+
+extern "C" dda_status dda_get_shape(const dda_ctx* c, int32_t target, uint32_t prec, int32_t* out8) {
+    if (!c || target < 0 || target >= (int)c->tg.size() || !out8) return DDA_ERR_INVALID_ARG;
+    const MvShape& s = prec == DDA_FP64 ? c->tg[target]->sh64 : c->tg[target]->sh32;
+    const int v[8] = {s.fused, s.nth_plane, s.nth_z, s.tx, s.lines_tl, s.nth_lines, s.ct, s.zrb};
+    for (int i = 0; i < 8; ++i) out8[i] = v[i];
+    return DDA_OK;
+}
+
+extern "C" dda_status dda_set_shape(dda_ctx* c, int32_t target, uint32_t prec, const int32_t* in8) {
+    SCHK(check_ctx(c));
+    if (target < 0 || target >= (int)c->tg.size() || !in8) return fail(c, DDA_ERR_INVALID_ARG, "set_shape: bad args");
+    Target& t = *c->tg[target];
+    MvShape s{in8[0], in8[1], in8[2], in8[3], in8[4], in8[5], in8[6], in8[7]};
+    const bool ok = prec == DDA_FP64 ? matvec_shape_ok<double>(t.geo(), t.plans, s)
+                                     : matvec_shape_ok<float>(t.geo(), t.plans, s);
+    if (!ok) return fail(c, DDA_ERR_INVALID_ARG, "set_shape: infeasible launch shape");
+    (prec == DDA_FP64 ? t.sh64 : t.sh32) = s;
+    c->ws_gen++;
     return DDA_OK;
 }

@@ -48,6 +48,15 @@ struct MvShape {
     int lines_tl;    // lines per block in the line-kernel fallback
     int nth_lines;
     int ct;          // bit 0: specialised plane kernels, bit 1: specialised z pass (cubic boxes)
+    int zrb;         // specialised z pass: 1 = loop over up to 8 rhs per block with the spectrum in registers
+};
+
+// Optional inner products fused into the last matvec pass (specialised plane
+// kernels only): dot = 1 -> <w, y> in slot 0; dot = 2 -> <y, x>, <y, y>.
+struct MvDot {
+    int dot;
+    const void* w;
+    double* partials;
 };
 
 enum { MV_AX = 0, MV_RESID = 1 };
@@ -56,12 +65,13 @@ enum { MV_AX = 0, MV_RESID = 1 };
 template <class T>
 hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh, int nrhs,
                          const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
-                         const Cx<T>* ainv, const int* active, int mode, hipStream_t st);
+                         const Cx<T>* ainv, const int* active, int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr});
 // Individual passes (for per-pass profiling).
 template <class T>
 hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh,
                        int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
-                       const Cx<T>* ainv, const int* active, int mode, hipStream_t st);
+                       const Cx<T>* ainv, const int* active, int mode, hipStream_t st,
+                       MvDot dot = MvDot{0, nullptr, nullptr});
 // Shared-memory bytes and feasibility of a shape.
 template <class T>
 bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh);
@@ -105,8 +115,8 @@ template <class T>
 hipError_t launch_bicg_xr(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p, const Cx<T>* s,
                           const Cx<T>* t, const Cx<T>* rhat, const BiState* st_, double* partials,
                           const int* active, hipStream_t st);
-// which: 0 alpha, 1 omega, 2 rho/convergence
-hipError_t launch_scalars(int which, int Npad, int nrhs, BiState* s, const double* partials, int* active,
+// which: 0 alpha, 1 omega, 2 rho/convergence; nblk partials per rhs and slot
+hipError_t launch_scalars(int which, int nblk, int nrhs, BiState* s, const double* partials, int* active,
                           hipStream_t st);
 template <class T>
 hipError_t launch_bicg_init(int Npad, int nrhs, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* rhat, Cx<T>* p,
@@ -143,12 +153,35 @@ hipError_t launch_ampl(const Geo& g, const double* origin3, double k, int nrhs, 
 
 hipError_t configure_fft_kernels();
 
+// Raise a kernel's dynamic-LDS limit to the 160 KB of a gfx950 CU minus the
+// kernel's static LDS (the attribute value is ignored beyond that).
+inline hipError_t set_lds_limit(const void* fn, hipFuncAttribute attr, int lim) {
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess) return e;
+    const int room = lim - (int)fa.sharedSizeBytes;
+    return hipFuncSetAttribute(fn, attr, room);
+}
+
 // ---- compile-time specialised passes (kernels_ct.hip) ----
 bool ct_supported(int n1, int n2, int n3);
 template <class T>
 int ct_available(int n, int tx);
 template <class T>
-hipError_t launch_pass_ct(int which, int tx, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
-                          const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv, const int* active,
-                          int mode, hipStream_t st);
+hipError_t launch_pass_ct(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x,
+                          Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
+                          const int* active, int mode, int dot, const Cx<T>* w, double* partials, hipStream_t st);
 hipError_t configure_ct_kernels();
+
+// ---- learned initial guess (nn.hip) ----
+struct dda_nn;
+struct dda_wave_;  // the ABI's dda_wave
+struct NnSiteView {
+    long long uid;  // identifies the target's site list
+    int n1, n2, n3, N, Npad, ncomp;
+    const uint32_t* site_xyz;
+    const uint8_t* site_comp;
+    double origin[3];
+    double kd;
+    const double* m;  // 2 * ncomp
+};

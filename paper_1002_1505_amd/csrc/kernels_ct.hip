@@ -127,11 +127,110 @@ __global__ void __launch_bounds__(zpass_threads<N>()) k_zpass_ct(Cx<T>* __restri
     }
 }
 
-template <class T, int N, int MODE>
+// z pass over a tile of columns for up to RB right-hand sides per block.
+// The tensor spectrum of the tile is loaded once into registers and reused
+// for every right-hand side; each register entry serves the folded frequency
+// kz_f in [0, n] and its mirror 2n - kz_f.
+template <class T, int N, int TX, int RB>
+__global__ void __launch_bounds__(zpass_threads<N>()) k_zpass2_ct(Cx<T>* __restrict__ slab,
+                                                                  const Cx<T>* __restrict__ gh, Geo g, Tw<T> tw,
+                                                                  int nrhs, const int* __restrict__ active) {
+    constexpr int NTH = zpass_threads<N>();
+    constexpr int NCOL = 4 * N * N;
+    constexpr int E = 3 * N * TX;
+    constexpr int NI = (N + 1) * TX;               // (folded kz, column) items
+    constexpr int MI = (NI + NTH - 1) / NTH;       // items per thread
+    constexpr int H = N / 2 + 1;
+    constexpr int D = 2 * H;
+    constexpr size_t CS = (size_t)D * D * D;
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* t3 = reinterpret_cast<Cx<T>*>(smem_raw);
+    Cx<T>* W = t3 + N;
+    const int tile = blockIdx.x;
+    const int r0 = blockIdx.y * RB, r1 = min(nrhs, r0 + RB);
+    bool any = false;
+    for (int r = r0; r < r1; ++r) any |= (!active || active[r]);
+    if (!any) return;
+    const int q0 = tile * TX;
+    const int par = q0 / (N * N), rem = q0 % (N * N);
+    const int px = par & 1, py = par >> 1;
+    const int kyp = rem / N, kx0 = rem % N;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += NTH) t3[i] = tw.f3[i];
+    // spectrum of this tile in registers: 6 components per item
+    Cx<T> G[MI][6];
+    int sy;
+    const int kyi = fold_idx(2 * kyp + py, N, sy);
+#pragma unroll
+    for (int m = 0; m < MI; ++m) {
+        const int it = tid + m * NTH;
+        if ((NI % NTH) == 0 || it < NI) {
+            const int col = it % TX, kzf = it / TX;
+            int sx, sz;
+            const int kxi = fold_idx(2 * (kx0 + col) + px, N, sx);
+            const int kzi = (kzf & 1) * H + (kzf >> 1);
+            const size_t gi = ((size_t)kzi * D + kyi) * D + kxi;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) G[m][q] = gh[q * CS + gi];
+            G[m][1] = (T)(sx * sy) * G[m][1];
+            G[m][2] = (T)sx * G[m][2];   // z sign applied per mirror below
+            G[m][4] = (T)sy * G[m][4];
+        }
+    }
+    for (int r = r0; r < r1; ++r) {
+        if (active && !active[r]) continue;
+        Cx<T>* base = slab + (size_t)r * 3 * N * NCOL + q0;
+        for (int e = tid; e < E; e += NTH) {
+            const int col = e % TX, cz = e / TX;
+            const int z = cz % N;
+            const Cx<T> v = base[(size_t)cz * NCOL + col];
+            W[e] = v;
+            W[E + e] = v * tw.h3[z];
+        }
+        __syncthreads();
+        ct_fft<T, -1, N, 6 * TX, NTH, TX, 1, N * TX, TX>(W, t3, tid);
+#pragma unroll
+        for (int m = 0; m < MI; ++m) {
+            const int it = tid + m * NTH;
+            if ((NI % NTH) == 0 || it < NI) {
+                const int col = it % TX, kzf = it / TX;
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    if (side == 1 && (kzf == 0 || kzf == N)) break;
+                    const int kz = side ? 2 * N - kzf : kzf;
+                    const T sz = side ? (T)-1 : (T)1;
+                    Cx<T>* w = W + (kz & 1) * E;
+                    const int kzp = kz >> 1;
+                    const Cx<T> gxx = G[m][0], gxy = G[m][1], gxz = sz * G[m][2];
+                    const Cx<T> gyy = G[m][3], gyz = sz * G[m][4], gzz = G[m][5];
+                    const int o0 = kzp * TX + col, o1 = (N + kzp) * TX + col, o2 = (2 * N + kzp) * TX + col;
+                    const Cx<T> a0 = w[o0], a1 = w[o1], a2 = w[o2];
+                    w[o0] = gxx * a0 + gxy * a1 + gxz * a2;
+                    w[o1] = gxy * a0 + gyy * a1 + gyz * a2;
+                    w[o2] = gxz * a0 + gyz * a1 + gzz * a2;
+                }
+            }
+        }
+        __syncthreads();
+        ct_fft<T, +1, N, 6 * TX, NTH, TX, 1, N * TX, TX>(W, t3, tid);
+        for (int e = tid; e < E; e += NTH) {
+            const int col = e % TX, cz = e / TX;
+            const int z = cz % N;
+            base[(size_t)cz * NCOL + col] = W[e] + cmulc(tw.h3[z], W[E + e]);
+        }
+        __syncthreads();
+    }
+}
+
+// DOT = 1: per-block partial sums of conj(w_j) . y_j (slot 0); DOT = 2:
+// conj(y_j) . x_j (slot 0) and |y_j|^2 (slot 1).  partials[rhs][slot][blk]
+// with blk = (plane within rhs) * 4 + class, 12 n blocks per rhs.
+template <class T, int N, int MODE, int DOT>
 __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __restrict__ slab, const Cx<T>* __restrict__ x,
                                                                 Cx<T>* __restrict__ y, const Cx<T>* __restrict__ bvec,
                                                                 const Cx<T>* __restrict__ ainv, Geo g, Tw<T> tw, int nrhs,
-                                                                const int* __restrict__ active) {
+                                                                const int* __restrict__ active,
+                                                                const Cx<T>* __restrict__ wv, double* __restrict__ partials) {
     constexpr int NTH = plane_threads<N>();
     constexpr int PITCH = N + 1;
     constexpr int NN = N * N;
@@ -169,13 +268,41 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
     const Cx<T>* av = ainv + (size_t)rhs * g.ncomp;
     const int j0 = g.plane_start[z], j1 = g.plane_start[z + 1];
+    double a0r = 0, a0i = 0, a1r = 0;
     for (int j = j0 + tid; j < j1; j += NTH) {
         const uint32_t s = g.site_xyz[j];
         const int sx = s & 1023, sy = (s >> 10) & 1023;
         if ((sx & 1) != qx || (sy & 1) != qy) continue;
-        const Cx<T> v = buf[(sy >> 1) * PITCH + (sx >> 1)] + av[g.site_comp[j]] * x[vo + j];
-        if (MODE == MV_AX) y[vo + j] = v;
-        else y[vo + j] = bvec[vo + j] - v;
+        const Cx<T> xj = x[vo + j];
+        Cx<T> v = buf[(sy >> 1) * PITCH + (sx >> 1)] + av[g.site_comp[j]] * xj;
+        if (MODE == MV_RESID) v = bvec[vo + j] - v;
+        y[vo + j] = v;
+        if (DOT == 1) {
+            const Cx<T> wj = wv[vo + j];
+            a0r += (double)wj.re * v.re + (double)wj.im * v.im;
+            a0i += (double)wj.re * v.im - (double)wj.im * v.re;
+        } else if (DOT == 2) {
+            a0r += (double)v.re * xj.re + (double)v.im * xj.im;
+            a0i += (double)v.re * xj.im - (double)v.im * xj.re;
+            a1r += (double)v.re * v.re + (double)v.im * v.im;
+        }
+    }
+    if (DOT) {
+        __shared__ double sh[16];
+        const int nblk = 12 * N;
+        const int blk = (plane % (3 * N)) * 4 + q;
+        const double s0r = block_sum(a0r, sh), s0i = block_sum(a0i, sh);
+        double s1r = 0;
+        if (DOT == 2) s1r = block_sum(a1r, sh);
+        if (tid == 0) {
+            double* o = partials + ((size_t)rhs * 4 * nblk + blk) * 2;
+            o[0] = s0r;
+            o[1] = s0i;
+            if (DOT == 2) {
+                o[2 * nblk] = s1r;
+                o[2 * nblk + 1] = 0;
+            }
+        }
     }
 }
 
@@ -185,10 +312,18 @@ template <class T, int N, int TX>
 constexpr size_t zpass_lds() { return (size_t)(N + 6 * N * TX) * sizeof(Cx<T>); }
 constexpr size_t LDS_MAX = 160 * 1024;
 
+template <class T, int N, int MODE, int DOT>
+void launch_pinv(int nblk, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* b,
+                 const Cx<T>* slab, const Cx<T>* ainv, const int* active, const Cx<T>* w, double* partials,
+                 hipStream_t st) {
+    hipLaunchKernelGGL((k_pinv_ct<T, N, MODE, DOT>), dim3(nblk), dim3(plane_threads<N>()), (plane_lds<T, N>()), st,
+                       slab, x, y, b, ainv, g, tw, nrhs, active, w, partials);
+}
+
 template <class T, int N>
-hipError_t pass_n(int which, int tx, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
+hipError_t pass_n(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
                   const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv, const int* active, int mode,
-                  hipStream_t st) {
+                  int dot, const Cx<T>* w, double* partials, hipStream_t st) {
     const int nplanes = nrhs * 3 * N;
     const int nblk_plane = (nplanes + 7) / 8 * 8 * 4;
     if (which == 0 || which == 2) {
@@ -199,16 +334,31 @@ hipError_t pass_n(int which, int tx, const Geo& g, const Tw<T>& tw, int nrhs, co
                 hipLaunchKernelGGL((k_pfwd_ct<T, N>), dim3(nblk_plane), dim3(plane_threads<N>()), (plane_lds<T, N>()), st,
                                    x, slab, g, tw, nrhs, active);
             } else if (mode == MV_AX) {
-                hipLaunchKernelGGL((k_pinv_ct<T, N, MV_AX>), dim3(nblk_plane), dim3(plane_threads<N>()),
-                                   (plane_lds<T, N>()), st, slab, x, y, b, ainv, g, tw, nrhs, active);
+                if (dot == 1) launch_pinv<T, N, MV_AX, 1>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                else if (dot == 2) launch_pinv<T, N, MV_AX, 2>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                else launch_pinv<T, N, MV_AX, 0>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
             } else {
-                hipLaunchKernelGGL((k_pinv_ct<T, N, MV_RESID>), dim3(nblk_plane), dim3(plane_threads<N>()),
-                                   (plane_lds<T, N>()), st, slab, x, y, b, ainv, g, tw, nrhs, active);
+                launch_pinv<T, N, MV_RESID, 0>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
             }
             return hipGetLastError();
         }
     }
     const int ntile = 4 * N * N;
+#define ZP2(TXV)                                                                                                   \
+    if (tx == TXV && zrb) {                                                                                        \
+        if constexpr (zpass_lds<T, N, TXV>() > LDS_MAX || (N % TXV) != 0) {                                        \
+            return hipErrorNotSupported;                                                                           \
+        } else {                                                                                                   \
+            hipLaunchKernelGGL((k_zpass2_ct<T, N, TXV, 8>), dim3(ntile / TXV, (nrhs + 7) / 8),                     \
+                               dim3(zpass_threads<N>()), (zpass_lds<T, N, TXV>()), st, slab, ghat, g, tw, nrhs,    \
+                               active);                                                                            \
+            return hipGetLastError();                                                                              \
+        }                                                                                                          \
+    }
+    ZP2(8)
+    ZP2(16)
+    ZP2(32)
+#undef ZP2
 #define ZP(TXV)                                                                                                    \
     if (tx == TXV) {                                                                                               \
         if constexpr (zpass_lds<T, N, TXV>() > LDS_MAX || (N % TXV) != 0) {                                        \
@@ -231,22 +381,27 @@ hipError_t set_attrs_n() {
     const int lim = 160 * 1024;
     hipError_t e = hipSuccess;
     if constexpr (plane_lds<T, N>() <= LDS_MAX) {
-        e = hipFuncSetAttribute((const void*)k_pfwd_ct<T, N>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_pinv_ct<T, N, MV_AX>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_pinv_ct<T, N, MV_RESID>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    lim);
+        e = set_lds_limit((const void*)k_pfwd_ct<T, N>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        const void* fns[] = {(const void*)k_pinv_ct<T, N, MV_AX, 0>, (const void*)k_pinv_ct<T, N, MV_AX, 1>,
+                             (const void*)k_pinv_ct<T, N, MV_AX, 2>, (const void*)k_pinv_ct<T, N, MV_RESID, 0>};
+        for (const void* f : fns)
+            if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     }
     if constexpr (zpass_lds<T, N, 8>() <= LDS_MAX && N % 8 == 0)
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_zpass_ct<T, N, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+            e = set_lds_limit((const void*)k_zpass_ct<T, N, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_zpass2_ct<T, N, 8, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if constexpr (zpass_lds<T, N, 16>() <= LDS_MAX && N % 16 == 0)
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_zpass_ct<T, N, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+            e = set_lds_limit((const void*)k_zpass_ct<T, N, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_zpass2_ct<T, N, 16, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if constexpr (zpass_lds<T, N, 32>() <= LDS_MAX && N % 32 == 0)
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_zpass_ct<T, N, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+            e = set_lds_limit((const void*)k_zpass_ct<T, N, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_zpass2_ct<T, N, 32, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     return e;
 }
 
@@ -258,17 +413,19 @@ bool ct_supported(int n1, int n2, int n3) {
 }
 
 template <class T>
-hipError_t launch_pass_ct(int which, int tx, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
-                          const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv, const int* active,
-                          int mode, hipStream_t st) {
+hipError_t launch_pass_ct(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x,
+                          Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
+                          const int* active, int mode, int dot, const Cx<T>* w, double* partials, hipStream_t st) {
     if (!ct_supported(g.n1, g.n2, g.n3)) return hipErrorNotSupported;
+#define PN(NV) pass_n<T, NV>(which, tx, zrb, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, dot, w, partials, st)
     switch (g.n1) {
-        case 16: return pass_n<T, 16>(which, tx, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, st);
-        case 32: return pass_n<T, 32>(which, tx, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, st);
-        case 48: return pass_n<T, 48>(which, tx, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, st);
-        case 64: return pass_n<T, 64>(which, tx, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, st);
-        default: return pass_n<T, 128>(which, tx, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, st);
+        case 16: return PN(16);
+        case 32: return PN(32);
+        case 48: return PN(48);
+        case 64: return PN(64);
+        default: return PN(128);
     }
+#undef PN
 }
 
 // Which passes of a cubic box of side n have a specialised kernel in precision
@@ -294,11 +451,12 @@ hipError_t configure_ct_kernels() {
     return hipSuccess;
 }
 
-template hipError_t launch_pass_ct<float>(int, int, const Geo&, const Tw<float>&, int, const Cx<float>*, Cx<float>*,
-                                          const Cx<float>*, Cx<float>*, const Cx<float>*, const Cx<float>*, const int*,
-                                          int, hipStream_t);
-template hipError_t launch_pass_ct<double>(int, int, const Geo&, const Tw<double>&, int, const Cx<double>*,
+template hipError_t launch_pass_ct<float>(int, int, int, const Geo&, const Tw<float>&, int, const Cx<float>*,
+                                          Cx<float>*, const Cx<float>*, Cx<float>*, const Cx<float>*, const Cx<float>*,
+                                          const int*, int, int, const Cx<float>*, double*, hipStream_t);
+template hipError_t launch_pass_ct<double>(int, int, int, const Geo&, const Tw<double>&, int, const Cx<double>*,
                                            Cx<double>*, const Cx<double>*, Cx<double>*, const Cx<double>*,
-                                           const Cx<double>*, const int*, int, hipStream_t);
+                                           const Cx<double>*, const int*, int, int, const Cx<double>*, double*,
+                                           hipStream_t);
 template int ct_available<float>(int, int);
 template int ct_available<double>(int, int);

@@ -477,9 +477,9 @@ hipError_t launch_bicg_xr(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p
                        st_, partials, active);
     return hipGetLastError();
 }
-hipError_t launch_scalars(int which, int Npad, int nrhs, BiState* s, const double* partials, int* active,
+hipError_t launch_scalars(int which, int nblk, int nrhs, BiState* s, const double* partials, int* active,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_scalars, dim3(nrhs), dim3(256), 0, st, which, vec_blocks(Npad), s, partials, active);
+    hipLaunchKernelGGL(k_scalars, dim3(nrhs), dim3(256), 0, st, which, nblk, s, partials, active);
     return hipGetLastError();
 }
 template <class T>

@@ -1,0 +1,935 @@
+// Learned Krylov initial guess for the DDA solve: a 3D convolutional network
+// on the target's n x n x n box, trained on the GPU by its own BF16 MFMA
+// kernels (FP32 accumulate, FP32 master weights, Adam).
+//
+// Input features per voxel (16 channels, zero outside the target):
+//   occupancy, Re/Im E_inc (3 components), Re/Im (eps-1)/(eps+2), k d, khat.
+// Output: 16 channels, the first 6 = Re/Im of a correction to the local field:
+//   E_loc = E_inc + net(features),  P0 = alpha E_loc = E_loc / (1/alpha).
+// A network of zeros therefore reproduces the guess P0 = alpha E_inc.
+//
+// Layers: 3x3x3 convolutions with dilation, ReLU after all but the last.
+// Activations are channels-last BF16 [sample][voxel][channel].
+//
+// Convolution = implicit GEMM on v_mfma_f32_16x16x16_bf16: M = voxels (16 per
+// wave, 64 per block), N = output channels, K = 27 offsets x input channels.
+// The same kernel computes the data gradient (convolution of the output
+// gradient with the flipped, channel-transposed weights, masked by the ReLU of
+// the layer input).  The weight gradient is a GEMM over voxels with operands
+// transposed through LDS, accumulated per block and reduced over blocks.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/dda.h"
+#include "dda_internal.h"
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+namespace nnk {
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ __forceinline__ void offset_of(int o, int& dx, int& dy, int& dz) {
+    dz = o / 9 - 1;
+    dy = (o / 3) % 3 - 1;
+    dx = o % 3 - 1;
+}
+
+enum { EPI_RELU = 0, EPI_F32 = 1, EPI_MASK = 2 };
+
+// Implicit-GEMM convolution.  X: [ns][V][KC] bf16.  Wb: [27][NC][KC] bf16 (the
+// B operand; for the data gradient the caller passes the weights with the
+// channel roles swapped and FLIP = 1, which negates the offsets).
+template <int KC, int NC, int FLIP, int EPI>
+__global__ void __launch_bounds__(256) k_conv(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wb,
+                                              const float* __restrict__ bias, void* __restrict__ Y,
+                                              const uint16_t* __restrict__ mask_act, int D, int dil) {
+    extern __shared__ unsigned char smem_raw[];
+    uint16_t* wl = reinterpret_cast<uint16_t*>(smem_raw);
+    const int V = D * D * D;
+    const int s = blockIdx.y;
+    const int tid = threadIdx.x;
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(Wb);
+        uint4* dst = reinterpret_cast<uint4*>(wl);
+        for (int i = tid; i < 27 * NC * KC / 8; i += 256) dst[i] = src[i];
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    const int i = lane & 15, kb = (lane >> 4) * 4;
+    const int vb = blockIdx.x * 64 + wave * 16;
+    const int v = vb + i;
+    const int x = v % D, y = (v / D) % D, z = v / (D * D);
+    const uint16_t* xs = X + (size_t)s * V * KC;
+    f4 acc[NC / 16];
+#pragma unroll
+    for (int t = 0; t < NC / 16; ++t) acc[t] = f4{0, 0, 0, 0};
+    for (int o = 0; o < 27; ++o) {
+        int dx, dy, dz;
+        offset_of(o, dx, dy, dz);
+        if (FLIP) {
+            dx = -dx;
+            dy = -dy;
+            dz = -dz;
+        }
+        const int xx = x + dil * dx, yy = y + dil * dy, zz = z + dil * dz;
+        const bool ok = (v < V) && xx >= 0 && xx < D && yy >= 0 && yy < D && zz >= 0 && zz < D;
+        const uint16_t* src = xs + ((size_t)(zz * D + yy) * D + xx) * KC;
+#pragma unroll
+        for (int kc = 0; kc < KC; kc += 16) {
+            s4 a = {0, 0, 0, 0};
+            if (ok) a = *reinterpret_cast<const s4*>(src + kc + kb);
+#pragma unroll
+            for (int t = 0; t < NC / 16; ++t) {
+                const s4 b = *reinterpret_cast<const s4*>(wl + ((o * NC) + t * 16 + i) * KC + kc + kb);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // D fragment: lane holds rows (lane >> 4) * 4 + r, column lane & 15
+    const int i4 = (lane >> 4) * 4, j = lane & 15;
+#pragma unroll
+    for (int t = 0; t < NC / 16; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int vv = vb + i4 + r;
+            if (vv >= V) continue;
+            const int ch = t * 16 + j;
+            const size_t oi = ((size_t)s * V + vv) * NC + ch;
+            float val = acc[t][r];
+            if (EPI == EPI_RELU) {
+                val = fmaxf(val + bias[ch], 0.0f);
+                reinterpret_cast<uint16_t*>(Y)[oi] = f2bf(val);
+            } else if (EPI == EPI_F32) {
+                reinterpret_cast<float*>(Y)[oi] = val + bias[ch];
+            } else {
+                if (!(bf2f(mask_act[oi]) > 0.0f)) val = 0.0f;
+                reinterpret_cast<uint16_t*>(Y)[oi] = f2bf(val);
+            }
+        }
+    }
+}
+
+// Weight gradient: dW[o][ci][co] += sum_v X[v + dil off_o][ci] dY[v][co] for a
+// block of consecutive x-rows of one sample; partials[blk][27][KC][NC].
+// LDS: the 9 input rows around the output row, transposed to [ci][x + pad],
+// and the output-gradient row transposed to [co][x].
+template <int KC, int NC>
+__global__ void __launch_bounds__(256) k_wgrad(const uint16_t* __restrict__ X, const uint16_t* __restrict__ dY,
+                                               float* __restrict__ partials, int D, int dil, int rows_per_block) {
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int NT = 27 * (KC / 16) * (NC / 16);  // 16x16 tiles of dW
+    constexpr int TPW = (NT + 3) / 4;               // tiles per wave
+    const int pad = dil;
+    const int XW = D + 2 * pad;
+    uint16_t* xt = reinterpret_cast<uint16_t*>(smem_raw);  // [9][KC][XW]
+    uint16_t* gt = xt + 9 * KC * XW;                        // [NC][D]
+    const int V = D * D * D;
+    const int s = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i = lane & 15, kb = (lane >> 4) * 4;
+    f4 acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = f4{0, 0, 0, 0};
+    const int row0 = blockIdx.x * rows_per_block;
+    for (int rr = 0; rr < rows_per_block; ++rr) {
+        const int row = row0 + rr;
+        if (row >= D * D) break;
+        const int y = row % D, z = row / D;
+        __syncthreads();
+        // input rows (z + dil dz, y + dil dy), padded in x
+        for (int idx = tid; idx < 9 * KC * XW; idx += 256) {
+            const int xw = idx % XW, ci = (idx / XW) % KC, r9 = idx / (XW * KC);
+            const int yy = y + dil * (r9 % 3 - 1), zz = z + dil * (r9 / 3 - 1), xx = xw - pad;
+            uint16_t val = 0;
+            if (xx >= 0 && xx < D && yy >= 0 && yy < D && zz >= 0 && zz < D)
+                val = X[((size_t)s * V + (size_t)(zz * D + yy) * D + xx) * KC + ci];
+            xt[idx] = val;
+        }
+        for (int idx = tid; idx < NC * D; idx += 256) {
+            const int xx = idx % D, co = idx / D;
+            gt[idx] = dY[((size_t)s * V + (size_t)row * D + xx) * NC + co];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int tile = wave * TPW + t;
+            if (tile >= NT) break;
+            const int o = tile / ((KC / 16) * (NC / 16));
+            const int cit = (tile / (NC / 16)) % (KC / 16), cot = tile % (NC / 16);
+            int dx, dy, dz;
+            offset_of(o, dx, dy, dz);
+            const int r9 = (dz + 1) * 3 + (dy + 1);
+            const uint16_t* arow = xt + ((size_t)r9 * KC + cit * 16 + i) * XW + pad + dil * dx;
+            const uint16_t* brow = gt + (size_t)(cot * 16 + i) * D;
+            for (int x0 = 0; x0 < D; x0 += 16) {
+                s4 a, b;
+                a[0] = arow[x0 + kb];
+                a[1] = arow[x0 + kb + 1];
+                a[2] = arow[x0 + kb + 2];
+                a[3] = arow[x0 + kb + 3];
+                b[0] = brow[x0 + kb];
+                b[1] = brow[x0 + kb + 1];
+                b[2] = brow[x0 + kb + 2];
+                b[3] = brow[x0 + kb + 3];
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // write this block's partial: D[i = ci][j = co]
+    const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    float* out = partials + blk * 27 * KC * NC;
+    const int i4 = (lane >> 4) * 4, j = lane & 15;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int tile = wave * TPW + t;
+        if (tile >= NT) break;
+        const int o = tile / ((KC / 16) * (NC / 16));
+        const int cit = (tile / (NC / 16)) % (KC / 16), cot = tile % (NC / 16);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            out[((size_t)o * KC + cit * 16 + i4 + r) * NC + cot * 16 + j] = acc[t][r];
+    }
+}
+
+__global__ void k_reduce_partials(const float* __restrict__ partials, int nblk, int n, float* __restrict__ g) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float acc = 0;
+    for (int b = 0; b < nblk; ++b) acc += partials[(size_t)b * n + e];
+    g[e] += acc;
+}
+
+// db[co] += sum over voxels and samples of dY[.][co]
+__global__ void k_bias_grad(const uint16_t* __restrict__ dY, int nvox, int NC, float* __restrict__ g) {
+    __shared__ double sh[16];
+    const int co = blockIdx.x;
+    double acc = 0;
+    for (int v = threadIdx.x; v < nvox; v += blockDim.x) acc += bf2f(dY[(size_t)v * NC + co]);
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) g[co] += (float)acc;
+}
+
+// Adam with decoupled weight decay on FP32 master weights; refreshes the two
+// BF16 operand layouts of every layer (forward [o][co][ci], data gradient
+// [o][ci][co]); the bias is copied as is.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       int n, float lr, float b1, float b2, float eps, float wd, float c1, float c2, float gscale) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gg = g[e] * gscale;
+    const float mm = b1 * m[e] + (1 - b1) * gg;
+    const float vv = b2 * v[e] + (1 - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    p[e] -= lr * ((mm / c1) / (sqrtf(vv / c2) + eps) + wd * p[e]);
+}
+
+__global__ void k_pack_weights(const float* __restrict__ w, int cin, int cout, uint16_t* __restrict__ wf,
+                               uint16_t* __restrict__ wd) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 27 * cin * cout) return;
+    const int co = e % cout, ci = (e / cout) % cin, o = e / (cin * cout);
+    const uint16_t h = f2bf(w[e]);
+    wf[((size_t)o * cout + co) * cin + ci] = h;
+    wd[e] = h;
+}
+
+// Features of one sample on the n^3 box (zero outside the target).
+struct SampleDev {
+    double khat[3];
+    double e[6];
+    double kd;
+    double ox, oy, oz;
+    int N, Npad;
+    const uint32_t* site_xyz;
+    const uint8_t* site_comp;
+    const double* kfac;  // Re/Im (eps-1)/(eps+2) per composition
+    const double* ainv;  // Re/Im 1/alpha per composition
+    const float* resid;  // [3][Npad] complex: E_loc - E_inc (training target) or nullptr
+};
+
+__global__ void k_zero16(uint16_t* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void k_features(const SampleDev* __restrict__ sd, int D, uint16_t* __restrict__ X) {
+    const int s = blockIdx.y;
+    const SampleDev S = sd[s];
+    const size_t V = (size_t)D * D * D;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < S.N; j += gridDim.x * blockDim.x) {
+        const uint32_t q = S.site_xyz[j];
+        const int x = q & 1023, y = (q >> 10) & 1023, z = q >> 20;
+        const int c = S.site_comp[j];
+        double sn, cs;
+        sincos(S.kd * (S.khat[0] * (x - S.ox) + S.khat[1] * (y - S.oy) + S.khat[2] * (z - S.oz)), &sn, &cs);
+        float f[16];
+        f[0] = 1.0f;
+        for (int a = 0; a < 3; ++a) {
+            f[1 + 2 * a] = (float)(S.e[2 * a] * cs - S.e[2 * a + 1] * sn);
+            f[2 + 2 * a] = (float)(S.e[2 * a] * sn + S.e[2 * a + 1] * cs);
+        }
+        f[7] = (float)S.kfac[2 * c];
+        f[8] = (float)S.kfac[2 * c + 1];
+        f[9] = (float)S.kd;
+        f[10] = (float)S.khat[0];
+        f[11] = (float)S.khat[1];
+        f[12] = (float)S.khat[2];
+        f[13] = f[14] = f[15] = 0.0f;
+        uint16_t* o = X + ((size_t)s * V + (size_t)(z * D + y) * D + x) * 16;
+        for (int k = 0; k < 16; ++k) o[k] = f2bf(f[k]);
+    }
+}
+
+// Masked loss: per sample sum over sites of |out - resid|^2 / sum |resid + E_inc|^2
+// (normalised by the local field), gradient into dY (bf16, zero elsewhere).
+__global__ void k_loss(const SampleDev* __restrict__ sd, int D, const float* __restrict__ out,
+                       uint16_t* __restrict__ dY, double* __restrict__ loss_acc, float gnorm) {
+    __shared__ double sh[16];
+    const int s = blockIdx.y;
+    const SampleDev S = sd[s];
+    const size_t V = (size_t)D * D * D;
+    double num = 0, den = 0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < S.N; j += gridDim.x * blockDim.x) {
+        const uint32_t q = S.site_xyz[j];
+        const int x = q & 1023, y = (q >> 10) & 1023, z = q >> 20;
+        const size_t vi = (size_t)s * V + (size_t)(z * D + y) * D + x;
+        for (int a = 0; a < 3; ++a) {
+            const float tr = S.resid[(size_t)(2 * a) * S.Npad + 2 * j], ti = S.resid[(size_t)(2 * a) * S.Npad + 2 * j + 1];
+            const float orr = out[vi * 16 + 2 * a], oi = out[vi * 16 + 2 * a + 1];
+            const float dr = orr - tr, di = oi - ti;
+            num += (double)dr * dr + (double)di * di;
+            dY[vi * 16 + 2 * a] = f2bf(2.0f * dr * gnorm);
+            dY[vi * 16 + 2 * a + 1] = f2bf(2.0f * di * gnorm);
+        }
+        (void)den;
+    }
+    num = block_sum(num, sh);
+    if (threadIdx.x == 0) atomicAdd(loss_acc + s, num);
+}
+
+// Guess P0 = (E_inc + out) / (1/alpha) into x64 ([3][Npad] complex128 of rhs slot).
+__global__ void k_guess(const SampleDev* __restrict__ sd, int D, const float* __restrict__ out, Cx<double>* __restrict__ x64) {
+    const int s = blockIdx.y;
+    const SampleDev S = sd[s];
+    const size_t V = (size_t)D * D * D;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < S.N; j += gridDim.x * blockDim.x) {
+        const uint32_t q = S.site_xyz[j];
+        const int x = q & 1023, y = (q >> 10) & 1023, z = q >> 20;
+        const int c = S.site_comp[j];
+        const size_t vi = (size_t)s * V + (size_t)(z * D + y) * D + x;
+        double sn, cs;
+        sincos(S.kd * (S.khat[0] * (x - S.ox) + S.khat[1] * (y - S.oy) + S.khat[2] * (z - S.oz)), &sn, &cs);
+        const double ar = S.ainv[2 * c], ai = S.ainv[2 * c + 1];
+        const double den = ar * ar + ai * ai;
+        for (int a = 0; a < 3; ++a) {
+            const double er = S.e[2 * a] * cs - S.e[2 * a + 1] * sn + out[vi * 16 + 2 * a];
+            const double ei = S.e[2 * a] * sn + S.e[2 * a + 1] * cs + out[vi * 16 + 2 * a + 1];
+            // (er + i ei) / (ar + i ai)
+            x64[((size_t)s * 3 + a) * S.Npad + j] = Cx<double>{(er * ar + ei * ai) / den, (ei * ar - er * ai) / den};
+        }
+    }
+}
+
+// Training target: resid = (1/alpha) P - E_inc from a solution in [3][Npad] complex128.
+__global__ void k_record(const SampleDev* __restrict__ sd, const Cx<double>* __restrict__ P, float* __restrict__ resid) {
+    const SampleDev S = sd[0];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < S.N; j += gridDim.x * blockDim.x) {
+        const uint32_t q = S.site_xyz[j];
+        const int x = q & 1023, y = (q >> 10) & 1023, z = q >> 20;
+        const int c = S.site_comp[j];
+        double sn, cs;
+        sincos(S.kd * (S.khat[0] * (x - S.ox) + S.khat[1] * (y - S.oy) + S.khat[2] * (z - S.oz)), &sn, &cs);
+        const double ar = S.ainv[2 * c], ai = S.ainv[2 * c + 1];
+        for (int a = 0; a < 3; ++a) {
+            const Cx<double> p = P[(size_t)a * S.Npad + j];
+            const double lr = ar * p.re - ai * p.im, li = ar * p.im + ai * p.re;
+            resid[(size_t)(2 * a) * S.Npad + 2 * j] = (float)(lr - (S.e[2 * a] * cs - S.e[2 * a + 1] * sn));
+            resid[(size_t)(2 * a) * S.Npad + 2 * j + 1] = (float)(li - (S.e[2 * a] * sn + S.e[2 * a + 1] * cs));
+        }
+    }
+}
+
+// dense test-hook helpers: float <-> bf16 arrays
+__global__ void k_f2bf(const float* __restrict__ a, uint16_t* __restrict__ b, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = f2bf(a[i]);
+}
+// masked-MSE gradient on dense arrays (test hook): per sample normalised by sum |target|^2 over the mask
+__global__ void k_dense_loss(const float* __restrict__ out, const float* __restrict__ tgt, const uint8_t* __restrict__ mask,
+                             const double* __restrict__ den, int V, int nout, uint16_t* __restrict__ dY,
+                             double* __restrict__ loss, float scale) {
+    __shared__ double sh[16];
+    const int s = blockIdx.y;
+    double num = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < V; v += gridDim.x * blockDim.x) {
+        const size_t vi = (size_t)s * V + v;
+        const bool m = mask[vi] != 0;
+        for (int c = 0; c < 16; ++c) {
+            float g = 0;
+            if (m && c < nout) {
+                const float d = out[vi * 16 + c] - tgt[vi * 16 + c];
+                num += (double)d * d;
+                g = (float)(2.0 * d / den[s]) * scale;
+            }
+            dY[vi * 16 + c] = f2bf(g);
+        }
+    }
+    num = block_sum(num, sh);
+    if (threadIdx.x == 0) atomicAdd(loss + s, num / den[s]);
+}
+
+}  // namespace nnk
+
+using namespace nnk;
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+namespace {
+struct DBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    ~DBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        if (!bytes) return hipSuccess;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipSuccess) n = bytes;
+        return e;
+    }
+    template <class U>
+    U* as() const { return reinterpret_cast<U*>(p); }
+};
+
+struct Layer {
+    int cin, cout, dil;
+    size_t woff, boff;  // offsets into the flat parameter vector (floats)
+};
+
+struct Sample {
+    int tgt;  // target id in the context at recording time
+    SampleDev dev;
+    std::shared_ptr<DBuf> resid;
+};
+
+#define NCHK(x)                                   \
+    do {                                          \
+        hipError_t e_ = (x);                      \
+        if (e_ != hipSuccess) return e_;          \
+    } while (0)
+
+template <int KC, int NC>
+size_t conv_lds() { return (size_t)27 * NC * KC * 2; }
+
+template <int KC, int NC, int FLIP, int EPI>
+hipError_t conv_launch(const uint16_t* X, const uint16_t* W, const float* b, void* Y, const uint16_t* mask, int D, int dil,
+                       int ns, hipStream_t st) {
+    const int V = D * D * D;
+    static bool attr = false;
+    if (!attr) {
+        NCHK(set_lds_limit((const void*)k_conv<KC, NC, FLIP, EPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                           160 * 1024));
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_conv<KC, NC, FLIP, EPI>), dim3((V + 63) / 64, ns), dim3(256), (conv_lds<KC, NC>()), st, X, W, b,
+                       Y, mask, D, dil);
+    return hipGetLastError();
+}
+
+template <int KC, int NC>
+hipError_t wgrad_launch(const uint16_t* X, const uint16_t* dY, float* partials, float* g, int D, int dil, int ns,
+                        int rows_per_block, hipStream_t st) {
+    static bool attr = false;
+    if (!attr) {
+        NCHK(set_lds_limit((const void*)k_wgrad<KC, NC>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr = true;
+    }
+    const int nbx = (D * D + rows_per_block - 1) / rows_per_block;
+    const size_t lds = ((size_t)9 * KC * (D + 2 * dil) + (size_t)NC * D) * 2;
+    hipLaunchKernelGGL((k_wgrad<KC, NC>), dim3(nbx, ns), dim3(256), lds, st, X, dY, partials, D, dil, rows_per_block);
+    NCHK(hipGetLastError());
+    const int n = 27 * KC * NC;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((n + 255) / 256), dim3(256), 0, st, partials, nbx * ns, n, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+struct dda_nn {
+    int width = 32, depth = 6, seed = 1;
+    int D = 0;    // box side the buffers are sized for
+    int box = 0;  // box side of the recorded training samples
+    std::vector<Layer> layers;
+    size_t nparams = 0;
+    DBuf p, g, m, v;                  // FP32 master params, grads, Adam moments
+    std::vector<DBuf> wf, wd;         // per layer BF16 operand layouts
+    std::vector<DBuf> act;            // per layer output activations (bf16), act[0] = features
+    DBuf out32, dA, dB, partials, lossacc, sdev;
+    int ns_cap = 0;
+    int adam_t = 0;
+    std::vector<Sample> samples;
+    std::string err;
+};
+
+namespace {
+
+hipError_t nn_pack(dda_nn* nn, hipStream_t st) {
+    for (size_t l = 0; l < nn->layers.size(); ++l) {
+        const Layer& L = nn->layers[l];
+        const int n = 27 * L.cin * L.cout;
+        hipLaunchKernelGGL(k_pack_weights, dim3((n + 255) / 256), dim3(256), 0, st, nn->p.as<float>() + L.woff, L.cin,
+                           L.cout, nn->wf[l].as<uint16_t>(), nn->wd[l].as<uint16_t>());
+        NCHK(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+hipError_t nn_buffers(dda_nn* nn, int D, int ns) {
+    if (nn->D == D && nn->ns_cap >= ns) return hipSuccess;
+    const size_t V = (size_t)D * D * D;
+    nn->act.resize(nn->layers.size() + 1);
+    NCHK(nn->act[0].ensure(V * ns * 16 * 2));
+    for (size_t l = 0; l < nn->layers.size(); ++l) NCHK(nn->act[l + 1].ensure(V * ns * nn->layers[l].cout * 2));
+    NCHK(nn->out32.ensure(V * ns * 16 * 4));
+    const int wmax = std::max(nn->width, 16);
+    NCHK(nn->dA.ensure(V * ns * wmax * 2));
+    NCHK(nn->dB.ensure(V * ns * wmax * 2));
+    NCHK(nn->partials.ensure((size_t)ns * D * 27 * wmax * wmax * 4));
+    NCHK(nn->lossacc.ensure(ns * sizeof(double)));
+    NCHK(nn->sdev.ensure(ns * sizeof(SampleDev)));
+    nn->D = D;
+    nn->ns_cap = ns;
+    return hipSuccess;
+}
+
+template <int W>
+hipError_t conv_fwd_layer(dda_nn* nn, int l, int ns, hipStream_t st) {
+    const Layer& L = nn->layers[l];
+    const uint16_t* X = nn->act[l].as<uint16_t>();
+    const float* b = nn->p.as<float>() + L.boff;
+    const bool last = (size_t)l + 1 == nn->layers.size();
+    const uint16_t* Wt = nn->wf[l].as<uint16_t>();
+    if (last) {
+        if (L.cin == W) return conv_launch<W, 16, 0, EPI_F32>(X, Wt, b, nn->out32.p, nullptr, nn->D, L.dil, ns, st);
+        return conv_launch<16, 16, 0, EPI_F32>(X, Wt, b, nn->out32.p, nullptr, nn->D, L.dil, ns, st);
+    }
+    void* Y = nn->act[l + 1].p;
+    if (L.cin == 16) return conv_launch<16, W, 0, EPI_RELU>(X, Wt, b, Y, nullptr, nn->D, L.dil, ns, st);
+    return conv_launch<W, W, 0, EPI_RELU>(X, Wt, b, Y, nullptr, nn->D, L.dil, ns, st);
+}
+
+template <int W>
+hipError_t nn_forward(dda_nn* nn, int ns, hipStream_t st) {
+    for (size_t l = 0; l < nn->layers.size(); ++l) NCHK(conv_fwd_layer<W>(nn, (int)l, ns, st));
+    return hipSuccess;
+}
+
+// Backward from dY of the last layer (in nn->dA); accumulates nn->g.
+template <int W>
+hipError_t nn_backward(dda_nn* nn, int ns, hipStream_t st) {
+    uint16_t* gcur = nn->dA.as<uint16_t>();
+    uint16_t* gnext = nn->dB.as<uint16_t>();
+    const int D = nn->D;
+    const int rpb = D;  // one z-plane of rows per block
+    for (int l = (int)nn->layers.size() - 1; l >= 0; --l) {
+        const Layer& L = nn->layers[l];
+        const uint16_t* X = nn->act[l].as<uint16_t>();
+        float* gw = nn->g.as<float>() + L.woff;
+        float* gb = nn->g.as<float>() + L.boff;
+        // weight and bias gradients
+        if (L.cin == 16 && L.cout == W) NCHK((wgrad_launch<16, W>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
+        else if (L.cin == W && L.cout == W) NCHK((wgrad_launch<W, W>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
+        else if (L.cin == W && L.cout == 16) NCHK((wgrad_launch<W, 16>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
+        else NCHK((wgrad_launch<16, 16>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
+        hipLaunchKernelGGL(k_bias_grad, dim3(L.cout), dim3(256), 0, st, gcur, D * D * D * ns, L.cout, gb);
+        NCHK(hipGetLastError());
+        if (l == 0) break;
+        // data gradient, masked by the ReLU of this layer's input
+        const uint16_t* Wd = nn->wd[l].as<uint16_t>();
+        if (L.cout == 16 && L.cin == W)
+            NCHK((conv_launch<16, W, 1, EPI_MASK>(gcur, Wd, nullptr, gnext, X, D, L.dil, ns, st)));
+        else if (L.cout == W && L.cin == W)
+            NCHK((conv_launch<W, W, 1, EPI_MASK>(gcur, Wd, nullptr, gnext, X, D, L.dil, ns, st)));
+        else if (L.cout == W && L.cin == 16)
+            NCHK((conv_launch<W, 16, 1, EPI_MASK>(gcur, Wd, nullptr, gnext, X, D, L.dil, ns, st)));
+        else
+            NCHK((conv_launch<16, 16, 1, EPI_MASK>(gcur, Wd, nullptr, gnext, X, D, L.dil, ns, st)));
+        std::swap(gcur, gnext);
+    }
+    return hipSuccess;
+}
+
+hipError_t nn_forward_any(dda_nn* nn, int ns, hipStream_t st) {
+    if (nn->width == 32) return nn_forward<32>(nn, ns, st);
+    return nn_forward<16>(nn, ns, st);
+}
+hipError_t nn_backward_any(dda_nn* nn, int ns, hipStream_t st) {
+    if (nn->width == 32) return nn_backward<32>(nn, ns, st);
+    return nn_backward<16>(nn, ns, st);
+}
+
+hipError_t nn_adam(dda_nn* nn, float lr, float wd, float gscale, hipStream_t st) {
+    nn->adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)nn->adam_t), c2 = 1.0f - powf(b2, (float)nn->adam_t);
+    const int n = (int)nn->nparams;
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, nn->p.as<float>(), nn->g.as<float>(),
+                       nn->m.as<float>(), nn->v.as<float>(), n, lr, b1, b2, 1e-8f, wd, c1, c2, gscale);
+    NCHK(hipGetLastError());
+    return nn_pack(nn, st);
+}
+
+}  // namespace
+
+hipError_t nn_make_sample_dev(const NnSiteView& t, const dda_wave& w, const double* ainv, SampleDev& sd,
+                              DBuf& kfac_ainv) {
+    std::vector<double> h(4 * t.ncomp);
+    for (int c = 0; c < t.ncomp; ++c) {
+        const double mr = t.m[2 * c], mi = t.m[2 * c + 1];
+        // eps = m^2; K = (eps - 1)/(eps + 2)
+        const double er = mr * mr - mi * mi, ei = 2 * mr * mi;
+        const double nr = er - 1, ni = ei, dr = er + 2, di = ei;
+        const double dd = dr * dr + di * di;
+        h[2 * c] = (nr * dr + ni * di) / dd;
+        h[2 * c + 1] = (ni * dr - nr * di) / dd;
+        h[2 * t.ncomp + 2 * c] = ainv[2 * c];
+        h[2 * t.ncomp + 2 * c + 1] = ainv[2 * c + 1];
+    }
+    NCHK(kfac_ainv.ensure(h.size() * sizeof(double)));
+    NCHK(hipMemcpy(kfac_ainv.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    for (int i = 0; i < 3; ++i) sd.khat[i] = w.khat[i];
+    for (int i = 0; i < 6; ++i) sd.e[i] = w.e0[i];
+    sd.kd = t.kd;
+    sd.ox = t.origin[0];
+    sd.oy = t.origin[1];
+    sd.oz = t.origin[2];
+    sd.N = t.N;
+    sd.Npad = t.Npad;
+    sd.site_xyz = t.site_xyz;
+    sd.site_comp = t.site_comp;
+    sd.kfac = kfac_ainv.as<double>();
+    sd.ainv = kfac_ainv.as<double>() + 2 * t.ncomp;
+    sd.resid = nullptr;
+    return hipSuccess;
+}
+
+// Sample bookkeeping kept alive with the network: per-sample constants and
+// private copies of the site lists (so that samples outlive their targets).
+struct NnSampleStore {
+    std::vector<std::shared_ptr<DBuf>> aux;
+    std::vector<std::pair<long long, std::pair<std::shared_ptr<DBuf>, std::shared_ptr<DBuf>>>> geo;
+};
+static std::vector<std::pair<const dda_nn*, std::shared_ptr<NnSampleStore>>> g_stores;
+static NnSampleStore& store_of(const dda_nn* nn) {
+    for (auto& kv : g_stores)
+        if (kv.first == nn) return *kv.second;
+    g_stores.emplace_back(nn, std::make_shared<NnSampleStore>());
+    return *g_stores.back().second;
+}
+static void drop_store(const dda_nn* nn) {
+    for (size_t i = 0; i < g_stores.size(); ++i)
+        if (g_stores[i].first == nn) {
+            g_stores.erase(g_stores.begin() + i);
+            return;
+        }
+}
+
+// Record one solution (x64 slot of [3][Npad] complex128) as a training sample.
+hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, const double* ainv,
+                         const Cx<double>* x64, hipStream_t st) {
+    if (tv.n1 != tv.n2 || tv.n2 != tv.n3 || tv.n1 % 16) return hipErrorNotSupported;
+    if (nn->box && nn->box != tv.n1) return hipErrorInvalidValue;
+    nn->box = tv.n1;
+    NnSampleStore& store = store_of(nn);
+    NnSiteView t = tv;
+    // private copy of the site list, once per target
+    std::shared_ptr<DBuf> gx, gc;
+    for (auto& kv : store.geo)
+        if (kv.first == t.uid) {
+            gx = kv.second.first;
+            gc = kv.second.second;
+        }
+    if (!gx) {
+        gx = std::make_shared<DBuf>();
+        gc = std::make_shared<DBuf>();
+        NCHK(gx->ensure((size_t)t.N * 4));
+        NCHK(gc->ensure((size_t)t.N));
+        NCHK(hipMemcpy(gx->p, t.site_xyz, (size_t)t.N * 4, hipMemcpyDeviceToDevice));
+        NCHK(hipMemcpy(gc->p, t.site_comp, (size_t)t.N, hipMemcpyDeviceToDevice));
+        store.geo.push_back({t.uid, {gx, gc}});
+    }
+    t.site_xyz = gx->as<uint32_t>();
+    t.site_comp = gc->as<uint8_t>();
+    auto kb = std::make_shared<DBuf>();
+    auto rb = std::make_shared<DBuf>();
+    Sample S;
+    S.tgt = -1;
+    NCHK(nn_make_sample_dev(t, w, ainv, S.dev, *kb));
+    NCHK(rb->ensure((size_t)6 * t.Npad * sizeof(float)));
+    NCHK(hipMemsetAsync(rb->p, 0, rb->n, st));
+    DBuf one;
+    NCHK(one.ensure(sizeof(SampleDev)));
+    NCHK(hipMemcpyAsync(one.p, &S.dev, sizeof(SampleDev), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_record, dim3((t.N + 255) / 256), dim3(256), 0, st, one.as<SampleDev>(), x64, rb->as<float>());
+    NCHK(hipGetLastError());
+    NCHK(hipStreamSynchronize(st));
+    S.dev.resid = rb->as<float>();
+    S.resid = rb;
+    store.aux.push_back(kb);
+    nn->samples.push_back(S);
+    return hipSuccess;
+}
+
+// Guesses P0 for nr right-hand sides of one target into x64 ([rhs][3][Npad] complex128).
+hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves, const double* ainv, int nr,
+                          Cx<double>* x64, hipStream_t st) {
+    if (t.n1 != t.n2 || t.n2 != t.n3 || t.n1 % 16) return hipErrorNotSupported;
+    const int D = t.n1;
+    const int chunk = 4;
+    NCHK(nn_buffers(nn, D, chunk));
+    std::vector<SampleDev> sds(chunk);
+    std::vector<DBuf> kb(chunk);
+    const size_t V = (size_t)D * D * D;
+    for (int s0 = 0; s0 < nr; s0 += chunk) {
+        const int nb = std::min(chunk, nr - s0);
+        for (int k = 0; k < nb; ++k) NCHK(nn_make_sample_dev(t, waves[s0 + k], ainv + (size_t)(s0 + k) * 2 * t.ncomp, sds[k], kb[k]));
+        NCHK(hipMemcpyAsync(nn->sdev.p, sds.data(), nb * sizeof(SampleDev), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, nn->act[0].as<uint16_t>(), V * nb * 16);
+        NCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_features, dim3(256, nb), dim3(256), 0, st, nn->sdev.as<SampleDev>(), D,
+                           nn->act[0].as<uint16_t>());
+        NCHK(hipGetLastError());
+        NCHK(nn_forward_any(nn, nb, st));
+        hipLaunchKernelGGL(k_guess, dim3(256, nb), dim3(256), 0, st, nn->sdev.as<SampleDev>(), D, nn->out32.as<float>(),
+                           x64 + (size_t)s0 * 3 * t.Npad);
+        NCHK(hipGetLastError());
+        NCHK(hipStreamSynchronize(st));  // sdev and kb are reused by the next chunk
+    }
+    return hipSuccess;
+}
+
+
+// ---- C ABI ----
+extern "C" {
+
+dda_status dda_nn_create(dda_ctx* ctx, const dda_nn_config* cfg, dda_nn** out) {
+    (void)ctx;
+    if (!cfg || !out) return DDA_ERR_INVALID_ARG;
+    if (!(cfg->width == 16 || cfg->width == 32) || cfg->depth < 2 || cfg->depth > 16)
+        return DDA_ERR_INVALID_ARG;
+    std::unique_ptr<dda_nn> nn(new dda_nn());
+    nn->width = cfg->width;
+    nn->depth = cfg->depth;
+    nn->seed = cfg->seed;
+    static const int mid[] = {2, 4, 8, 1};
+    size_t off = 0;
+    for (int l = 0; l < cfg->depth; ++l) {
+        Layer L;
+        L.cin = l == 0 ? 16 : cfg->width;
+        L.cout = l == cfg->depth - 1 ? 16 : cfg->width;
+        L.dil = (l == 0 || l >= cfg->depth - 2) ? 1 : mid[(l - 1) % 4];
+        L.woff = off;
+        off += (size_t)27 * L.cin * L.cout;
+        L.boff = off;
+        off += L.cout;
+        nn->layers.push_back(L);
+    }
+    nn->nparams = off;
+    // He-style initialisation; the last layer starts at zero so that the
+    // untrained network reproduces P0 = alpha E_inc.
+    std::vector<float> h(off, 0.0f);
+    std::mt19937 rng(cfg->seed);
+    for (size_t l = 0; l + 1 < nn->layers.size(); ++l) {
+        const Layer& L = nn->layers[l];
+        std::normal_distribution<float> nd(0.0f, std::sqrt(2.0f / (27.0f * L.cin)));
+        for (size_t i = 0; i < (size_t)27 * L.cin * L.cout; ++i) h[L.woff + i] = nd(rng);
+    }
+    if (nn->p.ensure(off * 4) != hipSuccess || nn->g.ensure(off * 4) != hipSuccess || nn->m.ensure(off * 4) != hipSuccess ||
+        nn->v.ensure(off * 4) != hipSuccess)
+        return DDA_ERR_OOM;
+    if (hipMemcpy(nn->p.p, h.data(), off * 4, hipMemcpyHostToDevice) != hipSuccess) return DDA_ERR_HIP;
+    (void)hipMemset(nn->g.p, 0, off * 4);
+    (void)hipMemset(nn->m.p, 0, off * 4);
+    (void)hipMemset(nn->v.p, 0, off * 4);
+    nn->wf.resize(nn->layers.size());
+    nn->wd.resize(nn->layers.size());
+    for (size_t l = 0; l < nn->layers.size(); ++l) {
+        const size_t n = (size_t)27 * nn->layers[l].cin * nn->layers[l].cout * 2;
+        if (nn->wf[l].ensure(n) != hipSuccess || nn->wd[l].ensure(n) != hipSuccess) return DDA_ERR_OOM;
+    }
+    if (nn_pack(nn.get(), nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return DDA_ERR_HIP;
+    *out = nn.release();
+    return DDA_OK;
+}
+
+dda_status dda_nn_destroy(dda_nn* nn) {
+    if (!nn) return DDA_OK;
+    (void)hipDeviceSynchronize();
+    drop_store(nn);
+    delete nn;
+    return DDA_OK;
+}
+
+int64_t dda_nn_num_params(const dda_nn* nn) { return nn ? (int64_t)nn->nparams : 0; }
+
+int32_t dda_nn_num_samples(const dda_nn* nn) { return nn ? (int32_t)nn->samples.size() : 0; }
+
+dda_status dda_nn_get_params(const dda_nn* nn, float* out) {
+    if (!nn || !out) return DDA_ERR_INVALID_ARG;
+    return hipMemcpy(out, nn->p.p, nn->nparams * 4, hipMemcpyDeviceToHost) == hipSuccess ? DDA_OK : DDA_ERR_HIP;
+}
+
+dda_status dda_nn_set_params(dda_nn* nn, const float* in) {
+    if (!nn || !in) return DDA_ERR_INVALID_ARG;
+    if (hipMemcpy(nn->p.p, in, nn->nparams * 4, hipMemcpyHostToDevice) != hipSuccess) return DDA_ERR_HIP;
+    if (nn_pack(nn, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return DDA_ERR_HIP;
+    return DDA_OK;
+}
+
+dda_status dda_nn_layer_info(const dda_nn* nn, int32_t* out3 /* depth x {cin, cout, dil} */) {
+    if (!nn || !out3) return DDA_ERR_INVALID_ARG;
+    for (size_t l = 0; l < nn->layers.size(); ++l) {
+        out3[3 * l] = nn->layers[l].cin;
+        out3[3 * l + 1] = nn->layers[l].cout;
+        out3[3 * l + 2] = nn->layers[l].dil;
+    }
+    return DDA_OK;
+}
+
+dda_status dda_nn_forward_backward(dda_nn* nn, int32_t ns, int32_t D, const float* x_in, const float* target,
+                                   const uint8_t* mask, int32_t nout, float* out, float* grads, double* loss) {
+    if (!nn || ns <= 0 || D < 16 || (D * D * D) % 64 || !x_in || nout < 1 || nout > 16) return DDA_ERR_INVALID_ARG;
+    const size_t V = (size_t)D * D * D;
+    hipStream_t st = nullptr;
+    if (nn_buffers(nn, D, ns) != hipSuccess) return DDA_ERR_OOM;
+    DBuf xf, tf, mk, den, lo;
+    if (xf.ensure(V * ns * 16 * 4) != hipSuccess) return DDA_ERR_OOM;
+    if (hipMemcpy(xf.p, x_in, V * ns * 16 * 4, hipMemcpyHostToDevice) != hipSuccess) return DDA_ERR_HIP;
+    hipLaunchKernelGGL(k_f2bf, dim3(1024), dim3(256), 0, st, xf.as<float>(), nn->act[0].as<uint16_t>(), V * ns * 16);
+    if (nn_forward_any(nn, ns, st) != hipSuccess) return DDA_ERR_HIP;
+    if (out && hipMemcpy(out, nn->out32.p, V * ns * 16 * 4, hipMemcpyDeviceToHost) != hipSuccess) return DDA_ERR_HIP;
+    if (!target || !mask || !grads) return hipDeviceSynchronize() == hipSuccess ? DDA_OK : DDA_ERR_HIP;
+    std::vector<double> hden(ns, 0.0);
+    for (int s = 0; s < ns; ++s)
+        for (size_t v = 0; v < V; ++v)
+            if (mask[s * V + v])
+                for (int c = 0; c < nout; ++c) hden[s] += (double)target[(s * V + v) * 16 + c] * target[(s * V + v) * 16 + c];
+    if (tf.ensure(V * ns * 16 * 4) || mk.ensure(V * ns) || den.ensure(ns * 8) || lo.ensure(ns * 8)) return DDA_ERR_OOM;
+    (void)hipMemcpy(tf.p, target, V * ns * 16 * 4, hipMemcpyHostToDevice);
+    (void)hipMemcpy(mk.p, mask, V * ns, hipMemcpyHostToDevice);
+    (void)hipMemcpy(den.p, hden.data(), ns * 8, hipMemcpyHostToDevice);
+    (void)hipMemset(lo.p, 0, ns * 8);
+    (void)hipMemset(nn->g.p, 0, nn->nparams * 4);
+    hipLaunchKernelGGL(k_dense_loss, dim3(64, ns), dim3(256), 0, st, nn->out32.as<float>(), tf.as<float>(),
+                       mk.as<uint8_t>(), den.as<double>(), (int)V, nout, nn->dA.as<uint16_t>(), lo.as<double>(),
+                       1.0f / ns);
+    if (nn_backward_any(nn, ns, st) != hipSuccess) return DDA_ERR_HIP;
+    if (hipMemcpy(grads, nn->g.p, nn->nparams * 4, hipMemcpyDeviceToHost) != hipSuccess) return DDA_ERR_HIP;
+    std::vector<double> hl(ns);
+    (void)hipMemcpy(hl.data(), lo.p, ns * 8, hipMemcpyDeviceToHost);
+    if (loss) {
+        *loss = 0;
+        for (double x : hl) *loss += x / ns;
+    }
+    return hipDeviceSynchronize() == hipSuccess ? DDA_OK : DDA_ERR_HIP;
+}
+
+dda_status dda_nn_train(dda_ctx* ctx, dda_nn* nn, const dda_nn_train_opts* o, double* loss_out) {
+    (void)ctx;
+    if (!nn || !o) return DDA_ERR_INVALID_ARG;
+    const int ns_total = (int)nn->samples.size();
+    if (ns_total == 0) return DDA_ERR_STATE;
+    const int B = std::max(1, std::min(o->batch > 0 ? o->batch : 4, 8));
+    const int epochs = o->epochs > 0 ? o->epochs : 1;
+    const float lr = o->lr > 0 ? (float)o->lr : 1e-3f;
+    const float wd = (float)o->weight_decay;
+    int D = 0;
+    D = nn->box;
+    if (D == 0) return DDA_ERR_STATE;
+    hipStream_t st = nullptr;
+    if (nn_buffers(nn, D, B) != hipSuccess) return DDA_ERR_OOM;
+    std::mt19937 rng(nn->seed + 7);
+    std::vector<int> order(ns_total);
+    for (int i = 0; i < ns_total; ++i) order[i] = i;
+    double last = 0;
+    const size_t V = (size_t)D * D * D;
+    std::vector<SampleDev> sds(B);
+    std::vector<double> hl(B);
+    for (int ep = 0; ep < epochs; ++ep) {
+        std::shuffle(order.begin(), order.end(), rng);
+        double esum = 0;
+        int ecount = 0;
+        for (int b0 = 0; b0 + B <= ns_total; b0 += B) {
+            for (int k = 0; k < B; ++k) sds[k] = nn->samples[order[b0 + k]].dev;
+            if (hipMemcpyAsync(nn->sdev.p, sds.data(), B * sizeof(SampleDev), hipMemcpyHostToDevice, st) != hipSuccess)
+                return DDA_ERR_HIP;
+            hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, nn->act[0].as<uint16_t>(), V * B * 16);
+            hipLaunchKernelGGL(k_features, dim3(256, B), dim3(256), 0, st, nn->sdev.as<SampleDev>(), D,
+                               nn->act[0].as<uint16_t>());
+            if (nn_forward_any(nn, B, st) != hipSuccess) return DDA_ERR_HIP;
+            hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, nn->dA.as<uint16_t>(), V * B * 16);
+            (void)hipMemsetAsync(nn->lossacc.p, 0, B * sizeof(double), st);
+            // gradient scaled by 1/(B * N) so that the loss is a per-site mean
+            const float gnorm = 1.0f / (3.0f * (float)B * (float)sds[0].N);
+            hipLaunchKernelGGL(k_loss, dim3(256, B), dim3(256), 0, st, nn->sdev.as<SampleDev>(), D, nn->out32.as<float>(),
+                               nn->dA.as<uint16_t>(), nn->lossacc.as<double>(), gnorm);
+            (void)hipMemsetAsync(nn->g.p, 0, nn->nparams * 4, st);
+            if (nn_backward_any(nn, B, st) != hipSuccess) return DDA_ERR_HIP;
+            if (nn_adam(nn, lr, wd, 1.0f, st) != hipSuccess) return DDA_ERR_HIP;
+            (void)hipMemcpyAsync(hl.data(), nn->lossacc.p, B * sizeof(double), hipMemcpyDeviceToHost, st);
+            if (hipStreamSynchronize(st) != hipSuccess) return DDA_ERR_HIP;
+            for (int k = 0; k < B; ++k) esum += hl[k] / (3.0 * sds[k].N);
+            ecount += B;
+        }
+        last = ecount ? esum / ecount : 0;
+    }
+    if (loss_out) *loss_out = last;
+    return DDA_OK;
+}
+
+dda_status dda_nn_save(const dda_nn* nn, const char* path) {
+    if (!nn || !path) return DDA_ERR_INVALID_ARG;
+    std::vector<float> h(nn->nparams);
+    if (hipMemcpy(h.data(), nn->p.p, h.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return DDA_ERR_HIP;
+    std::ofstream f(path, std::ios::binary);
+    if (!f) return DDA_ERR_IO;
+    const int32_t hdr[4] = {0x444e4e31, nn->width, nn->depth, (int32_t)nn->nparams};
+    f.write((const char*)hdr, sizeof hdr);
+    f.write((const char*)h.data(), h.size() * 4);
+    return f ? DDA_OK : DDA_ERR_IO;
+}
+
+dda_status dda_nn_load(dda_nn* nn, const char* path) {
+    if (!nn || !path) return DDA_ERR_INVALID_ARG;
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return DDA_ERR_IO;
+    int32_t hdr[4];
+    f.read((char*)hdr, sizeof hdr);
+    if (!f || hdr[0] != 0x444e4e31 || hdr[1] != nn->width || hdr[2] != nn->depth || hdr[3] != (int32_t)nn->nparams)
+        return DDA_ERR_INVALID_ARG;
+    std::vector<float> h(nn->nparams);
+    f.read((char*)h.data(), h.size() * 4);
+    if (!f) return DDA_ERR_IO;
+    return dda_nn_set_params(nn, h.data());
+}
+
+}  // extern "C"

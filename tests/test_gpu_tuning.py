@@ -1,0 +1,82 @@
+"""Every launch shape the autotuner can pick computes the same product, and
+the tuner's cache round-trips.  Expected values from the oracle's direct sum."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1002_1505_amd as P
+
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _shapes():
+    out = []
+    for tx in (8, 16, 32):
+        for zrb in (0, 1):
+            out.append(dict(fused=1, nth_plane=256, nth_z=256, tx=tx, lines_tl=16, nth_lines=256, ct=3, zrb=zrb))
+    for tx in (4, 8, 16):
+        for fused in (1, 0):
+            out.append(dict(fused=fused, nth_plane=256, nth_z=512, tx=tx, lines_tl=16, nth_lines=256, ct=0, zrb=0))
+    return out
+
+
+@pytest.mark.parametrize("n", [16, 32, 48])
+def test_all_launch_shapes_agree_with_oracle(ctx, n):
+    import paper_1002_1505_amd as P
+
+    occ = synth.sphere_occupancy(n)
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    kd = 0.35
+    ctx.set_target(occ, [1.5 + 0.1j], kd, P.DDA_ALPHA_LDR)
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((3, len(r), 3)) + 1j * rng.standard_normal((3, len(r), 3))
+    ainv = np.array([[2.0 + 0.3j], [1.0 - 0.2j], [3.0 + 0.0j]])
+    rows = rng.choice(len(r), 40, replace=False)
+    refs = [dda.matvec_rows(r, kd, np.full(len(r), ainv[s, 0]), x[s], rows) for s in range(3)]
+    tried = 0
+    for prec, tol in ((P.DDA_FP32, 5e-6), (P.DDA_FP64, 1e-12)):
+        for sh in _shapes():
+            try:
+                ctx.set_shape(sh, prec=prec)
+            except P.DDAError:
+                continue  # does not fit LDS / threads for this box
+            tried += 1
+            y = ctx.matvec(x, ainv=ainv, prec=prec)
+            for s in range(3):
+                err = np.sqrt(np.mean(np.abs(y[s][rows] - refs[s]) ** 2)) / np.sqrt(np.mean(np.abs(refs[s]) ** 2))
+                assert err < tol, (n, prec, sh, err)
+    assert tried >= 8
+
+
+def test_autotune_cache_roundtrip(ctx, tmp_path):
+    import paper_1002_1505_amd as P
+
+    occ = synth.sphere_occupancy(32)
+    ctx.set_target(occ, [1.4 + 0.05j], 0.3)
+    path = str(tmp_path / "tune.json")
+    ctx.autotune(2, path)
+    s32, s64 = ctx.get_shape(prec=P.DDA_FP32), ctx.get_shape(prec=P.DDA_FP64)
+    data = json.load(open(path))
+    assert len(data) == 2
+    # a new context reads the cache instead of timing, and picks the same shapes
+    with P.Context(0) as c2:
+        c2.set_target(occ, [1.4 + 0.05j], 0.3)
+        c2.autotune(2, path)
+        assert c2.get_shape(prec=P.DDA_FP32) == s32 and c2.get_shape(prec=P.DDA_FP64) == s64
+    assert os.path.getsize(path) > 0
+    # the tuned shape still solves correctly
+    khat, e0 = P.orientation_waves(0.2, 0.3, 0.4)
+    Pg, st, status = ctx.solve(khat, e0)
+    assert status == 0 and all(s["rel_resid"] <= 1e-5 for s in st)
