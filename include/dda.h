@@ -75,7 +75,10 @@ enum {
     DDA_GUESS_ZERO = 0,   /* P0 = 0 (the guide's default) */
     DDA_GUESS_USER = 1,   /* P0 from the p0 argument */
     DDA_GUESS_PREV = 2,   /* P0 = this context's previous solution in the same rhs slot */
-    DDA_GUESS_NN = 3      /* P0 from the attached learned-guess network */
+    DDA_GUESS_NN = 3,     /* P0 = alpha (E_sh + net(features)), attached learned-guess network */
+    DDA_GUESS_PREV_SHIFT = 4  /* P0 = alpha_new E_sh: the previous local field carried to the new
+                                 incidence direction, E_sh,j = (1/alpha_prev) P_prev,j
+                                 exp(i k (khat - khat_prev) . r_j) */
 };
 
 /* Flags. */
@@ -161,6 +164,9 @@ dda_status dda_build_green_fft(dda_ctx* ctx, uint32_t prec);
  * to keep the solution on the device only (for cross sections, amplitudes or
  * DDA_GUESS_PREV).  stats (nrhs entries) may be NULL.  The waves of one call
  * may reference different targets (batched multi-target solve).
+ * DDA_GUESS_PREV, _PREV_SHIFT and _NN need a previous solve with the same
+ * nrhs whose slots hold the same targets (DDA_ERR_STATE otherwise); the waves
+ * themselves may change (the next orientation or direction of a sweep).
  * Returns DDA_WARN_NOT_CONVERGED if any right-hand side missed tol.
  */
 dda_status dda_solve(dda_ctx* ctx, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* opts,
@@ -235,7 +241,8 @@ dda_status dda_scattering_frame(int32_t ndir, const double* theta, const double*
 
 dda_status dda_autotune(dda_ctx* ctx, int32_t nrhs_hint, const char* cache_path);
 
-/* Milliseconds the last solve spent producing its learned initial guess. */
+/* Milliseconds the last solve spent producing an initial guess from the
+ * previous solution (phase shift, plus the network for DDA_GUESS_NN). */
 dda_status dda_last_guess_ms(const dda_ctx* ctx, double* ms);
 
 /* Launch shape of a target's matvec passes for precision DDA_FP32 or
@@ -259,14 +266,17 @@ dda_status dda_profile_matvec(dda_ctx* ctx, int32_t target, int32_t nrhs, uint32
                               double* ms, double* bytes);
 
 /* ---- Learned initial guess ----
- * A 3D convolutional network on the target's cubic box (side divisible by
- * 16) predicts the local field E_loc = E_inc + net(features) at the occupied
- * sites; the guess is P0 = E_loc / (1/alpha).  Features per voxel:
- * occupancy, E_inc, (eps-1)/(eps+2), k d, khat.  3x3x3 convolutions with
- * dilations 1, 2, 4, 8, ReLU; BF16 operands on MFMA with FP32 accumulation;
- * FP32 master weights trained with Adam on fields the solver produced
- * (dda_nn_record).  The network of zeros reproduces P0 = alpha E_inc.  A
- * guess is used only if its FP64 residual is below ||E|| (else P0 = 0). */
+ * For a sweep over orientations (or incidence directions) of one target, a 3D
+ * convolutional network on the target's cubic box (side divisible by 16)
+ * corrects the previous solution carried to the new direction: the local
+ * field is E_loc = E_sh + net(features) at the occupied sites (E_sh as for
+ * DDA_GUESS_PREV_SHIFT) and the guess is P0 = E_loc / (1/alpha).  Features
+ * per voxel: occupancy, E_inc, E_sh, (eps-1)/(eps+2), k d (16 channels).
+ * 3x3x3 convolutions with dilations 1, 2, 4, 8, ReLU; BF16 operands on MFMA
+ * with FP32 accumulation; FP32 master weights trained with Adam on pairs of
+ * consecutive solutions (dda_nn_record).  The network of zeros reproduces
+ * DDA_GUESS_PREV_SHIFT.  A guess is used only if its FP64 residual is below
+ * ||E|| (else P0 = 0). */
 typedef struct dda_nn dda_nn;
 
 typedef struct {
@@ -296,7 +306,9 @@ dda_status dda_nn_get_params(const dda_nn* nn, float* out);
 dda_status dda_nn_set_params(dda_nn* nn, const float* in);
 /* Attach a network as the DDA_GUESS_NN model of the context (NULL detaches). */
 dda_status dda_set_guess_model(dda_ctx* ctx, dda_nn* nn);
-/* Record every solution of the last solve as a training sample. */
+/* Record every solution of the last solve as a training sample (target
+ * E_loc - E_sh).  The last solve must have used DDA_GUESS_PREV, _PREV_SHIFT
+ * or _NN, so that E_sh exists (DDA_ERR_STATE otherwise). */
 dda_status dda_nn_record(dda_ctx* ctx, dda_nn* nn);
 /* Train on the recorded samples; mean loss of the last epoch in *loss. */
 dda_status dda_nn_train(dda_ctx* ctx, dda_nn* nn, const dda_nn_train_opts* opts, double* loss);

@@ -397,3 +397,20 @@ def scattering_double_sum(r, k, P):
         total += np.real(np.sum(np.conj(P[j])[None, :] * ImGP))
     csca = 4.0 * np.pi * k * total
     return float(csca / (np.pi * effective_radius(n) ** 2))
+
+
+def shifted_previous_guess(r, k, P_prev, ainv_prev, ainv_new, khat_prev, khat_new):
+    """Initial guess for the next wave of a sweep from the previous solution.
+
+    The guide's default guess is P = 0 ("Choice of Iterative Algorithm"); a
+    sweep over orientations may start instead from the previous orientation's
+    polarization.  Its local field E_loc,j = (1/alpha_prev,j) P_prev,j is
+    carried to the new incidence direction by the ratio of the two incident
+    phases at the site, E_sh,j = E_loc,j exp(i k (khat_new - khat_prev) . r_j),
+    and the guess is P0,j = E_sh,j / (1/alpha_new,j).  Returns (E_sh, P0), both
+    (N, 3) complex; ainv_* are per-site (N,) arrays.
+    """
+    dk = k * (np.asarray(khat_new, dtype=float) - np.asarray(khat_prev, dtype=float))
+    phase = np.exp(1j * (r @ dk))
+    e_sh = (ainv_prev[:, None] * P_prev) * phase[:, None]
+    return e_sh, e_sh / ainv_new[:, None]

@@ -55,15 +55,28 @@ def conv3d_backward(x, w, dy, d=1):
     return dx, dw, db
 
 
+def bf16_round(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64.
+    bfloat16 keeps the 8 high mantissa bits of an IEEE float32."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 class Net:
     """Stack of 3x3x3 convolutions; ReLU after every layer but the last.
 
     layers: list of (cin, cout, dilation).  Parameters: list of (w, b).
+    `quantize` (default: none) is applied where a reduced-precision
+    implementation stores values: hidden activations after the ReLU, the
+    output gradient, and the data gradient of every hidden layer.
     """
 
-    def __init__(self, layers, params):
+    def __init__(self, layers, params, quantize=None):
         self.layers = layers
         self.params = params
+        self.q = quantize if quantize is not None else (lambda a: a)
 
     def forward(self, x):
         acts = [x]
@@ -71,21 +84,20 @@ class Net:
         for i, ((cin, cout, d), (w, b)) in enumerate(zip(self.layers, self.params)):
             h = conv3d(h, w, b, d)
             if i < len(self.layers) - 1:
-                h = np.maximum(h, 0.0)
+                h = self.q(np.maximum(h, 0.0))
             acts.append(h)
         return h, acts
 
     def backward(self, acts, dout):
         grads = [None] * len(self.layers)
-        g = dout
+        g = self.q(dout)
         for i in range(len(self.layers) - 1, -1, -1):
             cin, cout, d = self.layers[i]
             w, b = self.params[i]
-            if i < len(self.layers) - 1:
-                g = g * (acts[i + 1] > 0)
             dx, dw, db = conv3d_backward(acts[i], w, g, d)
             grads[i] = (dw, db)
-            g = dx
+            if i > 0:
+                g = self.q(dx * (acts[i] > 0))
         return grads
 
 

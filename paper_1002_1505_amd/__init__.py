@@ -12,7 +12,8 @@ import numpy as np
 
 from . import _lib as L
 from ._lib import (DDA_ALPHA_CM, DDA_ALPHA_CM_RR, DDA_ALPHA_LDR, DDA_DEVICE_PTRS, DDA_FP32, DDA_FP64,  # noqa: F401
-                   DDA_GUESS_NN, DDA_GUESS_PREV, DDA_GUESS_USER, DDA_GUESS_ZERO, DDA_NO_FALLBACK, DDA_NO_GRAPH,
+                   DDA_GUESS_NN, DDA_GUESS_PREV, DDA_GUESS_PREV_SHIFT, DDA_GUESS_USER, DDA_GUESS_ZERO,
+                   DDA_NO_FALLBACK, DDA_NO_GRAPH,
                    DDA_SOLVE_FP32_REFINE, DDA_SOLVE_FP64, DDA_WARN_MKD_GE_1, DDA_WARN_NOT_CONVERGED)
 
 __all__ = ["Context", "DDAError", "lab_frame", "mueller", "orientation_waves", "scattering_frame", "load_library"]

@@ -36,6 +36,7 @@ DDA_GUESS_ZERO = 0
 DDA_GUESS_USER = 1
 DDA_GUESS_PREV = 2
 DDA_GUESS_NN = 3
+DDA_GUESS_PREV_SHIFT = 4
 
 DDA_DEVICE_PTRS = 1
 DDA_NO_GRAPH = 2

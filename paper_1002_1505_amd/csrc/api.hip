@@ -27,9 +27,9 @@
 using cd = std::complex<double>;
 
 hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, const double* ainv,
-                         const Cx<double>* x64, hipStream_t st);
+                         const Cx<double>* x64, const Cx<float>* esh, hipStream_t st);
 hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves, const double* ainv, int nr,
-                          Cx<double>* x64, hipStream_t st);
+                          const Cx<float>* esh, Cx<double>* x64, hipStream_t st);
 
 namespace {
 
@@ -117,9 +117,14 @@ struct Group {
     int tgt = -1, nr = 0, kprec = 0;
     std::vector<int> idx;  // call-level rhs index of each member
     DevMem waves, ainv64, ainv32, b64, x64, r64;
-    DevMem kv[7];  // inner Krylov vectors x r rhat p v s t (kprec precision)
+    DevMem kv[8];  // inner Krylov vectors x r rhat p v s t p' (kprec precision)
     DevMem slab32, slab64;
     DevMem state, active, partials, scale, tolrel2, maxit, norms, mask;
+    // previous solve of the same slots: waves and 1/alpha, and its local field
+    // carried to the current incidence direction (FP32), for the guesses that
+    // start from the previous solution
+    DevMem wprev, ainvprev, esh;
+    bool has_esh = false;
     // host staging buffers of asynchronous uploads (must outlive the copies)
     std::vector<WaveDev> hw;
     std::vector<cd> hainv;  // [nr][ncomp]
@@ -392,11 +397,12 @@ dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
 
 template <class T>
 hipError_t matvec_group(const Target& t, Group& g, int nr, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, const int* active,
-                        int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr}) {
+                        int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr},
+                        MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}) {
     Cx<T>* slab = std::is_same<T, double>::value ? g.slab64.as<Cx<T>>() : g.slab32.as<Cx<T>>();
     const Cx<T>* ainv = std::is_same<T, double>::value ? g.ainv64.as<Cx<T>>() : g.ainv32.as<Cx<T>>();
     return launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab, t.ghat<T>(), ainv, active,
-                            mode, st, dot);
+                            mode, st, dot, upd);
 }
 
 size_t slab_elems(const Target& t, int nr) { return (size_t)nr * 3 * 4 * t.n[0] * t.n[1] * t.n[2]; }
@@ -411,7 +417,7 @@ dda_status ensure_group(dda_ctx* c, Group& g, const Target& t, int prec, bool* r
     void* before[24];
     int nb = 0;
     DevMem* all[] = {&g.b64, &g.x64, &g.r64, &g.slab32, &g.slab64, &g.kv[0], &g.kv[1], &g.kv[2], &g.kv[3],
-                     &g.kv[4], &g.kv[5], &g.kv[6], &g.state, &g.active, &g.partials};
+                     &g.kv[4], &g.kv[5], &g.kv[6], &g.kv[7], &g.state, &g.active, &g.partials};
     for (DevMem* d : all) before[nb++] = d->p;
     HCHK(c, g.waves.ensure(nr * sizeof(WaveDev)));
     HCHK(c, g.ainv64.ensure((size_t)nr * t.ncomp * sizeof(Cx<double>)));
@@ -421,7 +427,7 @@ dda_status ensure_group(dda_ctx* c, Group& g, const Target& t, int prec, bool* r
     HCHK(c, g.r64.ensure(v64));
     HCHK(c, g.slab64.ensure(slab_elems(t, nr) * sizeof(Cx<double>)));
     if (kp == DDA_FP32) HCHK(c, g.slab32.ensure(slab_elems(t, nr) * sizeof(Cx<float>)));
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < 8; ++i) {
         if (g.kprec != kp) g.kv[i].release();
         HCHK(c, g.kv[i].ensure(vk));
     }
@@ -440,15 +446,16 @@ dda_status ensure_group(dda_ctx* c, Group& g, const Target& t, int prec, bool* r
     if (changed) {
         // zero the padded vectors once so that padding stays zero
         for (DevMem* d : {&g.b64, &g.x64, &g.r64}) HCHK(c, hipMemsetAsync(d->p, 0, d->n, c->stream));
-        for (int i = 0; i < 7; ++i) HCHK(c, hipMemsetAsync(g.kv[i].p, 0, g.kv[i].n, c->stream));
+        for (int i = 0; i < 8; ++i) HCHK(c, hipMemsetAsync(g.kv[i].p, 0, g.kv[i].n, c->stream));
     }
     *realloc = changed;
     return DDA_OK;
 }
 
+
 // One BiCGstab iteration for every group (precision T), enqueued on st.
 template <class T>
-hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st) {
+hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st, int k) {
     for (auto& gp : c->groups) {
         Group& g = *gp;
         const Target& t = *c->tg[g.tgt];
@@ -456,34 +463,43 @@ hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st) {
         Cx<T>* x = g.kv[0].as<Cx<T>>();
         Cx<T>* r = g.kv[1].as<Cx<T>>();
         Cx<T>* rh = g.kv[2].as<Cx<T>>();
-        Cx<T>* p = g.kv[3].as<Cx<T>>();
         Cx<T>* v = g.kv[4].as<Cx<T>>();
         Cx<T>* s = g.kv[5].as<Cx<T>>();
         Cx<T>* tt = g.kv[6].as<Cx<T>>();
+        // the direction vector alternates between two buffers so that the
+        // fused update never reads what it writes; iteration parity picks them
+        Cx<T>* pin = (k & 1) ? g.kv[7].as<Cx<T>>() : g.kv[3].as<Cx<T>>();
+        Cx<T>* pout = (k & 1) ? g.kv[3].as<Cx<T>>() : g.kv[7].as<Cx<T>>();
         BiState* bs = g.state.as<BiState>();
         int* act = g.active.as<int>();
         double* part = g.partials.as<double>();
         hipError_t e;
         const bool fuse = (t.shape<T>().ct & 1) != 0;
         const int nbv = vec_blocks(Np), nbp = fuse ? 12 * t.n[0] : nbv;
-        if ((e = launch_bicg_p<T>(Np, nr, p, r, v, rh, bs, act, st)) != hipSuccess) return e;
+        if (!fuse) pin = pout = g.kv[3].as<Cx<T>>();  // separate update kernel works in place
         if (fuse) {
-            if ((e = matvec_group<T>(t, g, nr, p, v, nullptr, act, MV_AX, st, MvDot{1, rh, part})) != hipSuccess) return e;
+            // the inverse pass reads the updated direction (written by the
+            // forward pass) for the diagonal term
+            if ((e = matvec_group<T>(t, g, nr, pout, v, nullptr, act, MV_AX, st, MvDot{1, rh, part},
+                                     MvUpd{1, r, v, pin, pout, rh, bs})) != hipSuccess)
+                return e;
         } else {
-            if ((e = matvec_group<T>(t, g, nr, p, v, nullptr, act, MV_AX, st)) != hipSuccess) return e;
+            if ((e = launch_bicg_p<T>(Np, nr, pin, r, v, rh, bs, act, st)) != hipSuccess) return e;
+            if ((e = matvec_group<T>(t, g, nr, pin, v, nullptr, act, MV_AX, st)) != hipSuccess) return e;
             if ((e = launch_dot<T>(Np, nr, 1, rh, v, nullptr, nullptr, part, act, st)) != hipSuccess) return e;
         }
         if ((e = launch_scalars(0, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
-        if ((e = launch_bicg_s<T>(Np, nr, s, r, v, bs, act, st)) != hipSuccess) return e;
         if (fuse) {
-            if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st, MvDot{2, nullptr, part})) != hipSuccess)
+            if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st, MvDot{2, nullptr, part},
+                                     MvUpd{2, r, v, nullptr, s, nullptr, bs})) != hipSuccess)
                 return e;
         } else {
+            if ((e = launch_bicg_s<T>(Np, nr, s, r, v, bs, act, st)) != hipSuccess) return e;
             if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st)) != hipSuccess) return e;
             if ((e = launch_dot<T>(Np, nr, 2, tt, s, tt, tt, part, act, st)) != hipSuccess) return e;
         }
         if ((e = launch_scalars(1, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
-        if ((e = launch_bicg_xr<T>(Np, nr, x, r, p, s, tt, rh, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_bicg_xr<T>(Np, nr, x, r, pout, s, tt, rh, bs, part, act, st)) != hipSuccess) return e;
         if ((e = launch_scalars(2, nbv, nr, bs, part, act, st)) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -516,7 +532,7 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
         hipGraph_t graph;
         HCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
-        for (int k = 0; k < kiters && e == hipSuccess; ++k) e = enqueue_iteration<T>(c, st);
+        for (int k = 0; k < kiters && e == hipSuccess; ++k) e = enqueue_iteration<T>(c, st, k);
         hipError_t e2 = hipStreamEndCapture(st, &graph);
         HCHK(c, e);
         HCHK(c, e2);
@@ -543,7 +559,7 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
         if (use_graph) {
             HCHK(c, hipGraphLaunch(c->gexec, st));
         } else {
-            for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st));
+            for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st, k));
         }
     }
     return DDA_OK;
@@ -713,12 +729,17 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
     if (prec != DDA_SOLVE_FP64 && prec != DDA_SOLVE_FP32_REFINE) return fail(c, DDA_ERR_INVALID_ARG, "bad prec");
     const bool devptr = (o->flags & DDA_DEVICE_PTRS) != 0;
     const bool use_graph = !(o->flags & DDA_NO_GRAPH);
-    const int kiters = o->graph_iters > 0 ? o->graph_iters : 4;
+    // an even count keeps the alternating direction buffers aligned across replays
+    const int kiters = 2 * std::max(1, ((o->graph_iters > 0 ? o->graph_iters : 4) + 1) / 2);
     if (o->guess == DDA_GUESS_USER && !p0) return fail(c, DDA_ERR_INVALID_ARG, "GUESS_USER needs p0");
+    if (o->guess < DDA_GUESS_ZERO || o->guess > DDA_GUESS_PREV_SHIFT)
+        return fail(c, DDA_ERR_INVALID_ARG, "unknown guess %d", o->guess);
     if (o->guess == DDA_GUESS_NN && !c->nn) return fail(c, DDA_ERR_STATE, "no learned-guess model attached");
-    if (o->guess == DDA_GUESS_PREV && (!c->have_solution || c->last_nrhs != nrhs))
-        return fail(c, DDA_ERR_STATE, "GUESS_PREV needs a previous solve with the same right-hand sides");
-    const bool keep_prev = (o->guess == DDA_GUESS_PREV);
+    // PREV, PREV_SHIFT and NN start from the previous solution of each slot
+    const bool keep_prev = (o->guess == DDA_GUESS_PREV || o->guess == DDA_GUESS_PREV_SHIFT || o->guess == DDA_GUESS_NN);
+    if (keep_prev && (!c->have_solution || c->last_nrhs != nrhs))
+        return fail(c, DDA_ERR_STATE, "guess %d needs a previous solve with the same number of right-hand sides",
+                    o->guess);
     if (!keep_prev) SCHK(group_waves(c, nrhs, waves));
     else
         for (int i = 0; i < nrhs; ++i)
@@ -736,6 +757,18 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
             c->ws_gen++;
             if (keep_prev) return fail(c, DDA_ERR_STATE, "GUESS_PREV: workspace changed");
         }
+    }
+    // keep the previous waves and polarizabilities of every slot
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        g.has_esh = false;
+        if (!keep_prev) continue;
+        const Target& t = *c->tg[g.tgt];
+        HCHK(c, g.wprev.ensure(g.nr * sizeof(WaveDev)));
+        HCHK(c, g.ainvprev.ensure((size_t)g.nr * t.ncomp * sizeof(Cx<double>)));
+        HCHK(c, hipMemcpyAsync(g.wprev.p, g.waves.p, g.nr * sizeof(WaveDev), hipMemcpyDeviceToDevice, st));
+        HCHK(c, hipMemcpyAsync(g.ainvprev.p, g.ainv64.p, (size_t)g.nr * t.ncomp * sizeof(Cx<double>),
+                               hipMemcpyDeviceToDevice, st));
     }
     // waves, polarizabilities, incident field, norms
     for (auto& gp : c->groups) {
@@ -784,18 +817,27 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
             HCHK(c, launch_from_abi<double>(t.N, t.Npad, g.nr, dtmp.as<Cx<double>>(), g.x64.as<Cx<double>>(), st));
             HCHK(c, hipStreamSynchronize(st));
         }
-        // GUESS_PREV: x64 already holds the previous solution
+        // PREV, PREV_SHIFT, NN: x64 holds the previous solution here
     }
     c->ms_guess = 0;
-    if (o->guess == DDA_GUESS_NN) {
+    if (keep_prev) {
         HCHK(c, hipEventRecord(c->ev1, st));
         for (auto& gp : c->groups) {
             Group& g = *gp;
             Target& t = *c->tg[g.tgt];
+            // E_sh = (1/alpha_prev) P_prev exp(i k (khat - khat_prev) . r); PREV_SHIFT
+            // takes P0 = alpha E_sh, PREV keeps P_prev, NN corrects E_sh
+            HCHK(c, g.esh.ensure(vec_elems(t, g.nr) * sizeof(Cx<float>)));
+            HCHK(c, launch_prev_shift(t.geo(), t.origin, g.nr, g.x64.as<Cx<double>>(), g.ainvprev.as<Cx<double>>(),
+                                      g.ainv64.as<Cx<double>>(), g.wprev.as<WaveDev>(), g.waves.as<WaveDev>(),
+                                      g.esh.as<Cx<float>>(),
+                                      o->guess == DDA_GUESS_PREV_SHIFT ? g.x64.as<Cx<double>>() : nullptr, st));
+            g.has_esh = true;
+            if (o->guess != DDA_GUESS_NN) continue;
             std::vector<dda_wave> gw(g.nr);
             for (int s = 0; s < g.nr; ++s) gw[s] = waves[g.idx[s]];
             hipError_t e = nn_guess_group(c->nn, site_view(t), gw.data(), reinterpret_cast<const double*>(g.hainv.data()),
-                                          g.nr, g.x64.as<Cx<double>>(), st);
+                                          g.nr, g.esh.as<Cx<float>>(), g.x64.as<Cx<double>>(), st);
             if (e == hipErrorNotSupported)
                 return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "learned guess needs a cubic box with side divisible by 16");
             HCHK(c, e);
@@ -1226,13 +1268,18 @@ dda_status dda_nn_record(dda_ctx* c, dda_nn* nn) {
     SCHK(check_ctx(c));
     if (!nn) return fail(c, DDA_ERR_INVALID_ARG, "nn_record: null network");
     if (!c->have_solution) return fail(c, DDA_ERR_STATE, "nn_record before a solve");
+    for (auto& gp : c->groups)
+        if (!gp->has_esh)
+            return fail(c, DDA_ERR_STATE, "nn_record needs a solve started from the previous solution "
+                                          "(guess PREV, PREV_SHIFT or NN)");
     for (int i = 0; i < c->last_nrhs; ++i) {
         Group& g = *c->groups[c->rhs_group[i]];
         Target& t = *c->tg[g.tgt];
         const int s = c->rhs_slot[i];
         hipError_t e = nn_record_one(nn, site_view(t), c->last_waves[i],
                                      reinterpret_cast<const double*>(g.hainv.data()) + (size_t)s * 2 * t.ncomp,
-                                     g.x64.as<Cx<double>>() + (size_t)s * 3 * t.Npad, c->stream);
+                                     g.x64.as<Cx<double>>() + (size_t)s * 3 * t.Npad,
+                                     g.esh.as<Cx<float>>() + (size_t)s * 3 * t.Npad, c->stream);
         if (e == hipErrorNotSupported)
             return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "nn_record: needs a cubic box with side divisible by 16");
         if (e == hipErrorInvalidValue) return fail(c, DDA_ERR_INVALID_ARG, "nn_record: all samples must share one box size");

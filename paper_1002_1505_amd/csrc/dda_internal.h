@@ -51,6 +51,19 @@ struct MvShape {
     int zrb;         // specialised z pass: 1 = loop over up to 8 rhs per block with the spectrum in registers
 };
 
+// Optional BiCGstab vector update fused into the first matvec pass
+// (specialised plane kernels only): mode 1 = direction update into pout,
+// mode 2 = s = r - alpha v into pout; the transformed vector is the updated one.
+struct MvUpd {
+    int mode;
+    const void* r;
+    const void* v;
+    const void* p;
+    void* pout;
+    void* rhat;
+    const BiState* st;
+};
+
 // Optional inner products fused into the last matvec pass (specialised plane
 // kernels only): dot = 1 -> <w, y> in slot 0; dot = 2 -> <y, x>, <y, y>.
 struct MvDot {
@@ -65,13 +78,15 @@ enum { MV_AX = 0, MV_RESID = 1 };
 template <class T>
 hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh, int nrhs,
                          const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
-                         const Cx<T>* ainv, const int* active, int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr});
+                         const Cx<T>* ainv, const int* active, int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr},
+                         MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr});
 // Individual passes (for per-pass profiling).
 template <class T>
 hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh,
                        int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
                        const Cx<T>* ainv, const int* active, int mode, hipStream_t st,
-                       MvDot dot = MvDot{0, nullptr, nullptr});
+                       MvDot dot = MvDot{0, nullptr, nullptr},
+                       MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr});
 // Shared-memory bytes and feasibility of a shape.
 template <class T>
 bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh);
@@ -153,6 +168,13 @@ hipError_t launch_ampl(const Geo& g, const double* origin3, double k, int nrhs, 
 
 hipError_t configure_fft_kernels();
 
+// Previous local field (1/alpha_prev) P_prev carried to the new incidence
+// direction (FP32 esh); when p0 != nullptr also P0 = esh / (1/alpha_new).
+struct WaveDev;
+hipError_t launch_prev_shift(const Geo& g, const double* origin, int nrhs, const Cx<double>* Pprev,
+                             const Cx<double>* ainv_prev, const Cx<double>* ainv_new, const WaveDev* wprev,
+                             const WaveDev* wnew, Cx<float>* esh, Cx<double>* p0, hipStream_t st);
+
 // Raise a kernel's dynamic-LDS limit to the 160 KB of a gfx950 CU minus the
 // kernel's static LDS (the attribute value is ignored beyond that).
 inline hipError_t set_lds_limit(const void* fn, hipFuncAttribute attr, int lim) {
@@ -170,7 +192,8 @@ int ct_available(int n, int tx);
 template <class T>
 hipError_t launch_pass_ct(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x,
                           Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
-                          const int* active, int mode, int dot, const Cx<T>* w, double* partials, hipStream_t st);
+                          const int* active, int mode, int dot, const Cx<T>* w, double* partials, const MvUpd& upd,
+                          hipStream_t st);
 hipError_t configure_ct_kernels();
 
 // ---- learned initial guess (nn.hip) ----

@@ -30,9 +30,23 @@ __device__ __forceinline__ int fold_idx(int k, int n, int& sgn) {
 template <int N> constexpr int plane_threads() { return N >= 128 ? 1024 : 256; }
 template <int N> constexpr int zpass_threads() { return N >= 128 ? 512 : 256; }
 
-template <class T, int N>
+// UPD = 0: transform x.  UPD = 1: BiCGstab direction update p' = r + beta (p - omega v)
+// (p' = r and rhat = r on restart), transform p' and store it in pout.
+// UPD = 2: s = r - alpha v, transform s and store it in pout.  Only the
+// parity-0 block of a plane stores, and pout never aliases an input.
+struct UpdArgs {
+    const void* r;
+    const void* v;
+    const void* p;
+    void* pout;
+    void* rhat;
+    const BiState* st;
+};
+
+template <class T, int N, int UPD>
 __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __restrict__ x, Cx<T>* __restrict__ slab,
-                                                                Geo g, Tw<T> tw, int nrhs, const int* __restrict__ active) {
+                                                                Geo g, Tw<T> tw, int nrhs, const int* __restrict__ active,
+                                                                UpdArgs u) {
     constexpr int NTH = plane_threads<N>();
     constexpr int PITCH = N + 1;
     extern __shared__ unsigned char smem_raw[];
@@ -51,12 +65,40 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     for (int i = tid; i < N; i += NTH) t1[i] = tw.f1[i];
     for (int i = tid; i < N * PITCH; i += NTH) buf[i] = Cx<T>{0, 0};
     __syncthreads();
-    const Cx<T>* xv = x + ((size_t)rhs * 3 + c) * g.Npad;
+    const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
     const int j0 = g.plane_start[z], j1 = g.plane_start[z + 1];
+    Cx<T> c1 = {0, 0}, c2 = {0, 0};
+    int restart = 0;
+    if (UPD == 1) {
+        const BiState sv = u.st[rhs];
+        c1 = Cx<T>{(T)sv.beta[0], (T)sv.beta[1]};
+        c2 = Cx<T>{(T)sv.omega[0], (T)sv.omega[1]};
+        restart = sv.restart;
+    } else if (UPD == 2) {
+        c1 = Cx<T>{(T)u.st[rhs].alpha[0], (T)u.st[rhs].alpha[1]};
+    }
+    const Cx<T>* rv = reinterpret_cast<const Cx<T>*>(u.r);
+    const Cx<T>* vv = reinterpret_cast<const Cx<T>*>(u.v);
+    const Cx<T>* pv = reinterpret_cast<const Cx<T>*>(u.p);
+    Cx<T>* po = reinterpret_cast<Cx<T>*>(u.pout);
+    Cx<T>* rh = reinterpret_cast<Cx<T>*>(u.rhat);
     for (int j = j0 + tid; j < j1; j += NTH) {
         const uint32_t s = g.site_xyz[j];
         const int sx = s & 1023, sy = (s >> 10) & 1023;
-        Cx<T> v = xv[j];
+        Cx<T> v;
+        if (UPD == 0) {
+            v = x[vo + j];
+        } else if (UPD == 1) {
+            const Cx<T> rj = rv[vo + j];
+            v = restart ? rj : rj + c1 * (pv[vo + j] - c2 * vv[vo + j]);
+            if (par == 0) {
+                po[vo + j] = v;
+                if (restart) rh[vo + j] = rj;
+            }
+        } else {
+            v = rv[vo + j] - c1 * vv[vo + j];
+            if (par == 0) po[vo + j] = v;
+        }
         if (px) v = v * tw.h1[sx];
         if (py) v = v * tw.h2[sy];
         buf[sy * PITCH + sx] = v;
@@ -323,16 +365,26 @@ void launch_pinv(int nblk, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>*
 template <class T, int N>
 hipError_t pass_n(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
                   const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv, const int* active, int mode,
-                  int dot, const Cx<T>* w, double* partials, hipStream_t st) {
+                  int dot, const Cx<T>* w, double* partials, const MvUpd& upd, hipStream_t st) {
     const int nplanes = nrhs * 3 * N;
     const int nblk_plane = (nplanes + 7) / 8 * 8 * 4;
+    if (which == 2 && !x) return hipErrorInvalidValue;        // diagonal term reads x
+    if (which == 0 && upd.mode == 0 && !x) return hipErrorInvalidValue;
     if (which == 0 || which == 2) {
         if constexpr (plane_lds<T, N>() > LDS_MAX) {
             return hipErrorNotSupported;
         } else {
             if (which == 0) {
-                hipLaunchKernelGGL((k_pfwd_ct<T, N>), dim3(nblk_plane), dim3(plane_threads<N>()), (plane_lds<T, N>()), st,
-                                   x, slab, g, tw, nrhs, active);
+                const UpdArgs ua{upd.r, upd.v, upd.p, upd.pout, upd.rhat, upd.st};
+                if (upd.mode == 1)
+                    hipLaunchKernelGGL((k_pfwd_ct<T, N, 1>), dim3(nblk_plane), dim3(plane_threads<N>()),
+                                       (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
+                else if (upd.mode == 2)
+                    hipLaunchKernelGGL((k_pfwd_ct<T, N, 2>), dim3(nblk_plane), dim3(plane_threads<N>()),
+                                       (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
+                else
+                    hipLaunchKernelGGL((k_pfwd_ct<T, N, 0>), dim3(nblk_plane), dim3(plane_threads<N>()),
+                                       (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
             } else if (mode == MV_AX) {
                 if (dot == 1) launch_pinv<T, N, MV_AX, 1>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
                 else if (dot == 2) launch_pinv<T, N, MV_AX, 2>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
@@ -381,7 +433,11 @@ hipError_t set_attrs_n() {
     const int lim = 160 * 1024;
     hipError_t e = hipSuccess;
     if constexpr (plane_lds<T, N>() <= LDS_MAX) {
-        e = set_lds_limit((const void*)k_pfwd_ct<T, N>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        e = set_lds_limit((const void*)k_pfwd_ct<T, N, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_pfwd_ct<T, N, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_pfwd_ct<T, N, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         const void* fns[] = {(const void*)k_pinv_ct<T, N, MV_AX, 0>, (const void*)k_pinv_ct<T, N, MV_AX, 1>,
                              (const void*)k_pinv_ct<T, N, MV_AX, 2>, (const void*)k_pinv_ct<T, N, MV_RESID, 0>};
         for (const void* f : fns)
@@ -415,9 +471,10 @@ bool ct_supported(int n1, int n2, int n3) {
 template <class T>
 hipError_t launch_pass_ct(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x,
                           Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
-                          const int* active, int mode, int dot, const Cx<T>* w, double* partials, hipStream_t st) {
+                          const int* active, int mode, int dot, const Cx<T>* w, double* partials, const MvUpd& upd,
+                          hipStream_t st) {
     if (!ct_supported(g.n1, g.n2, g.n3)) return hipErrorNotSupported;
-#define PN(NV) pass_n<T, NV>(which, tx, zrb, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, dot, w, partials, st)
+#define PN(NV) pass_n<T, NV>(which, tx, zrb, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, dot, w, partials, upd, st)
     switch (g.n1) {
         case 16: return PN(16);
         case 32: return PN(32);
@@ -453,10 +510,10 @@ hipError_t configure_ct_kernels() {
 
 template hipError_t launch_pass_ct<float>(int, int, int, const Geo&, const Tw<float>&, int, const Cx<float>*,
                                           Cx<float>*, const Cx<float>*, Cx<float>*, const Cx<float>*, const Cx<float>*,
-                                          const int*, int, int, const Cx<float>*, double*, hipStream_t);
+                                          const int*, int, int, const Cx<float>*, double*, const MvUpd&, hipStream_t);
 template hipError_t launch_pass_ct<double>(int, int, int, const Geo&, const Tw<double>&, int, const Cx<double>*,
                                            Cx<double>*, const Cx<double>*, Cx<double>*, const Cx<double>*,
                                            const Cx<double>*, const int*, int, int, const Cx<double>*, double*,
-                                           hipStream_t);
+                                           const MvUpd&, hipStream_t);
 template int ct_available<float>(int, int);
 template int ct_available<double>(int, int);

@@ -488,12 +488,12 @@ bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh) {
 template <class T>
 hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh, int nrhs,
                        const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
-                       const int* active, int mode, hipStream_t st, MvDot dot) {
+                       const int* active, int mode, hipStream_t st, MvDot dot, MvUpd upd) {
     const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
     const long long np = (long long)n1 * n2;
     if ((which == 1 && (sh.ct & 2)) || (which != 1 && (sh.ct & 1)))
         return launch_pass_ct<T>(which, sh.tx, sh.zrb, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode,
-                                 which == 2 ? dot.dot : 0, (const Cx<T>*)dot.w, dot.partials, st);
+                                 which == 2 ? dot.dot : 0, (const Cx<T>*)dot.w, dot.partials, upd, st);
     if (which == 0) {
         if (sh.fused) {
             const int nplanes = nrhs * 3 * n3;
@@ -548,10 +548,10 @@ hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* 
 template <class T>
 hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh, int nrhs,
                          const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
-                         const int* active, int mode, hipStream_t st, MvDot dot) {
-    if (dot.dot && !(sh.ct & 1)) return hipErrorNotSupported;
+                         const int* active, int mode, hipStream_t st, MvDot dot, MvUpd upd) {
+    if ((dot.dot || upd.mode) && !(sh.ct & 1)) return hipErrorNotSupported;
     for (int w = 0; w < 3; ++w)
-        HIP_TRY(launch_pass<T>(w, g, tw, plans, sh, nrhs, x, y, b, slab, ghat, ainv, active, mode, st, dot));
+        HIP_TRY(launch_pass<T>(w, g, tw, plans, sh, nrhs, x, y, b, slab, ghat, ainv, active, mode, st, dot, upd));
     return hipSuccess;
 }
 
@@ -575,16 +575,16 @@ hipError_t launch_green(const Geo& g, const Tw<double>& tw, const FftPlan* plans
 
 template hipError_t launch_matvec<float>(const Geo&, const Tw<float>&, const FftPlan*, const MvShape&, int,
                                          const Cx<float>*, Cx<float>*, const Cx<float>*, Cx<float>*, const Cx<float>*,
-                                         const Cx<float>*, const int*, int, hipStream_t, MvDot);
+                                         const Cx<float>*, const int*, int, hipStream_t, MvDot, MvUpd);
 template hipError_t launch_matvec<double>(const Geo&, const Tw<double>&, const FftPlan*, const MvShape&, int,
                                           const Cx<double>*, Cx<double>*, const Cx<double>*, Cx<double>*,
-                                          const Cx<double>*, const Cx<double>*, const int*, int, hipStream_t, MvDot);
+                                          const Cx<double>*, const Cx<double>*, const int*, int, hipStream_t, MvDot, MvUpd);
 template hipError_t launch_pass<float>(int, const Geo&, const Tw<float>&, const FftPlan*, const MvShape&, int,
                                        const Cx<float>*, Cx<float>*, const Cx<float>*, Cx<float>*, const Cx<float>*,
-                                       const Cx<float>*, const int*, int, hipStream_t, MvDot);
+                                       const Cx<float>*, const int*, int, hipStream_t, MvDot, MvUpd);
 template hipError_t launch_pass<double>(int, const Geo&, const Tw<double>&, const FftPlan*, const MvShape&, int,
                                         const Cx<double>*, Cx<double>*, const Cx<double>*, Cx<double>*,
-                                        const Cx<double>*, const Cx<double>*, const int*, int, hipStream_t, MvDot);
+                                        const Cx<double>*, const Cx<double>*, const int*, int, hipStream_t, MvDot, MvUpd);
 template bool matvec_shape_ok<float>(const Geo&, const FftPlan*, const MvShape&);
 template bool matvec_shape_ok<double>(const Geo&, const FftPlan*, const MvShape&);
 

@@ -429,7 +429,47 @@ __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, doubl
     }
 }
 
+// Previous local field carried to the new incidence direction:
+//   esh_j = (1/alpha_prev) P_prev,j exp(i k (khat - khat_prev) . r_j)   (FP32 out),
+// and optionally P0_j = esh_j / (1/alpha_new) (FP64 out).
+__global__ void k_prev_shift(Geo g, double ox, double oy, double oz, const Cx<double>* __restrict__ Pprev,
+                             const Cx<double>* __restrict__ ainv_prev, const Cx<double>* __restrict__ ainv_new,
+                             const WaveDev* __restrict__ wprev, const WaveDev* __restrict__ wnew,
+                             Cx<float>* __restrict__ esh, Cx<double>* __restrict__ p0) {
+    const int rhs = blockIdx.y;
+    const WaveDev a = wprev[rhs], b = wnew[rhs];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.Npad; j += gridDim.x * blockDim.x) {
+        Cx<double> ph = {0, 0};
+        Cx<double> ap = {0, 0}, an = {1, 0};
+        if (j < g.N) {
+            const uint32_t s = g.site_xyz[j];
+            const double x = (double)(s & 1023) - ox, y = (double)((s >> 10) & 1023) - oy, z = (double)(s >> 20) - oz;
+            double sn, cs;
+            sincos(b.k * ((b.khat[0] - a.khat[0]) * x + (b.khat[1] - a.khat[1]) * y + (b.khat[2] - a.khat[2]) * z),
+                   &sn, &cs);
+            ph = Cx<double>{cs, sn};
+            ap = ainv_prev[(size_t)rhs * g.ncomp + g.site_comp[j]];
+            an = ainv_new[(size_t)rhs * g.ncomp + g.site_comp[j]];
+        }
+        const double dn = an.re * an.re + an.im * an.im;
+        for (int c = 0; c < 3; ++c) {
+            const size_t i = ((size_t)rhs * 3 + c) * g.Npad + j;
+            const Cx<double> e = (ap * Pprev[i]) * ph;
+            esh[i] = Cx<float>{(float)e.re, (float)e.im};
+            if (p0) p0[i] = Cx<double>{(e.re * an.re + e.im * an.im) / dn, (e.im * an.re - e.re * an.im) / dn};
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_prev_shift(const Geo& g, const double* origin, int nrhs, const Cx<double>* Pprev,
+                             const Cx<double>* ainv_prev, const Cx<double>* ainv_new, const WaveDev* wprev,
+                             const WaveDev* wnew, Cx<float>* esh, Cx<double>* p0, hipStream_t st) {
+    hipLaunchKernelGGL(k_prev_shift, dim3((g.Npad + 255) / 256, nrhs), dim3(256), 0, st, g, origin[0], origin[1],
+                       origin[2], Pprev, ainv_prev, ainv_new, wprev, wnew, esh, p0);
+    return hipGetLastError();
+}
 
 int vec_blocks(int Npad) { return (3 * Npad + VB - 1) / VB; }
 

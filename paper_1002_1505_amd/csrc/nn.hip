@@ -2,11 +2,14 @@
 // on the target's n x n x n box, trained on the GPU by its own BF16 MFMA
 // kernels (FP32 accumulate, FP32 master weights, Adam).
 //
+// The network refines the previous orientation's solution.  With E_sh the
+// previous local field (1/alpha) P_prev carried to the new incidence
+// direction by the phase factor exp(i k (khat - khat_prev) . r), the guess is
+//   E_loc = E_sh + net(features),  P0 = alpha E_loc = E_loc / (1/alpha).
 // Input features per voxel (16 channels, zero outside the target):
-//   occupancy, Re/Im E_inc (3 components), Re/Im (eps-1)/(eps+2), k d, khat.
-// Output: 16 channels, the first 6 = Re/Im of a correction to the local field:
-//   E_loc = E_inc + net(features),  P0 = alpha E_loc = E_loc / (1/alpha).
-// A network of zeros therefore reproduces the guess P0 = alpha E_inc.
+//   occupancy, Re/Im E_inc (3 components), Re/Im E_sh (3 components),
+//   Re/Im (eps-1)/(eps+2), k d.
+// A network of zeros reproduces the phase-shifted previous solution.
 //
 // Layers: 3x3x3 convolutions with dilation, ReLU after all but the last.
 // Activations are channels-last BF16 [sample][voxel][channel].
@@ -259,7 +262,8 @@ struct SampleDev {
     const uint8_t* site_comp;
     const double* kfac;  // Re/Im (eps-1)/(eps+2) per composition
     const double* ainv;  // Re/Im 1/alpha per composition
-    const float* resid;  // [3][Npad] complex: E_loc - E_inc (training target) or nullptr
+    const float* resid;  // [3][Npad] complex: E_loc - E_sh (training target) or nullptr
+    const float* esh;    // [3][Npad] complex: phase-shifted previous local field
 };
 
 __global__ void k_zero16(uint16_t* __restrict__ p, size_t n) {
@@ -281,14 +285,12 @@ __global__ void k_features(const SampleDev* __restrict__ sd, int D, uint16_t* __
         for (int a = 0; a < 3; ++a) {
             f[1 + 2 * a] = (float)(S.e[2 * a] * cs - S.e[2 * a + 1] * sn);
             f[2 + 2 * a] = (float)(S.e[2 * a] * sn + S.e[2 * a + 1] * cs);
+            f[7 + 2 * a] = S.esh[(size_t)(2 * a) * S.Npad + 2 * j];
+            f[8 + 2 * a] = S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1];
         }
-        f[7] = (float)S.kfac[2 * c];
-        f[8] = (float)S.kfac[2 * c + 1];
-        f[9] = (float)S.kd;
-        f[10] = (float)S.khat[0];
-        f[11] = (float)S.khat[1];
-        f[12] = (float)S.khat[2];
-        f[13] = f[14] = f[15] = 0.0f;
+        f[13] = (float)S.kfac[2 * c];
+        f[14] = (float)S.kfac[2 * c + 1];
+        f[15] = (float)S.kd;
         uint16_t* o = X + ((size_t)s * V + (size_t)(z * D + y) * D + x) * 16;
         for (int k = 0; k < 16; ++k) o[k] = f2bf(f[k]);
     }
@@ -297,10 +299,11 @@ __global__ void k_features(const SampleDev* __restrict__ sd, int D, uint16_t* __
 // Masked loss: per sample sum over sites of |out - resid|^2 / sum |resid + E_inc|^2
 // (normalised by the local field), gradient into dY (bf16, zero elsewhere).
 __global__ void k_loss(const SampleDev* __restrict__ sd, int D, const float* __restrict__ out,
-                       uint16_t* __restrict__ dY, double* __restrict__ loss_acc, float gnorm) {
+                       uint16_t* __restrict__ dY, double* __restrict__ loss_acc, float gscale) {
     __shared__ double sh[16];
     const int s = blockIdx.y;
     const SampleDev S = sd[s];
+    const float gnorm = gscale / (float)S.N;  // per-site mean of each sample
     const size_t V = (size_t)D * D * D;
     double num = 0, den = 0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < S.N; j += gridDim.x * blockDim.x) {
@@ -321,7 +324,7 @@ __global__ void k_loss(const SampleDev* __restrict__ sd, int D, const float* __r
     if (threadIdx.x == 0) atomicAdd(loss_acc + s, num);
 }
 
-// Guess P0 = (E_inc + out) / (1/alpha) into x64 ([3][Npad] complex128 of rhs slot).
+// Guess P0 = (E_sh + out) / (1/alpha) into x64 ([3][Npad] complex128 of rhs slot).
 __global__ void k_guess(const SampleDev* __restrict__ sd, int D, const float* __restrict__ out, Cx<double>* __restrict__ x64) {
     const int s = blockIdx.y;
     const SampleDev S = sd[s];
@@ -331,34 +334,28 @@ __global__ void k_guess(const SampleDev* __restrict__ sd, int D, const float* __
         const int x = q & 1023, y = (q >> 10) & 1023, z = q >> 20;
         const int c = S.site_comp[j];
         const size_t vi = (size_t)s * V + (size_t)(z * D + y) * D + x;
-        double sn, cs;
-        sincos(S.kd * (S.khat[0] * (x - S.ox) + S.khat[1] * (y - S.oy) + S.khat[2] * (z - S.oz)), &sn, &cs);
         const double ar = S.ainv[2 * c], ai = S.ainv[2 * c + 1];
         const double den = ar * ar + ai * ai;
         for (int a = 0; a < 3; ++a) {
-            const double er = S.e[2 * a] * cs - S.e[2 * a + 1] * sn + out[vi * 16 + 2 * a];
-            const double ei = S.e[2 * a] * sn + S.e[2 * a + 1] * cs + out[vi * 16 + 2 * a + 1];
+            const double er = S.esh[(size_t)(2 * a) * S.Npad + 2 * j] + out[vi * 16 + 2 * a];
+            const double ei = S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1] + out[vi * 16 + 2 * a + 1];
             // (er + i ei) / (ar + i ai)
             x64[((size_t)s * 3 + a) * S.Npad + j] = Cx<double>{(er * ar + ei * ai) / den, (ei * ar - er * ai) / den};
         }
     }
 }
 
-// Training target: resid = (1/alpha) P - E_inc from a solution in [3][Npad] complex128.
+// Training target: resid = (1/alpha) P - E_sh from a solution in [3][Npad] complex128.
 __global__ void k_record(const SampleDev* __restrict__ sd, const Cx<double>* __restrict__ P, float* __restrict__ resid) {
     const SampleDev S = sd[0];
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < S.N; j += gridDim.x * blockDim.x) {
-        const uint32_t q = S.site_xyz[j];
-        const int x = q & 1023, y = (q >> 10) & 1023, z = q >> 20;
         const int c = S.site_comp[j];
-        double sn, cs;
-        sincos(S.kd * (S.khat[0] * (x - S.ox) + S.khat[1] * (y - S.oy) + S.khat[2] * (z - S.oz)), &sn, &cs);
         const double ar = S.ainv[2 * c], ai = S.ainv[2 * c + 1];
         for (int a = 0; a < 3; ++a) {
             const Cx<double> p = P[(size_t)a * S.Npad + j];
             const double lr = ar * p.re - ai * p.im, li = ar * p.im + ai * p.re;
-            resid[(size_t)(2 * a) * S.Npad + 2 * j] = (float)(lr - (S.e[2 * a] * cs - S.e[2 * a + 1] * sn));
-            resid[(size_t)(2 * a) * S.Npad + 2 * j + 1] = (float)(li - (S.e[2 * a] * sn + S.e[2 * a + 1] * cs));
+            resid[(size_t)(2 * a) * S.Npad + 2 * j] = (float)(lr - S.esh[(size_t)(2 * a) * S.Npad + 2 * j]);
+            resid[(size_t)(2 * a) * S.Npad + 2 * j + 1] = (float)(li - S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1]);
         }
     }
 }
@@ -428,7 +425,7 @@ struct Layer {
 struct Sample {
     int tgt;  // target id in the context at recording time
     SampleDev dev;
-    std::shared_ptr<DBuf> resid;
+    std::shared_ptr<DBuf> resid, esh;
 };
 
 #define NCHK(x)                                   \
@@ -629,6 +626,7 @@ hipError_t nn_make_sample_dev(const NnSiteView& t, const dda_wave& w, const doub
     sd.kfac = kfac_ainv.as<double>();
     sd.ainv = kfac_ainv.as<double>() + 2 * t.ncomp;
     sd.resid = nullptr;
+    sd.esh = nullptr;
     return hipSuccess;
 }
 
@@ -655,7 +653,7 @@ static void drop_store(const dda_nn* nn) {
 
 // Record one solution (x64 slot of [3][Npad] complex128) as a training sample.
 hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, const double* ainv,
-                         const Cx<double>* x64, hipStream_t st) {
+                         const Cx<double>* x64, const Cx<float>* esh, hipStream_t st) {
     if (tv.n1 != tv.n2 || tv.n2 != tv.n3 || tv.n1 % 16) return hipErrorNotSupported;
     if (nn->box && nn->box != tv.n1) return hipErrorInvalidValue;
     nn->box = tv.n1;
@@ -686,6 +684,10 @@ hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, co
     NCHK(nn_make_sample_dev(t, w, ainv, S.dev, *kb));
     NCHK(rb->ensure((size_t)6 * t.Npad * sizeof(float)));
     NCHK(hipMemsetAsync(rb->p, 0, rb->n, st));
+    auto eb = std::make_shared<DBuf>();
+    NCHK(eb->ensure((size_t)6 * t.Npad * sizeof(float)));
+    NCHK(hipMemcpyAsync(eb->p, esh, (size_t)6 * t.Npad * sizeof(float), hipMemcpyDeviceToDevice, st));
+    S.dev.esh = eb->as<float>();
     DBuf one;
     NCHK(one.ensure(sizeof(SampleDev)));
     NCHK(hipMemcpyAsync(one.p, &S.dev, sizeof(SampleDev), hipMemcpyHostToDevice, st));
@@ -694,6 +696,7 @@ hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, co
     NCHK(hipStreamSynchronize(st));
     S.dev.resid = rb->as<float>();
     S.resid = rb;
+    S.esh = eb;
     store.aux.push_back(kb);
     nn->samples.push_back(S);
     return hipSuccess;
@@ -701,7 +704,7 @@ hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, co
 
 // Guesses P0 for nr right-hand sides of one target into x64 ([rhs][3][Npad] complex128).
 hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves, const double* ainv, int nr,
-                          Cx<double>* x64, hipStream_t st) {
+                          const Cx<float>* esh, Cx<double>* x64, hipStream_t st) {
     if (t.n1 != t.n2 || t.n2 != t.n3 || t.n1 % 16) return hipErrorNotSupported;
     const int D = t.n1;
     const int chunk = 4;
@@ -711,7 +714,10 @@ hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves
     const size_t V = (size_t)D * D * D;
     for (int s0 = 0; s0 < nr; s0 += chunk) {
         const int nb = std::min(chunk, nr - s0);
-        for (int k = 0; k < nb; ++k) NCHK(nn_make_sample_dev(t, waves[s0 + k], ainv + (size_t)(s0 + k) * 2 * t.ncomp, sds[k], kb[k]));
+        for (int k = 0; k < nb; ++k) {
+            NCHK(nn_make_sample_dev(t, waves[s0 + k], ainv + (size_t)(s0 + k) * 2 * t.ncomp, sds[k], kb[k]));
+            sds[k].esh = reinterpret_cast<const float*>(esh + (size_t)(s0 + k) * 3 * t.Npad);
+        }
         NCHK(hipMemcpyAsync(nn->sdev.p, sds.data(), nb * sizeof(SampleDev), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, nn->act[0].as<uint16_t>(), V * nb * 16);
         NCHK(hipGetLastError());
@@ -888,8 +894,8 @@ dda_status dda_nn_train(dda_ctx* ctx, dda_nn* nn, const dda_nn_train_opts* o, do
             if (nn_forward_any(nn, B, st) != hipSuccess) return DDA_ERR_HIP;
             hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, nn->dA.as<uint16_t>(), V * B * 16);
             (void)hipMemsetAsync(nn->lossacc.p, 0, B * sizeof(double), st);
-            // gradient scaled by 1/(B * N) so that the loss is a per-site mean
-            const float gnorm = 1.0f / (3.0f * (float)B * (float)sds[0].N);
+            // gradient of the batch mean of per-sample, per-site mean losses
+            const float gnorm = 1.0f / (3.0f * (float)B);
             hipLaunchKernelGGL(k_loss, dim3(256, B), dim3(256), 0, st, nn->sdev.as<SampleDev>(), D, nn->out32.as<float>(),
                                nn->dA.as<uint16_t>(), nn->lossacc.as<double>(), gnorm);
             (void)hipMemsetAsync(nn->g.p, 0, nn->nparams * 4, st);

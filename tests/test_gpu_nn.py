@@ -1,10 +1,13 @@
 """The learned-guess network on the GPU (BF16 MFMA kernels, FP32 accumulate)
 against the FP64 oracle network: forward output and parameter gradients.
 
-Weights and inputs are rounded to BF16 before both sides see them, so the
-remaining difference comes from the BF16 rounding of the activations and of
-the output gradient between layers (8-bit mantissa: ~0.4 % per rounding,
-a few roundings deep) -- bars: 3 % relative L2 and cosine >= 0.999."""
+Weights and inputs are rounded to BF16 before both sides see them.  Two
+comparisons: (1) against the oracle that rounds activations and gradients to
+BF16 at the same points as the kernels (same rounding decisions; what
+remains is FP32-vs-FP64 accumulation order and the occasional BF16 tie that
+falls the other way) -- 1 % relative L2, cosine >= 0.9999; (2) against the
+pure FP64 oracle, where BF16 rounding (2^-9 relative per store) compounds
+over the layers -- 5 % relative L2, cosine >= 0.998."""
 import numpy as np
 import pytest
 
@@ -38,22 +41,100 @@ def test_forward_and_gradients_match_oracle(width, depth):
     mask = rng.random((ns, D, D, D)) < 0.4
     target = rng.standard_normal((ns, D, D, D, 16)).astype(np.float32)
     out, grads, loss = net.forward_backward(x, target, mask, nout=6)
-    onet = onn.Net(layers, [(w.astype(np.float64), b.astype(np.float64)) for w, b in params])
-    losses, ograds = [], None
-    for s in range(ns):
-        o, acts = onet.forward(x[s].astype(np.float64))
-        rel = np.linalg.norm(out[s] - o) / np.linalg.norm(o)
-        assert rel < 3e-2, rel
-        ls, dout = onn.masked_mse(o, target[s].astype(np.float64), mask[s], 6)
-        losses.append(ls)
-        g = onet.backward(acts, dout / ns)
-        ograds = g if ograds is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(ograds, g)]
-    assert abs(loss - np.mean(losses)) / np.mean(losses) < 2e-2
-    for li, ((gw, gb), (ow, ob)) in enumerate(zip(grads, ograds)):
-        rel = np.linalg.norm(gw - ow) / np.linalg.norm(ow)
-        cos = np.sum(gw * ow) / (np.linalg.norm(gw) * np.linalg.norm(ow))
-        assert rel < 3e-2 and cos > 0.999, (li, rel, cos)
-        relb = np.linalg.norm(gb - ob) / np.linalg.norm(ob)
-        assert relb < 3e-2, (li, relb)
+    for quant, tol, cmin in ((onn.bf16_round, 1e-2, 0.9999), (None, 5e-2, 0.998)):
+        onet = onn.Net(layers, [(w.astype(np.float64), b.astype(np.float64)) for w, b in params], quantize=quant)
+        losses, ograds = [], None
+        for s in range(ns):
+            o, acts = onet.forward(x[s].astype(np.float64))
+            rel = np.linalg.norm(out[s] - o) / np.linalg.norm(o)
+            assert rel < tol, (quant, rel)
+            ls, dout = onn.masked_mse(o, target[s][..., :6].astype(np.float64), mask[s], 6)
+            losses.append(ls)
+            g = onet.backward(acts, dout / ns)
+            ograds = g if ograds is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(ograds, g)]
+        assert abs(loss - np.mean(losses)) / np.mean(losses) < tol
+        for li, ((gw, gb), (ow, ob)) in enumerate(zip(grads, ograds)):
+            rel = np.linalg.norm(gw - ow) / np.linalg.norm(ow)
+            cos = np.sum(gw * ow) / (np.linalg.norm(gw) * np.linalg.norm(ow))
+            assert rel < tol and cos > cmin, (quant, li, rel, cos)
+            relb = np.linalg.norm(gb - ob) / np.linalg.norm(ob)
+            assert relb < tol, (quant, li, relb)
+    net.close()
+    ctx.close()
+
+
+def _sweep_waves(count, beta=0.3, phi=0.2):
+    import synth
+    from oracle import dda
+
+    out = []
+    for b, th, ph in synth.theta_sweep(count, beta, phi):
+        kh, es, _ = dda.waves_for_orientation(b, th, ph)
+        out.append(([kh, kh], es))
+    return out
+
+
+def test_zero_network_reproduces_shifted_guess_and_state_errors():
+    """The network starts with a zero last layer, so its guess is the
+    phase-shifted previous solution; the learned guess and recording need a
+    previous solution."""
+    import synth
+    import paper_1002_1505_amd as P
+
+    ctx = P.Context(0)
+    ctx.set_target(synth.sphere_occupancy(16), [1.5 + 0.05j], 0.6, P.DDA_ALPHA_LDR)
+    net = P.Net(ctx, width=16, depth=4, seed=5)
+    net.attach()
+    sw = _sweep_waves(6)
+    with pytest.raises(P.DDAError):
+        ctx.solve(*sw[0], guess=P.DDA_GUESS_NN, want_p=False)
+    ctx.solve(*sw[0], prec=P.DDA_SOLVE_FP64, tol=1e-10, want_p=False)
+    with pytest.raises(P.DDAError):
+        net.record()
+    res = {}
+    for name, g in (("shift", P.DDA_GUESS_PREV_SHIFT), ("nn", P.DDA_GUESS_NN)):
+        ctx.solve(*sw[0], prec=P.DDA_SOLVE_FP64, tol=1e-10, want_p=False)
+        _, st, _ = ctx.solve(*sw[1], prec=P.DDA_SOLVE_FP64, tol=1e-5, guess=g, want_p=False)
+        res[name] = [s["guess_resid"] for s in st]
+        assert all(s["rel_resid"] <= 1e-5 for s in st)
+    for a, b in zip(res["nn"], res["shift"]):
+        assert a < 1.0 and abs(a - b) <= 1e-5 * b + 1e-7, (a, b)
+    net.record()
+    assert net.num_samples == 2
+    net.close()
+    ctx.close()
+
+
+def test_training_lowers_guess_residual_on_its_sweep():
+    """Record the solutions of a 12-orientation sweep of a porous aggregate,
+    train, then run the sweep again: the learned guess starts closer to the
+    solution than the phase-shifted previous solution it corrects."""
+    import synth
+    import paper_1002_1505_amd as P
+
+    ctx = P.Context(0)
+    occ = synth.aggregate_occupancy(16, np.random.default_rng(synth.CONFIG_SEED_BASE + 50))
+    ctx.set_target(occ, [1.5 + 0.05j], 0.8, P.DDA_ALPHA_LDR)
+    net = P.Net(ctx, width=16, depth=4, seed=7)
+    sw = _sweep_waves(12)
+    ctx.solve(*sw[0], want_p=False)
+    for w in sw[1:]:
+        ctx.solve(*w, guess=P.DDA_GUESS_PREV_SHIFT, want_p=False)
+        net.record()
+    assert net.num_samples == 22
+    first = net.train(epochs=1, batch=2, lr=2e-3)
+    last = net.train(epochs=60, batch=2, lr=2e-3)
+    assert last < 0.8 * first, (first, last)
+    net.attach()
+    res = {}
+    for name, g in (("shift", P.DDA_GUESS_PREV_SHIFT), ("nn", P.DDA_GUESS_NN)):
+        ctx.solve(*sw[0], want_p=False)
+        r = []
+        for w in sw[1:]:
+            _, st, _ = ctx.solve(*w, guess=g, want_p=False)
+            assert all(s["rel_resid"] <= 1e-5 for s in st)
+            r += [s["guess_resid"] for s in st]
+        res[name] = np.mean(r)
+    assert res["nn"] < res["shift"], res
     net.close()
     ctx.close()

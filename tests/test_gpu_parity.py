@@ -225,3 +225,41 @@ def test_graph_and_eager_agree(ctx):
     for l in range(2):
         assert sg[l]["iters"] == se[l]["iters"]
         assert _rel(Pg[l], Pe[l]) < 1e-6
+
+
+def test_shifted_previous_guess_vs_oracle(ctx):
+    """Two consecutive orientations of a sweep (Theta step, both
+    polarizations): the residual of the PREV and PREV_SHIFT guesses on the
+    GPU equals the oracle's residual of the same guesses built from the
+    oracle's own previous solution."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.ellipsoid_occupancy((12, 16, 10), (11.0, 15.0, 9.5))
+    m, kd = [1.5 + 0.05j], 0.5
+    r, comp = _setup(ctx, occ, m, kd, dda.ALPHA_LDR)
+    kp, ep, _ = dda.waves_for_orientation(0.4, 0.9, 0.3)
+    kn, en, _ = dda.waves_for_orientation(0.4, 1.05, 0.3)
+
+    def oracle_solve(kh, e):
+        ainv = dda.site_inverse_polarizability(comp, m, kd, dda.ALPHA_LDR, kh, e)
+        E = dda.incident_field(r, kd, kh, e)
+        return ainv, E, dda.solve_dense(r, kd, ainv, E)
+
+    expect = {"prev": [], "shift": []}
+    for l in range(2):
+        ap, _, Pp = oracle_solve(kp, ep[l])
+        an = dda.site_inverse_polarizability(comp, m, kd, dda.ALPHA_LDR, kn, en[l])
+        En = dda.incident_field(r, kd, kn, en[l])
+        _, P0 = dda.shifted_previous_guess(r, kd, Pp, ap, an, kp, kn)
+        y0 = dda.matvec_direct(r, kd, an, Pp)
+        y1 = dda.matvec_direct(r, kd, an, P0)
+        expect["prev"].append(np.linalg.norm(En - y0) / np.linalg.norm(En))
+        expect["shift"].append(np.linalg.norm(En - y1) / np.linalg.norm(En))
+    for name, guess in (("prev", P.DDA_GUESS_PREV), ("shift", P.DDA_GUESS_PREV_SHIFT)):
+        ctx.solve([kp, kp], ep, prec=P.DDA_SOLVE_FP64, tol=1e-11, want_p=False)
+        _, st, _ = ctx.solve([kn, kn], en, prec=P.DDA_SOLVE_FP64, tol=1e-5, guess=guess)
+        for l in range(2):
+            assert abs(st[l]["guess_resid"] - expect[name][l]) <= 1e-7 + 1e-6 * expect[name][l], (name, l)
+            assert st[l]["rel_resid"] <= 1e-5
+    # on this sweep step the phase shift improves on the unshifted previous solution
+    assert sum(expect["shift"]) < sum(expect["prev"])

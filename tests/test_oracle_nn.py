@@ -83,3 +83,26 @@ def test_adam_matches_textbook_first_step():
     g = rng.standard_normal(10)
     p1, m, v = nn.adam_step(p, g, np.zeros(10), np.zeros(10), 1, lr=1e-2)
     assert np.allclose(p1 - p, -1e-2 * np.sign(g), atol=1e-9)
+
+
+def test_bf16_rounding_known_values():
+    """bfloat16 keeps 8 mantissa bits: 1 + 2^-8 rounds to even (1), 1 + 3*2^-8
+    rounds up to 1 + 2^-6... checked against exact binary expansions."""
+    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -7, -2.5, 3.140625])
+    r = nn.bf16_round(v)
+    assert np.array_equal(r, [1.0, 1.0, 1.0 + 2 ** -6, 1.0 + 2 ** -7, -2.5, 3.140625])
+
+
+def test_quantized_backward_equals_plain_backward_without_rounding():
+    """With the identity quantizer the two backward formulations agree."""
+    rng = np.random.default_rng(4)
+    layers = [(2, 3, 1), (3, 2, 2)]
+    net = _rand_net(rng, layers)
+    x = rng.standard_normal((4, 4, 4, 2))
+    out, acts = net.forward(x)
+    g = net.backward(acts, np.ones_like(out))
+    net2 = nn.Net(layers, net.params, quantize=lambda a: a)
+    out2, acts2 = net2.forward(x)
+    g2 = net2.backward(acts2, np.ones_like(out2))
+    for (a, b), (c, d) in zip(g, g2):
+        assert np.allclose(a, c) and np.allclose(b, d)

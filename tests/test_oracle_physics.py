@@ -196,3 +196,43 @@ def test_cabs_of_lossless_target_vanishes():
     P = dda.solve_dense(r, k, ainv, E)
     qext, qabs, qsca = dda.cross_sections(k, E, P, ainv)
     assert abs(qabs) < 1e-12 * qext
+
+
+def test_shifted_guess_exact_for_isolated_dipole():
+    """One dipole off the origin, incidence rotated about a fixed polarization:
+    the exact new solution alpha_new E_inc,new(r0) is reproduced, with LDR
+    polarizabilities that differ between the two directions (S = 0 vs 8/25)."""
+    k, m = 0.4, 1.5 + 0.1j
+    r = np.array([[0.3, -1.2, 2.1]])
+    e = np.array([1.0, 2.0, 0.0]) / np.sqrt(5)
+    kp, kn = np.array([0.0, 0.0, 1.0]), np.array([2.0, -1.0, 0.0]) / np.sqrt(5)
+    ap = np.array([dda.inverse_polarizability(m, k, dda.ALPHA_LDR, kp, e)])
+    an = np.array([dda.inverse_polarizability(m, k, dda.ALPHA_LDR, kn, e)])
+    assert abs(ap[0] - an[0]) > 1e-3 * abs(an[0])
+    Pp = dda.incident_field(r, k, kp, e) / ap[:, None]
+    e_sh, P0 = dda.shifted_previous_guess(r, k, Pp, ap, an, kp, kn)
+    En = dda.incident_field(r, k, kn, e)
+    assert np.allclose(e_sh, En, rtol=1e-14)
+    assert np.allclose(P0, En / an[:, None], rtol=1e-14)
+
+
+def test_shifted_guess_same_wave_and_static_limit():
+    """Same wave twice: the guess is the previous solution.  Static limit
+    (k -> 0) with the polarization kept: the local field no longer depends on
+    the incidence direction, so the shifted guess solves the new system to O(k)."""
+    occ = synth.sphere_occupancy(6)
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    m = 1.6 + 0.2j
+    e = np.array([0.0, 0.0, 1.0])
+    kp, kn = np.array([1.0, 0.0, 0.0]), np.array([0.6, 0.8, 0.0])
+    for k, bound in ((0.5, None), (1e-4, 1e-3)):
+        ainv = np.full(len(r), dda.inverse_polarizability(m, k, dda.ALPHA_CM_RR))
+        Pp = dda.solve_dense(r, k, ainv, dda.incident_field(r, k, kp, e))
+        _, same = dda.shifted_previous_guess(r, k, Pp, ainv, ainv, kp, kp)
+        assert np.allclose(same, Pp, rtol=1e-14, atol=0)
+        if bound is None:
+            continue
+        _, P0 = dda.shifted_previous_guess(r, k, Pp, ainv, ainv, kp, kn)
+        En = dda.incident_field(r, k, kn, e)
+        rel = np.linalg.norm(En.reshape(-1) - dda.dense_matrix(r, k, ainv) @ P0.reshape(-1)) / np.linalg.norm(En)
+        assert rel < bound
