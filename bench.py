@@ -38,10 +38,13 @@ def parse():
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--x", type=float, default=10.0)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run three plain 256 MiB device copies (reference kernel for HBM byte counters)")
     ap.add_argument("--train-targets", type=int, default=16)
     ap.add_argument("--train-orient", type=int, default=32)
     ap.add_argument("--nn-width", type=int, default=16)
     ap.add_argument("--nn-depth", type=int, default=6)
+    ap.add_argument("--history", type=int, default=3, help="solutions kept per slot for the least-squares guess")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--eval-targets", type=int, default=2)
     ap.add_argument("--sweep", type=int, default=32)
@@ -63,6 +66,13 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if a.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = P.Context(0, stream=stream.cuda_stream)
 
     n = a.box
@@ -206,14 +216,14 @@ def _aggregate_problem(synth, rng):
 def learned_vs_plain(P, ctx, a):
     """Learned initial guess on porous aggregates in a 64^3 box (seeded
     Gaussian-random-field targets, fill 0.3, m = U[1.3,1.7] + i U[0.01,0.1],
-    x = U[2,10]).  Training pairs come from orientation sweeps (uniform in
+    x = U[2,10]).  Training fields come from orientation sweeps (uniform in
     cos Theta, random beta, Phi) of held-in targets: each solve after the
-    first starts from the phase-shifted previous solution and is recorded.
-    Evaluation runs sweeps of held-out targets one orientation (2
-    polarizations) per solve, with P0 = 0, the previous orientation's P, that
-    P phase-shifted to the new direction, and the network's correction of the
-    shifted P; every mode starts its sweep from P0 = 0 and is timed whole,
-    guess cost included."""
+    first starts from the least-squares guess over the last `history`
+    solutions and is recorded.  Evaluation runs sweeps of held-out targets
+    one orientation (2 polarizations) per solve, with P0 = 0, the previous
+    orientation's P, that P phase-shifted to the new direction, the
+    least-squares guess, and the network's correction of it; every mode
+    starts its sweep from P0 = 0 and is timed whole, guess cost included."""
     import torch
 
     import synth
@@ -227,18 +237,19 @@ def learned_vs_plain(P, ctx, a):
         ori = synth.theta_sweep(a.train_orient, beta=rng.uniform(0, 2 * np.pi), phi=rng.uniform(0, 2 * np.pi))
         for i, (b, t, p) in enumerate(ori):
             kh, ee = P.orientation_waves(b, t, p)
-            ctx.solve(kh, ee, tol=1e-5, want_p=False,
-                      guess=P.DDA_GUESS_ZERO if i == 0 else P.DDA_GUESS_PREV_SHIFT)
+            ctx.solve(kh, ee, tol=1e-5, want_p=False, history=a.history,
+                      guess=P.DDA_GUESS_ZERO if i == 0 else P.DDA_GUESS_PROJECT)
             if i:
                 net.record()
     gen_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    loss = net.train(epochs=a.epochs, batch=4, lr=1e-3)
+    loss0 = net.train(epochs=1, batch=4, lr=1e-3)
+    loss = net.train(epochs=a.epochs - 1, batch=4, lr=1e-3) if a.epochs > 1 else loss0
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     net.attach()
     modes = (("zero", P.DDA_GUESS_ZERO), ("prev", P.DDA_GUESS_PREV), ("prev_shift", P.DDA_GUESS_PREV_SHIFT),
-             ("nn", P.DDA_GUESS_NN))
+             ("project", P.DDA_GUESS_PROJECT), ("nn", P.DDA_GUESS_NN))
     res = {m: [0, 0.0, 0] for m, _ in modes}  # iters, seconds, converged solves
     resid = {m: [] for m, _ in modes}
     guess_ms = {m: 0.0 for m, _ in modes}
@@ -253,7 +264,7 @@ def learned_vs_plain(P, ctx, a):
             t1 = time.perf_counter()
             for i, (kh, ee) in enumerate(waves):
                 gg = P.DDA_GUESS_ZERO if i == 0 else g
-                _, st, _ = ctx.solve(kh, ee, tol=1e-5, guess=gg, want_p=False)
+                _, st, _ = ctx.solve(kh, ee, tol=1e-5, guess=gg, want_p=False, history=a.history)
                 res[mode][0] += sum(s["iters"] for s in st)
                 res[mode][2] += sum(1 for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
                 if i:
@@ -267,6 +278,8 @@ def learned_vs_plain(P, ctx, a):
                     f"sweeps x 2 pol ({net.num_samples} recorded fields), {a.eval_targets} held-out targets x "
                     f"{a.sweep}-orientation sweeps x 2 pol, one orientation per solve, tol 1e-5",
         "net": f"width {a.nn_width}, depth {a.nn_depth}, {net.num_params} params, BF16 MFMA",
+        "history": a.history,
+        "train_loss_first_epoch": round(loss0, 4),
         "train_loss": round(loss, 4),
         "gen_s": round(gen_s, 2),
         "train_s": round(train_s, 2),
@@ -278,7 +291,7 @@ def learned_vs_plain(P, ctx, a):
                      "converged": f"{conv}/{n_solves}",
                      "mean_guess_resid": round(float(np.mean(resid[mode])), 4) if resid[mode] else 1.0,
                      "guess_ms_per_solve": round(guess_ms[mode] / max(1, n_solves // 2 - a.eval_targets), 3)}
-    for base in ("zero", "prev", "prev_shift"):
+    for base in ("zero", "prev", "prev_shift", "project"):
         out[f"nn_vs_{base}"] = round(out["nn"]["solves_per_s"] / out[base]["solves_per_s"], 3)
     net.close()
     return out

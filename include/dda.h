@@ -76,9 +76,14 @@ enum {
     DDA_GUESS_USER = 1,   /* P0 from the p0 argument */
     DDA_GUESS_PREV = 2,   /* P0 = this context's previous solution in the same rhs slot */
     DDA_GUESS_NN = 3,     /* P0 = alpha (E_sh + net(features)), attached learned-guess network */
-    DDA_GUESS_PREV_SHIFT = 4  /* P0 = alpha_new E_sh: the previous local field carried to the new
+    DDA_GUESS_PREV_SHIFT = 4, /* P0 = alpha_new E_sh: the previous local field carried to the new
                                  incidence direction, E_sh,j = (1/alpha_prev) P_prev,j
                                  exp(i k (khat - khat_prev) . r_j) */
+    DDA_GUESS_PROJECT = 5     /* P0 = sum_e c_e v_e over the slot's history of solutions (see
+                                 dda_solve_opts.history; the previous solution alone while the
+                                 history is empty), v_e each carried to the new direction as for
+                                 PREV_SHIFT, c minimising ||E - A P0||_2 (one FP32 matvec per
+                                 basis vector) */
 };
 
 /* Flags. */
@@ -106,7 +111,9 @@ typedef struct {
     int32_t prec;         /* DDA_SOLVE_* */
     uint32_t flags;       /* DDA_DEVICE_PTRS | DDA_NO_GRAPH | DDA_NO_FALLBACK */
     int32_t graph_iters;  /* BiCGstab iterations per graph replay; 0 = autotuned/default */
-    int32_t reserved[3];
+    int32_t history;      /* 0..4: keep the solutions of the last `history` solves of every slot
+                             (for DDA_GUESS_PROJECT and the learned guess); 0 clears them */
+    int32_t reserved[2];
 } dda_solve_opts;
 
 typedef struct {
@@ -164,9 +171,10 @@ dda_status dda_build_green_fft(dda_ctx* ctx, uint32_t prec);
  * to keep the solution on the device only (for cross sections, amplitudes or
  * DDA_GUESS_PREV).  stats (nrhs entries) may be NULL.  The waves of one call
  * may reference different targets (batched multi-target solve).
- * DDA_GUESS_PREV, _PREV_SHIFT and _NN need a previous solve with the same
- * nrhs whose slots hold the same targets (DDA_ERR_STATE otherwise); the waves
- * themselves may change (the next orientation or direction of a sweep).
+ * DDA_GUESS_PREV, _PREV_SHIFT, _PROJECT and _NN need a previous solve with
+ * the same nrhs whose slots hold the same targets (DDA_ERR_STATE otherwise);
+ * the waves themselves may change (the next orientation or direction of a
+ * sweep).  Redefining a target clears the history of its slots.
  * Returns DDA_WARN_NOT_CONVERGED if any right-hand side missed tol.
  */
 dda_status dda_solve(dda_ctx* ctx, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* opts,
@@ -268,14 +276,18 @@ dda_status dda_profile_matvec(dda_ctx* ctx, int32_t target, int32_t nrhs, uint32
 /* ---- Learned initial guess ----
  * For a sweep over orientations (or incidence directions) of one target, a 3D
  * convolutional network on the target's cubic box (side divisible by 16)
- * corrects the previous solution carried to the new direction: the local
- * field is E_loc = E_sh + net(features) at the occupied sites (E_sh as for
- * DDA_GUESS_PREV_SHIFT) and the guess is P0 = E_loc / (1/alpha).  Features
- * per voxel: occupancy, E_inc, E_sh, (eps-1)/(eps+2), k d (16 channels).
+ * corrects the DDA_GUESS_PROJECT guess P_b.  With E_b = (1/alpha) P_b its
+ * local field, R = E_inc - A P_b its residual field (both FP32, R from the
+ * products the projection already formed) and sigma the rms of R, the local
+ * field is E_loc = E_b + sigma net(features) at the occupied sites and the
+ * guess is P0 = E_loc / (1/alpha): a learned approximate inverse of A applied
+ * once to R / sigma.  Features per voxel: occupancy, R / sigma, E_b,
+ * (eps-1)/(eps+2), k d (16 channels).  Train and use the network with the
+ * same history setting.
  * 3x3x3 convolutions with dilations 1, 2, 4, 8, ReLU; BF16 operands on MFMA
- * with FP32 accumulation; FP32 master weights trained with Adam on pairs of
- * consecutive solutions (dda_nn_record).  The network of zeros reproduces
- * DDA_GUESS_PREV_SHIFT.  A guess is used only if its FP64 residual is below
+ * with FP32 accumulation; FP32 master weights trained with Adam on solutions
+ * of DDA_GUESS_PROJECT solves (dda_nn_record).  The network of zeros reproduces
+ * DDA_GUESS_PROJECT.  A guess is used only if its FP64 residual is below
  * ||E|| (else P0 = 0). */
 typedef struct dda_nn dda_nn;
 
@@ -307,8 +319,8 @@ dda_status dda_nn_set_params(dda_nn* nn, const float* in);
 /* Attach a network as the DDA_GUESS_NN model of the context (NULL detaches). */
 dda_status dda_set_guess_model(dda_ctx* ctx, dda_nn* nn);
 /* Record every solution of the last solve as a training sample (target
- * E_loc - E_sh).  The last solve must have used DDA_GUESS_PREV, _PREV_SHIFT
- * or _NN, so that E_sh exists (DDA_ERR_STATE otherwise). */
+ * (E_loc - E_b) / sigma).  The last solve must have used DDA_GUESS_PROJECT or
+ * DDA_GUESS_NN, so that E_b and R exist (DDA_ERR_STATE otherwise). */
 dda_status dda_nn_record(dda_ctx* ctx, dda_nn* nn);
 /* Train on the recorded samples; mean loss of the last epoch in *loss. */
 dda_status dda_nn_train(dda_ctx* ctx, dda_nn* nn, const dda_nn_train_opts* opts, double* loss);

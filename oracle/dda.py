@@ -414,3 +414,18 @@ def shifted_previous_guess(r, k, P_prev, ainv_prev, ainv_new, khat_prev, khat_ne
     phase = np.exp(1j * (r @ dk))
     e_sh = (ainv_prev[:, None] * P_prev) * phase[:, None]
     return e_sh, e_sh / ainv_new[:, None]
+
+
+def projected_history_guess(r, k, ainv_new, khat_new, E_new, history):
+    """Least-squares initial guess over earlier solutions of a sweep.
+
+    Each earlier solution (P, ainv, khat) in ``history`` is carried to the new
+    incidence direction as in ``shifted_previous_guess``, giving v_e; the guess
+    is P0 = sum_e c_e v_e with c minimising ||E_new - A P0||_2, the linear
+    least-squares problem min_c ||E - W c|| with W = [A v_1 ... A v_h] (A of
+    eq. AP=E with the new 1/alpha, by the direct matvec).  Returns (P0, c).
+    """
+    basis = [shifted_previous_guess(r, k, P, a, ainv_new, kh, khat_new)[1] for P, a, kh in history]
+    W = np.stack([matvec_direct(r, k, ainv_new, v).reshape(-1) for v in basis], axis=1)
+    c, *_ = np.linalg.lstsq(W, np.asarray(E_new).reshape(-1), rcond=None)
+    return sum(ce * v for ce, v in zip(c, basis)), c

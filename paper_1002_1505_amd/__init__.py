@@ -12,8 +12,8 @@ import numpy as np
 
 from . import _lib as L
 from ._lib import (DDA_ALPHA_CM, DDA_ALPHA_CM_RR, DDA_ALPHA_LDR, DDA_DEVICE_PTRS, DDA_FP32, DDA_FP64,  # noqa: F401
-                   DDA_GUESS_NN, DDA_GUESS_PREV, DDA_GUESS_PREV_SHIFT, DDA_GUESS_USER, DDA_GUESS_ZERO,
-                   DDA_NO_FALLBACK, DDA_NO_GRAPH,
+                   DDA_GUESS_NN, DDA_GUESS_PREV, DDA_GUESS_PREV_SHIFT, DDA_GUESS_PROJECT, DDA_GUESS_USER,
+                   DDA_GUESS_ZERO, DDA_NO_FALLBACK, DDA_NO_GRAPH,
                    DDA_SOLVE_FP32_REFINE, DDA_SOLVE_FP64, DDA_WARN_MKD_GE_1, DDA_WARN_NOT_CONVERGED)
 
 __all__ = ["Context", "DDAError", "lab_frame", "mueller", "orientation_waves", "scattering_frame", "load_library"]
@@ -136,13 +136,13 @@ class Context:
 
     # -- solve -----------------------------------------------------------
     def solve(self, khat, e0, targets=None, tol=1e-5, max_iter=1000, guess=DDA_GUESS_ZERO,
-              prec=DDA_SOLVE_FP32_REFINE, p0=None, want_p=True, flags=0, graph_iters=0):
+              prec=DDA_SOLVE_FP32_REFINE, p0=None, want_p=True, flags=0, graph_iters=0, history=0):
         """Solve A P = E_inc for each wave; returns (P or None, stats list, status).
 
         P is a list of (N_t, 3) complex128 arrays (one per wave)."""
         arr, n = _waves(khat, e0, targets)
         opts = L.dda_solve_opts(tol=tol, max_iter=max_iter, guess=guess, prec=prec, flags=flags,
-                                graph_iters=graph_iters)
+                                graph_iters=graph_iters, history=history)
         tg = [arr[i].target for i in range(n)]
         sizes = [self.n_sites[t] for t in tg]
         p0buf = None

@@ -37,6 +37,7 @@ DDA_GUESS_USER = 1
 DDA_GUESS_PREV = 2
 DDA_GUESS_NN = 3
 DDA_GUESS_PREV_SHIFT = 4
+DDA_GUESS_PROJECT = 5
 
 DDA_DEVICE_PTRS = 1
 DDA_NO_GRAPH = 2
@@ -49,7 +50,8 @@ class dda_wave(C.Structure):
 
 class dda_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("guess", C.c_int32), ("prec", C.c_int32),
-                ("flags", C.c_uint32), ("graph_iters", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("flags", C.c_uint32), ("graph_iters", C.c_int32), ("history", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class dda_solve_stats(C.Structure):

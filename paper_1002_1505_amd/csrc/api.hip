@@ -27,9 +27,11 @@
 using cd = std::complex<double>;
 
 hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, const double* ainv,
-                         const Cx<double>* x64, const Cx<float>* esh, hipStream_t st);
+                         const Cx<double>* x64, const Cx<float>* esh, const Cx<float>* rf, float rscale,
+                         hipStream_t st);
 hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves, const double* ainv, int nr,
-                          const Cx<float>* esh, Cx<double>* x64, hipStream_t st);
+                          const Cx<float>* esh, const Cx<float>* rf, const float* rscale, Cx<double>* x64,
+                          hipStream_t st);
 
 namespace {
 
@@ -40,6 +42,7 @@ constexpr double LDR_B1 = -1.8915316, LDR_B2 = 0.1648469, LDR_B3 = -1.7700004;
 struct DevMem {
     void* p = nullptr;
     size_t n = 0;
+    unsigned gen = 0;  // allocations so far (a new allocation may reuse the old address)
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
@@ -59,6 +62,7 @@ struct DevMem {
             return e;
         }
         n = bytes;
+        ++gen;
         return hipSuccess;
     }
     template <class U>
@@ -120,11 +124,20 @@ struct Group {
     DevMem kv[8];  // inner Krylov vectors x r rhat p v s t p' (kprec precision)
     DevMem slab32, slab64;
     DevMem state, active, partials, scale, tolrel2, maxit, norms, mask;
-    // previous solve of the same slots: waves and 1/alpha, and its local field
-    // carried to the current incidence direction (FP32), for the guesses that
-    // start from the previous solution
-    DevMem wprev, ainvprev, esh;
-    bool has_esh = false;
+    // previous solve of the same slots: waves and 1/alpha; the local field
+    // (1/alpha) P0 of the least-squares guess, its residual field E - A P0
+    // (FP32) and the rms of that residual per slot, inputs of the learned guess
+    DevMem wprev, ainvprev, esh, rf;
+    std::vector<float> hrscale;
+    bool has_r = false;
+    // ring of the last `hdepth` solutions of every slot with their waves and
+    // 1/alpha (filled by solves with history > 0), and the scratch of the
+    // least-squares guess over it
+    DevMem hx[HIST_MAX], hwv[HIST_MAX], hainvv[HIST_MAX];
+    int hdepth = 0, hn = 0, hhead = 0;
+    DevMem pv32, pw32, pcoef, gpart;
+    std::vector<double> hgram;
+    std::vector<Cx<double>> hcoef;
     // host staging buffers of asynchronous uploads (must outlive the copies)
     std::vector<WaveDev> hw;
     std::vector<cd> hainv;  // [nr][ncomp]
@@ -414,11 +427,11 @@ dda_status ensure_group(dda_ctx* c, Group& g, const Target& t, int prec, bool* r
     const size_t v64 = vec_elems(t, nr) * sizeof(Cx<double>);
     const int kp = (prec == DDA_SOLVE_FP32_REFINE) ? DDA_FP32 : DDA_FP64;
     const size_t vk = vec_elems(t, nr) * (kp == DDA_FP32 ? sizeof(Cx<float>) : sizeof(Cx<double>));
-    void* before[24];
+    unsigned before[24];
     int nb = 0;
     DevMem* all[] = {&g.b64, &g.x64, &g.r64, &g.slab32, &g.slab64, &g.kv[0], &g.kv[1], &g.kv[2], &g.kv[3],
                      &g.kv[4], &g.kv[5], &g.kv[6], &g.kv[7], &g.state, &g.active, &g.partials};
-    for (DevMem* d : all) before[nb++] = d->p;
+    for (DevMem* d : all) before[nb++] = d->gen;
     HCHK(c, g.waves.ensure(nr * sizeof(WaveDev)));
     HCHK(c, g.ainv64.ensure((size_t)nr * t.ncomp * sizeof(Cx<double>)));
     HCHK(c, g.ainv32.ensure((size_t)nr * t.ncomp * sizeof(Cx<float>)));
@@ -442,7 +455,7 @@ dda_status ensure_group(dda_ctx* c, Group& g, const Target& t, int prec, bool* r
     HCHK(c, g.norms.ensure(nr * sizeof(double)));
     nb = 0;
     bool changed = false;
-    for (DevMem* d : all) changed |= (before[nb++] != d->p);
+    for (DevMem* d : all) changed |= (before[nb++] != d->gen);
     if (changed) {
         // zero the padded vectors once so that padding stays zero
         for (DevMem* d : {&g.b64, &g.x64, &g.r64}) HCHK(c, hipMemsetAsync(d->p, 0, d->n, c->stream));
@@ -562,6 +575,127 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
             for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st, k));
         }
     }
+    return DDA_OK;
+}
+
+// Keep the group's current solution, waves and 1/alpha in its history ring
+// (depth 0 clears the ring).
+dda_status push_history(dda_ctx* c, Group& g, const Target& t, int depth) {
+    if (depth != g.hdepth) {
+        g.hdepth = depth;
+        g.hn = 0;
+        g.hhead = 0;
+    }
+    if (depth == 0) return DDA_OK;
+    hipStream_t st = c->stream;
+    const int e = g.hhead;
+    const size_t vb = vec_elems(t, g.nr) * sizeof(Cx<double>), ab = (size_t)g.nr * t.ncomp * sizeof(Cx<double>);
+    HCHK(c, g.hx[e].ensure(vb));
+    HCHK(c, g.hwv[e].ensure(g.nr * sizeof(WaveDev)));
+    HCHK(c, g.hainvv[e].ensure(ab));
+    HCHK(c, hipMemcpyAsync(g.hx[e].p, g.x64.p, vb, hipMemcpyDeviceToDevice, st));
+    HCHK(c, hipMemcpyAsync(g.hwv[e].p, g.waves.p, g.nr * sizeof(WaveDev), hipMemcpyDeviceToDevice, st));
+    HCHK(c, hipMemcpyAsync(g.hainvv[e].p, g.ainv64.p, ab, hipMemcpyDeviceToDevice, st));
+    g.hhead = (e + 1) % depth;
+    g.hn = std::min(g.hn + 1, depth);
+    return DDA_OK;
+}
+
+// Solve the h x h normal equations G c = q (G Hermitian positive
+// semi-definite, upper triangle given) by Gaussian elimination with partial
+// pivoting after a relative diagonal shift of 1e-12.
+void solve_small(int h, const cd* Gu, const cd* q, cd* out) {
+    cd A[HIST_MAX][HIST_MAX + 1];
+    double dmax = 0;
+    for (int e = 0; e < h; ++e) dmax = std::max(dmax, std::abs(Gu[e * HIST_MAX + e]));
+    for (int e = 0; e < h; ++e) {
+        for (int f = 0; f < h; ++f) A[e][f] = e <= f ? Gu[e * HIST_MAX + f] : std::conj(Gu[f * HIST_MAX + e]);
+        A[e][e] += 1e-12 * dmax + 1e-300;
+        A[e][h] = q[e];
+    }
+    for (int k = 0; k < h; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < h; ++i)
+            if (std::abs(A[i][k]) > std::abs(A[piv][k])) piv = i;
+        for (int j = 0; j <= h; ++j) std::swap(A[k][j], A[piv][j]);
+        for (int i = k + 1; i < h; ++i) {
+            const cd f = A[i][k] / A[k][k];
+            for (int j = k; j <= h; ++j) A[i][j] -= f * A[k][j];
+        }
+    }
+    for (int k = h - 1; k >= 0; --k) {
+        cd v = A[k][h];
+        for (int j = k + 1; j < h; ++j) v -= A[k][j] * out[j];
+        out[k] = v / A[k][k];
+    }
+}
+
+// Least-squares guess over earlier solutions of the group's slots (the
+// history ring, or only the previous solution held in x64 when the ring is
+// empty): every solution is phase shifted to the current wave (as the
+// PREV_SHIFT guess), multiplied by A in FP32, and the combination minimising
+// ||E - A x|| per rhs becomes x64.  Its local field (1/alpha) x goes to g.esh,
+// its residual field to g.rf and the residual's rms per site component to
+// g.hrscale.
+dda_status project_history(dda_ctx* c, Group& g, Target& t) {
+    hipStream_t st = c->stream;
+    const bool from_last = g.hn == 0;
+    const int h = from_last ? 1 : g.hn, nr = g.nr;
+    const size_t ve = vec_elems(t, nr);
+    HCHK(c, g.pv32.ensure((size_t)HIST_MAX * ve * sizeof(Cx<float>)));
+    const unsigned w_before = g.pw32.gen;
+    HCHK(c, g.pw32.ensure((size_t)HIST_MAX * ve * sizeof(Cx<float>)));
+    // the matvec writes the sites only: zero the padding of the products once
+    if (g.pw32.gen != w_before) HCHK(c, hipMemsetAsync(g.pw32.p, 0, g.pw32.n, st));
+    HCHK(c, g.slab32.ensure(slab_elems(t, nr) * sizeof(Cx<float>)));
+    if (!t.have32) SCHK(ensure_green(c, t, DDA_FP32 | DDA_FP64));
+    const int nblk = gram_blocks(t.Npad);
+    HCHK(c, g.gpart.ensure((size_t)nr * nblk * HIST_NGRAM * 2 * sizeof(double)));
+    HCHK(c, g.pcoef.ensure((size_t)nr * HIST_MAX * sizeof(Cx<double>)));
+    Cx<float>* V = g.pv32.as<Cx<float>>();
+    Cx<float>* W = g.pw32.as<Cx<float>>();
+    HCHK(c, g.esh.ensure(ve * sizeof(Cx<float>)));
+    HCHK(c, g.rf.ensure(ve * sizeof(Cx<float>)));
+    for (int e = 0; e < h; ++e) {
+        const Cx<double>* px = from_last ? g.x64.as<Cx<double>>() : g.hx[e].as<Cx<double>>();
+        const Cx<double>* pa = from_last ? g.ainvprev.as<Cx<double>>() : g.hainvv[e].as<Cx<double>>();
+        const WaveDev* pw = from_last ? g.wprev.as<WaveDev>() : g.hwv[e].as<WaveDev>();
+        HCHK(c, launch_prev_shift(t.geo(), t.origin, nr, px, pa, g.ainv64.as<Cx<double>>(), pw, g.waves.as<WaveDev>(),
+                                  nullptr, nullptr, V + e * ve, st));
+        HCHK(c, matvec_group<float>(t, g, nr, V + e * ve, W + e * ve, nullptr, nullptr, MV_AX, st));
+    }
+    HCHK(c, launch_gram(t.Npad, nr, h, W, g.b64.as<Cx<double>>(), g.gpart.as<double>(), st));
+    g.hgram.resize((size_t)nr * nblk * HIST_NGRAM * 2);
+    HCHK(c, hipMemcpyAsync(g.hgram.data(), g.gpart.p, g.hgram.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HCHK(c, hipStreamSynchronize(st));
+    g.hcoef.assign((size_t)nr * HIST_MAX, Cx<double>{0, 0});
+    for (int s = 0; s < nr; ++s) {
+        cd acc[HIST_NGRAM];
+        for (int q = 0; q < HIST_NGRAM; ++q) acc[q] = 0;
+        for (int b = 0; b < nblk; ++b)
+            for (int q = 0; q < HIST_NGRAM; ++q) {
+                const double* p = &g.hgram[(((size_t)s * nblk + b) * HIST_NGRAM + q) * 2];
+                acc[q] += cd(p[0], p[1]);
+            }
+        cd Gu[HIST_MAX * HIST_MAX], rhs[HIST_MAX], cf[HIST_MAX];
+        int q = 0;
+        for (int e = 0; e < HIST_MAX; ++e)
+            for (int f = e; f < HIST_MAX; ++f) Gu[e * HIST_MAX + f] = acc[q++];
+        for (int e = 0; e < HIST_MAX; ++e) rhs[e] = acc[q + e];
+        solve_small(h, Gu, rhs, cf);
+        for (int e = 0; e < h; ++e) g.hcoef[(size_t)s * HIST_MAX + e] = Cx<double>{cf[e].real(), cf[e].imag()};
+    }
+    HCHK(c, hipMemcpyAsync(g.pcoef.p, g.hcoef.data(), g.hcoef.size() * sizeof(Cx<double>), hipMemcpyHostToDevice, st));
+    HCHK(c, launch_hist_combine(t.geo(), nr, h, V, g.pcoef.as<Cx<double>>(), g.x64.as<Cx<double>>(),
+                                g.ainv64.as<Cx<double>>(), g.esh.as<Cx<float>>(), W, g.b64.as<Cx<double>>(),
+                                g.rf.as<Cx<float>>(), st));
+    HCHK(c, launch_norm2<float>(t.Npad, nr, g.rf.as<Cx<float>>(), g.partials.as<double>(), g.norms.as<double>(), st));
+    std::vector<double> n2(nr);
+    HCHK(c, hipMemcpyAsync(n2.data(), g.norms.p, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    HCHK(c, hipStreamSynchronize(st));
+    g.hrscale.resize(nr);
+    for (int s = 0; s < nr; ++s) g.hrscale[s] = (float)std::max(std::sqrt(n2[s] / (3.0 * t.N)), 1e-30);
+    g.has_r = true;
     return DDA_OK;
 }
 
@@ -732,11 +866,14 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
     // an even count keeps the alternating direction buffers aligned across replays
     const int kiters = 2 * std::max(1, ((o->graph_iters > 0 ? o->graph_iters : 4) + 1) / 2);
     if (o->guess == DDA_GUESS_USER && !p0) return fail(c, DDA_ERR_INVALID_ARG, "GUESS_USER needs p0");
-    if (o->guess < DDA_GUESS_ZERO || o->guess > DDA_GUESS_PREV_SHIFT)
+    if (o->guess < DDA_GUESS_ZERO || o->guess > DDA_GUESS_PROJECT)
         return fail(c, DDA_ERR_INVALID_ARG, "unknown guess %d", o->guess);
+    if (o->history < 0 || o->history > HIST_MAX)
+        return fail(c, DDA_ERR_INVALID_ARG, "history %d outside [0, %d]", o->history, HIST_MAX);
     if (o->guess == DDA_GUESS_NN && !c->nn) return fail(c, DDA_ERR_STATE, "no learned-guess model attached");
     // PREV, PREV_SHIFT and NN start from the previous solution of each slot
-    const bool keep_prev = (o->guess == DDA_GUESS_PREV || o->guess == DDA_GUESS_PREV_SHIFT || o->guess == DDA_GUESS_NN);
+    const bool keep_prev = (o->guess == DDA_GUESS_PREV || o->guess == DDA_GUESS_PREV_SHIFT || o->guess == DDA_GUESS_NN ||
+                            o->guess == DDA_GUESS_PROJECT);
     if (keep_prev && (!c->have_solution || c->last_nrhs != nrhs))
         return fail(c, DDA_ERR_STATE, "guess %d needs a previous solve with the same number of right-hand sides",
                     o->guess);
@@ -761,7 +898,7 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
     // keep the previous waves and polarizabilities of every slot
     for (auto& gp : c->groups) {
         Group& g = *gp;
-        g.has_esh = false;
+        g.has_r = false;
         if (!keep_prev) continue;
         const Target& t = *c->tg[g.tgt];
         HCHK(c, g.wprev.ensure(g.nr * sizeof(WaveDev)));
@@ -825,19 +962,23 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
         for (auto& gp : c->groups) {
             Group& g = *gp;
             Target& t = *c->tg[g.tgt];
-            // E_sh = (1/alpha_prev) P_prev exp(i k (khat - khat_prev) . r); PREV_SHIFT
-            // takes P0 = alpha E_sh, PREV keeps P_prev, NN corrects E_sh
-            HCHK(c, g.esh.ensure(vec_elems(t, g.nr) * sizeof(Cx<float>)));
-            HCHK(c, launch_prev_shift(t.geo(), t.origin, g.nr, g.x64.as<Cx<double>>(), g.ainvprev.as<Cx<double>>(),
-                                      g.ainv64.as<Cx<double>>(), g.wprev.as<WaveDev>(), g.waves.as<WaveDev>(),
-                                      g.esh.as<Cx<float>>(),
-                                      o->guess == DDA_GUESS_PREV_SHIFT ? g.x64.as<Cx<double>>() : nullptr, st));
-            g.has_esh = true;
+            g.has_r = false;
+            // PREV keeps P_prev; PREV_SHIFT carries it to the new direction,
+            // P0 = (1/alpha_prev) P_prev exp(i k (khat - khat_prev) . r) / (1/alpha);
+            // PROJECT takes the least-squares combination of such shifted
+            // solutions; NN corrects the PROJECT guess
+            if (o->guess == DDA_GUESS_PREV_SHIFT)
+                HCHK(c, launch_prev_shift(t.geo(), t.origin, g.nr, g.x64.as<Cx<double>>(), g.ainvprev.as<Cx<double>>(),
+                                          g.ainv64.as<Cx<double>>(), g.wprev.as<WaveDev>(), g.waves.as<WaveDev>(),
+                                          nullptr, g.x64.as<Cx<double>>(), nullptr, st));
+            if (o->guess != DDA_GUESS_PROJECT && o->guess != DDA_GUESS_NN) continue;
+            SCHK(project_history(c, g, t));
             if (o->guess != DDA_GUESS_NN) continue;
             std::vector<dda_wave> gw(g.nr);
             for (int s = 0; s < g.nr; ++s) gw[s] = waves[g.idx[s]];
             hipError_t e = nn_guess_group(c->nn, site_view(t), gw.data(), reinterpret_cast<const double*>(g.hainv.data()),
-                                          g.nr, g.esh.as<Cx<float>>(), g.x64.as<Cx<double>>(), st);
+                                          g.nr, g.esh.as<Cx<float>>(), g.rf.as<Cx<float>>(), g.hrscale.data(),
+                                          g.x64.as<Cx<double>>(), st);
             if (e == hipErrorNotSupported)
                 return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "learned guess needs a cubic box with side divisible by 16");
             HCHK(c, e);
@@ -909,8 +1050,8 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
                 double rr = h[s];
                 double rl = bb[i] > 0 ? std::sqrt(rr / bb[i]) : 0.0;
                 if (it_out == 0) {
-                    if (guessed && rl > 1.0 && !(o->flags & DDA_NO_FALLBACK)) {
-                        // the guess is worse than P0 = 0: fall back to it
+                    if (guessed && !(rl <= 1.0) && !(o->flags & DDA_NO_FALLBACK)) {
+                        // the guess is worse than P0 = 0 (or not finite): fall back to it
                         const size_t off = (size_t)s * 3 * t.Npad;
                         HCHK(c, launch_fill<double>(g.x64.as<Cx<double>>() + off, (size_t)3 * t.Npad, st));
                         HCHK(c, hipMemcpyAsync(g.r64.as<Cx<double>>() + off, g.b64.as<Cx<double>>() + off,
@@ -923,6 +1064,11 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
                 rel[i] = rl;
                 if (rl <= tol || bb[i] == 0) {
                     done[i] = 1;
+                    continue;
+                }
+                if (!std::isfinite(rl)) {  // breakdown: no further refinement can help
+                    done[i] = 1;
+                    stat[i] = DDA_WARN_NOT_CONVERGED;
                     continue;
                 }
                 if (iters[i] >= max_iter || it_out == max_outer) {
@@ -1014,6 +1160,7 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
     c->ms_total = mst;
     c->have_solution = true;
     c->last_waves.assign(waves, waves + nrhs);
+    for (auto& gp : c->groups) SCHK(push_history(c, *gp, *c->tg[gp->tgt], o->history));
     int any_nc = 0;
     for (int i = 0; i < nrhs; ++i) {
         if (stats) {
@@ -1269,9 +1416,8 @@ dda_status dda_nn_record(dda_ctx* c, dda_nn* nn) {
     if (!nn) return fail(c, DDA_ERR_INVALID_ARG, "nn_record: null network");
     if (!c->have_solution) return fail(c, DDA_ERR_STATE, "nn_record before a solve");
     for (auto& gp : c->groups)
-        if (!gp->has_esh)
-            return fail(c, DDA_ERR_STATE, "nn_record needs a solve started from the previous solution "
-                                          "(guess PREV, PREV_SHIFT or NN)");
+        if (!gp->has_r)
+            return fail(c, DDA_ERR_STATE, "nn_record needs a solve with guess PROJECT or NN");
     for (int i = 0; i < c->last_nrhs; ++i) {
         Group& g = *c->groups[c->rhs_group[i]];
         Target& t = *c->tg[g.tgt];
@@ -1279,7 +1425,8 @@ dda_status dda_nn_record(dda_ctx* c, dda_nn* nn) {
         hipError_t e = nn_record_one(nn, site_view(t), c->last_waves[i],
                                      reinterpret_cast<const double*>(g.hainv.data()) + (size_t)s * 2 * t.ncomp,
                                      g.x64.as<Cx<double>>() + (size_t)s * 3 * t.Npad,
-                                     g.esh.as<Cx<float>>() + (size_t)s * 3 * t.Npad, c->stream);
+                                     g.esh.as<Cx<float>>() + (size_t)s * 3 * t.Npad,
+                                     g.rf.as<Cx<float>>() + (size_t)s * 3 * t.Npad, g.hrscale[s], c->stream);
         if (e == hipErrorNotSupported)
             return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "nn_record: needs a cubic box with side divisible by 16");
         if (e == hipErrorInvalidValue) return fail(c, DDA_ERR_INVALID_ARG, "nn_record: all samples must share one box size");

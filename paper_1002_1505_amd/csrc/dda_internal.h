@@ -169,11 +169,24 @@ hipError_t launch_ampl(const Geo& g, const double* origin3, double k, int nrhs, 
 hipError_t configure_fft_kernels();
 
 // Previous local field (1/alpha_prev) P_prev carried to the new incidence
-// direction (FP32 esh); when p0 != nullptr also P0 = esh / (1/alpha_new).
-struct WaveDev;
+// direction: optional outputs esh (the field, FP32), p0 = esh / (1/alpha_new)
+// (FP64, may alias Pprev) and v32 (the same guess in FP32).
 hipError_t launch_prev_shift(const Geo& g, const double* origin, int nrhs, const Cx<double>* Pprev,
                              const Cx<double>* ainv_prev, const Cx<double>* ainv_new, const WaveDev* wprev,
-                             const WaveDev* wnew, Cx<float>* esh, Cx<double>* p0, hipStream_t st);
+                             const WaveDev* wnew, Cx<float>* esh, Cx<double>* p0, Cx<float>* v32, hipStream_t st);
+// Least-squares combination of up to 4 basis vectors per rhs: block partials
+// [rhs][gram_blocks][14] complex of <W_e, W_f> (e <= f, row-major upper
+// triangle of the 4 x 4 matrix) then <W_e, b>; W, V are [h][nrhs][3][Npad].
+constexpr int HIST_MAX = 4;
+constexpr int HIST_NGRAM = HIST_MAX * (HIST_MAX + 1) / 2 + HIST_MAX;
+int gram_blocks(int Npad);
+hipError_t launch_gram(int Npad, int nrhs, int h, const Cx<float>* W, const Cx<double>* b, double* partials,
+                       hipStream_t st);
+// x64 = sum_e coef[rhs][e] V[e] (coef: [nrhs][4] complex); esh = (1/alpha) x64
+// and rf = b - sum_e coef[rhs][e] W[e] (FP32) where given.
+hipError_t launch_hist_combine(const Geo& g, int nrhs, int h, const Cx<float>* V, const Cx<double>* coef,
+                               Cx<double>* x64, const Cx<double>* ainv, Cx<float>* esh, const Cx<float>* W,
+                               const Cx<double>* b, Cx<float>* rf, hipStream_t st);
 
 // Raise a kernel's dynamic-LDS limit to the 160 KB of a gfx950 CU minus the
 // kernel's static LDS (the attribute value is ignored beyond that).

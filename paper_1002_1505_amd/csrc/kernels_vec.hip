@@ -430,12 +430,14 @@ __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, doubl
 }
 
 // Previous local field carried to the new incidence direction:
-//   esh_j = (1/alpha_prev) P_prev,j exp(i k (khat - khat_prev) . r_j)   (FP32 out),
-// and optionally P0_j = esh_j / (1/alpha_new) (FP64 out).
-__global__ void k_prev_shift(Geo g, double ox, double oy, double oz, const Cx<double>* __restrict__ Pprev,
+//   esh_j = (1/alpha_prev) P_prev,j exp(i k (khat - khat_prev) . r_j),
+// written (each output optional) as the field esh (FP32), as the guess
+// P0_j = esh_j / (1/alpha_new) in FP64 (p0) or in FP32 (v32).  p0 may alias
+// Pprev: every element is read and written by the same thread.
+__global__ void k_prev_shift(Geo g, double ox, double oy, double oz, const Cx<double>* Pprev,
                              const Cx<double>* __restrict__ ainv_prev, const Cx<double>* __restrict__ ainv_new,
                              const WaveDev* __restrict__ wprev, const WaveDev* __restrict__ wnew,
-                             Cx<float>* __restrict__ esh, Cx<double>* __restrict__ p0) {
+                             Cx<float>* __restrict__ esh, Cx<double>* p0, Cx<float>* __restrict__ v32) {
     const int rhs = blockIdx.y;
     const WaveDev a = wprev[rhs], b = wnew[rhs];
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.Npad; j += gridDim.x * blockDim.x) {
@@ -455,8 +457,91 @@ __global__ void k_prev_shift(Geo g, double ox, double oy, double oz, const Cx<do
         for (int c = 0; c < 3; ++c) {
             const size_t i = ((size_t)rhs * 3 + c) * g.Npad + j;
             const Cx<double> e = (ap * Pprev[i]) * ph;
-            esh[i] = Cx<float>{(float)e.re, (float)e.im};
-            if (p0) p0[i] = Cx<double>{(e.re * an.re + e.im * an.im) / dn, (e.im * an.re - e.re * an.im) / dn};
+            const Cx<double> q = {(e.re * an.re + e.im * an.im) / dn, (e.im * an.re - e.re * an.im) / dn};
+            if (esh) esh[i] = Cx<float>{(float)e.re, (float)e.im};
+            if (p0) p0[i] = q;
+            if (v32) v32[i] = Cx<float>{(float)q.re, (float)q.im};
+        }
+    }
+}
+
+// Normal equations of min || b - sum_e c_e W_e || per rhs over h <= 4 basis
+// vectors: partial sums of <W_e, W_f> (e <= f) and <W_e, b> per block,
+// written to partials[rhs][blockIdx.x][14] complex.  W is [h][nrhs][V].
+constexpr int MAXH = HIST_MAX;
+constexpr int NGRAM = HIST_NGRAM;
+__global__ void __launch_bounds__(VT) k_gram_part(int V, int nrhs, int h, const Cx<float>* __restrict__ W,
+                                                  const Cx<double>* __restrict__ b, double* __restrict__ partials) {
+    const int rhs = blockIdx.y;
+    double2 acc[NGRAM];
+#pragma unroll
+    for (int q = 0; q < NGRAM; ++q) acc[q] = double2{0, 0};
+    const size_t es = (size_t)nrhs * V, o = (size_t)rhs * V;
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i >= V) continue;
+        Cx<float> w[MAXH];
+#pragma unroll
+        for (int e = 0; e < MAXH; ++e) w[e] = e < h ? W[e * es + o + i] : Cx<float>{0, 0};
+        const Cx<double> bi = b[o + i];
+        int q = 0;
+#pragma unroll
+        for (int e = 0; e < MAXH; ++e) {
+#pragma unroll
+            for (int f = e; f < MAXH; ++f) acc_dot(acc[q++], w[e], w[f]);
+            acc_dot(acc[MAXH * (MAXH + 1) / 2 + e], Cx<double>{w[e].re, w[e].im}, bi);
+        }
+    }
+    __shared__ double sh[16];
+    for (int q = 0; q < NGRAM; ++q) {
+        const double re = block_sum(acc[q].x, sh);
+        const double im = block_sum(acc[q].y, sh);
+        if (threadIdx.x == 0) {
+            double* out = partials + (((size_t)rhs * gridDim.x + blockIdx.x) * NGRAM + q) * 2;
+            out[0] = re;
+            out[1] = im;
+        }
+    }
+}
+
+// x64 = sum_e c[rhs][e] V[e] (FP32 basis, FP64 result); when esh is given also
+// the local field esh = (1/alpha) x (FP32); when rf is given also the
+// residual field rf = b - sum_e c[rhs][e] W[e] (FP32, W[e] = A V[e]).
+__global__ void __launch_bounds__(VT) k_hist_combine(Geo g, int nrhs, int h, const Cx<float>* __restrict__ Vb,
+                                                     const Cx<double>* __restrict__ coef, Cx<double>* __restrict__ x64,
+                                                     const Cx<double>* __restrict__ ainv, Cx<float>* __restrict__ esh,
+                                                     const Cx<float>* __restrict__ Wb, const Cx<double>* __restrict__ b,
+                                                     Cx<float>* __restrict__ rf) {
+    const int rhs = blockIdx.y;
+    const size_t V = (size_t)3 * g.Npad, es = (size_t)nrhs * V, o = (size_t)rhs * V;
+    Cx<double> c[MAXH];
+#pragma unroll
+    for (int e = 0; e < MAXH; ++e) c[e] = e < h ? coef[rhs * MAXH + e] : Cx<double>{0, 0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += (size_t)gridDim.x * blockDim.x) {
+        Cx<double> acc = {0, 0};
+#pragma unroll
+        for (int e = 0; e < MAXH; ++e)
+            if (e < h) {
+                const Cx<float> v = Vb[e * es + o + i];
+                acc = acc + c[e] * Cx<double>{v.re, v.im};
+            }
+        x64[o + i] = acc;
+        if (rf) {
+            Cx<double> ax = {0, 0};
+#pragma unroll
+            for (int e = 0; e < MAXH; ++e)
+                if (e < h) {
+                    const Cx<float> w = Wb[e * es + o + i];
+                    ax = ax + c[e] * Cx<double>{w.re, w.im};
+                }
+            const Cx<double> rr = b[o + i] - ax;
+            rf[o + i] = Cx<float>{(float)rr.re, (float)rr.im};
+        }
+        if (esh) {
+            const int j = (int)(i % g.Npad);
+            const Cx<double> a = j < g.N ? ainv[(size_t)rhs * g.ncomp + g.site_comp[j]] : Cx<double>{0, 0};
+            const Cx<double> e = a * acc;
+            esh[o + i] = Cx<float>{(float)e.re, (float)e.im};
         }
     }
 }
@@ -465,9 +550,29 @@ __global__ void k_prev_shift(Geo g, double ox, double oy, double oz, const Cx<do
 
 hipError_t launch_prev_shift(const Geo& g, const double* origin, int nrhs, const Cx<double>* Pprev,
                              const Cx<double>* ainv_prev, const Cx<double>* ainv_new, const WaveDev* wprev,
-                             const WaveDev* wnew, Cx<float>* esh, Cx<double>* p0, hipStream_t st) {
+                             const WaveDev* wnew, Cx<float>* esh, Cx<double>* p0, Cx<float>* v32, hipStream_t st) {
     hipLaunchKernelGGL(k_prev_shift, dim3((g.Npad + 255) / 256, nrhs), dim3(256), 0, st, g, origin[0], origin[1],
-                       origin[2], Pprev, ainv_prev, ainv_new, wprev, wnew, esh, p0);
+                       origin[2], Pprev, ainv_prev, ainv_new, wprev, wnew, esh, p0, v32);
+    return hipGetLastError();
+}
+
+int gram_blocks(int Npad) { return (3 * Npad + VB - 1) / VB; }
+
+hipError_t launch_gram(int Npad, int nrhs, int h, const Cx<float>* W, const Cx<double>* b, double* partials,
+                       hipStream_t st) {
+    if (h < 1 || h > MAXH) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gram_part, dim3(gram_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, nrhs, h, W, b,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_combine(const Geo& g, int nrhs, int h, const Cx<float>* V, const Cx<double>* coef,
+                               Cx<double>* x64, const Cx<double>* ainv, Cx<float>* esh, const Cx<float>* W,
+                               const Cx<double>* b, Cx<float>* rf, hipStream_t st) {
+    if (h < 1 || h > MAXH) return hipErrorInvalidValue;
+    if (rf && (!W || !b)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_hist_combine, dim3((3 * g.Npad + VT - 1) / VT, nrhs), dim3(VT), 0, st, g, nrhs, h, V, coef,
+                       x64, ainv, esh, W, b, rf);
     return hipGetLastError();
 }
 

@@ -2,14 +2,17 @@
 // on the target's n x n x n box, trained on the GPU by its own BF16 MFMA
 // kernels (FP32 accumulate, FP32 master weights, Adam).
 //
-// The network refines the previous orientation's solution.  With E_sh the
-// previous local field (1/alpha) P_prev carried to the new incidence
-// direction by the phase factor exp(i k (khat - khat_prev) . r), the guess is
-//   E_loc = E_sh + net(features),  P0 = alpha E_loc = E_loc / (1/alpha).
+// The network corrects a plain guess built from earlier solutions of a sweep
+// (their least-squares combination, each carried to the new incidence
+// direction).  With E_b = (1/alpha) P_b the local field of that guess, R its
+// residual field E_inc - A P_b and sigma the rms of R over the sites,
+//   E_loc = E_b + sigma net(features),  P0 = alpha E_loc = E_loc / (1/alpha),
+// so the network acts as a learned approximate inverse of A applied once to
+// the scale-free residual R / sigma.
 // Input features per voxel (16 channels, zero outside the target):
-//   occupancy, Re/Im E_inc (3 components), Re/Im E_sh (3 components),
+//   occupancy, Re/Im R / sigma (3 components), Re/Im E_b (3 components),
 //   Re/Im (eps-1)/(eps+2), k d.
-// A network of zeros reproduces the phase-shifted previous solution.
+// A network of zeros reproduces the plain guess.
 //
 // Layers: 3x3x3 convolutions with dilation, ReLU after all but the last.
 // Activations are channels-last BF16 [sample][voxel][channel].
@@ -262,8 +265,11 @@ struct SampleDev {
     const uint8_t* site_comp;
     const double* kfac;  // Re/Im (eps-1)/(eps+2) per composition
     const double* ainv;  // Re/Im 1/alpha per composition
-    const float* resid;  // [3][Npad] complex: E_loc - E_sh (training target) or nullptr
-    const float* esh;    // [3][Npad] complex: phase-shifted previous local field
+    const float* resid;  // [3][Npad] complex: (E_loc - E_b) / sigma (training target) or nullptr
+    const float* esh;    // [3][Npad] complex: local field E_b of the plain guess
+    const float* rf;     // [3][Npad] complex: residual field R of the plain guess
+    float rscale;        // sigma
+    float pad_;
 };
 
 __global__ void k_zero16(uint16_t* __restrict__ p, size_t n) {
@@ -278,13 +284,12 @@ __global__ void k_features(const SampleDev* __restrict__ sd, int D, uint16_t* __
         const uint32_t q = S.site_xyz[j];
         const int x = q & 1023, y = (q >> 10) & 1023, z = q >> 20;
         const int c = S.site_comp[j];
-        double sn, cs;
-        sincos(S.kd * (S.khat[0] * (x - S.ox) + S.khat[1] * (y - S.oy) + S.khat[2] * (z - S.oz)), &sn, &cs);
+        const float inv = 1.0f / S.rscale;
         float f[16];
         f[0] = 1.0f;
         for (int a = 0; a < 3; ++a) {
-            f[1 + 2 * a] = (float)(S.e[2 * a] * cs - S.e[2 * a + 1] * sn);
-            f[2 + 2 * a] = (float)(S.e[2 * a] * sn + S.e[2 * a + 1] * cs);
+            f[1 + 2 * a] = S.rf[(size_t)(2 * a) * S.Npad + 2 * j] * inv;
+            f[2 + 2 * a] = S.rf[(size_t)(2 * a) * S.Npad + 2 * j + 1] * inv;
             f[7 + 2 * a] = S.esh[(size_t)(2 * a) * S.Npad + 2 * j];
             f[8 + 2 * a] = S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1];
         }
@@ -324,7 +329,7 @@ __global__ void k_loss(const SampleDev* __restrict__ sd, int D, const float* __r
     if (threadIdx.x == 0) atomicAdd(loss_acc + s, num);
 }
 
-// Guess P0 = (E_sh + out) / (1/alpha) into x64 ([3][Npad] complex128 of rhs slot).
+// Guess P0 = (E_b + sigma out) / (1/alpha) into x64 ([3][Npad] complex128 of rhs slot).
 __global__ void k_guess(const SampleDev* __restrict__ sd, int D, const float* __restrict__ out, Cx<double>* __restrict__ x64) {
     const int s = blockIdx.y;
     const SampleDev S = sd[s];
@@ -337,15 +342,15 @@ __global__ void k_guess(const SampleDev* __restrict__ sd, int D, const float* __
         const double ar = S.ainv[2 * c], ai = S.ainv[2 * c + 1];
         const double den = ar * ar + ai * ai;
         for (int a = 0; a < 3; ++a) {
-            const double er = S.esh[(size_t)(2 * a) * S.Npad + 2 * j] + out[vi * 16 + 2 * a];
-            const double ei = S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1] + out[vi * 16 + 2 * a + 1];
+            const double er = S.esh[(size_t)(2 * a) * S.Npad + 2 * j] + (double)S.rscale * out[vi * 16 + 2 * a];
+            const double ei = S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1] + (double)S.rscale * out[vi * 16 + 2 * a + 1];
             // (er + i ei) / (ar + i ai)
             x64[((size_t)s * 3 + a) * S.Npad + j] = Cx<double>{(er * ar + ei * ai) / den, (ei * ar - er * ai) / den};
         }
     }
 }
 
-// Training target: resid = (1/alpha) P - E_sh from a solution in [3][Npad] complex128.
+// Training target: resid = ((1/alpha) P - E_b) / sigma from a solution in [3][Npad] complex128.
 __global__ void k_record(const SampleDev* __restrict__ sd, const Cx<double>* __restrict__ P, float* __restrict__ resid) {
     const SampleDev S = sd[0];
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < S.N; j += gridDim.x * blockDim.x) {
@@ -354,8 +359,10 @@ __global__ void k_record(const SampleDev* __restrict__ sd, const Cx<double>* __r
         for (int a = 0; a < 3; ++a) {
             const Cx<double> p = P[(size_t)a * S.Npad + j];
             const double lr = ar * p.re - ai * p.im, li = ar * p.im + ai * p.re;
-            resid[(size_t)(2 * a) * S.Npad + 2 * j] = (float)(lr - S.esh[(size_t)(2 * a) * S.Npad + 2 * j]);
-            resid[(size_t)(2 * a) * S.Npad + 2 * j + 1] = (float)(li - S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1]);
+            const double inv = 1.0 / S.rscale;
+            resid[(size_t)(2 * a) * S.Npad + 2 * j] = (float)((lr - S.esh[(size_t)(2 * a) * S.Npad + 2 * j]) * inv);
+            resid[(size_t)(2 * a) * S.Npad + 2 * j + 1] =
+                (float)((li - S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1]) * inv);
         }
     }
 }
@@ -425,7 +432,7 @@ struct Layer {
 struct Sample {
     int tgt;  // target id in the context at recording time
     SampleDev dev;
-    std::shared_ptr<DBuf> resid, esh;
+    std::shared_ptr<DBuf> resid, esh, rf;
 };
 
 #define NCHK(x)                                   \
@@ -627,6 +634,9 @@ hipError_t nn_make_sample_dev(const NnSiteView& t, const dda_wave& w, const doub
     sd.ainv = kfac_ainv.as<double>() + 2 * t.ncomp;
     sd.resid = nullptr;
     sd.esh = nullptr;
+    sd.rf = nullptr;
+    sd.rscale = 1.0f;
+    sd.pad_ = 0.0f;
     return hipSuccess;
 }
 
@@ -653,7 +663,8 @@ static void drop_store(const dda_nn* nn) {
 
 // Record one solution (x64 slot of [3][Npad] complex128) as a training sample.
 hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, const double* ainv,
-                         const Cx<double>* x64, const Cx<float>* esh, hipStream_t st) {
+                         const Cx<double>* x64, const Cx<float>* esh, const Cx<float>* rf, float rscale,
+                         hipStream_t st) {
     if (tv.n1 != tv.n2 || tv.n2 != tv.n3 || tv.n1 % 16) return hipErrorNotSupported;
     if (nn->box && nn->box != tv.n1) return hipErrorInvalidValue;
     nn->box = tv.n1;
@@ -688,6 +699,11 @@ hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, co
     NCHK(eb->ensure((size_t)6 * t.Npad * sizeof(float)));
     NCHK(hipMemcpyAsync(eb->p, esh, (size_t)6 * t.Npad * sizeof(float), hipMemcpyDeviceToDevice, st));
     S.dev.esh = eb->as<float>();
+    auto fb = std::make_shared<DBuf>();
+    NCHK(fb->ensure((size_t)6 * t.Npad * sizeof(float)));
+    NCHK(hipMemcpyAsync(fb->p, rf, (size_t)6 * t.Npad * sizeof(float), hipMemcpyDeviceToDevice, st));
+    S.dev.rf = fb->as<float>();
+    S.dev.rscale = rscale;
     DBuf one;
     NCHK(one.ensure(sizeof(SampleDev)));
     NCHK(hipMemcpyAsync(one.p, &S.dev, sizeof(SampleDev), hipMemcpyHostToDevice, st));
@@ -697,6 +713,7 @@ hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, co
     S.dev.resid = rb->as<float>();
     S.resid = rb;
     S.esh = eb;
+    S.rf = fb;
     store.aux.push_back(kb);
     nn->samples.push_back(S);
     return hipSuccess;
@@ -704,7 +721,8 @@ hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, co
 
 // Guesses P0 for nr right-hand sides of one target into x64 ([rhs][3][Npad] complex128).
 hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves, const double* ainv, int nr,
-                          const Cx<float>* esh, Cx<double>* x64, hipStream_t st) {
+                          const Cx<float>* esh, const Cx<float>* rf, const float* rscale, Cx<double>* x64,
+                          hipStream_t st) {
     if (t.n1 != t.n2 || t.n2 != t.n3 || t.n1 % 16) return hipErrorNotSupported;
     const int D = t.n1;
     const int chunk = 4;
@@ -717,6 +735,8 @@ hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves
         for (int k = 0; k < nb; ++k) {
             NCHK(nn_make_sample_dev(t, waves[s0 + k], ainv + (size_t)(s0 + k) * 2 * t.ncomp, sds[k], kb[k]));
             sds[k].esh = reinterpret_cast<const float*>(esh + (size_t)(s0 + k) * 3 * t.Npad);
+            sds[k].rf = reinterpret_cast<const float*>(rf + (size_t)(s0 + k) * 3 * t.Npad);
+            sds[k].rscale = rscale[s0 + k];
         }
         NCHK(hipMemcpyAsync(nn->sdev.p, sds.data(), nb * sizeof(SampleDev), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, nn->act[0].as<uint16_t>(), V * nb * 16);
@@ -761,7 +781,7 @@ dda_status dda_nn_create(dda_ctx* ctx, const dda_nn_config* cfg, dda_nn** out) {
     }
     nn->nparams = off;
     // He-style initialisation; the last layer starts at zero so that the
-    // untrained network reproduces P0 = alpha E_inc.
+    // untrained network reproduces the plain guess.
     std::vector<float> h(off, 0.0f);
     std::mt19937 rng(cfg->seed);
     for (size_t l = 0; l + 1 < nn->layers.size(); ++l) {

@@ -74,10 +74,10 @@ def _sweep_waves(count, beta=0.3, phi=0.2):
     return out
 
 
-def test_zero_network_reproduces_shifted_guess_and_state_errors():
+def test_zero_network_reproduces_projected_guess_and_state_errors():
     """The network starts with a zero last layer, so its guess is the
-    phase-shifted previous solution; the learned guess and recording need a
-    previous solution."""
+    least-squares guess it corrects; the learned guess needs a previous
+    solution and recording needs a PROJECT or NN solve."""
     import synth
     import paper_1002_1505_amd as P
 
@@ -89,16 +89,23 @@ def test_zero_network_reproduces_shifted_guess_and_state_errors():
     with pytest.raises(P.DDAError):
         ctx.solve(*sw[0], guess=P.DDA_GUESS_NN, want_p=False)
     ctx.solve(*sw[0], prec=P.DDA_SOLVE_FP64, tol=1e-10, want_p=False)
+    ctx.solve(*sw[1], prec=P.DDA_SOLVE_FP64, tol=1e-10, want_p=False, guess=P.DDA_GUESS_PREV_SHIFT)
     with pytest.raises(P.DDAError):
         net.record()
     res = {}
-    for name, g in (("shift", P.DDA_GUESS_PREV_SHIFT), ("nn", P.DDA_GUESS_NN)):
-        ctx.solve(*sw[0], prec=P.DDA_SOLVE_FP64, tol=1e-10, want_p=False)
-        _, st, _ = ctx.solve(*sw[1], prec=P.DDA_SOLVE_FP64, tol=1e-5, guess=g, want_p=False)
-        res[name] = [s["guess_resid"] for s in st]
-        assert all(s["rel_resid"] <= 1e-5 for s in st)
-    for a, b in zip(res["nn"], res["shift"]):
-        assert a < 1.0 and abs(a - b) <= 1e-5 * b + 1e-7, (a, b)
+    for name, g in (("project", P.DDA_GUESS_PROJECT), ("nn", P.DDA_GUESS_NN)):
+        for hist in (0, 2):
+            ctx.solve(*sw[0], prec=P.DDA_SOLVE_FP64, tol=1e-10, want_p=False, history=hist)
+            ctx.solve(*sw[1], prec=P.DDA_SOLVE_FP64, tol=1e-10, want_p=False, history=hist,
+                      guess=P.DDA_GUESS_PREV)
+            _, st, _ = ctx.solve(*sw[2], prec=P.DDA_SOLVE_FP64, tol=1e-5, guess=g, want_p=False, history=hist)
+            res[name, hist] = [s["guess_resid"] for s in st]
+            assert all(s["rel_resid"] <= 1e-5 for s in st)
+    for hist in (0, 2):
+        for a, b in zip(res["nn", hist], res["project", hist]):
+            assert a < 1.0 and abs(a - b) <= 1e-5 * b + 1e-7, (hist, a, b)
+    # two earlier solutions span a better guess than the previous one alone
+    assert sum(res["project", 2]) < sum(res["project", 0])
     net.record()
     assert net.num_samples == 2
     net.close()
@@ -106,9 +113,10 @@ def test_zero_network_reproduces_shifted_guess_and_state_errors():
 
 
 def test_training_lowers_guess_residual_on_its_sweep():
-    """Record the solutions of a 12-orientation sweep of a porous aggregate,
-    train, then run the sweep again: the learned guess starts closer to the
-    solution than the phase-shifted previous solution it corrects."""
+    """Record the solutions of a 12-orientation sweep of a porous aggregate
+    (least-squares guesses over a history of 2), train, then run the sweep
+    again: the learned guess starts closer to the solution than the
+    least-squares guess it corrects."""
     import synth
     import paper_1002_1505_amd as P
 
@@ -117,9 +125,9 @@ def test_training_lowers_guess_residual_on_its_sweep():
     ctx.set_target(occ, [1.5 + 0.05j], 0.8, P.DDA_ALPHA_LDR)
     net = P.Net(ctx, width=16, depth=4, seed=7)
     sw = _sweep_waves(12)
-    ctx.solve(*sw[0], want_p=False)
+    ctx.solve(*sw[0], want_p=False, history=2)
     for w in sw[1:]:
-        ctx.solve(*w, guess=P.DDA_GUESS_PREV_SHIFT, want_p=False)
+        ctx.solve(*w, guess=P.DDA_GUESS_PROJECT, want_p=False, history=2)
         net.record()
     assert net.num_samples == 22
     first = net.train(epochs=1, batch=2, lr=2e-3)
@@ -127,14 +135,14 @@ def test_training_lowers_guess_residual_on_its_sweep():
     assert last < 0.8 * first, (first, last)
     net.attach()
     res = {}
-    for name, g in (("shift", P.DDA_GUESS_PREV_SHIFT), ("nn", P.DDA_GUESS_NN)):
-        ctx.solve(*sw[0], want_p=False)
+    for name, g in (("project", P.DDA_GUESS_PROJECT), ("nn", P.DDA_GUESS_NN)):
+        ctx.solve(*sw[0], want_p=False, history=2)
         r = []
         for w in sw[1:]:
-            _, st, _ = ctx.solve(*w, guess=g, want_p=False)
+            _, st, _ = ctx.solve(*w, guess=g, want_p=False, history=2)
             assert all(s["rel_resid"] <= 1e-5 for s in st)
             r += [s["guess_resid"] for s in st]
         res[name] = np.mean(r)
-    assert res["nn"] < res["shift"], res
+    assert res["nn"] < res["project"], res
     net.close()
     ctx.close()

@@ -263,3 +263,36 @@ def test_shifted_previous_guess_vs_oracle(ctx):
             assert st[l]["rel_resid"] <= 1e-5
     # on this sweep step the phase shift improves on the unshifted previous solution
     assert sum(expect["shift"]) < sum(expect["prev"])
+
+
+def test_projected_history_guess_vs_oracle(ctx):
+    """Least-squares guess over the last three solutions of a sweep (history
+    3): the GPU guess residual (FP32 basis and products, FP64 residual) equals
+    the oracle's residual of its own projection."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.ellipsoid_occupancy((12, 16, 10), (11.0, 15.0, 9.5))
+    m, kd = [1.5 + 0.05j], 0.5
+    r, comp = _setup(ctx, occ, m, kd, dda.ALPHA_LDR)
+    sweep = [dda.waves_for_orientation(0.4, th, 0.3) for th in (0.6, 0.75, 0.9, 1.05)]
+    hist = [[], []]
+    for kh, es, _ in sweep[:3]:
+        for l in range(2):
+            a = dda.site_inverse_polarizability(comp, m, kd, dda.ALPHA_LDR, kh, es[l])
+            hist[l].append((dda.solve_dense(r, kd, a, dda.incident_field(r, kd, kh, es[l])), a, kh))
+    kn, en, _ = sweep[3]
+    expect = []
+    for l in range(2):
+        an = dda.site_inverse_polarizability(comp, m, kd, dda.ALPHA_LDR, kn, en[l])
+        En = dda.incident_field(r, kd, kn, en[l])
+        P0, _ = dda.projected_history_guess(r, kd, an, kn, En, hist[l])
+        expect.append(np.linalg.norm(En - dda.matvec_direct(r, kd, an, P0)) / np.linalg.norm(En))
+    for i, (kh, es, _) in enumerate(sweep[:3]):
+        ctx.solve([kh, kh], es, prec=P.DDA_SOLVE_FP64, tol=1e-11, want_p=False, history=3,
+                  guess=P.DDA_GUESS_ZERO if i == 0 else P.DDA_GUESS_PREV)
+    _, st, _ = ctx.solve([kn, kn], en, prec=P.DDA_SOLVE_FP64, tol=1e-5, guess=P.DDA_GUESS_PROJECT, history=3)
+    for l in range(2):
+        assert abs(st[l]["guess_resid"] - expect[l]) <= 1e-7 + 1e-5 * expect[l], (l, st[l], expect[l])
+        assert st[l]["rel_resid"] <= 1e-5
+    with pytest.raises(P.DDAError):
+        ctx.solve([kn, kn], en, guess=P.DDA_GUESS_PROJECT, history=5)

@@ -236,3 +236,35 @@ def test_shifted_guess_same_wave_and_static_limit():
         En = dda.incident_field(r, k, kn, e)
         rel = np.linalg.norm(En.reshape(-1) - dda.dense_matrix(r, k, ainv) @ P0.reshape(-1)) / np.linalg.norm(En)
         assert rel < bound
+
+
+def test_projected_guess_recovers_solution_in_span_and_is_optimal():
+    """If the history holds the new wave's own solution the projection returns
+    it; with one basis vector the coefficient is the closed form <w,E>/<w,w>;
+    the projection's residual is never above that of any single basis vector."""
+    occ = synth.ellipsoid_occupancy((5, 6, 4), (5.0, 6.0, 4.0))
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    k, m = 0.7, [1.4 + 0.1j]
+    waves = [dda.waves_for_orientation(0.2, th, 0.5) for th in (0.6, 0.75, 0.9, 1.05)]
+    sols = []
+    for kh, es, _ in waves:
+        a = dda.site_inverse_polarizability(comp, m, k, dda.ALPHA_LDR, kh, es[0])
+        sols.append((dda.solve_dense(r, k, a, dda.incident_field(r, k, kh, es[0])), a, kh))
+    kn, en, _ = waves[3]
+    an = sols[3][1]
+    En = dda.incident_field(r, k, kn, en[0])
+
+    def res(P0):
+        return np.linalg.norm(En - dda.matvec_direct(r, k, an, P0)) / np.linalg.norm(En)
+
+    P0, c = dda.projected_history_guess(r, k, an, kn, En, sols[:3] + [sols[3]])
+    assert res(P0) < 1e-10 and abs(c[3] - 1) < 1e-8
+    P1, c1 = dda.projected_history_guess(r, k, an, kn, En, sols[2:3])
+    _, v = dda.shifted_previous_guess(r, k, *sols[2][:2], an, sols[2][2], kn)
+    w = dda.matvec_direct(r, k, an, v).reshape(-1)
+    assert np.isclose(c1[0], np.vdot(w, En.reshape(-1)) / np.vdot(w, w), rtol=1e-10)
+    P3, _ = dda.projected_history_guess(r, k, an, kn, En, sols[:3])
+    for P, a, kh in sols[:3]:
+        _, v = dda.shifted_previous_guess(r, k, P, a, an, kh, kn)
+        assert res(P3) <= res(v) + 1e-14
+    assert res(P3) < res(P1)
