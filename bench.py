@@ -127,9 +127,10 @@ def main():
     ms, by = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP32, reps=20)
     sh = ctx.get_shape(0, P.DDA_FP32)
     if sh["ct"] & 1:
-        names = [f"k_pfwd_ct<float, {n}>",
-                 f"k_zpass2_ct<float, {n}, {sh['tx']}, 8>" if sh["zrb"] else f"k_zpass_ct<float, {n}, {sh['tx']}>",
-                 f"k_pinv_ct<float, {n}, 0, 1|2>"]
+        zname = {0: f"k_zpass_ct<float, {n}, {sh['tx']}>", 1: f"k_zpass2_ct<float, {n}, {sh['tx']}, 8>",
+                 2: f"k_zpass3_ct<float, {n}, {sh['tx']}>"}[sh["zrb"]]
+        iname = "k_pinv3_ct" if sh["ct"] & 4 else "k_pinv_ct"
+        names = [f"k_pfwd_ct<float, {n}, 0|1|2>", zname, f"{iname}<float, {n}, 0, 0|1|2>"]
     else:
         names = ["k_plane_fwd<float>", "k_zpass<float>", "k_plane_inv<float, 0>"]
     dom = int(np.argmax(ms))

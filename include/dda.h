@@ -256,7 +256,10 @@ dda_status dda_last_guess_ms(const dda_ctx* ctx, double* ms);
 /* Launch shape of a target's matvec passes for precision DDA_FP32 or
  * DDA_FP64, as 8 integers: {planes in LDS, plane threads, z threads, z tile
  * columns, fallback lines per block, fallback threads, specialised kernels
- * bitmask, z pass over 8 rhs per block}.  dda_set_shape rejects shapes that do
+ * bitmask (1 plane passes, 2 z pass, 4 two-factor inverse plane pass for
+ * n = 64), z pass variant (0 one rhs per block, 1 up to 8 rhs per block with
+ * the spectrum in registers, 2 two-factor 8 x 8 pass for n = 64)}.
+ * dda_set_shape rejects shapes that do
  * not fit the kernels' LDS or thread limits. */
 dda_status dda_get_shape(const dda_ctx* ctx, int32_t target, uint32_t prec, int32_t* out8);
 dda_status dda_set_shape(dda_ctx* ctx, int32_t target, uint32_t prec, const int32_t* in8);

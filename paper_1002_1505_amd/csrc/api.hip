@@ -79,7 +79,8 @@ struct Target {
     double origin[3] = {0, 0, 0};
     double aeff = 0;
     FftPlan plans[3];
-    DevMem d_xyz, d_comp, d_pstart, tw64, tw32, gh64, gh32;
+    DevMem d_xyz, d_comp, d_pstart, d_cstart, d_perm, tw64, tw32, gh64, gh32;
+    DevMem gz64, gz32;  // n = 64: spectrum with components interleaved (two-factor z pass)
     bool have64 = false, have32 = false;
     MvShape sh32{}, sh64{};
     Geo geo() const {
@@ -91,6 +92,8 @@ struct Target {
         g.Npad = Npad;
         g.ncomp = ncomp;
         g.plane_start = d_pstart.as<int>();
+        g.class_start = d_cstart.as<int>();
+        g.perm = d_perm.as<int>();
         g.site_xyz = d_xyz.as<uint32_t>();
         g.site_comp = d_comp.as<uint8_t>();
         return g;
@@ -113,6 +116,13 @@ struct Target {
     template <class T>
     const Cx<T>* ghat() const {
         return std::is_same<T, double>::value ? gh64.as<Cx<T>>() : gh32.as<Cx<T>>();
+    }
+    // spectrum layout the launch shape's z pass reads
+    template <class T>
+    const Cx<T>* ghat_for(const MvShape& sh) const {
+        if ((sh.ct & 2) && sh.zrb == 2)
+            return std::is_same<T, double>::value ? gz64.as<Cx<T>>() : gz32.as<Cx<T>>();
+        return ghat<T>();
     }
 };
 
@@ -260,6 +270,18 @@ MvShape default_shape(const Target& t, int tx_pref) {
         // a generic z pass needs its own thread count for the chosen tile
         c.zrb = (c.ct & 2) ? 1 : 0;
         if (c.ct && matvec_shape_ok<T>(g, t.plans, c)) s = c;
+        // n = 64: the two-factor z pass (32-column tiles where they fit LDS)
+        for (int txc : {32, 16}) {
+            MvShape c3 = s;
+            c3.tx = txc;
+            // two-factor inverse plane pass: faster in FP64, on par in FP32
+            c3.ct = (ct_available<T>(g.n1, txc) | (s.ct & 1)) & (std::is_same<T, double>::value ? 7 : 3);
+            c3.zrb = 2;
+            if (matvec_shape_ok<T>(g, t.plans, c3)) {
+                s = c3;
+                break;
+            }
+        }
     }
     return s;
 }
@@ -276,25 +298,45 @@ dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint
     if (!(kd > 0) || !std::isfinite(kd)) return fail(c, DDA_ERR_INVALID_ARG, "kd must be positive");
     if (alpha_kind < DDA_ALPHA_CM || alpha_kind > DDA_ALPHA_LDR) return fail(c, DDA_ERR_INVALID_ARG, "bad alpha_kind");
     const int n1 = dims[0], n2 = dims[1], n3 = dims[2];
+    // stored order: plane z, then parity class q = 2 (y % 2) + (x % 2), then
+    // scan order; perm maps each stored site to its (z, y, x) scan position
     std::vector<uint32_t> xyz;
     std::vector<uint8_t> comp;
-    std::vector<int> ps(n3 + 1, 0);
+    std::vector<int> ps(n3 + 1, 0), cs(4 * n3 + 1, 0), perm;
     double cx = 0, cy = 0, cz = 0;
+    int scan = 0;
+    std::vector<uint32_t> cls_xyz[4];
+    std::vector<uint8_t> cls_comp[4];
+    std::vector<int> cls_scan[4];
     for (int z = 0; z < n3; ++z) {
         ps[z] = (int)xyz.size();
+        for (int q = 0; q < 4; ++q) {
+            cls_xyz[q].clear();
+            cls_comp[q].clear();
+            cls_scan[q].clear();
+        }
         for (int y = 0; y < n2; ++y)
             for (int x = 0; x < n1; ++x) {
                 const uint8_t o = occ[(size_t)x + (size_t)n1 * (y + (size_t)n2 * z)];
                 if (!o) continue;
                 if (o > ncomp) return fail(c, DDA_ERR_INVALID_ARG, "occupancy value %d exceeds ncomp=%d", o, ncomp);
-                xyz.push_back((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20));
-                comp.push_back((uint8_t)(o - 1));
+                const int q = 2 * (y & 1) + (x & 1);
+                cls_xyz[q].push_back((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20));
+                cls_comp[q].push_back((uint8_t)(o - 1));
+                cls_scan[q].push_back(scan++);
                 cx += x;
                 cy += y;
                 cz += z;
             }
+        for (int q = 0; q < 4; ++q) {
+            cs[4 * z + q] = (int)xyz.size();
+            xyz.insert(xyz.end(), cls_xyz[q].begin(), cls_xyz[q].end());
+            comp.insert(comp.end(), cls_comp[q].begin(), cls_comp[q].end());
+            perm.insert(perm.end(), cls_scan[q].begin(), cls_scan[q].end());
+        }
     }
     ps[n3] = (int)xyz.size();
+    cs[4 * n3] = (int)xyz.size();
     if (xyz.empty()) return fail(c, DDA_ERR_INVALID_ARG, "target has no occupied site");
     t.n[0] = n1;
     t.n[1] = n2;
@@ -319,9 +361,13 @@ dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint
     HCHK(c, t.d_xyz.ensure(xyz.size() * 4));
     HCHK(c, t.d_comp.ensure(comp.size()));
     HCHK(c, t.d_pstart.ensure(ps.size() * 4));
+    HCHK(c, t.d_cstart.ensure(cs.size() * 4));
+    HCHK(c, t.d_perm.ensure(perm.size() * 4));
     HCHK(c, hipMemcpy(t.d_xyz.p, xyz.data(), xyz.size() * 4, hipMemcpyHostToDevice));
     HCHK(c, hipMemcpy(t.d_comp.p, comp.data(), comp.size(), hipMemcpyHostToDevice));
     HCHK(c, hipMemcpy(t.d_pstart.p, ps.data(), ps.size() * 4, hipMemcpyHostToDevice));
+    HCHK(c, hipMemcpy(t.d_cstart.p, cs.data(), cs.size() * 4, hipMemcpyHostToDevice));
+    HCHK(c, hipMemcpy(t.d_perm.p, perm.data(), perm.size() * 4, hipMemcpyHostToDevice));
     // twiddles: f_i (n_i) then h_i (n_i)
     std::vector<Cx<double>> tw;
     for (int i = 0; i < 3; ++i)
@@ -402,6 +448,15 @@ dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
     HCHK(c, work.ensure((size_t)48 * t.n[0] * t.n[1] * t.n[2] * sizeof(Cx<double>)));
     HCHK(c, launch_green(t.geo(), t.tw<double>(), t.plans, t.kd, work.as<Cx<double>>(), t.gh64.as<Cx<double>>(),
                          t.gh32.p ? t.gh32.as<Cx<float>>() : nullptr, c->stream));
+    if (t.n[0] == 64 && t.n[1] == 64 && t.n[2] == 64) {
+        const size_t cs = oct / 6;
+        HCHK(c, t.gz64.ensure(oct * sizeof(Cx<double>)));
+        HCHK(c, launch_green_interleave<double>(t.gh64.as<Cx<double>>(), t.gz64.as<Cx<double>>(), cs, c->stream));
+        if (t.gh32.p) {
+            HCHK(c, t.gz32.ensure(oct * sizeof(Cx<float>)));
+            HCHK(c, launch_green_interleave<float>(t.gh32.as<Cx<float>>(), t.gz32.as<Cx<float>>(), cs, c->stream));
+        }
+    }
     HCHK(c, hipStreamSynchronize(c->stream));
     t.have64 = true;
     if (t.gh32.p) t.have32 = true;
@@ -414,7 +469,7 @@ hipError_t matvec_group(const Target& t, Group& g, int nr, const Cx<T>* x, Cx<T>
                         MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}) {
     Cx<T>* slab = std::is_same<T, double>::value ? g.slab64.as<Cx<T>>() : g.slab32.as<Cx<T>>();
     const Cx<T>* ainv = std::is_same<T, double>::value ? g.ainv64.as<Cx<T>>() : g.ainv32.as<Cx<T>>();
-    return launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab, t.ghat<T>(), ainv, active,
+    return launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab, t.ghat_for<T>(t.shape<T>()), ainv, active,
                             mode, st, dot, upd);
 }
 
@@ -951,7 +1006,7 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
                 HCHK(c, hipMemcpyAsync((char*)dtmp.p + s * per, (const char*)p0 + off, per,
                                        devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
             }
-            HCHK(c, launch_from_abi<double>(t.N, t.Npad, g.nr, dtmp.as<Cx<double>>(), g.x64.as<Cx<double>>(), st));
+            HCHK(c, launch_from_abi<double>(t.geo(), g.nr, dtmp.as<Cx<double>>(), g.x64.as<Cx<double>>(), st));
             HCHK(c, hipStreamSynchronize(st));
         }
         // PREV, PREV_SHIFT, NN: x64 holds the previous solution here
@@ -1144,7 +1199,7 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
             const int s = c->rhs_slot[i];
             const size_t per = (size_t)t.N * 3 * sizeof(Cx<double>);
             HCHK(c, dtmp.ensure(per));
-            HCHK(c, launch_to_abi<double>(t.N, t.Npad, 1, g.x64.as<Cx<double>>() + (size_t)s * 3 * t.Npad,
+            HCHK(c, launch_to_abi<double>(t.geo(), 1, g.x64.as<Cx<double>>() + (size_t)s * 3 * t.Npad,
                                           devptr ? (Cx<double>*)((char*)p_out + off) : dtmp.as<Cx<double>>(), st));
             if (!devptr) HCHK(c, hipMemcpyAsync((char*)p_out + off, dtmp.p, per, hipMemcpyDeviceToHost, st));
             HCHK(c, hipStreamSynchronize(st));
@@ -1212,9 +1267,9 @@ dda_status dda_matvec(dda_ctx* c, int32_t target, int32_t nrhs, const double* ai
         HCHK(c, g.slab64.ensure(slab_elems(t, nrhs) * sizeof(Cx<double>)));
         HCHK(c, vx.ensure(vec_elems(t, nrhs) * sizeof(Cx<double>)));
         HCHK(c, vy.ensure(vec_elems(t, nrhs) * sizeof(Cx<double>)));
-        HCHK(c, launch_from_abi<double>(t.N, t.Npad, nrhs, dx.as<Cx<double>>(), vx.as<Cx<double>>(), st));
+        HCHK(c, launch_from_abi<double>(t.geo(), nrhs, dx.as<Cx<double>>(), vx.as<Cx<double>>(), st));
         HCHK(c, matvec_group<double>(t, g, nrhs, vx.as<Cx<double>>(), vy.as<Cx<double>>(), nullptr, nullptr, MV_AX, st));
-        HCHK(c, launch_to_abi<double>(t.N, t.Npad, nrhs, vy.as<Cx<double>>(), dy.as<Cx<double>>(), st));
+        HCHK(c, launch_to_abi<double>(t.geo(), nrhs, vy.as<Cx<double>>(), dy.as<Cx<double>>(), st));
     } else {
         std::vector<Cx<float>> a32(ai.size());
         for (size_t i = 0; i < ai.size(); ++i) a32[i] = Cx<float>{(float)ai[i].real(), (float)ai[i].imag()};
@@ -1223,9 +1278,9 @@ dda_status dda_matvec(dda_ctx* c, int32_t target, int32_t nrhs, const double* ai
         HCHK(c, g.slab32.ensure(slab_elems(t, nrhs) * sizeof(Cx<float>)));
         HCHK(c, vx.ensure(vec_elems(t, nrhs) * sizeof(Cx<float>)));
         HCHK(c, vy.ensure(vec_elems(t, nrhs) * sizeof(Cx<float>)));
-        HCHK(c, launch_from_abi<float>(t.N, t.Npad, nrhs, dx.as<Cx<double>>(), vx.as<Cx<float>>(), st));
+        HCHK(c, launch_from_abi<float>(t.geo(), nrhs, dx.as<Cx<double>>(), vx.as<Cx<float>>(), st));
         HCHK(c, matvec_group<float>(t, g, nrhs, vx.as<Cx<float>>(), vy.as<Cx<float>>(), nullptr, nullptr, MV_AX, st));
-        HCHK(c, launch_to_abi<float>(t.N, t.Npad, nrhs, vy.as<Cx<float>>(), dy.as<Cx<double>>(), st));
+        HCHK(c, launch_to_abi<float>(t.geo(), nrhs, vy.as<Cx<float>>(), dy.as<Cx<double>>(), st));
     }
     HCHK(c, hipMemcpyAsync(y, dy.p, per * nrhs, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     HCHK(c, hipStreamSynchronize(st));
@@ -1476,7 +1531,7 @@ dda_status profile_passes(dda_ctx* c, Target& t, int nrhs, int reps, const MvSha
         HCHK(c, hipEventRecord(ev[0], st));
         for (int w = 0; w < 3; ++w) {
             HCHK(c, launch_pass<T>(w, geo, tw, t.plans, sh, nrhs, vx.as<Cx<T>>(), vy.as<Cx<T>>(), nullptr,
-                                   slab.as<Cx<T>>(), t.ghat<T>(), ai.as<Cx<T>>(), nullptr, MV_AX, st));
+                                   slab.as<Cx<T>>(), t.ghat_for<T>(sh), ai.as<Cx<T>>(), nullptr, MV_AX, st));
             HCHK(c, hipEventRecord(ev[w + 1], st));
         }
         HCHK(c, hipEventSynchronize(ev[3]));
@@ -1525,15 +1580,17 @@ std::vector<MvShape> shape_candidates(const Target& t) {
     const MvShape base = default_shape<T>(t, 16);
     if (ct_supported(g.n1, g.n2, g.n3)) {
         for (int tx : {8, 16, 32})
-            for (int zrb : {0, 1}) {
-                MvShape c = base;
-                c.tx = tx;
-                c.ct = ct_available<T>(g.n1, tx);
-                if (!(c.ct & 2)) continue;
-                c.zrb = zrb;
-                c.fused = 1;
-                if (matvec_shape_ok<T>(g, t.plans, c)) out.push_back(c);
-            }
+            for (int zrb : {0, 1, 2})
+                for (int pv : {0, 4}) {  // inverse plane pass variant
+                    MvShape c = base;
+                    c.tx = tx;
+                    const int av = ct_available<T>(g.n1, tx);
+                    if (!(av & 2) || (pv && !(av & 4))) continue;
+                    c.ct = (av & 3) | pv;
+                    c.zrb = zrb;
+                    c.fused = 1;
+                    if (matvec_shape_ok<T>(g, t.plans, c)) out.push_back(c);
+                }
     }
     for (int tx : {4, 8, 16, 32})
         for (int fused : {1, 0}) {

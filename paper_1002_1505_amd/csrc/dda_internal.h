@@ -9,13 +9,17 @@
 // Geometry of one target on the device.  Sites are ordered by linear box index;
 // site_xyz packs (x | y << 10 | z << 20); plane_start[z] is the first site of
 // plane z (n3 + 1 entries).
+// Sites are stored plane by plane (z), and inside a plane grouped by parity
+// class q = 2 (y % 2) + (x % 2), scan order (y, then x) inside a class.
 struct Geo {
     int n1, n2, n3;
     int N, Npad;
     int ncomp;
-    const int* plane_start;
-    const uint32_t* site_xyz;
+    const int* plane_start;    // [n3 + 1]: first site of plane z
+    const int* class_start;    // [4 n3 + 1]: first site of class q of plane z at 4 z + q
+    const uint32_t* site_xyz;  // x | y << 10 | z << 20
     const uint8_t* site_comp;  // 0-based composition index
+    const int* perm;           // [N]: position of each stored site in the (z, y, x) scan order
 };
 
 // Twiddle tables of one target: f_i[k] = exp(-2 pi i k / n_i) (k < n_i) and
@@ -47,8 +51,10 @@ struct MvShape {
     int tx;          // columns per z-pass block
     int lines_tl;    // lines per block in the line-kernel fallback
     int nth_lines;
-    int ct;          // bit 0: specialised plane kernels, bit 1: specialised z pass (cubic boxes)
-    int zrb;         // specialised z pass: 1 = loop over up to 8 rhs per block with the spectrum in registers
+    int ct;          // bit 0: specialised plane kernels, bit 1: specialised z pass (cubic boxes),
+                     // bit 2: two-factor inverse plane pass (n = 64, with bit 0)
+    int zrb;         // specialised z pass variant: 0 = one rhs per block, 1 = loop over up to 8 rhs per
+                     // block with the spectrum in registers, 2 = two-factor 8 x 8 pass (n = 64)
 };
 
 // Optional BiCGstab vector update fused into the first matvec pass
@@ -94,6 +100,10 @@ bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh);
 // Spectrum of the interaction tensor: fills the octant arrays (6 components,
 // scaled by 1/(M1 M2 M3)) in FP64 and, when g32 != nullptr, an FP32 copy.
 // work must hold 48 * n1 n2 n3 complex doubles.
+// The tensor spectrum with the 6 components of each frequency adjacent,
+// gz[i * 6 + q] = gh[q * cs + i] (read by the two-factor z pass).
+template <class T>
+hipError_t launch_green_interleave(const Cx<T>* gh, Cx<T>* gz, size_t cs, hipStream_t st);
 hipError_t launch_green(const Geo& g, const Tw<double>& tw, const FftPlan* plans, double kd, Cx<double>* work,
                         Cx<double>* g64, Cx<float>* g32, hipStream_t st);
 
@@ -152,12 +162,12 @@ hipError_t launch_axpy_masked(int Npad, int nrhs, Cx<T>* x, const Cx<T>* d, cons
 template <class T>
 hipError_t launch_norm2(int Npad, int nrhs, const Cx<T>* v, double* partials, double* out, hipStream_t st);
 
-// Layout conversion between the ABI ([rhs][N][3] complex128) and the device
-// layout ([rhs][3][Npad]).
+// Layout conversion between the ABI ([rhs][N][3] complex128, sites in
+// (z, y, x) scan order) and the device layout ([rhs][3][Npad], stored order).
 template <class T>
-hipError_t launch_from_abi(int N, int Npad, int nrhs, const Cx<double>* in, Cx<T>* out, hipStream_t st);
+hipError_t launch_from_abi(const Geo& g, int nrhs, const Cx<double>* in, Cx<T>* out, hipStream_t st);
 template <class T>
-hipError_t launch_to_abi(int N, int Npad, int nrhs, const Cx<T>* in, Cx<double>* out, hipStream_t st);
+hipError_t launch_to_abi(const Geo& g, int nrhs, const Cx<T>* in, Cx<double>* out, hipStream_t st);
 
 // Cross-section sums: out[rhs] = {sum Im(E^* . P), sum |P|^2 * (-Im ainv_c - (2/3) k^3)}.
 hipError_t launch_xsec(const Geo& g, int nrhs, const Cx<double>* E, const Cx<double>* P, const Cx<double>* ainv,
@@ -203,8 +213,10 @@ bool ct_supported(int n1, int n2, int n3);
 template <class T>
 int ct_available(int n, int tx);
 template <class T>
-hipError_t launch_pass_ct(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x,
-                          Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
+bool ct_zpass_fits(int n, int tx, int zrb);
+template <class T>
+hipError_t launch_pass_ct(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>& tw, int nrhs,
+                          const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
                           const int* active, int mode, int dot, const Cx<T>* w, double* partials, const MvUpd& upd,
                           hipStream_t st);
 hipError_t configure_ct_kernels();

@@ -63,6 +63,7 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     const int px = par & 1, py = par >> 1;
     const int tid = threadIdx.x;
     for (int i = tid; i < N; i += NTH) t1[i] = tw.f1[i];
+#pragma unroll 4
     for (int i = tid; i < N * PITCH; i += NTH) buf[i] = Cx<T>{0, 0};
     __syncthreads();
     const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
@@ -82,6 +83,7 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     const Cx<T>* pv = reinterpret_cast<const Cx<T>*>(u.p);
     Cx<T>* po = reinterpret_cast<Cx<T>*>(u.pout);
     Cx<T>* rh = reinterpret_cast<Cx<T>*>(u.rhat);
+#pragma unroll 4
     for (int j = j0 + tid; j < j1; j += NTH) {
         const uint32_t s = g.site_xyz[j];
         const int sx = s & 1023, sy = (s >> 10) & 1023;
@@ -107,6 +109,7 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     ct_fft<T, -1, N, N, NTH, N, PITCH, 0, 1>(buf, t1, tid);   // along x: lines are rows
     ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y: lines are columns
     Cx<T>* out = slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + par) * (size_t)(N * N);
+#pragma unroll 8
     for (int i = tid; i < N * N; i += NTH) out[i] = buf[(i / N) * PITCH + (i % N)];
 }
 
@@ -264,6 +267,133 @@ __global__ void __launch_bounds__(zpass_threads<N>()) k_zpass2_ct(Cx<T>* __restr
     }
 }
 
+// z pass as a two-factor decomposition N = 8 x 8 with the spectrum product
+// in registers.  With z = z1 + 8 z2 and k = k2 + 8 k1, the forward N-point
+// DFT is an 8-point DFT over z2 (thread (c, z1)), a twiddle w_N^(z1 k2), an
+// exchange through LDS and an 8-point DFT over z1 (thread (c, k2)); the
+// inverse runs the same steps backwards, so no digit reversal is needed and
+// each direction crosses LDS once.  Thread (c, k2) multiplies the 3 vector
+// components by the 3 x 3 tensor spectrum at kz = 2 k + pz for both
+// frequency parities pz; the parity-1 input is pre-twiddled by h3 and its
+// output post-twiddled by conj(h3).  One block per (tile of TX columns, rhs);
+// the blocks of one tile for all rhs share an XCD (block index mod 8).  gh is
+// the spectrum with the 6 components of each frequency adjacent.
+template <class T, int N, int TX>
+__global__ void __launch_bounds__(TX * 8) k_zpass3_ct(Cx<T>* __restrict__ slab, const Cx<T>* __restrict__ gh,
+                                                      Tw<T> tw, int nrhs, const int* __restrict__ active) {
+    static_assert(N == 64, "two-factor z pass is written for N = 64");
+    constexpr int R = 8;
+    constexpr int NCOL = 4 * N * N;
+    constexpr int H = N / 2 + 1;
+    constexpr int D = 2 * H;
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* X = reinterpret_cast<Cx<T>*>(smem_raw);  // [a][k2][z1][c]
+    const int b = blockIdx.x;
+    const int rest = b >> 3;
+    const int r = rest % nrhs;
+    const int tile = (rest / nrhs) * 8 + (b & 7);
+    if (active && !active[r]) return;
+    const int tid = threadIdx.x;
+    const int c = tid % TX, j = tid / TX;  // j: z1 in the outer steps, k2 in the inner ones
+    const int q0 = tile * TX;
+    const int par = q0 / (N * N), rem = q0 % (N * N);
+    const int px = par & 1, py = par >> 1;
+    const int kyp = rem / N, kx0 = rem % N;
+    int sx, sy;
+    const int kxi = fold_idx(2 * (kx0 + c) + px, N, sx);
+    const int kyi = fold_idx(2 * kyp + py, N, sy);
+    const T sxy = (T)(sx * sy);
+    Cx<T> w[R];  // w_N^(j m)
+#pragma unroll
+    for (int m = 0; m < R; ++m) w[m] = tw.f3[j * m];
+    // rhs base is uniform; per-thread offsets stay 32-bit (3 N NCOL < 2^32)
+    Cx<T>* base = slab + (size_t)r * 3 * N * NCOL;
+    const uint32_t o0 = (uint32_t)j * NCOL + q0 + c;
+    Cx<T> acc[3][R];
+#pragma unroll 1
+    for (int pz = 0; pz < 2; ++pz) {
+        // forward, outer factor: thread (c, z1 = j)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Cx<T> u[R];
+#pragma unroll
+            for (int z2 = 0; z2 < R; ++z2) {
+                u[z2] = base[o0 + (uint32_t)(a * N + R * z2) * NCOL];
+                if (pz) u[z2] = u[z2] * tw.h3[j + R * z2];
+            }
+            bfly<T, -1, R>(u);
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) X[((a * R + k2) * R + j) * TX + c] = k2 ? u[k2] * w[k2] : u[k2];
+        }
+        __syncthreads();
+        // inner factor, tensor product, inverse inner factor: thread (c, k2 = j)
+        {
+            Cx<T> f[3][R];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                for (int z1 = 0; z1 < R; ++z1) f[a][z1] = X[((a * R + j) * R + z1) * TX + c];
+                bfly<T, -1, R>(f[a]);
+            }
+#pragma unroll
+            for (int k1 = 0; k1 < R; ++k1) {
+                // keep at most two frequencies of tensor loads in flight (register pressure)
+                if (k1 % 2 == 0) __builtin_amdgcn_sched_barrier(0);
+                const int kz = 2 * (j + R * k1) + pz;
+                const bool mir = kz > N;
+                const int kzf = mir ? 2 * N - kz : kz;
+                const T sz = mir ? (T)-1 : (T)1;
+                // spectrum with the 6 components of a frequency adjacent (48 or 96 bytes)
+                const uint32_t gi = ((uint32_t)(pz * H + (kzf >> 1)) * D + kyi) * D + kxi;
+                Cx<T> gg[6];
+                if constexpr (sizeof(T) == 4) {
+                    const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)gi * 3;
+                    const float4 v0 = gp[0], v1 = gp[1], v2 = gp[2];
+                    gg[0] = Cx<T>{v0.x, v0.y};
+                    gg[1] = Cx<T>{v0.z, v0.w};
+                    gg[2] = Cx<T>{v1.x, v1.y};
+                    gg[3] = Cx<T>{v1.z, v1.w};
+                    gg[4] = Cx<T>{v2.x, v2.y};
+                    gg[5] = Cx<T>{v2.z, v2.w};
+                } else {
+#pragma unroll
+                    for (int qq = 0; qq < 6; ++qq) gg[qq] = gh[(size_t)gi * 6 + qq];
+                }
+                const Cx<T> gxx = gg[0], gxy = sxy * gg[1], gxz = ((T)sx * sz) * gg[2];
+                const Cx<T> gyy = gg[3], gyz = ((T)sy * sz) * gg[4], gzz = gg[5];
+                const Cx<T> a0 = f[0][k1], a1 = f[1][k1], a2 = f[2][k1];
+                f[0][k1] = gxx * a0 + gxy * a1 + gxz * a2;
+                f[1][k1] = gxy * a0 + gyy * a1 + gyz * a2;
+                f[2][k1] = gxz * a0 + gyz * a1 + gzz * a2;
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                bfly<T, +1, R>(f[a]);
+                // each thread rewrites exactly the slots it read above
+#pragma unroll
+                for (int z1 = 0; z1 < R; ++z1)
+                    X[((a * R + j) * R + z1) * TX + c] = z1 ? cmulc(w[z1], f[a][z1]) : f[a][z1];
+            }
+        }
+        __syncthreads();
+        // inverse, outer factor: thread (c, z1 = j); the next parity's forward
+        // step rewrites only these slots, so no barrier is needed before it
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Cx<T> u[R];
+#pragma unroll
+            for (int k2 = 0; k2 < R; ++k2) u[k2] = X[((a * R + k2) * R + j) * TX + c];
+            bfly<T, +1, R>(u);
+#pragma unroll
+            for (int z2 = 0; z2 < R; ++z2) acc[a][z2] = pz ? acc[a][z2] + cmulc(tw.h3[j + R * z2], u[z2]) : u[z2];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int z2 = 0; z2 < R; ++z2) base[o0 + (uint32_t)(a * N + R * z2) * NCOL] = acc[a][z2];
+}
+
 // DOT = 1: per-block partial sums of conj(w_j) . y_j (slot 0); DOT = 2:
 // conj(y_j) . x_j (slot 0) and |y_j|^2 (slot 1).  partials[rhs][slot][blk]
 // with blk = (plane within rhs) * 4 + class, 12 n blocks per rhs.
@@ -293,6 +423,8 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     for (int i = tid; i < N; i += NTH) t1[i] = tw.f1[i];
     const Cx<T>* in = slab + (((size_t)rhs * 3 + c) * N + z) * 4 * (size_t)NN;
     const T sgx = qx ? (T)-1 : (T)1, sgy = qy ? (T)-1 : (T)1;
+    // batches of loads in flight per thread (the loop count NN / NTH is a constant)
+#pragma unroll 4
     for (int e = tid; e < NN; e += NTH) {
         const int kyp = e / N, kxp = e % N;
         const int bx = kxp >> 1, px = kxp & 1, by = kyp >> 1, py = kyp & 1;
@@ -309,14 +441,160 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     ct_fft<T, +1, N, HN, NTH, HN, PITCH, 0, 1>(buf, t1, tid);  // along x, rows y' < n/2
     const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
     const Cx<T>* av = ainv + (size_t)rhs * g.ncomp;
-    const int j0 = g.plane_start[z], j1 = g.plane_start[z + 1];
+    // the sites of output class q are stored contiguously within the plane
+    const int j0 = g.class_start[4 * z + q], j1 = g.class_start[4 * z + q + 1];
     double a0r = 0, a0i = 0, a1r = 0;
+#pragma unroll 2
     for (int j = j0 + tid; j < j1; j += NTH) {
         const uint32_t s = g.site_xyz[j];
         const int sx = s & 1023, sy = (s >> 10) & 1023;
-        if ((sx & 1) != qx || (sy & 1) != qy) continue;
         const Cx<T> xj = x[vo + j];
         Cx<T> v = buf[(sy >> 1) * PITCH + (sx >> 1)] + av[g.site_comp[j]] * xj;
+        if (MODE == MV_RESID) v = bvec[vo + j] - v;
+        y[vo + j] = v;
+        if (DOT == 1) {
+            const Cx<T> wj = wv[vo + j];
+            a0r += (double)wj.re * v.re + (double)wj.im * v.im;
+            a0i += (double)wj.re * v.im - (double)wj.im * v.re;
+        } else if (DOT == 2) {
+            a0r += (double)v.re * xj.re + (double)v.im * xj.im;
+            a0i += (double)v.re * xj.im - (double)v.im * xj.re;
+            a1r += (double)v.re * v.re + (double)v.im * v.im;
+        }
+    }
+    if (DOT) {
+        __shared__ double sh[16];
+        const int nblk = 12 * N;
+        const int blk = (plane % (3 * N)) * 4 + q;
+        const double s0r = block_sum(a0r, sh), s0i = block_sum(a0i, sh);
+        double s1r = 0;
+        if (DOT == 2) s1r = block_sum(a1r, sh);
+        if (tid == 0) {
+            double* o = partials + ((size_t)rhs * 4 * nblk + blk) * 2;
+            o[0] = s0r;
+            o[1] = s0i;
+            if (DOT == 2) {
+                o[2 * nblk] = s1r;
+                o[2 * nblk + 1] = 0;
+            }
+        }
+    }
+}
+
+// Inverse plane pass for n = 64 as two-factor 8 x 8 transforms with one LDS
+// exchange per axis.  Block per (plane, output parity class q) as above; the
+// class pre-combination of the four quadrants feeds registers directly.
+// Along y (all 64 columns): with ky = m1 + 8 m2 and y' = n2 + 8 n1, thread
+// (kx, m1) does the 8-point transform over m2 and the twiddle w^(-m1 n2),
+// thread (kx, n2) the transform over m1; only y' < n/2 is kept.  Along x on
+// those 32 rows the same two steps keep x' < n/2.  LDS: rows of the first
+// exchange [n2][m1][kx], then the 32 kept rows (pitch n + 1), the second
+// exchange [n2][m1][y'] and the 32 x 32 result (pitch n/2 + 1).
+template <class T, int N, int MODE, int DOT>
+__global__ void __launch_bounds__(256) k_pinv3_ct(const Cx<T>* __restrict__ slab, const Cx<T>* __restrict__ x,
+                                                  Cx<T>* __restrict__ y, const Cx<T>* __restrict__ bvec,
+                                                  const Cx<T>* __restrict__ ainv, Geo g, Tw<T> tw, int nrhs,
+                                                  const int* __restrict__ active, const Cx<T>* __restrict__ wv,
+                                                  double* __restrict__ partials) {
+    static_assert(N == 64, "two-factor plane pass is written for n = 64");
+    constexpr int R = 8, NN = N * N, HN = N / 2;
+    constexpr int PY = N + 1;       // pitch of the kept rows
+    constexpr int X2OFF = HN * PY;  // second exchange after the kept rows
+    constexpr int PF = HN + 1;      // pitch of the result
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* S = reinterpret_cast<Cx<T>*>(smem_raw);
+    const int nplanes = nrhs * 3 * N;
+    const int b = blockIdx.x;
+    const int plane = ((b >> 3) >> 2) * 8 + (b & 7);
+    const int q = (b >> 3) & 3;
+    if (plane >= nplanes) return;
+    const int rhs = plane / (3 * N);
+    if (active && !active[rhs]) return;
+    const int c = (plane / N) % 3, z = plane % N;
+    const int qx = q & 1, qy = q >> 1;
+    const int tid = threadIdx.x;
+    const Cx<T>* in = slab + (((size_t)rhs * 3 + c) * N + z) * 4 * (size_t)NN;
+    const T sgx = qx ? (T)-1 : (T)1, sgy = qy ? (T)-1 : (T)1;
+    // y, outer factor: thread (kx, m1) for m1 in {g, g + 4}
+    {
+        const int kx = tid & (N - 1), g4 = tid >> 6;
+        const int bx = kx >> 1, px = kx & 1;
+        const Cx<T> hx = tw.h1[kx];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int m1 = g4 + 4 * h;
+            Cx<T> u[R];
+#pragma unroll
+            for (int m2 = 0; m2 < R; ++m2) {
+                const int ky = m1 + R * m2;
+                const int by = ky >> 1, py = ky & 1;
+                const Cx<T>* blk = in + (size_t)(py * 2 + px) * NN;
+                const Cx<T> s00 = blk[by * N + bx], s10 = blk[by * N + bx + HN];
+                const Cx<T> s01 = blk[(by + HN) * N + bx], s11 = blk[(by + HN) * N + bx + HN];
+                Cx<T> v = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
+                if (qx) v = cmulc(hx, v);
+                if (qy) v = cmulc(tw.h2[ky], v);
+                u[m2] = v;
+            }
+            bfly<T, +1, R>(u);
+#pragma unroll
+            for (int n2 = 0; n2 < R; ++n2) S[(n2 * R + m1) * N + kx] = n2 ? cmulc(tw.f1[m1 * n2], u[n2]) : u[n2];
+        }
+    }
+    __syncthreads();
+    // y, inner factor: thread (kx, n2) for n2 in {g, g + 4}; keep y' = n2 + 8 n1 < n/2
+    {
+        const int kx = tid & (N - 1), g4 = tid >> 6;
+        Cx<T> o[2][R];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int n2 = g4 + 4 * h;
+#pragma unroll
+            for (int m1 = 0; m1 < R; ++m1) o[h][m1] = S[(n2 * R + m1) * N + kx];
+            bfly<T, +1, R>(o[h]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int n1 = 0; n1 < R / 2; ++n1) S[(g4 + 4 * h + R * n1) * PY + kx] = o[h][n1];
+    }
+    __syncthreads();
+    // x on the kept rows, outer factor: thread (y', m1) with y' fastest
+    {
+        const int yr = tid & (HN - 1), m1 = tid >> 5;
+        Cx<T> u[R];
+#pragma unroll
+        for (int m2 = 0; m2 < R; ++m2) u[m2] = S[yr * PY + m1 + R * m2];
+        bfly<T, +1, R>(u);
+#pragma unroll
+        for (int n2 = 0; n2 < R; ++n2)
+            S[X2OFF + (n2 * R + m1) * HN + yr] = n2 ? cmulc(tw.f1[m1 * n2], u[n2]) : u[n2];
+    }
+    __syncthreads();
+    // x, inner factor: thread (y', n2); keep x' = n2 + 8 n1 < n/2; the result
+    // overwrites the kept rows, which are no longer read
+    {
+        const int yr = tid & (HN - 1), n2 = tid >> 5;
+        Cx<T> o[R];
+#pragma unroll
+        for (int m1 = 0; m1 < R; ++m1) o[m1] = S[X2OFF + (n2 * R + m1) * HN + yr];
+        bfly<T, +1, R>(o);
+#pragma unroll
+        for (int n1 = 0; n1 < R / 2; ++n1) S[yr * PF + n2 + R * n1] = o[n1];
+    }
+    __syncthreads();
+    const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
+    const Cx<T>* av = ainv + (size_t)rhs * g.ncomp;
+    // the sites of output class q are stored contiguously within the plane
+    const int j0 = g.class_start[4 * z + q], j1 = g.class_start[4 * z + q + 1];
+    double a0r = 0, a0i = 0, a1r = 0;
+#pragma unroll 2
+    for (int j = j0 + tid; j < j1; j += 256) {
+        const uint32_t s = g.site_xyz[j];
+        const int sx = s & 1023, sy = (s >> 10) & 1023;
+        const Cx<T> xj = x[vo + j];
+        Cx<T> v = S[(sy >> 1) * PF + (sx >> 1)] + av[g.site_comp[j]] * xj;
         if (MODE == MV_RESID) v = bvec[vo + j] - v;
         y[vo + j] = v;
         if (DOT == 1) {
@@ -352,18 +630,27 @@ template <class T, int N>
 constexpr size_t plane_lds() { return (size_t)(N + N * (N + 1)) * sizeof(Cx<T>); }
 template <class T, int N, int TX>
 constexpr size_t zpass_lds() { return (size_t)(N + 6 * N * TX) * sizeof(Cx<T>); }
+template <class T, int N, int TX>
+constexpr size_t zpass3_lds() { return (size_t)3 * N * TX * sizeof(Cx<T>); }
 constexpr size_t LDS_MAX = 160 * 1024;
 
 template <class T, int N, int MODE, int DOT>
-void launch_pinv(int nblk, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* b,
-                 const Cx<T>* slab, const Cx<T>* ainv, const int* active, const Cx<T>* w, double* partials,
-                 hipStream_t st) {
+void launch_pinv(int nblk, bool two_factor, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
+                 const Cx<T>* b, const Cx<T>* slab, const Cx<T>* ainv, const int* active, const Cx<T>* w,
+                 double* partials, hipStream_t st) {
+    if constexpr (N == 64) {
+        if (two_factor) {
+            hipLaunchKernelGGL((k_pinv3_ct<T, N, MODE, DOT>), dim3(nblk), dim3(256), (plane_lds<T, N>()), st, slab, x,
+                               y, b, ainv, g, tw, nrhs, active, w, partials);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_pinv_ct<T, N, MODE, DOT>), dim3(nblk), dim3(plane_threads<N>()), (plane_lds<T, N>()), st,
                        slab, x, y, b, ainv, g, tw, nrhs, active, w, partials);
 }
 
 template <class T, int N>
-hipError_t pass_n(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
+hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
                   const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv, const int* active, int mode,
                   int dot, const Cx<T>* w, double* partials, const MvUpd& upd, hipStream_t st) {
     const int nplanes = nrhs * 3 * N;
@@ -386,18 +673,38 @@ hipError_t pass_n(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int
                     hipLaunchKernelGGL((k_pfwd_ct<T, N, 0>), dim3(nblk_plane), dim3(plane_threads<N>()),
                                        (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
             } else if (mode == MV_AX) {
-                if (dot == 1) launch_pinv<T, N, MV_AX, 1>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
-                else if (dot == 2) launch_pinv<T, N, MV_AX, 2>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
-                else launch_pinv<T, N, MV_AX, 0>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                if (dot == 1) launch_pinv<T, N, MV_AX, 1>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                else if (dot == 2) launch_pinv<T, N, MV_AX, 2>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                else launch_pinv<T, N, MV_AX, 0>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
             } else {
-                launch_pinv<T, N, MV_RESID, 0>(nblk_plane, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                launch_pinv<T, N, MV_RESID, 0>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
             }
             return hipGetLastError();
         }
     }
     const int ntile = 4 * N * N;
+    if (zrb == 2) {
+        if constexpr (N != 64) {
+            return hipErrorNotSupported;
+        } else {
+#define ZP3(TXV)                                                                                                   \
+    if (tx == TXV) {                                                                                               \
+        if constexpr (zpass3_lds<T, N, TXV>() > LDS_MAX) {                                                         \
+            return hipErrorNotSupported;                                                                           \
+        } else {                                                                                                   \
+            hipLaunchKernelGGL((k_zpass3_ct<T, N, TXV>), dim3(nrhs * (ntile / TXV)), dim3(TXV * 8),               \
+                               (zpass3_lds<T, N, TXV>()), st, slab, ghat, tw, nrhs, active);                        \
+            return hipGetLastError();                                                                              \
+        }                                                                                                          \
+    }
+            ZP3(16)
+            ZP3(32)
+#undef ZP3
+            return hipErrorNotSupported;
+        }
+    }
 #define ZP2(TXV)                                                                                                   \
-    if (tx == TXV && zrb) {                                                                                        \
+    if (tx == TXV && zrb == 1) {                                                                                   \
         if constexpr (zpass_lds<T, N, TXV>() > LDS_MAX || (N % TXV) != 0) {                                        \
             return hipErrorNotSupported;                                                                           \
         } else {                                                                                                   \
@@ -442,22 +749,38 @@ hipError_t set_attrs_n() {
                              (const void*)k_pinv_ct<T, N, MV_AX, 2>, (const void*)k_pinv_ct<T, N, MV_RESID, 0>};
         for (const void* f : fns)
             if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if constexpr (N == 64) {
+            const void* f3[] = {(const void*)k_pinv3_ct<T, N, MV_AX, 0>, (const void*)k_pinv3_ct<T, N, MV_AX, 1>,
+                                (const void*)k_pinv3_ct<T, N, MV_AX, 2>, (const void*)k_pinv3_ct<T, N, MV_RESID, 0>};
+            for (const void* f : f3)
+                if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        }
     }
-    if constexpr (zpass_lds<T, N, 8>() <= LDS_MAX && N % 8 == 0)
+    if constexpr (zpass_lds<T, N, 8>() <= LDS_MAX && N % 8 == 0) {
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass_ct<T, N, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass2_ct<T, N, 8, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if constexpr (zpass_lds<T, N, 16>() <= LDS_MAX && N % 16 == 0)
+    }
+    if constexpr (zpass_lds<T, N, 16>() <= LDS_MAX && N % 16 == 0) {
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass_ct<T, N, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass2_ct<T, N, 16, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if constexpr (zpass_lds<T, N, 32>() <= LDS_MAX && N % 32 == 0)
+    }
+    if constexpr (zpass_lds<T, N, 32>() <= LDS_MAX && N % 32 == 0) {
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass_ct<T, N, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass2_ct<T, N, 32, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    }
+    if constexpr (N == 64) {
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_zpass3_ct<T, N, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if constexpr (zpass3_lds<T, N, 32>() <= LDS_MAX)
+            if (e == hipSuccess)
+                e = set_lds_limit((const void*)k_zpass3_ct<T, N, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    }
     return e;
 }
 
@@ -469,12 +792,12 @@ bool ct_supported(int n1, int n2, int n3) {
 }
 
 template <class T>
-hipError_t launch_pass_ct(int which, int tx, int zrb, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x,
-                          Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
+hipError_t launch_pass_ct(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>& tw, int nrhs,
+                          const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
                           const int* active, int mode, int dot, const Cx<T>* w, double* partials, const MvUpd& upd,
                           hipStream_t st) {
     if (!ct_supported(g.n1, g.n2, g.n3)) return hipErrorNotSupported;
-#define PN(NV) pass_n<T, NV>(which, tx, zrb, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, dot, w, partials, upd, st)
+#define PN(NV) pass_n<T, NV>(which, tx, zrb, ct, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode, dot, w, partials, upd, st)
     switch (g.n1) {
         case 16: return PN(16);
         case 32: return PN(32);
@@ -485,6 +808,9 @@ hipError_t launch_pass_ct(int which, int tx, int zrb, const Geo& g, const Tw<T>&
 #undef PN
 }
 
+template <class T>
+bool ct_zpass_fits(int n, int tx, int zrb);
+
 // Which passes of a cubic box of side n have a specialised kernel in precision
 // T with z tile tx: bit 0 planes, bit 1 z pass.
 template <class T>
@@ -493,9 +819,18 @@ int ct_available(int n, int tx) {
     int bits = 0;
     if (!ct_supported(n, n, n)) return 0;
     if (planes((size_t)(n + n * (n + 1)) * sizeof(Cx<T>))) bits |= 1;
-    if ((tx == 8 || tx == 16 || tx == 32) && n % tx == 0 && (size_t)(n + 6 * n * tx) * sizeof(Cx<T>) <= LDS_MAX)
-        bits |= 2;
+    if ((bits & 1) && n == 64) bits |= 4;  // two-factor inverse plane pass
+    if (ct_zpass_fits<T>(n, tx, 0) || ct_zpass_fits<T>(n, tx, 2)) bits |= 2;
     return bits;
+}
+
+// Whether z-pass variant zrb (0, 1: LDS lines; 2: two-factor, n = 64) has a
+// kernel for a cubic box of side n with z tile tx in precision T.
+template <class T>
+bool ct_zpass_fits(int n, int tx, int zrb) {
+    if (!ct_supported(n, n, n) || !(tx == 8 || tx == 16 || tx == 32) || n % tx) return false;
+    if (zrb == 2) return n == 64 && tx >= 16 && (size_t)3 * n * tx * sizeof(Cx<T>) <= LDS_MAX;
+    return (zrb == 0 || zrb == 1) && (size_t)(n + 6 * n * tx) * sizeof(Cx<T>) <= LDS_MAX;
 }
 
 hipError_t configure_ct_kernels() {
@@ -508,12 +843,14 @@ hipError_t configure_ct_kernels() {
     return hipSuccess;
 }
 
-template hipError_t launch_pass_ct<float>(int, int, int, const Geo&, const Tw<float>&, int, const Cx<float>*,
+template hipError_t launch_pass_ct<float>(int, int, int, int, const Geo&, const Tw<float>&, int, const Cx<float>*,
                                           Cx<float>*, const Cx<float>*, Cx<float>*, const Cx<float>*, const Cx<float>*,
                                           const int*, int, int, const Cx<float>*, double*, const MvUpd&, hipStream_t);
-template hipError_t launch_pass_ct<double>(int, int, int, const Geo&, const Tw<double>&, int, const Cx<double>*,
+template hipError_t launch_pass_ct<double>(int, int, int, int, const Geo&, const Tw<double>&, int, const Cx<double>*,
                                            Cx<double>*, const Cx<double>*, Cx<double>*, const Cx<double>*,
                                            const Cx<double>*, const int*, int, int, const Cx<double>*, double*,
                                            const MvUpd&, hipStream_t);
 template int ct_available<float>(int, int);
 template int ct_available<double>(int, int);
+template bool ct_zpass_fits<float>(int, int, int);
+template bool ct_zpass_fits<double>(int, int, int);

@@ -463,11 +463,15 @@ static int rmin_of(const FftPlan& p) {
 template <class T>
 bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh) {
     const size_t lds_max = 160 * 1024;
+    if (sh.zrb < 0 || sh.zrb > 2) return false;
+    if (sh.zrb == 2 && !(sh.ct & 2)) return false;
     if (sh.ct) {
         if (g.n1 != g.n2 || g.n2 != g.n3) return false;
         const int av = ct_available<T>(g.n1, sh.tx);
         if ((sh.ct & av) != sh.ct) return false;
-        if (sh.ct == 3) return true;
+        if ((sh.ct & 2) && !ct_zpass_fits<T>(g.n1, sh.tx, sh.zrb)) return false;
+        if ((sh.ct & 4) && !(sh.ct & 1)) return false;
+        if ((sh.ct & 3) == 3) return true;
     }
     if (sh.tx <= 0 || (g.n1 % sh.tx) != 0) return false;
     if (zpass_smem<T>(g, sh.tx) > lds_max) return false;
@@ -492,7 +496,7 @@ hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* 
     const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
     const long long np = (long long)n1 * n2;
     if ((which == 1 && (sh.ct & 2)) || (which != 1 && (sh.ct & 1)))
-        return launch_pass_ct<T>(which, sh.tx, sh.zrb, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode,
+        return launch_pass_ct<T>(which, sh.tx, sh.zrb, sh.ct, g, tw, nrhs, x, y, b, slab, ghat, ainv, active, mode,
                                  which == 2 ? dot.dot : 0, (const Cx<T>*)dot.w, dot.partials, upd, st);
     if (which == 0) {
         if (sh.fused) {
@@ -554,6 +558,21 @@ hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, co
         HIP_TRY(launch_pass<T>(w, g, tw, plans, sh, nrhs, x, y, b, slab, ghat, ainv, active, mode, st, dot, upd));
     return hipSuccess;
 }
+
+template <class T>
+__global__ void k_green_interleave(const Cx<T>* __restrict__ gh, Cx<T>* __restrict__ gz, size_t cs) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cs; i += (size_t)gridDim.x * blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gz[i * 6 + q] = gh[q * cs + i];
+}
+
+template <class T>
+hipError_t launch_green_interleave(const Cx<T>* gh, Cx<T>* gz, size_t cs, hipStream_t st) {
+    hipLaunchKernelGGL((k_green_interleave<T>), dim3(1024), dim3(256), 0, st, gh, gz, cs);
+    return hipGetLastError();
+}
+template hipError_t launch_green_interleave<float>(const Cx<float>*, Cx<float>*, size_t, hipStream_t);
+template hipError_t launch_green_interleave<double>(const Cx<double>*, Cx<double>*, size_t, hipStream_t);
 
 hipError_t launch_green(const Geo& g, const Tw<double>& tw, const FftPlan* plans, double kd, Cx<double>* work,
                         Cx<double>* g64, Cx<float>* g32, hipStream_t st) {

@@ -348,13 +348,15 @@ __global__ void k_norm2_final(int nblk, const double* __restrict__ partials, dou
 }
 
 template <class T>
-__global__ void k_from_abi(int N, int Npad, const Cx<double>* __restrict__ in, Cx<T>* __restrict__ out) {
+__global__ void k_from_abi(int N, int Npad, const int* __restrict__ perm, const Cx<double>* __restrict__ in,
+                           Cx<T>* __restrict__ out) {
     const int rhs = blockIdx.y;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < Npad; j += gridDim.x * blockDim.x) {
+        const int ja = j < N ? perm[j] : 0;
         for (int c = 0; c < 3; ++c) {
             Cx<T> v = {0, 0};
             if (j < N) {
-                const Cx<double> a = in[((size_t)rhs * N + j) * 3 + c];
+                const Cx<double> a = in[((size_t)rhs * N + ja) * 3 + c];
                 v = Cx<T>{(T)a.re, (T)a.im};
             }
             out[((size_t)rhs * 3 + c) * Npad + j] = v;
@@ -363,12 +365,14 @@ __global__ void k_from_abi(int N, int Npad, const Cx<double>* __restrict__ in, C
 }
 
 template <class T>
-__global__ void k_to_abi(int N, int Npad, const Cx<T>* __restrict__ in, Cx<double>* __restrict__ out) {
+__global__ void k_to_abi(int N, int Npad, const int* __restrict__ perm, const Cx<T>* __restrict__ in,
+                         Cx<double>* __restrict__ out) {
     const int rhs = blockIdx.y;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+        const int ja = perm[j];
         for (int c = 0; c < 3; ++c) {
             const Cx<T> a = in[((size_t)rhs * 3 + c) * Npad + j];
-            out[((size_t)rhs * N + j) * 3 + c] = Cx<double>{(double)a.re, (double)a.im};
+            out[((size_t)rhs * N + ja) * 3 + c] = Cx<double>{(double)a.re, (double)a.im};
         }
     }
 }
@@ -662,13 +666,14 @@ hipError_t launch_norm2(int Npad, int nrhs, const Cx<T>* v, double* partials, do
     return hipGetLastError();
 }
 template <class T>
-hipError_t launch_from_abi(int N, int Npad, int nrhs, const Cx<double>* in, Cx<T>* out, hipStream_t st) {
-    hipLaunchKernelGGL((k_from_abi<T>), dim3((Npad + 255) / 256, nrhs), dim3(256), 0, st, N, Npad, in, out);
+hipError_t launch_from_abi(const Geo& g, int nrhs, const Cx<double>* in, Cx<T>* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_from_abi<T>), dim3((g.Npad + 255) / 256, nrhs), dim3(256), 0, st, g.N, g.Npad, g.perm, in,
+                       out);
     return hipGetLastError();
 }
 template <class T>
-hipError_t launch_to_abi(int N, int Npad, int nrhs, const Cx<T>* in, Cx<double>* out, hipStream_t st) {
-    hipLaunchKernelGGL((k_to_abi<T>), dim3((N + 255) / 256, nrhs), dim3(256), 0, st, N, Npad, in, out);
+hipError_t launch_to_abi(const Geo& g, int nrhs, const Cx<T>* in, Cx<double>* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_to_abi<T>), dim3((g.N + 255) / 256, nrhs), dim3(256), 0, st, g.N, g.Npad, g.perm, in, out);
     return hipGetLastError();
 }
 hipError_t launch_xsec(const Geo& g, int nrhs, const Cx<double>* E, const Cx<double>* P, const Cx<double>* ainv,
@@ -700,7 +705,7 @@ hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const 
                                             hipStream_t);                                                            \
     template hipError_t launch_axpy_masked<T>(int, int, Cx<T>*, const Cx<T>*, const int*, hipStream_t);              \
     template hipError_t launch_norm2<T>(int, int, const Cx<T>*, double*, double*, hipStream_t);                      \
-    template hipError_t launch_from_abi<T>(int, int, int, const Cx<double>*, Cx<T>*, hipStream_t);                   \
-    template hipError_t launch_to_abi<T>(int, int, int, const Cx<T>*, Cx<double>*, hipStream_t);
+    template hipError_t launch_from_abi<T>(const Geo&, int, const Cx<double>*, Cx<T>*, hipStream_t);                 \
+    template hipError_t launch_to_abi<T>(const Geo&, int, const Cx<T>*, Cx<double>*, hipStream_t);
 INST(float)
 INST(double)

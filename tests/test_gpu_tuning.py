@@ -24,15 +24,16 @@ def ctx():
 def _shapes():
     out = []
     for tx in (8, 16, 32):
-        for zrb in (0, 1):
-            out.append(dict(fused=1, nth_plane=256, nth_z=256, tx=tx, lines_tl=16, nth_lines=256, ct=3, zrb=zrb))
+        for zrb in (0, 1, 2):
+            for ct in (3, 7):
+                out.append(dict(fused=1, nth_plane=256, nth_z=256, tx=tx, lines_tl=16, nth_lines=256, ct=ct, zrb=zrb))
     for tx in (4, 8, 16):
         for fused in (1, 0):
             out.append(dict(fused=fused, nth_plane=256, nth_z=512, tx=tx, lines_tl=16, nth_lines=256, ct=0, zrb=0))
     return out
 
 
-@pytest.mark.parametrize("n", [16, 32, 48])
+@pytest.mark.parametrize("n", [16, 32, 48, 64])
 def test_all_launch_shapes_agree_with_oracle(ctx, n):
     import paper_1002_1505_amd as P
 
