@@ -466,7 +466,8 @@ dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
 template <class T>
 hipError_t matvec_group(const Target& t, Group& g, int nr, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, const int* active,
                         int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr},
-                        MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr}) {
+                        MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                          nullptr}) {
     Cx<T>* slab = std::is_same<T, double>::value ? g.slab64.as<Cx<T>>() : g.slab32.as<Cx<T>>();
     const Cx<T>* ainv = std::is_same<T, double>::value ? g.ainv64.as<Cx<T>>() : g.ainv32.as<Cx<T>>();
     return launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab, t.ghat_for<T>(t.shape<T>()), ainv, active,
@@ -546,29 +547,36 @@ hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st, int k) {
         const int nbv = vec_blocks(Np), nbp = fuse ? 12 * t.n[0] : nbv;
         if (!fuse) pin = pout = g.kv[3].as<Cx<T>>();  // separate update kernel works in place
         if (fuse) {
-            // the inverse pass reads the updated direction (written by the
-            // forward pass) for the diagonal term
+            // the forward pass first applies the previous iteration's pending
+            // x, r update; the inverse pass reads the updated direction
+            // (written by the forward pass) for the diagonal term
             if ((e = matvec_group<T>(t, g, nr, pout, v, nullptr, act, MV_AX, st, MvDot{1, rh, part},
-                                     MvUpd{1, r, v, pin, pout, rh, bs})) != hipSuccess)
+                                     MvUpd{3, r, v, pin, pout, rh, bs, s, tt, x})) != hipSuccess)
                 return e;
         } else {
             if ((e = launch_bicg_p<T>(Np, nr, pin, r, v, rh, bs, act, st)) != hipSuccess) return e;
             if ((e = matvec_group<T>(t, g, nr, pin, v, nullptr, act, MV_AX, st)) != hipSuccess) return e;
             if ((e = launch_dot<T>(Np, nr, 1, rh, v, nullptr, nullptr, part, act, st)) != hipSuccess) return e;
         }
-        if ((e = launch_scalars(0, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_scalars(0, nbp, nr, bs, part, act, 0, st)) != hipSuccess) return e;
         if (fuse) {
-            if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st, MvDot{2, nullptr, part},
-                                     MvUpd{2, r, v, nullptr, s, nullptr, bs})) != hipSuccess)
+            // the inverse pass also forms <rhat, s>, <rhat, t> and ||s||^2, from
+            // which the scalars follow without forming r = s - omega t; that
+            // update is left pending for the next iteration's forward pass
+            if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st, MvDot{3, rh, part},
+                                     MvUpd{2, r, v, nullptr, s, nullptr, bs, nullptr, nullptr, nullptr})) !=
+                hipSuccess)
                 return e;
+            if ((e = launch_scalars(3, nbp, nr, bs, part, act, k & 1, st)) != hipSuccess) return e;
+            continue;
         } else {
             if ((e = launch_bicg_s<T>(Np, nr, s, r, v, bs, act, st)) != hipSuccess) return e;
             if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st)) != hipSuccess) return e;
             if ((e = launch_dot<T>(Np, nr, 2, tt, s, tt, tt, part, act, st)) != hipSuccess) return e;
         }
-        if ((e = launch_scalars(1, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_scalars(1, nbp, nr, bs, part, act, 0, st)) != hipSuccess) return e;
         if ((e = launch_bicg_xr<T>(Np, nr, x, r, pout, s, tt, rh, bs, part, act, st)) != hipSuccess) return e;
-        if ((e = launch_scalars(2, nbv, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_scalars(2, nbv, nr, bs, part, act, 0, st)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -629,6 +637,15 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
         } else {
             for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st, k));
         }
+    }
+    // apply the update the last fused iteration of every rhs left pending; the
+    // direction of iteration k is in kv[7] for even k, kv[3] for odd k
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        const Target& t = *c->tg[g.tgt];
+        HCHK(c, launch_bicg_flush<T>(t.Npad, g.nr, g.kv[0].as<Cx<T>>(), g.kv[1].as<Cx<T>>(), g.kv[7].as<Cx<T>>(),
+                                     g.kv[3].as<Cx<T>>(), g.kv[5].as<Cx<T>>(), g.kv[6].as<Cx<T>>(),
+                                     g.state.as<BiState>(), st));
     }
     return DDA_OK;
 }

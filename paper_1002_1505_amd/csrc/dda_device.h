@@ -191,6 +191,26 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Sums of NV values over the block with one barrier; results valid in
+// thread 0 (v is overwritten).  `sh` needs NV * blockDim.x / 64 doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum_n(double* v, double* sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[w * NV + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double s = 0;
+            for (int k = 0; k < nw; ++k) s += sh[k * NV + i];
+            v[i] = s;
+        }
+}
+
 // Sum of `v` over the block; result valid in thread 0.  `sh` needs
 // blockDim.x / 64 doubles.
 __device__ __forceinline__ double block_sum(double v, double* sh) {

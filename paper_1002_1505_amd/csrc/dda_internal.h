@@ -41,6 +41,11 @@ struct BiState {
     double rr;     // ||r||^2 (recursive residual)
     double tol2;   // stop when rr <= tol2
     int it, maxit, restart, conv;
+    // fused iteration: the update x += alpha p + omega s, r = s - omega t of
+    // the last completed iteration is still to be applied (by the next
+    // iteration's first pass, or by the flush after the solve); p is in the
+    // direction buffer pbuf (0 or 1)
+    int pend, pbuf;
 };
 
 // Launch shapes of the three matvec passes for one target and precision.
@@ -59,19 +64,26 @@ struct MvShape {
 
 // Optional BiCGstab vector update fused into the first matvec pass
 // (specialised plane kernels only): mode 1 = direction update into pout,
-// mode 2 = s = r - alpha v into pout; the transformed vector is the updated one.
+// mode 2 = s = r - alpha v into pout, mode 3 = mode 1 after applying the
+// pending update r = s - omega t, x += alpha p + omega s of the previous
+// iteration when st.pend; the transformed vector is the updated one.
 struct MvUpd {
     int mode;
-    const void* r;
+    void* r;
     const void* v;
     const void* p;
     void* pout;
     void* rhat;
     const BiState* st;
+    const void* s;  // mode 3: pending update inputs s, t and the solution x
+    const void* t;
+    void* x;
 };
 
 // Optional inner products fused into the last matvec pass (specialised plane
-// kernels only): dot = 1 -> <w, y> in slot 0; dot = 2 -> <y, x>, <y, y>.
+// kernels only): dot = 1 -> <w, y> in slot 0; dot = 2 -> <y, x>, <y, y>;
+// dot = 3 -> <y, x> (slot 0), (<y, y>, <x, x>) (slot 1), <w, x> (slot 2),
+// <w, y> (slot 3).
 struct MvDot {
     int dot;
     const void* w;
@@ -85,14 +97,16 @@ template <class T>
 hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh, int nrhs,
                          const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
                          const Cx<T>* ainv, const int* active, int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr},
-                         MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr});
+                         MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                           nullptr});
 // Individual passes (for per-pass profiling).
 template <class T>
 hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh,
                        int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
                        const Cx<T>* ainv, const int* active, int mode, hipStream_t st,
                        MvDot dot = MvDot{0, nullptr, nullptr},
-                       MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr});
+                       MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                         nullptr});
 // Shared-memory bytes and feasibility of a shape.
 template <class T>
 bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh);
@@ -141,8 +155,13 @@ hipError_t launch_bicg_xr(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p
                           const Cx<T>* t, const Cx<T>* rhat, const BiState* st_, double* partials,
                           const int* active, hipStream_t st);
 // which: 0 alpha, 1 omega, 2 rho/convergence; nblk partials per rhs and slot
-hipError_t launch_scalars(int which, int nblk, int nrhs, BiState* s, const double* partials, int* active,
+hipError_t launch_scalars(int which, int nblk, int nrhs, BiState* s, const double* partials, int* active, int kpar,
                           hipStream_t st);
+// Apply the pending update of a fused iteration (BiState.pend): x += alpha p +
+// omega s, r = s - omega t with p in p0 or p1 by BiState.pbuf; clears pend.
+template <class T>
+hipError_t launch_bicg_flush(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p0, const Cx<T>* p1,
+                             const Cx<T>* s, const Cx<T>* t, BiState* st, hipStream_t stream);
 template <class T>
 hipError_t launch_bicg_init(int Npad, int nrhs, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* rhat, Cx<T>* p,
                             Cx<T>* v, hipStream_t st);

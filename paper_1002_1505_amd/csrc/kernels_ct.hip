@@ -32,15 +32,21 @@ template <int N> constexpr int zpass_threads() { return N >= 128 ? 512 : 256; }
 
 // UPD = 0: transform x.  UPD = 1: BiCGstab direction update p' = r + beta (p - omega v)
 // (p' = r and rhat = r on restart), transform p' and store it in pout.
-// UPD = 2: s = r - alpha v, transform s and store it in pout.  Only the
-// parity-0 block of a plane stores, and pout never aliases an input.
+// UPD = 2: s = r - alpha v, transform s and store it in pout.  UPD = 3: as
+// UPD = 1, but when st.pend the residual is first formed as r = s - omega t
+// and stored together with x += alpha p + omega s (the update the previous
+// iteration left pending).  Only the parity-0 block of a plane stores, and
+// pout never aliases an input.
 struct UpdArgs {
-    const void* r;
+    void* r;
     const void* v;
     const void* p;
     void* pout;
     void* rhat;
     const BiState* st;
+    const void* s;
+    const void* t;
+    void* x;
 };
 
 template <class T, int N, int UPD>
@@ -68,17 +74,22 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     __syncthreads();
     const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
     const int j0 = g.plane_start[z], j1 = g.plane_start[z + 1];
-    Cx<T> c1 = {0, 0}, c2 = {0, 0};
-    int restart = 0;
-    if (UPD == 1) {
+    Cx<T> c1 = {0, 0}, c2 = {0, 0}, c3 = {0, 0};
+    int restart = 0, pend = 0;
+    if (UPD == 1 || UPD == 3) {
         const BiState sv = u.st[rhs];
         c1 = Cx<T>{(T)sv.beta[0], (T)sv.beta[1]};
         c2 = Cx<T>{(T)sv.omega[0], (T)sv.omega[1]};
+        c3 = Cx<T>{(T)sv.alpha[0], (T)sv.alpha[1]};
         restart = sv.restart;
+        pend = UPD == 3 ? sv.pend : 0;
     } else if (UPD == 2) {
         c1 = Cx<T>{(T)u.st[rhs].alpha[0], (T)u.st[rhs].alpha[1]};
     }
-    const Cx<T>* rv = reinterpret_cast<const Cx<T>*>(u.r);
+    Cx<T>* rv = reinterpret_cast<Cx<T>*>(u.r);
+    const Cx<T>* sv_ = reinterpret_cast<const Cx<T>*>(u.s);
+    const Cx<T>* tv_ = reinterpret_cast<const Cx<T>*>(u.t);
+    Cx<T>* xv_ = reinterpret_cast<Cx<T>*>(u.x);
     const Cx<T>* vv = reinterpret_cast<const Cx<T>*>(u.v);
     const Cx<T>* pv = reinterpret_cast<const Cx<T>*>(u.p);
     Cx<T>* po = reinterpret_cast<Cx<T>*>(u.pout);
@@ -90,8 +101,18 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
         Cx<T> v;
         if (UPD == 0) {
             v = x[vo + j];
-        } else if (UPD == 1) {
-            const Cx<T> rj = rv[vo + j];
+        } else if (UPD == 1 || UPD == 3) {
+            Cx<T> rj;
+            if (UPD == 3 && pend) {
+                const Cx<T> sj = sv_[vo + j];
+                rj = sj - c2 * tv_[vo + j];
+                if (par == 0) {
+                    rv[vo + j] = rj;
+                    xv_[vo + j] = xv_[vo + j] + c3 * pv[vo + j] + c2 * sj;
+                }
+            } else {
+                rj = rv[vo + j];
+            }
             v = restart ? rj : rj + c1 * (pv[vo + j] - c2 * vv[vo + j]);
             if (par == 0) {
                 po[vo + j] = v;
@@ -395,7 +416,9 @@ __global__ void __launch_bounds__(TX * 8) k_zpass3_ct(Cx<T>* __restrict__ slab, 
 }
 
 // DOT = 1: per-block partial sums of conj(w_j) . y_j (slot 0); DOT = 2:
-// conj(y_j) . x_j (slot 0) and |y_j|^2 (slot 1).  partials[rhs][slot][blk]
+// conj(y_j) . x_j (slot 0) and |y_j|^2 (slot 1); DOT = 3: as DOT = 2 with
+// |x_j|^2 in the imaginary part of slot 1, conj(w_j) . x_j (slot 2) and
+// conj(w_j) . y_j (slot 3).  partials[rhs][slot][blk]
 // with blk = (plane within rhs) * 4 + class, 12 n blocks per rhs.
 template <class T, int N, int MODE, int DOT>
 __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __restrict__ slab, const Cx<T>* __restrict__ x,
@@ -443,7 +466,7 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     const Cx<T>* av = ainv + (size_t)rhs * g.ncomp;
     // the sites of output class q are stored contiguously within the plane
     const int j0 = g.class_start[4 * z + q], j1 = g.class_start[4 * z + q + 1];
-    double a0r = 0, a0i = 0, a1r = 0;
+    double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0, a3r = 0, a3i = 0;
 #pragma unroll 2
     for (int j = j0 + tid; j < j1; j += NTH) {
         const uint32_t s = g.site_xyz[j];
@@ -456,26 +479,43 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
             const Cx<T> wj = wv[vo + j];
             a0r += (double)wj.re * v.re + (double)wj.im * v.im;
             a0i += (double)wj.re * v.im - (double)wj.im * v.re;
-        } else if (DOT == 2) {
+        } else if (DOT == 2 || DOT == 3) {
             a0r += (double)v.re * xj.re + (double)v.im * xj.im;
             a0i += (double)v.re * xj.im - (double)v.im * xj.re;
             a1r += (double)v.re * v.re + (double)v.im * v.im;
+            if (DOT == 3) {
+                const Cx<T> wj = wv[vo + j];
+                a1i += (double)xj.re * xj.re + (double)xj.im * xj.im;
+                a2r += (double)wj.re * xj.re + (double)wj.im * xj.im;
+                a2i += (double)wj.re * xj.im - (double)wj.im * xj.re;
+                a3r += (double)wj.re * v.re + (double)wj.im * v.im;
+                a3i += (double)wj.re * v.im - (double)wj.im * v.re;
+            }
         }
     }
     if (DOT) {
-        __shared__ double sh[16];
+        __shared__ double sh[8 * 16];
         const int nblk = 12 * N;
         const int blk = (plane % (3 * N)) * 4 + q;
-        const double s0r = block_sum(a0r, sh), s0i = block_sum(a0i, sh);
-        double s1r = 0;
-        if (DOT == 2) s1r = block_sum(a1r, sh);
+        double red[8] = {a0r, a0i, a1r, a1i, a2r, a2i, a3r, a3i};
+        block_sum_n<DOT == 3 ? 8 : (DOT == 2 ? 3 : 2)>(red, sh);
+        const double s0r = red[0], s0i = red[1];
+        const double s1r = DOT >= 2 ? red[2] : 0, s1i = DOT == 3 ? red[3] : 0;
+        const double s2r = DOT == 3 ? red[4] : 0, s2i = DOT == 3 ? red[5] : 0;
+        const double s3r = DOT == 3 ? red[6] : 0, s3i = DOT == 3 ? red[7] : 0;
         if (tid == 0) {
             double* o = partials + ((size_t)rhs * 4 * nblk + blk) * 2;
             o[0] = s0r;
             o[1] = s0i;
-            if (DOT == 2) {
+            if (DOT >= 2) {
                 o[2 * nblk] = s1r;
-                o[2 * nblk + 1] = 0;
+                o[2 * nblk + 1] = s1i;
+            }
+            if (DOT == 3) {
+                o[4 * nblk] = s2r;
+                o[4 * nblk + 1] = s2i;
+                o[6 * nblk] = s3r;
+                o[6 * nblk + 1] = s3i;
             }
         }
     }
@@ -588,7 +628,7 @@ __global__ void __launch_bounds__(256) k_pinv3_ct(const Cx<T>* __restrict__ slab
     const Cx<T>* av = ainv + (size_t)rhs * g.ncomp;
     // the sites of output class q are stored contiguously within the plane
     const int j0 = g.class_start[4 * z + q], j1 = g.class_start[4 * z + q + 1];
-    double a0r = 0, a0i = 0, a1r = 0;
+    double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0, a3r = 0, a3i = 0;
 #pragma unroll 2
     for (int j = j0 + tid; j < j1; j += 256) {
         const uint32_t s = g.site_xyz[j];
@@ -601,26 +641,43 @@ __global__ void __launch_bounds__(256) k_pinv3_ct(const Cx<T>* __restrict__ slab
             const Cx<T> wj = wv[vo + j];
             a0r += (double)wj.re * v.re + (double)wj.im * v.im;
             a0i += (double)wj.re * v.im - (double)wj.im * v.re;
-        } else if (DOT == 2) {
+        } else if (DOT == 2 || DOT == 3) {
             a0r += (double)v.re * xj.re + (double)v.im * xj.im;
             a0i += (double)v.re * xj.im - (double)v.im * xj.re;
             a1r += (double)v.re * v.re + (double)v.im * v.im;
+            if (DOT == 3) {
+                const Cx<T> wj = wv[vo + j];
+                a1i += (double)xj.re * xj.re + (double)xj.im * xj.im;
+                a2r += (double)wj.re * xj.re + (double)wj.im * xj.im;
+                a2i += (double)wj.re * xj.im - (double)wj.im * xj.re;
+                a3r += (double)wj.re * v.re + (double)wj.im * v.im;
+                a3i += (double)wj.re * v.im - (double)wj.im * v.re;
+            }
         }
     }
     if (DOT) {
-        __shared__ double sh[16];
+        __shared__ double sh[8 * 16];
         const int nblk = 12 * N;
         const int blk = (plane % (3 * N)) * 4 + q;
-        const double s0r = block_sum(a0r, sh), s0i = block_sum(a0i, sh);
-        double s1r = 0;
-        if (DOT == 2) s1r = block_sum(a1r, sh);
+        double red[8] = {a0r, a0i, a1r, a1i, a2r, a2i, a3r, a3i};
+        block_sum_n<DOT == 3 ? 8 : (DOT == 2 ? 3 : 2)>(red, sh);
+        const double s0r = red[0], s0i = red[1];
+        const double s1r = DOT >= 2 ? red[2] : 0, s1i = DOT == 3 ? red[3] : 0;
+        const double s2r = DOT == 3 ? red[4] : 0, s2i = DOT == 3 ? red[5] : 0;
+        const double s3r = DOT == 3 ? red[6] : 0, s3i = DOT == 3 ? red[7] : 0;
         if (tid == 0) {
             double* o = partials + ((size_t)rhs * 4 * nblk + blk) * 2;
             o[0] = s0r;
             o[1] = s0i;
-            if (DOT == 2) {
+            if (DOT >= 2) {
                 o[2 * nblk] = s1r;
-                o[2 * nblk + 1] = 0;
+                o[2 * nblk + 1] = s1i;
+            }
+            if (DOT == 3) {
+                o[4 * nblk] = s2r;
+                o[4 * nblk + 1] = s2i;
+                o[6 * nblk] = s3r;
+                o[6 * nblk + 1] = s3i;
             }
         }
     }
@@ -662,8 +719,11 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
             return hipErrorNotSupported;
         } else {
             if (which == 0) {
-                const UpdArgs ua{upd.r, upd.v, upd.p, upd.pout, upd.rhat, upd.st};
-                if (upd.mode == 1)
+                const UpdArgs ua{upd.r, upd.v, upd.p, upd.pout, upd.rhat, upd.st, upd.s, upd.t, upd.x};
+                if (upd.mode == 3)
+                    hipLaunchKernelGGL((k_pfwd_ct<T, N, 3>), dim3(nblk_plane), dim3(plane_threads<N>()),
+                                       (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
+                else if (upd.mode == 1)
                     hipLaunchKernelGGL((k_pfwd_ct<T, N, 1>), dim3(nblk_plane), dim3(plane_threads<N>()),
                                        (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
                 else if (upd.mode == 2)
@@ -675,6 +735,7 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
             } else if (mode == MV_AX) {
                 if (dot == 1) launch_pinv<T, N, MV_AX, 1>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
                 else if (dot == 2) launch_pinv<T, N, MV_AX, 2>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                else if (dot == 3) launch_pinv<T, N, MV_AX, 3>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
                 else launch_pinv<T, N, MV_AX, 0>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
             } else {
                 launch_pinv<T, N, MV_RESID, 0>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
@@ -745,13 +806,17 @@ hipError_t set_attrs_n() {
             e = set_lds_limit((const void*)k_pfwd_ct<T, N, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_pfwd_ct<T, N, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_pfwd_ct<T, N, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         const void* fns[] = {(const void*)k_pinv_ct<T, N, MV_AX, 0>, (const void*)k_pinv_ct<T, N, MV_AX, 1>,
-                             (const void*)k_pinv_ct<T, N, MV_AX, 2>, (const void*)k_pinv_ct<T, N, MV_RESID, 0>};
+                             (const void*)k_pinv_ct<T, N, MV_AX, 2>, (const void*)k_pinv_ct<T, N, MV_AX, 3>,
+                             (const void*)k_pinv_ct<T, N, MV_RESID, 0>};
         for (const void* f : fns)
             if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if constexpr (N == 64) {
             const void* f3[] = {(const void*)k_pinv3_ct<T, N, MV_AX, 0>, (const void*)k_pinv3_ct<T, N, MV_AX, 1>,
-                                (const void*)k_pinv3_ct<T, N, MV_AX, 2>, (const void*)k_pinv3_ct<T, N, MV_RESID, 0>};
+                                (const void*)k_pinv3_ct<T, N, MV_AX, 2>, (const void*)k_pinv3_ct<T, N, MV_AX, 3>,
+                                (const void*)k_pinv3_ct<T, N, MV_RESID, 0>};
             for (const void* f : f3)
                 if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         }

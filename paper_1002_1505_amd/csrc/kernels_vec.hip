@@ -186,16 +186,73 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
 //  which 0: alpha = rho / <rhat, v>       (partials slot 0); breakdown -> alpha = 0, restart
 //  which 1: omega = <t, s> / <t, t>       (slots 0, 1); breakdown -> omega = 0, restart
 //  which 2: rho' = <rhat, r>, rr = <r, r> (slots 0, 1); beta, convergence, iteration count
+//  which 3: the fused end of an iteration that never forms r = s - omega t:
+//           omega from <t, s>, <t, t> (slots 0, 1.re), then
+//           rho' = <rhat, s> - omega <rhat, t> (slots 2, 3) and
+//           rr = ||s||^2 - 2 Re(conj(omega) <t, s>) + |omega|^2 ||t||^2 (slot 1.im),
+//           followed by the which-2 logic; marks the x, r update pending with
+//           the direction in buffer kpar
+__device__ void finish_iteration(BiState& s, double2 a, double2 b, int* active, int rhs) {
+    // a = <rhat, r>, b.x = <r, r>
+    const double2 rho = make_double2(s.rho[0], s.rho[1]);
+    s.it += 1;
+    s.rr = b.x;
+    const double2 al = make_double2(s.alpha[0], s.alpha[1]), om = make_double2(s.omega[0], s.omega[1]);
+    const double rn = sqrt(a.x * a.x + a.y * a.y);
+    if (s.restart || !(rn > 1e-14 * b.x) || (om.x == 0 && om.y == 0)) {
+        s.restart = 1;
+        s.rho[0] = b.x;
+        s.rho[1] = 0;
+    } else {
+        const double2 be = cmul2(cdiv(a, rho), cdiv(al, om));
+        s.beta[0] = be.x;
+        s.beta[1] = be.y;
+        s.rho[0] = a.x;
+        s.rho[1] = a.y;
+    }
+    if (!(b.x > s.tol2)) s.conv = 1;
+    if (s.conv || s.it >= s.maxit || !isfinite(b.x)) active[rhs] = 0;
+}
+
 __global__ void k_scalars(int which, int nblk, BiState* __restrict__ st, const double* __restrict__ partials,
-                          int* __restrict__ active) {
-    __shared__ double sh[16];
+                          int* __restrict__ active, int kpar) {
+    __shared__ double sh[8 * 16];
     const int rhs = blockIdx.x;
     if (!active[rhs]) return;
-    const double2 a = reduce_slot(partials, rhs, 0, nblk, sh);
-    double2 b = make_double2(0, 0);
-    if (which > 0) b = reduce_slot(partials, rhs, 1, nblk, sh);
+    // all slots the step needs in one pass over the block partials
+    const int nslot = which == 0 ? 1 : (which == 3 ? 4 : 2);
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < nslot; ++q) {
+        const double* p = partials + ((size_t)rhs * 4 + q) * nblk * 2;
+        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+            v[2 * q] += p[2 * i];
+            v[2 * q + 1] += p[2 * i + 1];
+        }
+    }
+    block_sum_n<8>(v, sh);
     if (threadIdx.x != 0) return;
+    const double2 a = make_double2(v[0], v[1]), b = make_double2(v[2], v[3]);
+    const double2 c2 = make_double2(v[4], v[5]), d2 = make_double2(v[6], v[7]);
     BiState s = st[rhs];
+    if (which == 3) {
+        // a = <t, s>, b = (<t, t>, <s, s>), c2 = <rhat, s>, d2 = <rhat, t>
+        double2 om = make_double2(0, 0);
+        if (!(b.x > 0)) {
+            s.restart = 1;
+        } else {
+            om = make_double2(a.x / b.x, a.y / b.x);
+            if (om.x == 0 && om.y == 0) s.restart = 1;
+        }
+        s.omega[0] = om.x;
+        s.omega[1] = om.y;
+        const double2 rho2 = make_double2(c2.x - (om.x * d2.x - om.y * d2.y), c2.y - (om.x * d2.y + om.y * d2.x));
+        const double rr = fmax(0.0, b.y - 2.0 * (om.x * a.x + om.y * a.y) + (om.x * om.x + om.y * om.y) * b.x);
+        finish_iteration(s, rho2, make_double2(rr, 0), active, rhs);
+        s.pend = 1;
+        s.pbuf = kpar;
+        st[rhs] = s;
+        return;
+    }
     const double2 rho = make_double2(s.rho[0], s.rho[1]);
     if (which == 0) {
         s.restart = 0;
@@ -219,26 +276,37 @@ __global__ void k_scalars(int which, int nblk, BiState* __restrict__ st, const d
             if (s.omega[0] == 0 && s.omega[1] == 0) s.restart = 1;
         }
     } else {
-        // a = <rhat, r>, b = <r, r>
-        s.it += 1;
-        s.rr = b.x;
-        const double2 al = make_double2(s.alpha[0], s.alpha[1]), om = make_double2(s.omega[0], s.omega[1]);
-        const double rn = sqrt(a.x * a.x + a.y * a.y);
-        if (s.restart || !(rn > 1e-14 * b.x) || (om.x == 0 && om.y == 0)) {
-            s.restart = 1;
-            s.rho[0] = b.x;
-            s.rho[1] = 0;
-        } else {
-            const double2 be = cmul2(cdiv(a, rho), cdiv(al, om));
-            s.beta[0] = be.x;
-            s.beta[1] = be.y;
-            s.rho[0] = a.x;
-            s.rho[1] = a.y;
-        }
-        if (!(b.x > s.tol2)) s.conv = 1;
-        if (s.conv || s.it >= s.maxit || !isfinite(b.x)) active[rhs] = 0;
+        (void)rho;
+        finish_iteration(s, a, b, active, rhs);
     }
     st[rhs] = s;
+}
+
+// Pending x, r update of a fused iteration.
+template <class T>
+__global__ void __launch_bounds__(VT) k_bicg_flush(int V, Cx<T>* __restrict__ x, Cx<T>* __restrict__ r,
+                                                   const Cx<T>* __restrict__ p0, const Cx<T>* __restrict__ p1,
+                                                   const Cx<T>* __restrict__ s, const Cx<T>* __restrict__ t,
+                                                   const BiState* __restrict__ st) {
+    const int rhs = blockIdx.y;
+    const BiState b = st[rhs];
+    if (!b.pend) return;
+    const Cx<T> al = {(T)b.alpha[0], (T)b.alpha[1]}, om = {(T)b.omega[0], (T)b.omega[1]};
+    const Cx<T>* p = b.pbuf ? p1 : p0;
+    const size_t o = (size_t)rhs * V;
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) {
+            const Cx<T> si = s[o + i];
+            x[o + i] = x[o + i] + al * p[o + i] + om * si;
+            r[o + i] = si - om * t[o + i];
+        }
+    }
+}
+
+__global__ void k_clear_pend(BiState* st, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) st[i].pend = 0;
 }
 
 // State initialisation from <r, r> in slot 0.
@@ -262,6 +330,8 @@ __global__ void k_state_init(int nblk, BiState* __restrict__ st, const double* _
     s.maxit = maxit[rhs];
     s.restart = 1;
     s.conv = (a.x <= s.tol2) ? 1 : 0;
+    s.pend = 0;
+    s.pbuf = 0;
     st[rhs] = s;
     active[rhs] = (maxit[rhs] > 0 && !s.conv && a.x > 0) ? 1 : 0;
     if (a.x == 0) st[rhs].conv = 1;
@@ -626,11 +696,25 @@ hipError_t launch_bicg_xr(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p
                        st_, partials, active);
     return hipGetLastError();
 }
-hipError_t launch_scalars(int which, int nblk, int nrhs, BiState* s, const double* partials, int* active,
+hipError_t launch_scalars(int which, int nblk, int nrhs, BiState* s, const double* partials, int* active, int kpar,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_scalars, dim3(nrhs), dim3(256), 0, st, which, nblk, s, partials, active);
+    hipLaunchKernelGGL(k_scalars, dim3(nrhs), dim3(256), 0, st, which, nblk, s, partials, active, kpar);
     return hipGetLastError();
 }
+template <class T>
+hipError_t launch_bicg_flush(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p0, const Cx<T>* p1,
+                             const Cx<T>* s, const Cx<T>* t, BiState* st, hipStream_t stream) {
+    hipLaunchKernelGGL((k_bicg_flush<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, stream, 3 * Npad, x, r, p0, p1,
+                       s, t, st);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_clear_pend, dim3((nrhs + 255) / 256), dim3(256), 0, stream, st, nrhs);
+    return hipGetLastError();
+}
+template hipError_t launch_bicg_flush<float>(int, int, Cx<float>*, Cx<float>*, const Cx<float>*, const Cx<float>*,
+                                             const Cx<float>*, const Cx<float>*, BiState*, hipStream_t);
+template hipError_t launch_bicg_flush<double>(int, int, Cx<double>*, Cx<double>*, const Cx<double>*,
+                                              const Cx<double>*, const Cx<double>*, const Cx<double>*, BiState*,
+                                              hipStream_t);
 template <class T>
 hipError_t launch_bicg_init(int Npad, int nrhs, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* rhat, Cx<T>* p, Cx<T>* v,
                             hipStream_t st) {
