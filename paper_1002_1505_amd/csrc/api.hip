@@ -81,6 +81,7 @@ struct Target {
     FftPlan plans[3];
     DevMem d_xyz, d_comp, d_pstart, d_cstart, d_perm, tw64, tw32, gh64, gh32;
     DevMem gz64, gz32;  // n = 64: spectrum with components interleaved (two-factor z pass)
+    DevMem zt16, zt32;  // n = 64: z-pass tile order per XCD
     bool have64 = false, have32 = false;
     MvShape sh32{}, sh64{};
     Geo geo() const {
@@ -94,6 +95,8 @@ struct Target {
         g.plane_start = d_pstart.as<int>();
         g.class_start = d_cstart.as<int>();
         g.perm = d_perm.as<int>();
+        g.ztiles16 = zt16.as<int>();
+        g.ztiles32 = zt32.as<int>();
         g.site_xyz = d_xyz.as<uint32_t>();
         g.site_comp = d_comp.as<uint8_t>();
         return g;
@@ -286,6 +289,49 @@ MvShape default_shape(const Target& t, int tx_pref) {
     return s;
 }
 
+// Tile order of the two-factor z pass (cubic box of side n, tiles of tx
+// columns of one (parity, ky) row): tiles whose columns fold onto the same
+// tensor-spectrum columns (ky and its mirror, both halves of the row) form a
+// group; groups go whole to the least-loaded XCD, giving [8][tiles / 8].
+std::vector<int> zpass_tile_order(int n, int tx) {
+    const int per_row = n / tx, ntile = 4 * n * n / tx;
+    auto fidx = [n](int k) {
+        const int f = k <= n ? k : 2 * n - k;
+        return (f & 1) * (n / 2 + 1) + (f >> 1);
+    };
+    std::vector<std::vector<int>> groups;
+    for (int par = 0; par < 4; ++par) {
+        const int py = par >> 1;
+        std::vector<int> done(n + 2, 0);
+        for (int kyp = 0; kyp < n; ++kyp) {
+            const int kyi = fidx(2 * kyp + py);
+            if (done[kyi]) continue;
+            done[kyi] = 1;
+            std::vector<int> g;
+            for (int k = 0; k < n; ++k)
+                if (fidx(2 * k + py) == kyi)
+                    for (int h = 0; h < per_row; ++h) g.push_back((par * n * n + k * n) / tx + h);
+            groups.push_back(g);
+        }
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const std::vector<int>& a, const std::vector<int>& b) {
+        return a.size() > b.size();
+    });
+    std::vector<std::vector<int>> lists(8);
+    for (auto& g : groups) {
+        int x = 0;
+        for (int i = 1; i < 8; ++i)
+            if (lists[i].size() < lists[x].size()) x = i;
+        lists[x].insert(lists[x].end(), g.begin(), g.end());
+    }
+    std::vector<int> out;
+    for (auto& l : lists) {
+        if ((int)l.size() != ntile / 8) return {};  // unbalanced: not used
+        out.insert(out.end(), l.begin(), l.end());
+    }
+    return out;
+}
+
 dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint8_t* occ, int32_t ncomp,
                         const double* m, double kd, int32_t alpha_kind, const double* origin) {
     if (!dims || !occ || !m || ncomp < 1 || ncomp > 255)
@@ -368,6 +414,17 @@ dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint
     HCHK(c, hipMemcpy(t.d_pstart.p, ps.data(), ps.size() * 4, hipMemcpyHostToDevice));
     HCHK(c, hipMemcpy(t.d_cstart.p, cs.data(), cs.size() * 4, hipMemcpyHostToDevice));
     HCHK(c, hipMemcpy(t.d_perm.p, perm.data(), perm.size() * 4, hipMemcpyHostToDevice));
+    t.zt16.release();
+    t.zt32.release();
+    if (n1 == 64 && n2 == 64 && n3 == 64) {
+        for (int tx : {16, 32}) {
+            const std::vector<int> order = zpass_tile_order(64, tx);
+            if (order.empty()) return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "z-pass tile order unbalanced");
+            DevMem& d = tx == 16 ? t.zt16 : t.zt32;
+            HCHK(c, d.ensure(order.size() * 4));
+            HCHK(c, hipMemcpy(d.p, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+        }
+    }
     // twiddles: f_i (n_i) then h_i (n_i)
     std::vector<Cx<double>> tw;
     for (int i = 0; i < 3; ++i)

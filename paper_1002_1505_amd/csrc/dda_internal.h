@@ -20,6 +20,11 @@ struct Geo {
     const uint32_t* site_xyz;  // x | y << 10 | z << 20
     const uint8_t* site_comp;  // 0-based composition index
     const int* perm;           // [N]: position of each stored site in the (z, y, x) scan order
+    // n = 64: z-pass tile order per XCD for tiles of 16 and 32 columns,
+    // [8][tiles / 8]; the tiles that share tensor-spectrum columns through
+    // the x and y folds are adjacent on one XCD (nullptr for other boxes)
+    const int* ztiles16;
+    const int* ztiles32;
 };
 
 // Twiddle tables of one target: f_i[k] = exp(-2 pi i k / n_i) (k < n_i) and

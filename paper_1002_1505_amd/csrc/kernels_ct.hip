@@ -297,11 +297,14 @@ __global__ void __launch_bounds__(zpass_threads<N>()) k_zpass2_ct(Cx<T>* __restr
 // components by the 3 x 3 tensor spectrum at kz = 2 k + pz for both
 // frequency parities pz; the parity-1 input is pre-twiddled by h3 and its
 // output post-twiddled by conj(h3).  One block per (tile of TX columns, rhs);
-// the blocks of one tile for all rhs share an XCD (block index mod 8).  gh is
-// the spectrum with the 6 components of each frequency adjacent.
+// block b runs on XCD b mod 8 and takes, in the order of that XCD's tile
+// list, every rhs of one tile before the next tile, so that the tiles sharing
+// tensor-spectrum columns read them from one L2.  gh is the spectrum with the
+// 6 components of each frequency adjacent.
 template <class T, int N, int TX>
 __global__ void __launch_bounds__(TX * 8) k_zpass3_ct(Cx<T>* __restrict__ slab, const Cx<T>* __restrict__ gh,
-                                                      Tw<T> tw, int nrhs, const int* __restrict__ active) {
+                                                      Tw<T> tw, int nrhs, const int* __restrict__ active,
+                                                      const int* __restrict__ tiles) {
     static_assert(N == 64, "two-factor z pass is written for N = 64");
     constexpr int R = 8;
     constexpr int NCOL = 4 * N * N;
@@ -309,10 +312,11 @@ __global__ void __launch_bounds__(TX * 8) k_zpass3_ct(Cx<T>* __restrict__ slab, 
     constexpr int D = 2 * H;
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* X = reinterpret_cast<Cx<T>*>(smem_raw);  // [a][k2][z1][c]
+    constexpr int PER_XCD = 4 * N * N / TX / 8;
     const int b = blockIdx.x;
-    const int rest = b >> 3;
-    const int r = rest % nrhs;
-    const int tile = (rest / nrhs) * 8 + (b & 7);
+    const int pos = b >> 3;
+    const int r = pos % nrhs;
+    const int tile = tiles[(b & 7) * PER_XCD + pos / nrhs];
     if (active && !active[r]) return;
     const int tid = threadIdx.x;
     const int c = tid % TX, j = tid / TX;  // j: z1 in the outer steps, k2 in the inner ones
@@ -753,8 +757,10 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
         if constexpr (zpass3_lds<T, N, TXV>() > LDS_MAX) {                                                         \
             return hipErrorNotSupported;                                                                           \
         } else {                                                                                                   \
+            const int* tl = TXV == 16 ? g.ztiles16 : g.ztiles32;                                               \
+            if (!tl) return hipErrorNotSupported;                                                              \
             hipLaunchKernelGGL((k_zpass3_ct<T, N, TXV>), dim3(nrhs * (ntile / TXV)), dim3(TXV * 8),               \
-                               (zpass3_lds<T, N, TXV>()), st, slab, ghat, tw, nrhs, active);                        \
+                               (zpass3_lds<T, N, TXV>()), st, slab, ghat, tw, nrhs, active, tl);                    \
             return hipGetLastError();                                                                              \
         }                                                                                                          \
     }
