@@ -144,7 +144,7 @@ class Context:
         opts = L.dda_solve_opts(tol=tol, max_iter=max_iter, guess=guess, prec=prec, flags=flags,
                                 graph_iters=graph_iters, history=history)
         tg = [arr[i].target for i in range(n)]
-        sizes = [self.n_sites[t] for t in tg]
+        sizes = [self.n_sites.get(t, 0) for t in tg]  # unknown ids: the library rejects the call
         p0buf = None
         if p0 is not None:
             p0buf = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.complex128).reshape(-1) for p in p0]))
