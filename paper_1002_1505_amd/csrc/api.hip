@@ -1208,8 +1208,11 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
                 all_done = false;
                 sc[s] = 1.0 / std::sqrt(rr);
                 double tin;
-                if (prec == DDA_SOLVE_FP32_REFINE) tin = std::min(0.5, std::max(2e-6, 0.3 * tol / rl));
-                else tin = std::min(0.5, std::max(1e-15, 0.3 * tol / rl));
+                // inner target below the outer one by the drift the inner
+                // recursive residual can have from the FP64 residual: larger
+                // for FP32 vectors; a miss costs one short extra refinement
+                if (prec == DDA_SOLVE_FP32_REFINE) tin = std::min(0.5, std::max(2e-6, 0.6 * tol / rl));
+                else tin = std::min(0.5, std::max(1e-15, 0.9 * tol / rl));
                 tr2[s] = tin * tin;
                 mi[s] = max_iter - iters[i];
             }
