@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--train-targets", type=int, default=16)
     ap.add_argument("--train-orient", type=int, default=32)
     ap.add_argument("--nn-width", type=int, default=16)
-    ap.add_argument("--nn-depth", type=int, default=6)
+    ap.add_argument("--nn-depth", type=int, default=4)
     ap.add_argument("--history", type=int, default=3, help="solutions kept per slot for the least-squares guess")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--eval-targets", type=int, default=2)
@@ -155,7 +155,7 @@ def main():
     sh = ctx.get_shape(0, P.DDA_FP32)
     if sh["ct"] & 1:
         zname = {0: f"k_zpass_ct<float, {n}, {sh['tx']}>", 1: f"k_zpass2_ct<float, {n}, {sh['tx']}, 8>",
-                 2: f"k_zpass3_ct<float, {n}, {sh['tx']}>"}[sh["zrb"]]
+                 2: f"k_zpass3_ct<float, {n}, {sh['tx']}>", 3: f"k_zpass4_ct<float, {n}, {sh['tx']}>"}[sh["zrb"]]
         iname = "k_pinv3_ct" if sh["ct"] & 4 else "k_pinv_ct"
         names = [f"k_pfwd_ct<float, {n}, 0|1|2>", zname, f"{iname}<float, {n}, 0, 0|1|2>"]
     else:

@@ -258,7 +258,8 @@ dda_status dda_last_guess_ms(const dda_ctx* ctx, double* ms);
  * columns, fallback lines per block, fallback threads, specialised kernels
  * bitmask (1 plane passes, 2 z pass, 4 two-factor inverse plane pass for
  * n = 64), z pass variant (0 one rhs per block, 1 up to 8 rhs per block with
- * the spectrum in registers, 2 two-factor 8 x 8 pass for n = 64)}.
+ * the spectrum in registers, 2 two-factor 8 x 8 pass for n = 64, 3 the same
+ * with the two frequency parities in the two halves of a block)}.
  * dda_set_shape rejects shapes that do
  * not fit the kernels' LDS or thread limits. */
 dda_status dda_get_shape(const dda_ctx* ctx, int32_t target, uint32_t prec, int32_t* out8);

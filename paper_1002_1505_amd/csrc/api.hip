@@ -123,7 +123,7 @@ struct Target {
     // spectrum layout the launch shape's z pass reads
     template <class T>
     const Cx<T>* ghat_for(const MvShape& sh) const {
-        if ((sh.ct & 2) && sh.zrb == 2)
+        if ((sh.ct & 2) && sh.zrb >= 2)
             return std::is_same<T, double>::value ? gz64.as<Cx<T>>() : gz32.as<Cx<T>>();
         return ghat<T>();
     }
@@ -273,13 +273,16 @@ MvShape default_shape(const Target& t, int tx_pref) {
         // a generic z pass needs its own thread count for the chosen tile
         c.zrb = (c.ct & 2) ? 1 : 0;
         if (c.ct && matvec_shape_ok<T>(g, t.plans, c)) s = c;
-        // n = 64: the two-factor z pass (32-column tiles where they fit LDS)
-        for (int txc : {32, 16}) {
+        // n = 64: the two-factor z pass; in FP32 the variant with one
+        // frequency parity per block half (16-column tiles, more waves per
+        // SIMD), in FP64 one parity after the other (32-column tiles)
+        const int zv[2][2] = {{3, 16}, {2, 32}};
+        for (int v = std::is_same<T, double>::value ? 1 : 0; v < 2; ++v) {
             MvShape c3 = s;
-            c3.tx = txc;
+            c3.tx = zv[v][1];
             // two-factor inverse plane pass: faster in FP64, on par in FP32
-            c3.ct = (ct_available<T>(g.n1, txc) | (s.ct & 1)) & (std::is_same<T, double>::value ? 7 : 3);
-            c3.zrb = 2;
+            c3.ct = (ct_available<T>(g.n1, c3.tx) | (s.ct & 1)) & (std::is_same<T, double>::value ? 7 : 3);
+            c3.zrb = zv[v][0];
             if (matvec_shape_ok<T>(g, t.plans, c3)) {
                 s = c3;
                 break;
@@ -1657,7 +1660,7 @@ std::vector<MvShape> shape_candidates(const Target& t) {
     const MvShape base = default_shape<T>(t, 16);
     if (ct_supported(g.n1, g.n2, g.n3)) {
         for (int tx : {8, 16, 32})
-            for (int zrb : {0, 1, 2})
+            for (int zrb : {0, 1, 2, 3})
                 for (int pv : {0, 4}) {  // inverse plane pass variant
                     MvShape c = base;
                     c.tx = tx;

@@ -64,7 +64,8 @@ struct MvShape {
     int ct;          // bit 0: specialised plane kernels, bit 1: specialised z pass (cubic boxes),
                      // bit 2: two-factor inverse plane pass (n = 64, with bit 0)
     int zrb;         // specialised z pass variant: 0 = one rhs per block, 1 = loop over up to 8 rhs per
-                     // block with the spectrum in registers, 2 = two-factor 8 x 8 pass (n = 64)
+                     // block with the spectrum in registers, 2 = two-factor 8 x 8 pass (n = 64),
+                     // 3 = two-factor pass with one frequency parity per block half (n = 64)
 };
 
 // Optional BiCGstab vector update fused into the first matvec pass

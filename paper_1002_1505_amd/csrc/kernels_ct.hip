@@ -419,6 +419,130 @@ __global__ void __launch_bounds__(TX * 8) k_zpass3_ct(Cx<T>* __restrict__ slab, 
         for (int z2 = 0; z2 < R; ++z2) base[o0 + (uint32_t)(a * N + R * z2) * NCOL] = acc[a][z2];
 }
 
+// The same two-factor z pass with the two frequency parities in the two
+// halves of the block (threads pz * 8 TX + ...): each half runs its parity
+// through its own LDS exchange buffer, and the parity-1 half hands its
+// post-twiddled output to the parity-0 half through LDS.  Each thread then
+// carries one parity's state, which halves the registers of the
+// single-half version and raises the waves per SIMD.
+template <class T, int N, int TX>
+__global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab, const Cx<T>* __restrict__ gh,
+                                                       Tw<T> tw, int nrhs, const int* __restrict__ active,
+                                                       const int* __restrict__ tiles) {
+    static_assert(N == 64, "two-factor z pass is written for N = 64");
+    constexpr int R = 8;
+    constexpr int NCOL = 4 * N * N;
+    constexpr int H = N / 2 + 1;
+    constexpr int D = 2 * H;
+    constexpr int XS = 3 * N * TX;  // one exchange buffer [a][k2][z1][c]
+    constexpr int PER_XCD = 4 * N * N / TX / 8;
+    extern __shared__ unsigned char smem_raw[];
+    const int b = blockIdx.x;
+    const int pos = b >> 3;
+    const int r = pos % nrhs;
+    const int tile = tiles[(b & 7) * PER_XCD + pos / nrhs];
+    if (active && !active[r]) return;
+    const int tid = threadIdx.x;
+    const int pz = tid / (TX * R);
+    const int tt = tid % (TX * R);
+    const int c = tt % TX, j = tt / TX;  // j: z1 in the outer steps, k2 in the inner ones
+    Cx<T>* X = reinterpret_cast<Cx<T>*>(smem_raw) + pz * XS;
+    const int q0 = tile * TX;
+    const int par = q0 / (N * N), rem = q0 % (N * N);
+    const int px = par & 1, py = par >> 1;
+    const int kyp = rem / N, kx0 = rem % N;
+    int sx, sy;
+    const int kxi = fold_idx(2 * (kx0 + c) + px, N, sx);
+    const int kyi = fold_idx(2 * kyp + py, N, sy);
+    const T sxy = (T)(sx * sy);
+    Cx<T> w[R];  // w_N^(j m)
+#pragma unroll
+    for (int m = 0; m < R; ++m) w[m] = tw.f3[j * m];
+    Cx<T>* base = slab + (size_t)r * 3 * N * NCOL;
+    const uint32_t o0 = (uint32_t)j * NCOL + q0 + c;
+    // forward, outer factor: thread (c, z1 = j) of half pz
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Cx<T> u[R];
+#pragma unroll
+        for (int z2 = 0; z2 < R; ++z2) {
+            u[z2] = base[o0 + (uint32_t)(a * N + R * z2) * NCOL];
+            if (pz) u[z2] = u[z2] * tw.h3[j + R * z2];
+        }
+        bfly<T, -1, R>(u);
+#pragma unroll
+        for (int k2 = 0; k2 < R; ++k2) X[((a * R + k2) * R + j) * TX + c] = k2 ? u[k2] * w[k2] : u[k2];
+    }
+    __syncthreads();
+    // inner factor, tensor product, inverse inner factor: thread (c, k2 = j)
+    {
+        Cx<T> f[3][R];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int z1 = 0; z1 < R; ++z1) f[a][z1] = X[((a * R + j) * R + z1) * TX + c];
+            bfly<T, -1, R>(f[a]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) {
+            const int kz = 2 * (j + R * k1) + pz;
+            const bool mir = kz > N;
+            const int kzf = mir ? 2 * N - kz : kz;
+            const T sz = mir ? (T)-1 : (T)1;
+            const uint32_t gi = ((uint32_t)(pz * H + (kzf >> 1)) * D + kyi) * D + kxi;
+            Cx<T> gg[6];
+            if constexpr (sizeof(T) == 4) {
+                const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)gi * 3;
+                const float4 v0 = gp[0], v1 = gp[1], v2 = gp[2];
+                gg[0] = Cx<T>{v0.x, v0.y};
+                gg[1] = Cx<T>{v0.z, v0.w};
+                gg[2] = Cx<T>{v1.x, v1.y};
+                gg[3] = Cx<T>{v1.z, v1.w};
+                gg[4] = Cx<T>{v2.x, v2.y};
+                gg[5] = Cx<T>{v2.z, v2.w};
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < 6; ++qq) gg[qq] = gh[(size_t)gi * 6 + qq];
+            }
+            const Cx<T> gxx = gg[0], gxy = sxy * gg[1], gxz = ((T)sx * sz) * gg[2];
+            const Cx<T> gyy = gg[3], gyz = ((T)sy * sz) * gg[4], gzz = gg[5];
+            const Cx<T> a0 = f[0][k1], a1 = f[1][k1], a2 = f[2][k1];
+            f[0][k1] = gxx * a0 + gxy * a1 + gxz * a2;
+            f[1][k1] = gxy * a0 + gyy * a1 + gyz * a2;
+            f[2][k1] = gxz * a0 + gyz * a1 + gzz * a2;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            bfly<T, +1, R>(f[a]);
+#pragma unroll
+            for (int z1 = 0; z1 < R; ++z1)
+                X[((a * R + j) * R + z1) * TX + c] = z1 ? cmulc(w[z1], f[a][z1]) : f[a][z1];
+        }
+    }
+    __syncthreads();
+    // inverse, outer factor: thread (c, z1 = j).  The parity-1 half writes its
+    // post-twiddled output into the slots it has just read.
+    Cx<T> u[3][R];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int k2 = 0; k2 < R; ++k2) u[a][k2] = X[((a * R + k2) * R + j) * TX + c];
+        bfly<T, +1, R>(u[a]);
+        if (pz)
+#pragma unroll
+            for (int z2 = 0; z2 < R; ++z2)
+                X[((a * R + z2) * R + j) * TX + c] = cmulc(tw.h3[j + R * z2], u[a][z2]);
+    }
+    __syncthreads();
+    if (pz) return;
+    const Cx<T>* X1 = reinterpret_cast<const Cx<T>*>(smem_raw) + XS;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int z2 = 0; z2 < R; ++z2)
+            base[o0 + (uint32_t)(a * N + R * z2) * NCOL] = u[a][z2] + X1[((a * R + z2) * R + j) * TX + c];
+}
+
 // DOT = 1: per-block partial sums of conj(w_j) . y_j (slot 0); DOT = 2:
 // conj(y_j) . x_j (slot 0) and |y_j|^2 (slot 1); DOT = 3: as DOT = 2 with
 // |x_j|^2 in the imaginary part of slot 1, conj(w_j) . x_j (slot 2) and
@@ -693,6 +817,8 @@ template <class T, int N, int TX>
 constexpr size_t zpass_lds() { return (size_t)(N + 6 * N * TX) * sizeof(Cx<T>); }
 template <class T, int N, int TX>
 constexpr size_t zpass3_lds() { return (size_t)3 * N * TX * sizeof(Cx<T>); }
+template <class T, int N, int TX>
+constexpr size_t zpass4_lds() { return (size_t)2 * 3 * N * TX * sizeof(Cx<T>); }
 constexpr size_t LDS_MAX = 160 * 1024;
 
 template <class T, int N, int MODE, int DOT>
@@ -748,6 +874,20 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
         }
     }
     const int ntile = 4 * N * N;
+    if (zrb == 3) {
+        if constexpr (N != 64) {
+            return hipErrorNotSupported;
+        } else {
+            if (tx != 16 || !g.ztiles16) return hipErrorNotSupported;
+            if constexpr (zpass4_lds<T, N, 16>() > LDS_MAX) {
+                return hipErrorNotSupported;
+            } else {
+                hipLaunchKernelGGL((k_zpass4_ct<T, N, 16>), dim3(nrhs * (ntile / 16)), dim3(16 * 16),
+                                   (zpass4_lds<T, N, 16>()), st, slab, ghat, tw, nrhs, active, g.ztiles16);
+                return hipGetLastError();
+            }
+        }
+    }
     if (zrb == 2) {
         if constexpr (N != 64) {
             return hipErrorNotSupported;
@@ -847,6 +987,8 @@ hipError_t set_attrs_n() {
     }
     if constexpr (N == 64) {
         if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_zpass4_ct<T, N, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass3_ct<T, N, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if constexpr (zpass3_lds<T, N, 32>() <= LDS_MAX)
             if (e == hipSuccess)
@@ -901,6 +1043,7 @@ template <class T>
 bool ct_zpass_fits(int n, int tx, int zrb) {
     if (!ct_supported(n, n, n) || !(tx == 8 || tx == 16 || tx == 32) || n % tx) return false;
     if (zrb == 2) return n == 64 && tx >= 16 && (size_t)3 * n * tx * sizeof(Cx<T>) <= LDS_MAX;
+    if (zrb == 3) return n == 64 && tx == 16 && (size_t)6 * n * tx * sizeof(Cx<T>) <= LDS_MAX;
     return (zrb == 0 || zrb == 1) && (size_t)(n + 6 * n * tx) * sizeof(Cx<T>) <= LDS_MAX;
 }
 
