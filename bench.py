@@ -32,8 +32,8 @@ METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM 
 # (FETCH x 1.99974, WRITE x 1.0); valid only while the kernel source is the
 # one measured (SHA-256 prefix of the file that holds the kernel).
 MEASURED_TRAFFIC = {
-    "k_zpass3_ct<float, 64, 32>": {"source": "paper_1002_1505_amd/csrc/kernels_ct.hip",
-                                   "sha256": "fbec2f0479fe53e0", "fetch_kib": 37131.2, "write_kib": 49152.0,
+    "k_zpass4_ct<float, 64, 16>": {"source": "paper_1002_1505_amd/csrc/kernels_ct.hip",
+                                   "sha256": "b265628890a9dbd8", "fetch_kib": 31967.6, "write_kib": 49152.0,
                                    "fetch_scale": 1.99974, "write_scale": 1.0},
 }
 
