@@ -25,6 +25,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA
 METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM peak"
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
@@ -319,6 +320,13 @@ def learned_vs_plain(P, ctx, a):
                      "converged": f"{conv}/{n_solves}",
                      "mean_guess_resid": round(float(np.mean(resid[mode])), 4) if resid[mode] else 1.0,
                      "guess_ms_per_solve": round(guess_ms[mode] / max(1, n_solves // 2 - a.eval_targets), 3)}
+    # the network's kernels against the BF16 MFMA roof (device-resident
+    # pseudo-random inputs on the same box, 2 samples = the 2 polarizations)
+    f_ms, b_ms, gflop = net.profile(64, 2, 10)
+    out["net_roofline"] = {"bound": "mfma", "achieved": round(gflop / f_ms, 1), "peak": BF16_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(gflop / f_ms / BF16_PEAK_TFLOPS, 4),
+                           "forward_ms_2_samples": round(f_ms, 4), "backward_ms_2_samples": round(b_ms, 4),
+                           "forward_gflop": round(gflop, 2)}
     for base in ("zero", "prev", "prev_shift", "project"):
         out[f"nn_vs_{base}"] = round(out["nn"]["solves_per_s"] / out[base]["solves_per_s"], 3)
     net.close()

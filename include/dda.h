@@ -336,6 +336,15 @@ dda_status dda_nn_load(dda_nn* nn, const char* path);
  * squared error over the first nout channels normalised per sample by the
  * target's squared norm, averaged over samples, and its parameter gradients
  * (flat, as dda_nn_get_params). */
+/* Timing hook: forward passes and parameter-gradient passes of the network
+ * on ns (1..8) samples of a D^3 box (D a multiple of 16) of device-resident
+ * pseudo-random BF16 features and output gradients, reps times each (HIP
+ * events on the null stream).  Mean milliseconds per forward (*ms_fwd) and
+ * per backward (*ms_bwd) pass over the ns samples, and the forward pass's
+ * dense GFLOP (2 x 27 cin cout D^3 ns summed over layers, *gflop_fwd); any
+ * pointer may be NULL.  Overwrites the network's activation buffers. */
+dda_status dda_nn_profile(dda_nn* nn, int32_t D, int32_t ns, int32_t reps, double* ms_fwd, double* ms_bwd,
+                          double* gflop_fwd);
 dda_status dda_nn_forward_backward(dda_nn* nn, int32_t ns, int32_t D, const float* x_in, const float* target,
                                    const uint8_t* mask, int32_t nout, float* out, float* grads, double* loss);
 

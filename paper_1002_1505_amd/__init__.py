@@ -363,6 +363,13 @@ class Net:
     def load(self, path):
         _check(None, self.lib.dda_nn_load(self.h, path.encode()))
 
+    def profile(self, D=64, ns=2, reps=10):
+        """(ms per forward, ms per parameter-gradient pass, forward GFLOP) on ns
+        device-resident D^3 samples."""
+        a, b, g = C.c_double(), C.c_double(), C.c_double()
+        _check(None, self.lib.dda_nn_profile(self.h, int(D), int(ns), int(reps), C.byref(a), C.byref(b), C.byref(g)))
+        return a.value, b.value, g.value
+
     def forward_backward(self, x, target=None, mask=None, nout=6):
         """x: (ns, D, D, D, 16) float32; returns (out, grads as [(dW, db)], loss)."""
         x = np.ascontiguousarray(x, dtype=np.float32)

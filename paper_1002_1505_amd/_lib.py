@@ -112,6 +112,7 @@ SIGNATURES = {
     "dda_nn_load": (C.c_int32, [P, C.c_char_p]),
     "dda_nn_forward_backward": (C.c_int32, [P, C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float),
                                             P, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float), D]),
+    "dda_nn_profile": (C.c_int32, [P, C.c_int32, C.c_int32, C.c_int32, D, D, D]),
 }
 
 _lib = None

@@ -211,22 +211,32 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t* __restrict__ X, c
     }
 }
 
+// g[e] += sum over block partials; blockIdx.y takes a chunk of RCH blocks and
+// adds its sum atomically (the order of the chunk sums is not fixed).
+// x-rows per weight-gradient block (enough blocks to fill the chip)
+constexpr int WG_ROWS = 8;
+constexpr int RCH = 32;
 __global__ void k_reduce_partials(const float* __restrict__ partials, int nblk, int n, float* __restrict__ g) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
+    const int b0 = blockIdx.y * RCH, b1 = min(nblk, b0 + RCH);
     float acc = 0;
-    for (int b = 0; b < nblk; ++b) acc += partials[(size_t)b * n + e];
-    g[e] += acc;
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) acc += partials[(size_t)b * n + e];
+    atomicAdd(g + e, acc);
 }
 
-// db[co] += sum over voxels and samples of dY[.][co]
+// db[co] += sum over voxels and samples of dY[.][co]; blockIdx.y takes a
+// chunk of the voxels and adds its sum atomically.
 __global__ void k_bias_grad(const uint16_t* __restrict__ dY, int nvox, int NC, float* __restrict__ g) {
     __shared__ double sh[16];
     const int co = blockIdx.x;
+    const int per = (nvox + gridDim.y - 1) / gridDim.y;
+    const int v0 = blockIdx.y * per, v1 = min(nvox, v0 + per);
     double acc = 0;
-    for (int v = threadIdx.x; v < nvox; v += blockDim.x) acc += bf2f(dY[(size_t)v * NC + co]);
+    for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) acc += bf2f(dY[(size_t)v * NC + co]);
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) g[co] += (float)acc;
+    if (threadIdx.x == 0) atomicAdd(g + co, (float)acc);
 }
 
 // Adam with decoupled weight decay on FP32 master weights; refreshes the two
@@ -274,6 +284,18 @@ struct SampleDev {
 
 __global__ void k_zero16(uint16_t* __restrict__ p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Pseudo-random BF16 values in [-0.5, 0.5) (integer hash of index and seed),
+// inputs of the timing hook.
+__global__ void k_rand16(uint16_t* __restrict__ p, size_t n, uint32_t seed) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+        h ^= h >> 16;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        p[i] = f2bf((float)h * 2.3283064365386963e-10f - 0.5f);
+    }
 }
 
 __global__ void k_features(const SampleDev* __restrict__ sd, int D, uint16_t* __restrict__ X) {
@@ -472,7 +494,8 @@ hipError_t wgrad_launch(const uint16_t* X, const uint16_t* dY, float* partials, 
     hipLaunchKernelGGL((k_wgrad<KC, NC>), dim3(nbx, ns), dim3(256), lds, st, X, dY, partials, D, dil, rows_per_block);
     NCHK(hipGetLastError());
     const int n = 27 * KC * NC;
-    hipLaunchKernelGGL(k_reduce_partials, dim3((n + 255) / 256), dim3(256), 0, st, partials, nbx * ns, n, g);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((n + 255) / 256, (nbx * ns + RCH - 1) / RCH), dim3(256), 0, st,
+                       partials, nbx * ns, n, g);
     return hipGetLastError();
 }
 
@@ -517,7 +540,7 @@ hipError_t nn_buffers(dda_nn* nn, int D, int ns) {
     const int wmax = std::max(nn->width, 16);
     NCHK(nn->dA.ensure(V * ns * wmax * 2));
     NCHK(nn->dB.ensure(V * ns * wmax * 2));
-    NCHK(nn->partials.ensure((size_t)ns * D * 27 * wmax * wmax * 4));
+    NCHK(nn->partials.ensure((size_t)ns * ((D * D + WG_ROWS - 1) / WG_ROWS) * 27 * wmax * wmax * 4));
     NCHK(nn->lossacc.ensure(ns * sizeof(double)));
     NCHK(nn->sdev.ensure(ns * sizeof(SampleDev)));
     nn->D = D;
@@ -553,7 +576,7 @@ hipError_t nn_backward(dda_nn* nn, int ns, hipStream_t st) {
     uint16_t* gcur = nn->dA.as<uint16_t>();
     uint16_t* gnext = nn->dB.as<uint16_t>();
     const int D = nn->D;
-    const int rpb = D;  // one z-plane of rows per block
+    const int rpb = WG_ROWS;
     for (int l = (int)nn->layers.size() - 1; l >= 0; --l) {
         const Layer& L = nn->layers[l];
         const uint16_t* X = nn->act[l].as<uint16_t>();
@@ -564,7 +587,7 @@ hipError_t nn_backward(dda_nn* nn, int ns, hipStream_t st) {
         else if (L.cin == W && L.cout == W) NCHK((wgrad_launch<W, W>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
         else if (L.cin == W && L.cout == 16) NCHK((wgrad_launch<W, 16>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
         else NCHK((wgrad_launch<16, 16>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
-        hipLaunchKernelGGL(k_bias_grad, dim3(L.cout), dim3(256), 0, st, gcur, D * D * D * ns, L.cout, gb);
+        hipLaunchKernelGGL(k_bias_grad, dim3(L.cout, 64), dim3(256), 0, st, gcur, D * D * D * ns, L.cout, gb);
         NCHK(hipGetLastError());
         if (l == 0) break;
         // data gradient, masked by the ReLU of this layer's input
@@ -839,6 +862,44 @@ dda_status dda_nn_layer_info(const dda_nn* nn, int32_t* out3 /* depth x {cin, co
         out3[3 * l + 2] = nn->layers[l].dil;
     }
     return DDA_OK;
+}
+
+dda_status dda_nn_profile(dda_nn* nn, int32_t D, int32_t ns, int32_t reps, double* ms_fwd, double* ms_bwd,
+                          double* gflop_fwd) {
+    if (!nn || D < 16 || D % 16 || ns < 1 || ns > 8 || reps < 1) return DDA_ERR_INVALID_ARG;
+    hipStream_t st = nullptr;
+    if (nn_buffers(nn, D, ns) != hipSuccess) return DDA_ERR_OOM;
+    const size_t V = (size_t)D * D * D;
+    hipLaunchKernelGGL(k_rand16, dim3(1024), dim3(256), 0, st, nn->act[0].as<uint16_t>(), V * ns * 16, 12345u);
+    hipLaunchKernelGGL(k_rand16, dim3(1024), dim3(256), 0, st, nn->dA.as<uint16_t>(), V * ns * 16, 777u);
+    if (hipGetLastError() != hipSuccess) return DDA_ERR_HIP;
+    double flop = 0;
+    for (const Layer& L : nn->layers) flop += 2.0 * 27.0 * L.cin * L.cout * (double)V * ns;
+    if (gflop_fwd) *gflop_fwd = flop * 1e-9;
+    hipEvent_t e0, e1, e2;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || hipEventCreate(&e2) != hipSuccess)
+        return DDA_ERR_HIP;
+    dda_status rc = DDA_OK;
+    if (nn_forward_any(nn, ns, st) != hipSuccess) rc = DDA_ERR_HIP;  // warm-up
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps && rc == DDA_OK; ++i)
+        if (nn_forward_any(nn, ns, st) != hipSuccess) rc = DDA_ERR_HIP;
+    (void)hipEventRecord(e1, st);
+    for (int i = 0; i < reps && rc == DDA_OK; ++i) {
+        (void)hipMemsetAsync(nn->g.p, 0, nn->nparams * 4, st);
+        if (nn_backward_any(nn, ns, st) != hipSuccess) rc = DDA_ERR_HIP;
+    }
+    (void)hipEventRecord(e2, st);
+    if (hipEventSynchronize(e2) != hipSuccess) rc = DDA_ERR_HIP;
+    float a = 0, b = 0;
+    (void)hipEventElapsedTime(&a, e0, e1);
+    (void)hipEventElapsedTime(&b, e1, e2);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    if (ms_fwd) *ms_fwd = a / reps;
+    if (ms_bwd) *ms_bwd = b / reps;
+    return rc;
 }
 
 dda_status dda_nn_forward_backward(dda_nn* nn, int32_t ns, int32_t D, const float* x_in, const float* target,

@@ -146,3 +146,19 @@ def test_training_lowers_guess_residual_on_its_sweep():
     assert res["nn"] < res["project"], res
     net.close()
     ctx.close()
+
+
+def test_profile_hook_counts_flops_and_times():
+    """The timing hook reports positive times and the dense forward FLOP count
+    2 x 27 x cin x cout x D^3 x samples summed over the layers."""
+    import paper_1002_1505_amd as P
+
+    ctx = P.Context(0)
+    net = P.Net(ctx, width=16, depth=4, seed=2)
+    f_ms, b_ms, gflop = net.profile(32, 2, 2)
+    expect = sum(2.0 * 27 * cin * cout * 32 ** 3 * 2 for cin, cout, _ in net.layers()) * 1e-9
+    assert f_ms > 0 and b_ms > 0 and abs(gflop - expect) < 1e-9 * expect
+    with pytest.raises(P.DDAError):
+        net.profile(24, 2, 1)  # box side not a multiple of 16
+    net.close()
+    ctx.close()
