@@ -1400,15 +1400,16 @@ dda_status dda_amplitudes(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* 
     if (nrhs != c->last_nrhs || ndir <= 0 || !n_tf || !e_tf || !f)
         return fail(c, DDA_ERR_INVALID_ARG, "amplitudes: bad arguments");
     hipStream_t st = c->stream;
-    DevMem dn, dF;
+    DevMem dn, dF, dP;
     HCHK(c, dn.ensure((size_t)ndir * 3 * sizeof(double)));
     HCHK(c, hipMemcpyAsync(dn.p, n_tf, (size_t)ndir * 3 * sizeof(double), hipMemcpyHostToDevice, st));
     for (auto& gp : c->groups) {
         Group& g = *gp;
         Target& t = *c->tg[g.tgt];
         HCHK(c, dF.ensure((size_t)g.nr * ndir * 3 * sizeof(Cx<double>)));
+        HCHK(c, dP.ensure((size_t)ampl_chunks(ndir, g.nr, t.N) * g.nr * ndir * 6 * sizeof(double)));
         HCHK(c, launch_ampl(t.geo(), t.origin, t.kd, g.nr, g.x64.as<Cx<double>>(), ndir, dn.as<double>(),
-                            dF.as<Cx<double>>(), st));
+                            dF.as<Cx<double>>(), dP.as<double>(), st));
         std::vector<cd> F((size_t)g.nr * ndir * 3);
         HCHK(c, hipMemcpyAsync(F.data(), dF.p, F.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
         HCHK(c, hipStreamSynchronize(st));

@@ -198,8 +198,11 @@ hipError_t launch_to_abi(const Geo& g, int nrhs, const Cx<T>* in, Cx<double>* ou
 hipError_t launch_xsec(const Geo& g, int nrhs, const Cx<double>* E, const Cx<double>* P, const Cx<double>* ainv,
                        double k3, double* partials, double* out, hipStream_t st);
 // Amplitude sums F[rhs][dir][3] = sum_j P_j exp(-i k n . r_j) (FP64).
-hipError_t launch_ampl(const Geo& g, const double* origin3, double k, int nrhs, const Cx<double>* P, int ndir,
-                       const double* ndirs, Cx<double>* F, hipStream_t st);
+// Site chunks per (direction, rhs) of the amplitude sums; partials holds
+// ampl_chunks * nrhs * ndir * 6 doubles.
+int ampl_chunks(int ndir, int nrhs, int N);
+hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const Cx<double>* P, int ndir,
+                       const double* ndirs, Cx<double>* F, double* partials, hipStream_t st);
 
 hipError_t configure_fft_kernels();
 

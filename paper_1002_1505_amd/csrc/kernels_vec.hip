@@ -479,14 +479,18 @@ __global__ void k_xsec_final(int nblk, const double* __restrict__ partials, doub
 }
 
 // One block per (direction, rhs): F = sum_j P_j exp(-i k n . r_j), FP64.
+// Block (dir, rhs, chunk): partial sums of F over one chunk of the sites,
+// partials[((chunk * nrhs + rhs) * ndir + dir) * 6 + q].
 __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, double oz, double k,
                                               const Cx<double>* __restrict__ P, const double* __restrict__ nd,
-                                              Cx<double>* __restrict__ F, int ndir) {
-    __shared__ double sh[16];
-    const int dir = blockIdx.x, rhs = blockIdx.y;
+                                              double* __restrict__ partials, int ndir, int nrhs) {
+    __shared__ double sh[6 * 4];
+    const int dir = blockIdx.x, rhs = blockIdx.y, chunk = blockIdx.z;
+    const int per = (g.N + gridDim.z - 1) / gridDim.z;
+    const int j0 = chunk * per, j1 = min(g.N, j0 + per);
     const double nx = nd[3 * dir], ny = nd[3 * dir + 1], nz = nd[3 * dir + 2];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int j = threadIdx.x; j < g.N; j += blockDim.x) {
+    for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
         const uint32_t s = g.site_xyz[j];
         const double x = (double)(s & 1023) - ox, y = (double)((s >> 10) & 1023) - oy, z = (double)(s >> 20) - oz;
         double sn, cs;
@@ -497,10 +501,17 @@ __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, doubl
             acc[2 * c + 1] += p.re * sn + p.im * cs;
         }
     }
-    for (int q = 0; q < 6; ++q) {
-        const double v = block_sum(acc[q], sh);
-        if (threadIdx.x == 0) reinterpret_cast<double*>(F)[((size_t)rhs * ndir + dir) * 6 + q] = v;
-    }
+    block_sum_n<6>(acc, sh);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) partials[(((size_t)chunk * nrhs + rhs) * ndir + dir) * 6 + q] = acc[q];
+}
+
+__global__ void k_ampl_reduce(const double* __restrict__ partials, int nchunk, int n, double* __restrict__ F) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double s = 0;
+    for (int c = 0; c < nchunk; ++c) s += partials[(size_t)c * n + e];
+    F[e] = s;
 }
 
 // Previous local field carried to the new incidence direction:
@@ -768,9 +779,19 @@ hipError_t launch_xsec(const Geo& g, int nrhs, const Cx<double>* E, const Cx<dou
     hipLaunchKernelGGL(k_xsec_final, dim3(nrhs), dim3(256), 0, st, nblk, partials, out);
     return hipGetLastError();
 }
+int ampl_chunks(int ndir, int nrhs, int N) {
+    const int want = (2048 + ndir * nrhs - 1) / (ndir * nrhs);
+    return std::max(1, std::min({64, want, (N + 1023) / 1024}));
+}
 hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const Cx<double>* P, int ndir,
-                       const double* ndirs, Cx<double>* F, hipStream_t st) {
-    hipLaunchKernelGGL(k_ampl, dim3(ndir, nrhs), dim3(256), 0, st, g, o[0], o[1], o[2], k, P, ndirs, F, ndir);
+                       const double* ndirs, Cx<double>* F, double* partials, hipStream_t st) {
+    const int nc = ampl_chunks(ndir, nrhs, g.N);
+    hipLaunchKernelGGL(k_ampl, dim3(ndir, nrhs, nc), dim3(256), 0, st, g, o[0], o[1], o[2], k, P, ndirs, partials,
+                       ndir, nrhs);
+    HIP_TRY(hipGetLastError());
+    const int n = nrhs * ndir * 6;
+    hipLaunchKernelGGL(k_ampl_reduce, dim3((n + 255) / 256), dim3(256), 0, st, partials, nc, n,
+                       reinterpret_cast<double*>(F));
     return hipGetLastError();
 }
 

@@ -83,6 +83,11 @@ __global__ void __launch_bounds__(256) k_conv(const uint16_t* __restrict__ X, co
     f4 acc[NC / 16];
 #pragma unroll
     for (int t = 0; t < NC / 16; ++t) acc[t] = f4{0, 0, 0, 0};
+    // the A operands of all 27 offsets are loaded first (independent loads in
+    // flight together), then consumed by the MFMAs
+    constexpr int KCH = KC / 16;
+    s4 av[27][KCH];
+#pragma unroll
     for (int o = 0; o < 27; ++o) {
         int dx, dy, dz;
         offset_of(o, dx, dy, dz);
@@ -95,16 +100,20 @@ __global__ void __launch_bounds__(256) k_conv(const uint16_t* __restrict__ X, co
         const bool ok = (v < V) && xx >= 0 && xx < D && yy >= 0 && yy < D && zz >= 0 && zz < D;
         const uint16_t* src = xs + ((size_t)(zz * D + yy) * D + xx) * KC;
 #pragma unroll
-        for (int kc = 0; kc < KC; kc += 16) {
-            s4 a = {0, 0, 0, 0};
-            if (ok) a = *reinterpret_cast<const s4*>(src + kc + kb);
-#pragma unroll
-            for (int t = 0; t < NC / 16; ++t) {
-                const s4 b = *reinterpret_cast<const s4*>(wl + ((o * NC) + t * 16 + i) * KC + kc + kb);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-            }
+        for (int kq = 0; kq < KCH; ++kq) {
+            av[o][kq] = s4{0, 0, 0, 0};
+            if (ok) av[o][kq] = *reinterpret_cast<const s4*>(src + kq * 16 + kb);
         }
     }
+#pragma unroll
+    for (int o = 0; o < 27; ++o)
+#pragma unroll
+        for (int kq = 0; kq < KCH; ++kq)
+#pragma unroll
+            for (int t = 0; t < NC / 16; ++t) {
+                const s4 b = *reinterpret_cast<const s4*>(wl + ((o * NC) + t * 16 + i) * KC + kq * 16 + kb);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[o][kq], b, acc[t], 0, 0, 0);
+            }
     // D fragment: lane holds rows (lane >> 4) * 4 + r, column lane & 15
     const int i4 = (lane >> 4) * 4, j = lane & 15;
 #pragma unroll
