@@ -257,7 +257,9 @@ dda_status dda_last_guess_ms(const dda_ctx* ctx, double* ms);
  * DDA_FP64, as 8 integers: {planes in LDS, plane threads, z threads, z tile
  * columns, fallback lines per block, fallback threads, specialised kernels
  * bitmask (1 plane passes, 2 z pass, 4 two-factor inverse plane pass for
- * n = 64), z pass variant (0 one rhs per block, 1 up to 8 rhs per block with
+ * n = 64, 8 class-grouped spectrum slab for n = 64 with z pass variant 3: the
+ * z pass combines the four quadrants that each output parity class of the
+ * inverse plane pass needs), z pass variant (0 one rhs per block, 1 up to 8 rhs per block with
  * the spectrum in registers, 2 two-factor 8 x 8 pass for n = 64, 3 the same
  * with the two frequency parities in the two halves of a block)}.
  * dda_set_shape rejects shapes that do

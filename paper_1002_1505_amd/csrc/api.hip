@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <map>
 #include <memory>
 #include <sstream>
 #include <string>
@@ -81,7 +82,8 @@ struct Target {
     FftPlan plans[3];
     DevMem d_xyz, d_comp, d_pstart, d_cstart, d_perm, tw64, tw32, gh64, gh32;
     DevMem gz64, gz32;  // n = 64: spectrum with components interleaved (two-factor z pass)
-    DevMem zt16, zt32;  // n = 64: z-pass tile order per XCD
+    DevMem gz64g, gz32g;  // the same with x columns in the class-grouped slab's group order
+    DevMem zt16, zt32, zt16g;  // n = 64: z-pass tile order per XCD
     bool have64 = false, have32 = false;
     MvShape sh32{}, sh64{};
     Geo geo() const {
@@ -97,6 +99,7 @@ struct Target {
         g.perm = d_perm.as<int>();
         g.ztiles16 = zt16.as<int>();
         g.ztiles32 = zt32.as<int>();
+        g.ztiles16g = zt16g.as<int>();
         g.site_xyz = d_xyz.as<uint32_t>();
         g.site_comp = d_comp.as<uint8_t>();
         return g;
@@ -123,6 +126,7 @@ struct Target {
     // spectrum layout the launch shape's z pass reads
     template <class T>
     const Cx<T>* ghat_for(const MvShape& sh) const {
+        if (sh.ct & 8) return std::is_same<T, double>::value ? gz64g.as<Cx<T>>() : gz32g.as<Cx<T>>();
         if ((sh.ct & 2) && sh.zrb >= 2)
             return std::is_same<T, double>::value ? gz64.as<Cx<T>>() : gz32.as<Cx<T>>();
         return ghat<T>();
@@ -280,8 +284,10 @@ MvShape default_shape(const Target& t, int tx_pref) {
         for (int v = std::is_same<T, double>::value ? 1 : 0; v < 2; ++v) {
             MvShape c3 = s;
             c3.tx = zv[v][1];
-            // two-factor inverse plane pass: faster in FP64, on par in FP32
-            c3.ct = (ct_available<T>(g.n1, c3.tx) | (s.ct & 1)) & (std::is_same<T, double>::value ? 7 : 3);
+            // two-factor inverse plane pass: faster in FP64, on par in FP32;
+            // with variant 3 the z pass pre-combines the inverse pass's
+            // quadrants (class-grouped slab)
+            c3.ct = (ct_available<T>(g.n1, c3.tx) | (s.ct & 1)) & (std::is_same<T, double>::value ? 7 : 11);
             c3.zrb = zv[v][0];
             if (matvec_shape_ok<T>(g, t.plans, c3)) {
                 s = c3;
@@ -293,29 +299,35 @@ MvShape default_shape(const Target& t, int tx_pref) {
 }
 
 // Tile order of the two-factor z pass (cubic box of side n, tiles of tx
-// columns of one (parity, ky) row): tiles whose columns fold onto the same
-// tensor-spectrum columns (ky and its mirror, both halves of the row) form a
-// group; groups go whole to the least-loaded XCD, giving [8][tiles / 8].
-std::vector<int> zpass_tile_order(int n, int tx) {
-    const int per_row = n / tx, ntile = 4 * n * n / tx;
+// columns): tiles whose columns fold onto the same tensor-spectrum rows form
+// a group; groups go whole to the least-loaded XCD, giving [8][tiles / 8].
+// In the row layout a tile covers one (parity, ky) row and groups are ky
+// with its mirror; in the class-grouped layout (grouped) a tile covers rows
+// ky and ky + n, and groups are the pairs {ky, n - ky}.
+std::vector<int> zpass_tile_order(int n, int tx, bool grouped) {
+    const int ntile = 4 * n * n / tx;
     auto fidx = [n](int k) {
         const int f = k <= n ? k : 2 * n - k;
         return (f & 1) * (n / 2 + 1) + (f >> 1);
     };
     std::vector<std::vector<int>> groups;
-    for (int par = 0; par < 4; ++par) {
-        const int py = par >> 1;
-        std::vector<int> done(n + 2, 0);
-        for (int kyp = 0; kyp < n; ++kyp) {
-            const int kyi = fidx(2 * kyp + py);
-            if (done[kyi]) continue;
-            done[kyi] = 1;
-            std::vector<int> g;
-            for (int k = 0; k < n; ++k)
-                if (fidx(2 * k + py) == kyi)
-                    for (int h = 0; h < per_row; ++h) g.push_back((par * n * n + k * n) / tx + h);
-            groups.push_back(g);
+    std::map<int, int> gid;  // (parity, smallest folded row) -> group
+    for (int tile = 0; tile < ntile; ++tile) {
+        const int q0 = tile * tx, par = q0 / (n * n), rem = q0 % (n * n), py = par >> 1;
+        int key;
+        if (grouped) {
+            const int ky = 2 * ((rem >> 2) / (n / 2)) + py;
+            key = std::min(fidx(ky), fidx(ky + n));
+        } else {
+            key = fidx(2 * (rem / n) + py);
         }
+        key += par * (n + 2);
+        auto it = gid.find(key);
+        if (it == gid.end()) {
+            it = gid.emplace(key, (int)groups.size()).first;
+            groups.emplace_back();
+        }
+        groups[it->second].push_back(tile);
     }
     std::stable_sort(groups.begin(), groups.end(), [](const std::vector<int>& a, const std::vector<int>& b) {
         return a.size() > b.size();
@@ -419,11 +431,13 @@ dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint
     HCHK(c, hipMemcpy(t.d_perm.p, perm.data(), perm.size() * 4, hipMemcpyHostToDevice));
     t.zt16.release();
     t.zt32.release();
+    t.zt16g.release();
     if (n1 == 64 && n2 == 64 && n3 == 64) {
-        for (int tx : {16, 32}) {
-            const std::vector<int> order = zpass_tile_order(64, tx);
+        for (int v = 0; v < 3; ++v) {
+            const int tx = v == 1 ? 32 : 16;
+            const std::vector<int> order = zpass_tile_order(64, tx, v == 2);
             if (order.empty()) return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "z-pass tile order unbalanced");
-            DevMem& d = tx == 16 ? t.zt16 : t.zt32;
+            DevMem& d = v == 0 ? t.zt16 : (v == 1 ? t.zt32 : t.zt16g);
             HCHK(c, d.ensure(order.size() * 4));
             HCHK(c, hipMemcpy(d.p, order.data(), order.size() * 4, hipMemcpyHostToDevice));
         }
@@ -510,11 +524,15 @@ dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
                          t.gh32.p ? t.gh32.as<Cx<float>>() : nullptr, c->stream));
     if (t.n[0] == 64 && t.n[1] == 64 && t.n[2] == 64) {
         const size_t cs = oct / 6;
-        HCHK(c, t.gz64.ensure(oct * sizeof(Cx<double>)));
-        HCHK(c, launch_green_interleave<double>(t.gh64.as<Cx<double>>(), t.gz64.as<Cx<double>>(), cs, c->stream));
-        if (t.gh32.p) {
-            HCHK(c, t.gz32.ensure(oct * sizeof(Cx<float>)));
-            HCHK(c, launch_green_interleave<float>(t.gh32.as<Cx<float>>(), t.gz32.as<Cx<float>>(), cs, c->stream));
+        for (int hx : {0, 32}) {
+            DevMem& d64 = hx ? t.gz64g : t.gz64;
+            HCHK(c, d64.ensure(oct * sizeof(Cx<double>)));
+            HCHK(c, launch_green_interleave<double>(t.gh64.as<Cx<double>>(), d64.as<Cx<double>>(), cs, hx, c->stream));
+            if (t.gh32.p) {
+                DevMem& d32 = hx ? t.gz32g : t.gz32;
+                HCHK(c, d32.ensure(oct * sizeof(Cx<float>)));
+                HCHK(c, launch_green_interleave<float>(t.gh32.as<Cx<float>>(), d32.as<Cx<float>>(), cs, hx, c->stream));
+            }
         }
     }
     HCHK(c, hipStreamSynchronize(c->stream));
@@ -1662,11 +1680,11 @@ std::vector<MvShape> shape_candidates(const Target& t) {
     if (ct_supported(g.n1, g.n2, g.n3)) {
         for (int tx : {8, 16, 32})
             for (int zrb : {0, 1, 2, 3})
-                for (int pv : {0, 4}) {  // inverse plane pass variant
+                for (int pv : {0, 4, 8, 12}) {  // inverse plane pass variant, slab layout
                     MvShape c = base;
                     c.tx = tx;
                     const int av = ct_available<T>(g.n1, tx);
-                    if (!(av & 2) || (pv && !(av & 4))) continue;
+                    if (!(av & 2) || (pv & ~av)) continue;
                     c.ct = (av & 3) | pv;
                     c.zrb = zrb;
                     c.fused = 1;

@@ -27,6 +27,56 @@ template <class T, int S> __device__ __forceinline__ Cx<T> mul_si(Cx<T> a) {
 }
 template <class To, class Ti> __device__ __forceinline__ Cx<To> cvt(Cx<Ti> a) { return {(To)a.re, (To)a.im}; }
 
+// Value held by lane (lane ^ M) of the same group of four lanes, M in {1, 2}:
+// a DPP quad permutation, no LDS round trip.  Every lane of the wave must be
+// active.
+template <int M> __device__ __forceinline__ int quad_xor_i(int v) {
+    static_assert(M == 1 || M == 2, "quad lanes 1 or 2 apart");
+    return __builtin_amdgcn_mov_dpp(v, M == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int M> __device__ __forceinline__ float quad_xor(float v) { return __int_as_float(quad_xor_i<M>(__float_as_int(v))); }
+template <int M> __device__ __forceinline__ double quad_xor(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)quad_xor_i<M>((int)(unsigned)b), hi = (unsigned)quad_xor_i<M>((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int M, class T> __device__ __forceinline__ Cx<T> quad_xor(Cx<T> v) {
+    return {quad_xor<M>(v.re), quad_xor<M>(v.im)};
+}
+// Class-grouped slab of the n = 64 matvec: group position p in a row of
+// H = n/2 groups holds b'x = grp_bx(p, px), frequency parity px.  The folded
+// spectrum column of b'x + n/2 is that of H - px - b'x, so positions
+// (2k, 2k + 1) hold such a pair: (k, H - 1 - k) for px = 1; (k + 1, H - k - 1)
+// for px = 0, where b'x = 0 and b'x = H/2 fold onto themselves and take the
+// last two places.  grp_pos is the inverse.
+__device__ __forceinline__ int grp_bx(int p, int px, int H) {
+    if (px) return (p & 1) ? H - 1 - (p >> 1) : p >> 1;
+    if (p < H - 2) {
+        const int k = (p >> 1) + 1;
+        return (p & 1) ? H - k : k;
+    }
+    return p == H - 2 ? 0 : H / 2;
+}
+__device__ __forceinline__ int grp_pos(int b, int px, int H) {
+    if (px) return b < H / 2 ? 2 * b : 2 * (H - 1 - b) + 1;
+    if (b == 0) return H - 2;
+    if (b == H / 2) return H - 1;
+    return b < H / 2 ? 2 * (b - 1) : 2 * (H - b - 1) + 1;
+}
+// Slot of folded column f/2 = u (0..H) of parity half px in the spectrum copy
+// that follows the group order (u = H, the even half's Nyquist column and the
+// odd half's unused slot, stays last).
+__device__ __forceinline__ int spec_xpos(int u, int px, int H) { return u == H ? H : grp_pos(u, px, H); }
+
+// 2 x 2 Hadamard transform over the four lanes of a quad, lane bits (hy, hx):
+// lane (qy, qx) returns sum over (hy, hx) of (-1)^(qx hx + qy hy) v(hy, hx).
+template <class T> __device__ __forceinline__ Cx<T> quad_hadamard(Cx<T> v, int lane) {
+    Cx<T> o = quad_xor<1>(v);
+    v = (lane & 1) ? o - v : v + o;
+    o = quad_xor<2>(v);
+    return (lane & 2) ? o - v : v + o;
+}
+
 // ---------------------------------------------------------------------------
 // Butterflies: DFT of length R in registers.  DIR = -1 forward, +1 inverse.
 // ---------------------------------------------------------------------------

@@ -20,11 +20,13 @@ struct Geo {
     const uint32_t* site_xyz;  // x | y << 10 | z << 20
     const uint8_t* site_comp;  // 0-based composition index
     const int* perm;           // [N]: position of each stored site in the (z, y, x) scan order
-    // n = 64: z-pass tile order per XCD for tiles of 16 and 32 columns,
-    // [8][tiles / 8]; the tiles that share tensor-spectrum columns through
-    // the x and y folds are adjacent on one XCD (nullptr for other boxes)
+    // n = 64: z-pass tile order per XCD for tiles of 16 and 32 columns and
+    // for 16-column tiles of the class-grouped slab, [8][tiles / 8]; the
+    // tiles that share tensor-spectrum columns through the x and y folds are
+    // adjacent on one XCD (nullptr for other boxes)
     const int* ztiles16;
     const int* ztiles32;
+    const int* ztiles16g;
 };
 
 // Twiddle tables of one target: f_i[k] = exp(-2 pi i k / n_i) (k < n_i) and
@@ -62,7 +64,8 @@ struct MvShape {
     int lines_tl;    // lines per block in the line-kernel fallback
     int nth_lines;
     int ct;          // bit 0: specialised plane kernels, bit 1: specialised z pass (cubic boxes),
-                     // bit 2: two-factor inverse plane pass (n = 64, with bit 0)
+                     // bit 2: two-factor inverse plane pass (n = 64, with bit 0), bit 3: class-grouped
+                     // slab, the quadrant pre-combination done by the z pass (n = 64, bits 0, 1, zrb 3)
     int zrb;         // specialised z pass variant: 0 = one rhs per block, 1 = loop over up to 8 rhs per
                      // block with the spectrum in registers, 2 = two-factor 8 x 8 pass (n = 64),
                      // 3 = two-factor pass with one frequency parity per block half (n = 64)
@@ -121,9 +124,11 @@ bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh);
 // scaled by 1/(M1 M2 M3)) in FP64 and, when g32 != nullptr, an FP32 copy.
 // work must hold 48 * n1 n2 n3 complex doubles.
 // The tensor spectrum with the 6 components of each frequency adjacent,
-// gz[i * 6 + q] = gh[q * cs + i] (read by the two-factor z pass).
+// gz[i * 6 + q] = gh[q * cs + i] (read by the two-factor z pass); hx = n/2 > 0
+// also permutes the x columns of each parity half into the group order of the
+// class-grouped slab (hx = 0: no permutation).
 template <class T>
-hipError_t launch_green_interleave(const Cx<T>* gh, Cx<T>* gz, size_t cs, hipStream_t st);
+hipError_t launch_green_interleave(const Cx<T>* gh, Cx<T>* gz, size_t cs, int hx, hipStream_t st);
 hipError_t launch_green(const Geo& g, const Tw<double>& tw, const FftPlan* plans, double kd, Cx<double>* work,
                         Cx<double>* g64, Cx<float>* g32, hipStream_t st);
 

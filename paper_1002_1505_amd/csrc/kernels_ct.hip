@@ -13,6 +13,17 @@
 //    plane, runs the inverse FFT along y on all columns and along x on the
 //    first n/2 rows only, and gathers the sites (x, y) with x % 2 = qx and
 //    y % 2 = qy, adding the diagonal term.  No accumulator crosses the FFTs.
+//  * class-grouped slab (n = 64, specialised-kernel bit 8): the forward pass
+//    stores the four quadrant partners (b, b + n/2 in y and in x) of each
+//    parity block next to each other, slot (b'y n/2 + b'x) * 4 + 2 hy + hx;
+//    the z pass, whose 16-column tiles then hold four whole partner groups,
+//    replaces each group by its 2 x 2 Hadamard transform before the store, so
+//    slot q of a group is already the class-q pre-combination and each
+//    inverse block reads one value per frequency instead of four.  Within a
+//    row the groups are ordered so that a tile holds two groups b'x and
+//    n/2 - px - b'x whose columns fold onto the same tensor-spectrum
+//    columns: a tile reads 8 spectrum columns instead of 16, and in a copy
+//    of the spectrum with x columns in the same order they are adjacent.
 #include "dda_internal.h"
 
 namespace {
@@ -49,7 +60,7 @@ struct UpdArgs {
     void* x;
 };
 
-template <class T, int N, int UPD>
+template <class T, int N, int UPD, bool G>
 __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __restrict__ x, Cx<T>* __restrict__ slab,
                                                                 Geo g, Tw<T> tw, int nrhs, const int* __restrict__ active,
                                                                 UpdArgs u) {
@@ -130,8 +141,17 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     ct_fft<T, -1, N, N, NTH, N, PITCH, 0, 1>(buf, t1, tid);   // along x: lines are rows
     ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y: lines are columns
     Cx<T>* out = slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + par) * (size_t)(N * N);
+    if constexpr (G) {
+        constexpr int HN = N / 2;
 #pragma unroll 8
-    for (int i = tid; i < N * N; i += NTH) out[i] = buf[(i / N) * PITCH + (i % N)];
+        for (int i = tid; i < N * N; i += NTH) {
+            const int h = i & 3, gq = i >> 2;
+            out[i] = buf[(gq / HN + (h >> 1) * HN) * PITCH + grp_bx(gq % HN, px, HN) + (h & 1) * HN];
+        }
+    } else {
+#pragma unroll 8
+        for (int i = tid; i < N * N; i += NTH) out[i] = buf[(i / N) * PITCH + (i % N)];
+    }
 }
 
 template <class T, int N, int TX>
@@ -425,7 +445,11 @@ __global__ void __launch_bounds__(TX * 8) k_zpass3_ct(Cx<T>* __restrict__ slab, 
 // post-twiddled output to the parity-0 half through LDS.  Each thread then
 // carries one parity's state, which halves the registers of the
 // single-half version and raises the waves per SIMD.
-template <class T, int N, int TX>
+//
+// G: class-grouped slab.  Column c of a tile is quadrant partner (hy, hx) =
+// (c >> 1 & 1, c & 1) of group c >> 2; the four partners of a group sit in
+// one quad of lanes, which exchange values by DPP for the Hadamard step.
+template <class T, int N, int TX, bool G>
 __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab, const Cx<T>* __restrict__ gh,
                                                        Tw<T> tw, int nrhs, const int* __restrict__ active,
                                                        const int* __restrict__ tiles) {
@@ -450,10 +474,22 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
     const int q0 = tile * TX;
     const int par = q0 / (N * N), rem = q0 % (N * N);
     const int px = par & 1, py = par >> 1;
-    const int kyp = rem / N, kx0 = rem % N;
-    int sx, sy;
-    const int kxi = fold_idx(2 * (kx0 + c) + px, N, sx);
-    const int kyi = fold_idx(2 * kyp + py, N, sy);
+    int sx, sy, kxi, kyi;
+    if constexpr (G) {
+        static_assert(TX % 4 == 0, "tiles of whole partner groups");
+        constexpr int HN = N / 2;
+        const int gq = (rem >> 2) + (c >> 2);
+        // spectrum copy whose x columns follow the group order
+        const int kx = 2 * (grp_bx(gq % HN, px, HN) + (c & 1) * HN) + px;
+        const int fx = kx > N ? 2 * N - kx : kx;
+        sx = kx > N ? -1 : 1;
+        kxi = px * (HN + 1) + spec_xpos(fx >> 1, px, HN);
+        kyi = fold_idx(2 * (gq / HN + ((c >> 1) & 1) * HN) + py, N, sy);
+    } else {
+        const int kyp = rem / N, kx0 = rem % N;
+        kxi = fold_idx(2 * (kx0 + c) + px, N, sx);
+        kyi = fold_idx(2 * kyp + py, N, sy);
+    }
     const T sxy = (T)(sx * sy);
     Cx<T> w[R];  // w_N^(j m)
 #pragma unroll
@@ -539,8 +575,11 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int z2 = 0; z2 < R; ++z2)
-            base[o0 + (uint32_t)(a * N + R * z2) * NCOL] = u[a][z2] + X1[((a * R + z2) * R + j) * TX + c];
+        for (int z2 = 0; z2 < R; ++z2) {
+            Cx<T> v = u[a][z2] + X1[((a * R + z2) * R + j) * TX + c];
+            if constexpr (G) v = quad_hadamard(v, c);
+            base[o0 + (uint32_t)(a * N + R * z2) * NCOL] = v;
+        }
 }
 
 // DOT = 1: per-block partial sums of conj(w_j) . y_j (slot 0); DOT = 2:
@@ -548,7 +587,7 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
 // |x_j|^2 in the imaginary part of slot 1, conj(w_j) . x_j (slot 2) and
 // conj(w_j) . y_j (slot 3).  partials[rhs][slot][blk]
 // with blk = (plane within rhs) * 4 + class, 12 n blocks per rhs.
-template <class T, int N, int MODE, int DOT>
+template <class T, int N, int MODE, int DOT, bool G>
 __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __restrict__ slab, const Cx<T>* __restrict__ x,
                                                                 Cx<T>* __restrict__ y, const Cx<T>* __restrict__ bvec,
                                                                 const Cx<T>* __restrict__ ainv, Geo g, Tw<T> tw, int nrhs,
@@ -580,9 +619,14 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
         const int kyp = e / N, kxp = e % N;
         const int bx = kxp >> 1, px = kxp & 1, by = kyp >> 1, py = kyp & 1;
         const Cx<T>* blk = in + (size_t)(py * 2 + px) * NN;
-        const Cx<T> s00 = blk[by * N + bx], s10 = blk[by * N + bx + HN];
-        const Cx<T> s01 = blk[(by + HN) * N + bx], s11 = blk[(by + HN) * N + bx + HN];
-        Cx<T> v = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
+        Cx<T> v;
+        if constexpr (G) {
+            v = blk[(by * HN + grp_pos(bx, px, HN)) * 4 + q];
+        } else {
+            const Cx<T> s00 = blk[by * N + bx], s10 = blk[by * N + bx + HN];
+            const Cx<T> s01 = blk[(by + HN) * N + bx], s11 = blk[(by + HN) * N + bx + HN];
+            v = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
+        }
         if (qx) v = cmulc(tw.h1[kxp], v);
         if (qy) v = cmulc(tw.h2[kyp], v);
         buf[kyp * PITCH + kxp] = v;
@@ -658,7 +702,7 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
 // those 32 rows the same two steps keep x' < n/2.  LDS: rows of the first
 // exchange [n2][m1][kx], then the 32 kept rows (pitch n + 1), the second
 // exchange [n2][m1][y'] and the 32 x 32 result (pitch n/2 + 1).
-template <class T, int N, int MODE, int DOT>
+template <class T, int N, int MODE, int DOT, bool G>
 __global__ void __launch_bounds__(256) k_pinv3_ct(const Cx<T>* __restrict__ slab, const Cx<T>* __restrict__ x,
                                                   Cx<T>* __restrict__ y, const Cx<T>* __restrict__ bvec,
                                                   const Cx<T>* __restrict__ ainv, Geo g, Tw<T> tw, int nrhs,
@@ -697,9 +741,14 @@ __global__ void __launch_bounds__(256) k_pinv3_ct(const Cx<T>* __restrict__ slab
                 const int ky = m1 + R * m2;
                 const int by = ky >> 1, py = ky & 1;
                 const Cx<T>* blk = in + (size_t)(py * 2 + px) * NN;
-                const Cx<T> s00 = blk[by * N + bx], s10 = blk[by * N + bx + HN];
-                const Cx<T> s01 = blk[(by + HN) * N + bx], s11 = blk[(by + HN) * N + bx + HN];
-                Cx<T> v = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
+                Cx<T> v;
+                if constexpr (G) {
+                    v = blk[(by * HN + grp_pos(bx, px, HN)) * 4 + q];
+                } else {
+                    const Cx<T> s00 = blk[by * N + bx], s10 = blk[by * N + bx + HN];
+                    const Cx<T> s01 = blk[(by + HN) * N + bx], s11 = blk[(by + HN) * N + bx + HN];
+                    v = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
+                }
                 if (qx) v = cmulc(hx, v);
                 if (qy) v = cmulc(tw.h2[ky], v);
                 u[m2] = v;
@@ -821,19 +870,45 @@ template <class T, int N, int TX>
 constexpr size_t zpass4_lds() { return (size_t)2 * 3 * N * TX * sizeof(Cx<T>); }
 constexpr size_t LDS_MAX = 160 * 1024;
 
-template <class T, int N, int MODE, int DOT>
-void launch_pinv(int nblk, bool two_factor, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
-                 const Cx<T>* b, const Cx<T>* slab, const Cx<T>* ainv, const int* active, const Cx<T>* w,
-                 double* partials, hipStream_t st) {
+template <class T, int N, int MODE, int DOT, bool G>
+void launch_pinv_g(int nblk, bool two_factor, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
+                   const Cx<T>* b, const Cx<T>* slab, const Cx<T>* ainv, const int* active, const Cx<T>* w,
+                   double* partials, hipStream_t st) {
     if constexpr (N == 64) {
         if (two_factor) {
-            hipLaunchKernelGGL((k_pinv3_ct<T, N, MODE, DOT>), dim3(nblk), dim3(256), (plane_lds<T, N>()), st, slab, x,
-                               y, b, ainv, g, tw, nrhs, active, w, partials);
+            hipLaunchKernelGGL((k_pinv3_ct<T, N, MODE, DOT, G>), dim3(nblk), dim3(256), (plane_lds<T, N>()), st, slab,
+                               x, y, b, ainv, g, tw, nrhs, active, w, partials);
             return;
         }
     }
-    hipLaunchKernelGGL((k_pinv_ct<T, N, MODE, DOT>), dim3(nblk), dim3(plane_threads<N>()), (plane_lds<T, N>()), st,
+    hipLaunchKernelGGL((k_pinv_ct<T, N, MODE, DOT, G>), dim3(nblk), dim3(plane_threads<N>()), (plane_lds<T, N>()), st,
                        slab, x, y, b, ainv, g, tw, nrhs, active, w, partials);
+}
+
+// grouped: class-grouped slab (n = 64 only)
+template <class T, int N, int MODE, int DOT>
+void launch_pinv(int nblk, bool two_factor, bool grouped, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x,
+                 Cx<T>* y, const Cx<T>* b, const Cx<T>* slab, const Cx<T>* ainv, const int* active, const Cx<T>* w,
+                 double* partials, hipStream_t st) {
+    if constexpr (N == 64)
+        if (grouped)
+            return launch_pinv_g<T, N, MODE, DOT, true>(nblk, two_factor, g, tw, nrhs, x, y, b, slab, ainv, active, w,
+                                                        partials, st);
+    launch_pinv_g<T, N, MODE, DOT, false>(nblk, two_factor, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+}
+
+template <class T, int N, int UPD>
+void launch_pfwd(int nblk, bool grouped, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* slab,
+                 const int* active, const UpdArgs& ua, hipStream_t st) {
+    if constexpr (N == 64) {
+        if (grouped) {
+            hipLaunchKernelGGL((k_pfwd_ct<T, N, UPD, true>), dim3(nblk), dim3(plane_threads<N>()), (plane_lds<T, N>()),
+                               st, x, slab, g, tw, nrhs, active, ua);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_pfwd_ct<T, N, UPD, false>), dim3(nblk), dim3(plane_threads<N>()), (plane_lds<T, N>()), st,
+                       x, slab, g, tw, nrhs, active, ua);
 }
 
 template <class T, int N>
@@ -848,27 +923,20 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
         if constexpr (plane_lds<T, N>() > LDS_MAX) {
             return hipErrorNotSupported;
         } else {
+            const bool tf = (ct & 4) != 0, gr = (ct & 8) != 0;
             if (which == 0) {
                 const UpdArgs ua{upd.r, upd.v, upd.p, upd.pout, upd.rhat, upd.st, upd.s, upd.t, upd.x};
-                if (upd.mode == 3)
-                    hipLaunchKernelGGL((k_pfwd_ct<T, N, 3>), dim3(nblk_plane), dim3(plane_threads<N>()),
-                                       (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
-                else if (upd.mode == 1)
-                    hipLaunchKernelGGL((k_pfwd_ct<T, N, 1>), dim3(nblk_plane), dim3(plane_threads<N>()),
-                                       (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
-                else if (upd.mode == 2)
-                    hipLaunchKernelGGL((k_pfwd_ct<T, N, 2>), dim3(nblk_plane), dim3(plane_threads<N>()),
-                                       (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
-                else
-                    hipLaunchKernelGGL((k_pfwd_ct<T, N, 0>), dim3(nblk_plane), dim3(plane_threads<N>()),
-                                       (plane_lds<T, N>()), st, x, slab, g, tw, nrhs, active, ua);
+                if (upd.mode == 3) launch_pfwd<T, N, 3>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
+                else if (upd.mode == 1) launch_pfwd<T, N, 1>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
+                else if (upd.mode == 2) launch_pfwd<T, N, 2>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
+                else launch_pfwd<T, N, 0>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
             } else if (mode == MV_AX) {
-                if (dot == 1) launch_pinv<T, N, MV_AX, 1>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
-                else if (dot == 2) launch_pinv<T, N, MV_AX, 2>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
-                else if (dot == 3) launch_pinv<T, N, MV_AX, 3>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
-                else launch_pinv<T, N, MV_AX, 0>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                if (dot == 1) launch_pinv<T, N, MV_AX, 1>(nblk_plane, tf, gr, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                else if (dot == 2) launch_pinv<T, N, MV_AX, 2>(nblk_plane, tf, gr, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                else if (dot == 3) launch_pinv<T, N, MV_AX, 3>(nblk_plane, tf, gr, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                else launch_pinv<T, N, MV_AX, 0>(nblk_plane, tf, gr, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
             } else {
-                launch_pinv<T, N, MV_RESID, 0>(nblk_plane, (ct & 4) != 0, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
+                launch_pinv<T, N, MV_RESID, 0>(nblk_plane, tf, gr, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
             }
             return hipGetLastError();
         }
@@ -878,12 +946,17 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
         if constexpr (N != 64) {
             return hipErrorNotSupported;
         } else {
-            if (tx != 16 || !g.ztiles16) return hipErrorNotSupported;
+            const int* tl = (ct & 8) ? g.ztiles16g : g.ztiles16;
+            if (tx != 16 || !tl) return hipErrorNotSupported;
             if constexpr (zpass4_lds<T, N, 16>() > LDS_MAX) {
                 return hipErrorNotSupported;
             } else {
-                hipLaunchKernelGGL((k_zpass4_ct<T, N, 16>), dim3(nrhs * (ntile / 16)), dim3(16 * 16),
-                                   (zpass4_lds<T, N, 16>()), st, slab, ghat, tw, nrhs, active, g.ztiles16);
+                if (ct & 8)
+                    hipLaunchKernelGGL((k_zpass4_ct<T, N, 16, true>), dim3(nrhs * (ntile / 16)), dim3(16 * 16),
+                                       (zpass4_lds<T, N, 16>()), st, slab, ghat, tw, nrhs, active, tl);
+                else
+                    hipLaunchKernelGGL((k_zpass4_ct<T, N, 16, false>), dim3(nrhs * (ntile / 16)), dim3(16 * 16),
+                                       (zpass4_lds<T, N, 16>()), st, slab, ghat, tw, nrhs, active, tl);
                 return hipGetLastError();
             }
         }
@@ -947,22 +1020,26 @@ hipError_t set_attrs_n() {
     const int lim = 160 * 1024;
     hipError_t e = hipSuccess;
     if constexpr (plane_lds<T, N>() <= LDS_MAX) {
-        e = set_lds_limit((const void*)k_pfwd_ct<T, N, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        if (e == hipSuccess)
-            e = set_lds_limit((const void*)k_pfwd_ct<T, N, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        if (e == hipSuccess)
-            e = set_lds_limit((const void*)k_pfwd_ct<T, N, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        if (e == hipSuccess)
-            e = set_lds_limit((const void*)k_pfwd_ct<T, N, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        const void* fns[] = {(const void*)k_pinv_ct<T, N, MV_AX, 0>, (const void*)k_pinv_ct<T, N, MV_AX, 1>,
-                             (const void*)k_pinv_ct<T, N, MV_AX, 2>, (const void*)k_pinv_ct<T, N, MV_AX, 3>,
-                             (const void*)k_pinv_ct<T, N, MV_RESID, 0>};
+        const void* fns[] = {(const void*)k_pfwd_ct<T, N, 0, false>, (const void*)k_pfwd_ct<T, N, 1, false>,
+                             (const void*)k_pfwd_ct<T, N, 2, false>, (const void*)k_pfwd_ct<T, N, 3, false>,
+                             (const void*)k_pinv_ct<T, N, MV_AX, 0, false>, (const void*)k_pinv_ct<T, N, MV_AX, 1, false>,
+                             (const void*)k_pinv_ct<T, N, MV_AX, 2, false>, (const void*)k_pinv_ct<T, N, MV_AX, 3, false>,
+                             (const void*)k_pinv_ct<T, N, MV_RESID, 0, false>};
         for (const void* f : fns)
             if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if constexpr (N == 64) {
-            const void* f3[] = {(const void*)k_pinv3_ct<T, N, MV_AX, 0>, (const void*)k_pinv3_ct<T, N, MV_AX, 1>,
-                                (const void*)k_pinv3_ct<T, N, MV_AX, 2>, (const void*)k_pinv3_ct<T, N, MV_AX, 3>,
-                                (const void*)k_pinv3_ct<T, N, MV_RESID, 0>};
+            const void* f3[] = {
+                (const void*)k_pinv3_ct<T, N, MV_AX, 0, false>, (const void*)k_pinv3_ct<T, N, MV_AX, 1, false>,
+                (const void*)k_pinv3_ct<T, N, MV_AX, 2, false>, (const void*)k_pinv3_ct<T, N, MV_AX, 3, false>,
+                (const void*)k_pinv3_ct<T, N, MV_RESID, 0, false>,
+                (const void*)k_pfwd_ct<T, N, 0, true>, (const void*)k_pfwd_ct<T, N, 1, true>,
+                (const void*)k_pfwd_ct<T, N, 2, true>, (const void*)k_pfwd_ct<T, N, 3, true>,
+                (const void*)k_pinv_ct<T, N, MV_AX, 0, true>, (const void*)k_pinv_ct<T, N, MV_AX, 1, true>,
+                (const void*)k_pinv_ct<T, N, MV_AX, 2, true>, (const void*)k_pinv_ct<T, N, MV_AX, 3, true>,
+                (const void*)k_pinv_ct<T, N, MV_RESID, 0, true>,
+                (const void*)k_pinv3_ct<T, N, MV_AX, 0, true>, (const void*)k_pinv3_ct<T, N, MV_AX, 1, true>,
+                (const void*)k_pinv3_ct<T, N, MV_AX, 2, true>, (const void*)k_pinv3_ct<T, N, MV_AX, 3, true>,
+                (const void*)k_pinv3_ct<T, N, MV_RESID, 0, true>};
             for (const void* f : f3)
                 if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         }
@@ -987,7 +1064,9 @@ hipError_t set_attrs_n() {
     }
     if constexpr (N == 64) {
         if (e == hipSuccess)
-            e = set_lds_limit((const void*)k_zpass4_ct<T, N, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+            e = set_lds_limit((const void*)k_zpass4_ct<T, N, 16, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_zpass4_ct<T, N, 16, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass3_ct<T, N, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if constexpr (zpass3_lds<T, N, 32>() <= LDS_MAX)
@@ -1025,7 +1104,8 @@ template <class T>
 bool ct_zpass_fits(int n, int tx, int zrb);
 
 // Which passes of a cubic box of side n have a specialised kernel in precision
-// T with z tile tx: bit 0 planes, bit 1 z pass.
+// T with z tile tx: bit 0 planes, bit 1 z pass, bit 2 two-factor inverse
+// plane pass, bit 3 class-grouped slab (with z pass variant 3 only).
 template <class T>
 int ct_available(int n, int tx) {
     auto planes = [](size_t lds) { return lds <= LDS_MAX; };
@@ -1034,6 +1114,7 @@ int ct_available(int n, int tx) {
     if (planes((size_t)(n + n * (n + 1)) * sizeof(Cx<T>))) bits |= 1;
     if ((bits & 1) && n == 64) bits |= 4;  // two-factor inverse plane pass
     if (ct_zpass_fits<T>(n, tx, 0) || ct_zpass_fits<T>(n, tx, 2)) bits |= 2;
+    if ((bits & 3) == 3 && ct_zpass_fits<T>(n, tx, 3)) bits |= 8;  // class-grouped slab
     return bits;
 }
 

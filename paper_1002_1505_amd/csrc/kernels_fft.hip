@@ -471,6 +471,7 @@ bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh) {
         if ((sh.ct & av) != sh.ct) return false;
         if ((sh.ct & 2) && !ct_zpass_fits<T>(g.n1, sh.tx, sh.zrb)) return false;
         if ((sh.ct & 4) && !(sh.ct & 1)) return false;
+        if ((sh.ct & 8) && ((sh.ct & 3) != 3 || sh.zrb != 3)) return false;
         if ((sh.ct & 3) == 3) return true;
     }
     if (sh.tx <= 0 || (g.n1 % sh.tx) != 0) return false;
@@ -560,19 +561,26 @@ hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, co
 }
 
 template <class T>
-__global__ void k_green_interleave(const Cx<T>* __restrict__ gh, Cx<T>* __restrict__ gz, size_t cs) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cs; i += (size_t)gridDim.x * blockDim.x)
+__global__ void k_green_interleave(const Cx<T>* __restrict__ gh, Cx<T>* __restrict__ gz, size_t cs, int hx) {
+    const int H1 = hx + 1, Dx = 2 * H1;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cs; i += (size_t)gridDim.x * blockDim.x) {
+        size_t o = i;
+        if (hx) {  // x columns in the order of the class-grouped slab's groups
+            const int xi = (int)(i % Dx), half = xi / H1;
+            o = i - xi + half * H1 + spec_xpos(xi % H1, half, hx);
+        }
 #pragma unroll
-        for (int q = 0; q < 6; ++q) gz[i * 6 + q] = gh[q * cs + i];
+        for (int q = 0; q < 6; ++q) gz[o * 6 + q] = gh[q * cs + i];
+    }
 }
 
 template <class T>
-hipError_t launch_green_interleave(const Cx<T>* gh, Cx<T>* gz, size_t cs, hipStream_t st) {
-    hipLaunchKernelGGL((k_green_interleave<T>), dim3(1024), dim3(256), 0, st, gh, gz, cs);
+hipError_t launch_green_interleave(const Cx<T>* gh, Cx<T>* gz, size_t cs, int hx, hipStream_t st) {
+    hipLaunchKernelGGL((k_green_interleave<T>), dim3(1024), dim3(256), 0, st, gh, gz, cs, hx);
     return hipGetLastError();
 }
-template hipError_t launch_green_interleave<float>(const Cx<float>*, Cx<float>*, size_t, hipStream_t);
-template hipError_t launch_green_interleave<double>(const Cx<double>*, Cx<double>*, size_t, hipStream_t);
+template hipError_t launch_green_interleave<float>(const Cx<float>*, Cx<float>*, size_t, int, hipStream_t);
+template hipError_t launch_green_interleave<double>(const Cx<double>*, Cx<double>*, size_t, int, hipStream_t);
 
 hipError_t launch_green(const Geo& g, const Tw<double>& tw, const FftPlan* plans, double kd, Cx<double>* work,
                         Cx<double>* g64, Cx<float>* g32, hipStream_t st) {

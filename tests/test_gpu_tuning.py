@@ -25,7 +25,7 @@ def _shapes():
     out = []
     for tx in (8, 16, 32):
         for zrb in (0, 1, 2, 3):
-            for ct in (3, 7):
+            for ct in (3, 7, 11, 15):  # 8: class-grouped slab (n = 64, z pass variant 3)
                 out.append(dict(fused=1, nth_plane=256, nth_z=256, tx=tx, lines_tl=16, nth_lines=256, ct=ct, zrb=zrb))
     for tx in (4, 8, 16):
         for fused in (1, 0):
