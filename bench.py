@@ -30,12 +30,12 @@ METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM 
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
 # bench (2 rhs, 64^3 box), scaled by the counts of a 256 MiB device copy
-# (FETCH x 1.99974, WRITE x 1.0); valid only while the kernel source is the
+# (FETCH x 1.9998, WRITE x 1.0); valid only while the kernel source is the
 # one measured (SHA-256 prefix of the file that holds the kernel).
 MEASURED_TRAFFIC = {
-    "k_zpass4_ct<float, 64, 16>": {"source": "paper_1002_1505_amd/csrc/kernels_ct.hip",
-                                   "sha256": "b265628890a9dbd8", "fetch_kib": 31967.6, "write_kib": 49152.0,
-                                   "fetch_scale": 1.99974, "write_scale": 1.0},
+    "k_zpass4_ct<float, 64, 16, true>": {"source": "paper_1002_1505_amd/csrc/kernels_ct.hip",
+                                         "sha256": "3ed8323af2c121ee", "fetch_kib": 31541.6, "write_kib": 49152.0,
+                                         "fetch_scale": 1.9998, "write_scale": 1.0},
 }
 
 
@@ -155,10 +155,12 @@ def main():
     ms, by = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP32, reps=20)
     sh = ctx.get_shape(0, P.DDA_FP32)
     if sh["ct"] & 1:
+        grp = "true" if sh["ct"] & 8 else "false"  # class-grouped slab
         zname = {0: f"k_zpass_ct<float, {n}, {sh['tx']}>", 1: f"k_zpass2_ct<float, {n}, {sh['tx']}, 8>",
-                 2: f"k_zpass3_ct<float, {n}, {sh['tx']}>", 3: f"k_zpass4_ct<float, {n}, {sh['tx']}>"}[sh["zrb"]]
+                 2: f"k_zpass3_ct<float, {n}, {sh['tx']}>",
+                 3: f"k_zpass4_ct<float, {n}, {sh['tx']}, {grp}>"}[sh["zrb"]]
         iname = "k_pinv3_ct" if sh["ct"] & 4 else "k_pinv_ct"
-        names = [f"k_pfwd_ct<float, {n}, 0|1|2>", zname, f"{iname}<float, {n}, 0, 0|1|2>"]
+        names = [f"k_pfwd_ct<float, {n}, 0|1|2|3, {grp}>", zname, f"{iname}<float, {n}, 0, 0|1|2|3, {grp}>"]
     else:
         names = ["k_plane_fwd<float>", "k_zpass<float>", "k_plane_inv<float, 0>"]
     dom = int(np.argmax(ms))

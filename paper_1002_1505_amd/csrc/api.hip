@@ -544,8 +544,7 @@ dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
 template <class T>
 hipError_t matvec_group(const Target& t, Group& g, int nr, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, const int* active,
                         int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr},
-                        MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                          nullptr}) {
+                        MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr}) {
     Cx<T>* slab = std::is_same<T, double>::value ? g.slab64.as<Cx<T>>() : g.slab32.as<Cx<T>>();
     const Cx<T>* ainv = std::is_same<T, double>::value ? g.ainv64.as<Cx<T>>() : g.ainv32.as<Cx<T>>();
     return launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab, t.ghat_for<T>(t.shape<T>()), ainv, active,
@@ -625,11 +624,12 @@ hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st, int k) {
         const int nbv = vec_blocks(Np), nbp = fuse ? 12 * t.n[0] : nbv;
         if (!fuse) pin = pout = g.kv[3].as<Cx<T>>();  // separate update kernel works in place
         if (fuse) {
-            // the forward pass first applies the previous iteration's pending
-            // x, r update; the inverse pass reads the updated direction
-            // (written by the forward pass) for the diagonal term
-            if ((e = matvec_group<T>(t, g, nr, pout, v, nullptr, act, MV_AX, st, MvDot{1, rh, part},
-                                     MvUpd{3, r, v, pin, pout, rh, bs, s, tt, x})) != hipSuccess)
+            // one stream applies the previous iteration's pending x, r update
+            // and forms the new direction (a separate kernel: in the forward
+            // pass each of the four parity blocks of a plane would re-load all
+            // five vectors); the inverse pass forms <rhat, v>
+            if ((e = launch_bicg_upd<T>(Np, nr, x, r, pin, pout, v, rh, s, tt, bs, act, st)) != hipSuccess) return e;
+            if ((e = matvec_group<T>(t, g, nr, pout, v, nullptr, act, MV_AX, st, MvDot{1, rh, part})) != hipSuccess)
                 return e;
         } else {
             if ((e = launch_bicg_p<T>(Np, nr, pin, r, v, rh, bs, act, st)) != hipSuccess) return e;
@@ -642,7 +642,7 @@ hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st, int k) {
             // which the scalars follow without forming r = s - omega t; that
             // update is left pending for the next iteration's forward pass
             if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st, MvDot{3, rh, part},
-                                     MvUpd{2, r, v, nullptr, s, nullptr, bs, nullptr, nullptr, nullptr})) !=
+                                     MvUpd{2, r, v, s, bs})) !=
                 hipSuccess)
                 return e;
             if ((e = launch_scalars(3, nbp, nr, bs, part, act, k & 1, st)) != hipSuccess) return e;

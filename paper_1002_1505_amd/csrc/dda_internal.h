@@ -72,21 +72,14 @@ struct MvShape {
 };
 
 // Optional BiCGstab vector update fused into the first matvec pass
-// (specialised plane kernels only): mode 1 = direction update into pout,
-// mode 2 = s = r - alpha v into pout, mode 3 = mode 1 after applying the
-// pending update r = s - omega t, x += alpha p + omega s of the previous
-// iteration when st.pend; the transformed vector is the updated one.
+// (specialised plane kernels only): mode 2 = s = r - alpha v (alpha from st)
+// into pout, and the transformed vector is s; mode 0 = none.
 struct MvUpd {
     int mode;
-    void* r;
+    const void* r;
     const void* v;
-    const void* p;
     void* pout;
-    void* rhat;
     const BiState* st;
-    const void* s;  // mode 3: pending update inputs s, t and the solution x
-    const void* t;
-    void* x;
 };
 
 // Optional inner products fused into the last matvec pass (specialised plane
@@ -106,16 +99,14 @@ template <class T>
 hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh, int nrhs,
                          const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
                          const Cx<T>* ainv, const int* active, int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr},
-                         MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                           nullptr});
+                         MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr});
 // Individual passes (for per-pass profiling).
 template <class T>
 hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh,
                        int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
                        const Cx<T>* ainv, const int* active, int mode, hipStream_t st,
                        MvDot dot = MvDot{0, nullptr, nullptr},
-                       MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                         nullptr});
+                       MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr});
 // Shared-memory bytes and feasibility of a shape.
 template <class T>
 bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh);
@@ -170,6 +161,12 @@ hipError_t launch_scalars(int which, int nblk, int nrhs, BiState* s, const doubl
                           hipStream_t st);
 // Apply the pending update of a fused iteration (BiState.pend): x += alpha p +
 // omega s, r = s - omega t with p in p0 or p1 by BiState.pbuf; clears pend.
+// Fused iteration's direction update as a separate stream over all sites
+// (what the forward pass does in mode 3), p' into pout.
+template <class T>
+hipError_t launch_bicg_upd(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p, Cx<T>* pout, const Cx<T>* v,
+                           Cx<T>* rhat, const Cx<T>* s, const Cx<T>* t, const BiState* st, const int* active,
+                           hipStream_t stream);
 template <class T>
 hipError_t launch_bicg_flush(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p0, const Cx<T>* p1,
                              const Cx<T>* s, const Cx<T>* t, BiState* st, hipStream_t stream);

@@ -41,23 +41,14 @@ __device__ __forceinline__ int fold_idx(int k, int n, int& sgn) {
 template <int N> constexpr int plane_threads() { return N >= 128 ? 1024 : 256; }
 template <int N> constexpr int zpass_threads() { return N >= 128 ? 512 : 256; }
 
-// UPD = 0: transform x.  UPD = 1: BiCGstab direction update p' = r + beta (p - omega v)
-// (p' = r and rhat = r on restart), transform p' and store it in pout.
-// UPD = 2: s = r - alpha v, transform s and store it in pout.  UPD = 3: as
-// UPD = 1, but when st.pend the residual is first formed as r = s - omega t
-// and stored together with x += alpha p + omega s (the update the previous
-// iteration left pending).  Only the parity-0 block of a plane stores, and
-// pout never aliases an input.
+// UPD = 0: transform x.  UPD = 2: BiCGstab update s = r - alpha v, transform
+// s and store it in pout (only the parity-0 block of a plane stores; pout
+// never aliases an input).
 struct UpdArgs {
-    void* r;
+    const void* r;
     const void* v;
-    const void* p;
     void* pout;
-    void* rhat;
     const BiState* st;
-    const void* s;
-    const void* t;
-    void* x;
 };
 
 template <class T, int N, int UPD, bool G>
@@ -85,26 +76,11 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     __syncthreads();
     const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
     const int j0 = g.plane_start[z], j1 = g.plane_start[z + 1];
-    Cx<T> c1 = {0, 0}, c2 = {0, 0}, c3 = {0, 0};
-    int restart = 0, pend = 0;
-    if (UPD == 1 || UPD == 3) {
-        const BiState sv = u.st[rhs];
-        c1 = Cx<T>{(T)sv.beta[0], (T)sv.beta[1]};
-        c2 = Cx<T>{(T)sv.omega[0], (T)sv.omega[1]};
-        c3 = Cx<T>{(T)sv.alpha[0], (T)sv.alpha[1]};
-        restart = sv.restart;
-        pend = UPD == 3 ? sv.pend : 0;
-    } else if (UPD == 2) {
-        c1 = Cx<T>{(T)u.st[rhs].alpha[0], (T)u.st[rhs].alpha[1]};
-    }
-    Cx<T>* rv = reinterpret_cast<Cx<T>*>(u.r);
-    const Cx<T>* sv_ = reinterpret_cast<const Cx<T>*>(u.s);
-    const Cx<T>* tv_ = reinterpret_cast<const Cx<T>*>(u.t);
-    Cx<T>* xv_ = reinterpret_cast<Cx<T>*>(u.x);
+    Cx<T> c1 = {0, 0};
+    if (UPD == 2) c1 = Cx<T>{(T)u.st[rhs].alpha[0], (T)u.st[rhs].alpha[1]};
+    const Cx<T>* rv = reinterpret_cast<const Cx<T>*>(u.r);
     const Cx<T>* vv = reinterpret_cast<const Cx<T>*>(u.v);
-    const Cx<T>* pv = reinterpret_cast<const Cx<T>*>(u.p);
     Cx<T>* po = reinterpret_cast<Cx<T>*>(u.pout);
-    Cx<T>* rh = reinterpret_cast<Cx<T>*>(u.rhat);
 #pragma unroll 4
     for (int j = j0 + tid; j < j1; j += NTH) {
         const uint32_t s = g.site_xyz[j];
@@ -112,23 +88,6 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
         Cx<T> v;
         if (UPD == 0) {
             v = x[vo + j];
-        } else if (UPD == 1 || UPD == 3) {
-            Cx<T> rj;
-            if (UPD == 3 && pend) {
-                const Cx<T> sj = sv_[vo + j];
-                rj = sj - c2 * tv_[vo + j];
-                if (par == 0) {
-                    rv[vo + j] = rj;
-                    xv_[vo + j] = xv_[vo + j] + c3 * pv[vo + j] + c2 * sj;
-                }
-            } else {
-                rj = rv[vo + j];
-            }
-            v = restart ? rj : rj + c1 * (pv[vo + j] - c2 * vv[vo + j]);
-            if (par == 0) {
-                po[vo + j] = v;
-                if (restart) rh[vo + j] = rj;
-            }
         } else {
             v = rv[vo + j] - c1 * vv[vo + j];
             if (par == 0) po[vo + j] = v;
@@ -925,11 +884,10 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
         } else {
             const bool tf = (ct & 4) != 0, gr = (ct & 8) != 0;
             if (which == 0) {
-                const UpdArgs ua{upd.r, upd.v, upd.p, upd.pout, upd.rhat, upd.st, upd.s, upd.t, upd.x};
-                if (upd.mode == 3) launch_pfwd<T, N, 3>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
-                else if (upd.mode == 1) launch_pfwd<T, N, 1>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
-                else if (upd.mode == 2) launch_pfwd<T, N, 2>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
-                else launch_pfwd<T, N, 0>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
+                const UpdArgs ua{upd.r, upd.v, upd.pout, upd.st};
+                if (upd.mode == 2) launch_pfwd<T, N, 2>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
+                else if (upd.mode == 0) launch_pfwd<T, N, 0>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
+                else return hipErrorInvalidValue;
             } else if (mode == MV_AX) {
                 if (dot == 1) launch_pinv<T, N, MV_AX, 1>(nblk_plane, tf, gr, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
                 else if (dot == 2) launch_pinv<T, N, MV_AX, 2>(nblk_plane, tf, gr, g, tw, nrhs, x, y, b, slab, ainv, active, w, partials, st);
@@ -1020,8 +978,7 @@ hipError_t set_attrs_n() {
     const int lim = 160 * 1024;
     hipError_t e = hipSuccess;
     if constexpr (plane_lds<T, N>() <= LDS_MAX) {
-        const void* fns[] = {(const void*)k_pfwd_ct<T, N, 0, false>, (const void*)k_pfwd_ct<T, N, 1, false>,
-                             (const void*)k_pfwd_ct<T, N, 2, false>, (const void*)k_pfwd_ct<T, N, 3, false>,
+        const void* fns[] = {(const void*)k_pfwd_ct<T, N, 0, false>, (const void*)k_pfwd_ct<T, N, 2, false>,
                              (const void*)k_pinv_ct<T, N, MV_AX, 0, false>, (const void*)k_pinv_ct<T, N, MV_AX, 1, false>,
                              (const void*)k_pinv_ct<T, N, MV_AX, 2, false>, (const void*)k_pinv_ct<T, N, MV_AX, 3, false>,
                              (const void*)k_pinv_ct<T, N, MV_RESID, 0, false>};
@@ -1032,8 +989,7 @@ hipError_t set_attrs_n() {
                 (const void*)k_pinv3_ct<T, N, MV_AX, 0, false>, (const void*)k_pinv3_ct<T, N, MV_AX, 1, false>,
                 (const void*)k_pinv3_ct<T, N, MV_AX, 2, false>, (const void*)k_pinv3_ct<T, N, MV_AX, 3, false>,
                 (const void*)k_pinv3_ct<T, N, MV_RESID, 0, false>,
-                (const void*)k_pfwd_ct<T, N, 0, true>, (const void*)k_pfwd_ct<T, N, 1, true>,
-                (const void*)k_pfwd_ct<T, N, 2, true>, (const void*)k_pfwd_ct<T, N, 3, true>,
+                (const void*)k_pfwd_ct<T, N, 0, true>, (const void*)k_pfwd_ct<T, N, 2, true>,
                 (const void*)k_pinv_ct<T, N, MV_AX, 0, true>, (const void*)k_pinv_ct<T, N, MV_AX, 1, true>,
                 (const void*)k_pinv_ct<T, N, MV_AX, 2, true>, (const void*)k_pinv_ct<T, N, MV_AX, 3, true>,
                 (const void*)k_pinv_ct<T, N, MV_RESID, 0, true>,

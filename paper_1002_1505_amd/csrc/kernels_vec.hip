@@ -304,6 +304,45 @@ __global__ void __launch_bounds__(VT) k_bicg_flush(int V, Cx<T>* __restrict__ x,
     }
 }
 
+// Direction update of a fused iteration, ahead of its forward pass: first the
+// pending x, r update of the previous iteration when st.pend (x += alpha p +
+// omega s, r = s - omega t), then p' = r + beta (p - omega v), or p' = r and
+// rhat = r on restart.  p' goes to its own buffer (pout never aliases p).
+template <class T>
+__global__ void __launch_bounds__(VT) k_bicg_upd(int V, Cx<T>* __restrict__ x, Cx<T>* __restrict__ r,
+                                                 const Cx<T>* __restrict__ p, Cx<T>* __restrict__ pout,
+                                                 const Cx<T>* __restrict__ v, Cx<T>* __restrict__ rhat,
+                                                 const Cx<T>* __restrict__ s, const Cx<T>* __restrict__ t,
+                                                 const BiState* __restrict__ st, const int* __restrict__ active) {
+    const int rhs = blockIdx.y;
+    if (inactive(active, rhs)) return;
+    const BiState b = st[rhs];
+    const Cx<T> al = {(T)b.alpha[0], (T)b.alpha[1]}, om = {(T)b.omega[0], (T)b.omega[1]};
+    const Cx<T> be = {(T)b.beta[0], (T)b.beta[1]};
+    const size_t o = (size_t)rhs * V;
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i < V) {
+            const Cx<T> pi = p[o + i];
+            Cx<T> ri;
+            if (b.pend) {
+                const Cx<T> si = s[o + i];
+                ri = si - om * t[o + i];
+                r[o + i] = ri;
+                x[o + i] = x[o + i] + al * pi + om * si;
+            } else {
+                ri = r[o + i];
+            }
+            if (b.restart) {
+                rhat[o + i] = ri;
+                pout[o + i] = ri;
+            } else {
+                pout[o + i] = ri + be * (pi - om * v[o + i]);
+            }
+        }
+    }
+}
+
 __global__ void k_clear_pend(BiState* st, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) st[i].pend = 0;
@@ -712,6 +751,20 @@ hipError_t launch_scalars(int which, int nblk, int nrhs, BiState* s, const doubl
     hipLaunchKernelGGL(k_scalars, dim3(nrhs), dim3(256), 0, st, which, nblk, s, partials, active, kpar);
     return hipGetLastError();
 }
+template <class T>
+hipError_t launch_bicg_upd(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p, Cx<T>* pout, const Cx<T>* v,
+                           Cx<T>* rhat, const Cx<T>* s, const Cx<T>* t, const BiState* st, const int* active,
+                           hipStream_t stream) {
+    hipLaunchKernelGGL((k_bicg_upd<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, stream, 3 * Npad, x, r, p, pout, v,
+                       rhat, s, t, st, active);
+    return hipGetLastError();
+}
+template hipError_t launch_bicg_upd<float>(int, int, Cx<float>*, Cx<float>*, const Cx<float>*, Cx<float>*,
+                                           const Cx<float>*, Cx<float>*, const Cx<float>*, const Cx<float>*,
+                                           const BiState*, const int*, hipStream_t);
+template hipError_t launch_bicg_upd<double>(int, int, Cx<double>*, Cx<double>*, const Cx<double>*, Cx<double>*,
+                                            const Cx<double>*, Cx<double>*, const Cx<double>*, const Cx<double>*,
+                                            const BiState*, const int*, hipStream_t);
 template <class T>
 hipError_t launch_bicg_flush(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p0, const Cx<T>* p1,
                              const Cx<T>* s, const Cx<T>* t, BiState* st, hipStream_t stream) {
