@@ -199,6 +199,23 @@ dda_status dda_inverse_polarizability(const dda_ctx* ctx, int32_t target, const 
  * Calculate?"; sums from Draine 1988).  FP64 reductions on the device. */
 dda_status dda_cross_sections(dda_ctx* ctx, int32_t nrhs, double* q);
 
+/* Efficiencies at other target rotations Phi about the incidence direction
+ * without new solves (guide, section "Scattering by Finite Targets", the
+ * IORTH remark: the solution for another Phi is a linear combination of the
+ * solutions for two incident polarizations of one orientation).  Right-hand
+ * sides 2p and 2p+1 of the last solve form pair p: one target, one incidence
+ * direction, polarizations e_0, e_1.  coeffs: npairs x ncomb x 2 (output
+ * state l) x 2 (basis a) complex128 (re, im) with E_l = sum_a c[l][a] E_a,
+ * e.g. from dda_phi_coefficients; the solution is combined the same way.
+ * q: npairs x ncomb x 2 x {Q_ext, Q_abs, Q_sca}, the sums of
+ * dda_cross_sections on the combined field and solution (FP64 pair sums on
+ * the device, 2 x 2 bilinear forms combined on the host).  Exact only when
+ * 1/alpha does not depend on the polarization: DDA_ERR_INVALID_ARG for LDR
+ * targets, for 2 * npairs != rhs count of the last solve, and for pairs that
+ * span two targets or two incidence directions; DDA_ERR_STATE before a
+ * solve. */
+dda_status dda_cross_sections_phi(dda_ctx* ctx, int32_t npairs, int32_t ncomb, const double* coeffs, double* q);
+
 /* Scattering amplitudes of the last solve:
  *   f[rhs][dir][m] = k^3 e_m . sum_j P_j exp(-i k n_dir . r_j),  m = 0, 1,
  * with n (ndir x 3 doubles) and the two scattered polarization vectors e_1,
@@ -237,6 +254,31 @@ dda_status dda_lab_frame(double beta, double theta, double phi, const double* a1
  * receive the waves with target = `target`. */
 dda_status dda_orientation_waves(double beta, double theta, double phi, const double* a1, const double* a2,
                                  const double* e01, int32_t target, dda_wave* out);
+
+/* Orientation samples and weights for orientational averages (guide,
+ * sections "Sampling in Theta, Phi, and beta" and "Orientational
+ * Averaging").  lims: {BETAMI, BETAMX, THETMI, THETMX, PHIMIN, PHIMAX} in
+ * radians; counts: {NBETA, NTHETA, NPHI}, each >= 1.  beta (NBETA) and phi
+ * (NPHI) are the midpoints of equal intervals of their ranges; theta
+ * (NTHETA) is uniform in cos(Theta): for odd NTHETA from THETMI to THETMX
+ * inclusive with Simpson weights (1, 4, 2, ..., 4, 1) / (3 (NTHETA - 1)), for
+ * even NTHETA the midpoints of NTHETA equal intervals of cos(Theta) with
+ * weight 1/NTHETA (the guide prints the odd-NTHETA weights over NTHETA,
+ * which does not sum to one; the normalized Simpson form is used), for
+ * NTHETA = 1 THETMI alone.  weight: NBETA x NTHETA x NPHI (beta slowest),
+ * the product of the beta, Theta and Phi weights; it sums to one.  Host
+ * arithmetic; DDA_ERR_INVALID_ARG for NULL pointers or counts < 1. */
+dda_status dda_orientation_samples(const double* lims, const int32_t* counts, double* beta, double* theta,
+                                   double* phi, double* weight);
+
+/* Combination coefficients for other rotations Phi of one (beta, Theta): for
+ * each phi[k], c[k][l][a] (complex128, (re, im)) with e_l(beta, Theta, phi[k])
+ * = sum_a c[k][l][a] e_a(beta, Theta, phi_ref), the target-frame incident
+ * polarizations of dda_orientation_waves (same a1, a2, e01 arguments).  The
+ * incidence direction does not depend on Phi, so the fields combine the same
+ * way.  coeffs: nphi x 2 x 2 complex128.  Host arithmetic. */
+dda_status dda_phi_coefficients(double beta, double theta, double phi_ref, int32_t nphi, const double* phi,
+                                const double* a1, const double* a2, const double* e01, double* coeffs);
 
 /* Target-frame scattering directions and polarization basis for lab-frame
  * scattering angles: n = x cos(theta) + y sin(theta) cos(phi) + z sin(theta)

@@ -184,6 +184,16 @@ class Context:
         _check(self.h, self.lib.dda_cross_sections(self.h, int(nrhs), _dptr(q)))
         return q.reshape(nrhs, 3)
 
+    def cross_sections_phi(self, coeffs):
+        """Efficiencies of combined polarization pairs (dda_cross_sections_phi):
+        coeffs (npairs, ncomb, 2, 2) complex; returns (npairs, ncomb, 2, 3)."""
+        c = np.asarray(coeffs, dtype=np.complex128)
+        npairs, ncomb = c.shape[0], c.shape[1]
+        cc = np.ascontiguousarray(np.stack([c.real, c.imag], axis=-1).reshape(-1))
+        q = np.zeros(npairs * ncomb * 2 * 3)
+        _check(self.h, self.lib.dda_cross_sections_phi(self.h, int(npairs), int(ncomb), _dptr(cc), _dptr(q)))
+        return q.reshape(npairs, ncomb, 2, 3)
+
     def amplitudes(self, nrhs: int, n_tf, e_tf):
         n_tf = np.ascontiguousarray(n_tf, dtype=np.float64).reshape(-1, 3)
         e_tf = np.ascontiguousarray(e_tf, dtype=np.float64).reshape(-1, 6)
@@ -252,6 +262,40 @@ def orientation_waves(beta, theta, phi, e01=None, a1=None, a2=None, target=0):
     kh = np.array([[out[w].khat[i] for i in range(3)] for w in range(2)])
     e0 = np.array([[out[w].e0[2 * i] + 1j * out[w].e0[2 * i + 1] for i in range(3)] for w in range(2)])
     return kh, e0
+
+
+def orientation_samples(lims, counts):
+    """(beta, theta, phi, weight (nb, nt, np)) of dda_orientation_samples;
+    lims = (BETAMI, BETAMX, THETMI, THETMX, PHIMIN, PHIMAX) in radians."""
+    lib = L.load()
+    lm = np.ascontiguousarray(lims, dtype=np.float64)
+    n = (C.c_int32 * 3)(*[int(v) for v in counts])
+    b, t, p = np.zeros(n[0]), np.zeros(n[1]), np.zeros(n[2])
+    w = np.zeros(n[0] * n[1] * n[2])
+    st = lib.dda_orientation_samples(_dptr(lm), n, _dptr(b), _dptr(t), _dptr(p), _dptr(w))
+    if st < 0:
+        raise DDAError(st, "dda_orientation_samples")
+    return b, t, p, w.reshape(n[0], n[1], n[2])
+
+
+def phi_coefficients(beta, theta, phi_ref, phis, e01=None, a1=None, a2=None):
+    """c (nphi, 2, 2) complex of dda_phi_coefficients."""
+    lib = L.load()
+    ph = np.ascontiguousarray(phis, dtype=np.float64).reshape(-1)
+    e = None
+    if e01 is not None:
+        ev = np.asarray(e01, dtype=np.complex128)
+        e = np.ascontiguousarray(np.stack([ev.real, ev.imag], axis=1).reshape(-1))
+    a1 = None if a1 is None else np.ascontiguousarray(a1, dtype=np.float64)
+    a2 = None if a2 is None else np.ascontiguousarray(a2, dtype=np.float64)
+    out = np.zeros(len(ph) * 8)
+    st = lib.dda_phi_coefficients(float(beta), float(theta), float(phi_ref), len(ph), _dptr(ph),
+                                  None if a1 is None else _dptr(a1), None if a2 is None else _dptr(a2),
+                                  None if e is None else _dptr(e), _dptr(out))
+    if st < 0:
+        raise DDAError(st, "dda_phi_coefficients")
+    out = out.reshape(len(ph), 2, 2, 2)
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def scattering_frame(theta, phi, lab_axes):

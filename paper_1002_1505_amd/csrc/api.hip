@@ -1412,6 +1412,80 @@ dda_status dda_cross_sections(dda_ctx* c, int32_t nrhs, double* q) {
     return DDA_OK;
 }
 
+dda_status dda_cross_sections_phi(dda_ctx* c, int32_t npairs, int32_t ncomb, const double* coeffs, double* q) {
+    SCHK(check_ctx(c));
+    if (!c->have_solution) return fail(c, DDA_ERR_STATE, "cross_sections_phi before a solve");
+    if (npairs < 1 || ncomb < 1 || !coeffs || !q || 2 * npairs != c->last_nrhs)
+        return fail(c, DDA_ERR_INVALID_ARG, "cross_sections_phi: need 2 * npairs == rhs of the last solve");
+    for (int p = 0; p < npairs; ++p) {
+        const int i0 = 2 * p, i1 = 2 * p + 1;
+        if (c->rhs_group[i0] != c->rhs_group[i1])
+            return fail(c, DDA_ERR_INVALID_ARG, "cross_sections_phi: pair %d spans two targets", p);
+        const dda_wave &w0 = c->last_waves[i0], &w1 = c->last_waves[i1];
+        for (int k = 0; k < 3; ++k)
+            if (std::abs(w0.khat[k] - w1.khat[k]) > 1e-12)
+                return fail(c, DDA_ERR_INVALID_ARG, "cross_sections_phi: pair %d has two incidence directions", p);
+        const Target& t = *c->tg[c->groups[c->rhs_group[i0]]->tgt];
+        if (t.alpha_kind == DDA_ALPHA_LDR)
+            return fail(c, DDA_ERR_INVALID_ARG,
+                        "cross_sections_phi: the LDR polarizability depends on the polarization, so combinations "
+                        "of solutions are not solutions");
+    }
+    hipStream_t st = c->stream;
+    DevMem dslots, dpart;
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        Group& g = *c->groups[gi];
+        const Target& t = *c->tg[g.tgt];
+        std::vector<int> pairs, slots;
+        for (int p = 0; p < npairs; ++p)
+            if (c->rhs_group[2 * p] == (int)gi) {
+                pairs.push_back(p);
+                slots.push_back(c->rhs_slot[2 * p]);
+                slots.push_back(c->rhs_slot[2 * p + 1]);
+            }
+        if (pairs.empty()) continue;
+        const int np = (int)pairs.size(), nblk = xsec_pair_blocks(t.N);
+        HCHK(c, dslots.ensure(slots.size() * sizeof(int)));
+        HCHK(c, dpart.ensure((size_t)np * nblk * 16 * sizeof(double)));
+        HCHK(c, hipMemcpyAsync(dslots.p, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        HCHK(c, launch_xsec_pair(t.geo(), np, g.b64.as<Cx<double>>(), g.x64.as<Cx<double>>(),
+                                 g.ainv64.as<Cx<double>>(), t.kd * t.kd * t.kd, dslots.as<int>(), dpart.as<double>(),
+                                 st));
+        std::vector<double> h((size_t)np * nblk * 16);
+        HCHK(c, hipMemcpyAsync(h.data(), dpart.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HCHK(c, hipStreamSynchronize(st));
+        const double scale = 4 * PI * t.kd / (PI * t.aeff * t.aeff);
+        for (int k = 0; k < np; ++k) {
+            double v[16] = {0};
+            for (int b = 0; b < nblk; ++b)
+                for (int e = 0; e < 16; ++e) v[e] += h[((size_t)k * nblk + b) * 16 + e];
+            cd S[2][2], G[2][2];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    S[a][b] = cd(v[2 * (2 * a + b)], v[2 * (2 * a + b) + 1]);
+                    G[a][b] = cd(v[8 + 2 * (2 * a + b)], v[9 + 2 * (2 * a + b)]);
+                }
+            const int p = pairs[k];
+            for (int m = 0; m < ncomb; ++m)
+                for (int l = 0; l < 2; ++l) {
+                    const double* cc = coeffs + (((size_t)p * ncomb + m) * 2 + l) * 4;
+                    const cd cl[2] = {cd(cc[0], cc[1]), cd(cc[2], cc[3])};
+                    cd ext = 0, ab = 0;
+                    for (int a = 0; a < 2; ++a)
+                        for (int b = 0; b < 2; ++b) {
+                            ext += std::conj(cl[a]) * cl[b] * S[a][b];
+                            ab += std::conj(cl[a]) * cl[b] * G[a][b];
+                        }
+                    double* o = q + (((size_t)p * ncomb + m) * 2 + l) * 3;
+                    o[0] = scale * ext.imag();
+                    o[1] = scale * ab.real();
+                    o[2] = o[0] - o[1];
+                }
+        }
+    }
+    return DDA_OK;
+}
+
 dda_status dda_amplitudes(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* n_tf, const double* e_tf, double* f) {
     SCHK(check_ctx(c));
     if (!c->have_solution) return fail(c, DDA_ERR_STATE, "amplitudes before a solve");
@@ -1540,6 +1614,60 @@ dda_status dda_orientation_waves(double beta, double theta, double phi, const do
         }
         out[w].target = target;
         out[w].pad_ = 0;
+    }
+    return DDA_OK;
+}
+
+dda_status dda_orientation_samples(const double* lims, const int32_t* counts, double* beta, double* theta, double* phi,
+                                   double* weight) {
+    if (!lims || !counts || !beta || !theta || !phi || !weight) return DDA_ERR_INVALID_ARG;
+    const int nb = counts[0], nt = counts[1], np = counts[2];
+    if (nb < 1 || nt < 1 || np < 1) return DDA_ERR_INVALID_ARG;
+    for (int i = 0; i < nb; ++i) beta[i] = lims[0] + (i + 0.5) * (lims[1] - lims[0]) / nb;
+    for (int i = 0; i < np; ++i) phi[i] = lims[4] + (i + 0.5) * (lims[5] - lims[4]) / np;
+    // Theta uniform in cos(Theta): both ends and Simpson's rule for odd counts,
+    // interval midpoints and equal weights for even counts
+    const double u0 = std::cos(lims[2]), u1 = std::cos(lims[3]);
+    std::vector<double> wt(nt);
+    for (int j = 0; j < nt; ++j) {
+        double u;
+        if (nt == 1) {
+            theta[j] = lims[2];
+            wt[j] = 1;
+            continue;
+        }
+        if (nt % 2) {
+            u = u0 + j * (u1 - u0) / (nt - 1);
+            wt[j] = (j == 0 || j == nt - 1) ? 1.0 : (j % 2 ? 4.0 : 2.0);
+            wt[j] /= 3.0 * (nt - 1);
+        } else {
+            u = u0 + (j + 0.5) * (u1 - u0) / nt;
+            wt[j] = 1.0 / nt;
+        }
+        theta[j] = std::acos(std::max(-1.0, std::min(1.0, u)));
+    }
+    for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nt; ++j)
+            for (int k = 0; k < np; ++k) weight[((size_t)i * nt + j) * np + k] = wt[j] / ((double)nb * np);
+    return DDA_OK;
+}
+
+dda_status dda_phi_coefficients(double beta, double theta, double phi_ref, int32_t nphi, const double* phi,
+                                const double* a1, const double* a2, const double* e01, double* coeffs) {
+    if (nphi < 1 || !phi || !coeffs) return DDA_ERR_INVALID_ARG;
+    dda_wave ref[2], w[2];
+    dda_status s = dda_orientation_waves(beta, theta, phi_ref, a1, a2, e01, 0, ref);
+    if (s < 0) return s;
+    for (int k = 0; k < nphi; ++k) {
+        if ((s = dda_orientation_waves(beta, theta, phi[k], a1, a2, e01, 0, w)) < 0) return s;
+        for (int l = 0; l < 2; ++l)
+            for (int a = 0; a < 2; ++a) {
+                cd v = 0;
+                for (int i = 0; i < 3; ++i)
+                    v += std::conj(cd(ref[a].e0[2 * i], ref[a].e0[2 * i + 1])) * cd(w[l].e0[2 * i], w[l].e0[2 * i + 1]);
+                coeffs[((size_t)k * 2 + l) * 4 + 2 * a] = v.real();
+                coeffs[((size_t)k * 2 + l) * 4 + 2 * a + 1] = v.imag();
+            }
     }
     return DDA_OK;
 }

@@ -199,6 +199,13 @@ hipError_t launch_to_abi(const Geo& g, int nrhs, const Cx<T>* in, Cx<double>* ou
 // Cross-section sums: out[rhs] = {sum Im(E^* . P), sum |P|^2 * (-Im ainv_c - (2/3) k^3)}.
 hipError_t launch_xsec(const Geo& g, int nrhs, const Cx<double>* E, const Cx<double>* P, const Cx<double>* ainv,
                        double k3, double* partials, double* out, hipStream_t st);
+// Pair sums of the cross sections of combined solutions: for each pair of
+// slots (slots[2p], slots[2p+1]), xsec_pair_blocks(N) block partials of the
+// 16 doubles S_ab = sum conj(E_a) . P_b, G_ab = sum w conj(P_a) . P_b
+// (w = -Im ainv - (2/3) k^3) into part[(p * nblk + blk) * 16 + q].
+int xsec_pair_blocks(int N);
+hipError_t launch_xsec_pair(const Geo& g, int npairs, const Cx<double>* E, const Cx<double>* P,
+                            const Cx<double>* ainv, double k3, const int* slots, double* part, hipStream_t st);
 // Amplitude sums F[rhs][dir][3] = sum_j P_j exp(-i k n . r_j) (FP64).
 // Site chunks per (direction, rhs) of the amplitude sums; partials holds
 // ampl_chunks * nrhs * ndir * 6 doubles.

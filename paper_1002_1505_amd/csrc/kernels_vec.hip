@@ -517,6 +517,43 @@ __global__ void k_xsec_final(int nblk, const double* __restrict__ partials, doub
     }
 }
 
+// Pair sums for the cross sections of linear combinations of two solutions
+// (slots s0, s1 of one group): S_ab = sum_j conj(E_a,j) . P_b,j and
+// G_ab = sum_j w_j conj(P_a,j) . P_b,j with w_j = -Im(1/alpha_j) - (2/3) k^3
+// (1/alpha of slot s0).  Block partials, (re, im) of S00 S01 S10 S11 G00 G01
+// G10 G11: part[((pair * gridDim.x) + blk) * 16 + q].
+__global__ void __launch_bounds__(256) k_xsec_pair(Geo g, const Cx<double>* __restrict__ E,
+                                                   const Cx<double>* __restrict__ P,
+                                                   const Cx<double>* __restrict__ ainv, double k3,
+                                                   const int* __restrict__ slots, double* __restrict__ part) {
+    __shared__ double sh[16 * 4];
+    const int pr = blockIdx.y;
+    const int s0 = slots[2 * pr], s1 = slots[2 * pr + 1];
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.N; j += gridDim.x * blockDim.x) {
+        const double w = -ainv[(size_t)s0 * g.ncomp + g.site_comp[j]].im - (2.0 / 3.0) * k3;
+        for (int c = 0; c < 3; ++c) {
+            const Cx<double> e[2] = {E[((size_t)s0 * 3 + c) * g.Npad + j], E[((size_t)s1 * 3 + c) * g.Npad + j]};
+            const Cx<double> p[2] = {P[((size_t)s0 * 3 + c) * g.Npad + j], P[((size_t)s1 * 3 + c) * g.Npad + j]};
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int q = 2 * (2 * a + b);
+                    acc[q] += e[a].re * p[b].re + e[a].im * p[b].im;
+                    acc[q + 1] += e[a].re * p[b].im - e[a].im * p[b].re;
+                    acc[8 + q] += w * (p[a].re * p[b].re + p[a].im * p[b].im);
+                    acc[9 + q] += w * (p[a].re * p[b].im - p[a].im * p[b].re);
+                }
+        }
+    }
+    block_sum_n<16>(acc, sh);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 16; ++q) part[((size_t)pr * gridDim.x + blockIdx.x) * 16 + q] = acc[q];
+}
+
 // One block per (direction, rhs): F = sum_j P_j exp(-i k n . r_j), FP64.
 // Block (dir, rhs, chunk): partial sums of F over one chunk of the sites,
 // partials[((chunk * nrhs + rhs) * ndir + dir) * 6 + q].
@@ -830,6 +867,13 @@ hipError_t launch_xsec(const Geo& g, int nrhs, const Cx<double>* E, const Cx<dou
     hipLaunchKernelGGL(k_xsec_part, dim3(nblk, nrhs), dim3(VT), 0, st, g, E, P, ainv, k3, partials);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_xsec_final, dim3(nrhs), dim3(256), 0, st, nblk, partials, out);
+    return hipGetLastError();
+}
+int xsec_pair_blocks(int N) { return std::max(1, std::min(256, (N + 255) / 256)); }
+hipError_t launch_xsec_pair(const Geo& g, int npairs, const Cx<double>* E, const Cx<double>* P,
+                            const Cx<double>* ainv, double k3, const int* slots, double* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_xsec_pair, dim3(xsec_pair_blocks(g.N), npairs), dim3(256), 0, st, g, E, P, ainv, k3, slots,
+                       part);
     return hipGetLastError();
 }
 int ampl_chunks(int ndir, int nrhs, int N) {

@@ -75,3 +75,31 @@ def test_no_device_error_is_clean():
         pass
     with pytest.raises(P.DDAError):
         P.Context(0)
+
+
+def test_orientation_helpers_without_gpu():
+    """dda_orientation_samples and dda_phi_coefficients are host arithmetic;
+    checked against the oracle's sampling rules and polarization projection."""
+    import numpy as np
+
+    import paper_1002_1505_amd as P
+    from oracle import orient as O
+
+    lims = np.deg2rad([0, 360, 0, 180, 0, 360])
+    for counts in [(1, 1, 1), (2, 3, 2), (3, 4, 5), (4, 7, 3)]:
+        got, want = P.orientation_samples(lims, counts), O.orientation_samples(lims, counts)
+        for g, w in zip(got, want):
+            assert np.allclose(g, w, atol=1e-14)
+    lims = np.deg2rad([10, 80, 20, 150, 5, 95])
+    got, want = P.orientation_samples(lims, (3, 2, 4)), O.orientation_samples(lims, (3, 2, 4))
+    for g, w in zip(got, want):
+        assert np.allclose(g, w, atol=1e-14)
+    rng = np.random.default_rng(2)
+    for _ in range(4):
+        be, th, p0 = rng.uniform(0, 2 * np.pi, 3)
+        phis = rng.uniform(0, 2 * np.pi, 3)
+        c = P.phi_coefficients(be, th, p0, phis)
+        for k, ph in enumerate(phis):
+            assert np.allclose(c[k], O.phi_coefficients(be, th, p0, ph), atol=1e-13)
+    with pytest.raises(P.DDAError):
+        P.orientation_samples(lims, (0, 1, 1))

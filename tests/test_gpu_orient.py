@@ -1,0 +1,128 @@
+"""Orientational averaging on the GPU: efficiencies at other rotations Phi
+from polarization pairs (dda_cross_sections_phi) against the oracle's
+combination of dense solutions, its error paths, and a full average over
+(beta, Theta, Phi) against the oracle's."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dda
+from oracle import orient as O
+
+pytestmark = pytest.mark.gpu
+
+M = [1.6 + 0.15j]
+KD = 0.45
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1002_1505_amd as P
+
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _target():
+    occ = synth.ellipsoid_occupancy((10, 9, 8), (9.5, 7.4, 6.1))
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    return occ, r, comp
+
+
+def _oracle_pair(r, comp, be, th, ph, kind):
+    kh, e, _ = dda.waves_for_orientation(be, th, ph)
+    ainv = dda.site_inverse_polarizability(comp, M, KD, kind)
+    A = dda.dense_matrix(r, KD, ainv)
+    E = np.stack([dda.incident_field(r, KD, kh, e[l]) for l in range(2)])
+    P = np.linalg.solve(A, E.reshape(2, -1).T).T.reshape(E.shape)
+    return E, P, ainv
+
+
+@pytest.mark.parametrize("kind_name", ["cm", "cm_rr"])
+def test_phi_efficiencies_match_oracle(ctx, kind_name):
+    import paper_1002_1505_amd as P
+
+    kind, akind = {"cm": (dda.ALPHA_CM, P.DDA_ALPHA_CM), "cm_rr": (dda.ALPHA_CM_RR, P.DDA_ALPHA_CM_RR)}[kind_name]
+    occ, r, comp = _target()
+    ctx.set_target(occ, M, KD, akind)
+    orients = [(0.3, 0.9, 0.1), (1.7, 2.2, 0.6), (4.0, 0.2, 2.9)]
+    phis = np.array([0.0, 0.8, 2.4, 5.5])
+    kh, e0 = [], []
+    for be, th, ph in orients:
+        k2, e2 = P.orientation_waves(be, th, ph)
+        kh += list(k2)
+        e0 += list(e2)
+    _, st, _ = ctx.solve(kh, e0, tol=1e-11, prec=P.DDA_SOLVE_FP64, want_p=False)
+    assert all(s["rel_resid"] <= 1e-11 for s in st)
+    coeffs = np.stack([P.phi_coefficients(be, th, ph, ph + phis) for be, th, ph in orients])
+    q = ctx.cross_sections_phi(coeffs)
+    assert q.shape == (3, len(phis), 2, 3)
+    for p, (be, th, ph) in enumerate(orients):
+        E, Pp, ainv = _oracle_pair(r, comp, be, th, ph, kind)
+        for m, dph in enumerate(phis):
+            c = O.phi_coefficients(be, th, ph, ph + dph)
+            want = O.cross_sections_at_phi(KD, E, Pp, ainv, c)
+            for l in range(2):
+                assert np.allclose(q[p, m, l], want[l], rtol=1e-8, atol=1e-12), (p, m, l, q[p, m, l], want[l])
+    # Phi offset zero reproduces the plain efficiencies of the solved pairs
+    qp = ctx.cross_sections(6).reshape(3, 2, 3)
+    assert np.allclose(q[:, 0], qp, rtol=1e-12, atol=1e-14)
+
+
+def test_phi_efficiencies_errors(ctx):
+    import paper_1002_1505_amd as P
+
+    occ, r, comp = _target()
+    ctx.set_target(occ, M, KD, P.DDA_ALPHA_LDR)
+    kh, e0 = P.orientation_waves(0.3, 0.9, 0.1)
+    ctx.solve(list(kh), list(e0), tol=1e-6, want_p=False)
+    c = np.ones((1, 1, 2, 2), complex)
+    with pytest.raises(P.DDAError):  # LDR: 1/alpha depends on the polarization
+        ctx.cross_sections_phi(c)
+    ctx.set_target(occ, M, KD, P.DDA_ALPHA_CM)
+    k2, e2 = P.orientation_waves(1.0, 0.5, 0.2)
+    ctx.solve([kh[0], k2[1]], [e0[0], e2[1]], tol=1e-6, want_p=False)
+    with pytest.raises(P.DDAError):  # two incidence directions in one pair
+        ctx.cross_sections_phi(c)
+    ctx.solve([kh[0], kh[1], kh[0]], [e0[0], e0[1], e0[0]], tol=1e-6, want_p=False)
+    with pytest.raises(P.DDAError):  # odd rhs count
+        ctx.cross_sections_phi(c)
+    ctx.solve(list(kh), list(e0), tol=1e-6, want_p=False)
+    assert ctx.cross_sections_phi(c).shape == (1, 1, 2, 3)
+
+
+def test_orientational_average_matches_oracle(ctx):
+    """Average over beta in [0, 2 pi), Theta in [0, pi] (Simpson, 5 values),
+    Phi in [0, 2 pi) from one solved pair per (beta, Theta)."""
+    import paper_1002_1505_amd as P
+
+    occ, r, comp = _target()
+    ctx.set_target(occ, M, KD, P.DDA_ALPHA_CM)
+    lims = np.deg2rad([0, 360, 0, 180, 0, 360])
+    counts = (2, 5, 3)
+    b, t, p, w = P.orientation_samples(lims, counts)
+    kh, e0, coeffs = [], [], []
+    for be in b:
+        for th in t:
+            k2, e2 = P.orientation_waves(be, th, p[0])
+            kh += list(k2)
+            e0 += list(e2)
+            coeffs.append(P.phi_coefficients(be, th, p[0], p))
+    _, st, _ = ctx.solve(kh, e0, tol=1e-11, prec=P.DDA_SOLVE_FP64, want_p=False)
+    q = ctx.cross_sections_phi(np.stack(coeffs)).reshape(len(b), len(t), len(p), 2, 3)
+    avg = O.orientational_average(q, w)  # (2 polarizations, 3)
+    # oracle: its own samples and weights, one LU of the orientation-independent A
+    ob, ot, op, ow = O.orientation_samples(lims, counts)
+    ainv = dda.site_inverse_polarizability(comp, M, KD, dda.ALPHA_CM)
+    A = dda.dense_matrix(r, KD, ainv)
+    ref = np.zeros((len(ob), len(ot), len(op), 2, 3))
+    for i, be in enumerate(ob):
+        for j, th in enumerate(ot):
+            k0, e_, _ = dda.waves_for_orientation(be, th, op[0])
+            E = np.stack([dda.incident_field(r, KD, k0, e_[l]) for l in range(2)])
+            Pp = np.linalg.solve(A, E.reshape(2, -1).T).T.reshape(E.shape)
+            for k, ph in enumerate(op):
+                ref[i, j, k] = O.cross_sections_at_phi(KD, E, Pp, ainv, O.phi_coefficients(be, th, op[0], ph))
+    want = O.orientational_average(ref, ow)
+    assert np.allclose(avg, want, rtol=1e-8), (avg, want)
