@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--x", type=float, default=10.0)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
+    ap.add_argument("--no-orient", action="store_true", help="skip the orientational-average leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three plain 256 MiB device copies (reference kernel for HBM byte counters)")
     ap.add_argument("--train-targets", type=int, default=16)
@@ -227,12 +228,65 @@ def main():
         },
         "setup_s": round(setup_s, 3),
     }
+    if not a.no_orient:
+        out["orient_avg"] = orientation_average(P, ctx, a, occ, kd, m)
     if not a.no_learned:
         out["learned"] = learned_vs_plain(P, ctx, a)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(occ, kd, m, stats[-1], a.cpu_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def orientation_average(P, ctx, a, occ, kd, m, counts=(2, 5, 8), reps=3):
+    """Orientationally averaged efficiencies of the bench sphere with the
+    Clausius-Mossotti polarizability (the Phi combination needs a
+    polarization-independent 1/alpha): NBETA x NTHETA (beta, Theta) pairs
+    solved in one batch of 2 NBETA NTHETA right-hand sides, NPHI rotations
+    each from dda_cross_sections_phi, weights from dda_orientation_samples."""
+    import torch
+
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_CM)
+    ctx.build_green_fft(P.DDA_FP32 | P.DDA_FP64)
+    lims = np.deg2rad([0, 360, 0, 180, 0, 360])
+    b, t, p, w = P.orientation_samples(lims, counts)
+    kh, e0, coeffs = [], [], []
+    for be in b:
+        for th in t:
+            k2, e2 = P.orientation_waves(be, th, p[0])
+            kh += list(k2)
+            e0 += list(e2)
+            coeffs.append(P.phi_coefficients(be, th, p[0], p))
+    coeffs = np.stack(coeffs)
+    nrhs = len(kh)
+    ctx.solve(kh, e0, tol=1e-5, want_p=False)  # warm-up (workspaces, graph)
+    torch.cuda.synchronize()
+    t_solve = t_phi = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, st, _ = ctx.solve(kh, e0, tol=1e-5, want_p=False)
+        t1 = time.perf_counter()
+        q = ctx.cross_sections_phi(coeffs)
+        t2 = time.perf_counter()
+        t_solve += t1 - t0
+        t_phi += t2 - t1
+    q = q.reshape(len(b), len(t), len(p), 2, 3)
+    qavg = np.tensordot(w, q, axes=([0, 1, 2], [0, 1, 2]))
+    norient = len(b) * len(t) * len(p)
+    conv = sum(1 for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
+    return {
+        "workload": f"{counts[0]} beta x {counts[1]} Theta (Simpson in cos Theta) x {counts[2]} Phi over the full "
+                    f"ranges, bench sphere with CM polarizability, {nrhs} rhs in one batch, tol 1e-5",
+        "orientations": norient,
+        "solves": nrhs,
+        "converged": f"{conv}/{nrhs}",
+        "orientations_per_s": round(norient * reps / (t_solve + t_phi), 2),
+        "solves_per_s": round(nrhs * reps / t_solve, 2),
+        "ms_solve_batch": round(1e3 * t_solve / reps, 3),
+        "ms_phi_combination": round(1e3 * t_phi / reps, 3),
+        "mean_iters": round(float(np.mean([s["iters"] for s in st])), 2),
+        "Q_avg": [[round(float(v), 6) for v in qq] for qq in qavg],
+    }
 
 
 def _aggregate_problem(synth, rng):

@@ -94,13 +94,13 @@ def test_phi_efficiencies_errors(ctx):
 
 def test_orientational_average_matches_oracle(ctx):
     """Average over beta in [0, 2 pi), Theta in [0, pi] (Simpson, 5 values),
-    Phi in [0, 2 pi) from one solved pair per (beta, Theta)."""
+    Phi in [0, 2 pi) (4 values) from one solved pair per (beta, Theta)."""
     import paper_1002_1505_amd as P
 
     occ, r, comp = _target()
     ctx.set_target(occ, M, KD, P.DDA_ALPHA_CM)
     lims = np.deg2rad([0, 360, 0, 180, 0, 360])
-    counts = (2, 5, 3)
+    counts = (2, 5, 4)
     b, t, p, w = P.orientation_samples(lims, counts)
     kh, e0, coeffs = [], [], []
     for be in b:
@@ -126,3 +126,7 @@ def test_orientational_average_matches_oracle(ctx):
                 ref[i, j, k] = O.cross_sections_at_phi(KD, E, Pp, ainv, O.phi_coefficients(be, th, op[0], ph))
     want = O.orientational_average(ref, ow)
     assert np.allclose(avg, want, rtol=1e-8), (avg, want)
+    # the second polarization is the first turned by 90 degrees about the
+    # incidence direction, a shift that maps the 4 Phi midpoints onto
+    # themselves: over full Phi both states average to the same efficiencies
+    assert np.allclose(avg[0], avg[1], rtol=1e-9)
