@@ -74,3 +74,31 @@ def mie_amplitudes(m: complex, x: float, theta):
         pi_next = ((2 * n + 1) * mu * pi_n - (n + 1) * pi_m1) / n
         pi_m1, pi_n = pi_n, pi_next
     return S1, S2
+
+
+def mie_asymmetry(m: complex, x: float):
+    """<cos theta> from the series Q_sca <cos theta> = (4/x^2) [sum n(n+2)/(n+1)
+    Re(a_n a_{n+1}^* + b_n b_{n+1}^*) + sum (2n+1)/(n(n+1)) Re(a_n b_n^*)]
+    (Bohren & Huffman, the asymmetry parameter of a sphere)."""
+    a, b = mie_coefficients(m, x)
+    n = np.arange(1, len(a) + 1)
+    t1 = np.sum((n[:-1] * (n[:-1] + 2) / (n[:-1] + 1)) * np.real(a[:-1] * np.conj(a[1:]) + b[:-1] * np.conj(b[1:])))
+    t2 = np.sum((2 * n + 1) / (n * (n + 1)) * np.real(a * np.conj(b)))
+    _, _, qsca = mie_efficiencies(m, x)
+    return float(4.0 / x ** 2 * (t1 + t2) / qsca)
+
+
+def mie_backscatter(m: complex, x: float):
+    """Q_bk = (dC_sca/dOmega at theta = pi) / (pi a^2) = |S_1(pi)|^2 / (pi x^2)."""
+    S1, _ = mie_amplitudes(m, x, np.pi)
+    return float(np.abs(S1[0]) ** 2 / (np.pi * x ** 2))
+
+
+def mie_phase_lag(m: complex, x: float):
+    """Q_pha = -(2/x^2) Im S(0): the forward amplitude's imaginary part (with
+    the scattered field exp(ikr)/(-ikr) S E_0 a dipole of polarizability alpha
+    has S(0) = -i k^3 alpha, and a dilute medium of such dipoles retards the
+    phase by 2 pi k Re(alpha) per unit target column, so
+    C_pha = -(2 pi / k^2) Im S(0))."""
+    S1, _ = mie_amplitudes(m, x, 0.0)
+    return float(-2.0 / x ** 2 * np.imag(S1[0]))

@@ -161,3 +161,55 @@ def scattering_quadrature(r, k, P, lab_axes, x, eta=0.5):
     Fperp = F - n_tf * np.sum(n_tf * F, axis=1)[:, None]
     dC = k ** 4 * np.sum(np.abs(Fperp) ** 2, axis=1)
     return float(np.sum(w * dC) / (np.pi * effective_radius(len(r)) ** 2))
+
+
+def quadrature_directions_tf(x, eta, lab_axes):
+    """Target-frame directions and solid-angle weights of the eta-controlled
+    scattering-direction set ("Averaging over Scattering Directions")."""
+    th, ph, w = scattering_directions(x, eta)
+    n_lab, _, _ = lab_direction_basis(th, ph)
+    return n_lab @ np.asarray(lab_axes, dtype=np.float64), w
+
+
+def differential_cross_section(r, k, P, n_tf):
+    """dC_sca/dOmega = k^4 |sum_j (P_j - n (n . P_j)) exp(-i k n . r_j)|^2 for
+    each direction n (|E_0| = 1)."""
+    phase = np.exp(-1j * k * (np.asarray(n_tf) @ np.asarray(r, dtype=np.float64).T))
+    F = phase @ np.asarray(P, dtype=np.complex128)
+    Fperp = F - n_tf * np.sum(n_tf * F, axis=1)[:, None]
+    return k ** 4 * np.sum(np.abs(Fperp) ** 2, axis=1)
+
+
+def scattering_moments(r, k, E, P, ainv, khat, n_tf, w):
+    """Efficiencies and moments of one solution, Q = C / (pi a_eff^2):
+
+    * Q_pha from C_pha = 2 pi k Re sum_j E_j^* . P_j (the phase-shift cross
+      section of Draine 1988: a dilute medium of targets retards the phase by
+      n_t C_pha per unit length; for a dipole alpha it is 2 pi k Re(alpha));
+    * Q_bk = (dC_sca/dOmega at n = -khat) / (pi a_eff^2);
+    * with the quadrature directions n_tf and weights w ("Averaging over
+      Scattering Directions"): Q_sca from the quadrature, Q_sca g = sum w dC n
+      / (pi a_eff^2) (target frame), <cos theta> = g . khat and
+      <cos^2 theta> = sum w dC (n . khat)^2 / C_sca, normalized by
+      C_sca = C_ext - C_abs (reading; the guide's printed worked example has
+      g(1) = Q_sca g(1) / Q_sca with that Q_sca);
+    * Q_pr = Q_ext khat - Q_sca g (section "Calculation of <cos theta>,
+      Radiative Force, and Radiation Torque").
+
+    Returns a dict of these values.
+    """
+    from .dda import cross_sections, effective_radius
+
+    n = len(r)
+    area = np.pi * effective_radius(n) ** 2
+    khat = np.asarray(khat, dtype=np.float64)
+    qext, qabs, qsca = cross_sections(k, E, P, ainv, n)
+    qpha = 2.0 * np.pi * k * np.sum(np.real(np.conj(E) * P)) / area
+    qbk = float(differential_cross_section(r, k, P, -khat[None, :])[0] / area)
+    dC = differential_cross_section(r, k, P, n_tf)
+    qsca_quad = float(np.sum(w * dC) / area)
+    qg = np.sum((w * dC)[:, None] * n_tf, axis=0) / area
+    cosm = float(np.dot(qg, khat) / qsca)
+    cos2 = float(np.sum(w * dC * (n_tf @ khat) ** 2) / area / qsca)
+    return {"Qext": qext, "Qabs": qabs, "Qsca": qsca, "Qpha": float(qpha), "Qbk": qbk,
+            "Qsca_quad": qsca_quad, "Qsca_g": qg, "cos": cosm, "cos2": cos2, "Qpr": qext * khat - qg}
