@@ -199,6 +199,29 @@ dda_status dda_inverse_polarizability(const dda_ctx* ctx, int32_t target, const 
  * Calculate?"; sums from Draine 1988).  FP64 reductions on the device. */
 dda_status dda_cross_sections(dda_ctx* ctx, int32_t nrhs, double* q);
 
+/* Phase-lag and backscattering efficiencies and the moments of the
+ * scattered intensity of the last solve (guide, sections "What Does It
+ * Calculate?", "Calculation of <cos theta>, Radiative Force, and Radiation
+ * Torque" and "Averaging over Scattering Directions").  n_tf, w: ndir
+ * target-frame scattering directions (3 doubles each) and solid-angle
+ * weights, e.g. from dda_scattering_quadrature.  out: nrhs x DDA_NMOMENTS
+ * doubles, per rhs
+ *   [0] Q_pha = 2 pi k Re(sum_j E_j^* . P_j) / (pi a_eff^2) (the phase-shift
+ *       cross section of Draine 1988 over pi a_eff^2);
+ *   [1] Q_bk = k^4 |sum_j (P_j - n (n . P_j)) exp(-i k n . r_j)|^2 / (pi a_eff^2)
+ *       at n = -khat (differential backscattering cross section per sr);
+ *   [2] Q_sca from the quadrature, sum_d w_d dC/dOmega(n_d) / (pi a_eff^2);
+ *   [3..5] Q_sca g = sum_d w_d dC/dOmega n_d / (pi a_eff^2), target frame;
+ *   [6] <cos theta> = g . khat and [7] <cos^2 theta>, both normalized by
+ *       Q_sca = Q_ext - Q_abs;
+ *   [8..10] Q_pr = Q_ext khat - Q_sca g, target frame.
+ * FP64 device sums over the sites (the amplitude kernel), weighted sums over
+ * the directions on the host.  DDA_ERR_STATE before a solve,
+ * DDA_ERR_INVALID_ARG for nrhs other than the last solve's or ndir < 1. */
+enum { DDA_NMOMENTS = 11 };
+dda_status dda_scattering_moments(dda_ctx* ctx, int32_t nrhs, int32_t ndir, const double* n_tf, const double* w,
+                                  double* out);
+
 /* Efficiencies at other target rotations Phi about the incidence direction
  * without new solves (guide, section "Scattering by Finite Targets", the
  * IORTH remark: the solution for another Phi is a linear combination of the
@@ -254,6 +277,20 @@ dda_status dda_lab_frame(double beta, double theta, double phi, const double* a1
  * receive the waves with target = `target`. */
 dda_status dda_orientation_waves(double beta, double theta, double phi, const double* a1, const double* a2,
                                  const double* e01, int32_t target, dda_wave* out);
+
+/* The scattering directions and solid-angle weights that average over
+ * directions (guide, section "Averaging over Scattering Directions"):
+ * theta_j at equal steps of s(theta) = theta + theta / (theta + theta0),
+ * theta0 = 2 pi / (1 + x), from 0 to pi, N_theta from eta (rounded to the
+ * nearest integer, at least 3); one phi at theta = 0 and pi, else
+ * N_phi(j) = max{3, nint[4 pi sin(theta_j) / (theta_{j+1} - theta_{j-1})]}
+ * values phi = 2 pi k / N_phi(j), k = 0.., about x_LF from y_LF; weights
+ * Omega_jk of the guide's formulas.  lab_axes: 9 doubles (dda_lab_frame).
+ * ndir receives the number of directions; with n_tf or w NULL only the count
+ * is returned, else n_tf (ndir x 3, target frame) and w (ndir) are filled when
+ * cap >= ndir (DDA_ERR_INVALID_ARG otherwise).  Host arithmetic. */
+dda_status dda_scattering_quadrature(double x, double eta, const double* lab_axes, int32_t cap, int32_t* ndir,
+                                     double* n_tf, double* w);
 
 /* Orientation samples and weights for orientational averages (guide,
  * sections "Sampling in Theta, Phi, and beta" and "Orientational

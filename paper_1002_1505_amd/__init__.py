@@ -194,6 +194,19 @@ class Context:
         _check(self.h, self.lib.dda_cross_sections_phi(self.h, int(npairs), int(ncomb), _dptr(cc), _dptr(q)))
         return q.reshape(npairs, ncomb, 2, 3)
 
+    MOMENT_KEYS = ("Qpha", "Qbk", "Qsca_quad", "Qsca_g", "cos", "cos2", "Qpr")
+
+    def scattering_moments(self, nrhs: int, n_tf, w):
+        """Per rhs dict of Q_pha, Q_bk, quadrature Q_sca, Q_sca g (3), <cos>,
+        <cos^2>, Q_pr (3) (dda_scattering_moments)."""
+        n_tf = np.ascontiguousarray(n_tf, dtype=np.float64).reshape(-1, 3)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+        out = np.zeros(nrhs * 11)
+        _check(self.h, self.lib.dda_scattering_moments(self.h, int(nrhs), len(w), _dptr(n_tf), _dptr(w), _dptr(out)))
+        out = out.reshape(nrhs, 11)
+        return [dict(Qpha=o[0], Qbk=o[1], Qsca_quad=o[2], Qsca_g=o[3:6].copy(), cos=o[6], cos2=o[7],
+                     Qpr=o[8:11].copy()) for o in out]
+
     def amplitudes(self, nrhs: int, n_tf, e_tf):
         n_tf = np.ascontiguousarray(n_tf, dtype=np.float64).reshape(-1, 3)
         e_tf = np.ascontiguousarray(e_tf, dtype=np.float64).reshape(-1, 6)
@@ -262,6 +275,21 @@ def orientation_waves(beta, theta, phi, e01=None, a1=None, a2=None, target=0):
     kh = np.array([[out[w].khat[i] for i in range(3)] for w in range(2)])
     e0 = np.array([[out[w].e0[2 * i] + 1j * out[w].e0[2 * i + 1] for i in range(3)] for w in range(2)])
     return kh, e0
+
+
+def scattering_quadrature(x, eta, lab_axes):
+    """(n_tf (ndir, 3), w (ndir,)) of dda_scattering_quadrature."""
+    lib = L.load()
+    La = np.ascontiguousarray(lab_axes, dtype=np.float64).reshape(-1)
+    nd = C.c_int32()
+    st = lib.dda_scattering_quadrature(float(x), float(eta), _dptr(La), 0, C.byref(nd), None, None)
+    if st < 0:
+        raise DDAError(st, "dda_scattering_quadrature")
+    n_tf, w = np.zeros(3 * nd.value), np.zeros(nd.value)
+    st = lib.dda_scattering_quadrature(float(x), float(eta), _dptr(La), nd.value, C.byref(nd), _dptr(n_tf), _dptr(w))
+    if st < 0:
+        raise DDAError(st, "dda_scattering_quadrature")
+    return n_tf.reshape(-1, 3), w
 
 
 def orientation_samples(lims, counts):

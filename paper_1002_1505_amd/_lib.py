@@ -87,6 +87,8 @@ SIGNATURES = {
     "dda_inverse_polarizability": (C.c_int32, [P, C.c_int32, C.POINTER(dda_wave), D]),
     "dda_cross_sections": (C.c_int32, [P, C.c_int32, D]),
     "dda_cross_sections_phi": (C.c_int32, [P, C.c_int32, C.c_int32, D, D]),
+    "dda_scattering_moments": (C.c_int32, [P, C.c_int32, C.c_int32, D, D, D]),
+    "dda_scattering_quadrature": (C.c_int32, [C.c_double, C.c_double, D, C.c_int32, C.POINTER(C.c_int32), D, D]),
     "dda_orientation_samples": (C.c_int32, [D, C.POINTER(C.c_int32), D, D, D, D]),
     "dda_phi_coefficients": (C.c_int32, [C.c_double, C.c_double, C.c_double, C.c_int32, D, D, D, D, D]),
     "dda_amplitudes": (C.c_int32, [P, C.c_int32, C.c_int32, D, D, D]),

@@ -1394,16 +1394,16 @@ dda_status dda_cross_sections(dda_ctx* c, int32_t nrhs, double* q) {
     for (auto& gp : c->groups) {
         Group& g = *gp;
         Target& t = *c->tg[g.tgt];
-        HCHK(c, out.ensure(2 * g.nr * sizeof(double)));
+        HCHK(c, out.ensure(3 * g.nr * sizeof(double)));
         HCHK(c, launch_xsec(t.geo(), g.nr, g.b64.as<Cx<double>>(), g.x64.as<Cx<double>>(), g.ainv64.as<Cx<double>>(),
                             t.kd * t.kd * t.kd, g.partials.as<double>(), out.as<double>(), st));
-        std::vector<double> h(2 * g.nr);
+        std::vector<double> h(3 * g.nr);
         HCHK(c, hipMemcpyAsync(h.data(), out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         HCHK(c, hipStreamSynchronize(st));
         const double area = PI * t.aeff * t.aeff;
         for (int s = 0; s < g.nr; ++s) {
             const int i = g.idx[s];
-            const double qext = 4 * PI * t.kd * h[2 * s] / area, qabs = 4 * PI * t.kd * h[2 * s + 1] / area;
+            const double qext = 4 * PI * t.kd * h[3 * s] / area, qabs = 4 * PI * t.kd * h[3 * s + 1] / area;
             q[3 * i] = qext;
             q[3 * i + 1] = qabs;
             q[3 * i + 2] = qext - qabs;
@@ -1481,6 +1481,81 @@ dda_status dda_cross_sections_phi(dda_ctx* c, int32_t npairs, int32_t ncomb, con
                     o[1] = scale * ab.real();
                     o[2] = o[0] - o[1];
                 }
+        }
+    }
+    return DDA_OK;
+}
+
+dda_status dda_scattering_moments(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* n_tf, const double* w,
+                                  double* out) {
+    SCHK(check_ctx(c));
+    if (!c->have_solution) return fail(c, DDA_ERR_STATE, "scattering_moments before a solve");
+    if (nrhs != c->last_nrhs || ndir < 1 || !n_tf || !w || !out)
+        return fail(c, DDA_ERR_INVALID_ARG, "scattering_moments: bad arguments (nrhs must match the last solve)");
+    hipStream_t st = c->stream;
+    DevMem dn, dF, dP, dx, db;
+    HCHK(c, dn.ensure((size_t)ndir * 3 * sizeof(double)));
+    HCHK(c, hipMemcpyAsync(dn.p, n_tf, (size_t)ndir * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        const Target& t = *c->tg[g.tgt];
+        const Geo geo = t.geo();
+        const double k = t.kd, k4 = k * k * k * k, area = PI * t.aeff * t.aeff;
+        // Q_ext, Q_abs and Re sum E^* . P
+        HCHK(c, dx.ensure(3 * g.nr * sizeof(double)));
+        HCHK(c, launch_xsec(geo, g.nr, g.b64.as<Cx<double>>(), g.x64.as<Cx<double>>(), g.ainv64.as<Cx<double>>(),
+                            k * k * k, g.partials.as<double>(), dx.as<double>(), st));
+        // F(n) = sum_j P_j exp(-i k n . r_j) at the quadrature directions
+        HCHK(c, dF.ensure((size_t)g.nr * ndir * 3 * sizeof(Cx<double>)));
+        HCHK(c, dP.ensure((size_t)ampl_chunks(ndir, g.nr, t.N) * g.nr * ndir * 6 * sizeof(double)));
+        HCHK(c, launch_ampl(geo, t.origin, k, g.nr, g.x64.as<Cx<double>>(), ndir, dn.as<double>(), dF.as<Cx<double>>(),
+                            dP.as<double>(), st));
+        std::vector<double> hx(3 * g.nr);
+        std::vector<cd> F((size_t)g.nr * ndir * 3);
+        HCHK(c, hipMemcpyAsync(hx.data(), dx.p, hx.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HCHK(c, hipMemcpyAsync(F.data(), dF.p, F.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
+        // the backscattering direction -khat of each rhs
+        std::vector<double> nb(3 * g.nr);
+        for (int s2 = 0; s2 < g.nr; ++s2)
+            for (int i = 0; i < 3; ++i) nb[3 * s2 + i] = -c->last_waves[g.idx[s2]].khat[i];
+        HCHK(c, db.ensure(nb.size() * sizeof(double)));
+        HCHK(c, hipMemcpyAsync(db.p, nb.data(), nb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        std::vector<cd> Fb(3 * g.nr);
+        DevMem dFb, dPb;
+        HCHK(c, dFb.ensure(3 * sizeof(Cx<double>) * g.nr));
+        HCHK(c, dPb.ensure((size_t)ampl_chunks(1, 1, t.N) * 6 * sizeof(double)));
+        for (int s2 = 0; s2 < g.nr; ++s2)
+            HCHK(c, launch_ampl(geo, t.origin, k, 1, g.x64.as<Cx<double>>() + (size_t)s2 * 3 * t.Npad, 1,
+                                db.as<double>() + 3 * s2, dFb.as<Cx<double>>() + 3 * s2, dPb.as<double>(), st));
+        HCHK(c, hipMemcpyAsync(Fb.data(), dFb.p, Fb.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
+        HCHK(c, hipStreamSynchronize(st));
+        auto dcs = [&](const cd* f, const double* n) {  // k^4 |F - n (n . F)|^2
+            const cd nf = n[0] * f[0] + n[1] * f[1] + n[2] * f[2];
+            double a = 0;
+            for (int i = 0; i < 3; ++i) a += std::norm(f[i] - n[i] * nf);
+            return k4 * a;
+        };
+        for (int s2 = 0; s2 < g.nr; ++s2) {
+            const double* kh = c->last_waves[g.idx[s2]].khat;
+            const double qext = 4 * PI * k * hx[3 * s2] / area, qabs = 4 * PI * k * hx[3 * s2 + 1] / area;
+            const double qsca = qext - qabs;
+            double csum = 0, gv[3] = {0, 0, 0}, c2 = 0;
+            for (int d = 0; d < ndir; ++d) {
+                const double* n = n_tf + 3 * d;
+                const double v = w[d] * dcs(&F[((size_t)s2 * ndir + d) * 3], n);
+                const double ct = n[0] * kh[0] + n[1] * kh[1] + n[2] * kh[2];
+                csum += v;
+                for (int i = 0; i < 3; ++i) gv[i] += v * n[i];
+                c2 += v * ct * ct;
+            }
+            double* o = out + (size_t)g.idx[s2] * DDA_NMOMENTS;
+            o[0] = 2 * PI * k * hx[3 * s2 + 2] / area;  // Q_pha
+            o[1] = dcs(&Fb[3 * s2], nb.data() + 3 * s2) / area;  // Q_bk
+            o[2] = csum / area;  // Q_sca by the quadrature
+            for (int i = 0; i < 3; ++i) o[3 + i] = gv[i] / area;  // Q_sca g
+            o[6] = (gv[0] * kh[0] + gv[1] * kh[1] + gv[2] * kh[2]) / area / qsca;
+            o[7] = c2 / area / qsca;
+            for (int i = 0; i < 3; ++i) o[8 + i] = qext * kh[i] - o[3 + i];  // Q_pr
         }
     }
     return DDA_OK;
@@ -1668,6 +1743,52 @@ dda_status dda_phi_coefficients(double beta, double theta, double phi_ref, int32
                 coeffs[((size_t)k * 2 + l) * 4 + 2 * a] = v.real();
                 coeffs[((size_t)k * 2 + l) * 4 + 2 * a + 1] = v.imag();
             }
+    }
+    return DDA_OK;
+}
+
+dda_status dda_scattering_quadrature(double x, double eta, const double* L, int32_t cap, int32_t* ndir, double* n_tf,
+                                     double* w) {
+    if (!(x > 0) || !(eta > 0) || !L || !ndir) return DDA_ERR_INVALID_ARG;
+    // theta_j at equal steps of s(theta) = theta + theta / (theta + theta0)
+    const double th0 = 2 * PI / (1 + x);
+    const double nr = 1 + 2 * (3 + x) / eta * (1 + 1 / (PI + th0)) / (1 + th0 / ((PI + th0) * (PI + th0)));
+    const double nrc = std::min(nr, 1.0e6);
+    const int nth = std::max(3, (int)std::lround(nrc));
+    std::vector<double> th(nth);
+    for (int j = 0; j < nth; ++j) {
+        const double sj = j * PI / (nth - 1) * (1 + 1 / (PI + th0));
+        th[j] = ((sj - 1 - th0) + std::sqrt((1 + th0 - sj) * (1 + th0 - sj) + 4 * th0 * sj)) / 2;
+    }
+    th[0] = 0;
+    th[nth - 1] = PI;
+    std::vector<int> nph(nth);
+    long long tot = 0;
+    for (int j = 0; j < nth; ++j) {
+        nph[j] = (j == 0 || j == nth - 1)
+                     ? 1
+                     : std::max(3, (int)std::lround(4 * PI * std::sin(th[j]) / (th[j + 1] - th[j - 1])));
+        tot += nph[j];
+    }
+    if (tot > (1LL << 30)) return DDA_ERR_INVALID_ARG;
+    *ndir = (int32_t)tot;
+    if (!n_tf || !w) return DDA_OK;  // size query
+    if (cap < tot) return DDA_ERR_INVALID_ARG;
+    long long d = 0;
+    for (int j = 0; j < nth; ++j) {
+        double wj;
+        if (j == 0)
+            wj = 2 * PI / nph[j] * (1 - (std::cos(th[0]) + std::cos(th[1])) / 2);
+        else if (j == nth - 1)
+            wj = 2 * PI / nph[j] * ((std::cos(th[nth - 2]) + std::cos(th[nth - 1])) / 2 + 1);
+        else
+            wj = PI / nph[j] * (std::cos(th[j - 1]) - std::cos(th[j + 1]));
+        for (int kk = 0; kk < nph[j]; ++kk, ++d) {
+            const double ph = 2 * PI * kk / nph[j];
+            const double nl[3] = {std::cos(th[j]), std::sin(th[j]) * std::cos(ph), std::sin(th[j]) * std::sin(ph)};
+            for (int i = 0; i < 3; ++i) n_tf[3 * d + i] = nl[0] * L[i] + nl[1] * L[3 + i] + nl[2] * L[6 + i];
+            w[d] = wj;
+        }
     }
     return DDA_OK;
 }

@@ -196,7 +196,8 @@ hipError_t launch_from_abi(const Geo& g, int nrhs, const Cx<double>* in, Cx<T>* 
 template <class T>
 hipError_t launch_to_abi(const Geo& g, int nrhs, const Cx<T>* in, Cx<double>* out, hipStream_t st);
 
-// Cross-section sums: out[rhs] = {sum Im(E^* . P), sum |P|^2 * (-Im ainv_c - (2/3) k^3)}.
+// Cross-section sums: out[rhs] = {sum Im(E^* . P), sum |P|^2 * (-Im ainv_c - (2/3) k^3),
+// sum Re(E^* . P)}.
 hipError_t launch_xsec(const Geo& g, int nrhs, const Cx<double>* E, const Cx<double>* P, const Cx<double>* ainv,
                        double k3, double* partials, double* out, hipStream_t st);
 // Pair sums of the cross sections of combined solutions: for each pair of

@@ -499,6 +499,7 @@ __global__ void __launch_bounds__(VT) k_xsec_part(Geo g, const Cx<double>* __res
             const size_t i = ((size_t)rhs * 3 + c) * g.Npad + j;
             const Cx<double> e = E[i], p = P[i];
             acc[0].x += e.re * p.im - e.im * p.re;  // Im(conj(e) p)
+            acc[0].y += e.re * p.re + e.im * p.im;  // Re(conj(e) p)
             p2 += p.re * p.re + p.im * p.im;
         }
         const Cx<double> ai = ainv[(size_t)rhs * g.ncomp + g.site_comp[j]];
@@ -512,8 +513,9 @@ __global__ void k_xsec_final(int nblk, const double* __restrict__ partials, doub
     const double2 a = reduce_slot(partials, blockIdx.x, 0, nblk, sh);
     const double2 b = reduce_slot(partials, blockIdx.x, 1, nblk, sh);
     if (threadIdx.x == 0) {
-        out[2 * blockIdx.x] = a.x;
-        out[2 * blockIdx.x + 1] = b.x;
+        out[3 * blockIdx.x] = a.x;
+        out[3 * blockIdx.x + 1] = b.x;
+        out[3 * blockIdx.x + 2] = a.y;
     }
 }
 

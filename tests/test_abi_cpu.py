@@ -103,3 +103,26 @@ def test_orientation_helpers_without_gpu():
             assert np.allclose(c[k], O.phi_coefficients(be, th, p0, ph), atol=1e-13)
     with pytest.raises(P.DDAError):
         P.orientation_samples(lims, (0, 1, 1))
+
+
+def test_scattering_quadrature_without_gpu():
+    """dda_scattering_quadrature is host arithmetic: the guide's worked
+    example (x = 6.187304, ETASCA = 0.5) uses NAVG = 2292 directions, and the
+    directions and weights equal the oracle's."""
+    import numpy as np
+
+    import paper_1002_1505_amd as P
+    from oracle import dda, scatter
+
+    L = dda.lab_axes_in_target_frame(0.0, 0.0, 0.0)
+    n, w = P.scattering_quadrature(6.187304, 0.5, L)
+    assert len(w) == 2292
+    for x, eta, ang in [(6.187304, 0.5, (0, 0, 0)), (1.0, 0.5, (0.3, 1.1, 2.0)), (10.0, 1.0, (2.0, 0.4, 0.7)),
+                        (0.2, 0.25, (1.0, 2.0, 3.0))]:
+        L = dda.lab_axes_in_target_frame(*ang)
+        n, w = P.scattering_quadrature(x, eta, L)
+        no, wo = scatter.quadrature_directions_tf(x, eta, L)
+        assert n.shape == no.shape and np.allclose(n, no, atol=1e-13) and np.allclose(w, wo, rtol=1e-13)
+        assert abs(w.sum() - 4 * np.pi) < 0.05
+    with pytest.raises(P.DDAError):
+        P.scattering_quadrature(-1.0, 0.5, L)

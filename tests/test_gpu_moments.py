@@ -1,0 +1,66 @@
+"""Phase-lag and backscattering efficiencies and the scattered-intensity
+moments on the GPU (dda_scattering_moments) against the oracle's values
+from its own dense solutions, on the same direction set."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dda, scatter
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1002_1505_amd as P
+
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("shape,diam,m,kd,orient", [
+    ((10, 9, 8), (9.5, 7.4, 6.1), 1.6 + 0.15j, 0.45, (0.3, 0.9, 0.1)),
+    ((12, 12, 12), (11.5, 11.5, 11.5), 1.33 + 0.01j, 0.3, (1.2, 2.0, 0.4)),
+])
+def test_moments_match_oracle(ctx, shape, diam, m, kd, orient):
+    import paper_1002_1505_amd as P
+
+    occ = synth.ellipsoid_occupancy(shape, diam)
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    kh, e0 = P.orientation_waves(*orient)
+    _, st, _ = ctx.solve(list(kh), list(e0), tol=1e-11, prec=P.DDA_SOLVE_FP64, want_p=False)
+    assert all(s["rel_resid"] <= 1e-11 for s in st)
+    L = P.lab_frame(*orient)
+    x = kd * dda.effective_radius(len(r))
+    n_tf, w = P.scattering_quadrature(x, 0.5, L)
+    got = ctx.scattering_moments(2, n_tf, w)
+    kho, eo, Lo = dda.waves_for_orientation(*orient)
+    no, wo = scatter.quadrature_directions_tf(x, 0.5, Lo)
+    for l in range(2):
+        ainv = dda.site_inverse_polarizability(comp, [m], kd, dda.ALPHA_LDR, kho, eo[l])
+        E = dda.incident_field(r, kd, kho, eo[l])
+        Pw = dda.solve_dense(r, kd, ainv, E)
+        want = scatter.scattering_moments(r, kd, E, Pw, ainv, kho, no, wo)
+        for key in ("Qpha", "Qbk", "Qsca_quad", "cos", "cos2"):
+            assert abs(got[l][key] - want[key]) <= 1e-8 * abs(want[key]) + 1e-13, (l, key, got[l][key], want[key])
+        for key in ("Qsca_g", "Qpr"):
+            scale = np.linalg.norm(want[key])
+            assert np.linalg.norm(got[l][key] - want[key]) <= 1e-8 * scale + 1e-13, (l, key, got[l][key], want[key])
+        # the efficiencies of dda_cross_sections are consistent with Q_pr
+        q = ctx.cross_sections(2)[l]
+        assert np.allclose(got[l]["Qpr"] + got[l]["Qsca_g"], q[0] * kho, rtol=1e-10, atol=1e-13)
+
+
+def test_moments_errors(ctx):
+    import paper_1002_1505_amd as P
+
+    occ = synth.sphere_occupancy(8)
+    ctx.set_target(occ, [1.5 + 0.1j], 0.3)
+    kh, e0 = P.orientation_waves(0.0, 0.0, 0.0)
+    ctx.solve(list(kh), list(e0), tol=1e-6, want_p=False)
+    n, w = P.scattering_quadrature(1.0, 1.0, P.lab_frame(0.0, 0.0, 0.0))
+    with pytest.raises(P.DDAError):  # rhs count differs from the last solve
+        ctx.scattering_moments(3, n, w)
+    assert len(ctx.scattering_moments(2, n, w)) == 2
