@@ -152,6 +152,14 @@ def main():
     torch.cuda.synchronize()
     dt64 = time.perf_counter() - t1
     q_rel = float(np.max(np.abs(q - q64) / np.abs(q64)))
+    # Q_pha, Q_bk and the scattered-intensity moments of the FP64 solution
+    # over the eta = 0.5 direction set (outside the timed region)
+    n_q, w_q = P.scattering_quadrature(a.x, 0.5, L)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    mom = ctx.scattering_moments(2, n_q, w_q)
+    torch.cuda.synchronize()
+    ms_mom = 1e3 * (time.perf_counter() - t2)
     # per-pass matvec roofline (FP32, the solve's launch shapes, both rhs)
     ms, by = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP32, reps=20)
     sh = ctx.get_shape(0, P.DDA_FP32)
@@ -225,6 +233,14 @@ def main():
             "iters": [s["iters"] for s in st64],
             "rel_resid": [s["rel_resid"] for s in st64],
             "max_rel_diff_Q_fp32refine_vs_fp64": q_rel,
+        },
+        "moments": {
+            "ndir": int(len(w_q)),
+            "eta": 0.5,
+            "ms": round(ms_mom, 3),
+            "per_pol": [{"Qpha": round(float(mm["Qpha"]), 6), "Qbk": round(float(mm["Qbk"]), 6),
+                         "Qsca_quad": round(float(mm["Qsca_quad"]), 6), "cos": round(float(mm["cos"]), 6),
+                         "cos2": round(float(mm["cos2"]), 6)} for mm in mom],
         },
         "setup_s": round(setup_s, 3),
     }
