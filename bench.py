@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--x", type=float, default=10.0)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
     ap.add_argument("--no-orient", action="store_true", help="skip the orientational-average leg")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 128^3 sphere leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three plain 256 MiB device copies (reference kernel for HBM byte counters)")
     ap.add_argument("--train-targets", type=int, default=16)
@@ -246,12 +247,55 @@ def main():
     }
     if not a.no_orient:
         out["orient_avg"] = orientation_average(P, ctx, a, occ, kd, m)
+    if not a.no_c4:
+        out["c4"] = large_sphere(P, ctx, synth)
     if not a.no_learned:
         out["learned"] = learned_vs_plain(P, ctx, a)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(occ, kd, m, stats[-1], a.cpu_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def large_sphere(P, ctx, synth, n=128, x=20.0, m=1.33 + 0.01j, reps=2):
+    """The 128^3 sphere (N = 1,099,136, grid 256^3, x = 20, LDR): 2 rhs
+    solved to 1e-5 with FP32 matvecs and FP64 refinement, and the FP32
+    matvec passes with their algorithmic bytes."""
+    import torch
+
+    occ = synth.sphere_occupancy(n)
+    N = int(occ.sum())
+    kd = x / ((3.0 * N / (4.0 * np.pi)) ** (1.0 / 3.0))
+    t0 = time.perf_counter()
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    ctx.build_green_fft(P.DDA_FP32 | P.DDA_FP64)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    kh, e0 = P.orientation_waves(0.0, 0.0, 0.0)
+    ctx.solve(list(kh), list(e0), tol=1e-5, want_p=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st, _ = ctx.solve(list(kh), list(e0), tol=1e-5, want_p=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    conv = sum(1 for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
+    ms, by = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP32, reps=5)
+    q = ctx.cross_sections(2)
+    return {
+        "workload": f"sphere in {n}^3 box (N={N}), FFT grid {2 * n}^3, m=1.33+0.01i, x={x}, LDR, "
+                    "1 orientation x 2 polarizations, FP32 matvec + FP64 refinement, tol 1e-5",
+        "solves_per_s": round(2 * reps / dt, 3),
+        "converged": f"{conv}/2",
+        "iters": [s["iters"] for s in st],
+        "setup_s": round(setup, 3),
+        "matvec_pass_ms": [round(float(v), 4) for v in ms],
+        "matvec_ms": round(float(ms.sum()), 4),
+        "matvec_GBs": round(float(by.sum() / (ms.sum() * 1e-3) / 1e9), 1),
+        "matvec_frac_hbm": round(float(by.sum() / (ms.sum() * 1e-3) / 1e9) / HBM_PEAK_GBS, 4),
+        "shape": ctx.get_shape(0, P.DDA_FP32),
+        "Q": [list(map(float, qq)) for qq in q],
+    }
 
 
 def orientation_average(P, ctx, a, occ, kd, m, counts=(2, 5, 8), reps=3):

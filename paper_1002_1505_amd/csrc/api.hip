@@ -263,9 +263,12 @@ MvShape default_shape(const Target& t, int tx_pref) {
     s.zrb = 0;
     if (!matvec_shape_ok<T>(g, t.plans, s)) s.fused = 0;
     if (ct_supported(g.n1, g.n2, g.n3)) {
-        // specialised kernels; z tile 16 columns unless only another fits
+        // specialised kernels; z tile 16 columns (8 from n = 128 on, where
+        // the generic specialised z pass is faster with narrower tiles)
+        // unless only another fits
         MvShape c = s;
-        for (int txc : {16, 32, 8}) {
+        const int txo[3] = {g.n1 >= 128 ? 8 : 16, g.n1 >= 128 ? 16 : 32, g.n1 >= 128 ? 32 : 8};
+        for (int txc : txo) {
             c.tx = txc;
             c.ct = ct_available<T>(g.n1, txc);
             if ((c.ct & 2) && matvec_shape_ok<T>(g, t.plans, c)) break;
