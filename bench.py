@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
     ap.add_argument("--no-orient", action="store_true", help="skip the orientational-average leg")
     ap.add_argument("--no-c4", action="store_true", help="skip the 128^3 sphere leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the mixed-box batch leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three plain 256 MiB device copies (reference kernel for HBM byte counters)")
     ap.add_argument("--train-targets", type=int, default=16)
@@ -247,6 +248,8 @@ def main():
     }
     if not a.no_orient:
         out["orient_avg"] = orientation_average(P, ctx, a, occ, kd, m)
+    if not a.no_c3:
+        out["c3"] = mixed_batch(P, ctx, synth)
     if not a.no_c4:
         out["c4"] = large_sphere(P, ctx, synth)
     if not a.no_learned:
@@ -255,6 +258,69 @@ def main():
         out["cpu_baseline"] = cpu_baseline(occ, kd, m, stats[-1], a.cpu_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def mixed_batch(P, ctx, synth, boxes=(32, 32, 32, 48, 48, 48, 64, 64), n_orient=8, reps=2, max_iter=5000):
+    """Seeded random ellipsoids in 32^3, 48^3 and 64^3 boxes (axis ratios
+    1 : U[1,2] : U[1,3], random rotation), Re m ~ U[1.2, 1.8], Im m ~
+    log-U[0.001, 0.3], |m| k d ~ U[0.3, 0.8], LDR; n_orient uniform random
+    orientations x 2 polarizations per target, all in one solve call (one
+    graph over every target's group) and, for comparison, one call per
+    target."""
+    import torch
+
+    rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 3)
+    tgt = []
+    for n in boxes:
+        occ = synth.random_ellipsoid(n, rng)[0]
+        m = complex(rng.uniform(1.2, 1.8), np.exp(rng.uniform(np.log(1e-3), np.log(0.3))))
+        kd = rng.uniform(0.3, 0.8) / abs(m)
+        tgt.append((occ, m, kd))
+    for t, (occ, m, kd) in enumerate(tgt):
+        if t == 0:
+            ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+        else:
+            ctx.add_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    ctx.build_green_fft(P.DDA_FP32 | P.DDA_FP64)
+    kh, e0, tg = [], [], []
+    for t in range(len(tgt)):
+        for b, th, ph in synth.uniform_orientations(n_orient, rng):
+            k2, e2 = P.orientation_waves(b, th, ph)
+            kh += list(k2)
+            e0 += list(e2)
+            tg += [t, t]
+    nrhs = len(kh)
+    ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=max_iter)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st, _ = ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=max_iter)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    sel = [[i for i in range(nrhs) if tg[i] == t] for t in range(len(tgt))]
+    for t in range(len(tgt)):
+        ctx.solve([kh[i] for i in sel[t]], [e0[i] for i in sel[t]], targets=[t] * len(sel[t]), tol=1e-5, want_p=False,
+                  max_iter=max_iter)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        for t in range(len(tgt)):
+            ctx.solve([kh[i] for i in sel[t]], [e0[i] for i in sel[t]], targets=[t] * len(sel[t]), tol=1e-5,
+                      want_p=False, max_iter=max_iter)
+    torch.cuda.synchronize()
+    dt_sep = (time.perf_counter() - t1) / reps
+    conv = sum(1 for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
+    return {
+        "workload": f"{len(tgt)} random ellipsoids in boxes {list(boxes)}, {n_orient} orientations x 2 "
+                    "polarizations each, LDR, FP32 matvec + FP64 refinement, tol 1e-5",
+        "solves": nrhs,
+        "converged": f"{conv}/{nrhs}",
+        "solves_per_s_one_call": round(nrhs / dt, 2),
+        "solves_per_s_per_target_calls": round(nrhs / dt_sep, 2),
+        "mean_iters_by_target": [round(float(np.mean([st[i]["iters"] for i in sel[t]])), 1) for t in range(len(tgt))],
+        "m_kd": [[round(m.real, 3), round(m.imag, 4), round(kd, 4)] for _, m, kd in tgt],
+        "sites": [int(o.sum()) for o, _, _ in tgt],
+    }
 
 
 def large_sphere(P, ctx, synth, n=128, x=20.0, m=1.33 + 0.01j, reps=2):

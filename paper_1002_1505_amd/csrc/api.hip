@@ -176,9 +176,15 @@ struct dda_ctx {
     std::vector<int> rhs_group, rhs_slot;
     bool have_solution = false;
     // graph cache
-    hipGraphExec_t gexec = nullptr;
+    // captured inner iterations, one per set of groups that still iterate
+    // (a group whose rhs have all stopped is left out of the replays)
+    std::map<std::vector<char>, hipGraphExec_t> gexec;
     long long gkey_gen = -1;
     int gkey_prec = 0, gkey_k = 0;
+    void drop_graphs() {
+        for (auto& kv : gexec) (void)hipGraphExecDestroy(kv.second);
+        gexec.clear();
+    }
     long long ws_gen = 0;
     dda_nn* nn = nullptr;  // learned-guess model (not owned)
     std::vector<dda_wave> last_waves;
@@ -604,9 +610,10 @@ dda_status ensure_group(dda_ctx* c, Group& g, const Target& t, int prec, bool* r
 
 // One BiCGstab iteration for every group (precision T), enqueued on st.
 template <class T>
-hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st, int k) {
-    for (auto& gp : c->groups) {
-        Group& g = *gp;
+hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st, int k, const std::vector<char>& live) {
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        if (!live[gi]) continue;
+        Group& g = *c->groups[gi];
         const Target& t = *c->tg[g.tgt];
         const int Np = t.Npad, nr = g.nr;
         Cx<T>* x = g.kv[0].as<Cx<T>>();
@@ -681,28 +688,16 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
                                   g.tolrel2.as<double>(), g.maxit.as<int>(), g.active.as<int>(), st));
     }
     const int prec = std::is_same<T, double>::value ? DDA_FP64 : DDA_FP32;
-    if (use_graph && (c->gexec == nullptr || c->gkey_gen != c->ws_gen || c->gkey_prec != prec || c->gkey_k != kiters)) {
-        if (c->gexec) {
-            (void)hipGraphExecDestroy(c->gexec);
-            c->gexec = nullptr;
-        }
-        hipGraph_t graph;
-        HCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < kiters && e == hipSuccess; ++k) e = enqueue_iteration<T>(c, st, k);
-        hipError_t e2 = hipStreamEndCapture(st, &graph);
-        HCHK(c, e);
-        HCHK(c, e2);
-        e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        HCHK(c, e);
+    if (c->gkey_gen != c->ws_gen || c->gkey_prec != prec || c->gkey_k != kiters) {
+        c->drop_graphs();
         c->gkey_gen = c->ws_gen;
         c->gkey_prec = prec;
         c->gkey_k = kiters;
     }
     std::vector<std::vector<int>> hact(c->groups.size());
+    std::vector<char> live(c->groups.size());
     for (int guard = 0; guard < 1000000; ++guard) {
-        // poll: is any right-hand side still active?
+        // poll: which groups still have an active right-hand side?
         for (size_t k = 0; k < c->groups.size(); ++k) {
             hact[k].resize(c->groups[k]->nr);
             HCHK(c, hipMemcpyAsync(hact[k].data(), c->groups[k]->active.p, c->groups[k]->nr * sizeof(int),
@@ -710,13 +705,32 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
         }
         HCHK(c, hipStreamSynchronize(st));
         bool any = false;
-        for (auto& h : hact)
-            for (int v : h) any |= (v != 0);
+        for (size_t k = 0; k < hact.size(); ++k) {
+            live[k] = 0;
+            for (int v : hact[k]) live[k] |= (v != 0);
+            any |= live[k] != 0;
+        }
         if (!any) break;
         if (use_graph) {
-            HCHK(c, hipGraphLaunch(c->gexec, st));
+            auto it = c->gexec.find(live);
+            if (it == c->gexec.end()) {
+                if (c->gexec.size() >= 32) c->drop_graphs();  // bound the cache over many live sets
+                hipGraph_t graph;
+                hipGraphExec_t ex = nullptr;
+                HCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                hipError_t e = hipSuccess;
+                for (int k = 0; k < kiters && e == hipSuccess; ++k) e = enqueue_iteration<T>(c, st, k, live);
+                hipError_t e2 = hipStreamEndCapture(st, &graph);
+                HCHK(c, e);
+                HCHK(c, e2);
+                e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                HCHK(c, e);
+                it = c->gexec.emplace(live, ex).first;
+            }
+            HCHK(c, hipGraphLaunch(it->second, st));
         } else {
-            for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st, k));
+            for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st, k, live));
         }
     }
     // apply the update the last fused iteration of every rhs left pending; the
@@ -935,7 +949,7 @@ dda_status dda_destroy(dda_ctx* c) {
     if (!c) return DDA_OK;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->drop_graphs();
     c->groups.clear();
     c->tg.clear();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
