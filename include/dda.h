@@ -5,7 +5,10 @@
  * of polarizable points on a cubic lattice (DDSCAT 7.1 User Guide, section
  * "Choice of Iterative Algorithm", eq. AP=E), with the off-diagonal part of A
  * applied as a convolution by FFT on a doubled grid, a complex-symmetric
- * BiCGstab solver, and the cross-section and scattering-amplitude reductions.
+ * BiCGstab solver, and the cross-section and scattering-amplitude reductions;
+ * around them, the phase-lag and backscattering efficiencies and moments of
+ * the scattered intensity, and orientational averaging (orientation samples
+ * and weights, efficiencies at other rotations Phi from polarization pairs).
  *
  * Conventions shared by every call
  *  - Units: lattice spacing d = 1; incident amplitude |E0| = 1; Gaussian

@@ -38,7 +38,10 @@ __device__ __forceinline__ int fold_idx(int k, int n, int& sgn) {
     return (f & 1) * (n / 2 + 1) + (f >> 1);
 }
 
-template <int N> constexpr int plane_threads() { return N >= 128 ? 1024 : 256; }
+// threads of the plane passes: 512 for n = 64 (8 waves per block; with 4
+// blocks per CU by LDS that is 32 waves, against 16 with 256 threads and no
+// room for 1024)
+template <int N> constexpr int plane_threads() { return N >= 128 ? 1024 : (N == 64 ? 512 : 256); }
 template <int N> constexpr int zpass_threads() { return N >= 128 ? 512 : 256; }
 
 // UPD = 0: transform x.  UPD = 2: BiCGstab update s = r - alpha v, transform
