@@ -191,6 +191,11 @@ struct dda_ctx {
     double ms_guess = 0;
     // timing
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // convergence polls of the inner solve: active flags of every group
+    // copied into pinned host memory, two slots, one event per slot
+    int* poll_host = nullptr;
+    size_t poll_cap = 0;
+    hipEvent_t evpoll[2] = {nullptr, nullptr};
     double ms_mv32 = 0, ms_mv64 = 0, ms_total = 0;
 };
 
@@ -694,44 +699,78 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
         c->gkey_prec = prec;
         c->gkey_k = kiters;
     }
-    std::vector<std::vector<int>> hact(c->groups.size());
-    std::vector<char> live(c->groups.size());
-    for (int guard = 0; guard < 1000000; ++guard) {
-        // poll: which groups still have an active right-hand side?
-        for (size_t k = 0; k < c->groups.size(); ++k) {
-            hact[k].resize(c->groups[k]->nr);
-            HCHK(c, hipMemcpyAsync(hact[k].data(), c->groups[k]->active.p, c->groups[k]->nr * sizeof(int),
-                                   hipMemcpyDeviceToHost, st));
+    // Replays run one ahead of the convergence poll: replay i + 1 is queued
+    // before the flags left by replay i are read (pinned copies and events),
+    // so the device does not idle between replays; the replay queued after
+    // the last active rhs stopped runs with every block exiting early.
+    const size_t ng = c->groups.size();
+    std::vector<size_t> off(ng + 1, 0);
+    for (size_t k = 0; k < ng; ++k) off[k + 1] = off[k] + c->groups[k]->nr;
+    if (c->poll_cap < 2 * off[ng]) {
+        if (c->poll_host) (void)hipHostFree(c->poll_host);
+        c->poll_host = nullptr;
+        c->poll_cap = 0;
+        HCHK(c, hipHostMalloc((void**)&c->poll_host, 2 * off[ng] * sizeof(int), hipHostMallocDefault));
+        c->poll_cap = 2 * off[ng];
+    }
+    for (auto& e : c->evpoll)
+        if (!e) HCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    auto post_poll = [&](int slot) -> dda_status {
+        for (size_t k = 0; k < ng; ++k)
+            HCHK(c, hipMemcpyAsync(c->poll_host + slot * off[ng] + off[k], c->groups[k]->active.p,
+                                   c->groups[k]->nr * sizeof(int), hipMemcpyDeviceToHost, st));
+        HCHK(c, hipEventRecord(c->evpoll[slot], st));
+        return DDA_OK;
+    };
+    auto read_poll = [&](int slot, std::vector<char>& lv) -> int {  // -1: HIP error, else any active
+        if (hipEventSynchronize(c->evpoll[slot]) != hipSuccess) return -1;
+        int any = 0;
+        for (size_t k = 0; k < ng; ++k) {
+            lv[k] = 0;
+            for (size_t i = off[k]; i < off[k + 1]; ++i) lv[k] |= (c->poll_host[slot * off[ng] + i] != 0);
+            any |= lv[k];
         }
-        HCHK(c, hipStreamSynchronize(st));
-        bool any = false;
-        for (size_t k = 0; k < hact.size(); ++k) {
-            live[k] = 0;
-            for (int v : hact[k]) live[k] |= (v != 0);
-            any |= live[k] != 0;
-        }
-        if (!any) break;
+        return any;
+    };
+    auto launch = [&](const std::vector<char>& lv) -> dda_status {
         if (use_graph) {
-            auto it = c->gexec.find(live);
+            auto it = c->gexec.find(lv);
             if (it == c->gexec.end()) {
                 if (c->gexec.size() >= 32) c->drop_graphs();  // bound the cache over many live sets
                 hipGraph_t graph;
                 hipGraphExec_t ex = nullptr;
                 HCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
-                for (int k = 0; k < kiters && e == hipSuccess; ++k) e = enqueue_iteration<T>(c, st, k, live);
+                for (int k = 0; k < kiters && e == hipSuccess; ++k) e = enqueue_iteration<T>(c, st, k, lv);
                 hipError_t e2 = hipStreamEndCapture(st, &graph);
                 HCHK(c, e);
                 HCHK(c, e2);
                 e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
                 HCHK(c, e);
-                it = c->gexec.emplace(live, ex).first;
+                it = c->gexec.emplace(lv, ex).first;
             }
             HCHK(c, hipGraphLaunch(it->second, st));
         } else {
-            for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st, k, live));
+            for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st, k, lv));
         }
+        return DDA_OK;
+    };
+    std::vector<char> live(ng);
+    SCHK(post_poll(0));
+    int any = read_poll(0, live);
+    if (any < 0) return fail(c, DDA_ERR_HIP, "inner solve: poll failed");
+    int slot = 0;
+    if (any) {
+        SCHK(launch(live));
+        SCHK(post_poll(slot));
+    }
+    for (int guard = 0; any && guard < 1000000; ++guard) {
+        SCHK(launch(live));  // one replay ahead of the flags being read
+        SCHK(post_poll(slot ^ 1));
+        any = read_poll(slot, live);
+        if (any < 0) return fail(c, DDA_ERR_HIP, "inner solve: poll failed");
+        slot ^= 1;
     }
     // apply the update the last fused iteration of every rhs left pending; the
     // direction of iteration k is in kv[7] for even k, kv[3] for odd k
@@ -954,6 +993,9 @@ dda_status dda_destroy(dda_ctx* c) {
     c->tg.clear();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (auto& e : c->evpoll)
+        if (e) (void)hipEventDestroy(e);
+    if (c->poll_host) (void)hipHostFree(c->poll_host);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return DDA_OK;
