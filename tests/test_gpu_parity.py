@@ -227,6 +227,23 @@ def test_graph_and_eager_agree(ctx):
         assert _rel(Pg[l], Pe[l]) < 1e-6
 
 
+def test_replay_depth_does_not_change_the_iterates(ctx):
+    """The number of iterations per graph replay (and the replay queued
+    ahead of each convergence poll) only changes when convergence is
+    checked: iteration counts and solutions are the same for every depth."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.sphere_occupancy(16)
+    ctx.set_target(occ, [1.5 + 0.1j], 0.4)
+    khat, es, L = dda.waves_for_orientation(0.7, 1.1, 0.2)
+    ref, sref, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP32_REFINE, graph_iters=4)
+    for gi in (2, 6, 10):
+        Pg, sg, _ = ctx.solve([khat, khat], es, prec=P.DDA_SOLVE_FP32_REFINE, graph_iters=gi)
+        for l in range(2):
+            assert sg[l]["iters"] == sref[l]["iters"], (gi, l)
+            assert _rel(Pg[l], ref[l]) < 1e-12, (gi, l)
+
+
 def test_shifted_previous_guess_vs_oracle(ctx):
     """Two consecutive orientations of a sweep (Theta step, both
     polarizations): the residual of the PREV and PREV_SHIFT guesses on the
