@@ -558,7 +558,7 @@ dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
 template <class T>
 hipError_t matvec_group(const Target& t, Group& g, int nr, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, const int* active,
                         int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr},
-                        MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr}) {
+                        MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr}) {
     Cx<T>* slab = std::is_same<T, double>::value ? g.slab64.as<Cx<T>>() : g.slab32.as<Cx<T>>();
     const Cx<T>* ainv = std::is_same<T, double>::value ? g.ainv64.as<Cx<T>>() : g.ainv32.as<Cx<T>>();
     return launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab, t.ghat_for<T>(t.shape<T>()), ainv, active,
@@ -651,13 +651,13 @@ hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st, int k, const std::vecto
             if ((e = matvec_group<T>(t, g, nr, pin, v, nullptr, act, MV_AX, st)) != hipSuccess) return e;
             if ((e = launch_dot<T>(Np, nr, 1, rh, v, nullptr, nullptr, part, act, st)) != hipSuccess) return e;
         }
-        if ((e = launch_scalars(0, nbp, nr, bs, part, act, 0, st)) != hipSuccess) return e;
+        if (!fuse && (e = launch_scalars(0, nbp, nr, bs, part, act, 0, st)) != hipSuccess) return e;
         if (fuse) {
             // the inverse pass also forms <rhat, s>, <rhat, t> and ||s||^2, from
             // which the scalars follow without forming r = s - omega t; that
             // update is left pending for the next iteration's forward pass
             if ((e = matvec_group<T>(t, g, nr, s, tt, nullptr, act, MV_AX, st, MvDot{3, rh, part},
-                                     MvUpd{2, r, v, s, bs})) !=
+                                     MvUpd{2, r, v, s, bs, part})) !=
                 hipSuccess)
                 return e;
             if ((e = launch_scalars(3, nbp, nr, bs, part, act, k & 1, st)) != hipSuccess) return e;

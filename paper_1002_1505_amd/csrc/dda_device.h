@@ -232,6 +232,15 @@ __device__ void fft_lines(Cx<T>* buf, const FftPlan& p, int nl, LineAddr la, int
     }
 }
 
+// Complex quotient and product of FP64 scalars held as double2 (re, im).
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
 // ---------------------------------------------------------------------------
 // Wave-level and block-level reductions (64-wide wavefronts).
 // ---------------------------------------------------------------------------

@@ -79,7 +79,8 @@ struct MvUpd {
     const void* r;
     const void* v;
     void* pout;
-    const BiState* st;
+    BiState* st;
+    const double* part;  // mode 2: block partials of <rhat, v> (alpha is formed in the pass)
 };
 
 // Optional inner products fused into the last matvec pass (specialised plane
@@ -99,14 +100,14 @@ template <class T>
 hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh, int nrhs,
                          const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
                          const Cx<T>* ainv, const int* active, int mode, hipStream_t st, MvDot dot = MvDot{0, nullptr, nullptr},
-                         MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr});
+                         MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr});
 // Individual passes (for per-pass profiling).
 template <class T>
 hipError_t launch_pass(int which, const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh,
                        int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat,
                        const Cx<T>* ainv, const int* active, int mode, hipStream_t st,
                        MvDot dot = MvDot{0, nullptr, nullptr},
-                       MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr});
+                       MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr});
 // Shared-memory bytes and feasibility of a shape.
 template <class T>
 bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh);

@@ -46,12 +46,15 @@ template <int N> constexpr int zpass_threads() { return N >= 128 ? 512 : 256; }
 
 // UPD = 0: transform x.  UPD = 2: BiCGstab update s = r - alpha v, transform
 // s and store it in pout (only the parity-0 block of a plane stores; pout
-// never aliases an input).
+// never aliases an input).  alpha = rho / <rhat, v> is formed in the pass
+// itself from the inverse pass's block partials of <rhat, v> (slot 0 of
+// part, 12 n blocks per rhs).
 struct UpdArgs {
     const void* r;
     const void* v;
     void* pout;
-    const BiState* st;
+    BiState* st;
+    const double* part;
 };
 
 template <class T, int N, int UPD, bool G>
@@ -73,6 +76,26 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     const int c = (plane / N) % 3, z = plane % N;
     const int px = par & 1, py = par >> 1;
     const int tid = threadIdx.x;
+    constexpr int NW = NTH / 64;
+    __shared__ double red[2 * NW];
+    if constexpr (UPD == 2) {
+        // <rhat, v>: every block sums the 12 n block partials in one fixed
+        // order (thread strides, wave butterflies, waves in order), so all
+        // blocks of the pass hold the same alpha bit for bit
+        constexpr int NB = 12 * N;
+        const double* pp = u.part + (size_t)rhs * 4 * NB * 2;
+        double ar = 0, ai = 0;
+        for (int i = tid; i < NB; i += NTH) {
+            ar += pp[2 * i];
+            ai += pp[2 * i + 1];
+        }
+        ar = wave_sum(ar);
+        ai = wave_sum(ai);
+        if ((tid & 63) == 0) {
+            red[2 * (tid >> 6)] = ar;
+            red[2 * (tid >> 6) + 1] = ai;
+        }
+    }
     for (int i = tid; i < N; i += NTH) t1[i] = tw.f1[i];
 #pragma unroll 4
     for (int i = tid; i < N * PITCH; i += NTH) buf[i] = Cx<T>{0, 0};
@@ -80,7 +103,28 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
     const int j0 = g.plane_start[z], j1 = g.plane_start[z + 1];
     Cx<T> c1 = {0, 0};
-    if (UPD == 2) c1 = Cx<T>{(T)u.st[rhs].alpha[0], (T)u.st[rhs].alpha[1]};
+    if constexpr (UPD == 2) {
+        double ar = 0, ai = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            ar += red[2 * w];
+            ai += red[2 * w + 1];
+        }
+        // alpha = rho / <rhat, v>; a vanishing <rhat, v> (absolutely, or
+        // against ||r||^2) gives alpha = 0 and marks a restart
+        const double2 rho = make_double2(u.st[rhs].rho[0], u.st[rhs].rho[1]);
+        const double an = sqrt(ar * ar + ai * ai);
+        const int rs = (!(an > 1e-300) || !(an > 1e-14 * u.st[rhs].rr)) ? 1 : 0;
+        const double2 al = rs ? make_double2(0.0, 0.0) : cdiv(rho, make_double2(ar, ai));
+        c1 = Cx<T>{(T)al.x, (T)al.y};
+        // the rhs's first block records alpha and the restart flag; no block
+        // of this pass reads either field
+        if (tid == 0 && par == 0 && plane % (3 * N) == 0) {
+            u.st[rhs].alpha[0] = al.x;
+            u.st[rhs].alpha[1] = al.y;
+            u.st[rhs].restart = rs;
+        }
+    }
     const Cx<T>* rv = reinterpret_cast<const Cx<T>*>(u.r);
     const Cx<T>* vv = reinterpret_cast<const Cx<T>*>(u.v);
     Cx<T>* po = reinterpret_cast<Cx<T>*>(u.pout);
@@ -887,7 +931,7 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
         } else {
             const bool tf = (ct & 4) != 0, gr = (ct & 8) != 0;
             if (which == 0) {
-                const UpdArgs ua{upd.r, upd.v, upd.pout, upd.st};
+                const UpdArgs ua{upd.r, upd.v, upd.pout, upd.st, upd.part};
                 if (upd.mode == 2) launch_pfwd<T, N, 2>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
                 else if (upd.mode == 0) launch_pfwd<T, N, 0>(nblk_plane, gr, g, tw, nrhs, x, slab, active, ua, st);
                 else return hipErrorInvalidValue;

@@ -174,16 +174,9 @@ __device__ __forceinline__ double2 reduce_slot(const double* partials, int rhs, 
     return make_double2(re, im);
 }
 
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-    const double d = b.x * b.x + b.y * b.y;
-    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
-}
-__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
 // One block per rhs.
 //  which 0: alpha = rho / <rhat, v>       (partials slot 0); breakdown -> alpha = 0, restart
+//           (in the fused iteration the forward pass of s forms alpha itself)
 //  which 1: omega = <t, s> / <t, t>       (slots 0, 1); breakdown -> omega = 0, restart
 //  which 2: rho' = <rhat, r>, rr = <r, r> (slots 0, 1); beta, convergence, iteration count
 //  which 3: the fused end of an iteration that never forms r = s - omega t:
