@@ -148,11 +148,26 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y: lines are columns
     Cx<T>* out = slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + par) * (size_t)(N * N);
     if constexpr (G) {
+        // one lane per group: its four quadrant partners (y, x), (y, x + n/2),
+        // (y + n/2, x), (y + n/2, x + n/2) lie in one LDS bank, so the lane
+        // reads all four (lanes of one access hold different groups of a row)
+        // and stores them as 4 consecutive elements
         constexpr int HN = N / 2;
-#pragma unroll 8
-        for (int i = tid; i < N * N; i += NTH) {
-            const int h = i & 3, gq = i >> 2;
-            out[i] = buf[(gq / HN + (h >> 1) * HN) * PITCH + grp_bx(gq % HN, px, HN) + (h & 1) * HN];
+#pragma unroll 2
+        for (int gq = tid; gq < N * N / 4; gq += NTH) {
+            const Cx<T>* q = buf + (gq / HN) * PITCH + grp_bx(gq % HN, px, HN);
+            const Cx<T> a0 = q[0], a1 = q[HN], a2 = q[HN * PITCH], a3 = q[HN * PITCH + HN];
+            if constexpr (sizeof(Cx<T>) == 8) {
+                float4* o4 = reinterpret_cast<float4*>(out) + 2 * (size_t)gq;
+                o4[0] = make_float4(a0.re, a0.im, a1.re, a1.im);
+                o4[1] = make_float4(a2.re, a2.im, a3.re, a3.im);
+            } else {
+                Cx<T>* o = out + 4 * (size_t)gq;
+                o[0] = a0;
+                o[1] = a1;
+                o[2] = a2;
+                o[3] = a3;
+            }
         }
     } else {
 #pragma unroll 8

@@ -207,19 +207,28 @@ __device__ void finish_iteration(BiState& s, double2 a, double2 b, int* active, 
     if (s.conv || s.it >= s.maxit || !isfinite(b.x)) active[rhs] = 0;
 }
 
-__global__ void k_scalars(int which, int nblk, BiState* __restrict__ st, const double* __restrict__ partials,
-                          int* __restrict__ active, int kpar) {
-    __shared__ double sh[8 * 16];
+constexpr int SCALAR_THREADS = 1024;
+
+__global__ void __launch_bounds__(SCALAR_THREADS)
+    k_scalars(int which, int nblk, BiState* __restrict__ st, const double* __restrict__ partials,
+              int* __restrict__ active, int kpar) {
+    __shared__ double sh[8 * (SCALAR_THREADS / 64)];
     const int rhs = blockIdx.x;
     if (!active[rhs]) return;
-    // all slots the step needs in one pass over the block partials
+    // all slots the step needs in one pass over the block partials: the
+    // loads of every slot are issued together (one memory round trip per
+    // SCALAR_THREADS partials instead of one per slot and stride)
     const int nslot = which == 0 ? 1 : (which == 3 ? 4 : 2);
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int q = 0; q < nslot; ++q) {
-        const double* p = partials + ((size_t)rhs * 4 + q) * nblk * 2;
-        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
-            v[2 * q] += p[2 * i];
-            v[2 * q + 1] += p[2 * i + 1];
+    const double2* p2 = reinterpret_cast<const double2*>(partials) + (size_t)rhs * 4 * nblk;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        double2 e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[q] = q < nslot ? p2[(size_t)q * nblk + i] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[2 * q] += e[q].x;
+            v[2 * q + 1] += e[q].y;
         }
     }
     block_sum_n<8>(v, sh);
@@ -780,7 +789,7 @@ hipError_t launch_bicg_xr(int Npad, int nrhs, Cx<T>* x, Cx<T>* r, const Cx<T>* p
 }
 hipError_t launch_scalars(int which, int nblk, int nrhs, BiState* s, const double* partials, int* active, int kpar,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_scalars, dim3(nrhs), dim3(256), 0, st, which, nblk, s, partials, active, kpar);
+    hipLaunchKernelGGL(k_scalars, dim3(nrhs), dim3(SCALAR_THREADS), 0, st, which, nblk, s, partials, active, kpar);
     return hipGetLastError();
 }
 template <class T>
