@@ -122,7 +122,7 @@ typedef struct {
 typedef struct {
     int32_t iters;        /* BiCGstab iterations taken */
     int32_t matvecs;      /* FFT matvecs (FP32 and FP64) */
-    int32_t outer;        /* FP64 residual evaluations */
+    int32_t outer;        /* FP64 residual checks (from a zero guess the first is E itself, no matvec) */
     int32_t status;       /* 0 converged, DDA_WARN_NOT_CONVERGED otherwise */
     double rel_resid;     /* final ||E - A P|| / ||E|| with the FP64 matvec */
     double guess_resid;   /* ||E - A P0|| / ||E|| of the guess actually used */

@@ -1220,7 +1220,9 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
     HCHK(c, hipEventCreate(&eb));
     const int max_outer = 40;
     for (int it_out = 0; it_out <= max_outer; ++it_out) {
-        // FP64 residual r = b - A x for rhs not yet done
+        // FP64 residual r = b - A x for rhs not yet done; from x = 0 it is b
+        // itself (copied, its norm is the one above), with no matvec
+        const bool from_zero = it_out == 0 && !guessed;
         HCHK(c, hipEventRecord(ea, st));
         for (auto& gp : c->groups) {
             Group& g = *gp;
@@ -1229,6 +1231,11 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
             mk.resize(g.nr);
             for (int s = 0; s < g.nr; ++s) mk[s] = done[g.idx[s]] ? 0 : 1;
             HCHK(c, hipMemcpyAsync(g.mask.p, mk.data(), g.nr * sizeof(int), hipMemcpyHostToDevice, st));
+            if (from_zero) {
+                HCHK(c, hipMemcpyAsync(g.r64.p, g.b64.p, vec_elems(t, g.nr) * sizeof(Cx<double>),
+                                       hipMemcpyDeviceToDevice, st));
+                continue;
+            }
             HCHK(c, matvec_group<double>(t, g, g.nr, g.x64.as<Cx<double>>(), g.r64.as<Cx<double>>(),
                                          g.b64.as<Cx<double>>(), g.mask.as<int>(), MV_RESID, st));
             HCHK(c, launch_norm2<double>(t.Npad, g.nr, g.r64.as<Cx<double>>(), g.partials.as<double>(),
@@ -1244,7 +1251,11 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
             Group& g = *gp;
             Target& t = *c->tg[g.tgt];
             std::vector<double> h(g.nr);
-            HCHK(c, hipMemcpy(h.data(), g.norms.p, g.nr * sizeof(double), hipMemcpyDeviceToHost));
+            if (from_zero) {
+                for (int s = 0; s < g.nr; ++s) h[s] = bb[g.idx[s]];
+            } else {
+                HCHK(c, hipMemcpy(h.data(), g.norms.p, g.nr * sizeof(double), hipMemcpyDeviceToHost));
+            }
             std::vector<double>& sc = g.hscale;
             std::vector<double>& tr2 = g.htol2;
             std::vector<int>& mi = g.hmaxit;
@@ -1255,7 +1266,7 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
                 const int i = g.idx[s];
                 if (done[i]) continue;
                 outer[i] += 1;
-                mvs[i] += 1;
+                if (!from_zero) mvs[i] += 1;
                 double rr = h[s];
                 double rl = bb[i] > 0 ? std::sqrt(rr / bb[i]) : 0.0;
                 if (it_out == 0) {
