@@ -70,6 +70,35 @@ struct DevMem {
     U* as() const { return reinterpret_cast<U*>(p); }
 };
 
+// Pinned host memory, grown on demand: asynchronous copies from it return at
+// once (pageable sources are staged by the runtime and block the caller).
+// Contents must stay untouched until the copies that read them complete.
+struct PinMem {
+    void* p = nullptr;
+    size_t n = 0;
+    PinMem() = default;
+    PinMem(const PinMem&) = delete;
+    PinMem& operator=(const PinMem&) = delete;
+    ~PinMem() { release(); }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n && p) return hipSuccess;
+        release();
+        hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        n = bytes;
+        return hipSuccess;
+    }
+    template <class U> U* as() const { return static_cast<U*>(p); }
+};
+
 struct Target {
     long long uid = 0;
     int n[3] = {0, 0, 0};
@@ -159,8 +188,15 @@ struct Group {
     std::vector<WaveDev> hw;
     std::vector<cd> hainv;  // [nr][ncomp]
     std::vector<Cx<float>> hainv32;
-    std::vector<int> hmask, hmaxit;
-    std::vector<double> hscale, htol2;
+    std::vector<int> hmask;
+    // pinned staging of the refinement loop: per-slot scale and squared
+    // tolerance (double), iteration budget and mask (int); inner-solve states
+    PinMem hup, hst;
+    double* up_scale() const { return hup.as<double>(); }
+    double* up_tol2() const { return hup.as<double>() + nr; }
+    int* up_maxit() const { return reinterpret_cast<int*>(hup.as<double>() + 2 * nr); }
+    int* up_mask() const { return up_maxit() + nr; }
+    size_t up_bytes() const { return (size_t)nr * (2 * sizeof(double) + 2 * sizeof(int)); }
 };
 
 }  // namespace
@@ -197,6 +233,9 @@ struct dda_ctx {
     size_t poll_cap = 0;
     hipEvent_t evpoll[2] = {nullptr, nullptr};
     double ms_mv32 = 0, ms_mv64 = 0, ms_total = 0;
+    // device scratch of the post-solve calls (cross sections, amplitudes,
+    // moments), kept between calls: no allocation or free per call
+    DevMem scr[8];
 };
 
 namespace {
@@ -756,10 +795,16 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
         }
         return DDA_OK;
     };
+    // the first replay runs every group with a slot the refinement loop gave
+    // an iteration budget (its mask); the state initialisation activates no
+    // other slot, and one that starts converged only exits early
     std::vector<char> live(ng);
-    SCHK(post_poll(0));
-    int any = read_poll(0, live);
-    if (any < 0) return fail(c, DDA_ERR_HIP, "inner solve: poll failed");
+    int any = 0;
+    for (size_t k = 0; k < ng; ++k) {
+        live[k] = 0;
+        for (int v : c->groups[k]->hmask) live[k] |= (v != 0);
+        any |= live[k];
+    }
     int slot = 0;
     if (any) {
         SCHK(launch(live));
@@ -1227,10 +1272,10 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
         for (auto& gp : c->groups) {
             Group& g = *gp;
             Target& t = *c->tg[g.tgt];
-            std::vector<int>& mk = g.hmask;
-            mk.resize(g.nr);
+            HCHK(c, g.hup.ensure(g.up_bytes()));
+            int* mk = g.up_mask();
             for (int s = 0; s < g.nr; ++s) mk[s] = done[g.idx[s]] ? 0 : 1;
-            HCHK(c, hipMemcpyAsync(g.mask.p, mk.data(), g.nr * sizeof(int), hipMemcpyHostToDevice, st));
+            HCHK(c, hipMemcpyAsync(g.mask.p, mk, g.nr * sizeof(int), hipMemcpyHostToDevice, st));
             if (from_zero) {
                 HCHK(c, hipMemcpyAsync(g.r64.p, g.b64.p, vec_elems(t, g.nr) * sizeof(Cx<double>),
                                        hipMemcpyDeviceToDevice, st));
@@ -1256,12 +1301,15 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
             } else {
                 HCHK(c, hipMemcpy(h.data(), g.norms.p, g.nr * sizeof(double), hipMemcpyDeviceToHost));
             }
-            std::vector<double>& sc = g.hscale;
-            std::vector<double>& tr2 = g.htol2;
-            std::vector<int>& mi = g.hmaxit;
-            sc.assign(g.nr, 1.0);
-            tr2.assign(g.nr, 0.0);
-            mi.assign(g.nr, 0);
+            // the residual mask's upload from g.hup has completed (event above)
+            double* sc = g.up_scale();
+            double* tr2 = g.up_tol2();
+            int* mi = g.up_maxit();
+            for (int s = 0; s < g.nr; ++s) {
+                sc[s] = 1.0;
+                tr2[s] = 0.0;
+                mi[s] = 0;
+            }
             for (int s = 0; s < g.nr; ++s) {
                 const int i = g.idx[s];
                 if (done[i]) continue;
@@ -1307,16 +1355,20 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
                 tr2[s] = tin * tin;
                 mi[s] = max_iter - iters[i];
             }
-            HCHK(c, hipMemcpyAsync(g.scale.p, sc.data(), g.nr * sizeof(double), hipMemcpyHostToDevice, st));
-            HCHK(c, hipMemcpyAsync(g.tolrel2.p, tr2.data(), g.nr * sizeof(double), hipMemcpyHostToDevice, st));
-            HCHK(c, hipMemcpyAsync(g.maxit.p, mi.data(), g.nr * sizeof(int), hipMemcpyHostToDevice, st));
             std::vector<int>& mk = g.hmask;
             mk.resize(g.nr);
-            for (int s = 0; s < g.nr; ++s) mk[s] = mi[s] > 0 ? 1 : 0;
-            HCHK(c, hipMemcpyAsync(g.mask.p, mk.data(), g.nr * sizeof(int), hipMemcpyHostToDevice, st));
-            HCHK(c, hipStreamSynchronize(st));
+            for (int s = 0; s < g.nr; ++s) mk[s] = g.up_mask()[s] = mi[s] > 0 ? 1 : 0;
         }
         if (all_done) break;
+        // scale, tolerance, budget and mask of the inner solve: asynchronous
+        // copies from pinned staging, ordered before it by the stream
+        for (auto& gp : c->groups) {
+            Group& g = *gp;
+            HCHK(c, hipMemcpyAsync(g.scale.p, g.up_scale(), g.nr * sizeof(double), hipMemcpyHostToDevice, st));
+            HCHK(c, hipMemcpyAsync(g.tolrel2.p, g.up_tol2(), g.nr * sizeof(double), hipMemcpyHostToDevice, st));
+            HCHK(c, hipMemcpyAsync(g.maxit.p, g.up_maxit(), g.nr * sizeof(int), hipMemcpyHostToDevice, st));
+            HCHK(c, hipMemcpyAsync(g.mask.p, g.up_mask(), g.nr * sizeof(int), hipMemcpyHostToDevice, st));
+        }
         // inner solve: A d = r / ||r||
         HCHK(c, hipEventRecord(ea, st));
         for (auto& gp : c->groups) {
@@ -1340,9 +1392,14 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
             else
                 HCHK(c, launch_axpy_masked<double>(t.Npad, g.nr, g.x64.as<Cx<double>>(), g.kv[0].as<Cx<double>>(),
                                                    g.mask.as<int>(), st));
-            std::vector<BiState> hs(g.nr);
-            HCHK(c, hipMemcpyAsync(hs.data(), g.state.p, g.nr * sizeof(BiState), hipMemcpyDeviceToHost, st));
-            HCHK(c, hipStreamSynchronize(st));
+            HCHK(c, g.hst.ensure(g.nr * sizeof(BiState)));
+            HCHK(c, hipMemcpyAsync(g.hst.p, g.state.p, g.nr * sizeof(BiState), hipMemcpyDeviceToHost, st));
+        }
+        HCHK(c, hipEventRecord(eb, st));
+        HCHK(c, hipEventSynchronize(eb));
+        for (auto& gp : c->groups) {
+            Group& g = *gp;
+            const BiState* hs = g.hst.as<BiState>();
             const std::vector<int>& mk = g.hmask;
             for (int s = 0; s < g.nr; ++s) {
                 if (!mk[s]) continue;
@@ -1350,8 +1407,6 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
                 mvs[g.idx[s]] += 2 * hs[s].it;
             }
         }
-        HCHK(c, hipEventRecord(eb, st));
-        HCHK(c, hipEventSynchronize(eb));
         HCHK(c, hipEventElapsedTime(&ms, ea, eb));
         if (prec == DDA_SOLVE_FP32_REFINE) ms32 += ms;
         else ms64 += ms;
@@ -1460,7 +1515,7 @@ dda_status dda_cross_sections(dda_ctx* c, int32_t nrhs, double* q) {
     if (!c->have_solution) return fail(c, DDA_ERR_STATE, "cross_sections before a solve");
     if (nrhs != c->last_nrhs || !q) return fail(c, DDA_ERR_INVALID_ARG, "cross_sections: nrhs must match the last solve");
     hipStream_t st = c->stream;
-    DevMem out;
+    DevMem& out = c->scr[0];
     for (auto& gp : c->groups) {
         Group& g = *gp;
         Target& t = *c->tg[g.tgt];
@@ -1502,7 +1557,7 @@ dda_status dda_cross_sections_phi(dda_ctx* c, int32_t npairs, int32_t ncomb, con
                         "of solutions are not solutions");
     }
     hipStream_t st = c->stream;
-    DevMem dslots, dpart;
+    DevMem &dslots = c->scr[0], &dpart = c->scr[1];
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
         Group& g = *c->groups[gi];
         const Target& t = *c->tg[g.tgt];
@@ -1563,7 +1618,7 @@ dda_status dda_scattering_moments(dda_ctx* c, int32_t nrhs, int32_t ndir, const 
     if (nrhs != c->last_nrhs || ndir < 1 || !n_tf || !w || !out)
         return fail(c, DDA_ERR_INVALID_ARG, "scattering_moments: bad arguments (nrhs must match the last solve)");
     hipStream_t st = c->stream;
-    DevMem dn, dF, dP, dx, db;
+    DevMem &dn = c->scr[0], &dF = c->scr[1], &dP = c->scr[2], &dx = c->scr[3], &db = c->scr[4];
     HCHK(c, dn.ensure((size_t)ndir * 3 * sizeof(double)));
     HCHK(c, hipMemcpyAsync(dn.p, n_tf, (size_t)ndir * 3 * sizeof(double), hipMemcpyHostToDevice, st));
     for (auto& gp : c->groups) {
@@ -1591,7 +1646,7 @@ dda_status dda_scattering_moments(dda_ctx* c, int32_t nrhs, int32_t ndir, const 
         HCHK(c, db.ensure(nb.size() * sizeof(double)));
         HCHK(c, hipMemcpyAsync(db.p, nb.data(), nb.size() * sizeof(double), hipMemcpyHostToDevice, st));
         std::vector<cd> Fb(3 * g.nr);
-        DevMem dFb, dPb;
+        DevMem &dFb = c->scr[5], &dPb = c->scr[6];
         HCHK(c, dFb.ensure(3 * sizeof(Cx<double>) * g.nr));
         HCHK(c, dPb.ensure((size_t)ampl_chunks(1, 1, t.N) * 6 * sizeof(double)));
         for (int s2 = 0; s2 < g.nr; ++s2)
@@ -1637,7 +1692,7 @@ dda_status dda_amplitudes(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* 
     if (nrhs != c->last_nrhs || ndir <= 0 || !n_tf || !e_tf || !f)
         return fail(c, DDA_ERR_INVALID_ARG, "amplitudes: bad arguments");
     hipStream_t st = c->stream;
-    DevMem dn, dF, dP;
+    DevMem &dn = c->scr[0], &dF = c->scr[1], &dP = c->scr[2];
     HCHK(c, dn.ensure((size_t)ndir * 3 * sizeof(double)));
     HCHK(c, hipMemcpyAsync(dn.p, n_tf, (size_t)ndir * 3 * sizeof(double), hipMemcpyHostToDevice, st));
     for (auto& gp : c->groups) {
