@@ -64,3 +64,31 @@ def test_moments_errors(ctx):
     with pytest.raises(P.DDAError):  # rhs count differs from the last solve
         ctx.scattering_moments(3, n, w)
     assert len(ctx.scattering_moments(2, n, w)) == 2
+
+
+def test_post_solve_calls_share_scratch(ctx):
+    """Cross sections, amplitudes and moments reuse the context's device
+    scratch, which grows with the largest request: interleaved calls of
+    different sizes give the same values as the first call of each kind."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.ellipsoid_occupancy((12, 10, 9), (11.2, 9.4, 8.1))
+    ctx.set_target(occ, [1.5 + 0.05j], 0.4, P.DDA_ALPHA_LDR)
+    orient = (0.2, 0.7, 0.4)
+    kh, e0 = P.orientation_waves(*orient)
+    ctx.solve(list(kh), list(e0), tol=1e-8, prec=P.DDA_SOLVE_FP64, want_p=False)
+    L = P.lab_frame(*orient)
+    th = np.deg2rad(np.arange(0, 181, 15.0))
+    n_small, e_small = P.scattering_frame(th, np.zeros_like(th), L)
+    n_q, w_q = P.scattering_quadrature(4.0, 0.5, L)
+    q0 = ctx.cross_sections(2)
+    f0 = ctx.amplitudes(2, n_small, e_small)
+    m0 = ctx.scattering_moments(2, n_q, w_q)
+    for _ in range(2):
+        f1 = ctx.amplitudes(2, n_small, e_small)
+        m1 = ctx.scattering_moments(2, n_q, w_q)
+        q1 = ctx.cross_sections(2)
+        assert np.array_equal(f1, f0) and np.array_equal(q1, q0)
+        for l in range(2):
+            for key in P.Context.MOMENT_KEYS:
+                assert np.array_equal(np.asarray(m1[l][key]), np.asarray(m0[l][key])), key

@@ -313,3 +313,24 @@ def test_projected_history_guess_vs_oracle(ctx):
         assert st[l]["rel_resid"] <= 1e-5
     with pytest.raises(P.DDAError):
         ctx.solve([kn, kn], en, guess=P.DDA_GUESS_PROJECT, history=5)
+
+
+def test_zero_guess_shortcut_matches_a_zero_user_guess(ctx):
+    """From P0 = 0 the first FP64 residual is E itself, which the solve takes
+    without a matvec; a user guess of zeros takes the matvec path (E - A 0).
+    Both give E exactly, so solutions and iteration counts are identical, and
+    the shortcut saves one matvec per rhs."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.ellipsoid_occupancy((12, 10, 9), (11.5, 9.4, 8.6))
+    r, comp = _setup(ctx, occ, [1.45 + 0.08j], 0.35, dda.ALPHA_LDR)
+    khat, es, L = dda.waves_for_orientation(0.4, 0.8, 0.3)
+    for prec in (P.DDA_SOLVE_FP32_REFINE, P.DDA_SOLVE_FP64):
+        Pz, sz, _ = ctx.solve([khat, khat], es, prec=prec, tol=1e-6)
+        zeros = [np.zeros((len(r), 3), np.complex128) for _ in range(2)]
+        Pu, su, _ = ctx.solve([khat, khat], es, prec=prec, tol=1e-6, guess=P.DDA_GUESS_USER, p0=zeros)
+        for l in range(2):
+            assert sz[l]["iters"] == su[l]["iters"] and sz[l]["outer"] == su[l]["outer"], (prec, l)
+            assert sz[l]["matvecs"] == su[l]["matvecs"] - 1, (prec, l)
+            assert np.array_equal(Pz[l], Pu[l]), (prec, l)
+            assert sz[l]["rel_resid"] == su[l]["rel_resid"] and sz[l]["rel_resid"] <= 1e-6
