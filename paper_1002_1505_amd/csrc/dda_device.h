@@ -250,13 +250,43 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Value from another lane of the same row of 16 by a DPP row operation
+// (CTRL: quad permutation or row mirror).  Every lane of the wave must be
+// active.
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave, the same bits in every lane, without LDS
+// traffic (a shuffle of a double is two LDS permutes): DPP steps within rows
+// of 16 lanes, each pairing lanes that hold equal partial sums (quad swaps,
+// half-row mirror, row mirror), then the four row sums from lanes 0, 16, 32
+// and 48 in a fixed order.  Every lane of the wave must be active.
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
 // Sums of NV values over the block with one barrier; results valid in
-// thread 0 (v is overwritten).  `sh` needs NV * blockDim.x / 64 doubles.
+// thread 0 (v is overwritten).  `sh` needs NV * blockDim.x / 64 doubles;
+// blockDim.x is a multiple of 64 and every thread takes part.
 template <int NV>
 __device__ __forceinline__ void block_sum_n(double* v, double* sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    for (int i = 0; i < NV; ++i) v[i] = wave_total(v[i]);
     if (lane == 0)
 #pragma unroll
         for (int i = 0; i < NV; ++i) sh[w * NV + i] = v[i];

@@ -80,8 +80,8 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     __shared__ double red[2 * NW];
     if constexpr (UPD == 2) {
         // <rhat, v>: every block sums the 12 n block partials in one fixed
-        // order (thread strides, wave butterflies, waves in order), so all
-        // blocks of the pass hold the same alpha bit for bit
+        // order (thread strides, wave totals, waves in order), so all blocks
+        // of the pass hold the same alpha bit for bit
         constexpr int NB = 12 * N;
         const double* pp = u.part + (size_t)rhs * 4 * NB * 2;
         double ar = 0, ai = 0;
@@ -89,8 +89,8 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
             ar += pp[2 * i];
             ai += pp[2 * i + 1];
         }
-        ar = wave_sum(ar);
-        ai = wave_sum(ai);
+        ar = wave_total(ar);
+        ai = wave_total(ai);
         if ((tid & 63) == 0) {
             red[2 * (tid >> 6)] = ar;
             red[2 * (tid >> 6) + 1] = ai;
