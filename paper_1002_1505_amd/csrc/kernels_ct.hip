@@ -96,7 +96,14 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
             red[2 * (tid >> 6) + 1] = ai;
         }
     }
-    for (int i = tid; i < N; i += NTH) t1[i] = tw.f1[i];
+    // the half-shift twiddles of the site coordinates next to the plane, so
+    // the gather's lookups (addressed by the site just loaded) stay in LDS
+    Cx<T>* th = buf + N * PITCH;
+    for (int i = tid; i < N; i += NTH) {
+        t1[i] = tw.f1[i];
+        th[i] = tw.h1[i];
+        th[N + i] = tw.h2[i];
+    }
 #pragma unroll 4
     for (int i = tid; i < N * PITCH; i += NTH) buf[i] = Cx<T>{0, 0};
     __syncthreads();
@@ -139,8 +146,8 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
             v = rv[vo + j] - c1 * vv[vo + j];
             if (par == 0) po[vo + j] = v;
         }
-        if (px) v = v * tw.h1[sx];
-        if (py) v = v * tw.h2[sy];
+        if (px) v = v * th[sx];
+        if (py) v = v * th[N + sy];
         buf[sy * PITCH + sx] = v;
     }
     __syncthreads();
@@ -882,7 +889,7 @@ __global__ void __launch_bounds__(256) k_pinv3_ct(const Cx<T>* __restrict__ slab
 }
 
 template <class T, int N>
-constexpr size_t plane_lds() { return (size_t)(N + N * (N + 1)) * sizeof(Cx<T>); }
+constexpr size_t plane_lds() { return (size_t)(3 * N + N * (N + 1)) * sizeof(Cx<T>); }
 template <class T, int N, int TX>
 constexpr size_t zpass_lds() { return (size_t)(N + 6 * N * TX) * sizeof(Cx<T>); }
 template <class T, int N, int TX>
@@ -1129,7 +1136,7 @@ int ct_available(int n, int tx) {
     auto planes = [](size_t lds) { return lds <= LDS_MAX; };
     int bits = 0;
     if (!ct_supported(n, n, n)) return 0;
-    if (planes((size_t)(n + n * (n + 1)) * sizeof(Cx<T>))) bits |= 1;
+    if (planes((size_t)(3 * n + n * (n + 1)) * sizeof(Cx<T>))) bits |= 1;  // as plane_lds
     if ((bits & 1) && n == 64) bits |= 4;  // two-factor inverse plane pass
     if (ct_zpass_fits<T>(n, tx, 0) || ct_zpass_fits<T>(n, tx, 2)) bits |= 2;
     if ((bits & 3) == 3 && ct_zpass_fits<T>(n, tx, 3)) bits |= 8;  // class-grouped slab
