@@ -70,10 +70,14 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     const int b = blockIdx.x;
     const int plane = ((b >> 3) >> 2) * 8 + (b & 7);
     const int par = (b >> 3) & 3;
-    if (plane >= nplanes) return;
-    const int rhs = plane / (3 * N);
-    if (active && !active[rhs]) return;
+    // every scalar of the exit test is loaded before it (the rhs clamped into
+    // range for blocks past the last plane; a site range is never reversed),
+    // so the loads overlap instead of following one another
+    const int rhs = min(plane / (3 * N), nrhs - 1);
     const int c = (plane / N) % 3, z = plane % N;
+    const int j0 = g.plane_start[z], j1 = g.plane_start[z + 1];
+    const int on = active ? active[rhs] : 1;
+    if (plane >= nplanes || !on || j1 < j0) return;
     const int px = par & 1, py = par >> 1;
     const int tid = threadIdx.x;
     constexpr int NW = NTH / 64;
@@ -108,7 +112,6 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     for (int i = tid; i < N * PITCH; i += NTH) buf[i] = Cx<T>{0, 0};
     __syncthreads();
     const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
-    const int j0 = g.plane_start[z], j1 = g.plane_start[z + 1];
     Cx<T> c1 = {0, 0};
     if constexpr (UPD == 2) {
         double ar = 0, ai = 0;
@@ -365,7 +368,9 @@ __global__ void __launch_bounds__(TX * 8) k_zpass3_ct(Cx<T>* __restrict__ slab, 
     const int pos = b >> 3;
     const int r = pos % nrhs;
     const int tile = tiles[(b & 7) * PER_XCD + pos / nrhs];
-    if (active && !active[r]) return;
+    // the tile index enters the exit test (it is never negative), so its load
+    // is issued together with the flag's instead of after the branch
+    if ((active && !active[r]) || tile < 0) return;
     const int tid = threadIdx.x;
     const int c = tid % TX, j = tid / TX;  // j: z1 in the outer steps, k2 in the inner ones
     const int q0 = tile * TX;
@@ -493,7 +498,9 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
     const int pos = b >> 3;
     const int r = pos % nrhs;
     const int tile = tiles[(b & 7) * PER_XCD + pos / nrhs];
-    if (active && !active[r]) return;
+    // the tile index enters the exit test (it is never negative), so its load
+    // is issued together with the flag's instead of after the branch
+    if ((active && !active[r]) || tile < 0) return;
     const int tid = threadIdx.x;
     const int pz = tid / (TX * R);
     const int tt = tid % (TX * R);
@@ -632,10 +639,15 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     const int b = blockIdx.x;
     const int plane = ((b >> 3) >> 2) * 8 + (b & 7);
     const int q = (b >> 3) & 3;
-    if (plane >= nplanes) return;
-    const int rhs = plane / (3 * N);
-    if (active && !active[rhs]) return;
+    // every scalar of the exit test is loaded before it (the rhs clamped into
+    // range for blocks past the last plane; a site range is never reversed),
+    // so the loads overlap; the sites of output class q are stored
+    // contiguously within the plane
+    const int rhs = min(plane / (3 * N), nrhs - 1);
     const int c = (plane / N) % 3, z = plane % N;
+    const int j0 = g.class_start[4 * z + q], j1 = g.class_start[4 * z + q + 1];
+    const int on = active ? active[rhs] : 1;
+    if (plane >= nplanes || !on || j1 < j0) return;
     const int qx = q & 1, qy = q >> 1;
     const int tid = threadIdx.x;
     for (int i = tid; i < N; i += NTH) t1[i] = tw.f1[i];
@@ -664,8 +676,6 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     ct_fft<T, +1, N, HN, NTH, HN, PITCH, 0, 1>(buf, t1, tid);  // along x, rows y' < n/2
     const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
     const Cx<T>* av = ainv + (size_t)rhs * g.ncomp;
-    // the sites of output class q are stored contiguously within the plane
-    const int j0 = g.class_start[4 * z + q], j1 = g.class_start[4 * z + q + 1];
     double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0, a3r = 0, a3i = 0;
 #pragma unroll 2
     for (int j = j0 + tid; j < j1; j += NTH) {
