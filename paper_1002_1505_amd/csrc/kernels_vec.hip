@@ -560,21 +560,36 @@ __global__ void __launch_bounds__(256) k_xsec_pair(Geo g, const Cx<double>* __re
 
 // One block per (direction, rhs): F = sum_j P_j exp(-i k n . r_j), FP64.
 // Block (dir, rhs, chunk): partial sums of F over one chunk of the sites,
-// partials[((chunk * nrhs + rhs) * ndir + dir) * 6 + q].
+// partials[((chunk * nrhs + rhs) * ndir + dir) * 6 + q].  On the lattice the
+// phase separates per axis, so the block evaluates n1 + n2 + n3 sincos for
+// its direction and each site takes two complex products of table entries.
 __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, double oz, double k,
                                               const Cx<double>* __restrict__ P, const double* __restrict__ nd,
                                               double* __restrict__ partials, int ndir, int nrhs) {
     __shared__ double sh[6 * 4];
+    // the phase factors per axis, exp(-i k n_a (a - o_a)) for a = x, y, z at
+    // every lattice coordinate of the box: [n1 | n2 | n3]
+    extern __shared__ unsigned char smem_raw[];
+    Cx<double>* T = reinterpret_cast<Cx<double>*>(smem_raw);
     const int dir = blockIdx.x, rhs = blockIdx.y, chunk = blockIdx.z;
     const int per = (g.N + gridDim.z - 1) / gridDim.z;
     const int j0 = chunk * per, j1 = min(g.N, j0 + per);
     const double nx = nd[3 * dir], ny = nd[3 * dir + 1], nz = nd[3 * dir + 2];
+    const int n12 = g.n1 + g.n2, nt = n12 + g.n3;
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+        const double a = i < g.n1 ? nx * ((double)i - ox)
+                                  : (i < n12 ? ny * ((double)(i - g.n1) - oy) : nz * ((double)(i - n12) - oz));
+        double sn, cs;
+        sincos(-k * a, &sn, &cs);
+        T[i] = Cx<double>{cs, sn};
+    }
+    __syncthreads();
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
         const uint32_t s = g.site_xyz[j];
-        const double x = (double)(s & 1023) - ox, y = (double)((s >> 10) & 1023) - oy, z = (double)(s >> 20) - oz;
-        double sn, cs;
-        sincos(-k * (nx * x + ny * y + nz * z), &sn, &cs);
+        // exp(-i k n . (r - o)) as the product of the three axis factors
+        const Cx<double> ph = (T[s & 1023] * T[g.n1 + ((s >> 10) & 1023)]) * T[n12 + (s >> 20)];
+        const double cs = ph.re, sn = ph.im;
         for (int c = 0; c < 3; ++c) {
             const Cx<double> p = P[((size_t)rhs * 3 + c) * g.Npad + j];
             acc[2 * c] += p.re * cs - p.im * sn;
@@ -887,7 +902,8 @@ int ampl_chunks(int ndir, int nrhs, int N) {
 hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const Cx<double>* P, int ndir,
                        const double* ndirs, Cx<double>* F, double* partials, hipStream_t st) {
     const int nc = ampl_chunks(ndir, nrhs, g.N);
-    hipLaunchKernelGGL(k_ampl, dim3(ndir, nrhs, nc), dim3(256), 0, st, g, o[0], o[1], o[2], k, P, ndirs, partials,
+    const size_t lds = (size_t)(g.n1 + g.n2 + g.n3) * sizeof(Cx<double>);  // at most 3 x 1023 entries
+    hipLaunchKernelGGL(k_ampl, dim3(ndir, nrhs, nc), dim3(256), lds, st, g, o[0], o[1], o[2], k, P, ndirs, partials,
                        ndir, nrhs);
     HIP_TRY(hipGetLastError());
     const int n = nrhs * ndir * 6;
