@@ -183,6 +183,22 @@ dda_status dda_build_green_fft(dda_ctx* ctx, uint32_t prec);
 dda_status dda_solve(dda_ctx* ctx, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* opts,
                      const void* p0, void* p_out, dda_solve_stats* stats);
 
+/*
+ * Solve A P = E_inc for nrhs caller-supplied incident fields (the linear
+ * system of the guide's section "The DDA" for any right-hand side, not only
+ * a plane wave).  e_inc is [nrhs][N][3] complex128 in the same site order and
+ * concatenation as p0 and p_out (host memory, or device memory with
+ * DDA_DEVICE_PTRS); it is read during the call only.  waves[i] still selects
+ * the target of rhs i and, through khat and e0, its polarizability (LDR
+ * depends on them; CM does not).  Everything else is as for dda_solve; the
+ * guesses that carry a previous solution to a new incidence direction
+ * (PREV_SHIFT, PROJECT, NN) assume plane waves.  dda_cross_sections after
+ * this call uses e_inc as E.  Errors: DDA_ERR_INVALID_ARG for a NULL e_inc,
+ * otherwise those of dda_solve.
+ */
+dda_status dda_solve_field(dda_ctx* ctx, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* opts,
+                           const void* e_inc, const void* p0, void* p_out, dda_solve_stats* stats);
+
 /* y = A x for nrhs vectors on target `target`.  ainv holds 1/alpha per
  * (rhs, composition) as 2*nrhs*ncomp doubles, or is NULL to use the
  * polarizability of the target's prescription with the wave khat=(1,0,0),

@@ -136,10 +136,13 @@ class Context:
 
     # -- solve -----------------------------------------------------------
     def solve(self, khat, e0, targets=None, tol=1e-5, max_iter=1000, guess=DDA_GUESS_ZERO,
-              prec=DDA_SOLVE_FP32_REFINE, p0=None, want_p=True, flags=0, graph_iters=0, history=0):
+              prec=DDA_SOLVE_FP32_REFINE, p0=None, want_p=True, flags=0, graph_iters=0, history=0, e_inc=None):
         """Solve A P = E_inc for each wave; returns (P or None, stats list, status).
 
-        P is a list of (N_t, 3) complex128 arrays (one per wave)."""
+        P is a list of (N_t, 3) complex128 arrays (one per wave).  With e_inc
+        (a list of (N_t, 3) complex128 fields, one per wave) the right-hand
+        sides are those fields (dda_solve_field); the waves then select the
+        targets and polarizabilities only."""
         arr, n = _waves(khat, e0, targets)
         opts = L.dda_solve_opts(tol=tol, max_iter=max_iter, guess=guess, prec=prec, flags=flags,
                                 graph_iters=graph_iters, history=history)
@@ -150,9 +153,18 @@ class Context:
             p0buf = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.complex128).reshape(-1) for p in p0]))
         pout = np.zeros(3 * sum(sizes), dtype=np.complex128) if want_p else None
         stats = (L.dda_solve_stats * n)()
-        st = self.lib.dda_solve(self.h, n, arr, C.byref(opts),
-                                None if p0buf is None else p0buf.ctypes.data,
-                                None if pout is None else pout.ctypes.data, stats)
+        if e_inc is None:
+            st = self.lib.dda_solve(self.h, n, arr, C.byref(opts),
+                                    None if p0buf is None else p0buf.ctypes.data,
+                                    None if pout is None else pout.ctypes.data, stats)
+        else:
+            ebuf = np.ascontiguousarray(np.concatenate([np.asarray(e, dtype=np.complex128).reshape(-1)
+                                                        for e in e_inc]))
+            if ebuf.size != 3 * sum(sizes):
+                raise ValueError("e_inc: one (N_t, 3) field per wave")
+            st = self.lib.dda_solve_field(self.h, n, arr, C.byref(opts), ebuf.ctypes.data,
+                                          None if p0buf is None else p0buf.ctypes.data,
+                                          None if pout is None else pout.ctypes.data, stats)
         _check(self.h, st)
         P = None
         if want_p:

@@ -1099,8 +1099,29 @@ dda_status dda_inverse_polarizability(const dda_ctx* c, int32_t target, const dd
     return DDA_OK;
 }
 
-dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* o, const void* p0,
-                     void* p_out, dda_solve_stats* stats) {
+namespace {
+
+// Rows of the right-hand sides of group g from an ABI buffer ([nrhs][N][3]
+// complex128 of all rhs of the call, each with its own target's N) into the
+// device layout `out` ([nr][3][Npad], zero padding).  `tmp` is staging.
+dda_status gather_abi_rows(dda_ctx* c, const Group& g, const Target& t, const dda_wave* waves, const void* src,
+                           bool devptr, DevMem& tmp, Cx<double>* out, hipStream_t st) {
+    const size_t per = (size_t)t.N * 3 * sizeof(Cx<double>);
+    HCHK(c, tmp.ensure(per * g.nr));
+    for (int s = 0; s < g.nr; ++s) {
+        size_t off = 0;
+        for (int q = 0; q < g.idx[s]; ++q) off += (size_t)c->tg[waves[q].target]->N * 3 * sizeof(Cx<double>);
+        HCHK(c, hipMemcpyAsync((char*)tmp.p + s * per, (const char*)src + off, per,
+                               devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    }
+    HCHK(c, launch_from_abi<double>(t.geo(), g.nr, tmp.as<Cx<double>>(), out, st));
+    HCHK(c, hipStreamSynchronize(st));  // the staging is reused by the next group
+    return DDA_OK;
+}
+
+// dda_solve and dda_solve_field: e_inc NULL generates the plane waves.
+dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* o, const void* e_inc,
+                      const void* p0, void* p_out, dda_solve_stats* stats) {
     SCHK(check_ctx(c));
     if (nrhs <= 0 || !waves || !o) return fail(c, DDA_ERR_INVALID_ARG, "solve: nrhs <= 0 or null waves/opts");
     if (c->tg.empty()) return fail(c, DDA_ERR_STATE, "solve before set_target");
@@ -1185,28 +1206,23 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
         HCHK(c, hipMemcpyAsync(g.waves.p, g.hw.data(), g.nr * sizeof(WaveDev), hipMemcpyHostToDevice, st));
         HCHK(c, hipMemcpyAsync(g.ainv64.p, g.hainv.data(), g.hainv.size() * sizeof(cd), hipMemcpyHostToDevice, st));
         HCHK(c, hipMemcpyAsync(g.ainv32.p, a32.data(), a32.size() * sizeof(Cx<float>), hipMemcpyHostToDevice, st));
-        HCHK(c, launch_einc<double>(t.geo(), t.origin, g.waves.as<WaveDev>(), g.nr, g.b64.as<Cx<double>>(), st));
+    }
+    // incident field: the plane waves, or the caller's field
+    DevMem dtmp;
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        Target& t = *c->tg[g.tgt];
+        if (e_inc) SCHK(gather_abi_rows(c, g, t, waves, e_inc, devptr, dtmp, g.b64.as<Cx<double>>(), st));
+        else HCHK(c, launch_einc<double>(t.geo(), t.origin, g.waves.as<WaveDev>(), g.nr, g.b64.as<Cx<double>>(), st));
     }
     // initial guess
-    DevMem dtmp;
     for (auto& gp : c->groups) {
         Group& g = *gp;
         Target& t = *c->tg[g.tgt];
         if (o->guess == DDA_GUESS_ZERO) {
             HCHK(c, launch_fill<double>(g.x64.as<Cx<double>>(), vec_elems(t, g.nr), st));
         } else if (o->guess == DDA_GUESS_USER) {
-            // gather this group's rows from the ABI buffer (rows of all rhs
-            // are concatenated, each with its own target's N)
-            const size_t per = (size_t)t.N * 3 * sizeof(Cx<double>);
-            HCHK(c, dtmp.ensure(per * g.nr));
-            for (int s = 0; s < g.nr; ++s) {
-                size_t off = 0;
-                for (int q = 0; q < g.idx[s]; ++q) off += (size_t)c->tg[waves[q].target]->N * 3 * sizeof(Cx<double>);
-                HCHK(c, hipMemcpyAsync((char*)dtmp.p + s * per, (const char*)p0 + off, per,
-                                       devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-            }
-            HCHK(c, launch_from_abi<double>(t.geo(), g.nr, dtmp.as<Cx<double>>(), g.x64.as<Cx<double>>(), st));
-            HCHK(c, hipStreamSynchronize(st));
+            SCHK(gather_abi_rows(c, g, t, waves, p0, devptr, dtmp, g.x64.as<Cx<double>>(), st));
         }
         // PREV, PREV_SHIFT, NN: x64 holds the previous solution here
     }
@@ -1456,6 +1472,19 @@ dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_
         return DDA_WARN_NOT_CONVERGED;
     }
     return DDA_OK;
+}
+
+}  // namespace
+
+dda_status dda_solve(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* o, const void* p0,
+                     void* p_out, dda_solve_stats* stats) {
+    return solve_impl(c, nrhs, waves, o, nullptr, p0, p_out, stats);
+}
+
+dda_status dda_solve_field(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* o,
+                           const void* e_inc, const void* p0, void* p_out, dda_solve_stats* stats) {
+    if (c && !e_inc) return fail(c, DDA_ERR_INVALID_ARG, "solve_field: null e_inc");
+    return solve_impl(c, nrhs, waves, o, e_inc, p0, p_out, stats);
 }
 
 dda_status dda_matvec(dda_ctx* c, int32_t target, int32_t nrhs, const double* ainv, const void* x, void* y,
