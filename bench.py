@@ -548,7 +548,34 @@ def cpu_baseline(occ, kd, m, stats, seconds):
         "sample": f"direct O(N^2) FP64 matvec on {nrows} of {n} rows ({t_rows:.1f} s wall), extrapolated to "
                   f"{n} rows x {mv_per_solve:.0f} matvecs per solve",
         "matvec_s_extrapolated": round(t_matvec, 3),
+        "fft_host": fft_host_baseline(r, kd, ainv, x, mv_per_solve, dda.threads()),
     }
+
+
+def fft_host_baseline(r, kd, ainv, x, mv_per_solve, workers, reps=3):
+    """The FFT method on the host cores (numpy/scipy FFTs on the doubled grid,
+    not the oracle): full-size matvecs in complex64 and complex128 after one
+    warm-up, extrapolated to the GPU solve's matvec count."""
+    from oracle import fft_baseline
+
+    out = {"kind": "host FFT-DDA (numpy/scipy FFT, BiCGstab matvec count of the GPU solve), not the oracle",
+           "workers": workers}
+    for name, dt in (("c64", np.complex64), ("c128", np.complex128)):
+        t0 = time.perf_counter()
+        F = fft_baseline.FftDda(r, kd, ainv, dtype=dt, workers=workers)
+        setup = time.perf_counter() - t0
+        F.matvec(x)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            F.matvec(x)
+        tm = (time.perf_counter() - t0) / reps
+        out["grid"] = list(F.M)
+        out[name] = {"setup_s": round(setup, 2), "matvec_s": round(tm, 4),
+                     "solves_per_s": round(1.0 / (tm * mv_per_solve), 5)}
+        del F
+    out["sample"] = (f"{reps} full-size matvecs per precision after one warm-up, extrapolated to "
+                     f"{mv_per_solve:.0f} matvecs per solve")
+    return out
 
 
 if __name__ == "__main__":
