@@ -85,7 +85,7 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {a.gpus} is not supported "
               "(the right-hand sides would shard across GPUs with no communication inside a solve)",
               file=sys.stderr)
         sys.exit(2)

@@ -3,8 +3,8 @@
 A plain FP64 numpy version of the small 3D convolutional network the GPU
 library trains and runs: 3x3x3 convolutions with zero padding and dilation,
 ReLU, a masked squared-error loss, and Adam.  The guide itself has no learned
-component; the network is this build's predictor of the Krylov initial guess
-(the guide's default guess is P = 0, "Choice of Iterative Algorithm").
+component; the network is the library's predictor of the Krylov initial
+guess (the guide's default guess is P = 0, "Choice of Iterative Algorithm").
 
 Layout: activations are channels-last arrays x[z, y, x, c]; a weight tensor
 is w[o, ci, co] with the 27 offsets o = (dz+1)*9 + (dy+1)*3 + (dx+1),
