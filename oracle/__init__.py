@@ -4,7 +4,10 @@ A plain, slow, obviously-correct double-precision implementation of what the
 GPU library computes: lattice sites, frames, incident field, polarizabilities,
 the dense interaction matrix (LU solve), a direct O(N^2) matvec (C + OpenMP)
 inside the oracle's own BiCGstab, cross sections, scattering amplitudes,
-Mueller matrix, angular quadrature, and Mie theory for spheres.
+Mueller matrix, angular quadrature, orientation sampling and averaging, and
+Mie theory for spheres.  ``fft_baseline`` is not part of the oracle proper:
+it applies the same operator through host FFTs, only to time the FFT method
+on the CPU beside the GPU (pinned to the direct matvec in tests).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product (``paper_1002_1505_amd``)
