@@ -105,3 +105,75 @@ def test_solve_field_rejects_a_missing_field(ctx):
     opts = L.dda_solve_opts(tol=1e-5, max_iter=100, guess=P.DDA_GUESS_ZERO, prec=P.DDA_SOLVE_FP64)
     st = ctx.lib.dda_solve_field(ctx.h, 1, arr, C.byref(opts), None, None, None, None)
     assert st == L.DDA_ERR_INVALID_ARG
+
+
+class _DeviceBuffer:
+    """Device memory from the HIP runtime the library itself uses (the
+    library's soname, so the process has one runtime)."""
+
+    def __init__(self, nbytes):
+        import ctypes as C
+
+        from paper_1002_1505_amd import _lib as L
+
+        L.load()
+        self.hip = C.CDLL("libamdhip64.so.7")
+        self.n = nbytes
+        self.p = C.c_void_p()
+        assert self.hip.hipMalloc(C.byref(self.p), C.c_size_t(nbytes)) == 0
+
+    def upload(self, a):
+        import ctypes as C
+
+        a = np.ascontiguousarray(a)
+        assert a.nbytes == self.n
+        assert self.hip.hipMemcpy(self.p, C.c_void_p(a.ctypes.data), C.c_size_t(self.n), 1) == 0  # host to device
+
+    def download(self, dtype):
+        import ctypes as C
+
+        out = np.empty(self.n // np.dtype(dtype).itemsize, dtype=dtype)
+        assert self.hip.hipMemcpy(C.c_void_p(out.ctypes.data), self.p, C.c_size_t(self.n), 2) == 0  # device to host
+        return out
+
+    def free(self):
+        self.hip.hipFree(self.p)
+
+
+def test_device_pointer_buffers_match_host_buffers(ctx):
+    """DDA_DEVICE_PTRS: the caller's field, guess and solution as device
+    buffers give the same bits as host buffers."""
+    import ctypes as C
+
+    import paper_1002_1505_amd as P
+    from paper_1002_1505_amd import _lib as L
+
+    r, comp, m, kd = _target(ctx, dda.ALPHA_LDR)
+    kh, es, L_ = dda.waves_for_orientation(0.6, 2.1, 1.4)
+    rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 23)
+    E = [rng.standard_normal((len(r), 3)) + 1j * rng.standard_normal((len(r), 3)) for _ in range(2)]
+    Ph, sh, _ = ctx.solve([kh, kh], es, prec=P.DDA_SOLVE_FP64, tol=1e-10, e_inc=E)
+    eh = np.ascontiguousarray(np.concatenate([e.reshape(-1) for e in E]))
+    e_d, p_d, g_d, p2 = (_DeviceBuffer(eh.nbytes) for _ in range(4))
+    try:
+        e_d.upload(eh)
+        arr, n = P._waves([kh, kh], es, None)
+        stats = (L.dda_solve_stats * 2)()
+        opts = L.dda_solve_opts(tol=1e-10, max_iter=1000, guess=P.DDA_GUESS_ZERO, prec=P.DDA_SOLVE_FP64,
+                                flags=L.DDA_DEVICE_PTRS)
+        st = ctx.lib.dda_solve_field(ctx.h, 2, arr, C.byref(opts), e_d.p, None, p_d.p, stats)
+        assert st == 0, ctx.last_error()
+        Pd = p_d.download(np.complex128).reshape(2, len(r), 3)
+        for l in range(2):
+            assert stats[l].iters == sh[l]["iters"]
+            assert np.array_equal(Pd[l], Ph[l]), l
+        # the solution itself as a device guess: converged before any iteration
+        g_d.upload(Pd)
+        opts.guess = P.DDA_GUESS_USER
+        st = ctx.lib.dda_solve_field(ctx.h, 2, arr, C.byref(opts), e_d.p, g_d.p, p2.p, stats)
+        assert st == 0, ctx.last_error()
+        assert all(stats[l].iters == 0 for l in range(2))
+        assert np.array_equal(p2.download(np.complex128).reshape(2, len(r), 3), Pd)
+    finally:
+        for b in (e_d, p_d, g_d, p2):
+            b.free()
