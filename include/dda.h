@@ -277,6 +277,21 @@ dda_status dda_amplitudes(dda_ctx* ctx, int32_t nrhs, int32_t ndir, const double
 dda_status dda_mueller(int32_t ndir, const double* f, const double* phi, const double* e01,
                        const double* e02, double* S, double* mueller);
 
+/* Polarized differential scattering cross sections and the degree of linear
+ * polarization from the Mueller matrix (guide, "Polarization Properties of
+ * the Scattered Radiation": an ideal linear polarizer parallel or
+ * perpendicular to the scattering plane applied to the scattered Stokes
+ * vector; "Relation Between Mueller Matrix and Scattering Cross Sections":
+ * I_s r^2 = (dC_sca/dOmega) I_i).  mu: ndir x 16 Mueller elements S_ij,
+ * row-major as dda_mueller writes them; k: wavenumber in units of 1/d;
+ * stokes_in: the incident Stokes vector (I, Q, U, V) with I > 0 (results
+ * are per unit incident intensity).  out: ndir x 4 doubles = dC_sca/dOmega
+ * of the scattered light polarized parallel to the scattering plane,
+ * perpendicular to it, in total, and P = (S21^2 + S31^2)^(1/2) / S11, the
+ * linear polarization for unpolarized incidence (0 where S11 = 0).  Host
+ * only.  DDA_ERR_INVALID_ARG for ndir <= 0, NULL pointers, k <= 0 or I <= 0. */
+dda_status dda_polarization(int32_t ndir, const double* mu, double k, const double* stokes_in, double* out);
+
 /* Lab-frame axes in the target frame for target orientation (beta, Theta,
  * Phi) in radians and target axes a1, a2 (target frame; NULL for x and y)
  * (guide, section "Orientation of the Target in the Lab Frame").

@@ -103,6 +103,26 @@ def linear_polarization(M):
     return np.sqrt(M[..., 1, 0] ** 2 + M[..., 2, 0] ** 2) / M[..., 0, 0]
 
 
+def polarized_cross_sections(M, k, stokes_in):
+    """dC_sca/dOmega of the scattered light that an ideal linear polarizer
+    passes parallel (xi = 0) and perpendicular (xi = pi/2) to the scattering
+    plane, and in total, per unit incident intensity (guide, "Polarization
+    Properties of the Scattered Radiation": the polarizer's Mueller matrix
+    applied to the scattered Stokes vector, which is M s_i / (k r)^2; and
+    I_s r^2 = (dC_sca/dOmega) I_i, "Relation Between Mueller Matrix and
+    Scattering Cross Sections").  M: (..., 4, 4); stokes_in: (I, Q, U, V)
+    with I > 0.  Returns (..., 3): parallel, perpendicular, total."""
+    s = np.asarray(stokes_in, dtype=np.float64)
+    s = s / s[0]
+    scat = np.einsum("...ij,j->...i", np.asarray(M, dtype=np.float64), s) / k ** 2  # r^2 I_s, Q_s, ... per I_i
+    out = np.empty(scat.shape[:-1] + (3,))
+    for n, xi in enumerate((0.0, np.pi / 2)):
+        c2, s2 = np.cos(2 * xi), np.sin(2 * xi)
+        out[..., n] = 0.5 * (scat[..., 0] + c2 * scat[..., 1] + s2 * scat[..., 2])
+    out[..., 2] = scat[..., 0]
+    return out
+
+
 def scattering_theta_grid(x, eta):
     """theta_j (j = 1..N_theta) from the s(theta) = theta + theta/(theta+theta0)
     prescription with theta0 = 2 pi / (1 + x) ("Selection of Scattering

@@ -352,6 +352,21 @@ def scattering_frame(theta, phi, lab_axes):
     return n, e
 
 
+def polarization(mueller, k, stokes_in=(1.0, 0.0, 0.0, 0.0)):
+    """(ndir, 4): dC_sca/dOmega parallel and perpendicular to the scattering
+    plane and in total for the incident Stokes vector, and the linear
+    polarization P for unpolarized incidence (dda_polarization); mueller is
+    (ndir, 4, 4) as returned by mueller()."""
+    lib = L.load()
+    mu = np.ascontiguousarray(np.asarray(mueller, dtype=np.float64).reshape(-1, 16))
+    s = np.ascontiguousarray(np.asarray(stokes_in, dtype=np.float64).reshape(4))
+    out = np.zeros((len(mu), 4))
+    st = lib.dda_polarization(len(mu), _dptr(mu), float(k), _dptr(s), _dptr(out))
+    if st != 0:
+        raise DDAError(st, "dda_polarization: bad arguments")
+    return out
+
+
 def mueller(f, phi, e01, e02):
     """S_1..S_4 (ndir, 4) and Mueller (ndir, 4, 4) from f[dir, m, l]."""
     lib = L.load()

@@ -1796,6 +1796,24 @@ dda_status dda_mueller(int32_t ndir, const double* f, const double* phi, const d
     return DDA_OK;
 }
 
+dda_status dda_polarization(int32_t ndir, const double* mu, double k, const double* stokes_in, double* out) {
+    if (ndir <= 0 || !mu || !stokes_in || !out || !(k > 0) || !(stokes_in[0] > 0)) return DDA_ERR_INVALID_ARG;
+    const double q = stokes_in[1] / stokes_in[0], u = stokes_in[2] / stokes_in[0], v = stokes_in[3] / stokes_in[0];
+    const double k2 = k * k;
+    for (int d = 0; d < ndir; ++d) {
+        const double* M = mu + (size_t)d * 16;
+        // scattered I and Q times r^2 per unit incident intensity
+        const double is = (M[0] + M[1] * q + M[2] * u + M[3] * v) / k2;
+        const double qs = (M[4] + M[5] * q + M[6] * u + M[7] * v) / k2;
+        double* o = out + (size_t)d * 4;
+        o[0] = 0.5 * (is + qs);  // polarizer parallel to the scattering plane
+        o[1] = 0.5 * (is - qs);  // perpendicular to it
+        o[2] = is;
+        o[3] = M[0] > 0 ? std::sqrt(M[4] * M[4] + M[8] * M[8]) / M[0] : 0.0;
+    }
+    return DDA_OK;
+}
+
 dda_status dda_lab_frame(double beta, double theta, double phi, const double* a1in, const double* a2in, double* out) {
     if (!out) return DDA_ERR_INVALID_ARG;
     double a1[3] = {1, 0, 0}, a2[3] = {0, 1, 0};

@@ -126,3 +126,26 @@ def test_scattering_quadrature_without_gpu():
         assert abs(w.sum() - 4 * np.pi) < 0.05
     with pytest.raises(P.DDAError):
         P.scattering_quadrature(-1.0, 0.5, L)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdda.so not built")
+def test_polarization_without_gpu():
+    """dda_polarization (host arithmetic) against the oracle's polarized cross
+    sections and linear polarization, for random amplitude matrices and
+    incident states; bad arguments are rejected."""
+    import numpy as np
+
+    import paper_1002_1505_amd as P
+    from oracle import scatter
+
+    rng = np.random.default_rng(11)
+    S = rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4))
+    M = scatter.mueller(S)
+    k = 0.61
+    for stokes in ([1, 0, 0, 0], [1, 1, 0, 0], [1, -1, 0, 0], [2.0, 0.4, -1.1, 0.9], [1, 0, 0, -1]):
+        got = P.polarization(M, k, stokes)
+        assert np.allclose(got[:, :3], scatter.polarized_cross_sections(M, k, stokes), rtol=1e-12, atol=1e-15)
+        assert np.allclose(got[:, 3], scatter.linear_polarization(M), rtol=1e-12)
+    for bad in (dict(k=0.0), dict(stokes_in=[0, 1, 0, 0])):
+        with pytest.raises(P.DDAError):
+            P.polarization(M, bad.get("k", k), bad.get("stokes_in", [1, 0, 0, 0]))
