@@ -267,6 +267,24 @@ dda_status dda_cross_sections_phi(dda_ctx* ctx, int32_t npairs, int32_t ncomb, c
 dda_status dda_amplitudes(dda_ctx* ctx, int32_t nrhs, int32_t ndir, const double* n_tf,
                           const double* e_tf, double* f);
 
+/* Total E and B at npts points in or near the targets of the last solve
+ * (guide, "Postprocessing: Calculating E and B In or Near the Target"): the
+ * incident plane wave (B_inc = khat x E_inc) plus the retarded field of
+ * every dipole, E = exp(ikR)[k^2/R (p - n(n.p)) + (1/R^3 - ik/R^2)(3n(n.p) - p)]
+ * and B = exp(ikR)(k^2/R + ik/R^2)(n x p) for a dipole p at R = R n from the
+ * point (Gaussian units, exp(-i omega t)).  A point on an occupied site takes
+ * no contribution from that site, so there E is the site's local field
+ * (1/alpha) P.  The guide's smoothing of contributions from dipoles closer
+ * than d (a factor from a paper it cites but does not print) is not applied:
+ * the bare dipole sum is evaluated everywhere.  pts: npts x 3 doubles, target
+ * frame, units of d, from the same origin as the sites (dda_set_target's
+ * origin, by default the centroid); every rhs of the last solve is evaluated
+ * in its own target's frame.  E: nrhs x npts x 3 complex128 (interleaved);
+ * B: the same, or NULL.  FP64 on the device, O(npts x N) per rhs.  Errors:
+ * DDA_ERR_STATE before a solve, DDA_ERR_INVALID_ARG for nrhs other than the
+ * last solve's, npts <= 0 or NULL pts or E. */
+dda_status dda_near_field(dda_ctx* ctx, int32_t nrhs, int32_t npts, const double* pts, double* E, double* B);
+
 /* Amplitude matrix S_1..S_4 and the 4x4 Mueller matrix from the amplitudes
  * of two orthogonal incident polarizations (guide, eqs. S_1_relto_f21andf22
  * and the bilinears of "Relation Between Stokes Parameters of Incident and

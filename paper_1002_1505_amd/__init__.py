@@ -228,6 +228,23 @@ class Context:
         f = f.reshape(nrhs, ndir, 2, 2)
         return f[..., 0] + 1j * f[..., 1]
 
+    def near_field(self, nrhs: int, points, want_b=True):
+        """Total E (and B) at points (npts, 3) in the target frame, lattice
+        units from the target origin, for every rhs of the last solve
+        (dda_near_field); returns (E, B) of shape (nrhs, npts, 3) complex."""
+        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
+        n = len(pts)
+        E = np.zeros(nrhs * n * 6)
+        B = np.zeros(nrhs * n * 6) if want_b else None
+        _check(self.h, self.lib.dda_near_field(self.h, int(nrhs), n, _dptr(pts), _dptr(E),
+                                               None if B is None else _dptr(B)))
+        E = E.reshape(nrhs, n, 3, 2)
+        E = E[..., 0] + 1j * E[..., 1]
+        if B is not None:
+            B = B.reshape(nrhs, n, 3, 2)
+            B = B[..., 0] + 1j * B[..., 1]
+        return E, B
+
     def last_timing(self):
         a, b, t, g = C.c_double(), C.c_double(), C.c_double(), C.c_double()
         self.lib.dda_last_timing(self.h, C.byref(a), C.byref(b), C.byref(t))

@@ -1751,6 +1751,37 @@ dda_status dda_amplitudes(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* 
     return DDA_OK;
 }
 
+dda_status dda_near_field(dda_ctx* c, int32_t nrhs, int32_t npts, const double* pts, double* E, double* B) {
+    SCHK(check_ctx(c));
+    if (!c->have_solution) return fail(c, DDA_ERR_STATE, "near_field before a solve");
+    if (nrhs != c->last_nrhs || npts <= 0 || !pts || !E)
+        return fail(c, DDA_ERR_INVALID_ARG, "near_field: bad arguments (nrhs must match the last solve)");
+    hipStream_t st = c->stream;
+    DevMem &dq = c->scr[0], &dout = c->scr[1];
+    HCHK(c, dq.ensure((size_t)npts * 3 * sizeof(double)));
+    HCHK(c, hipMemcpyAsync(dq.p, pts, (size_t)npts * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        const Target& t = *c->tg[g.tgt];
+        const size_t per = (size_t)npts * 12;
+        HCHK(c, dout.ensure(per * g.nr * sizeof(double)));
+        HCHK(c, launch_near_field(t.geo(), t.origin, g.nr, g.x64.as<Cx<double>>(), g.waves.as<WaveDev>(),
+                                  dq.as<double>(), npts, dout.as<double>(), st));
+        std::vector<double> h(per * g.nr);
+        HCHK(c, hipMemcpyAsync(h.data(), dout.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HCHK(c, hipStreamSynchronize(st));
+        for (int s = 0; s < g.nr; ++s) {
+            const size_t dst = (size_t)g.idx[s] * npts * 6;
+            for (int q = 0; q < npts; ++q)
+                for (int v = 0; v < 6; ++v) {
+                    E[dst + (size_t)q * 6 + v] = h[((size_t)s * npts + q) * 12 + v];
+                    if (B) B[dst + (size_t)q * 6 + v] = h[((size_t)s * npts + q) * 12 + 6 + v];
+                }
+        }
+    }
+    return DDA_OK;
+}
+
 dda_status dda_mueller(int32_t ndir, const double* f, const double* phi, const double* e01, const double* e02,
                        double* S, double* mu) {
     if (ndir <= 0 || !f || !phi || !e01 || !e02) return DDA_ERR_INVALID_ARG;

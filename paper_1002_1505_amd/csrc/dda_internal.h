@@ -212,6 +212,10 @@ hipError_t launch_xsec_pair(const Geo& g, int npairs, const Cx<double>* E, const
 // Site chunks per (direction, rhs) of the amplitude sums; partials holds
 // ampl_chunks * nrhs * ndir * 6 doubles.
 int ampl_chunks(int ndir, int nrhs, int N);
+// E and B at npts points (TF, lattice units from the origin o) for nrhs
+// solutions P ([nrhs][3][Npad]) and their waves; out [nrhs][npts][12].
+hipError_t launch_near_field(const Geo& g, const double* o, int nrhs, const Cx<double>* P, const WaveDev* w,
+                             const double* pts, int npts, double* out, hipStream_t st);
 hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const Cx<double>* P, int ndir,
                        const double* ndirs, Cx<double>* F, double* partials, hipStream_t st);
 

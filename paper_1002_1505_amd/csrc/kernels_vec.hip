@@ -601,6 +601,70 @@ __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, doubl
         for (int q = 0; q < 6; ++q) partials[(((size_t)chunk * nrhs + rhs) * ndir + dir) * 6 + q] = acc[q];
 }
 
+// Total E and B at points (FP64): the incident wave plus the retarded field
+// of every dipole (guide, "Postprocessing: Calculating E and B In or Near the
+// Target"); for a dipole p at R = R n from the point, Gaussian units,
+//   E = exp(ikR) [k^2/R (p - n (n.p)) + (1/R^3 - ik/R^2) (3 n (n.p) - p)],
+//   B = exp(ikR) (k^2/R + ik/R^2) (n x p),
+// and the plane wave's B = khat x E_inc.  A point on a site takes no
+// contribution from that site.  Block (point, rhs) sums the sites;
+// out[(rhs * npts + pt) * 12]: E then B, (re, im) per component.
+__global__ void __launch_bounds__(256) k_near_field(Geo g, double ox, double oy, double oz,
+                                                    const Cx<double>* __restrict__ P,
+                                                    const WaveDev* __restrict__ w, const double* __restrict__ pts,
+                                                    int npts, double* __restrict__ out) {
+    __shared__ double sh[12 * 4];
+    const int pt = blockIdx.x, rhs = blockIdx.y;
+    const double k = w[rhs].k;
+    const double qx = pts[3 * pt], qy = pts[3 * pt + 1], qz = pts[3 * pt + 2];
+    double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const Cx<double>* Pr = P + (size_t)rhs * 3 * g.Npad;
+    for (int j = threadIdx.x; j < g.N; j += blockDim.x) {
+        const uint32_t s = g.site_xyz[j];
+        const double Rx = qx - ((double)(s & 1023) - ox), Ry = qy - ((double)((s >> 10) & 1023) - oy);
+        const double Rz = qz - ((double)(s >> 20) - oz);
+        const double R2 = Rx * Rx + Ry * Ry + Rz * Rz;
+        if (!(R2 > 1e-18)) continue;  // the point is this site
+        const double R = sqrt(R2), iR = 1.0 / R;
+        const double n[3] = {Rx * iR, Ry * iR, Rz * iR};
+        const Cx<double> p[3] = {Pr[j], Pr[g.Npad + j], Pr[2 * g.Npad + j]};
+        double sn, cs;
+        sincos(k * R, &sn, &cs);
+        const Cx<double> ph = {cs, sn};
+        const Cx<double> np = n[0] * p[0] + n[1] * p[1] + n[2] * p[2];
+        const double a = k * k * iR;
+        const Cx<double> b = {iR * iR * iR, -k * iR * iR};       // 1/R^3 - ik/R^2
+        const Cx<double> cb = ph * Cx<double>{a, k * iR * iR};  // exp(ikR) (k^2/R + ik/R^2)
+        const Cx<double> nxp[3] = {n[1] * p[2] - n[2] * p[1], n[2] * p[0] - n[0] * p[2], n[0] * p[1] - n[1] * p[0]};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const Cx<double> e = ph * (a * (p[c] - n[c] * np) + b * ((3.0 * n[c]) * np - p[c]));
+            const Cx<double> bb = cb * nxp[c];
+            acc[2 * c] += e.re;
+            acc[2 * c + 1] += e.im;
+            acc[6 + 2 * c] += bb.re;
+            acc[6 + 2 * c + 1] += bb.im;
+        }
+    }
+    block_sum_n<12>(acc, sh);
+    if (threadIdx.x != 0) return;
+    const WaveDev wv = w[rhs];
+    double sn, cs;
+    sincos(k * (wv.khat[0] * qx + wv.khat[1] * qy + wv.khat[2] * qz), &sn, &cs);
+    const Cx<double> ph = {cs, sn};
+    Cx<double> ei[3];
+    for (int c = 0; c < 3; ++c) ei[c] = Cx<double>{wv.e[2 * c], wv.e[2 * c + 1]} * ph;
+    const double* kh = wv.khat;
+    const Cx<double> bi[3] = {kh[1] * ei[2] - kh[2] * ei[1], kh[2] * ei[0] - kh[0] * ei[2], kh[0] * ei[1] - kh[1] * ei[0]};
+    double* o = out + ((size_t)rhs * npts + pt) * 12;
+    for (int c = 0; c < 3; ++c) {
+        o[2 * c] = acc[2 * c] + ei[c].re;
+        o[2 * c + 1] = acc[2 * c + 1] + ei[c].im;
+        o[6 + 2 * c] = acc[6 + 2 * c] + bi[c].re;
+        o[6 + 2 * c + 1] = acc[6 + 2 * c + 1] + bi[c].im;
+    }
+}
+
 __global__ void k_ampl_reduce(const double* __restrict__ partials, int nchunk, int n, double* __restrict__ F) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -898,6 +962,11 @@ hipError_t launch_xsec_pair(const Geo& g, int npairs, const Cx<double>* E, const
 int ampl_chunks(int ndir, int nrhs, int N) {
     const int want = (2048 + ndir * nrhs - 1) / (ndir * nrhs);
     return std::max(1, std::min({64, want, (N + 1023) / 1024}));
+}
+hipError_t launch_near_field(const Geo& g, const double* o, int nrhs, const Cx<double>* P, const WaveDev* w,
+                             const double* pts, int npts, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_near_field, dim3(npts, nrhs), dim3(256), 0, st, g, o[0], o[1], o[2], P, w, pts, npts, out);
+    return hipGetLastError();
 }
 hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const Cx<double>* P, int ndir,
                        const double* ndirs, Cx<double>* F, double* partials, hipStream_t st) {
