@@ -162,6 +162,17 @@ def main():
     mom = ctx.scattering_moments(2, n_q, w_q)
     torch.cuda.synchronize()
     ms_mom = 1e3 * (time.perf_counter() - t2)
+    # E and B along a 481-point track through the centre of the sphere,
+    # from 1.5 radii before it to 1.5 radii after (outside the timed region)
+    track = np.linspace([-1.5 * n / 2, 0.25, 0.25], [1.5 * n / 2, 0.25, 0.25], 481)
+    ctx.near_field(2, track)  # warm-up
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    Enf, Bnf = ctx.near_field(2, track)
+    torch.cuda.synchronize()
+    ms_nf = 1e3 * (time.perf_counter() - t2)
+    e2 = np.sum(np.abs(Enf) ** 2, axis=-1).mean(axis=0)  # |E|^2, mean of the two polarizations
+    inside = np.abs(track[:, 0]) < 0.95 * n / 2
     # per-pass matvec roofline (FP32, the solve's launch shapes, both rhs)
     ms, by = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP32, reps=20)
     sh = ctx.get_shape(0, P.DDA_FP32)
@@ -243,6 +254,14 @@ def main():
             "per_pol": [{"Qpha": round(float(mm["Qpha"]), 6), "Qbk": round(float(mm["Qbk"]), 6),
                          "Qsca_quad": round(float(mm["Qsca_quad"]), 6), "cos": round(float(mm["cos"]), 6),
                          "cos2": round(float(mm["cos2"]), 6)} for mm in mom],
+        },
+        "near_field": {
+            "points": int(len(track)),
+            "track": "x from -1.5 to +1.5 sphere radii at y = z = 0.25, lattice units from the centroid",
+            "ms": round(ms_nf, 3),
+            "site_fields_per_s": round(2 * len(track) * N / (ms_nf * 1e-3), 1),
+            "mean_E2_inside": round(float(e2[inside].mean()), 5),
+            "mean_E2_outside": round(float(e2[~inside].mean()), 5),
         },
         "setup_s": round(setup_s, 3),
     }
