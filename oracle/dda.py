@@ -318,6 +318,46 @@ def bicgstab(matvec, b, x0=None, tol=1e-10, max_iter=10000):
     return x, {"iters": it, "matvecs": nmv, "rel_resid": float(np.linalg.norm(r_true) / nb)}
 
 
+def cocg(matvec, b, x0=None, tol=1e-10, max_iter=10000, keep_residuals=False):
+    """Conjugate orthogonal conjugate gradients for a complex symmetric
+    A = A^T (the DDA matrix is one: A_jl = A_lj^T, and its diagonal is
+    symmetric): CG with the bilinear form x^T y in place of x^H y (van der
+    Vorst & Melissen 1990; the guide lists the complex-symmetric QMR family
+    among the PIM methods, "Choice of Iterative Algorithm").  One matvec per
+    iteration.  Stops when ||b - A x|| / ||b|| <= tol (residual recomputed at
+    the end).  Returns (x, info) with info = {iters, matvecs, rel_resid}, and
+    info["residuals"] (the recursive residuals) if keep_residuals."""
+    b = np.asarray(b, dtype=np.complex128).reshape(-1)
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.complex128).reshape(-1).copy()
+    nb = np.linalg.norm(b)
+    if nb == 0:
+        return x, {"iters": 0, "matvecs": 0, "rel_resid": 0.0}
+    r = b - matvec(x)
+    nmv = 1
+    p = r.copy()
+    rho = r @ r
+    res = [r.copy()] if keep_residuals else None
+    it = 0
+    while np.linalg.norm(r) / nb > tol and it < max_iter:
+        q = matvec(p)
+        nmv += 1
+        alpha = rho / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        rho_new = r @ r
+        p = r + (rho_new / rho) * p
+        rho = rho_new
+        it += 1
+        if keep_residuals:
+            res.append(r.copy())
+    r_true = b - matvec(x)
+    nmv += 1
+    info = {"iters": it, "matvecs": nmv, "rel_resid": float(np.linalg.norm(r_true) / nb)}
+    if keep_residuals:
+        info["residuals"] = res
+    return x, info
+
+
 def solve_iterative(r, k, ainv, E, tol=1e-10, x0=None, max_iter=10000):
     """P from BiCGstab over the direct matvec; E, P are (N, 3)."""
     n = len(r)
