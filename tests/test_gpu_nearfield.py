@@ -75,3 +75,28 @@ def test_local_field_identity_at_bench_size(ctx):
         a = ctx.inverse_polarizability(kh[l], e0[l])  # (Re, Im) per composition
         want = (a[0] + 1j * a[1]) * Pl[l][sel]
         assert _rel(E[l], want) < 1e-4, l
+
+
+def test_two_targets_in_one_call(ctx):
+    """A solve over two targets (one rhs each) with caller fields, then the
+    near field of both: each rhs equals the single-target call, each target
+    in its own frame (origin at its own centroid)."""
+    import paper_1002_1505_amd as P
+
+    occs = [synth.ellipsoid_occupancy((8, 6, 5), (7.6, 5.5, 4.6)), synth.sphere_occupancy(8)]
+    ms, ks = [1.6 + 0.2j, 1.4 + 0.05j], [0.5, 0.4]
+    kh, es, L = dda.waves_for_orientation(0.2, 0.7, 1.1)
+    rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 37)
+    sites = [dda.sites_from_occupancy(o)[0] for o in occs]
+    E = [rng.standard_normal((len(r), 3)) + 1j * rng.standard_normal((len(r), 3)) for r in sites]
+    pts = rng.uniform(-7, 7, size=(12, 3))
+    ctx.set_target(occs[0], [ms[0]], ks[0], P.DDA_ALPHA_LDR)
+    ctx.add_target(occs[1], [ms[1]], ks[1], P.DDA_ALPHA_LDR)
+    Pb, sb, _ = ctx.solve([kh, kh], [es[0], es[1]], targets=[0, 1], prec=P.DDA_SOLVE_FP64, tol=1e-11, e_inc=E)
+    Eb, Bb = ctx.near_field(2, pts)
+    for t in range(2):
+        ctx.set_target(occs[t], [ms[t]], ks[t], P.DDA_ALPHA_LDR)
+        Ps, ss, _ = ctx.solve([kh], [es[t]], prec=P.DDA_SOLVE_FP64, tol=1e-11, e_inc=[E[t]])
+        Es, Bs = ctx.near_field(1, pts)
+        assert _rel(Pb[t], Ps[0]) < 1e-9, t
+        assert _rel(Eb[t], Es[0]) < 1e-9 and _rel(Bb[t], Bs[0]) < 1e-9, t
