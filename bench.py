@@ -568,6 +568,31 @@ def cpu_baseline(occ, kd, m, stats, seconds):
                   f"{n} rows x {mv_per_solve:.0f} matvecs per solve",
         "matvec_s_extrapolated": round(t_matvec, 3),
         "fft_host": fft_host_baseline(r, kd, ainv, x, mv_per_solve, dda.threads()),
+        "other_sizes": oracle_sizes(t_rows / (nrows * n), mv_per_solve),
+    }
+
+
+def oracle_sizes(s_per_pair, mv_per_solve):
+    """The oracle at the other sizes: the dense LU solve of the 16-diameter
+    sphere (N = 2,176) timed in full, and the direct matvec of the 128^3
+    sphere extrapolated from the per-pair cost measured above."""
+    import synth
+    from oracle import dda
+
+    occ = synth.sphere_occupancy(16)
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    kd = 4.0 / dda.effective_radius(len(r))
+    ainv = dda.site_inverse_polarizability(comp, [1.5 + 0.1j], kd, dda.ALPHA_LDR, np.array([1.0, 0, 0]),
+                                           np.array([0, 1.0, 0]))
+    E = dda.incident_field(r, kd, np.array([1.0, 0, 0]), np.array([0, 1.0, 0]))
+    t0 = time.perf_counter()
+    dda.solve_dense(r, kd, ainv, E)
+    t_lu = time.perf_counter() - t0
+    n4 = int(synth.sphere_occupancy(128).sum())
+    return {
+        "dense_lu_sphere16": {"sites": len(r), "s_per_solve": round(t_lu, 3)},
+        "direct_sphere128_extrapolated": {"sites": n4, "matvec_s": round(s_per_pair * n4 * n4, 1),
+                                          "s_per_solve": round(s_per_pair * n4 * n4 * mv_per_solve, 0)},
     }
 
 
