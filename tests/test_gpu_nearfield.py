@@ -100,3 +100,27 @@ def test_two_targets_in_one_call(ctx):
         Es, Bs = ctx.near_field(1, pts)
         assert _rel(Pb[t], Ps[0]) < 1e-9, t
         assert _rel(Eb[t], Es[0]) < 1e-9 and _rel(Bb[t], Bs[0]) < 1e-9, t
+
+
+def test_near_field_errors():
+    import ctypes as C
+
+    import paper_1002_1505_amd as P
+    from paper_1002_1505_amd import _lib as L
+
+    c = P.Context(0)
+    try:
+        c.set_target(synth.sphere_occupancy(6), [1.5 + 0.1j], 0.4)
+        E = np.zeros(12)
+        pts = np.zeros(3)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        assert c.lib.dda_near_field(c.h, 1, 1, dp(pts), dp(E), None) == L.DDA_ERR_STATE  # before a solve
+        kh, e0 = P.orientation_waves(0.0, 0.0, 0.0)
+        c.solve(list(kh), list(e0), tol=1e-6, want_p=False)
+        assert c.lib.dda_near_field(c.h, 1, 1, dp(pts), dp(E), None) == L.DDA_ERR_INVALID_ARG  # 2 rhs solved
+        assert c.lib.dda_near_field(c.h, 2, 0, dp(pts), dp(E), None) == L.DDA_ERR_INVALID_ARG
+        assert c.lib.dda_near_field(c.h, 2, 1, None, dp(E), None) == L.DDA_ERR_INVALID_ARG
+        with pytest.raises(P.DDAError):
+            c.near_field(1, [[0.0, 0.0, 5.0]])
+    finally:
+        c.close()
