@@ -607,18 +607,21 @@ __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, doubl
 //   E = exp(ikR) [k^2/R (p - n (n.p)) + (1/R^3 - ik/R^2) (3 n (n.p) - p)],
 //   B = exp(ikR) (k^2/R + ik/R^2) (n x p),
 // and the plane wave's B = khat x E_inc.  A point on a site takes no
-// contribution from that site.  Block (point, rhs) sums the sites;
+// contribution from that site.  Block (point, rhs pair) sums the sites; the
+// rhs of one target share k, so each site's exp(ikR) serves both.
 // out[(rhs * npts + pt) * 12]: E then B, (re, im) per component.
 __global__ void __launch_bounds__(256) k_near_field(Geo g, double ox, double oy, double oz,
                                                     const Cx<double>* __restrict__ P,
                                                     const WaveDev* __restrict__ w, const double* __restrict__ pts,
-                                                    int npts, double* __restrict__ out) {
-    __shared__ double sh[12 * 4];
-    const int pt = blockIdx.x, rhs = blockIdx.y;
-    const double k = w[rhs].k;
+                                                    int npts, int nrhs, double* __restrict__ out) {
+    __shared__ double sh[24 * 4];
+    const int pt = blockIdx.x, r0 = 2 * blockIdx.y;
+    const int nr = min(2, nrhs - r0);
+    const double k = w[r0].k;
     const double qx = pts[3 * pt], qy = pts[3 * pt + 1], qz = pts[3 * pt + 2];
-    double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const Cx<double>* Pr = P + (size_t)rhs * 3 * g.Npad;
+    double acc[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) acc[i] = 0;
     for (int j = threadIdx.x; j < g.N; j += blockDim.x) {
         const uint32_t s = g.site_xyz[j];
         const double Rx = qx - ((double)(s & 1023) - ox), Ry = qy - ((double)((s >> 10) & 1023) - oy);
@@ -627,41 +630,54 @@ __global__ void __launch_bounds__(256) k_near_field(Geo g, double ox, double oy,
         if (!(R2 > 1e-18)) continue;  // the point is this site
         const double R = sqrt(R2), iR = 1.0 / R;
         const double n[3] = {Rx * iR, Ry * iR, Rz * iR};
-        const Cx<double> p[3] = {Pr[j], Pr[g.Npad + j], Pr[2 * g.Npad + j]};
         double sn, cs;
         sincos(k * R, &sn, &cs);
         const Cx<double> ph = {cs, sn};
-        const Cx<double> np = n[0] * p[0] + n[1] * p[1] + n[2] * p[2];
         const double a = k * k * iR;
         const Cx<double> b = {iR * iR * iR, -k * iR * iR};       // 1/R^3 - ik/R^2
         const Cx<double> cb = ph * Cx<double>{a, k * iR * iR};  // exp(ikR) (k^2/R + ik/R^2)
-        const Cx<double> nxp[3] = {n[1] * p[2] - n[2] * p[1], n[2] * p[0] - n[0] * p[2], n[0] * p[1] - n[1] * p[0]};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const Cx<double> e = ph * (a * (p[c] - n[c] * np) + b * ((3.0 * n[c]) * np - p[c]));
-            const Cx<double> bb = cb * nxp[c];
-            acc[2 * c] += e.re;
-            acc[2 * c + 1] += e.im;
-            acc[6 + 2 * c] += bb.re;
-            acc[6 + 2 * c + 1] += bb.im;
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nr) break;
+            const Cx<double>* Pr = P + (size_t)(r0 + h) * 3 * g.Npad;
+            const Cx<double> p[3] = {Pr[j], Pr[g.Npad + j], Pr[2 * g.Npad + j]};
+            const Cx<double> np = n[0] * p[0] + n[1] * p[1] + n[2] * p[2];
+            const Cx<double> nxp[3] = {n[1] * p[2] - n[2] * p[1], n[2] * p[0] - n[0] * p[2],
+                                       n[0] * p[1] - n[1] * p[0]};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const Cx<double> e = ph * (a * (p[c] - n[c] * np) + b * ((3.0 * n[c]) * np - p[c]));
+                const Cx<double> bb = cb * nxp[c];
+                acc[12 * h + 2 * c] += e.re;
+                acc[12 * h + 2 * c + 1] += e.im;
+                acc[12 * h + 6 + 2 * c] += bb.re;
+                acc[12 * h + 6 + 2 * c + 1] += bb.im;
+            }
         }
     }
-    block_sum_n<12>(acc, sh);
+    block_sum_n<24>(acc, sh);
     if (threadIdx.x != 0) return;
-    const WaveDev wv = w[rhs];
-    double sn, cs;
-    sincos(k * (wv.khat[0] * qx + wv.khat[1] * qy + wv.khat[2] * qz), &sn, &cs);
-    const Cx<double> ph = {cs, sn};
-    Cx<double> ei[3];
-    for (int c = 0; c < 3; ++c) ei[c] = Cx<double>{wv.e[2 * c], wv.e[2 * c + 1]} * ph;
-    const double* kh = wv.khat;
-    const Cx<double> bi[3] = {kh[1] * ei[2] - kh[2] * ei[1], kh[2] * ei[0] - kh[0] * ei[2], kh[0] * ei[1] - kh[1] * ei[0]};
-    double* o = out + ((size_t)rhs * npts + pt) * 12;
-    for (int c = 0; c < 3; ++c) {
-        o[2 * c] = acc[2 * c] + ei[c].re;
-        o[2 * c + 1] = acc[2 * c + 1] + ei[c].im;
-        o[6 + 2 * c] = acc[6 + 2 * c] + bi[c].re;
-        o[6 + 2 * c + 1] = acc[6 + 2 * c + 1] + bi[c].im;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // unrolled: acc is indexed by constants only
+        if (h >= nr) break;
+        const WaveDev wv = w[r0 + h];
+        double sn, cs;
+        sincos(k * (wv.khat[0] * qx + wv.khat[1] * qy + wv.khat[2] * qz), &sn, &cs);
+        const Cx<double> ph = {cs, sn};
+        Cx<double> ei[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ei[c] = Cx<double>{wv.e[2 * c], wv.e[2 * c + 1]} * ph;
+        const double* kh = wv.khat;
+        const Cx<double> bi[3] = {kh[1] * ei[2] - kh[2] * ei[1], kh[2] * ei[0] - kh[0] * ei[2],
+                                  kh[0] * ei[1] - kh[1] * ei[0]};
+        double* o = out + ((size_t)(r0 + h) * npts + pt) * 12;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o[2 * c] = acc[12 * h + 2 * c] + ei[c].re;
+            o[2 * c + 1] = acc[12 * h + 2 * c + 1] + ei[c].im;
+            o[6 + 2 * c] = acc[12 * h + 6 + 2 * c] + bi[c].re;
+            o[6 + 2 * c + 1] = acc[12 * h + 6 + 2 * c + 1] + bi[c].im;
+        }
     }
 }
 
@@ -965,7 +981,8 @@ int ampl_chunks(int ndir, int nrhs, int N) {
 }
 hipError_t launch_near_field(const Geo& g, const double* o, int nrhs, const Cx<double>* P, const WaveDev* w,
                              const double* pts, int npts, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_near_field, dim3(npts, nrhs), dim3(256), 0, st, g, o[0], o[1], o[2], P, w, pts, npts, out);
+    hipLaunchKernelGGL(k_near_field, dim3(npts, (nrhs + 1) / 2), dim3(256), 0, st, g, o[0], o[1], o[2], P, w, pts,
+                       npts, nrhs, out);
     return hipGetLastError();
 }
 hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const Cx<double>* P, int ndir,
