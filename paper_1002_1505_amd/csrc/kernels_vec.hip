@@ -558,20 +558,22 @@ __global__ void __launch_bounds__(256) k_xsec_pair(Geo g, const Cx<double>* __re
         for (int q = 0; q < 16; ++q) part[((size_t)pr * gridDim.x + blockIdx.x) * 16 + q] = acc[q];
 }
 
-// One block per (direction, rhs): F = sum_j P_j exp(-i k n . r_j), FP64.
-// Block (dir, rhs, chunk): partial sums of F over one chunk of the sites,
+// F = sum_j P_j exp(-i k n . r_j) per direction and rhs, FP64.
+// Block (dir, rhs pair, chunk): partial sums of F over one chunk of the sites,
 // partials[((chunk * nrhs + rhs) * ndir + dir) * 6 + q].  On the lattice the
 // phase separates per axis, so the block evaluates n1 + n2 + n3 sincos for
 // its direction and each site takes two complex products of table entries.
 __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, double oz, double k,
                                               const Cx<double>* __restrict__ P, const double* __restrict__ nd,
                                               double* __restrict__ partials, int ndir, int nrhs) {
-    __shared__ double sh[6 * 4];
+    __shared__ double sh[12 * 4];
     // the phase factors per axis, exp(-i k n_a (a - o_a)) for a = x, y, z at
     // every lattice coordinate of the box: [n1 | n2 | n3]
     extern __shared__ unsigned char smem_raw[];
     Cx<double>* T = reinterpret_cast<Cx<double>*>(smem_raw);
-    const int dir = blockIdx.x, rhs = blockIdx.y, chunk = blockIdx.z;
+    // a block serves a pair of rhs (same target, same phases)
+    const int dir = blockIdx.x, r0 = 2 * blockIdx.y, chunk = blockIdx.z;
+    const int nr = min(2, nrhs - r0);
     const int per = (g.N + gridDim.z - 1) / gridDim.z;
     const int j0 = chunk * per, j1 = min(g.N, j0 + per);
     const double nx = nd[3 * dir], ny = nd[3 * dir + 1], nz = nd[3 * dir + 2];
@@ -584,21 +586,34 @@ __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, doubl
         T[i] = Cx<double>{cs, sn};
     }
     __syncthreads();
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[i] = 0;
     for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
         const uint32_t s = g.site_xyz[j];
         // exp(-i k n . (r - o)) as the product of the three axis factors
         const Cx<double> ph = (T[s & 1023] * T[g.n1 + ((s >> 10) & 1023)]) * T[n12 + (s >> 20)];
         const double cs = ph.re, sn = ph.im;
-        for (int c = 0; c < 3; ++c) {
-            const Cx<double> p = P[((size_t)rhs * 3 + c) * g.Npad + j];
-            acc[2 * c] += p.re * cs - p.im * sn;
-            acc[2 * c + 1] += p.re * sn + p.im * cs;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nr) break;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const Cx<double> p = P[((size_t)(r0 + h) * 3 + c) * g.Npad + j];
+                acc[6 * h + 2 * c] += p.re * cs - p.im * sn;
+                acc[6 * h + 2 * c + 1] += p.re * sn + p.im * cs;
+            }
         }
     }
-    block_sum_n<6>(acc, sh);
+    block_sum_n<12>(acc, sh);
     if (threadIdx.x == 0)
-        for (int q = 0; q < 6; ++q) partials[(((size_t)chunk * nrhs + rhs) * ndir + dir) * 6 + q] = acc[q];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= nr) break;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                partials[(((size_t)chunk * nrhs + r0 + h) * ndir + dir) * 6 + q] = acc[6 * h + q];
+        }
 }
 
 // Total E and B at points (FP64): the incident wave plus the retarded field
@@ -989,8 +1004,8 @@ hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const 
                        const double* ndirs, Cx<double>* F, double* partials, hipStream_t st) {
     const int nc = ampl_chunks(ndir, nrhs, g.N);
     const size_t lds = (size_t)(g.n1 + g.n2 + g.n3) * sizeof(Cx<double>);  // at most 3 x 1023 entries
-    hipLaunchKernelGGL(k_ampl, dim3(ndir, nrhs, nc), dim3(256), lds, st, g, o[0], o[1], o[2], k, P, ndirs, partials,
-                       ndir, nrhs);
+    hipLaunchKernelGGL(k_ampl, dim3(ndir, (nrhs + 1) / 2, nc), dim3(256), lds, st, g, o[0], o[1], o[2], k, P, ndirs,
+                       partials, ndir, nrhs);
     HIP_TRY(hipGetLastError());
     const int n = nrhs * ndir * 6;
     hipLaunchKernelGGL(k_ampl_reduce, dim3((n + 255) / 256), dim3(256), 0, st, partials, nc, n,
