@@ -49,19 +49,19 @@ template <int M, class T> __device__ __forceinline__ Cx<T> quad_xor(Cx<T> v) {
 // (2k, 2k + 1) hold such a pair: (k, H - 1 - k) for px = 1; (k + 1, H - k - 1)
 // for px = 0, where b'x = 0 and b'x = H/2 fold onto themselves and take the
 // last two places.  grp_pos is the inverse.
+// Both are select chains (no early returns), so a lane-dependent argument
+// costs a few conditional moves rather than divergent branches.
 __device__ __forceinline__ int grp_bx(int p, int px, int H) {
-    if (px) return (p & 1) ? H - 1 - (p >> 1) : p >> 1;
-    if (p < H - 2) {
-        const int k = (p >> 1) + 1;
-        return (p & 1) ? H - k : k;
-    }
-    return p == H - 2 ? 0 : H / 2;
+    const int k = p >> 1, odd = p & 1;
+    const int b1 = odd ? H - 1 - k : k;
+    const int b0 = p < H - 2 ? (odd ? H - 1 - k : k + 1) : (p == H - 2 ? 0 : H / 2);
+    return px ? b1 : b0;
 }
 __device__ __forceinline__ int grp_pos(int b, int px, int H) {
-    if (px) return b < H / 2 ? 2 * b : 2 * (H - 1 - b) + 1;
-    if (b == 0) return H - 2;
-    if (b == H / 2) return H - 1;
-    return b < H / 2 ? 2 * (b - 1) : 2 * (H - b - 1) + 1;
+    const bool lo = b < H / 2;
+    const int p1 = lo ? 2 * b : 2 * (H - 1 - b) + 1;
+    const int p0 = b == 0 ? H - 2 : (b == H / 2 ? H - 1 : (lo ? 2 * (b - 1) : 2 * (H - b - 1) + 1));
+    return px ? p1 : p0;
 }
 // Slot of folded column f/2 = u (0..H) of parity half px in the spectrum copy
 // that follows the group order (u = H, the even half's Nyquist column and the

@@ -138,20 +138,41 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     const Cx<T>* rv = reinterpret_cast<const Cx<T>*>(u.r);
     const Cx<T>* vv = reinterpret_cast<const Cx<T>*>(u.v);
     Cx<T>* po = reinterpret_cast<Cx<T>*>(u.pout);
-#pragma unroll 4
-    for (int j = j0 + tid; j < j1; j += NTH) {
-        const uint32_t s = g.site_xyz[j];
-        const int sx = s & 1023, sy = (s >> 10) & 1023;
-        Cx<T> v;
-        if (UPD == 0) {
-            v = x[vo + j];
-        } else {
-            v = rv[vo + j] - c1 * vv[vo + j];
-            if (par == 0) po[vo + j] = v;
+    // batches of UB sites per thread: every global load of a batch is issued
+    // (indices past the plane clamped to its last site) before any is used,
+    // and only the LDS work is predicated
+    constexpr int UB = 4;
+    for (int jb = j0 + tid; jb < j1; jb += UB * NTH) {
+        uint32_t sv[UB];
+        Cx<T> xa[UB], xb[UB];
+#pragma unroll
+        for (int k = 0; k < UB; ++k) {
+            const int j = min(jb + k * NTH, j1 - 1);
+            sv[k] = g.site_xyz[j];
+            if (UPD == 0) {
+                xa[k] = x[vo + j];
+            } else {
+                xa[k] = rv[vo + j];
+                xb[k] = vv[vo + j];
+            }
         }
-        if (px) v = v * th[sx];
-        if (py) v = v * th[N + sy];
-        buf[sy * PITCH + sx] = v;
+#pragma unroll
+        for (int k = 0; k < UB; ++k) {
+            const int j = jb + k * NTH;
+            if (j < j1) {
+                const int sx = sv[k] & 1023, sy = (sv[k] >> 10) & 1023;
+                Cx<T> v;
+                if (UPD == 0) {
+                    v = xa[k];
+                } else {
+                    v = xa[k] - c1 * xb[k];
+                    if (par == 0) po[vo + j] = v;
+                }
+                if (px) v = v * th[sx];
+                if (py) v = v * th[N + sy];
+                buf[sy * PITCH + sx] = v;
+            }
+        }
     }
     __syncthreads();
     ct_fft<T, -1, N, N, NTH, N, PITCH, 0, 1>(buf, t1, tid);   // along x: lines are rows
@@ -502,7 +523,11 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
     // is issued together with the flag's instead of after the branch
     if ((active && !active[r]) || tile < 0) return;
     const int tid = threadIdx.x;
-    const int pz = tid / (TX * R);
+    // each half is a whole number of waves, so the parity is wave-uniform;
+    // saying so lets its branches below run on the scalar unit instead of
+    // masking lanes, and the twiddle loads under them issue as one batch
+    static_assert((TX * R) % 64 == 0, "halves of whole waves");
+    const int pz = __builtin_amdgcn_readfirstlane(tid / (TX * R));
     const int tt = tid % (TX * R);
     const int c = tt % TX, j = tt / TX;  // j: z1 in the outer steps, k2 in the inner ones
     Cx<T>* X = reinterpret_cast<Cx<T>*>(smem_raw) + pz * XS;
@@ -531,14 +556,21 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
     for (int m = 0; m < R; ++m) w[m] = tw.f3[j * m];
     Cx<T>* base = slab + (size_t)r * 3 * N * NCOL;
     const uint32_t o0 = (uint32_t)j * NCOL + q0 + c;
+    // half-shift twiddles of the parity-1 half (the same for all three components)
+    Cx<T> h[R];
+    if (pz) {
+#pragma unroll
+        for (int z2 = 0; z2 < R; ++z2) h[z2] = tw.h3[j + R * z2];
+    }
     // forward, outer factor: thread (c, z1 = j) of half pz
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         Cx<T> u[R];
 #pragma unroll
-        for (int z2 = 0; z2 < R; ++z2) {
-            u[z2] = base[o0 + (uint32_t)(a * N + R * z2) * NCOL];
-            if (pz) u[z2] = u[z2] * tw.h3[j + R * z2];
+        for (int z2 = 0; z2 < R; ++z2) u[z2] = base[o0 + (uint32_t)(a * N + R * z2) * NCOL];
+        if (pz) {
+#pragma unroll
+            for (int z2 = 0; z2 < R; ++z2) u[z2] = u[z2] * h[z2];
         }
         bfly<T, -1, R>(u);
 #pragma unroll
@@ -602,7 +634,7 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
         if (pz)
 #pragma unroll
             for (int z2 = 0; z2 < R; ++z2)
-                X[((a * R + z2) * R + j) * TX + c] = cmulc(tw.h3[j + R * z2], u[a][z2]);
+                X[((a * R + z2) * R + j) * TX + c] = cmulc(h[z2], u[a][z2]);
     }
     __syncthreads();
     if (pz) return;
@@ -653,23 +685,55 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     for (int i = tid; i < N; i += NTH) t1[i] = tw.f1[i];
     const Cx<T>* in = slab + (((size_t)rhs * 3 + c) * N + z) * 4 * (size_t)NN;
     const T sgx = qx ? (T)-1 : (T)1, sgy = qy ? (T)-1 : (T)1;
-    // batches of loads in flight per thread (the loop count NN / NTH is a constant)
-#pragma unroll 4
-    for (int e = tid; e < NN; e += NTH) {
-        const int kyp = e / N, kxp = e % N;
-        const int bx = kxp >> 1, px = kxp & 1, by = kyp >> 1, py = kyp & 1;
-        const Cx<T>* blk = in + (size_t)(py * 2 + px) * NN;
-        Cx<T> v;
-        if constexpr (G) {
-            v = blk[(by * HN + grp_pos(bx, px, HN)) * 4 + q];
-        } else {
-            const Cx<T> s00 = blk[by * N + bx], s10 = blk[by * N + bx + HN];
-            const Cx<T> s01 = blk[(by + HN) * N + bx], s11 = blk[(by + HN) * N + bx + HN];
-            v = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
+    constexpr int NI = NN / NTH;  // frequencies per thread
+    if constexpr (G && NN % NTH == 0 && NTH % N == 0 && NI <= 16) {
+        // grouped slab (one load per frequency): a thread keeps one column kx
+        // (NTH is a multiple of n); all its loads are issued before the first
+        // use, and the block-uniform class branches around the twiddles are
+        // scalar
+        const int kxp = tid % N, bx = kxp >> 1, px = kxp & 1;
+        const int gs = grp_pos(bx, px, HN) * 4 + q;
+        Cx<T> hy[NI];
+        if (qy) {
+#pragma unroll
+            for (int i = 0; i < NI; ++i) hy[i] = tw.h2[(tid + i * NTH) / N];
         }
-        if (qx) v = cmulc(tw.h1[kxp], v);
-        if (qy) v = cmulc(tw.h2[kyp], v);
-        buf[kyp * PITCH + kxp] = v;
+        const Cx<T> hx = qx ? tw.h1[kxp] : Cx<T>{1, 0};
+        Cx<T> v[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int kyp = (tid + i * NTH) / N;
+            const int by = kyp >> 1, py = kyp & 1;
+            v[i] = in[(size_t)(py * 2 + px) * NN + by * HN * 4 + gs];
+        }
+        if (qx) {
+#pragma unroll
+            for (int i = 0; i < NI; ++i) v[i] = cmulc(hx, v[i]);
+        }
+        if (qy) {
+#pragma unroll
+            for (int i = 0; i < NI; ++i) v[i] = cmulc(hy[i], v[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i) buf[((tid + i * NTH) / N) * PITCH + kxp] = v[i];
+    } else {
+#pragma unroll 4
+        for (int e = tid; e < NN; e += NTH) {
+            const int kyp = e / N, kxp = e % N;
+            const int bx = kxp >> 1, px = kxp & 1, by = kyp >> 1, py = kyp & 1;
+            const Cx<T>* blk = in + (size_t)(py * 2 + px) * NN;
+            Cx<T> v;
+            if constexpr (G) {
+                v = blk[(by * HN + grp_pos(bx, px, HN)) * 4 + q];
+            } else {
+                const Cx<T> s00 = blk[by * N + bx], s10 = blk[by * N + bx + HN];
+                const Cx<T> s01 = blk[(by + HN) * N + bx], s11 = blk[(by + HN) * N + bx + HN];
+                v = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
+            }
+            if (qx) v = cmulc(tw.h1[kxp], v);
+            if (qy) v = cmulc(tw.h2[kyp], v);
+            buf[kyp * PITCH + kxp] = v;
+        }
     }
     __syncthreads();
     ct_fft<T, +1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);    // along y, every column
@@ -770,26 +834,39 @@ __global__ void __launch_bounds__(256) k_pinv3_ct(const Cx<T>* __restrict__ slab
         const int kx = tid & (N - 1), g4 = tid >> 6;
         const int bx = kx >> 1, px = kx & 1;
         const Cx<T> hx = tw.h1[kx];
+        // slot of this thread's column in a row of the grouped slab
+        const int gs = G ? grp_pos(bx, px, HN) * 4 + q : 0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int m1 = g4 + 4 * h;
+            // ky = m1 + 8 m2 keeps the parity of m1: one quadrant block per h
+            const Cx<T>* blk = in + (size_t)((m1 & 1) * 2 + px) * NN;
+            // the class is block-uniform, so these branches are scalar and
+            // every load of the step is in flight before the first use
+            Cx<T> hy[R];
+            if (qy) {
+#pragma unroll
+                for (int m2 = 0; m2 < R; ++m2) hy[m2] = tw.h2[m1 + R * m2];
+            }
             Cx<T> u[R];
 #pragma unroll
             for (int m2 = 0; m2 < R; ++m2) {
-                const int ky = m1 + R * m2;
-                const int by = ky >> 1, py = ky & 1;
-                const Cx<T>* blk = in + (size_t)(py * 2 + px) * NN;
-                Cx<T> v;
+                const int by = (m1 + R * m2) >> 1;
                 if constexpr (G) {
-                    v = blk[(by * HN + grp_pos(bx, px, HN)) * 4 + q];
+                    u[m2] = blk[by * HN * 4 + gs];
                 } else {
                     const Cx<T> s00 = blk[by * N + bx], s10 = blk[by * N + bx + HN];
                     const Cx<T> s01 = blk[(by + HN) * N + bx], s11 = blk[(by + HN) * N + bx + HN];
-                    v = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
+                    u[m2] = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
                 }
-                if (qx) v = cmulc(hx, v);
-                if (qy) v = cmulc(tw.h2[ky], v);
-                u[m2] = v;
+            }
+            if (qx) {
+#pragma unroll
+                for (int m2 = 0; m2 < R; ++m2) u[m2] = cmulc(hx, u[m2]);
+            }
+            if (qy) {
+#pragma unroll
+                for (int m2 = 0; m2 < R; ++m2) u[m2] = cmulc(hy[m2], u[m2]);
             }
             bfly<T, +1, R>(u);
 #pragma unroll
