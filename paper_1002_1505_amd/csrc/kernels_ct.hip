@@ -716,6 +716,40 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
         }
 #pragma unroll
         for (int i = 0; i < NI; ++i) buf[((tid + i * NTH) / N) * PITCH + kxp] = v[i];
+    } else if constexpr (!G && NN % NTH == 0 && NTH % N == 0) {
+        // row layout (four quadrant loads per frequency): the same scheme in
+        // batches of BI frequencies, which bounds the registers in flight
+        constexpr int BI = NI < 4 ? NI : 4;
+        static_assert(NI % BI == 0, "whole batches");
+        const int kxp = tid % N, bx = kxp >> 1, px = kxp & 1;
+        const Cx<T> hx = qx ? tw.h1[kxp] : Cx<T>{1, 0};
+#pragma unroll 1
+        for (int i0 = 0; i0 < NI; i0 += BI) {
+            Cx<T> hy[BI], v[BI];
+            if (qy) {
+#pragma unroll
+                for (int i = 0; i < BI; ++i) hy[i] = tw.h2[(tid + (i0 + i) * NTH) / N];
+            }
+#pragma unroll
+            for (int i = 0; i < BI; ++i) {
+                const int kyp = (tid + (i0 + i) * NTH) / N;
+                const int by = kyp >> 1, py = kyp & 1;
+                const Cx<T>* blk = in + (size_t)(py * 2 + px) * NN;
+                const Cx<T> s00 = blk[by * N + bx], s10 = blk[by * N + bx + HN];
+                const Cx<T> s01 = blk[(by + HN) * N + bx], s11 = blk[(by + HN) * N + bx + HN];
+                v[i] = s00 + sgx * s10 + sgy * (s01 + sgx * s11);
+            }
+            if (qx) {
+#pragma unroll
+                for (int i = 0; i < BI; ++i) v[i] = cmulc(hx, v[i]);
+            }
+            if (qy) {
+#pragma unroll
+                for (int i = 0; i < BI; ++i) v[i] = cmulc(hy[i], v[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < BI; ++i) buf[((tid + (i0 + i) * NTH) / N) * PITCH + kxp] = v[i];
+        }
     } else {
 #pragma unroll 4
         for (int e = tid; e < NN; e += NTH) {
