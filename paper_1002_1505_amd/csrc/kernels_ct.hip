@@ -416,9 +416,14 @@ __global__ void __launch_bounds__(TX * 8) k_zpass3_ct(Cx<T>* __restrict__ slab, 
         for (int a = 0; a < 3; ++a) {
             Cx<T> u[R];
 #pragma unroll
-            for (int z2 = 0; z2 < R; ++z2) {
-                u[z2] = base[o0 + (uint32_t)(a * N + R * z2) * NCOL];
-                if (pz) u[z2] = u[z2] * tw.h3[j + R * z2];
+            for (int z2 = 0; z2 < R; ++z2) u[z2] = base[o0 + (uint32_t)(a * N + R * z2) * NCOL];
+            // pz is the loop counter (uniform): the twiddles load as one batch
+            if (pz) {
+                Cx<T> hz[R];
+#pragma unroll
+                for (int z2 = 0; z2 < R; ++z2) hz[z2] = tw.h3[j + R * z2];
+#pragma unroll
+                for (int z2 = 0; z2 < R; ++z2) u[z2] = u[z2] * hz[z2];
             }
             bfly<T, -1, R>(u);
 #pragma unroll
