@@ -80,6 +80,30 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     if (plane >= nplanes || !on || j1 < j0) return;
     const int px = par & 1, py = par >> 1;
     const int tid = threadIdx.x;
+    // gather operands: batches of UB sites per thread, every global load of a
+    // batch issued (indices past the plane clamped to its last site, j1 > j0
+    // here) before any is used; the first batch is issued now, so its latency
+    // overlaps the set-up below
+    constexpr int UB = 4;
+    const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
+    const Cx<T>* rv = reinterpret_cast<const Cx<T>*>(u.r);
+    const Cx<T>* vv = reinterpret_cast<const Cx<T>*>(u.v);
+    uint32_t sv[UB];
+    Cx<T> xa[UB], xb[UB];
+    auto load_batch = [&](int jb) {
+#pragma unroll
+        for (int k = 0; k < UB; ++k) {
+            const int j = min(jb + k * NTH, j1 - 1);
+            sv[k] = g.site_xyz[j];
+            if (UPD == 0) {
+                xa[k] = x[vo + j];
+            } else {
+                xa[k] = rv[vo + j];
+                xb[k] = vv[vo + j];
+            }
+        }
+    };
+    if (j1 > j0) load_batch(j0 + tid);
     constexpr int NW = NTH / 64;
     __shared__ double red[2 * NW];
     if constexpr (UPD == 2) {
@@ -111,7 +135,6 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
 #pragma unroll 4
     for (int i = tid; i < N * PITCH; i += NTH) buf[i] = Cx<T>{0, 0};
     __syncthreads();
-    const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
     Cx<T> c1 = {0, 0};
     if constexpr (UPD == 2) {
         double ar = 0, ai = 0;
@@ -135,27 +158,9 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
             u.st[rhs].restart = rs;
         }
     }
-    const Cx<T>* rv = reinterpret_cast<const Cx<T>*>(u.r);
-    const Cx<T>* vv = reinterpret_cast<const Cx<T>*>(u.v);
     Cx<T>* po = reinterpret_cast<Cx<T>*>(u.pout);
-    // batches of UB sites per thread: every global load of a batch is issued
-    // (indices past the plane clamped to its last site) before any is used,
-    // and only the LDS work is predicated
-    constexpr int UB = 4;
     for (int jb = j0 + tid; jb < j1; jb += UB * NTH) {
-        uint32_t sv[UB];
-        Cx<T> xa[UB], xb[UB];
-#pragma unroll
-        for (int k = 0; k < UB; ++k) {
-            const int j = min(jb + k * NTH, j1 - 1);
-            sv[k] = g.site_xyz[j];
-            if (UPD == 0) {
-                xa[k] = x[vo + j];
-            } else {
-                xa[k] = rv[vo + j];
-                xb[k] = vv[vo + j];
-            }
-        }
+        if (jb != j0 + tid) load_batch(jb);
 #pragma unroll
         for (int k = 0; k < UB; ++k) {
             const int j = jb + k * NTH;
