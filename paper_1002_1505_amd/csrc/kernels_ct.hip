@@ -586,6 +586,22 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
 #pragma unroll
         for (int k2 = 0; k2 < R; ++k2) X[((a * R + k2) * R + j) * TX + c] = k2 ? u[k2] * w[k2] : u[k2];
     }
+    // spectrum index of inner step k1 (frequency kz = 2 (j + 8 k1) + pz, folded)
+    auto spec_at = [&](int k1) -> uint32_t {
+        const int kz = 2 * (j + R * k1) + pz;
+        const int kzf = kz > N ? 2 * N - kz : kz;
+        return ((uint32_t)(pz * H + (kzf >> 1)) * D + kyi) * D + kxi;
+    };
+    // FP32: the first inner step's spectrum is loaded before the barrier, so
+    // that its latency overlaps the wait (later steps load in turn: one step
+    // ahead would cost a wave per SIMD in registers)
+    float4 g0[3];
+    if constexpr (sizeof(T) == 4) {
+        const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)spec_at(0) * 3;
+        g0[0] = gp[0];
+        g0[1] = gp[1];
+        g0[2] = gp[2];
+    }
     __syncthreads();
     // inner factor, tensor product, inverse inner factor: thread (c, k2 = j)
     {
@@ -599,14 +615,12 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
 #pragma unroll
         for (int k1 = 0; k1 < R; ++k1) {
             const int kz = 2 * (j + R * k1) + pz;
-            const bool mir = kz > N;
-            const int kzf = mir ? 2 * N - kz : kz;
-            const T sz = mir ? (T)-1 : (T)1;
-            const uint32_t gi = ((uint32_t)(pz * H + (kzf >> 1)) * D + kyi) * D + kxi;
+            const T sz = kz > N ? (T)-1 : (T)1;
+            const uint32_t gi = spec_at(k1);
             Cx<T> gg[6];
             if constexpr (sizeof(T) == 4) {
                 const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)gi * 3;
-                const float4 v0 = gp[0], v1 = gp[1], v2 = gp[2];
+                const float4 v0 = k1 ? gp[0] : g0[0], v1 = k1 ? gp[1] : g0[1], v2 = k1 ? gp[2] : g0[2];
                 gg[0] = Cx<T>{v0.x, v0.y};
                 gg[1] = Cx<T>{v0.z, v0.w};
                 gg[2] = Cx<T>{v1.x, v1.y};
