@@ -34,7 +34,7 @@ METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM 
 # one measured (SHA-256 prefix of the file that holds the kernel).
 MEASURED_TRAFFIC = {
     "k_zpass4_ct<float, 64, 16, true>": {"source": "paper_1002_1505_amd/csrc/kernels_ct.hip",
-                                         "sha256": "1a331f0be776253e", "fetch_kib": 31534.0, "write_kib": 49152.0,
+                                         "sha256": "b51fc94e2f6dd614", "fetch_kib": 31530.19, "write_kib": 49152.0,
                                          "fetch_scale": 1.9998, "write_scale": 1.0},
 }
 
