@@ -1,24 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the DDA solve hot path on one MI355X.
 
-Workload: sphere inscribed in a 64^3 box (N = 137,376 dipoles), doubled FFT
-grid 128^3, m = 1.5 + 0.1i, size parameter x = 10 (k d = 0.3124), LDR
-polarizability, one orientation x 2 orthogonal polarizations.  One step is
-the whole hot path for that batch: the incident fields, the FP32-matvec
-BiCGstab with FP64 residual refinement to ||E - A P|| / ||E|| <= 1e-5, the
-cross sections, and the scattering amplitudes at 37 angles in two planes.
-The one-off target set-up and Green's-tensor FFT are outside the timed
-region.  ``value`` = converged solves per second.
+Headline workload: sphere inscribed in a 128^3 box (N = 1,099,136 dipoles),
+doubled FFT grid 256^3, m = 1.33 + 0.01i, size parameter x = 20 (k d =
+0.3124), LDR polarizability, 16 random orientations x 2 orthogonal
+polarizations = 32 right-hand sides sharing one Green's-tensor spectrum.  One
+step is the whole hot path for that batch: the incident fields, the
+FP32-matvec BiCGstab with FP64 residual refinement to ||E - A P|| / ||E|| <=
+1e-5, the cross sections, and the scattering amplitudes at 37 angles in two
+planes of every orientation.  The one-off target set-up and Green's-tensor FFT
+are outside the timed region.  ``value`` = converged solves per second.
 
-Also reported: the per-pass matvec roofline (HIP events on the context's
-stream, algorithmic bytes of each pass), an all-FP64 comparison, and the CPU
-oracle timed on a bounded sample of the same workload.
+Also reported: the per-pass matvec roofline at 32 rhs (HIP events on the
+context's stream, algorithmic bytes of each pass) and the matvec at 2, 8 and
+32 rhs; the 64^3 sphere (2 rhs, with an all-FP64 comparison, moments and near
+field); orientational averaging; the mixed-box batch; the learned initial
+guess; and the CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -28,22 +33,18 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA
 METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM peak"
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
-# bench (2 rhs, 64^3 box), scaled by the counts of a 256 MiB device copy
-# (FETCH x 1.9998, WRITE x 1.0); valid only while the kernel source is the
-# one measured (SHA-256 prefix of the file that holds the kernel).
-MEASURED_TRAFFIC = {
-    "k_zpass4_ct<float, 64, 16, true>": {"source": "paper_1002_1505_amd/csrc/kernels_ct.hip",
-                                         "sha256": "b51fc94e2f6dd614", "fetch_kib": 31530.19, "write_kib": 49152.0,
-                                         "fetch_scale": 1.9998, "write_scale": 1.0},
-}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
+# the counts of a 256 MiB device copy (FETCH x 1.9998, WRITE x 1.0); valid
+# only while the kernel source is the one measured (SHA-256 prefix of the file
+# that holds the kernel).  Keyed by kernel name and rhs count of the launch.
+MEASURED_TRAFFIC = {}
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, nrhs: int):
     """HBM bytes per launch of `kernel` if its source is unchanged since the counters were taken, else None."""
     import hashlib
 
-    m = MEASURED_TRAFFIC.get(kernel)
+    m = MEASURED_TRAFFIC.get((kernel, nrhs))
     if m is None:
         return None
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), m["source"])
@@ -59,16 +60,16 @@ def measured_traffic(kernel: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--orientations", type=int, default=16, help="orientations of the headline sphere (2 rhs each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target wall time of the CPU sample")
-    ap.add_argument("--box", type=int, default=64)
-    ap.add_argument("--x", type=float, default=10.0)
+    ap.add_argument("--no-c2", action="store_true", help="skip the 64^3 sphere leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess comparison")
     ap.add_argument("--no-orient", action="store_true", help="skip the orientational-average leg")
-    ap.add_argument("--no-c4", action="store_true", help="skip the 128^3 sphere leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the mixed-box batch leg")
+    ap.add_argument("--c3-orientations", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three plain 256 MiB device copies (reference kernel for HBM byte counters)")
     ap.add_argument("--train-targets", type=int, default=16)
@@ -80,6 +81,20 @@ def parse():
     ap.add_argument("--eval-targets", type=int, default=2)
     ap.add_argument("--sweep", type=int, default=32)
     return ap.parse_args()
+
+
+def pass_names(P, ctx, n, prec_name="float"):
+    """Kernel names of the three matvec passes for the context's current FP32 shape."""
+    sh = ctx.get_shape(0, P.DDA_FP32)
+    if sh["ct"] & 1:
+        grp = "true" if sh["ct"] & 8 else "false"  # class-grouped slab
+        zname = {0: f"k_zpass_ct<float, {n}, {sh['tx']}>", 1: f"k_zpass2_ct<float, {n}, {sh['tx']}, 8>",
+                 2: f"k_zpass3_ct<float, {n}, {sh['tx']}>",
+                 3: f"k_zpass4_ct<float, {n}, {sh['tx']}, {grp}>",
+                 4: f"k_zpass5_ct<{sh['tx']}>"}[sh["zrb"]]
+        iname = "k_pinv3_ct" if sh["ct"] & 4 else "k_pinv_ct"
+        return [f"k_pfwd_ct<float, {n}, 0|1|2|3, {grp}>", zname, f"{iname}<float, {n}, 0, 0|1|2|3, {grp}>"], sh
+    return ["k_plane_fwd<float>", "k_zpass<float>", "k_plane_inv<float, 0>"], sh
 
 
 def main():
@@ -106,108 +121,86 @@ def main():
         del src, dst
     ctx = P.Context(0, stream=stream.cuda_stream)
 
-    n = a.box
+    # headline: the 128^3 sphere, 16 orientations x 2 polarizations
+    n, x, m = 128, 20.0, 1.33 + 0.01j
     occ = synth.sphere_occupancy(n)
     N = int(occ.sum())
     aeff = (3.0 * N / (4.0 * np.pi)) ** (1.0 / 3.0)
-    kd = a.x / aeff
-    m = 1.5 + 0.1j
+    kd = x / aeff
     t0 = time.time()
     ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
     ctx.build_green_fft(P.DDA_FP32 | P.DDA_FP64)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
-    khat, e0 = P.orientation_waves(0.0, 0.0, 0.0)
-    L = P.lab_frame(0.0, 0.0, 0.0)
+    rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 4)
+    ori = synth.uniform_orientations(a.orientations, rng)
+    kh, e0, n_tf, e_tf = [], [], [], []
     th = np.deg2rad(np.arange(0, 181, 5.0))
     thetas = np.concatenate([th, th])
     phis = np.concatenate([np.zeros_like(th), np.full_like(th, np.pi / 2)])
-    n_tf, e_tf = P.scattering_frame(thetas, phis, L)
+    for b, t, p in ori:
+        k2, e2 = P.orientation_waves(b, t, p)
+        kh += list(k2)
+        e0 += list(e2)
+        nt, et = P.scattering_frame(thetas, phis, P.lab_frame(b, t, p))
+        n_tf.append(nt)
+        e_tf.append(et)
+    nrhs = len(kh)
+    n_tf = np.concatenate(n_tf)  # every orientation's 74 directions, in the target frame
+    e_tf = np.concatenate(e_tf)
+    ndir1 = len(thetas)
 
-    def step(prec):
-        _, st, status = ctx.solve(khat, e0, tol=1e-5, prec=prec, want_p=False)
-        q = ctx.cross_sections(2)
-        f = ctx.amplitudes(2, n_tf, e_tf)
-        return st, q, f
+    def step():
+        _, st, status = ctx.solve(kh, e0, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE, want_p=False)
+        q = ctx.cross_sections(nrhs)
+        f = ctx.amplitudes(nrhs, n_tf, e_tf)  # (rhs, all directions, 2)
+        # each orientation's own 74 directions
+        f_own = np.stack([f[i, (i // 2) * ndir1:(i // 2 + 1) * ndir1] for i in range(nrhs)])
+        return st, q, f_own
 
     for _ in range(a.warmup):
-        step(P.DDA_SOLVE_FP32_REFINE)
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
     for _ in range(a.steps):
-        st, q, f = step(P.DDA_SOLVE_FP32_REFINE)
+        st, q, f = step()
         stats.append(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tim = ctx.last_timing()
-    nsolve = 2 * a.steps
+    nsolve = nrhs * a.steps
     conv = sum(1 for st in stats for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
     value = conv / dt
-    # all-FP64 comparison (same step, fewer repetitions)
-    st64, q64, f64 = step(P.DDA_SOLVE_FP64)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    k64 = max(2, a.steps // 4)
-    for _ in range(k64):
-        st64, q64, f64 = step(P.DDA_SOLVE_FP64)
-    torch.cuda.synchronize()
-    dt64 = time.perf_counter() - t1
-    q_rel = float(np.max(np.abs(q - q64) / np.abs(q64)))
-    # Q_pha, Q_bk and the scattered-intensity moments of the FP64 solution
-    # over the eta = 0.5 direction set (outside the timed region)
-    n_q, w_q = P.scattering_quadrature(a.x, 0.5, L)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    mom = ctx.scattering_moments(2, n_q, w_q)
-    torch.cuda.synchronize()
-    ms_mom = 1e3 * (time.perf_counter() - t2)
-    # E and B along a 481-point track through the centre of the sphere,
-    # from 1.5 radii before it to 1.5 radii after (outside the timed region)
-    track = np.linspace([-1.5 * n / 2, 0.25, 0.25], [1.5 * n / 2, 0.25, 0.25], 481)
-    ctx.near_field(2, track)  # warm-up
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    Enf, Bnf = ctx.near_field(2, track)
-    torch.cuda.synchronize()
-    ms_nf = 1e3 * (time.perf_counter() - t2)
-    e2 = np.sum(np.abs(Enf) ** 2, axis=-1).mean(axis=0)  # |E|^2, mean of the two polarizations
-    inside = np.abs(track[:, 0]) < 0.95 * n / 2
-    # per-pass matvec roofline (FP32, the solve's launch shapes, both rhs)
-    ms, by = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP32, reps=20)
-    sh = ctx.get_shape(0, P.DDA_FP32)
-    if sh["ct"] & 1:
-        grp = "true" if sh["ct"] & 8 else "false"  # class-grouped slab
-        zname = {0: f"k_zpass_ct<float, {n}, {sh['tx']}>", 1: f"k_zpass2_ct<float, {n}, {sh['tx']}, 8>",
-                 2: f"k_zpass3_ct<float, {n}, {sh['tx']}>",
-                 3: f"k_zpass4_ct<float, {n}, {sh['tx']}, {grp}>"}[sh["zrb"]]
-        iname = "k_pinv3_ct" if sh["ct"] & 4 else "k_pinv_ct"
-        names = [f"k_pfwd_ct<float, {n}, 0|1|2|3, {grp}>", zname, f"{iname}<float, {n}, 0, 0|1|2|3, {grp}>"]
-    else:
-        names = ["k_plane_fwd<float>", "k_zpass<float>", "k_plane_inv<float, 0>"]
+    # per-pass matvec roofline at the batch size of the headline solve, and
+    # the whole matvec at 2, 8 and 32 rhs (FP32, the solve's launch shapes)
+    names, sh = pass_names(P, ctx, n)
+    mv = {}
+    for nr in (2, 8, nrhs):
+        ms, by = ctx.profile_matvec(0, nrhs=nr, prec=P.DDA_FP32, reps=5 if nr > 8 else 10)
+        mv[nr] = (ms, by)
+    ms, by = mv[nrhs]
     dom = int(np.argmax(ms))
     gbs = by / (ms * 1e-3) / 1e9
-    mv_ms = float(ms.sum())
-    mv_gbs = float(by.sum() / (mv_ms * 1e-3) / 1e9)
-    ms64, by64 = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP64, reps=5)
-
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(value, 4),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(dt / a.steps * 1e3, 3),
+        "ms_per_step": round(dt / a.steps * 1e3, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64 matvec / f64 refine",
-        "data": "synthetic: seeded pseudosphere, no external data",
+        "data": "synthetic: seeded pseudosphere and orientations, no external data",
         "config": {
-            "workload": f"sphere in {n}^3 box (N={N}), FFT grid {2*n}^3, m=1.5+0.1i, x={a.x}, LDR, "
-                        "1 orientation x 2 polarizations, FP32 matvec + FP64 refinement, tol 1e-5",
-            "global_batch": 2,
+            "workload": f"sphere in {n}^3 box (N={N}), FFT grid {2 * n}^3, m=1.33+0.01i, x={x}, LDR, "
+                        f"{a.orientations} random orientations x 2 polarizations = {nrhs} rhs in one solve, "
+                        "FP32 matvec + FP64 refinement, tol 1e-5, cross sections and 74-direction amplitudes "
+                        "per orientation",
+            "global_batch": nrhs,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -217,60 +210,40 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(float(gbs[dom]) / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(names[dom]),
+            "traffic": measured_traffic(names[dom], nrhs),
             "bytes_per_launch": float(by[dom]),
             "avg_launch_ms": round(float(ms[dom]), 5),
+            "nrhs": nrhs,
             "shape": sh,
         },
         "matvec": {
-            "nrhs": 2,
-            "pass_ms": [round(float(v), 5) for v in ms],
-            "pass_GBs": [round(float(v), 1) for v in gbs],
-            "total_ms": round(mv_ms, 5),
-            "GBs": round(mv_gbs, 1),
-            "frac_hbm": round(mv_gbs / HBM_PEAK_GBS, 4),
-            "fp64_total_ms": round(float(ms64.sum()), 5),
-            "fp64_GBs": round(float(by64.sum() / (ms64.sum() * 1e-3) / 1e9), 1),
-        },
+            str(nr): {"pass_ms": [round(float(v), 5) for v in mv[nr][0]],
+                      "pass_GBs": [round(float(v), 1) for v in mv[nr][1] / (mv[nr][0] * 1e-3) / 1e9],
+                      "total_ms": round(float(mv[nr][0].sum()), 5),
+                      "GBs": round(float(mv[nr][1].sum() / (mv[nr][0].sum() * 1e-3) / 1e9), 1),
+                      "frac_hbm": round(float(mv[nr][1].sum() / (mv[nr][0].sum() * 1e-3) / 1e9) / HBM_PEAK_GBS, 4)}
+            for nr in mv},
         "solve": {
-            "iters": [s["iters"] for s in stats[-1]],
-            "outer": [s["outer"] for s in stats[-1]],
-            "rel_resid": [s["rel_resid"] for s in stats[-1]],
+            "iters_mean": round(float(np.mean([s["iters"] for s in stats[-1]])), 2),
+            "iters_max": int(max(s["iters"] for s in stats[-1])),
+            "outer": sorted(set(s["outer"] for s in stats[-1])),
+            "rel_resid_max": max(s["rel_resid"] for s in stats[-1]),
             "converged": f"{conv}/{nsolve}",
             "ms_fp32_inner": round(tim["ms_mv32"], 3),
             "ms_fp64_residual": round(tim["ms_mv64"], 3),
-            "Q": [list(map(float, qq)) for qq in q],
-        },
-        "fp64_solve": {
-            "solves_per_s": round(2 * k64 / dt64, 3),
-            "iters": [s["iters"] for s in st64],
-            "rel_resid": [s["rel_resid"] for s in st64],
-            "max_rel_diff_Q_fp32refine_vs_fp64": q_rel,
-        },
-        "moments": {
-            "ndir": int(len(w_q)),
-            "eta": 0.5,
-            "ms": round(ms_mom, 3),
-            "per_pol": [{"Qpha": round(float(mm["Qpha"]), 6), "Qbk": round(float(mm["Qbk"]), 6),
-                         "Qsca_quad": round(float(mm["Qsca_quad"]), 6), "cos": round(float(mm["cos"]), 6),
-                         "cos2": round(float(mm["cos2"]), 6)} for mm in mom],
-        },
-        "near_field": {
-            "points": int(len(track)),
-            "track": "x from -1.5 to +1.5 sphere radii at y = z = 0.25, lattice units from the centroid",
-            "ms": round(ms_nf, 3),
-            "site_fields_per_s": round(2 * len(track) * N / (ms_nf * 1e-3), 1),
-            "mean_E2_inside": round(float(e2[inside].mean()), 5),
-            "mean_E2_outside": round(float(e2[~inside].mean()), 5),
+            "Q_mean": [round(float(v), 6) for v in q.mean(axis=0)],
+            "S11_forward_mean": round(float(np.mean(np.abs(f[:, 0, :]) ** 2)), 3),
         },
         "setup_s": round(setup_s, 3),
     }
+    if not a.no_c2:
+        out["c2"] = sphere64(P, ctx, synth, a)
     if not a.no_orient:
-        out["orient_avg"] = orientation_average(P, ctx, a, occ, kd, m)
+        occ64 = synth.sphere_occupancy(64)
+        kd64 = 10.0 / ((3.0 * int(occ64.sum()) / (4.0 * np.pi)) ** (1.0 / 3.0))
+        out["orient_avg"] = orientation_average(P, ctx, a, occ64, kd64, 1.5 + 0.1j)
     if not a.no_c3:
-        out["c3"] = mixed_batch(P, ctx, synth)
-    if not a.no_c4:
-        out["c4"] = large_sphere(P, ctx, synth)
+        out["c3"] = mixed_batch(P, ctx, synth, n_orient=a.c3_orientations)
     if not a.no_learned:
         out["learned"] = learned_vs_plain(P, ctx, a)
     if not a.no_cpu_baseline:
@@ -279,22 +252,109 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def mixed_batch(P, ctx, synth, boxes=(32, 32, 32, 48, 48, 48, 64, 64), n_orient=8, reps=2, max_iter=5000):
+def sphere64(P, ctx, synth, a, steps=10):
+    """The 64^3 sphere (N = 137,376, grid 128^3, m = 1.5+0.1i, x = 10, LDR),
+    one orientation x 2 polarizations: solves/s with FP32 matvecs and FP64
+    refinement and all-FP64, the per-pass matvec roofline at 2 rhs, Q_pha,
+    Q_bk and the eta = 0.5 moments, and E and B along a track."""
+    import torch
+
+    n, x, m = 64, 10.0, 1.5 + 0.1j
+    occ = synth.sphere_occupancy(n)
+    N = int(occ.sum())
+    kd = x / ((3.0 * N / (4.0 * np.pi)) ** (1.0 / 3.0))
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    ctx.build_green_fft(P.DDA_FP32 | P.DDA_FP64)
+    khat, e0 = P.orientation_waves(0.0, 0.0, 0.0)
+    L = P.lab_frame(0.0, 0.0, 0.0)
+    th = np.deg2rad(np.arange(0, 181, 5.0))
+    n_tf, e_tf = P.scattering_frame(np.concatenate([th, th]),
+                                    np.concatenate([np.zeros_like(th), np.full_like(th, np.pi / 2)]), L)
+
+    def step(prec):
+        _, st, status = ctx.solve(khat, e0, tol=1e-5, prec=prec, want_p=False)
+        return st, ctx.cross_sections(2), ctx.amplitudes(2, n_tf, e_tf)
+
+    step(P.DDA_SOLVE_FP32_REFINE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, q, f = step(P.DDA_SOLVE_FP32_REFINE)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    step(P.DDA_SOLVE_FP64)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k64 = max(2, steps // 4)
+    for _ in range(k64):
+        st64, q64, f64 = step(P.DDA_SOLVE_FP64)
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t1
+    q_rel = float(np.max(np.abs(q - q64) / np.abs(q64)))
+    n_q, w_q = P.scattering_quadrature(x, 0.5, L)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    mom = ctx.scattering_moments(2, n_q, w_q)
+    torch.cuda.synchronize()
+    ms_mom = 1e3 * (time.perf_counter() - t2)
+    track = np.linspace([-1.5 * n / 2, 0.25, 0.25], [1.5 * n / 2, 0.25, 0.25], 481)
+    ctx.near_field(2, track)  # warm-up
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    Enf, Bnf = ctx.near_field(2, track)
+    torch.cuda.synchronize()
+    ms_nf = 1e3 * (time.perf_counter() - t2)
+    e2 = np.sum(np.abs(Enf) ** 2, axis=-1).mean(axis=0)
+    inside = np.abs(track[:, 0]) < 0.95 * n / 2
+    ms, by = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP32, reps=20)
+    names, sh = pass_names(P, ctx, n)
+    dom = int(np.argmax(ms))
+    gbs = by / (ms * 1e-3) / 1e9
+    ms64, by64 = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP64, reps=5)
+    conv = sum(1 for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
+    return {
+        "workload": f"sphere in {n}^3 box (N={N}), FFT grid {2 * n}^3, m=1.5+0.1i, x={x}, LDR, 1 orientation x 2 "
+                    "polarizations, FP32 matvec + FP64 refinement, tol 1e-5, cross sections and 74 amplitudes",
+        "solves_per_s": round(2 * steps / dt, 3),
+        "converged": f"{conv}/2",
+        "iters": [s["iters"] for s in st],
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": round(float(gbs[dom]), 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(float(gbs[dom]) / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(names[dom], 2), "bytes_per_launch": float(by[dom]),
+                     "avg_launch_ms": round(float(ms[dom]), 5), "shape": sh},
+        "matvec": {"nrhs": 2, "pass_ms": [round(float(v), 5) for v in ms],
+                   "pass_GBs": [round(float(v), 1) for v in gbs], "total_ms": round(float(ms.sum()), 5),
+                   "GBs": round(float(by.sum() / (ms.sum() * 1e-3) / 1e9), 1),
+                   "frac_hbm": round(float(by.sum() / (ms.sum() * 1e-3) / 1e9) / HBM_PEAK_GBS, 4),
+                   "fp64_total_ms": round(float(ms64.sum()), 5),
+                   "fp64_GBs": round(float(by64.sum() / (ms64.sum() * 1e-3) / 1e9), 1)},
+        "fp64_solve": {"solves_per_s": round(2 * k64 / dt64, 3), "iters": [s["iters"] for s in st64],
+                       "max_rel_diff_Q_fp32refine_vs_fp64": q_rel},
+        "Q": [list(map(float, qq)) for qq in q],
+        "moments": {"ndir": int(len(w_q)), "eta": 0.5, "ms": round(ms_mom, 3),
+                    "per_pol": [{"Qpha": round(float(mm["Qpha"]), 6), "Qbk": round(float(mm["Qbk"]), 6),
+                                 "Qsca_quad": round(float(mm["Qsca_quad"]), 6), "cos": round(float(mm["cos"]), 6),
+                                 "cos2": round(float(mm["cos2"]), 6)} for mm in mom]},
+        "near_field": {"points": int(len(track)),
+                       "track": "x from -1.5 to +1.5 sphere radii at y = z = 0.25, lattice units from the centroid",
+                       "ms": round(ms_nf, 3), "site_fields_per_s": round(2 * len(track) * N / (ms_nf * 1e-3), 1),
+                       "mean_E2_inside": round(float(e2[inside].mean()), 5),
+                       "mean_E2_outside": round(float(e2[~inside].mean()), 5)},
+    }
+
+
+def mixed_batch(P, ctx, synth, boxes=(32, 32, 32, 48, 48, 48, 64, 64), n_orient=64, max_iter=5000):
     """Seeded random ellipsoids in 32^3, 48^3 and 64^3 boxes (axis ratios
     1 : U[1,2] : U[1,3], random rotation), Re m ~ U[1.2, 1.8], Im m ~
     log-U[0.001, 0.3], |m| k d ~ U[0.3, 0.8], LDR; n_orient uniform random
     orientations x 2 polarizations per target, all in one solve call (one
-    graph over every target's group) and, for comparison, one call per
-    target."""
+    graph over every target's group), launch shapes from the autotuner."""
+    import tempfile
+
     import torch
 
     rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 3)
-    tgt = []
-    for n in boxes:
-        occ = synth.random_ellipsoid(n, rng)[0]
-        m = complex(rng.uniform(1.2, 1.8), np.exp(rng.uniform(np.log(1e-3), np.log(0.3))))
-        kd = rng.uniform(0.3, 0.8) / abs(m)
-        tgt.append((occ, m, kd))
+    tgt = synth.mixed_box_targets(boxes, rng)
     for t, (occ, m, kd) in enumerate(tgt):
         if t == 0:
             ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
@@ -309,77 +369,33 @@ def mixed_batch(P, ctx, synth, boxes=(32, 32, 32, 48, 48, 48, 64, 64), n_orient=
             e0 += list(e2)
             tg += [t, t]
     nrhs = len(kh)
-    ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=max_iter)
+    t0 = time.perf_counter()
+    with tempfile.TemporaryDirectory() as d:
+        ctx.autotune(2 * n_orient, os.path.join(d, "tune.json"))
+    tune_s = time.perf_counter() - t0
+    # warm-up: workspaces and graphs, a few iterations
+    ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        _, st, _ = ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=max_iter)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    sel = [[i for i in range(nrhs) if tg[i] == t] for t in range(len(tgt))]
-    for t in range(len(tgt)):
-        ctx.solve([kh[i] for i in sel[t]], [e0[i] for i in sel[t]], targets=[t] * len(sel[t]), tol=1e-5, want_p=False,
-                  max_iter=max_iter)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(reps):
-        for t in range(len(tgt)):
-            ctx.solve([kh[i] for i in sel[t]], [e0[i] for i in sel[t]], targets=[t] * len(sel[t]), tol=1e-5,
-                      want_p=False, max_iter=max_iter)
-    torch.cuda.synchronize()
-    dt_sep = (time.perf_counter() - t1) / reps
-    conv = sum(1 for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
-    return {
-        "workload": f"{len(tgt)} random ellipsoids in boxes {list(boxes)}, {n_orient} orientations x 2 "
-                    "polarizations each, LDR, FP32 matvec + FP64 refinement, tol 1e-5",
-        "solves": nrhs,
-        "converged": f"{conv}/{nrhs}",
-        "solves_per_s_one_call": round(nrhs / dt, 2),
-        "solves_per_s_per_target_calls": round(nrhs / dt_sep, 2),
-        "mean_iters_by_target": [round(float(np.mean([st[i]["iters"] for i in sel[t]])), 1) for t in range(len(tgt))],
-        "m_kd": [[round(m.real, 3), round(m.imag, 4), round(kd, 4)] for _, m, kd in tgt],
-        "sites": [int(o.sum()) for o, _, _ in tgt],
-    }
-
-
-def large_sphere(P, ctx, synth, n=128, x=20.0, m=1.33 + 0.01j, reps=2):
-    """The 128^3 sphere (N = 1,099,136, grid 256^3, x = 20, LDR): 2 rhs
-    solved to 1e-5 with FP32 matvecs and FP64 refinement, and the FP32
-    matvec passes with their algorithmic bytes."""
-    import torch
-
-    occ = synth.sphere_occupancy(n)
-    N = int(occ.sum())
-    kd = x / ((3.0 * N / (4.0 * np.pi)) ** (1.0 / 3.0))
-    t0 = time.perf_counter()
-    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
-    ctx.build_green_fft(P.DDA_FP32 | P.DDA_FP64)
-    torch.cuda.synchronize()
-    setup = time.perf_counter() - t0
-    kh, e0 = P.orientation_waves(0.0, 0.0, 0.0)
-    ctx.solve(list(kh), list(e0), tol=1e-5, want_p=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        _, st, _ = ctx.solve(list(kh), list(e0), tol=1e-5, want_p=False)
+    _, st, _ = ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=max_iter)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    sel = [[i for i in range(nrhs) if tg[i] == t] for t in range(len(tgt))]
     conv = sum(1 for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
-    ms, by = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP32, reps=5)
-    q = ctx.cross_sections(2)
+    iters = [float(np.mean([st[i]["iters"] for i in sel[t]])) for t in range(len(tgt))]
     return {
-        "workload": f"sphere in {n}^3 box (N={N}), FFT grid {2 * n}^3, m=1.33+0.01i, x={x}, LDR, "
-                    "1 orientation x 2 polarizations, FP32 matvec + FP64 refinement, tol 1e-5",
-        "solves_per_s": round(2 * reps / dt, 3),
-        "converged": f"{conv}/2",
-        "iters": [s["iters"] for s in st],
-        "setup_s": round(setup, 3),
-        "matvec_pass_ms": [round(float(v), 4) for v in ms],
-        "matvec_ms": round(float(ms.sum()), 4),
-        "matvec_GBs": round(float(by.sum() / (ms.sum() * 1e-3) / 1e9), 1),
-        "matvec_frac_hbm": round(float(by.sum() / (ms.sum() * 1e-3) / 1e9) / HBM_PEAK_GBS, 4),
-        "shape": ctx.get_shape(0, P.DDA_FP32),
-        "Q": [list(map(float, qq)) for qq in q],
+        "workload": f"{len(tgt)} random ellipsoids in boxes {list(boxes)}, {n_orient} orientations x 2 "
+                    "polarizations each, LDR, FP32 matvec + FP64 refinement, tol 1e-5, one solve call, "
+                    "autotuned launch shapes",
+        "solves": nrhs,
+        "converged": f"{conv}/{nrhs}",
+        "solves_per_s": round(nrhs / dt, 2),
+        "solve_s": round(dt, 3),
+        "autotune_s": round(tune_s, 2),
+        "mean_iters_by_target": [round(v, 1) for v in iters],
+        "median_target_iters": round(float(np.median(iters)), 1),
+        "m_kd": [[round(m.real, 3), round(m.imag, 4), round(kd, 4), round(abs(m) * kd, 3)] for _, m, kd in tgt],
+        "sites": [int(o.sum()) for o, _, _ in tgt],
     }
 
 
@@ -534,9 +550,29 @@ def learned_vs_plain(P, ctx, a):
     return out
 
 
+def host_info():
+    """Host cores the CPU baselines ran on: logical CPUs, the process's CPU
+    affinity, and the processor model (from /proc/cpuinfo, else lscpu)."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    if not model:
+        try:
+            txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+            model = next((l.split(":", 1)[1].strip() for l in txt.splitlines() if l.startswith("Model name")), "")
+        except (OSError, subprocess.SubprocessError):
+            pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model or platform.processor()}
+
+
 def cpu_baseline(occ, kd, m, stats, seconds):
     """The oracle's direct O(N^2) FP64 matvec on a bounded sample of rows of
-    the same workload, extrapolated to full solves: a solve costs as many
+    the headline workload, extrapolated to full solves: a solve costs as many
     matvecs as the GPU solve took (its FP32 and FP64 products counted as FP64
     oracle products)."""
     from oracle import dda
@@ -547,11 +583,11 @@ def cpu_baseline(occ, kd, m, stats, seconds):
     ainv = dda.site_inverse_polarizability(comp, [m], kd, dda.ALPHA_LDR, khat, e)
     rng = np.random.default_rng(0)
     x = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
-    rows = rng.choice(n, size=256, replace=False)
+    rows = rng.choice(n, size=64, replace=False)
     t0 = time.perf_counter()
     dda.matvec_rows(r, kd, ainv, x, rows)
     t_probe = time.perf_counter() - t0
-    nrows = int(min(n, max(256, 256 * seconds / max(t_probe, 1e-6))))
+    nrows = int(min(n, max(64, 64 * seconds / max(t_probe, 1e-6))))
     rows = rng.choice(n, size=nrows, replace=False)
     t0 = time.perf_counter()
     dda.matvec_rows(r, kd, ainv, x, rows)
@@ -560,21 +596,22 @@ def cpu_baseline(occ, kd, m, stats, seconds):
     mv_per_solve = float(np.mean([s["matvecs"] for s in stats]))
     t_solve = t_matvec * mv_per_solve
     return {
-        "value": round(1.0 / t_solve, 8),
+        "value": round(1.0 / t_solve, 10),
         "unit": "solves/s",
         "cores": dda.threads(),
         "kind": "oracle",
         "sample": f"direct O(N^2) FP64 matvec on {nrows} of {n} rows ({t_rows:.1f} s wall), extrapolated to "
                   f"{n} rows x {mv_per_solve:.0f} matvecs per solve",
-        "matvec_s_extrapolated": round(t_matvec, 3),
+        "host": host_info(),
+        "matvec_s_extrapolated": round(t_matvec, 1),
         "fft_host": fft_host_baseline(r, kd, ainv, x, mv_per_solve, dda.threads()),
-        "other_sizes": oracle_sizes(t_rows / (nrows * n), mv_per_solve),
+        "other_sizes": oracle_sizes(t_rows / (nrows * n)),
     }
 
 
-def oracle_sizes(s_per_pair, mv_per_solve):
+def oracle_sizes(s_per_pair):
     """The oracle at the other sizes: the dense LU solve of the 16-diameter
-    sphere (N = 2,176) timed in full, and the direct matvec of the 128^3
+    sphere (N = 2,176) timed in full, and the direct matvec of the 64^3
     sphere extrapolated from the per-pair cost measured above."""
     import synth
     from oracle import dda
@@ -588,37 +625,35 @@ def oracle_sizes(s_per_pair, mv_per_solve):
     t0 = time.perf_counter()
     dda.solve_dense(r, kd, ainv, E)
     t_lu = time.perf_counter() - t0
-    n4 = int(synth.sphere_occupancy(128).sum())
+    n2 = int(synth.sphere_occupancy(64).sum())
     return {
         "dense_lu_sphere16": {"sites": len(r), "s_per_solve": round(t_lu, 3)},
-        "direct_sphere128_extrapolated": {"sites": n4, "matvec_s": round(s_per_pair * n4 * n4, 1),
-                                          "s_per_solve": round(s_per_pair * n4 * n4 * mv_per_solve, 0)},
+        "direct_sphere64_extrapolated": {"sites": n2, "matvec_s": round(s_per_pair * n2 * n2, 2)},
     }
 
 
-def fft_host_baseline(r, kd, ainv, x, mv_per_solve, workers, reps=3):
+def fft_host_baseline(r, kd, ainv, x, mv_per_solve, workers):
     """The FFT method on the host cores (numpy/scipy FFTs on the doubled grid,
-    not the oracle): full-size matvecs in complex64 and complex128 after one
-    warm-up, extrapolated to the GPU solve's matvec count."""
+    not the oracle): one full-size matvec in complex64 and in complex128 after
+    a complex64 warm-up, extrapolated to the GPU solve's matvec count."""
     from oracle import fft_baseline
 
     out = {"kind": "host FFT-DDA (numpy/scipy FFT, BiCGstab matvec count of the GPU solve), not the oracle",
            "workers": workers}
-    for name, dt in (("c64", np.complex64), ("c128", np.complex128)):
+    for i, (name, dt) in enumerate((("c64", np.complex64), ("c128", np.complex128))):
         t0 = time.perf_counter()
         F = fft_baseline.FftDda(r, kd, ainv, dtype=dt, workers=workers)
         setup = time.perf_counter() - t0
-        F.matvec(x)
-        t0 = time.perf_counter()
-        for _ in range(reps):
+        if i == 0:
             F.matvec(x)
-        tm = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        F.matvec(x)
+        tm = time.perf_counter() - t0
         out["grid"] = list(F.M)
         out[name] = {"setup_s": round(setup, 2), "matvec_s": round(tm, 4),
-                     "solves_per_s": round(1.0 / (tm * mv_per_solve), 5)}
+                     "solves_per_s": round(1.0 / (tm * mv_per_solve), 6)}
         del F
-    out["sample"] = (f"{reps} full-size matvecs per precision after one warm-up, extrapolated to "
-                     f"{mv_per_solve:.0f} matvecs per solve")
+    out["sample"] = f"one full-size matvec per precision, extrapolated to {mv_per_solve:.0f} matvecs per solve"
     return out
 
 

@@ -101,8 +101,9 @@ typedef struct dda_ctx dda_ctx;
 /* One incident wave, target-frame components (guide, section "Target
  * Orientation": the lab axis x_LF is the incidence direction). */
 typedef struct {
-    double khat[3];   /* unit propagation direction */
-    double e0[6];     /* polarization vector, (re, im) x 3, |e0| = 1, khat . e0 = 0 */
+    double khat[3];   /* unit propagation direction (|khat| = 1 within 1e-6, else DDA_ERR_INVALID_ARG) */
+    double e0[6];     /* polarization vector, (re, im) x 3, khat . e0 = 0, |e0| = 1 within 1e-6
+                         (else DDA_ERR_INVALID_ARG: the efficiencies are per unit |E0|^2) */
     int32_t target;   /* id returned by dda_set_target (0) or dda_add_target */
     int32_t pad_;
 } dda_wave;
@@ -116,7 +117,10 @@ typedef struct {
     int32_t graph_iters;  /* BiCGstab iterations per graph replay; 0 = autotuned/default */
     int32_t history;      /* 0..4: keep the solutions of the last `history` solves of every slot
                              (for DDA_GUESS_PROJECT and the learned guess); 0 clears them */
-    int32_t reserved[2];
+    int32_t restart_every; /* test hook: force the breakdown restart of the inner BiCGstab
+                              (rhat = p = r) after every restart_every-th iteration; 0 = never
+                              (normal operation), < 0 is DDA_ERR_INVALID_ARG */
+    int32_t reserved;
 } dda_solve_opts;
 
 typedef struct {
@@ -178,7 +182,16 @@ dda_status dda_build_green_fft(dda_ctx* ctx, uint32_t prec);
  * the same nrhs whose slots hold the same targets (DDA_ERR_STATE otherwise);
  * the waves themselves may change (the next orientation or direction of a
  * sweep).  Redefining a target clears the history of its slots.
- * Returns DDA_WARN_NOT_CONVERGED if any right-hand side missed tol.
+ * Returns DDA_WARN_NOT_CONVERGED if any right-hand side missed tol: max_iter
+ * reached, 40 refinement steps, or an inner breakdown that ended non-finite
+ * (its P is then the last finite iterate).  DDA_ERR_INVALID_ARG for a
+ * non-finite incident field.
+ *
+ * Environment: DDA_TRACE=path appends, per solve call, one line per FP64
+ * residual check ("rhs outer iteration rel_resid fp64") and per inner
+ * BiCGstab iteration ("... inner", the inner recursive residual times the
+ * FP64 relative residual it started from, an estimate of ||E - A P|| / ||E||)
+ * to that text file; DDA_ERR_IO if it cannot be opened.
  */
 dda_status dda_solve(dda_ctx* ctx, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* opts,
                      const void* p0, void* p_out, dda_solve_stats* stats);
@@ -193,8 +206,11 @@ dda_status dda_solve(dda_ctx* ctx, int32_t nrhs, const dda_wave* waves, const dd
  * depends on them; CM does not).  Everything else is as for dda_solve; the
  * guesses that carry a previous solution to a new incidence direction
  * (PREV_SHIFT, PROJECT, NN) assume plane waves.  dda_cross_sections after
- * this call uses e_inc as E.  Errors: DDA_ERR_INVALID_ARG for a NULL e_inc,
- * otherwise those of dda_solve.
+ * this call uses e_inc as E in the same sums, still divided by pi a_eff^2
+ * only: they are efficiencies per unit incident |E0|^2 only if the caller's
+ * field has unit amplitude (scale them by 1/|E0|^2 otherwise).  Errors:
+ * DDA_ERR_INVALID_ARG for a NULL or non-finite e_inc, otherwise those of
+ * dda_solve.
  */
 dda_status dda_solve_field(dda_ctx* ctx, int32_t nrhs, const dda_wave* waves, const dda_solve_opts* opts,
                            const void* e_inc, const void* p0, void* p_out, dda_solve_stats* stats);
@@ -317,10 +333,6 @@ dda_status dda_polarization(int32_t ndir, const double* mu, double k, const doub
 dda_status dda_lab_frame(double beta, double theta, double phi, const double* a1, const double* a2,
                          double* out);
 
-/* Choose FFT tile shapes and graph depth for every target by timing
- * candidates on the device; results are cached in the JSON file named by
- * `cache_path` (NULL: the DDA_TUNE_CACHE environment variable, else no
- * file).  `nrhs_hint` is the batch size to tune for. */
 /* The two incident waves of orientation (beta, Theta, Phi): khat = x_LF, and
  * the polarizations e01 (lab frame, 6 doubles, normalized here) and
  * e02 = x_LF x conj(e01) (guide, sections "Target Orientation" and "Incident
@@ -378,6 +390,10 @@ dda_status dda_phi_coefficients(double beta, double theta, double phi_ref, int32
 dda_status dda_scattering_frame(int32_t ndir, const double* theta, const double* phi, const double* lab_axes,
                                 double* n_tf, double* e_tf);
 
+/* Choose FFT tile shapes and graph depth for every target by timing
+ * candidates on the device; results are cached in the JSON file named by
+ * `cache_path` (NULL: the DDA_TUNE_CACHE environment variable, else no
+ * file).  `nrhs_hint` is the batch size to tune for. */
 dda_status dda_autotune(dda_ctx* ctx, int32_t nrhs_hint, const char* cache_path);
 
 /* Milliseconds the last solve spent producing an initial guess from the
@@ -463,12 +479,6 @@ dda_status dda_nn_record(dda_ctx* ctx, dda_nn* nn);
 dda_status dda_nn_train(dda_ctx* ctx, dda_nn* nn, const dda_nn_train_opts* opts, double* loss);
 dda_status dda_nn_save(const dda_nn* nn, const char* path);
 dda_status dda_nn_load(dda_nn* nn, const char* path);
-/* Test hook on dense host arrays over a D^3 box (D >= 16): x_in [ns][D^3][16],
- * target [ns][D^3][16], mask [ns][D^3]; runs the forward pass (out, [ns][D^3][16],
- * may be NULL) and, when target, mask and grads are given, the masked mean
- * squared error over the first nout channels normalised per sample by the
- * target's squared norm, averaged over samples, and its parameter gradients
- * (flat, as dda_nn_get_params). */
 /* Timing hook: forward passes and parameter-gradient passes of the network
  * on ns (1..8) samples of a D^3 box (D a multiple of 16) of device-resident
  * pseudo-random BF16 features and output gradients, reps times each (HIP
@@ -478,6 +488,12 @@ dda_status dda_nn_load(dda_nn* nn, const char* path);
  * pointer may be NULL.  Overwrites the network's activation buffers. */
 dda_status dda_nn_profile(dda_nn* nn, int32_t D, int32_t ns, int32_t reps, double* ms_fwd, double* ms_bwd,
                           double* gflop_fwd);
+/* Test hook on dense host arrays over a D^3 box (D >= 16): x_in [ns][D^3][16],
+ * target [ns][D^3][16], mask [ns][D^3]; runs the forward pass (out, [ns][D^3][16],
+ * may be NULL) and, when target, mask and grads are given, the masked mean
+ * squared error over the first nout channels normalised per sample by the
+ * target's squared norm, averaged over samples, and its parameter gradients
+ * (flat, as dda_nn_get_params). */
 dda_status dda_nn_forward_backward(dda_nn* nn, int32_t ns, int32_t D, const float* x_in, const float* target,
                                    const uint8_t* mask, int32_t nout, float* out, float* grads, double* loss);
 

@@ -136,7 +136,8 @@ class Context:
 
     # -- solve -----------------------------------------------------------
     def solve(self, khat, e0, targets=None, tol=1e-5, max_iter=1000, guess=DDA_GUESS_ZERO,
-              prec=DDA_SOLVE_FP32_REFINE, p0=None, want_p=True, flags=0, graph_iters=0, history=0, e_inc=None):
+              prec=DDA_SOLVE_FP32_REFINE, p0=None, want_p=True, flags=0, graph_iters=0, history=0, e_inc=None,
+              restart_every=0):
         """Solve A P = E_inc for each wave; returns (P or None, stats list, status).
 
         P is a list of (N_t, 3) complex128 arrays (one per wave).  With e_inc
@@ -145,7 +146,7 @@ class Context:
         targets and polarizabilities only."""
         arr, n = _waves(khat, e0, targets)
         opts = L.dda_solve_opts(tol=tol, max_iter=max_iter, guess=guess, prec=prec, flags=flags,
-                                graph_iters=graph_iters, history=history)
+                                graph_iters=graph_iters, history=history, restart_every=restart_every)
         tg = [arr[i].target for i in range(n)]
         sizes = [self.n_sites.get(t, 0) for t in tg]  # unknown ids: the library rejects the call
         p0buf = None

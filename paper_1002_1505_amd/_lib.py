@@ -51,7 +51,7 @@ class dda_wave(C.Structure):
 class dda_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("guess", C.c_int32), ("prec", C.c_int32),
                 ("flags", C.c_uint32), ("graph_iters", C.c_int32), ("history", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("restart_every", C.c_int32), ("reserved", C.c_int32)]
 
 
 class dda_solve_stats(C.Structure):

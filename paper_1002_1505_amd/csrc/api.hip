@@ -113,6 +113,7 @@ struct Target {
     DevMem gz64, gz32;  // n = 64: spectrum with components interleaved (two-factor z pass)
     DevMem gz64g, gz32g;  // the same with x columns in the class-grouped slab's group order
     DevMem zt16, zt32, zt16g;  // n = 64: z-pass tile order per XCD
+    DevMem zt8;                // n = 128: the same for 8-column tiles
     bool have64 = false, have32 = false;
     MvShape sh32{}, sh64{};
     Geo geo() const {
@@ -129,6 +130,7 @@ struct Target {
         g.ztiles16 = zt16.as<int>();
         g.ztiles32 = zt32.as<int>();
         g.ztiles16g = zt16g.as<int>();
+        g.ztiles8 = zt8.as<int>();
         g.site_xyz = d_xyz.as<uint32_t>();
         g.site_comp = d_comp.as<uint8_t>();
         return g;
@@ -170,6 +172,9 @@ struct Group {
     DevMem kv[8];  // inner Krylov vectors x r rhat p v s t p' (kprec precision)
     DevMem slab32, slab64;
     DevMem state, active, partials, scale, tolrel2, maxit, norms, mask;
+    // per-iteration recursive residuals of the inner solve (DDA_TRACE), [nr][tcap]
+    DevMem trace;
+    int tcap = 0;
     // previous solve of the same slots: waves and 1/alpha; the local field
     // (1/alpha) P0 of the least-squares guess, its residual field E - A P0
     // (FP32) and the rms of that residual per slot, inputs of the learned guess
@@ -225,6 +230,11 @@ struct dda_ctx {
     dda_nn* nn = nullptr;  // learned-guess model (not owned)
     std::vector<dda_wave> last_waves;
     double ms_guess = 0;
+    // test hook of the solve options: forced restart period of the inner BiCGstab
+    int force_restart = 0;
+    // DDA_TRACE: file receiving the per-iteration residuals of every solve
+    std::string trace_path;
+    long long ncalls = 0;
     // timing
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // convergence polls of the inner solve: active flags of every group
@@ -330,6 +340,15 @@ MvShape default_shape(const Target& t, int tx_pref) {
         // a generic z pass needs its own thread count for the chosen tile
         c.zrb = (c.ct & 2) ? 1 : 0;
         if (c.ct && matvec_shape_ok<T>(g, t.plans, c)) s = c;
+        // n = 128, FP32: the two-factor 16 x 8 z pass with one frequency
+        // parity per block half
+        if (std::is_same<T, float>::value && g.n1 == 128) {
+            MvShape c5 = s;
+            c5.tx = 8;
+            c5.ct = (ct_available<T>(g.n1, 8) & 3);
+            c5.zrb = 4;
+            if ((c5.ct & 3) == 3 && matvec_shape_ok<T>(g, t.plans, c5)) s = c5;
+        }
         // n = 64: the two-factor z pass; in FP32 the variant with one
         // frequency parity per block half (16-column tiles, more waves per
         // SIMD), in FP64 one parity after the other (32-column tiles)
@@ -485,6 +504,13 @@ dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint
     t.zt16.release();
     t.zt32.release();
     t.zt16g.release();
+    t.zt8.release();
+    if (n1 == 128 && n2 == 128 && n3 == 128) {
+        const std::vector<int> order = zpass_tile_order(128, 8, false);
+        if (order.empty()) return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "z-pass tile order unbalanced");
+        HCHK(c, t.zt8.ensure(order.size() * 4));
+        HCHK(c, hipMemcpy(t.zt8.p, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+    }
     if (n1 == 64 && n2 == 64 && n3 == 64) {
         for (int v = 0; v < 3; ++v) {
             const int tx = v == 1 ? 32 : 16;
@@ -575,9 +601,13 @@ dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
     HCHK(c, work.ensure((size_t)48 * t.n[0] * t.n[1] * t.n[2] * sizeof(Cx<double>)));
     HCHK(c, launch_green(t.geo(), t.tw<double>(), t.plans, t.kd, work.as<Cx<double>>(), t.gh64.as<Cx<double>>(),
                          t.gh32.p ? t.gh32.as<Cx<float>>() : nullptr, c->stream));
-    if (t.n[0] == 64 && t.n[1] == 64 && t.n[2] == 64) {
+    const bool cube = t.n[0] == t.n[1] && t.n[1] == t.n[2];
+    if (cube && (t.n[0] == 64 || t.n[0] == 128)) {
+        // spectrum with the 6 components of a frequency adjacent (two-factor
+        // z passes); n = 64 also in the class-grouped column order
         const size_t cs = oct / 6;
         for (int hx : {0, 32}) {
+            if (hx && t.n[0] != 64) continue;
             DevMem& d64 = hx ? t.gz64g : t.gz64;
             HCHK(c, d64.ensure(oct * sizeof(Cx<double>)));
             HCHK(c, launch_green_interleave<double>(t.gh64.as<Cx<double>>(), d64.as<Cx<double>>(), cs, hx, c->stream));
@@ -729,7 +759,8 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
                                     g.kv[4].as<Cx<T>>(), st));
         HCHK(c, launch_dot<T>(t.Npad, g.nr, 1, r, r, nullptr, nullptr, g.partials.as<double>(), nullptr, st));
         HCHK(c, launch_state_init(t.Npad, g.nr, g.state.as<BiState>(), g.partials.as<double>(),
-                                  g.tolrel2.as<double>(), g.maxit.as<int>(), g.active.as<int>(), st));
+                                  g.tolrel2.as<double>(), g.maxit.as<int>(), g.active.as<int>(), c->force_restart,
+                                  g.tcap > 0 ? g.trace.as<double>() : nullptr, g.tcap, st));
     }
     const int prec = std::is_same<T, double>::value ? DDA_FP64 : DDA_FP32;
     if (c->gkey_gen != c->ws_gen || c->gkey_prec != prec || c->gkey_k != kiters) {
@@ -1131,13 +1162,25 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
         double kn = 0;
         for (int j = 0; j < 3; ++j) kn += waves[i].khat[j] * waves[i].khat[j];
         if (std::fabs(kn - 1.0) > 1e-6) return fail(c, DDA_ERR_INVALID_ARG, "wave %d: |khat| != 1", i);
+        // the efficiencies are normalised by |E0|^2 = 1 and LDR's S assumes it
+        double en = 0;
+        for (int j = 0; j < 6; ++j) en += waves[i].e0[j] * waves[i].e0[j];
+        if (std::fabs(en - 1.0) > 1e-6) return fail(c, DDA_ERR_INVALID_ARG, "wave %d: |e0| != 1", i);
     }
+    if (o && o->restart_every < 0) return fail(c, DDA_ERR_INVALID_ARG, "restart_every < 0");
     const double tol = o->tol > 0 ? o->tol : 1e-5;
     const int max_iter = o->max_iter > 0 ? o->max_iter : 1000;
     const int prec = o->prec;
     if (prec != DDA_SOLVE_FP64 && prec != DDA_SOLVE_FP32_REFINE) return fail(c, DDA_ERR_INVALID_ARG, "bad prec");
     const bool devptr = (o->flags & DDA_DEVICE_PTRS) != 0;
     const bool use_graph = !(o->flags & DDA_NO_GRAPH);
+    c->force_restart = o->restart_every;
+    {
+        const char* tp = std::getenv("DDA_TRACE");
+        c->trace_path = tp ? tp : "";
+    }
+    const bool tracing = !c->trace_path.empty();
+    c->ncalls++;
     // an even count keeps the alternating direction buffers aligned across replays
     const int kiters = 2 * std::max(1, ((o->graph_iters > 0 ? o->graph_iters : 4) + 1) / 2);
     if (o->guess == DDA_GUESS_USER && !p0) return fail(c, DDA_ERR_INVALID_ARG, "GUESS_USER needs p0");
@@ -1170,6 +1213,25 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
             if (keep_prev) return fail(c, DDA_ERR_STATE, "GUESS_PREV: workspace changed");
         }
     }
+    // per-iteration residual trace of the inner solves (DDA_TRACE)
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        g.tcap = tracing ? std::min(max_iter, 100000) : 0;
+        if (tracing) HCHK(c, g.trace.ensure((size_t)g.nr * g.tcap * sizeof(double)));
+    }
+    FILE* tf = nullptr;
+    if (tracing) {
+        tf = std::fopen(c->trace_path.c_str(), "a");
+        if (!tf) return fail(c, DDA_ERR_IO, "DDA_TRACE: cannot open %s", c->trace_path.c_str());
+        std::fprintf(tf, "# solve call %lld: nrhs %d tol %g prec %s; columns: rhs outer iteration rel_resid kind\n",
+                     c->ncalls, nrhs, tol, prec == DDA_SOLVE_FP64 ? "fp64" : "fp32_refine");
+    }
+    struct TraceCloser {
+        FILE* f;
+        ~TraceCloser() {
+            if (f) std::fclose(f);
+        }
+    } trace_closer{tf};
     // keep the previous waves and polarizabilities of every slot
     for (auto& gp : c->groups) {
         Group& g = *gp;
@@ -1274,6 +1336,8 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
         HCHK(c, hipStreamSynchronize(st));
         for (int s = 0; s < g.nr; ++s) bb[g.idx[s]] = h[s];
     }
+    for (int i = 0; i < nrhs; ++i)
+        if (!std::isfinite(bb[i])) return fail(c, DDA_ERR_INVALID_ARG, "rhs %d: the incident field is not finite", i);
     const bool guessed = o->guess != DDA_GUESS_ZERO;
     float ms32 = 0, ms64 = 0;
     hipEvent_t e0 = c->ev0, ea, eb;
@@ -1346,6 +1410,7 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
                     grel[i] = rl;
                 }
                 rel[i] = rl;
+                if (tf) std::fprintf(tf, "%d %d %d %.6e fp64\n", i, outer[i], iters[i], rl);
                 if (rl <= tol || bb[i] == 0) {
                     done[i] = 1;
                     continue;
@@ -1404,10 +1469,10 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
             Target& t = *c->tg[g.tgt];
             if (prec == DDA_SOLVE_FP32_REFINE)
                 HCHK(c, launch_promote_add(t.Npad, g.nr, g.x64.as<Cx<double>>(), g.kv[0].as<Cx<float>>(),
-                                           g.scale.as<double>(), g.mask.as<int>(), st));
+                                           g.scale.as<double>(), g.mask.as<int>(), g.state.as<BiState>(), st));
             else
                 HCHK(c, launch_axpy_masked<double>(t.Npad, g.nr, g.x64.as<Cx<double>>(), g.kv[0].as<Cx<double>>(),
-                                                   g.mask.as<int>(), st));
+                                                   g.mask.as<int>(), g.state.as<BiState>(), st));
             HCHK(c, g.hst.ensure(g.nr * sizeof(BiState)));
             HCHK(c, hipMemcpyAsync(g.hst.p, g.state.p, g.nr * sizeof(BiState), hipMemcpyDeviceToHost, st));
         }
@@ -1417,10 +1482,29 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
             Group& g = *gp;
             const BiState* hs = g.hst.as<BiState>();
             const std::vector<int>& mk = g.hmask;
+            std::vector<double> tr;
+            if (tf) {
+                tr.resize((size_t)g.nr * g.tcap);
+                HCHK(c, hipMemcpy(tr.data(), g.trace.p, tr.size() * sizeof(double), hipMemcpyDeviceToHost));
+            }
             for (int s = 0; s < g.nr; ++s) {
                 if (!mk[s]) continue;
-                iters[g.idx[s]] += hs[s].it;
-                mvs[g.idx[s]] += 2 * hs[s].it;
+                const int i = g.idx[s];
+                // the inner right-hand side is r / ||r||: its recursive residual
+                // times the FP64 relative residual estimates ||E - A P|| / ||E||
+                if (tf)
+                    for (int k = 0; k < std::min(hs[s].it, g.tcap); ++k)
+                        std::fprintf(tf, "%d %d %d %.6e inner\n", i, outer[i], iters[i] + k + 1,
+                                     rel[i] * std::sqrt(std::max(0.0, tr[(size_t)s * g.tcap + k])));
+                iters[i] += hs[s].it;
+                mvs[i] += 2 * hs[s].it;
+                // a breakdown the inner solve could not recover from ended it
+                // non-finite: its correction was not applied, and repeating
+                // it from the same residual would end the same way
+                if (!std::isfinite(hs[s].rr)) {
+                    done[i] = 1;
+                    stat[i] = DDA_WARN_NOT_CONVERGED;
+                }
             }
         }
         HCHK(c, hipEventElapsedTime(&ms, ea, eb));
@@ -2131,7 +2215,7 @@ std::vector<MvShape> shape_candidates(const Target& t) {
     const MvShape base = default_shape<T>(t, 16);
     if (ct_supported(g.n1, g.n2, g.n3)) {
         for (int tx : {8, 16, 32})
-            for (int zrb : {0, 1, 2, 3})
+            for (int zrb : {0, 1, 2, 3, 4})
                 for (int pv : {0, 4, 8, 12}) {  // inverse plane pass variant, slab layout
                     MvShape c = base;
                     c.tx = tx;

@@ -27,6 +27,8 @@ struct Geo {
     const int* ztiles16;
     const int* ztiles32;
     const int* ztiles16g;
+    // n = 128: the same for 8-column tiles (two-factor 16 x 8 z pass)
+    const int* ztiles8;
 };
 
 // Twiddle tables of one target: f_i[k] = exp(-2 pi i k / n_i) (k < n_i) and
@@ -53,6 +55,11 @@ struct BiState {
     // iteration's first pass, or by the flush after the solve); p is in the
     // direction buffer pbuf (0 or 1)
     int pend, pbuf;
+    // test hook: a breakdown restart is forced after every frs-th iteration
+    // (0: never); trace: when non-null, rr after iteration i is written to
+    // trace[i - 1] for i <= tcap
+    int frs, tcap;
+    double* trace;
 };
 
 // Launch shapes of the three matvec passes for one target and precision.
@@ -68,7 +75,8 @@ struct MvShape {
                      // slab, the quadrant pre-combination done by the z pass (n = 64, bits 0, 1, zrb 3)
     int zrb;         // specialised z pass variant: 0 = one rhs per block, 1 = loop over up to 8 rhs per
                      // block with the spectrum in registers, 2 = two-factor 8 x 8 pass (n = 64),
-                     // 3 = two-factor pass with one frequency parity per block half (n = 64)
+                     // 3 = two-factor pass with one frequency parity per block half (n = 64),
+                     // 4 = two-factor 16 x 8 pass with one parity per block half (n = 128, FP32)
 };
 
 // Optional BiCGstab vector update fused into the first matvec pass
@@ -175,17 +183,21 @@ template <class T>
 hipError_t launch_bicg_init(int Npad, int nrhs, const Cx<T>* b, Cx<T>* x, Cx<T>* r, Cx<T>* rhat, Cx<T>* p,
                             Cx<T>* v, hipStream_t st);
 // state init from partials holding <r,r> in slot 0: rho = rr, restart = 1
+// frs: forced-restart period (0 = none); trace: nrhs x tcap doubles or null
 hipError_t launch_state_init(int Npad, int nrhs, BiState* s, const double* partials, const double* tol_rel2,
-                             const int* maxit, int* active, hipStream_t st);
+                             const int* maxit, int* active, int frs, double* trace, int tcap, hipStream_t st);
 
 // Mixed precision helpers.
 // r32 = r64 * scale[rhs] (scale = 1/||r||); x64 += (1/scale[rhs]) * d32
 hipError_t launch_demote(int Npad, int nrhs, const Cx<double>* r64, Cx<float>* r32, const double* scale,
                          const int* mask, hipStream_t st);
+// Both skip a rhs whose inner solve ended with a non-finite recursive
+// residual (st[rhs].rr), so that x64 keeps its last finite value.
 hipError_t launch_promote_add(int Npad, int nrhs, Cx<double>* x64, const Cx<float>* d32, const double* scale,
-                              const int* mask, hipStream_t st);
+                              const int* mask, const BiState* st, hipStream_t stream);
 template <class T>
-hipError_t launch_axpy_masked(int Npad, int nrhs, Cx<T>* x, const Cx<T>* d, const int* mask, hipStream_t st);
+hipError_t launch_axpy_masked(int Npad, int nrhs, Cx<T>* x, const Cx<T>* d, const int* mask, const BiState* st,
+                              hipStream_t stream);
 // per-rhs ||v||^2 into out[rhs] (double), two-stage
 template <class T>
 hipError_t launch_norm2(int Npad, int nrhs, const Cx<T>* v, double* partials, double* out, hipStream_t st);

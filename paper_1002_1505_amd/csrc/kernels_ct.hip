@@ -24,6 +24,8 @@
 //    n/2 - px - b'x whose columns fold onto the same tensor-spectrum
 //    columns: a tile reads 8 spectrum columns instead of 16, and in a copy
 //    of the spectrum with x columns in the same order they are adjacent.
+#include <type_traits>
+
 #include "dda_internal.h"
 
 namespace {
@@ -673,6 +675,203 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
         }
 }
 
+// Lane (lane ^ 8) of the same row of 16 lanes: a DPP row rotation by 8.
+// Every lane of the wave must be active.
+__device__ __forceinline__ float row_xor8(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));
+}
+__device__ __forceinline__ Cx<float> row_xor8(Cx<float> v) { return {row_xor8(v.re), row_xor8(v.im)}; }
+
+// z pass of the n = 128 box (FP32) as a two-factor decomposition 128 = 16 x 8
+// with one frequency parity per block half.  With z = z1 + 16 z2 and
+// k = k2 + 8 k1, the forward DFT is an 8-point DFT over z2 (thread (c, z1),
+// 16 threads per column), a twiddle w_128^(z1 k2), one exchange through LDS
+// and a 16-point DFT over z1.  That 16-point DFT is split over a pair of
+// lanes (row_xor8 partners): thread (c, k2, e) with e the parity of z1 takes
+// the 8-point DFT over z1 = e + 2 z1' and the pair finishes it with one
+// radix-2 step, F[k1' + 8 s] = G_0[k1'] + (-1)^s w_16^k1' G_1[k1'], lane e
+// keeping s = e; so each thread holds 8 frequencies k = k2 + 8 k1' + 64 e of
+// its column for the tensor product, the register load of the 64-point pass
+// with twice the threads per column.  The inverse runs the same steps
+// backwards; the outer threads apply both twiddles, so the inner steps need
+// only the eight constants w_16^k1'.  The parity-1 half's shift h3[z] splits
+// into a constant per z2 and a factor per z1 that joins the outer twiddles,
+// so no twiddle beyond those eight per thread is held; that half hands its
+// output to the parity-0 half through LDS.  Block b runs on XCD b mod 8,
+// taking every rhs of one tile before the next tile of its XCD's list.
+template <int TX>
+__global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3, 3))) k_zpass5_ct(Cx<float>* __restrict__ slab, const Cx<float>* __restrict__ gh,
+                                                      Tw<float> tw, int nrhs, const int* __restrict__ active,
+                                                      const int* __restrict__ tiles) {
+    using T = float;
+    constexpr int N = 128;
+    constexpr int R2 = 8;   // outer factor: 8 points over z2
+    constexpr int R1 = 16;  // inner factor: 16 points over z1 (radix 2 across a lane pair x 8)
+    constexpr int NCOL = 4 * N * N;
+    constexpr int H = N / 2 + 1;
+    constexpr int D = 2 * H;
+    constexpr int XS = 3 * R2 * R1 * TX;  // one exchange buffer [a][k2][z1][c]
+    constexpr int PER_XCD = NCOL / TX / 8;
+    static_assert(TX == 8, "lane layout: 8 columns, bit 3 of the lane is the parity of z1");
+    extern __shared__ unsigned char smem_raw[];
+    const int b = blockIdx.x;
+    const int pos = b >> 3;
+    const int r = pos % nrhs;
+    const int tile = tiles[(b & 7) * PER_XCD + pos / nrhs];
+    if ((active && !active[r]) || tile < 0) return;
+    const int tid = threadIdx.x;
+    const int pz = __builtin_amdgcn_readfirstlane(tid / (TX * R1));
+    const int tt = tid % (TX * R1);
+    const int c = tt % TX, j = tt / TX;  // outer steps: j = z1; inner steps: j = 2 k2 + e
+    Cx<T>* X = reinterpret_cast<Cx<T>*>(smem_raw) + pz * XS;
+    // LDS slot of (a, k2, z1, c); bit 1 of z1 is flipped for odd k2, so the
+    // inner steps' reads (four k2 and both e per wave) touch every bank pair
+    // exactly twice, as the outer steps' accesses do
+    auto xi = [c](int a, int k2, int z1) { return ((a * R2 + k2) * R1 + (z1 ^ ((k2 & 1) << 1))) * TX + c; };
+    const int q0 = tile * TX;
+    const int par = q0 / (N * N), rem = q0 % (N * N);
+    const int px = par & 1, py = par >> 1;
+    const int kyp = rem / N, kx0 = rem % N;
+    int sx, sy;
+    const int kxi = fold_idx(2 * (kx0 + c) + px, N, sx);
+    const int kyi = fold_idx(2 * kyp + py, N, sy);
+    const T sxy = (T)(sx * sy);
+    Cx<T>* base = slab + (size_t)r * 3 * N * NCOL;
+    const uint32_t o0 = (uint32_t)j * NCOL + q0 + c;
+    // w_16^m = exp(-2 pi i m / 16), m < 8: the radix-2 twiddles of the inner
+    // step and the z2-dependent part of the parity-1 half shift
+    constexpr T C1 = (T)0.92387953251128675613, S1 = (T)0.38268343236508977173;
+    constexpr T RS = (T)0.70710678118654752440;
+    const Cx<T> w16[8] = {{1, 0}, {C1, -S1}, {RS, -RS}, {S1, -C1}, {0, -1}, {-S1, -C1}, {-RS, -RS}, {-C1, -S1}};
+    // outer twiddles of thread z1 = j: w_128^(j k2) in the parity-0 half; in
+    // the parity-1 half they absorb the common factor w_256^j of the half
+    // shift h3[j + 16 z2] = w_256^j w_16^z2, giving w_256^(j (2 k2 + 1))
+    // (from the h3 table, which holds w_256^q for q < 128, and
+    // w_256^(q + 128) = -w_256^q); the factor w_16^z2 is a constant
+    Cx<T> w[R2];
+#pragma unroll
+    for (int m = 0; m < R2; ++m) {
+        if (pz) {
+            const int q = j * (2 * m + 1);
+            const Cx<T> hv = tw.h3[q & (N - 1)];
+            w[m] = (q & N) ? Cx<T>{-hv.re, -hv.im} : hv;
+        } else {
+            w[m] = tw.f3[j * m];
+        }
+    }
+    // forward, outer factor: thread (c, z1 = j)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Cx<T> u[R2];
+#pragma unroll
+        for (int z2 = 0; z2 < R2; ++z2) u[z2] = base[o0 + (uint32_t)(a * N + R1 * z2) * NCOL];
+        if (pz) {
+#pragma unroll
+            for (int z2 = 1; z2 < R2; ++z2) u[z2] = w16[z2] * u[z2];
+        }
+        bfly<T, -1, R2>(u);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) X[xi(a, k2, j)] = (k2 || pz) ? u[k2] * w[k2] : u[k2];
+    }
+    const int k2 = j >> 1, e = j & 1;
+    const T sgn = e ? (T)-1 : (T)1;
+    // spectrum index of inner frequency k = k2 + 8 (k1' + 8 e), kz = 2 k + pz (folded)
+    auto spec_at = [&](int k1p) -> uint32_t {
+        const int kz = 2 * (k2 + R2 * (k1p + 8 * e)) + pz;
+        const int kzf = kz > N ? 2 * N - kz : kz;
+        return ((uint32_t)(pz * H + (kzf >> 1)) * D + kyi) * D + kxi;
+    };
+    // the first frequency's spectrum is loaded before the barrier
+    float4 g0[3];
+    {
+        const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)spec_at(0) * 3;
+        g0[0] = gp[0];
+        g0[1] = gp[1];
+        g0[2] = gp[2];
+    }
+    __syncthreads();
+    {
+        Cx<T> f[3][R2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int z1p = 0; z1p < R2; ++z1p) f[a][z1p] = X[xi(a, k2, e + 2 * z1p)];
+            bfly<T, -1, R2>(f[a]);
+            // radix-2 step across the lane pair: lane e contributes G_0 or
+            // w_16^k1' G_1 and keeps F[k1' + 8 e] = contribution of lane 0
+            // +/- that of lane 1
+#pragma unroll
+            for (int k1p = 0; k1p < R2; ++k1p) {
+                if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
+                const Cx<T> mine = (k1p && e) ? w16[k1p] * f[a][k1p] : f[a][k1p];
+                const Cx<T> other = row_xor8(mine);
+                f[a][k1p] = Cx<T>{fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
+            }
+        }
+#pragma unroll
+        for (int k1p = 0; k1p < R2; ++k1p) {
+            // at most two frequencies of spectrum loads in flight (registers)
+            if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
+            const int kz = 2 * (k2 + R2 * (k1p + 8 * e)) + pz;
+            const T sz = kz > N ? (T)-1 : (T)1;
+            const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)spec_at(k1p) * 3;
+            const float4 v0 = k1p ? gp[0] : g0[0], v1 = k1p ? gp[1] : g0[1], v2 = k1p ? gp[2] : g0[2];
+            const Cx<T> gxx = {v0.x, v0.y}, gxy = sxy * Cx<T>{v0.z, v0.w}, gxz = ((T)sx * sz) * Cx<T>{v1.x, v1.y};
+            const Cx<T> gyy = {v1.z, v1.w}, gyz = ((T)sy * sz) * Cx<T>{v2.x, v2.y}, gzz = {v2.z, v2.w};
+            const Cx<T> a0 = f[0][k1p], a1 = f[1][k1p], a2 = f[2][k1p];
+            f[0][k1p] = gxx * a0 + gxy * a1 + gxz * a2;
+            f[1][k1p] = gxy * a0 + gyy * a1 + gyz * a2;
+            f[2][k1p] = gxz * a0 + gyz * a1 + gzz * a2;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // inverse radix-2 step: lane e forms Y0 + Y1 (e = 0) or
+            // (Y0 - Y1) conj(w_16^k1') (e = 1) from its value and its partner's
+#pragma unroll
+            for (int k1p = 0; k1p < R2; ++k1p) {
+                if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
+                const Cx<T> mine = f[a][k1p];
+                const Cx<T> other = row_xor8(mine);
+                const Cx<T> s = {fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
+                f[a][k1p] = (k1p && e) ? cmulc(w16[k1p], s) : s;
+            }
+            bfly<T, +1, R2>(f[a]);
+            // each thread rewrites exactly the slots it read above
+#pragma unroll
+            for (int z1p = 0; z1p < R2; ++z1p) X[xi(a, k2, e + 2 * z1p)] = f[a][z1p];
+        }
+    }
+    __syncthreads();
+    // inverse, outer factor: thread (c, z1 = j), the conjugate twiddles; the
+    // parity-1 half finishes its half shift with conj(w_16^z2) and writes its
+    // output into the slots it has just read
+    Cx<T> u[3][R2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int k2o = 0; k2o < R2; ++k2o) {
+            const Cx<T> v = X[xi(a, k2o, j)];
+            u[a][k2o] = (k2o || pz) ? cmulc(w[k2o], v) : v;
+        }
+        bfly<T, +1, R2>(u[a]);
+        if (pz) {
+#pragma unroll
+            for (int z2 = 0; z2 < R2; ++z2) X[xi(a, z2, j)] = z2 ? cmulc(w16[z2], u[a][z2]) : u[a][z2];
+        }
+    }
+    __syncthreads();
+    if (pz) return;
+    const Cx<T>* X1 = reinterpret_cast<const Cx<T>*>(smem_raw) + XS;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int z2 = 0; z2 < R2; ++z2)
+            base[o0 + (uint32_t)(a * N + R1 * z2) * NCOL] = u[a][z2] + X1[xi(a, z2, j)];
+}
+
+template <int TX>
+constexpr size_t zpass5_lds() { return (size_t)2 * 3 * 8 * 16 * TX * sizeof(Cx<float>); }
+
 // DOT = 1: per-block partial sums of conj(w_j) . y_j (slot 0); DOT = 2:
 // conj(y_j) . x_j (slot 0) and |y_j|^2 (slot 1); DOT = 3: as DOT = 2 with
 // |x_j|^2 in the imaginary part of slot 1, conj(w_j) . x_j (slot 2) and
@@ -1114,6 +1313,16 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
         }
     }
     const int ntile = 4 * N * N;
+    if (zrb == 4) {
+        if constexpr (N != 128 || !std::is_same<T, float>::value) {
+            return hipErrorNotSupported;
+        } else {
+            if (tx != 8 || !g.ztiles8) return hipErrorNotSupported;
+            hipLaunchKernelGGL((k_zpass5_ct<8>), dim3(nrhs * (ntile / 8)), dim3(8 * 32), (zpass5_lds<8>()), st, slab,
+                               ghat, tw, nrhs, active, g.ztiles8);
+            return hipGetLastError();
+        }
+    }
     if (zrb == 3) {
         if constexpr (N != 64) {
             return hipErrorNotSupported;
@@ -1232,6 +1441,10 @@ hipError_t set_attrs_n() {
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass2_ct<T, N, 32, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     }
+    if constexpr (N == 128 && std::is_same<T, float>::value) {
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_zpass5_ct<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    }
     if constexpr (N == 64) {
         if (e == hipSuccess)
             e = set_lds_limit((const void*)k_zpass4_ct<T, N, 16, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -1283,7 +1496,7 @@ int ct_available(int n, int tx) {
     if (!ct_supported(n, n, n)) return 0;
     if (planes((size_t)(3 * n + n * (n + 1)) * sizeof(Cx<T>))) bits |= 1;  // as plane_lds
     if ((bits & 1) && n == 64) bits |= 4;  // two-factor inverse plane pass
-    if (ct_zpass_fits<T>(n, tx, 0) || ct_zpass_fits<T>(n, tx, 2)) bits |= 2;
+    if (ct_zpass_fits<T>(n, tx, 0) || ct_zpass_fits<T>(n, tx, 2) || ct_zpass_fits<T>(n, tx, 4)) bits |= 2;
     if ((bits & 3) == 3 && ct_zpass_fits<T>(n, tx, 3)) bits |= 8;  // class-grouped slab
     return bits;
 }
@@ -1295,6 +1508,7 @@ bool ct_zpass_fits(int n, int tx, int zrb) {
     if (!ct_supported(n, n, n) || !(tx == 8 || tx == 16 || tx == 32) || n % tx) return false;
     if (zrb == 2) return n == 64 && tx >= 16 && (size_t)3 * n * tx * sizeof(Cx<T>) <= LDS_MAX;
     if (zrb == 3) return n == 64 && tx == 16 && (size_t)6 * n * tx * sizeof(Cx<T>) <= LDS_MAX;
+    if (zrb == 4) return n == 128 && tx == 8 && std::is_same<T, float>::value;
     return (zrb == 0 || zrb == 1) && (size_t)(n + 6 * n * tx) * sizeof(Cx<T>) <= LDS_MAX;
 }
 

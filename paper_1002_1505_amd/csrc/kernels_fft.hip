@@ -463,7 +463,7 @@ static int rmin_of(const FftPlan& p) {
 template <class T>
 bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh) {
     const size_t lds_max = 160 * 1024;
-    if (sh.zrb < 0 || sh.zrb > 3) return false;
+    if (sh.zrb < 0 || sh.zrb > 4) return false;
     if (sh.zrb >= 2 && !(sh.ct & 2)) return false;
     if (sh.ct) {
         if (g.n1 != g.n2 || g.n2 != g.n3) return false;

@@ -190,6 +190,8 @@ __device__ void finish_iteration(BiState& s, double2 a, double2 b, int* active, 
     const double2 rho = make_double2(s.rho[0], s.rho[1]);
     s.it += 1;
     s.rr = b.x;
+    if (s.trace && s.it <= s.tcap) s.trace[s.it - 1] = b.x;
+    if (s.frs > 0 && s.it % s.frs == 0) s.restart = 1;
     const double2 al = make_double2(s.alpha[0], s.alpha[1]), om = make_double2(s.omega[0], s.omega[1]);
     const double rn = sqrt(a.x * a.x + a.y * a.y);
     if (s.restart || !(rn > 1e-14 * b.x) || (om.x == 0 && om.y == 0)) {
@@ -292,7 +294,8 @@ __global__ void __launch_bounds__(VT) k_bicg_flush(int V, Cx<T>* __restrict__ x,
                                                    const BiState* __restrict__ st) {
     const int rhs = blockIdx.y;
     const BiState b = st[rhs];
-    if (!b.pend) return;
+    // an iteration that ended non-finite is not applied
+    if (!b.pend || !isfinite(b.rr)) return;
     const Cx<T> al = {(T)b.alpha[0], (T)b.alpha[1]}, om = {(T)b.omega[0], (T)b.omega[1]};
     const Cx<T>* p = b.pbuf ? p1 : p0;
     const size_t o = (size_t)rhs * V;
@@ -353,7 +356,7 @@ __global__ void k_clear_pend(BiState* st, int n) {
 // State initialisation from <r, r> in slot 0.
 __global__ void k_state_init(int nblk, BiState* __restrict__ st, const double* __restrict__ partials,
                              const double* __restrict__ tol_rel2, const int* __restrict__ maxit,
-                             int* __restrict__ active) {
+                             int* __restrict__ active, int frs, double* trace, int tcap) {
     __shared__ double sh[16];
     const int rhs = blockIdx.x;
     const double2 a = reduce_slot(partials, rhs, 0, nblk, sh);
@@ -373,6 +376,9 @@ __global__ void k_state_init(int nblk, BiState* __restrict__ st, const double* _
     s.conv = (a.x <= s.tol2) ? 1 : 0;
     s.pend = 0;
     s.pbuf = 0;
+    s.frs = frs;
+    s.tcap = trace ? tcap : 0;
+    s.trace = trace ? trace + (size_t)rhs * tcap : nullptr;
     st[rhs] = s;
     active[rhs] = (maxit[rhs] > 0 && !s.conv && a.x > 0) ? 1 : 0;
     if (a.x == 0) st[rhs].conv = 1;
@@ -414,9 +420,9 @@ __global__ void __launch_bounds__(VT) k_demote(int V, const Cx<double>* __restri
 
 __global__ void __launch_bounds__(VT) k_promote_add(int V, Cx<double>* __restrict__ x64,
                                                     const Cx<float>* __restrict__ d32, const double* __restrict__ scale,
-                                                    const int* __restrict__ mask) {
+                                                    const int* __restrict__ mask, const BiState* __restrict__ st) {
     const int rhs = blockIdx.y;
-    if (inactive(mask, rhs)) return;
+    if (inactive(mask, rhs) || !isfinite(st[rhs].rr)) return;
     const size_t o = (size_t)rhs * V;
     const double sc = 1.0 / scale[rhs];
     for (int k = 0; k < VPT; ++k) {
@@ -430,9 +436,9 @@ __global__ void __launch_bounds__(VT) k_promote_add(int V, Cx<double>* __restric
 
 template <class T>
 __global__ void __launch_bounds__(VT) k_axpy_masked(int V, Cx<T>* __restrict__ x, const Cx<T>* __restrict__ d,
-                                                    const int* __restrict__ mask) {
+                                                    const int* __restrict__ mask, const BiState* __restrict__ st) {
     const int rhs = blockIdx.y;
-    if (inactive(mask, rhs)) return;
+    if (inactive(mask, rhs) || !isfinite(st[rhs].rr)) return;
     const size_t o = (size_t)rhs * V;
     for (int k = 0; k < VPT; ++k) {
         const int i = blockIdx.x * VB + k * VT + threadIdx.x;
@@ -937,9 +943,9 @@ hipError_t launch_bicg_init(int Npad, int nrhs, const Cx<T>* b, Cx<T>* x, Cx<T>*
     return hipGetLastError();
 }
 hipError_t launch_state_init(int Npad, int nrhs, BiState* s, const double* partials, const double* tol_rel2,
-                             const int* maxit, int* active, hipStream_t st) {
+                             const int* maxit, int* active, int frs, double* trace, int tcap, hipStream_t st) {
     hipLaunchKernelGGL(k_state_init, dim3(nrhs), dim3(256), 0, st, vec_blocks(Npad), s, partials, tol_rel2, maxit,
-                       active);
+                       active, frs, trace, tcap);
     return hipGetLastError();
 }
 hipError_t launch_demote(int Npad, int nrhs, const Cx<double>* r64, Cx<float>* r32, const double* scale,
@@ -948,13 +954,15 @@ hipError_t launch_demote(int Npad, int nrhs, const Cx<double>* r64, Cx<float>* r
     return hipGetLastError();
 }
 hipError_t launch_promote_add(int Npad, int nrhs, Cx<double>* x64, const Cx<float>* d32, const double* scale,
-                              const int* mask, hipStream_t st) {
-    hipLaunchKernelGGL(k_promote_add, dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, x64, d32, scale, mask);
+                              const int* mask, const BiState* bst, hipStream_t st) {
+    hipLaunchKernelGGL(k_promote_add, dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, x64, d32, scale, mask,
+                       bst);
     return hipGetLastError();
 }
 template <class T>
-hipError_t launch_axpy_masked(int Npad, int nrhs, Cx<T>* x, const Cx<T>* d, const int* mask, hipStream_t st) {
-    hipLaunchKernelGGL((k_axpy_masked<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, x, d, mask);
+hipError_t launch_axpy_masked(int Npad, int nrhs, Cx<T>* x, const Cx<T>* d, const int* mask, const BiState* bst,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_axpy_masked<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, x, d, mask, bst);
     return hipGetLastError();
 }
 template <class T>
@@ -1026,7 +1034,8 @@ hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const 
                                           const Cx<T>*, const BiState*, double*, const int*, hipStream_t);           \
     template hipError_t launch_bicg_init<T>(int, int, const Cx<T>*, Cx<T>*, Cx<T>*, Cx<T>*, Cx<T>*, Cx<T>*,          \
                                             hipStream_t);                                                            \
-    template hipError_t launch_axpy_masked<T>(int, int, Cx<T>*, const Cx<T>*, const int*, hipStream_t);              \
+    template hipError_t launch_axpy_masked<T>(int, int, Cx<T>*, const Cx<T>*, const int*, const BiState*,           \
+                                              hipStream_t);                                                          \
     template hipError_t launch_norm2<T>(int, int, const Cx<T>*, double*, double*, hipStream_t);                      \
     template hipError_t launch_from_abi<T>(const Geo&, int, const Cx<double>*, Cx<T>*, hipStream_t);                 \
     template hipError_t launch_to_abi<T>(const Geo&, int, const Cx<T>*, Cx<double>*, hipStream_t);

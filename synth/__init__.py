@@ -27,6 +27,7 @@ __all__ = [
     "aggregate_occupancy",
     "uniform_orientations",
     "theta_sweep",
+    "mixed_box_targets",
     "CONFIG_SEED_BASE",
 ]
 
@@ -140,3 +141,18 @@ def theta_sweep(count: int, beta: float = 0.0, phi: float = 0.0):
     th = np.arccos(c)
     return np.stack([np.full(count, beta), th, np.full(count, phi)], axis=1)
 
+
+
+def mixed_box_targets(boxes, rng: np.random.Generator):
+    """Targets of a mixed-box batch, one per box side in ``boxes``: a random
+    ellipsoid (``random_ellipsoid``), a refractive index with Re m uniform in
+    [1.2, 1.8] and Im m log-uniform in [0.001, 0.3], and a lattice wavenumber
+    k d with |m| k d uniform in [0.3, 0.8].  Returns a list of
+    (occupancy, m, kd), drawn in that order per target."""
+    out = []
+    for n in boxes:
+        occ = random_ellipsoid(int(n), rng)[0]
+        m = complex(rng.uniform(1.2, 1.8), np.exp(rng.uniform(np.log(1e-3), np.log(0.3))))
+        kd = rng.uniform(0.3, 0.8) / abs(m)
+        out.append((occ, m, kd))
+    return out

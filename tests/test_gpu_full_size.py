@@ -1,16 +1,31 @@
-"""GPU parity at the full workload sizes, checked on sampled outputs the
-oracle computes one row at a time (direct O(N) sum per row), and through
-properties that hold at any size.
+"""GPU parity at the full workload sizes.
 
  * sphere in a 64^3 box (N = 137,376), FFT grid 128^3, m = 1.5+0.1i, x = 10
  * sphere in a 128^3 box (N = 1,099,136), FFT grid 256^3, m = 1.33+0.01i, x = 20
-   (its FP64 products use the global-memory plane fallback)
+ * the guide's worked example, a 32 x 64 x 64 block (N = 131,072),
+   m = 0.9656+1.8628i, x = 6.187304
+ * a mixed-box batch: ellipsoids in 32^3, 48^3 and 64^3 boxes in one call
+
+The matvec is checked on sampled rows the oracle computes one at a time
+(direct O(N) sum per row).  Solutions are checked through the full-vector
+FP64 residual ||E - A P|| / ||E|| <= 1e-5, with A applied by the oracle's
+host FFT matvec in complex128 (pinned to the direct pair sum in
+test_oracle_fft_baseline.py), plus an element-wise bound on the residual;
+efficiencies against the oracle's own solutions to 1e-10, stored by
+tests/golden/make_oracle_golden.py (which calls only the oracle), within
+1e-4 relative.
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import synth
-from oracle import dda
+from oracle import dda, fft_baseline
+
+sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+import make_oracle_golden as golden  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -18,6 +33,12 @@ WORKLOADS = {
     "box64_grid128": dict(n=64, m=1.5 + 0.1j, x=10.0),
     "box128_grid256": dict(n=128, m=1.33 + 0.01j, x=20.0),
 }
+
+
+def _gold(name, pol):
+    if not hasattr(_gold, "table"):
+        _gold.table = golden.read_golden()
+    return _gold.table[(name, pol)]
 
 
 @pytest.fixture(scope="module")
@@ -37,6 +58,29 @@ def _problem(name):
     return occ, r, comp, kd, w["m"]
 
 
+def _check_solution(tag, r, comp, m, kd, kh, e, P_gpu, st, q_gpu=None, q_ref=None):
+    """Full-vector residual with the oracle's FFT matvec, element-wise
+    residual bound, and the efficiencies against the oracle's solution."""
+    ainv = dda.site_inverse_polarizability(comp, m, kd, dda.ALPHA_LDR, kh, e)
+    E = dda.incident_field(r, kd, kh, e)
+    res = E - fft_baseline.FftDda(r, kd, ainv).matvec(P_gpu)
+    rel = np.linalg.norm(res) / np.linalg.norm(E)
+    # element-wise: no site carries more than a small multiple of the rms
+    # residual allowed by the 1e-5 bar (an error confined to a few sites, a
+    # parity class or the box edge would show here)
+    el = np.abs(res).max() / np.sqrt(np.mean(np.abs(E) ** 2))
+    print(f"[{tag}] full residual {rel:.3e} (library {st['rel_resid']:.3e}), max site residual / rms field "
+          f"{el:.3e}", flush=True)
+    assert rel <= 1e-5 * (1 + 1e-6)
+    assert abs(rel - st["rel_resid"]) <= 1e-9
+    assert el <= 2e-4
+    if q_ref is not None:
+        d = np.abs(np.asarray(q_gpu) - np.asarray(q_ref)) / np.abs(np.asarray(q_ref))
+        print(f"[{tag}] Q {np.round(q_gpu, 7)} oracle {np.round(q_ref, 7)} rel diff {d}", flush=True)
+        assert np.all(d[:2] <= 1e-4)  # Q_ext, Q_abs
+        assert d[2] <= 1e-4
+
+
 @pytest.mark.parametrize("name", list(WORKLOADS))
 def test_matvec_sampled_rows(ctx, name):
     import paper_1002_1505_amd as P
@@ -54,35 +98,71 @@ def test_matvec_sampled_rows(ctx, name):
     for prec, tol in ((P.DDA_FP64, 1e-12), (P.DDA_FP32, 5e-6)):
         y = ctx.matvec(x, ainv=[[ainv]], prec=prec)[0]
         err = np.sqrt(np.mean(np.abs(y[rows] - ref) ** 2)) / scale
-        print(f"[{name}] prec={prec} sampled rel err {err:.3e}", flush=True)
-        assert err < tol
+        emax = np.abs(y[rows] - ref).max() / scale
+        print(f"[{name}] prec={prec} sampled rel err {err:.3e} max {emax:.3e}", flush=True)
+        assert err < tol and emax < 5 * tol
 
 
 @pytest.mark.parametrize("name", list(WORKLOADS))
-def test_solve_sampled_residual_and_cross_sections(ctx, name):
+def test_solve_full_residual_and_cross_sections(ctx, name):
     import paper_1002_1505_amd as P
 
     occ, r, comp, kd, m = _problem(name)
     ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
-    n = len(r)
     khat, e0 = P.orientation_waves(0.4, 1.0, 0.3)
     Pg, st, status = ctx.solve(khat, e0, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE)
     print(f"[{name}] stats {st}", flush=True)
     assert status == 0
     q = ctx.cross_sections(2)
-    rng = np.random.default_rng(9)
-    rows = rng.choice(n, 48, replace=False)
     for l in range(2):
-        assert st[l]["rel_resid"] <= 1e-5
-        ainv = dda.site_inverse_polarizability(comp, [m], kd, dda.ALPHA_LDR, khat[l], e0[l])
-        E = dda.incident_field(r, kd, khat[l], e0[l])
-        # residual at sampled sites, relative to the rms field: consistent with
-        # a global relative residual <= 1e-5
-        AP = dda.matvec_rows(r, kd, ainv, Pg[l], rows)
-        rs = np.sqrt(np.mean(np.abs(E[rows] - AP) ** 2)) / np.sqrt(np.mean(np.abs(E) ** 2))
-        print(f"[{name}] pol {l} sampled residual {rs:.2e}", flush=True)
-        assert rs < 1e-4
-        # the library's reductions on its own P equal the oracle's sums on that P
-        qo = np.array(dda.cross_sections(kd, E, Pg[l], ainv))
-        assert np.all(np.abs(q[l] - qo) / np.abs(qo) < 1e-9)
+        ref = _gold("sphere64", l) if name == "box64_grid128" else None
+        _check_solution(f"{name} pol {l}", r, comp, [m], kd, khat[l], e0[l], Pg[l], st[l], q[l], ref)
         assert q[l, 1] > 0 and q[l, 2] > 0
+
+
+def test_worked_example_block_vs_oracle(ctx):
+    """The guide's worked example on the GPU (a 32 x 64 x 64 box runs the
+    generic-box kernels): residual and efficiencies against the oracle's
+    solution, and the printed efficiencies within the per-cent agreement of
+    LATTDR with the guide's GKDLDR run."""
+    import paper_1002_1505_amd as P
+
+    occ, m, kd, (b, t, p) = golden.case_inputs("block32x64x64")
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    khat, e0 = P.orientation_waves(b, t, p)
+    Pg, st, status = ctx.solve(khat, e0, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE)
+    assert status == 0
+    q = ctx.cross_sections(2)
+    for l in range(2):
+        _check_solution(f"block pol {l}", r, comp, [m], kd, khat[l], e0[l], Pg[l], st[l], q[l],
+                        _gold("block32x64x64", l))
+        assert np.all(np.abs(q[l] - [3.6494, 1.2208, 2.4287]) <= 0.015 * np.array([3.6494, 1.2208, 2.4287]))
+
+
+def test_mixed_box_batch_vs_oracle(ctx):
+    """Ellipsoids in 32^3, 48^3 and 64^3 boxes, one orientation x 2
+    polarizations each, solved in one call (one graph over the three
+    targets' groups): every rhs against the oracle."""
+    import paper_1002_1505_amd as P
+
+    cases = golden.mixed_batch()
+    kh, ee, tg = [], [], []
+    for t, (name, occ, m, kd, (b, th, ph)) in enumerate(cases):
+        if t == 0:
+            ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+        else:
+            ctx.add_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+        k2, e2 = P.orientation_waves(b, th, ph)
+        kh += list(k2)
+        ee += list(e2)
+        tg += [t, t]
+    Pg, st, status = ctx.solve(kh, ee, targets=tg, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE, max_iter=5000)
+    print(f"[mixed] iterations {[s['iters'] for s in st]}", flush=True)
+    assert status == 0
+    q = ctx.cross_sections(len(tg))
+    for i in range(len(tg)):
+        name, occ, m, kd, _ = cases[tg[i]]
+        r, comp, _ = dda.sites_from_occupancy(occ)
+        _check_solution(f"{name} pol {i % 2}", r, comp, [m], kd, kh[i], ee[i], Pg[i], st[i], q[i],
+                        _gold(name, i % 2))
