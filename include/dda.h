@@ -222,6 +222,29 @@ dda_status dda_solve_field(dda_ctx* ctx, int32_t nrhs, const dda_wave* waves, co
 dda_status dda_matvec(dda_ctx* ctx, int32_t target, int32_t nrhs, const double* ainv,
                       const void* x, void* y, uint32_t prec, uint32_t flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A x as
+ * dda_matvec computes it, with every intermediate (the site-ordered vectors,
+ * the spectrum slab, the FP32 copy of 1/alpha) in a fixed device array of
+ * DDA_NOALLOC_SCRATCH_BYTES per GPU, held from the first dda_create on that
+ * GPU until the process ends.  No hipMalloc, hipFree, allocating library call
+ * or synchronization: the work is enqueued on the context's stream and the
+ * call returns.
+ *   ainv  device pointer, [nrhs][ncomp] complex128 1/alpha per (rhs, composition)
+ *   x, y  device pointers, [nrhs][N][3] complex128 in the ABI site order
+ *   prec  DDA_FP32 or DDA_FP64 (the matvec's arithmetic)
+ * The target's spectrum for `prec` must exist (dda_build_green_fft or an
+ * earlier solve or matvec of that precision), else DDA_ERR_STATE; a call whose
+ * scratch need, nrhs x (spectrum slab + 2 vectors) in the precision of the
+ * matvec plus the 1/alpha copy, exceeds DDA_NOALLOC_SCRATCH_BYTES returns
+ * DDA_ERR_INVALID_ARG (64 MiB: e.g. 2 FP32 rhs of a 64^3 box, 13 of a 32^3
+ * box).  Every call on a GPU shares that GPU's scratch and leaves its
+ * contents behind: calls that overlap on one GPU (other contexts or streams)
+ * race and must be ordered by the caller. */
+#define DDA_NOALLOC_SCRATCH_BYTES (64u << 20)
+dda_status dda_matvec_noalloc(dda_ctx* ctx, int32_t target, int32_t nrhs, const void* ainv, const void* x, void* y,
+                              uint32_t prec);
+
 /* 1/alpha of every composition of a target for a wave (host arithmetic);
  * out: 2*ncomp doubles. */
 dda_status dda_inverse_polarizability(const dda_ctx* ctx, int32_t target, const dda_wave* wave,

@@ -86,6 +86,7 @@ SIGNATURES = {
     "dda_solve_field": (C.c_int32, [P, C.c_int32, C.POINTER(dda_wave), C.POINTER(dda_solve_opts), P, P, P,
                                     C.POINTER(dda_solve_stats)]),
     "dda_matvec": (C.c_int32, [P, C.c_int32, C.c_int32, D, P, P, C.c_uint32, C.c_uint32]),
+    "dda_matvec_noalloc": (C.c_int32, [P, C.c_int32, C.c_int32, P, P, P, C.c_uint32]),
     "dda_inverse_polarizability": (C.c_int32, [P, C.c_int32, C.POINTER(dda_wave), D]),
     "dda_cross_sections": (C.c_int32, [P, C.c_int32, D]),
     "dda_cross_sections_phi": (C.c_int32, [P, C.c_int32, C.c_int32, D, D]),

@@ -18,6 +18,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1017,6 +1018,34 @@ dda_status group_waves(dda_ctx* c, int nrhs, const dda_wave* waves) {
 // error text of a failed dda_create (there is no context to hold it)
 thread_local std::string g_create_err = "no error";
 
+// Device scratch of dda_matvec_noalloc: one array per GPU for the life of
+// the process.  Host code never passes its name to a kernel or a copy (on
+// the host the name is only a stand-in for the symbol); it uses the device
+// address that hipGetSymbolAddress returns for the current device, looked up
+// once per device by dda_create and kept in g_scratch_ptr.
+constexpr size_t NOALLOC_BYTES = (size_t)DDA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on `device` (the current device); looked up on
+// the first call per device.
+hipError_t scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
 }  // namespace
 
 // ===========================================================================
@@ -1049,6 +1078,8 @@ dda_status dda_create(dda_ctx** out, int32_t device, void* hip_stream) {
         c->own_stream = true;
     }
     hipError_t e1 = configure_fft_kernels(), e2 = configure_ct_kernels();
+    void* sp = nullptr;
+    if (e1 == hipSuccess && e2 == hipSuccess) e1 = scratch_address(device, &sp);
     if (e1 != hipSuccess || e2 != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess) {
         g_create_err = std::string("dda_create: kernel configuration failed: ") +
@@ -1620,6 +1651,59 @@ dda_status dda_matvec(dda_ctx* c, int32_t target, int32_t nrhs, const double* ai
     }
     HCHK(c, hipMemcpyAsync(y, dy.p, per * nrhs, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     HCHK(c, hipStreamSynchronize(st));
+    return DDA_OK;
+}
+
+dda_status dda_matvec_noalloc(dda_ctx* c, int32_t target, int32_t nrhs, const void* ainv, const void* x, void* y,
+                              uint32_t prec) {
+    SCHK(check_ctx(c));
+    if (target < 0 || target >= (int)c->tg.size() || nrhs <= 0 || !ainv || !x || !y)
+        return fail(c, DDA_ERR_INVALID_ARG, "matvec_noalloc: bad target/nrhs/pointers");
+    if (prec != DDA_FP32 && prec != DDA_FP64)
+        return fail(c, DDA_ERR_INVALID_ARG, "matvec_noalloc: prec must be FP32 or FP64");
+    Target& t = *c->tg[target];
+    if (!(prec == DDA_FP32 ? t.have32 : t.have64))
+        return fail(c, DDA_ERR_STATE, "matvec_noalloc: build the target's spectrum first (dda_build_green_fft)");
+    const size_t esz = prec == DDA_FP32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
+    const size_t b_ainv = prec == DDA_FP32 ? align256((size_t)nrhs * t.ncomp * sizeof(Cx<float>)) : 0;
+    const size_t b_vec = align256(vec_elems(t, nrhs) * esz);
+    const size_t b_slab = align256(slab_elems(t, nrhs) * esz);
+    const size_t need = b_ainv + 2 * b_vec + b_slab;
+    if (need > NOALLOC_BYTES)
+        return fail(c, DDA_ERR_INVALID_ARG, "matvec_noalloc: %d rhs of this target need %zu bytes of scratch, above the "
+                    "%zu-byte limit (use fewer rhs or dda_matvec)", nrhs, need, NOALLOC_BYTES);
+    void* base = nullptr;
+    {
+        // looked up by dda_create on this context's device
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = c->device < MAX_DEVICES ? g_scratch_ptr[c->device] : nullptr;
+    }
+    if (!base) return fail(c, DDA_ERR_STATE, "matvec_noalloc: no scratch address for device %d", c->device);
+    unsigned char* p = static_cast<unsigned char*>(base);
+    hipStream_t st = c->stream;
+    const Geo g = t.geo();
+    const Cx<double>* xin = static_cast<const Cx<double>*>(x);
+    Cx<double>* yout = static_cast<Cx<double>*>(y);
+    if (prec == DDA_FP64) {
+        Cx<double>* vx = reinterpret_cast<Cx<double>*>(p);
+        Cx<double>* vy = reinterpret_cast<Cx<double>*>(p + b_vec);
+        Cx<double>* slab = reinterpret_cast<Cx<double>*>(p + 2 * b_vec);
+        HCHK(c, launch_from_abi<double>(g, nrhs, xin, vx, st));
+        HCHK(c, launch_matvec<double>(g, t.tw<double>(), t.plans, t.shape<double>(), nrhs, vx, vy, nullptr, slab,
+                                      t.ghat_for<double>(t.shape<double>()), static_cast<const Cx<double>*>(ainv),
+                                      nullptr, MV_AX, st));
+        HCHK(c, launch_to_abi<double>(g, nrhs, vy, yout, st));
+    } else {
+        Cx<float>* a32 = reinterpret_cast<Cx<float>*>(p);
+        Cx<float>* vx = reinterpret_cast<Cx<float>*>(p + b_ainv);
+        Cx<float>* vy = reinterpret_cast<Cx<float>*>(p + b_ainv + b_vec);
+        Cx<float>* slab = reinterpret_cast<Cx<float>*>(p + b_ainv + 2 * b_vec);
+        HCHK(c, launch_demote_table(nrhs * t.ncomp, static_cast<const Cx<double>*>(ainv), a32, st));
+        HCHK(c, launch_from_abi<float>(g, nrhs, xin, vx, st));
+        HCHK(c, launch_matvec<float>(g, t.tw<float>(), t.plans, t.shape<float>(), nrhs, vx, vy, nullptr, slab,
+                                     t.ghat_for<float>(t.shape<float>()), a32, nullptr, MV_AX, st));
+        HCHK(c, launch_to_abi<float>(g, nrhs, vy, yout, st));
+    }
     return DDA_OK;
 }
 

@@ -191,6 +191,8 @@ hipError_t launch_state_init(int Npad, int nrhs, BiState* s, const double* parti
 // r32 = r64 * scale[rhs] (scale = 1/||r||); x64 += (1/scale[rhs]) * d32
 hipError_t launch_demote(int Npad, int nrhs, const Cx<double>* r64, Cx<float>* r32, const double* scale,
                          const int* mask, hipStream_t st);
+// out[i] = in[i] rounded to FP32, i < n (a 1/alpha table)
+hipError_t launch_demote_table(int n, const Cx<double>* in, Cx<float>* out, hipStream_t st);
 // Both skip a rhs whose inner solve ended with a non-finite recursive
 // residual (st[rhs].rr), so that x64 keeps its last finite value.
 hipError_t launch_promote_add(int Npad, int nrhs, Cx<double>* x64, const Cx<float>* d32, const double* scale,

@@ -953,6 +953,14 @@ hipError_t launch_demote(int Npad, int nrhs, const Cx<double>* r64, Cx<float>* r
     hipLaunchKernelGGL(k_demote, dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, r64, r32, scale, mask);
     return hipGetLastError();
 }
+__global__ void k_demote_table(int n, const Cx<double>* __restrict__ in, Cx<float>* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = Cx<float>{(float)in[i].re, (float)in[i].im};
+}
+hipError_t launch_demote_table(int n, const Cx<double>* in, Cx<float>* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_demote_table, dim3((n + 255) / 256), dim3(256), 0, st, n, in, out);
+    return hipGetLastError();
+}
 hipError_t launch_promote_add(int Npad, int nrhs, Cx<double>* x64, const Cx<float>* d32, const double* scale,
                               const int* mask, const BiState* bst, hipStream_t st) {
     hipLaunchKernelGGL(k_promote_add, dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, x64, d32, scale, mask,
