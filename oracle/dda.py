@@ -318,6 +318,89 @@ def bicgstab(matvec, b, x0=None, tol=1e-10, max_iter=10000):
     return x, {"iters": it, "matvecs": nmv, "rel_resid": float(np.linalg.norm(r_true) / nb)}
 
 
+def bicgstab_l(matvec, b, ell=2, x0=None, tol=1e-10, max_iter=10000, keep_residuals=False):
+    """BiCGstab(ell) for a general complex system A x = b (Sleijpen & Fokkema
+    1993): each cycle takes ell BiCG steps, keeping the residuals r_0..r_ell
+    and directions u_0..u_ell = A^i applied to the cycle's first ones, then
+    replaces the ell one-dimensional minimisations of BiCGstab by one
+    minimisation of ||r_0 - sum_j gamma_j r_j|| over a polynomial of degree
+    ell (modified Gram-Schmidt on r_1..r_ell).  ell = 1 is BiCGstab.  The
+    guide's default solver PBCGS2 is this method with ell = 2 (the routine
+    ZBCG2, after Fokkema's thesis and Sleijpen & van der Vorst; "Choice of
+    Iterative Algorithm").
+
+    Inner products (a, b) = a^H b.  Stops at the end of the first cycle with
+    ||r_0|| / ||b|| <= tol (r_0 is the residual of the current x throughout)
+    or with max_iter BiCG steps taken, and recomputes the true residual at
+    the end.  Returns (x, info) with info = {iters (BiCG steps, 2 matvecs
+    each), matvecs, rel_resid} and info["residuals"], the recursive residual
+    norms at the start and after each cycle, if keep_residuals."""
+    b = np.asarray(b, dtype=np.complex128).reshape(-1)
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.complex128).reshape(-1).copy()
+    nb = np.linalg.norm(b)
+    if nb == 0:
+        return x, {"iters": 0, "matvecs": 0, "rel_resid": 0.0}
+    r = [b - matvec(x)] + [None] * ell
+    u = [np.zeros_like(b)] + [None] * ell
+    nmv = 1
+    rt = r[0].copy()  # shadow residual
+    rho0, alpha, omega = 1.0 + 0j, 0.0 + 0j, 1.0 + 0j
+    hist = [np.linalg.norm(r[0]) / nb]
+    it = 0
+    done = hist[0] <= tol
+    while not done:
+        rho0 = -omega * rho0
+        # BiCG part
+        for j in range(ell):
+            rho1 = np.vdot(rt, r[j])
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                u[i] = r[i] - beta * u[i]
+            u[j + 1] = matvec(u[j])
+            gamma = np.vdot(rt, u[j + 1])
+            alpha = rho0 / gamma
+            for i in range(j + 1):
+                r[i] = r[i] - alpha * u[i + 1]
+            r[j + 1] = matvec(r[j])
+            x = x + alpha * u[0]
+            nmv += 2
+            it += 1
+        # MR part: modified Gram-Schmidt on r_1..r_ell, then the polynomial
+        tau = np.zeros((ell + 1, ell + 1), dtype=np.complex128)
+        sigma = np.zeros(ell + 1)
+        gp = np.zeros(ell + 1, dtype=np.complex128)
+        for j in range(1, ell + 1):
+            for i in range(1, j):
+                tau[i, j] = np.vdot(r[i], r[j]) / sigma[i]
+                r[j] = r[j] - tau[i, j] * r[i]
+            sigma[j] = np.vdot(r[j], r[j]).real
+            gp[j] = np.vdot(r[j], r[0]) / sigma[j]
+        g = np.zeros(ell + 1, dtype=np.complex128)
+        g[ell] = gp[ell]
+        omega = g[ell]
+        for j in range(ell - 1, 0, -1):
+            g[j] = gp[j] - sum(tau[j, i] * g[i] for i in range(j + 1, ell + 1))
+        gpp = np.zeros(ell + 1, dtype=np.complex128)
+        for j in range(1, ell):
+            gpp[j] = g[j + 1] + sum(tau[j, i] * g[i + 1] for i in range(j + 1, ell))
+        x = x + g[1] * r[0]
+        r[0] = r[0] - gp[ell] * r[ell]
+        u[0] = u[0] - g[ell] * u[ell]
+        for j in range(1, ell):
+            u[0] = u[0] - g[j] * u[j]
+            x = x + gpp[j] * r[j]
+            r[0] = r[0] - gp[j] * r[j]
+        hist.append(np.linalg.norm(r[0]) / nb)
+        done = hist[-1] <= tol or it >= max_iter
+    r_true = b - matvec(x)
+    nmv += 1
+    info = {"iters": it, "matvecs": nmv, "rel_resid": float(np.linalg.norm(r_true) / nb)}
+    if keep_residuals:
+        info["residuals"] = hist
+    return x, info
+
+
 def cocg(matvec, b, x0=None, tol=1e-10, max_iter=10000, keep_residuals=False):
     """Conjugate orthogonal conjugate gradients for a complex symmetric
     A = A^T (the DDA matrix is one: A_jl = A_lj^T, and its diagonal is

@@ -58,3 +58,39 @@ def test_cocg_and_bicgstab_matvec_counts(m, k):
     _, ib = dda.bicgstab(mv, E.reshape(-1), tol=1e-5)
     assert ic["rel_resid"] <= 1e-5 and ib["rel_resid"] <= 1e-5
     assert ic["matvecs"] <= 1.5 * ib["matvecs"] and ib["matvecs"] <= 1.5 * ic["matvecs"], (ic, ib)
+
+
+def _small_system(seed, m=1.7 + 0.02j, kd=0.5):
+    occ = synth.ellipsoid_occupancy((10, 12, 8), (9.5, 11.5, 7.5))
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    kh, es, _ = dda.waves_for_orientation(0.3 + seed, 0.8, 0.1)
+    ainv = dda.site_inverse_polarizability(comp, [m], kd, dda.ALPHA_LDR, kh, es[0])
+    E = dda.incident_field(r, kd, kh, es[0]).reshape(-1)
+    A = dda.dense_matrix(r, kd, ainv)
+    return A, E
+
+
+def test_bicgstab_ell_one_is_bicgstab():
+    """BiCGstab(1) takes the same iterates as BiCGstab (two independent codes
+    of the same recurrences), cycle by cycle."""
+    A, E = _small_system(0)
+    mv = lambda v: A @ v
+    for k in (1, 2, 5, 10):
+        x1, _ = dda.bicgstab_l(mv, E, ell=1, tol=0, max_iter=k)
+        x2, _ = dda.bicgstab(mv, E, tol=0, max_iter=k)
+        assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x2), k
+
+
+@pytest.mark.parametrize("ell", [1, 2, 4])
+def test_bicgstab_ell_solves_the_dense_system(ell):
+    """BiCGstab(ell) reaches the LU solution; its recursive residual r_0 is
+    the residual of its iterate (the true residual agrees at the end); the
+    iteration count is a multiple of ell (convergence is checked at the end
+    of a cycle)."""
+    A, E = _small_system(1)
+    Pd = np.linalg.solve(A, E)
+    x, info = dda.bicgstab_l(lambda v: A @ v, E, ell=ell, tol=1e-10, keep_residuals=True)
+    assert info["rel_resid"] <= 1e-10 * 1.01
+    assert np.linalg.norm(x - Pd) <= 1e-8 * np.linalg.norm(Pd)
+    assert abs(info["residuals"][-1] - info["rel_resid"]) <= 1e-12
+    assert info["iters"] % ell == 0 and info["matvecs"] == 2 * info["iters"] + 2  # + initial and final residual
