@@ -165,6 +165,38 @@ def inverse_polarizability(m, k, kind=ALPHA_LDR, khat=None, e=None):
     raise ValueError(kind)
 
 
+def dielectric_frame(theta_df, phi_df, beta_df):
+    """Target-frame components of the principal axes e_1, e_2, e_3 of a
+    dielectric tensor whose Dielectric Frame is rotated by (Theta_DF, Phi_DF,
+    beta_DF) from the Target Frame ("Composite Targets with Anisotropic
+    Constituents": rotate by Theta_DF about y_TF, by Phi_DF about x_TF, then
+    by beta_DF about e_1; the guide's expansion of e_1, e_2, e_3).  Returns a
+    (3, 3) array whose rows are e_1, e_2, e_3."""
+    ct, st = np.cos(theta_df), np.sin(theta_df)
+    cp, sp = np.cos(phi_df), np.sin(phi_df)
+    cb, sb = np.cos(beta_df), np.sin(beta_df)
+    e1 = np.array([ct, st * cp, st * sp])
+    e2 = np.array([-st * cb, ct * cb * cp - sb * sp, ct * cb * sp + sb * cp])
+    e3 = np.array([st * sb, -(ct * sb * cp + cb * sp), -(ct * sb * sp - cb * cp)])
+    return np.stack([e1, e2, e3])
+
+
+def anisotropic_inverse_polarizability(m3, angles, k, kind=ALPHA_LDR, khat=None, e=None):
+    """Target-frame 3 x 3 tensor 1/alpha of a material with refractive index
+    m3[j] along principal axis e_j of its Dielectric Frame (angles =
+    (Theta_DF, Phi_DF, beta_DF), see dielectric_frame).  The polarizability
+    is diagonal in the DF, each element from the prescription with eps_j =
+    m3[j]^2 (for LDR with the incident k and polarization as for an
+    isotropic site, S taken in the target frame of the lattice); in the TF
+    alpha = sum_j alpha_j e_j e_j^T, so 1/alpha = sum_j (1/alpha_j) e_j e_j^T.
+    Reading: the guide defines R_ij = x_i . e_j and writes alpha_TF = R
+    alpha_DF R^-1 (a symmetric tensor), which is this sum; its printed matrix
+    is the transpose of that definition."""
+    ef = dielectric_frame(*angles)
+    inv = [inverse_polarizability(mj, k, kind, khat, e) for mj in m3]
+    return sum(inv[j] * np.outer(ef[j], ef[j]) for j in range(3))
+
+
 def site_inverse_polarizability(comp, m_list, k, kind=ALPHA_LDR, khat=None, e=None):
     """Per-site 1/alpha (N,) from composition ids (1-based) and m per composition."""
     table = np.array([inverse_polarizability(mm, k, kind, khat, e) for mm in m_list])
@@ -190,7 +222,8 @@ def interaction_block(rvec, k):
 
 
 def dense_matrix(r, k, ainv):
-    """The 3N x 3N matrix A of eq. AP=E, site-major (row 3 j + a)."""
+    """The 3N x 3N matrix A of eq. AP=E, site-major (row 3 j + a).  ainv is
+    1/alpha per site, (N,), or the per-site 3 x 3 tensor, (N, 3, 3)."""
     r = np.asarray(r, dtype=np.float64)
     n = len(r)
     A = np.zeros((3 * n, 3 * n), dtype=np.complex128)
@@ -209,8 +242,14 @@ def dense_matrix(r, k, ainv):
             np.fill_diagonal(blk, 0.0)
             A[a::3, b::3] = blk
     idx = np.arange(n)
-    for a in range(3):
-        A[3 * idx + a, 3 * idx + a] = ainv
+    ainv = np.asarray(ainv)
+    if ainv.ndim == 3:  # per-site 3 x 3 blocks (anisotropic sites)
+        for a in range(3):
+            for b in range(3):
+                A[3 * idx + a, 3 * idx + b] = ainv[:, a, b]
+    else:
+        for a in range(3):
+            A[3 * idx + a, 3 * idx + a] = ainv
     return A
 
 
@@ -475,13 +514,22 @@ def cross_sections(k, E, P, ainv, n_dipoles=None):
 
     C_ext = 4 pi k sum_j Im(E_j^* . P_j)
     C_abs = 4 pi k sum_j [ Im(P_j . conj(1/alpha_j) P_j^*) - (2/3) k^3 |P_j|^2 ]
+
+    ainv: 1/alpha per site (N,), or per-site 3 x 3 tensors (N, 3, 3), for
+    which P_j . conj(1/alpha_j) P_j^* is the quadratic form.
     """
     E = np.asarray(E, dtype=np.complex128)
     P = np.asarray(P, dtype=np.complex128)
     n = len(P) if n_dipoles is None else n_dipoles
     cext = 4.0 * np.pi * k * np.sum(np.imag(np.conj(E) * P))
     p2 = np.sum(np.abs(P) ** 2, axis=1)
-    cabs = 4.0 * np.pi * k * np.sum(np.imag(np.conj(ainv)) * p2 - (2.0 / 3.0) * k ** 3 * p2)
+    ainv = np.asarray(ainv)
+    if ainv.ndim == 3:
+        # tensor 1/alpha: Im(P . (1/alpha)^* P^*) = Im(P^T conj(T) conj(P))
+        quad = np.einsum("ja,jab,jb->j", P, np.conj(ainv), np.conj(P))
+        cabs = 4.0 * np.pi * k * np.sum(np.imag(quad) - (2.0 / 3.0) * k ** 3 * p2)
+    else:
+        cabs = 4.0 * np.pi * k * np.sum(np.imag(np.conj(ainv)) * p2 - (2.0 / 3.0) * k ** 3 * p2)
     area = np.pi * effective_radius(n) ** 2
     qext, qabs = cext / area, cabs / area
     return float(qext), float(qabs), float(qext - qabs)
