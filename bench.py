@@ -501,11 +501,15 @@ def learned_vs_plain(P, ctx, a):
     guess_ms = {m: 0.0 for m, _ in modes}
     for _ in range(a.eval_targets):
         occ, m, kd = _aggregate_problem(synth, rng)
-        ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
         ori = synth.theta_sweep(a.sweep, beta=rng.uniform(0, 2 * np.pi), phi=rng.uniform(0, 2 * np.pi))
         waves = [P.orientation_waves(b, t, p) for b, t, p in ori]
-        ctx.solve(waves[0][0], waves[0][1], want_p=False)  # warm-up (workspace, graph)
         for mode, g in modes:
+            # every mode starts from the same state: the target defined anew
+            # (which clears the slots' history of earlier solutions), its
+            # spectrum built and one warm-up solve, outside the timed sweep
+            ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+            ctx.build_green_fft(P.DDA_FP32 | P.DDA_FP64)
+            ctx.solve(waves[0][0], waves[0][1], want_p=False)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             for i, (kh, ee) in enumerate(waves):

@@ -117,11 +117,22 @@ typedef struct {
     int32_t graph_iters;  /* BiCGstab iterations per graph replay; 0 = autotuned/default */
     int32_t history;      /* 0..4: keep the solutions of the last `history` solves of every slot
                              (for DDA_GUESS_PROJECT and the learned guess); 0 clears them */
-    int32_t restart_every; /* test hook: force the breakdown restart of the inner BiCGstab
-                              (rhat = p = r) after every restart_every-th iteration; 0 = never
-                              (normal operation), < 0 is DDA_ERR_INVALID_ARG */
-    int32_t reserved;
+    int32_t restart_every; /* test hook: force the breakdown restart of the inner Krylov solver
+                              (BiCGstab: rhat = p = r after every restart_every-th iteration;
+                              BiCGstab(2): rt = r0 at the next cycle once the BiCG step count is a
+                              multiple of it); 0 = never (normal operation), < 0 is
+                              DDA_ERR_INVALID_ARG */
+    int32_t solver;        /* DDA_SOLVER_*: inner Krylov method */
 } dda_solve_opts;
+
+/* Inner Krylov methods (guide, section "Choice of Iterative Algorithm"). */
+enum {
+    DDA_SOLVER_BICGSTAB = 0,  /* BiCGstab (van der Vorst 1992), fused into the matvec passes */
+    DDA_SOLVER_BICGSTAB2 = 1  /* BiCGstab(2) (Sleijpen & Fokkema 1993), the guide's PBCGS2:
+                                 cycles of two BiCG steps and a degree-2 minimal-residual step;
+                                 iteration counts are BiCG steps (two matvecs each), convergence is
+                                 checked at the end of a cycle */
+};
 
 typedef struct {
     int32_t iters;        /* BiCGstab iterations taken */
@@ -165,6 +176,30 @@ dda_status dda_add_target(dda_ctx* ctx, const int32_t dims[3], const uint8_t* oc
 /* Number of occupied sites N and the effective radius a_eff = (3N/4pi)^(1/3)
  * (guide, section "Applicability of the DDA") of a target. */
 dda_status dda_target_info(const dda_ctx* ctx, int32_t target, int64_t* n_sites, double* aeff);
+
+/*
+ * Make composition `comp` (1..ncomp) of a target anisotropic (guide, section
+ * "Composite Targets with Anisotropic Constituents"): a dielectric tensor that
+ * is diagonal in its Dielectric Frame, with principal refractive indices
+ * m3[0..2] ((re, im) x 3, eps_j = m_j^2) along the frame's axes e_1, e_2,
+ * e_3, the frame rotated from the target frame by angles[] = {Theta_DF,
+ * Phi_DF, beta_DF} (radians; e_j in target-frame components as the guide
+ * expands them).  Each site of the composition then has the symmetric
+ * polarizability tensor sum_j alpha_j e_j e_j^T, alpha_j from the target's
+ * prescription with eps_j (LDR with the wave's S, taken in the target frame),
+ * in the diagonal term of A and in the absorption sum
+ * C_abs = 4 pi k sum_j [Im(P_j . (1/alpha_j)^* P_j^*) - (2/3) k^3 |P_j|^2].
+ * The composition's isotropic m from dda_set_target is no longer used.
+ * Anisotropic targets are solved without the matvec passes' fused inner
+ * products; the guesses PREV_SHIFT, PROJECT and NN and
+ * dda_cross_sections_phi are refused for them (DDA_ERR_INVALID_ARG), and
+ * dda_matvec takes their tensors for the wave khat = x, e0 = y (its ainv
+ * entries of these compositions are not used).  Clears the context's solve
+ * state (groups, previous solutions).  Returns DDA_WARN_MKD_GE_1 when
+ * max_j |m_j| k d >= 1; DDA_ERR_INVALID_ARG for an unknown target or
+ * composition, null pointers or non-finite values.
+ */
+dda_status dda_set_anisotropic(dda_ctx* ctx, int32_t target, int32_t comp, const double* m3, const double* angles);
 
 /* Build the FFT of the Green's tensor on the doubled grid for every target
  * whose spectrum is missing or stale.  Always computed in FP64; `prec` selects

@@ -14,7 +14,8 @@ from . import _lib as L
 from ._lib import (DDA_ALPHA_CM, DDA_ALPHA_CM_RR, DDA_ALPHA_LDR, DDA_DEVICE_PTRS, DDA_FP32, DDA_FP64,  # noqa: F401
                    DDA_GUESS_NN, DDA_GUESS_PREV, DDA_GUESS_PREV_SHIFT, DDA_GUESS_PROJECT, DDA_GUESS_USER,
                    DDA_GUESS_ZERO, DDA_NO_FALLBACK, DDA_NO_GRAPH,
-                   DDA_SOLVE_FP32_REFINE, DDA_SOLVE_FP64, DDA_WARN_MKD_GE_1, DDA_WARN_NOT_CONVERGED)
+                   DDA_SOLVE_FP32_REFINE, DDA_SOLVE_FP64, DDA_SOLVER_BICGSTAB, DDA_SOLVER_BICGSTAB2,
+                   DDA_WARN_MKD_GE_1, DDA_WARN_NOT_CONVERGED)
 
 __all__ = ["Context", "DDAError", "lab_frame", "mueller", "orientation_waves", "scattering_frame", "load_library"]
 
@@ -124,6 +125,15 @@ class Context:
         _check(self.h, self.lib.dda_target_info(self.h, int(target), C.byref(n), C.byref(a)))
         return int(n.value), float(a.value)
 
+    def set_anisotropic(self, comp, m3, angles, target: int = 0) -> int:
+        """Composition `comp` (1-based) anisotropic: principal refractive
+        indices m3 (3 complex) along the Dielectric Frame axes, frame angles
+        (Theta_DF, Phi_DF, beta_DF) in radians (dda_set_anisotropic)."""
+        mm = np.asarray(m3, dtype=np.complex128).reshape(3)
+        marr = np.ascontiguousarray(np.stack([mm.real, mm.imag], axis=1).reshape(-1))
+        ang = np.ascontiguousarray(np.asarray(angles, dtype=np.float64).reshape(3))
+        return _check(self.h, self.lib.dda_set_anisotropic(self.h, int(target), int(comp), _dptr(marr), _dptr(ang)))
+
     def build_green_fft(self, prec=DDA_FP32 | DDA_FP64):
         return _check(self.h, self.lib.dda_build_green_fft(self.h, int(prec)))
 
@@ -137,7 +147,7 @@ class Context:
     # -- solve -----------------------------------------------------------
     def solve(self, khat, e0, targets=None, tol=1e-5, max_iter=1000, guess=DDA_GUESS_ZERO,
               prec=DDA_SOLVE_FP32_REFINE, p0=None, want_p=True, flags=0, graph_iters=0, history=0, e_inc=None,
-              restart_every=0):
+              restart_every=0, solver=DDA_SOLVER_BICGSTAB):
         """Solve A P = E_inc for each wave; returns (P or None, stats list, status).
 
         P is a list of (N_t, 3) complex128 arrays (one per wave).  With e_inc
@@ -146,7 +156,8 @@ class Context:
         targets and polarizabilities only."""
         arr, n = _waves(khat, e0, targets)
         opts = L.dda_solve_opts(tol=tol, max_iter=max_iter, guess=guess, prec=prec, flags=flags,
-                                graph_iters=graph_iters, history=history, restart_every=restart_every)
+                                graph_iters=graph_iters, history=history, restart_every=restart_every,
+                                solver=solver)
         tg = [arr[i].target for i in range(n)]
         sizes = [self.n_sites.get(t, 0) for t in tg]  # unknown ids: the library rejects the call
         p0buf = None

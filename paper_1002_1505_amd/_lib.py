@@ -39,6 +39,9 @@ DDA_GUESS_NN = 3
 DDA_GUESS_PREV_SHIFT = 4
 DDA_GUESS_PROJECT = 5
 
+DDA_SOLVER_BICGSTAB = 0
+DDA_SOLVER_BICGSTAB2 = 1
+
 DDA_DEVICE_PTRS = 1
 DDA_NO_GRAPH = 2
 DDA_NO_FALLBACK = 4
@@ -51,7 +54,7 @@ class dda_wave(C.Structure):
 class dda_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("guess", C.c_int32), ("prec", C.c_int32),
                 ("flags", C.c_uint32), ("graph_iters", C.c_int32), ("history", C.c_int32),
-                ("restart_every", C.c_int32), ("reserved", C.c_int32)]
+                ("restart_every", C.c_int32), ("solver", C.c_int32)]
 
 
 class dda_solve_stats(C.Structure):
@@ -81,6 +84,7 @@ SIGNATURES = {
                                    C.POINTER(C.c_int32)]),
     "dda_target_info": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64), D]),
     "dda_build_green_fft": (C.c_int32, [P, C.c_uint32]),
+    "dda_set_anisotropic": (C.c_int32, [P, C.c_int32, C.c_int32, D, D]),
     "dda_solve": (C.c_int32, [P, C.c_int32, C.POINTER(dda_wave), C.POINTER(dda_solve_opts), P, P,
                               C.POINTER(dda_solve_stats)]),
     "dda_solve_field": (C.c_int32, [P, C.c_int32, C.POINTER(dda_wave), C.POINTER(dda_solve_opts), P, P, P,

@@ -9,6 +9,7 @@
 // matvec, recomputes the residual b - A x with the FP64 matvec, and refines x
 // in FP64 until the FP64 residual meets the tolerance.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
@@ -32,7 +33,7 @@ hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, co
                          const Cx<double>* x64, const Cx<float>* esh, const Cx<float>* rf, float rscale,
                          hipStream_t st);
 hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves, const double* ainv, int nr,
-                          const Cx<float>* esh, const Cx<float>* rf, const float* rscale, Cx<double>* x64,
+                          const Cx<float>* esh, const Cx<float>* rf, const double* rn2, Cx<double>* x64,
                           hipStream_t st);
 
 namespace {
@@ -105,6 +106,13 @@ struct Target {
     int n[3] = {0, 0, 0};
     int N = 0, Npad = 0, ncomp = 0;
     std::vector<cd> m;
+    // anisotropic compositions: principal refractive indices and the
+    // Dielectric Frame angles (Theta_DF, Phi_DF, beta_DF); aniso[c] = 0 for
+    // isotropic compositions
+    std::vector<char> aniso;
+    std::vector<std::array<cd, 3>> m3;
+    std::vector<std::array<double, 3>> dfang;
+    bool any_aniso = false;
     double kd = 0;
     int alpha_kind = DDA_ALPHA_LDR;
     double origin[3] = {0, 0, 0};
@@ -173,13 +181,18 @@ struct Group {
     DevMem kv[8];  // inner Krylov vectors x r rhat p v s t p' (kprec precision)
     DevMem slab32, slab64;
     DevMem state, active, partials, scale, tolrel2, maxit, norms, mask;
+    // tensor 1/alpha of anisotropic compositions per (slot, composition), 6
+    // complex (xx, xy, xz, yy, yz, zz), zero for isotropic ones
+    DevMem aten64, aten32;
+    std::vector<cd> haten;
+    std::vector<Cx<float>> haten32;
     // per-iteration recursive residuals of the inner solve (DDA_TRACE), [nr][tcap]
     DevMem trace;
     int tcap = 0;
     // previous solve of the same slots: waves and 1/alpha; the local field
     // (1/alpha) P0 of the least-squares guess, its residual field E - A P0
     // (FP32) and the rms of that residual per slot, inputs of the learned guess
-    DevMem wprev, ainvprev, esh, rf;
+    DevMem wprev, ainvprev, esh, rf, rfn2;  // rfn2: ||E - A P0||^2 per slot (FP32 field, FP64 sum)
     std::vector<float> hrscale;
     bool has_r = false;
     // ring of the last `hdepth` solutions of every slot with their waves and
@@ -188,8 +201,6 @@ struct Group {
     DevMem hx[HIST_MAX], hwv[HIST_MAX], hainvv[HIST_MAX];
     int hdepth = 0, hn = 0, hhead = 0;
     DevMem pv32, pw32, pcoef, gpart;
-    std::vector<double> hgram;
-    std::vector<Cx<double>> hcoef;
     // host staging buffers of asynchronous uploads (must outlive the copies)
     std::vector<WaveDev> hw;
     std::vector<cd> hainv;  // [nr][ncomp]
@@ -233,6 +244,9 @@ struct dda_ctx {
     double ms_guess = 0;
     // test hook of the solve options: forced restart period of the inner BiCGstab
     int force_restart = 0;
+    // inner Krylov method (DDA_SOLVER_*) of the solve in progress
+    int solver = 0;
+    int gkey_solver = -1;
     // DDA_TRACE: file receiving the per-iteration residuals of every solve
     std::string trace_path;
     long long ncalls = 0;
@@ -480,6 +494,10 @@ dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint
     t.ncomp = ncomp;
     t.m.assign(ncomp, cd(0, 0));
     for (int i = 0; i < ncomp; ++i) t.m[i] = cd(m[2 * i], m[2 * i + 1]);
+    t.aniso.assign(ncomp, 0);
+    t.m3.assign(ncomp, std::array<cd, 3>{});
+    t.dfang.assign(ncomp, std::array<double, 3>{});
+    t.any_aniso = false;
     t.kd = kd;
     t.alpha_kind = alpha_kind;
     if (origin) {
@@ -567,6 +585,49 @@ cd inverse_alpha(cd mm, double kd, int kind, const double* khat, const double* e
     return inv + (LDR_B1 + eps * LDR_B2 + eps * LDR_B3 * S) * (kd * kd) + rr;
 }
 
+// Target-frame tensor 1/alpha of an anisotropic composition: the principal
+// axes e_1, e_2, e_3 of its Dielectric Frame (the guide's expansion in the
+// Target Frame for angles Theta_DF, Phi_DF, beta_DF), 1/alpha_j from the
+// prescription with eps_j = m_j^2 (for LDR with the wave's S, taken in the
+// target frame), and 1/alpha = sum_j (1/alpha_j) e_j e_j^T.  out: 6 entries
+// (xx, xy, xz, yy, yz, zz).
+void aniso_inverse_alpha(const std::array<cd, 3>& m3, const std::array<double, 3>& ang, double kd, int kind,
+                         const double* khat, const double* e, cd* out) {
+    const double ct = std::cos(ang[0]), st = std::sin(ang[0]), cp = std::cos(ang[1]), sp = std::sin(ang[1]);
+    const double cb = std::cos(ang[2]), sb = std::sin(ang[2]);
+    const double ax[3][3] = {{ct, st * cp, st * sp},
+                             {-st * cb, ct * cb * cp - sb * sp, ct * cb * sp + sb * cp},
+                             {st * sb, -(ct * sb * cp + cb * sp), -(ct * sb * sp - cb * cp)}};
+    cd inv[3];
+    for (int j = 0; j < 3; ++j) inv[j] = inverse_alpha(m3[j], kd, kind, khat, e);
+    const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int q = 0; q < 6; ++q) {
+        cd v = 0;
+        for (int j = 0; j < 3; ++j) v += inv[j] * (ax[j][ia[q]] * ax[j][ib[q]]);
+        out[q] = v;
+    }
+}
+
+// Tensor and scalar 1/alpha tables of a group for its waves: anisotropic
+// compositions get a zero scalar entry (the matvec passes then add nothing)
+// and their tensor; isotropic ones a zero tensor.
+void aniso_tables(const Target& t, Group& g, const dda_wave* waves_of_slot) {
+    g.haten.assign((size_t)g.nr * t.ncomp * 6, cd(0, 0));
+    g.haten32.assign(g.haten.size(), Cx<float>{0, 0});
+    for (int s = 0; s < g.nr; ++s) {
+        const dda_wave& w = waves_of_slot[s];
+        for (int q = 0; q < t.ncomp; ++q) {
+            if (!t.aniso[q]) continue;
+            cd* o = &g.haten[((size_t)s * t.ncomp + q) * 6];
+            aniso_inverse_alpha(t.m3[q], t.dfang[q], t.kd, t.alpha_kind, w.khat, w.e0, o);
+            for (int k = 0; k < 6; ++k)
+                g.haten32[((size_t)s * t.ncomp + q) * 6 + k] = Cx<float>{(float)o[k].real(), (float)o[k].imag()};
+            g.hainv[(size_t)s * t.ncomp + q] = 0;
+            g.hainv32[(size_t)s * t.ncomp + q] = Cx<float>{0, 0};
+        }
+    }
+}
+
 dda_status check_ctx(dda_ctx* c) {
     if (!c) return DDA_ERR_INVALID_ARG;
     hipError_t e = hipSetDevice(c->device);
@@ -631,8 +692,14 @@ hipError_t matvec_group(const Target& t, Group& g, int nr, const Cx<T>* x, Cx<T>
                         MvUpd upd = MvUpd{0, nullptr, nullptr, nullptr, nullptr, nullptr}) {
     Cx<T>* slab = std::is_same<T, double>::value ? g.slab64.as<Cx<T>>() : g.slab32.as<Cx<T>>();
     const Cx<T>* ainv = std::is_same<T, double>::value ? g.ainv64.as<Cx<T>>() : g.ainv32.as<Cx<T>>();
-    return launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab, t.ghat_for<T>(t.shape<T>()), ainv, active,
-                            mode, st, dot, upd);
+    // the passes' fused inner products and updates would miss the tensor part
+    // of an anisotropic diagonal, which is added after them
+    if (t.any_aniso && (dot.dot || upd.mode)) return hipErrorNotSupported;
+    hipError_t e = launch_matvec<T>(t.geo(), t.tw<T>(), t.plans, t.shape<T>(), nr, x, y, b, slab,
+                                    t.ghat_for<T>(t.shape<T>()), ainv, active, mode, st, dot, upd);
+    if (e != hipSuccess || !t.any_aniso) return e;
+    const Cx<T>* aten = std::is_same<T, double>::value ? g.aten64.as<Cx<T>>() : g.aten32.as<Cx<T>>();
+    return launch_aniso_diag<T>(t.geo(), nr, x, y, aten, mode == MV_RESID ? -1 : 1, st);
 }
 
 size_t slab_elems(const Target& t, int nr) { return (size_t)nr * 3 * 4 * t.n[0] * t.n[1] * t.n[2]; }
@@ -705,7 +772,7 @@ hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st, int k, const std::vecto
         int* act = g.active.as<int>();
         double* part = g.partials.as<double>();
         hipError_t e;
-        const bool fuse = (t.shape<T>().ct & 1) != 0;
+        const bool fuse = (t.shape<T>().ct & 1) != 0 && !t.any_aniso;
         const int nbv = vec_blocks(Np), nbp = fuse ? 12 * t.n[0] : nbv;
         if (!fuse) pin = pout = g.kv[3].as<Cx<T>>();  // separate update kernel works in place
         if (fuse) {
@@ -744,6 +811,64 @@ hipError_t enqueue_iteration(dda_ctx* c, hipStream_t st, int k, const std::vecto
     return hipSuccess;
 }
 
+// One BiCGstab(2) cycle (two BiCG steps, one minimal-residual step of
+// degree 2; the guide's PBCGS2) for every live group (precision T).  With the
+// specialised plane kernels the inner products of each matvec are formed by
+// its inverse pass; otherwise by separate reductions in the same layout.
+template <class T>
+hipError_t enqueue_cycle_l2(dda_ctx* c, hipStream_t st, const std::vector<char>& live) {
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        if (!live[gi]) continue;
+        Group& g = *c->groups[gi];
+        const Target& t = *c->tg[g.tgt];
+        const int Np = t.Npad, nr = g.nr;
+        Cx<T>* x = g.kv[0].as<Cx<T>>();
+        Cx<T>* r0 = g.kv[1].as<Cx<T>>();
+        Cx<T>* rt = g.kv[2].as<Cx<T>>();
+        Cx<T>* u0 = g.kv[3].as<Cx<T>>();
+        Cx<T>* u1 = g.kv[4].as<Cx<T>>();
+        Cx<T>* u2 = g.kv[5].as<Cx<T>>();
+        Cx<T>* r1 = g.kv[6].as<Cx<T>>();
+        Cx<T>* r2 = g.kv[7].as<Cx<T>>();
+        BiState* bs = g.state.as<BiState>();
+        int* act = g.active.as<int>();
+        double* part = g.partials.as<double>();
+        const bool fuse = (t.shape<T>().ct & 1) != 0 && !t.any_aniso;
+        const int nbv = vec_blocks(Np), nbp = fuse ? 12 * t.n[0] : nbv;
+        hipError_t e;
+        auto mv_dot1 = [&](const Cx<T>* in, Cx<T>* out) -> hipError_t {
+            // out = A in and <rt, out>
+            if (fuse) return matvec_group<T>(t, g, nr, in, out, nullptr, act, MV_AX, st, MvDot{1, rt, part});
+            hipError_t e2 = matvec_group<T>(t, g, nr, in, out, nullptr, act, MV_AX, st);
+            if (e2 != hipSuccess) return e2;
+            return launch_dot<T>(Np, nr, 1, rt, out, nullptr, nullptr, part, act, st);
+        };
+        if ((e = launch_l2_scalars(0, nbv, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_l2_update<T>(1, Np, nr, x, r0, rt, u0, u1, u2, r1, r2, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = mv_dot1(u0, u1)) != hipSuccess) return e;
+        if ((e = launch_l2_scalars(1, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_l2_update<T>(2, Np, nr, x, r0, rt, u0, u1, u2, r1, r2, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = mv_dot1(r0, r1)) != hipSuccess) return e;
+        if ((e = launch_l2_scalars(2, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_l2_update<T>(3, Np, nr, x, r0, rt, u0, u1, u2, r1, r2, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = mv_dot1(u1, u2)) != hipSuccess) return e;
+        if ((e = launch_l2_scalars(1, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_l2_update<T>(4, Np, nr, x, r0, rt, u0, u1, u2, r1, r2, bs, part, act, st)) != hipSuccess) return e;
+        // r2 = A r1 with the minimal-residual inner products of r0, r1, r2
+        if (fuse) {
+            if ((e = matvec_group<T>(t, g, nr, r1, r2, nullptr, act, MV_AX, st, MvDot{3, r0, part})) != hipSuccess)
+                return e;
+        } else {
+            if ((e = matvec_group<T>(t, g, nr, r1, r2, nullptr, act, MV_AX, st)) != hipSuccess) return e;
+            if ((e = launch_l2_mrdot<T>(Np, nr, r0, r1, r2, part, act, st)) != hipSuccess) return e;
+        }
+        if ((e = launch_l2_scalars(3, nbp, nr, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_l2_update<T>(5, Np, nr, x, r0, rt, u0, u1, u2, r1, r2, bs, part, act, st)) != hipSuccess) return e;
+        if ((e = launch_l2_scalars(4, nbv, nr, bs, part, act, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Inner BiCGstab on all groups: solves A d = b_inner from d = 0, where b_inner
 // is already in kv[1] (r).  Per-rhs relative tolerance and iteration budget
 // are in g.tolrel2 / g.maxit.  Returns when no rhs is active.
@@ -759,17 +884,28 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
         HCHK(c, launch_bicg_init<T>(t.Npad, g.nr, r, x, r, g.kv[2].as<Cx<T>>(), g.kv[3].as<Cx<T>>(),
                                     g.kv[4].as<Cx<T>>(), st));
         HCHK(c, launch_dot<T>(t.Npad, g.nr, 1, r, r, nullptr, nullptr, g.partials.as<double>(), nullptr, st));
-        HCHK(c, launch_state_init(t.Npad, g.nr, g.state.as<BiState>(), g.partials.as<double>(),
-                                  g.tolrel2.as<double>(), g.maxit.as<int>(), g.active.as<int>(), c->force_restart,
-                                  g.tcap > 0 ? g.trace.as<double>() : nullptr, g.tcap, st));
+        if (c->solver == DDA_SOLVER_BICGSTAB2)
+            HCHK(c, launch_l2_state_init(t.Npad, g.nr, g.state.as<BiState>(), g.partials.as<double>(),
+                                         g.tolrel2.as<double>(), g.maxit.as<int>(), g.active.as<int>(),
+                                         c->force_restart, g.tcap > 0 ? g.trace.as<double>() : nullptr, g.tcap, st));
+        else
+            HCHK(c, launch_state_init(t.Npad, g.nr, g.state.as<BiState>(), g.partials.as<double>(),
+                                      g.tolrel2.as<double>(), g.maxit.as<int>(), g.active.as<int>(), c->force_restart,
+                                      g.tcap > 0 ? g.trace.as<double>() : nullptr, g.tcap, st));
     }
     const int prec = std::is_same<T, double>::value ? DDA_FP64 : DDA_FP32;
-    if (c->gkey_gen != c->ws_gen || c->gkey_prec != prec || c->gkey_k != kiters) {
+    if (c->gkey_gen != c->ws_gen || c->gkey_prec != prec || c->gkey_k != kiters || c->gkey_solver != c->solver) {
         c->drop_graphs();
         c->gkey_gen = c->ws_gen;
         c->gkey_prec = prec;
         c->gkey_k = kiters;
+        c->gkey_solver = c->solver;
     }
+    // one BiCGstab(2) cycle takes two BiCG steps: kiters / 2 cycles per replay
+    auto enqueue = [&](int k, const std::vector<char>& lv) -> hipError_t {
+        if (c->solver == DDA_SOLVER_BICGSTAB2) return (k & 1) ? hipSuccess : enqueue_cycle_l2<T>(c, st, lv);
+        return enqueue_iteration<T>(c, st, k, lv);
+    };
     // Replays run one ahead of the convergence poll: replay i + 1 is queued
     // before the flags left by replay i are read (pinned copies and events),
     // so the device does not idle between replays; the replay queued after
@@ -812,7 +948,7 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
                 hipGraphExec_t ex = nullptr;
                 HCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
-                for (int k = 0; k < kiters && e == hipSuccess; ++k) e = enqueue_iteration<T>(c, st, k, lv);
+                for (int k = 0; k < kiters && e == hipSuccess; ++k) e = enqueue(k, lv);
                 hipError_t e2 = hipStreamEndCapture(st, &graph);
                 HCHK(c, e);
                 HCHK(c, e2);
@@ -823,7 +959,7 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
             }
             HCHK(c, hipGraphLaunch(it->second, st));
         } else {
-            for (int k = 0; k < kiters; ++k) HCHK(c, enqueue_iteration<T>(c, st, k, lv));
+            for (int k = 0; k < kiters; ++k) HCHK(c, enqueue(k, lv));
         }
         return DDA_OK;
     };
@@ -851,7 +987,9 @@ dda_status inner_solve(dda_ctx* c, int kiters, bool use_graph) {
     }
     // apply the update the last fused iteration of every rhs left pending; the
     // direction of iteration k is in kv[7] for even k, kv[3] for odd k
+    // (BiCGstab(2) applies every update within its cycle)
     for (auto& gp : c->groups) {
+        if (c->solver == DDA_SOLVER_BICGSTAB2) break;
         Group& g = *gp;
         const Target& t = *c->tg[g.tgt];
         HCHK(c, launch_bicg_flush<T>(t.Npad, g.nr, g.kv[0].as<Cx<T>>(), g.kv[1].as<Cx<T>>(), g.kv[7].as<Cx<T>>(),
@@ -887,31 +1025,6 @@ dda_status push_history(dda_ctx* c, Group& g, const Target& t, int depth) {
 // Solve the h x h normal equations G c = q (G Hermitian positive
 // semi-definite, upper triangle given) by Gaussian elimination with partial
 // pivoting after a relative diagonal shift of 1e-12.
-void solve_small(int h, const cd* Gu, const cd* q, cd* out) {
-    cd A[HIST_MAX][HIST_MAX + 1];
-    double dmax = 0;
-    for (int e = 0; e < h; ++e) dmax = std::max(dmax, std::abs(Gu[e * HIST_MAX + e]));
-    for (int e = 0; e < h; ++e) {
-        for (int f = 0; f < h; ++f) A[e][f] = e <= f ? Gu[e * HIST_MAX + f] : std::conj(Gu[f * HIST_MAX + e]);
-        A[e][e] += 1e-12 * dmax + 1e-300;
-        A[e][h] = q[e];
-    }
-    for (int k = 0; k < h; ++k) {
-        int piv = k;
-        for (int i = k + 1; i < h; ++i)
-            if (std::abs(A[i][k]) > std::abs(A[piv][k])) piv = i;
-        for (int j = 0; j <= h; ++j) std::swap(A[k][j], A[piv][j]);
-        for (int i = k + 1; i < h; ++i) {
-            const cd f = A[i][k] / A[k][k];
-            for (int j = k; j <= h; ++j) A[i][j] -= f * A[k][j];
-        }
-    }
-    for (int k = h - 1; k >= 0; --k) {
-        cd v = A[k][h];
-        for (int j = k + 1; j < h; ++j) v -= A[k][j] * out[j];
-        out[k] = v / A[k][k];
-    }
-}
 
 // Least-squares guess over earlier solutions of the group's slots (the
 // history ring, or only the previous solution held in x64 when the ring is
@@ -947,37 +1060,15 @@ dda_status project_history(dda_ctx* c, Group& g, Target& t) {
                                   nullptr, nullptr, V + e * ve, st));
         HCHK(c, matvec_group<float>(t, g, nr, V + e * ve, W + e * ve, nullptr, nullptr, MV_AX, st));
     }
+    // coefficients, combination, residual field and its norm on the device:
+    // the guess takes no host round trip
     HCHK(c, launch_gram(t.Npad, nr, h, W, g.b64.as<Cx<double>>(), g.gpart.as<double>(), st));
-    g.hgram.resize((size_t)nr * nblk * HIST_NGRAM * 2);
-    HCHK(c, hipMemcpyAsync(g.hgram.data(), g.gpart.p, g.hgram.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HCHK(c, hipStreamSynchronize(st));
-    g.hcoef.assign((size_t)nr * HIST_MAX, Cx<double>{0, 0});
-    for (int s = 0; s < nr; ++s) {
-        cd acc[HIST_NGRAM];
-        for (int q = 0; q < HIST_NGRAM; ++q) acc[q] = 0;
-        for (int b = 0; b < nblk; ++b)
-            for (int q = 0; q < HIST_NGRAM; ++q) {
-                const double* p = &g.hgram[(((size_t)s * nblk + b) * HIST_NGRAM + q) * 2];
-                acc[q] += cd(p[0], p[1]);
-            }
-        cd Gu[HIST_MAX * HIST_MAX], rhs[HIST_MAX], cf[HIST_MAX];
-        int q = 0;
-        for (int e = 0; e < HIST_MAX; ++e)
-            for (int f = e; f < HIST_MAX; ++f) Gu[e * HIST_MAX + f] = acc[q++];
-        for (int e = 0; e < HIST_MAX; ++e) rhs[e] = acc[q + e];
-        solve_small(h, Gu, rhs, cf);
-        for (int e = 0; e < h; ++e) g.hcoef[(size_t)s * HIST_MAX + e] = Cx<double>{cf[e].real(), cf[e].imag()};
-    }
-    HCHK(c, hipMemcpyAsync(g.pcoef.p, g.hcoef.data(), g.hcoef.size() * sizeof(Cx<double>), hipMemcpyHostToDevice, st));
+    HCHK(c, launch_proj_coef(t.Npad, nr, h, g.gpart.as<double>(), g.pcoef.as<Cx<double>>(), st));
     HCHK(c, launch_hist_combine(t.geo(), nr, h, V, g.pcoef.as<Cx<double>>(), g.x64.as<Cx<double>>(),
                                 g.ainv64.as<Cx<double>>(), g.esh.as<Cx<float>>(), W, g.b64.as<Cx<double>>(),
                                 g.rf.as<Cx<float>>(), st));
-    HCHK(c, launch_norm2<float>(t.Npad, nr, g.rf.as<Cx<float>>(), g.partials.as<double>(), g.norms.as<double>(), st));
-    std::vector<double> n2(nr);
-    HCHK(c, hipMemcpyAsync(n2.data(), g.norms.p, nr * sizeof(double), hipMemcpyDeviceToHost, st));
-    HCHK(c, hipStreamSynchronize(st));
-    g.hrscale.resize(nr);
-    for (int s = 0; s < nr; ++s) g.hrscale[s] = (float)std::max(std::sqrt(n2[s] / (3.0 * t.N)), 1e-30);
+    HCHK(c, g.rfn2.ensure(nr * sizeof(double)));
+    HCHK(c, launch_norm2<float>(t.Npad, nr, g.rf.as<Cx<float>>(), g.partials.as<double>(), g.rfn2.as<double>(), st));
     g.has_r = true;
     return DDA_OK;
 }
@@ -1142,6 +1233,41 @@ dda_status dda_target_info(const dda_ctx* c, int32_t target, int64_t* n_sites, d
     return DDA_OK;
 }
 
+dda_status dda_set_anisotropic(dda_ctx* c, int32_t target, int32_t comp, const double* m3, const double* angles) {
+    SCHK(check_ctx(c));
+    if (target < 0 || target >= (int)c->tg.size()) return fail(c, DDA_ERR_INVALID_ARG, "set_anisotropic: unknown target");
+    Target& t = *c->tg[target];
+    if (comp < 1 || comp > t.ncomp || !m3 || !angles)
+        return fail(c, DDA_ERR_INVALID_ARG, "set_anisotropic: composition %d outside [1, %d] or null pointers", comp,
+                    t.ncomp);
+    for (int j = 0; j < 6; ++j)
+        if (!std::isfinite(m3[j])) return fail(c, DDA_ERR_INVALID_ARG, "set_anisotropic: non-finite index");
+    for (int j = 0; j < 3; ++j)
+        if (!std::isfinite(angles[j])) return fail(c, DDA_ERR_INVALID_ARG, "set_anisotropic: non-finite angle");
+    (void)hipStreamSynchronize(c->stream);
+    const int q = comp - 1;
+    double mkd = 0;
+    for (int j = 0; j < 3; ++j) {
+        t.m3[q][j] = cd(m3[2 * j], m3[2 * j + 1]);
+        t.dfang[q][j] = angles[j];
+        mkd = std::max(mkd, std::abs(t.m3[q][j]) * t.kd);
+    }
+    t.aniso[q] = 1;
+    t.any_aniso = true;
+    // the solve's groups, graphs and previous solutions refer to the old
+    // diagonal: start over
+    c->groups.clear();
+    c->rhs_group.clear();
+    c->last_nrhs = 0;
+    c->ws_gen++;
+    c->have_solution = false;
+    if (mkd >= 1.0) {
+        fail(c, DDA_WARN_MKD_GE_1, "|m| k d = %.3f >= 1 for composition %d", mkd, comp);
+        return DDA_WARN_MKD_GE_1;
+    }
+    return DDA_OK;
+}
+
 dda_status dda_build_green_fft(dda_ctx* c, uint32_t prec) {
     SCHK(check_ctx(c));
     if (c->tg.empty()) return fail(c, DDA_ERR_STATE, "build_green_fft before set_target");
@@ -1199,6 +1325,8 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
         if (std::fabs(en - 1.0) > 1e-6) return fail(c, DDA_ERR_INVALID_ARG, "wave %d: |e0| != 1", i);
     }
     if (o && o->restart_every < 0) return fail(c, DDA_ERR_INVALID_ARG, "restart_every < 0");
+    if (o && o->solver != DDA_SOLVER_BICGSTAB && o->solver != DDA_SOLVER_BICGSTAB2)
+        return fail(c, DDA_ERR_INVALID_ARG, "unknown solver %d", o->solver);
     const double tol = o->tol > 0 ? o->tol : 1e-5;
     const int max_iter = o->max_iter > 0 ? o->max_iter : 1000;
     const int prec = o->prec;
@@ -1206,6 +1334,7 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
     const bool devptr = (o->flags & DDA_DEVICE_PTRS) != 0;
     const bool use_graph = !(o->flags & DDA_NO_GRAPH);
     c->force_restart = o->restart_every;
+    c->solver = o->solver;
     {
         const char* tp = std::getenv("DDA_TRACE");
         c->trace_path = tp ? tp : "";
@@ -1226,6 +1355,11 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
     if (keep_prev && (!c->have_solution || c->last_nrhs != nrhs))
         return fail(c, DDA_ERR_STATE, "guess %d needs a previous solve with the same number of right-hand sides",
                     o->guess);
+    if (o->guess == DDA_GUESS_PREV_SHIFT || o->guess == DDA_GUESS_PROJECT || o->guess == DDA_GUESS_NN)
+        for (int i = 0; i < nrhs; ++i)
+            if (c->tg[waves[i].target]->any_aniso)
+                return fail(c, DDA_ERR_INVALID_ARG,
+                            "guess %d carries local fields with a scalar 1/alpha: not for anisotropic targets", o->guess);
     if (!keep_prev) SCHK(group_waves(c, nrhs, waves));
     else
         for (int i = 0; i < nrhs; ++i)
@@ -1296,6 +1430,16 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
                 a32[(size_t)s * t.ncomp + q] = Cx<float>{(float)a.real(), (float)a.imag()};
             }
         }
+        if (t.any_aniso) {
+            std::vector<dda_wave> ws(g.nr);
+            for (int s = 0; s < g.nr; ++s) ws[s] = waves[g.idx[s]];
+            aniso_tables(t, g, ws.data());
+            HCHK(c, g.aten64.ensure(g.haten.size() * sizeof(cd)));
+            HCHK(c, g.aten32.ensure(g.haten32.size() * sizeof(Cx<float>)));
+            HCHK(c, hipMemcpyAsync(g.aten64.p, g.haten.data(), g.haten.size() * sizeof(cd), hipMemcpyHostToDevice, st));
+            HCHK(c, hipMemcpyAsync(g.aten32.p, g.haten32.data(), g.haten32.size() * sizeof(Cx<float>),
+                                   hipMemcpyHostToDevice, st));
+        }
         HCHK(c, hipMemcpyAsync(g.waves.p, g.hw.data(), g.nr * sizeof(WaveDev), hipMemcpyHostToDevice, st));
         HCHK(c, hipMemcpyAsync(g.ainv64.p, g.hainv.data(), g.hainv.size() * sizeof(cd), hipMemcpyHostToDevice, st));
         HCHK(c, hipMemcpyAsync(g.ainv32.p, a32.data(), a32.size() * sizeof(Cx<float>), hipMemcpyHostToDevice, st));
@@ -1340,7 +1484,7 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
             std::vector<dda_wave> gw(g.nr);
             for (int s = 0; s < g.nr; ++s) gw[s] = waves[g.idx[s]];
             hipError_t e = nn_guess_group(c->nn, site_view(t), gw.data(), reinterpret_cast<const double*>(g.hainv.data()),
-                                          g.nr, g.esh.as<Cx<float>>(), g.rf.as<Cx<float>>(), g.hrscale.data(),
+                                          g.nr, g.esh.as<Cx<float>>(), g.rf.as<Cx<float>>(), g.rfn2.as<double>(),
                                           g.x64.as<Cx<double>>(), st);
             if (e == hipErrorNotSupported)
                 return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "learned guess needs a cubic box with side divisible by 16");
@@ -1441,7 +1585,7 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
                     grel[i] = rl;
                 }
                 rel[i] = rl;
-                if (tf) std::fprintf(tf, "%d %d %d %.6e fp64\n", i, outer[i], iters[i], rl);
+                if (tf) std::fprintf(tf, "%d %d %d %.9e fp64\n", i, outer[i], iters[i], rl);
                 if (rl <= tol || bb[i] == 0) {
                     done[i] = 1;
                     continue;
@@ -1521,12 +1665,14 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
             for (int s = 0; s < g.nr; ++s) {
                 if (!mk[s]) continue;
                 const int i = g.idx[s];
-                // the inner right-hand side is r / ||r||: its recursive residual
-                // times the FP64 relative residual estimates ||E - A P|| / ||E||
+                // the inner right-hand side is r / ||r|| (FP32 inner solves; its
+                // recursive residual times the FP64 relative residual estimates
+                // ||E - A P|| / ||E||) or r itself (FP64: divided by ||E||)
+                const double tsc = prec == DDA_SOLVE_FP32_REFINE ? rel[i] : 1.0 / std::sqrt(bb[i]);
                 if (tf)
                     for (int k = 0; k < std::min(hs[s].it, g.tcap); ++k)
-                        std::fprintf(tf, "%d %d %d %.6e inner\n", i, outer[i], iters[i] + k + 1,
-                                     rel[i] * std::sqrt(std::max(0.0, tr[(size_t)s * g.tcap + k])));
+                        std::fprintf(tf, "%d %d %d %.9e inner\n", i, outer[i], iters[i] + k + 1,
+                                     tsc * std::sqrt(std::max(0.0, tr[(size_t)s * g.tcap + k])));
                 iters[i] += hs[s].it;
                 mvs[i] += 2 * hs[s].it;
                 // a breakdown the inner solve could not recover from ended it
@@ -1622,6 +1768,24 @@ dda_status dda_matvec(dda_ctx* c, int32_t target, int32_t nrhs, const double* ai
         for (int s = 0; s < nrhs; ++s)
             for (int q = 0; q < t.ncomp; ++q) ai[(size_t)s * t.ncomp + q] = inverse_alpha(t.m[q], t.kd, t.alpha_kind, kh, e);
     }
+    if (t.any_aniso) {
+        // anisotropic compositions: the tensor of the target's prescription for
+        // the wave khat = x, e0 = y (their entries of ainv are not used)
+        std::vector<dda_wave> ws(nrhs);
+        for (auto& w : ws) {
+            w = dda_wave{};
+            w.khat[0] = 1;
+            w.e0[2] = 1;
+        }
+        g.hainv = ai;
+        g.hainv32.resize(ai.size());
+        aniso_tables(t, g, ws.data());
+        ai = g.hainv;
+        HCHK(c, g.aten64.ensure(g.haten.size() * sizeof(cd)));
+        HCHK(c, g.aten32.ensure(g.haten32.size() * sizeof(Cx<float>)));
+        HCHK(c, hipMemcpy(g.aten64.p, g.haten.data(), g.haten.size() * sizeof(cd), hipMemcpyHostToDevice));
+        HCHK(c, hipMemcpy(g.aten32.p, g.haten32.data(), g.haten32.size() * sizeof(Cx<float>), hipMemcpyHostToDevice));
+    }
     const size_t per = (size_t)t.N * 3 * sizeof(Cx<double>);
     DevMem dx, dy, vx, vy;
     HCHK(c, dx.ensure(per * nrhs));
@@ -1707,6 +1871,30 @@ dda_status dda_matvec_noalloc(dda_ctx* c, int32_t target, int32_t nrhs, const vo
     return DDA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The tensor part of the absorption sums of an anisotropic target's group,
+// added to h[3 s + 1] (the layout of launch_xsec's output) after the stream
+// has run; synchronizes the stream.
+dda_status add_aniso_abs(dda_ctx* c, Group& g, const Target& t, double* h, hipStream_t st) {
+    if (!t.any_aniso) return DDA_OK;
+    DevMem& d = c->scr[7];
+    HCHK(c, d.ensure(g.nr * sizeof(double)));
+    HCHK(c, launch_aniso_abs(t.geo(), g.nr, g.x64.as<Cx<double>>(), g.aten64.as<Cx<double>>(), g.partials.as<double>(),
+                             d.as<double>(), st));
+    std::vector<double> a(g.nr);
+    HCHK(c, hipMemcpyAsync(a.data(), d.p, g.nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    HCHK(c, hipStreamSynchronize(st));
+    for (int s = 0; s < g.nr; ++s) h[3 * s + 1] += a[s];
+    return DDA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 dda_status dda_cross_sections(dda_ctx* c, int32_t nrhs, double* q) {
     SCHK(check_ctx(c));
     if (!c->have_solution) return fail(c, DDA_ERR_STATE, "cross_sections before a solve");
@@ -1721,6 +1909,7 @@ dda_status dda_cross_sections(dda_ctx* c, int32_t nrhs, double* q) {
                             t.kd * t.kd * t.kd, g.partials.as<double>(), out.as<double>(), st));
         std::vector<double> h(3 * g.nr);
         HCHK(c, hipMemcpyAsync(h.data(), out.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        SCHK(add_aniso_abs(c, g, t, h.data(), st));
         HCHK(c, hipStreamSynchronize(st));
         const double area = PI * t.aeff * t.aeff;
         for (int s = 0; s < g.nr; ++s) {
@@ -1739,6 +1928,9 @@ dda_status dda_cross_sections_phi(dda_ctx* c, int32_t npairs, int32_t ncomb, con
     if (!c->have_solution) return fail(c, DDA_ERR_STATE, "cross_sections_phi before a solve");
     if (npairs < 1 || ncomb < 1 || !coeffs || !q || 2 * npairs != c->last_nrhs)
         return fail(c, DDA_ERR_INVALID_ARG, "cross_sections_phi: need 2 * npairs == rhs of the last solve");
+    for (auto& gp : c->groups)
+        if (c->tg[gp->tgt]->any_aniso)
+            return fail(c, DDA_ERR_INVALID_ARG, "cross_sections_phi: not for anisotropic targets");
     for (int p = 0; p < npairs; ++p) {
         const int i0 = 2 * p, i1 = 2 * p + 1;
         if (c->rhs_group[i0] != c->rhs_group[i1])
@@ -1835,6 +2027,7 @@ dda_status dda_scattering_moments(dda_ctx* c, int32_t nrhs, int32_t ndir, const 
         std::vector<double> hx(3 * g.nr);
         std::vector<cd> F((size_t)g.nr * ndir * 3);
         HCHK(c, hipMemcpyAsync(hx.data(), dx.p, hx.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        SCHK(add_aniso_abs(c, g, t, hx.data(), st));
         HCHK(c, hipMemcpyAsync(F.data(), dF.p, F.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
         // the backscattering direction -khat of each rhs
         std::vector<double> nb(3 * g.nr);
@@ -2192,6 +2385,15 @@ dda_status dda_nn_record(dda_ctx* c, dda_nn* nn) {
     for (auto& gp : c->groups)
         if (!gp->has_r)
             return fail(c, DDA_ERR_STATE, "nn_record needs a solve with guess PROJECT or NN");
+    // sigma of every slot from the device norms of its residual field
+    for (auto& gp : c->groups) {
+        Group& g = *gp;
+        const Target& t = *c->tg[g.tgt];
+        std::vector<double> n2(g.nr);
+        HCHK(c, hipMemcpy(n2.data(), g.rfn2.p, g.nr * sizeof(double), hipMemcpyDeviceToHost));
+        g.hrscale.resize(g.nr);
+        for (int s = 0; s < g.nr; ++s) g.hrscale[s] = (float)std::max(std::sqrt(n2[s] / (3.0 * t.N)), 1e-30);
+    }
     for (int i = 0; i < c->last_nrhs; ++i) {
         Group& g = *c->groups[c->rhs_group[i]];
         Target& t = *c->tg[g.tgt];

@@ -60,6 +60,9 @@ struct BiState {
     // trace[i - 1] for i <= tcap
     int frs, tcap;
     double* trace;
+    // BiCGstab(2): <rt, r0> for the next cycle (0, 1), the polynomial
+    // coefficients gamma_1 (2, 3) and gamma_2 (4, 5) of the last MR step
+    double ex[6];
 };
 
 // Launch shapes of the three matvec passes for one target and precision.
@@ -187,6 +190,44 @@ hipError_t launch_bicg_init(int Npad, int nrhs, const Cx<T>* b, Cx<T>* x, Cx<T>*
 hipError_t launch_state_init(int Npad, int nrhs, BiState* s, const double* partials, const double* tol_rel2,
                              const int* maxit, int* active, int frs, double* trace, int tcap, hipStream_t st);
 
+// BiCGstab(2) (the guide's PBCGS2) on vectors [rhs][3][Npad]: x, r0, rt
+// (shadow residual), u0, u1, u2, r1, r2.  BiState fields: rho = rho0, alpha,
+// omega, beta as in BiCGstab; restart = the cycle in progress started over
+// (rt := r0), pend = a restart is due at the next cycle; ex as above.
+// State from <r0, r0> in partials slot 0: rho0 = 1, alpha = 0, omega = 1.
+hipError_t launch_l2_state_init(int Npad, int nrhs, BiState* s, const double* partials, const double* tol_rel2,
+                                const int* maxit, int* active, int frs, double* trace, int tcap, hipStream_t st);
+// which: 0 cycle start (beta of the first BiCG step), 1 alpha = rho0 / <rt, u> (slot 0),
+// 2 beta of the second BiCG step from <rt, r1> (slot 0), 3 the MR coefficients
+// from slots 0..3 as the inverse pass's DOT = 3 leaves them with x = r1, y = r2,
+// w = r0, 4 cycle end from <rt, r0> (slot 0) and ||r0||^2 (slot 1)
+hipError_t launch_l2_scalars(int which, int nblk, int nrhs, BiState* s, const double* partials, int* active,
+                             hipStream_t st);
+// step 1: u0 = r0 - beta u0 (rt = r0 on restart); 2: r0 -= alpha u1, x += alpha u0;
+// 3: u0 = r0 - beta u0, u1 = r1 - beta u1; 4: r0 -= alpha u1, r1 -= alpha u2, x += alpha u0;
+// 5: x += g1 r0 + g2 r1, r0 -= g1 r1 + g2 r2, u0 -= g1 u1 + g2 u2 with partials
+// <rt, r0> (slot 0) and ||r0||^2 (slot 1)
+template <class T>
+hipError_t launch_l2_update(int step, int Npad, int nrhs, Cx<T>* x, Cx<T>* r0, Cx<T>* rt, Cx<T>* u0, Cx<T>* u1,
+                            const Cx<T>* u2, Cx<T>* r1, const Cx<T>* r2, const BiState* s, double* partials,
+                            const int* active, hipStream_t st);
+// The MR inner products in the inverse pass's DOT = 3 layout: slot 0 <r2, r1>,
+// slot 1 (||r2||^2, ||r1||^2), slot 2 <r0, r1>, slot 3 <r0, r2> (<a, b> = a^H b)
+template <class T>
+hipError_t launch_l2_mrdot(int Npad, int nrhs, const Cx<T>* r0, const Cx<T>* r1, const Cx<T>* r2, double* partials,
+                           const int* active, hipStream_t st);
+
+// Anisotropic compositions.  tens: [rhs][ncomp][6] complex (xx, xy, xz, yy,
+// yz, zz) of the symmetric tensor 1/alpha, zero for isotropic compositions.
+// y += sgn T x at every site (sgn = +1 for A x, -1 for the residual b - A x);
+// out[rhs] = sum over sites of Im(P . conj(T) P^*) (the tensor part of the
+// absorption sum).
+template <class T>
+hipError_t launch_aniso_diag(const Geo& g, int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* tens, int sgn,
+                             hipStream_t st);
+hipError_t launch_aniso_abs(const Geo& g, int nrhs, const Cx<double>* P, const Cx<double>* tens, double* partials,
+                            double* out, hipStream_t st);
+
 // Mixed precision helpers.
 // r32 = r64 * scale[rhs] (scale = 1/||r||); x64 += (1/scale[rhs]) * d32
 hipError_t launch_demote(int Npad, int nrhs, const Cx<double>* r64, Cx<float>* r32, const double* scale,
@@ -249,6 +290,9 @@ constexpr int HIST_NGRAM = HIST_MAX * (HIST_MAX + 1) / 2 + HIST_MAX;
 int gram_blocks(int Npad);
 hipError_t launch_gram(int Npad, int nrhs, int h, const Cx<float>* W, const Cx<double>* b, double* partials,
                        hipStream_t st);
+// The least-squares coefficients from the Gram partials, on the device (coef:
+// [nrhs][HIST_MAX] complex)
+hipError_t launch_proj_coef(int Npad, int nrhs, int h, const double* partials, Cx<double>* coef, hipStream_t st);
 // x64 = sum_e coef[rhs][e] V[e] (coef: [nrhs][4] complex); esh = (1/alpha) x64
 // and rf = b - sum_e coef[rhs][e] W[e] (FP32) where given.
 hipError_t launch_hist_combine(const Geo& g, int nrhs, int h, const Cx<float>* V, const Cx<double>* coef,

@@ -286,6 +286,275 @@ __global__ void __launch_bounds__(SCALAR_THREADS)
     st[rhs] = s;
 }
 
+// ---------------------------------------------------------------------------
+// BiCGstab(2): per-rhs scalar steps and the vector updates of a cycle.
+// ---------------------------------------------------------------------------
+__global__ void k_l2_state_init(int nblk, BiState* __restrict__ st, const double* __restrict__ partials,
+                                const double* __restrict__ tol_rel2, const int* __restrict__ maxit,
+                                int* __restrict__ active, int frs, double* trace, int tcap) {
+    __shared__ double sh[16];
+    const int rhs = blockIdx.x;
+    const double2 a = reduce_slot(partials, rhs, 0, nblk, sh);
+    if (threadIdx.x != 0) return;
+    BiState s;
+    s.rho[0] = 1;
+    s.rho[1] = 0;
+    s.alpha[0] = s.alpha[1] = 0;
+    s.omega[0] = 1;
+    s.omega[1] = 0;
+    s.beta[0] = s.beta[1] = 0;
+    s.rr = a.x;
+    s.tol2 = tol_rel2[rhs] * a.x;
+    s.it = 0;
+    s.maxit = maxit[rhs];
+    s.restart = 0;
+    s.conv = (a.x <= s.tol2) ? 1 : 0;
+    s.pend = 0;
+    s.pbuf = 0;
+    s.frs = frs;
+    s.tcap = trace ? tcap : 0;
+    s.trace = trace ? trace + (size_t)rhs * tcap : nullptr;
+    s.ex[0] = a.x;  // <rt, r0> with rt = r0
+    s.ex[1] = 0;
+    s.ex[2] = s.ex[3] = s.ex[4] = s.ex[5] = 0;
+    st[rhs] = s;
+    active[rhs] = (maxit[rhs] > 0 && !s.conv && a.x > 0) ? 1 : 0;
+    if (a.x == 0) st[rhs].conv = 1;
+}
+
+__global__ void __launch_bounds__(SCALAR_THREADS)
+    k_l2_scalars(int which, int nblk, BiState* __restrict__ st, const double* __restrict__ partials,
+                 int* __restrict__ active) {
+    __shared__ double sh[8 * (SCALAR_THREADS / 64)];
+    const int rhs = blockIdx.x;
+    if (!active[rhs]) return;
+    const int nslot = (which == 3) ? 4 : (which == 4 ? 2 : (which == 0 ? 0 : 1));
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double2* p2 = reinterpret_cast<const double2*>(partials) + (size_t)rhs * 4 * nblk;
+    for (int i = threadIdx.x; i < nblk && nslot > 0; i += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < nslot) {
+                const double2 e = p2[(size_t)q * nblk + i];
+                v[2 * q] += e.x;
+                v[2 * q + 1] += e.y;
+            }
+        }
+    }
+    block_sum_n<8>(v, sh);
+    if (threadIdx.x != 0) return;
+    BiState s = st[rhs];
+    const double2 a = make_double2(v[0], v[1]);
+    const double tiny = 1e-14 * s.rr;
+    if (which == 0) {
+        // cycle start: rho0 = -omega rho0, beta = alpha rho1 / rho0, rho0 = rho1;
+        // a restart (breakdown or forced) starts over with rt = r0: beta = 0
+        double2 rho1 = make_double2(s.ex[0], s.ex[1]);
+        const double2 r0n = cmul2(make_double2(-s.omega[0], -s.omega[1]), make_double2(s.rho[0], s.rho[1]));
+        const double an = sqrt(r0n.x * r0n.x + r0n.y * r0n.y);
+        if (s.pend || !(an > 1e-300) || !(an > 1e-14 * s.rr)) {
+            s.restart = 1;
+            s.pend = 0;
+            rho1 = make_double2(s.rr, 0.0);
+            s.beta[0] = s.beta[1] = 0;
+            s.alpha[0] = s.alpha[1] = 0;
+        } else {
+            const double2 be = cmul2(make_double2(s.alpha[0], s.alpha[1]), cdiv(rho1, r0n));
+            s.beta[0] = be.x;
+            s.beta[1] = be.y;
+        }
+        s.rho[0] = rho1.x;
+        s.rho[1] = rho1.y;
+    } else if (which == 1) {
+        // alpha = rho0 / <rt, u_{j+1}>; a vanishing denominator leaves x and r
+        // as they are (alpha = 0) and restarts at the next cycle
+        s.restart = 0;
+        const double an = sqrt(a.x * a.x + a.y * a.y);
+        if (!(an > 1e-300) || !(an > tiny)) {
+            s.alpha[0] = s.alpha[1] = 0;
+            s.pend = 1;
+        } else {
+            const double2 al = cdiv(make_double2(s.rho[0], s.rho[1]), a);
+            s.alpha[0] = al.x;
+            s.alpha[1] = al.y;
+        }
+    } else if (which == 2) {
+        // second BiCG step: rho1 = <rt, r1>, beta = alpha rho1 / rho0, rho0 = rho1
+        const double2 rho0 = make_double2(s.rho[0], s.rho[1]);
+        const double rn = sqrt(rho0.x * rho0.x + rho0.y * rho0.y);
+        if (!(rn > 1e-300) || !(rn > tiny)) {
+            s.beta[0] = s.beta[1] = 0;
+            s.pend = 1;
+        } else {
+            const double2 be = cmul2(make_double2(s.alpha[0], s.alpha[1]), cdiv(a, rho0));
+            s.beta[0] = be.x;
+            s.beta[1] = be.y;
+        }
+        s.rho[0] = a.x;
+        s.rho[1] = a.y;
+    } else if (which == 3) {
+        // MR step over r1, r2: Gram-Schmidt r2' = r2 - tau r1, then
+        // gamma'_1 = <r1, r0> / sigma1, gamma'_2 = <r2', r0> / sigma2,
+        // gamma_2 = gamma'_2 = omega, gamma_1 = gamma'_1 - tau gamma_2
+        const double2 b = make_double2(v[4], v[5]), d = make_double2(v[6], v[7]);
+        const double s1 = v[3], n22 = v[2];
+        double2 g1 = make_double2(0, 0), g2 = make_double2(0, 0);
+        if (s1 > 1e-300) {
+            const double2 tau = make_double2(a.x / s1, -a.y / s1);  // <r1, r2> / sigma1
+            const double s2 = n22 - (a.x * a.x + a.y * a.y) / s1;
+            const double2 gp1 = make_double2(b.x / s1, -b.y / s1);   // <r1, r0> / sigma1
+            if (s2 > 1e-14 * n22 && s2 > 1e-300) {
+                // <r2', r0> = <r2, r0> - conj(tau) <r1, r0> = conj(d) - (a / sigma1) conj(b)
+                const double2 ab = cmul2(make_double2(a.x / s1, a.y / s1), make_double2(b.x, -b.y));
+                const double2 q = make_double2(d.x - ab.x, -d.y - ab.y);
+                g2 = make_double2(q.x / s2, q.y / s2);
+                const double2 tg = cmul2(tau, g2);
+                g1 = make_double2(gp1.x - tg.x, gp1.y - tg.y);
+            } else {
+                g1 = gp1;  // r2 adds nothing beyond r1: degree-one polynomial
+            }
+        }
+        if (g2.x == 0 && g2.y == 0) s.pend = 1;  // omega = 0: no BiCG recurrence after this cycle
+        s.omega[0] = g2.x;
+        s.omega[1] = g2.y;
+        s.ex[2] = g1.x;
+        s.ex[3] = g1.y;
+        s.ex[4] = g2.x;
+        s.ex[5] = g2.y;
+    } else {
+        // cycle end: ||r0||^2 (slot 1), <rt, r0> for the next cycle (slot 0)
+        const double rr = v[2];
+        s.it += 2;
+        s.rr = rr;
+        if (s.trace) {
+            if (s.it - 1 <= s.tcap) s.trace[s.it - 2] = rr;
+            if (s.it <= s.tcap) s.trace[s.it - 1] = rr;
+        }
+        s.ex[0] = a.x;
+        s.ex[1] = a.y;
+        if (s.frs > 0 && s.it % s.frs == 0) s.pend = 1;
+        if (!(rr > s.tol2)) s.conv = 1;
+        if (s.conv || s.it >= s.maxit || !isfinite(rr)) active[rhs] = 0;
+    }
+    st[rhs] = s;
+}
+
+template <class T>
+__global__ void __launch_bounds__(VT) k_l2_update(int step, int V, Cx<T>* __restrict__ x, Cx<T>* __restrict__ r0,
+                                                  Cx<T>* __restrict__ rt, Cx<T>* __restrict__ u0,
+                                                  Cx<T>* __restrict__ u1, const Cx<T>* __restrict__ u2,
+                                                  Cx<T>* __restrict__ r1, const Cx<T>* __restrict__ r2,
+                                                  const BiState* __restrict__ st, double* __restrict__ partials,
+                                                  const int* __restrict__ active) {
+    const int rhs = blockIdx.y;
+    if (inactive(active, rhs)) return;
+    const BiState b = st[rhs];
+    const Cx<T> al = {(T)b.alpha[0], (T)b.alpha[1]}, be = {(T)b.beta[0], (T)b.beta[1]};
+    const Cx<T> g1 = {(T)b.ex[2], (T)b.ex[3]}, g2 = {(T)b.ex[4], (T)b.ex[5]};
+    const size_t o = (size_t)rhs * V;
+    double2 acc[2] = {{0, 0}, {0, 0}};
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i >= V) continue;
+        const size_t e = o + i;
+        if (step == 1) {
+            const Cx<T> r = r0[e];
+            u0[e] = r - be * u0[e];
+            if (b.restart) rt[e] = r;
+        } else if (step == 2) {
+            r0[e] = r0[e] - al * u1[e];
+            x[e] = x[e] + al * u0[e];
+        } else if (step == 3) {
+            u0[e] = r0[e] - be * u0[e];
+            u1[e] = r1[e] - be * u1[e];
+        } else if (step == 4) {
+            const Cx<T> a1 = u1[e];
+            r0[e] = r0[e] - al * a1;
+            r1[e] = r1[e] - al * u2[e];
+            x[e] = x[e] + al * u0[e];
+        } else {
+            const Cx<T> q0 = r0[e], q1 = r1[e];
+            x[e] = x[e] + g1 * q0 + g2 * q1;
+            const Cx<T> rn = q0 - g1 * q1 - g2 * r2[e];
+            r0[e] = rn;
+            u0[e] = u0[e] - g1 * u1[e] - g2 * u2[e];
+            acc_dot(acc[0], rt[e], rn);
+            acc_dot(acc[1], rn, rn);
+        }
+    }
+    if (step == 5) store_partials(acc, 2, partials, rhs, gridDim.x);
+}
+
+// slot 0 <r2, r1>, slot 1 (||r2||^2, ||r1||^2), slot 2 <r0, r1>, slot 3 <r0, r2>
+template <class T>
+__global__ void __launch_bounds__(VT) k_l2_mrdot(int V, const Cx<T>* __restrict__ r0, const Cx<T>* __restrict__ r1,
+                                                 const Cx<T>* __restrict__ r2, double* __restrict__ partials,
+                                                 const int* __restrict__ active) {
+    const int rhs = blockIdx.y;
+    if (inactive(active, rhs)) return;
+    const size_t o = (size_t)rhs * V;
+    double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (int k = 0; k < VPT; ++k) {
+        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
+        if (i >= V) continue;
+        const Cx<T> a0 = r0[o + i], a1 = r1[o + i], a2 = r2[o + i];
+        acc_dot(acc[0], a2, a1);
+        const double n2 = (double)a2.re * a2.re + (double)a2.im * a2.im;
+        const double n1 = (double)a1.re * a1.re + (double)a1.im * a1.im;
+        acc[1].x += n2;
+        acc[1].y += n1;
+        acc_dot(acc[2], a0, a1);
+        acc_dot(acc[3], a0, a2);
+    }
+    store_partials(acc, 4, partials, rhs, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Anisotropic compositions: the tensor part of the diagonal term and of the
+// absorption sum.  tens: [rhs][ncomp][6] complex (xx, xy, xz, yy, yz, zz) of
+// the symmetric 3 x 3 1/alpha, zero for isotropic compositions (whose
+// scalar 1/alpha the matvec passes apply).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_aniso_diag(Geo g, const Cx<T>* __restrict__ x, Cx<T>* __restrict__ y,
+                                                    const Cx<T>* __restrict__ tens, T sgn) {
+    const int rhs = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.N) return;
+    const Cx<T>* tc = tens + ((size_t)rhs * g.ncomp + g.site_comp[j]) * 6;
+    const Cx<T> t[6] = {tc[0], tc[1], tc[2], tc[3], tc[4], tc[5]};
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) any |= (t[q].re != 0 || t[q].im != 0);
+    if (!any) return;
+    const size_t o = (size_t)rhs * 3 * g.Npad + j;
+    const Cx<T> x0 = x[o], x1 = x[o + g.Npad], x2 = x[o + 2 * (size_t)g.Npad];
+    y[o] = y[o] + sgn * (t[0] * x0 + t[1] * x1 + t[2] * x2);
+    y[o + g.Npad] = y[o + g.Npad] + sgn * (t[1] * x0 + t[3] * x1 + t[4] * x2);
+    y[o + 2 * (size_t)g.Npad] = y[o + 2 * (size_t)g.Npad] + sgn * (t[2] * x0 + t[4] * x1 + t[5] * x2);
+}
+
+// partials slot 0 (re): sum over anisotropic sites of Im(P . conj(T) P^*) = -Im(P^H T P)
+__global__ void __launch_bounds__(VT) k_aniso_abs(Geo g, const Cx<double>* __restrict__ P,
+                                                  const Cx<double>* __restrict__ tens, double* __restrict__ partials) {
+    const int rhs = blockIdx.y;
+    double2 acc[1] = {{0, 0}};
+    for (int j = blockIdx.x * VT + threadIdx.x; j < g.N; j += gridDim.x * VT) {
+        const Cx<double>* tc = tens + ((size_t)rhs * g.ncomp + g.site_comp[j]) * 6;
+        const size_t o = (size_t)rhs * 3 * g.Npad + j;
+        const Cx<double> p[3] = {P[o], P[o + g.Npad], P[o + 2 * (size_t)g.Npad]};
+        const int ix[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+        double im = 0;
+        for (int a = 0; a < 3; ++a) {
+            Cx<double> tp = {0, 0};
+            for (int b = 0; b < 3; ++b) tp = tp + tc[ix[a][b]] * p[b];
+            im += p[a].re * tp.im - p[a].im * tp.re;  // Im(conj(p_a) (T p)_a)
+        }
+        acc[0].x -= im;
+    }
+    store_partials(acc, 1, partials, rhs, gridDim.x);
+}
+
 // Pending x, r update of a fused iteration.
 template <class T>
 __global__ void __launch_bounds__(VT) k_bicg_flush(int V, Cx<T>* __restrict__ x, Cx<T>* __restrict__ r,
@@ -839,6 +1108,87 @@ hipError_t launch_prev_shift(const Geo& g, const double* origin, int nrhs, const
 
 int gram_blocks(int Npad) { return (3 * Npad + VB - 1) / VB; }
 
+// Least-squares coefficients of the history guess on the device: sum the
+// Gram partials of one rhs over the blocks (one wave, fixed order), then solve
+// the h x h Hermitian normal equations G c = <W_e, b> by Gaussian elimination
+// with partial pivoting in FP64, the diagonal raised by 1e-12 of its largest
+// entry.  coef: [rhs][HIST_MAX] complex.
+__global__ void __launch_bounds__(64) k_proj_coef(int nblk, int h, const double* __restrict__ partials,
+                                                  Cx<double>* __restrict__ coef) {
+    const int rhs = blockIdx.x;
+    double acc[2 * NGRAM];
+#pragma unroll
+    for (int q = 0; q < 2 * NGRAM; ++q) acc[q] = 0;
+    for (int b = threadIdx.x; b < nblk; b += 64) {
+        const double* p = partials + ((size_t)rhs * nblk + b) * NGRAM * 2;
+#pragma unroll
+        for (int q = 0; q < 2 * NGRAM; ++q) acc[q] += p[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * NGRAM; ++q) acc[q] = wave_total(acc[q]);
+    if (threadIdx.x != 0) return;
+    double2 A[MAXH][MAXH + 1];
+    int q = 0;
+    double dmax = 0;
+    for (int e = 0; e < MAXH; ++e)
+        for (int f = e; f < MAXH; ++f) {
+            const double2 v = make_double2(acc[2 * q], acc[2 * q + 1]);
+            ++q;
+            if (e < h && f < h) {
+                A[e][f] = v;
+                A[f][e] = make_double2(v.x, -v.y);
+                if (e == f) dmax = fmax(dmax, sqrt(v.x * v.x + v.y * v.y));
+            }
+        }
+    for (int e = 0; e < h; ++e) {
+        A[e][e].x += 1e-12 * dmax + 1e-300;
+        A[e][h] = make_double2(acc[2 * (q + e)], acc[2 * (q + e) + 1]);
+    }
+    for (int k = 0; k < h; ++k) {
+        int piv = k;
+        double best = A[k][k].x * A[k][k].x + A[k][k].y * A[k][k].y;
+        for (int i = k + 1; i < h; ++i) {
+            const double m2 = A[i][k].x * A[i][k].x + A[i][k].y * A[i][k].y;
+            if (m2 > best) {
+                best = m2;
+                piv = i;
+            }
+        }
+        if (piv != k)
+            for (int j = 0; j <= h; ++j) {
+                const double2 tmp = A[k][j];
+                A[k][j] = A[piv][j];
+                A[piv][j] = tmp;
+            }
+        for (int i = k + 1; i < h; ++i) {
+            const double2 f = cdiv(A[i][k], A[k][k]);
+            for (int j = k; j <= h; ++j) {
+                const double2 fa = cmul2(f, A[k][j]);
+                A[i][j] = make_double2(A[i][j].x - fa.x, A[i][j].y - fa.y);
+            }
+        }
+    }
+    double2 out[MAXH];
+    for (int k = h - 1; k >= 0; --k) {
+        double2 v = A[k][h];
+        for (int j = k + 1; j < h; ++j) {
+            const double2 aj = cmul2(A[k][j], out[j]);
+            v = make_double2(v.x - aj.x, v.y - aj.y);
+        }
+        out[k] = cdiv(v, A[k][k]);
+    }
+    for (int e = 0; e < MAXH; ++e)
+        coef[(size_t)rhs * MAXH + e] = e < h ? Cx<double>{out[e].x, out[e].y} : Cx<double>{0, 0};
+}
+
+hipError_t launch_proj_coef(int Npad, int nrhs, int h, const double* partials, Cx<double>* coef, hipStream_t st) {
+    if (h < 1 || h > MAXH) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_proj_coef, dim3(nrhs), dim3(64), 0, st, gram_blocks(Npad), h, partials, coef);
+    return hipGetLastError();
+}
+
+
+
 hipError_t launch_gram(int Npad, int nrhs, int h, const Cx<float>* W, const Cx<double>* b, double* partials,
                        hipStream_t st) {
     if (h < 1 || h > MAXH) return hipErrorInvalidValue;
@@ -946,6 +1296,60 @@ hipError_t launch_state_init(int Npad, int nrhs, BiState* s, const double* parti
                              const int* maxit, int* active, int frs, double* trace, int tcap, hipStream_t st) {
     hipLaunchKernelGGL(k_state_init, dim3(nrhs), dim3(256), 0, st, vec_blocks(Npad), s, partials, tol_rel2, maxit,
                        active, frs, trace, tcap);
+    return hipGetLastError();
+}
+hipError_t launch_l2_state_init(int Npad, int nrhs, BiState* s, const double* partials, const double* tol_rel2,
+                                const int* maxit, int* active, int frs, double* trace, int tcap, hipStream_t st) {
+    hipLaunchKernelGGL(k_l2_state_init, dim3(nrhs), dim3(256), 0, st, vec_blocks(Npad), s, partials, tol_rel2, maxit,
+                       active, frs, trace, tcap);
+    return hipGetLastError();
+}
+hipError_t launch_l2_scalars(int which, int nblk, int nrhs, BiState* s, const double* partials, int* active,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_l2_scalars, dim3(nrhs), dim3(SCALAR_THREADS), 0, st, which, nblk, s, partials, active);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_l2_update(int step, int Npad, int nrhs, Cx<T>* x, Cx<T>* r0, Cx<T>* rt, Cx<T>* u0, Cx<T>* u1,
+                            const Cx<T>* u2, Cx<T>* r1, const Cx<T>* r2, const BiState* s, double* partials,
+                            const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_l2_update<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, step, 3 * Npad, x, r0, rt, u0,
+                       u1, u2, r1, r2, s, partials, active);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_l2_mrdot(int Npad, int nrhs, const Cx<T>* r0, const Cx<T>* r1, const Cx<T>* r2, double* partials,
+                           const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_l2_mrdot<T>), dim3(vec_blocks(Npad), nrhs), dim3(VT), 0, st, 3 * Npad, r0, r1, r2, partials,
+                       active);
+    return hipGetLastError();
+}
+template hipError_t launch_l2_update<float>(int, int, int, Cx<float>*, Cx<float>*, Cx<float>*, Cx<float>*, Cx<float>*,
+                                            const Cx<float>*, Cx<float>*, const Cx<float>*, const BiState*, double*,
+                                            const int*, hipStream_t);
+template hipError_t launch_l2_update<double>(int, int, int, Cx<double>*, Cx<double>*, Cx<double>*, Cx<double>*,
+                                             Cx<double>*, const Cx<double>*, Cx<double>*, const Cx<double>*,
+                                             const BiState*, double*, const int*, hipStream_t);
+template hipError_t launch_l2_mrdot<float>(int, int, const Cx<float>*, const Cx<float>*, const Cx<float>*, double*,
+                                           const int*, hipStream_t);
+template hipError_t launch_l2_mrdot<double>(int, int, const Cx<double>*, const Cx<double>*, const Cx<double>*,
+                                            double*, const int*, hipStream_t);
+template <class T>
+hipError_t launch_aniso_diag(const Geo& g, int nrhs, const Cx<T>* x, Cx<T>* y, const Cx<T>* tens, int sgn,
+                             hipStream_t st) {
+    hipLaunchKernelGGL((k_aniso_diag<T>), dim3((g.N + 255) / 256, nrhs), dim3(256), 0, st, g, x, y, tens, (T)sgn);
+    return hipGetLastError();
+}
+template hipError_t launch_aniso_diag<float>(const Geo&, int, const Cx<float>*, Cx<float>*, const Cx<float>*, int,
+                                             hipStream_t);
+template hipError_t launch_aniso_diag<double>(const Geo&, int, const Cx<double>*, Cx<double>*, const Cx<double>*, int,
+                                              hipStream_t);
+hipError_t launch_aniso_abs(const Geo& g, int nrhs, const Cx<double>* P, const Cx<double>* tens, double* partials,
+                            double* out, hipStream_t st) {
+    const int nblk = vec_blocks(g.Npad);
+    hipLaunchKernelGGL(k_aniso_abs, dim3(nblk, nrhs), dim3(VT), 0, st, g, P, tens, partials);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_norm2_final, dim3(nrhs), dim3(256), 0, st, nblk, partials, out);
     return hipGetLastError();
 }
 hipError_t launch_demote(int Npad, int nrhs, const Cx<double>* r64, Cx<float>* r32, const double* scale,

@@ -287,9 +287,16 @@ struct SampleDev {
     const float* resid;  // [3][Npad] complex: (E_loc - E_b) / sigma (training target) or nullptr
     const float* esh;    // [3][Npad] complex: local field E_b of the plain guess
     const float* rf;     // [3][Npad] complex: residual field R of the plain guess
-    float rscale;        // sigma
+    float rscale;        // sigma (when rn2 is null)
     float pad_;
+    const double* rn2;   // device ||R||^2 of the sample, or nullptr: sigma = (||R||^2 / 3N)^(1/2)
 };
+
+// sigma of a sample: from the device norm of its residual field when given
+__device__ __forceinline__ double sample_sigma(const SampleDev& S) {
+    if (!S.rn2) return (double)S.rscale;
+    return fmax(sqrt(*S.rn2 / (3.0 * S.N)), 1e-30);
+}
 
 __global__ void k_zero16(uint16_t* __restrict__ p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
@@ -315,7 +322,7 @@ __global__ void k_features(const SampleDev* __restrict__ sd, int D, uint16_t* __
         const uint32_t q = S.site_xyz[j];
         const int x = q & 1023, y = (q >> 10) & 1023, z = q >> 20;
         const int c = S.site_comp[j];
-        const float inv = 1.0f / S.rscale;
+        const float inv = (float)(1.0 / sample_sigma(S));
         float f[16];
         f[0] = 1.0f;
         for (int a = 0; a < 3; ++a) {
@@ -372,9 +379,10 @@ __global__ void k_guess(const SampleDev* __restrict__ sd, int D, const float* __
         const size_t vi = (size_t)s * V + (size_t)(z * D + y) * D + x;
         const double ar = S.ainv[2 * c], ai = S.ainv[2 * c + 1];
         const double den = ar * ar + ai * ai;
+        const double sg = sample_sigma(S);
         for (int a = 0; a < 3; ++a) {
-            const double er = S.esh[(size_t)(2 * a) * S.Npad + 2 * j] + (double)S.rscale * out[vi * 16 + 2 * a];
-            const double ei = S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1] + (double)S.rscale * out[vi * 16 + 2 * a + 1];
+            const double er = S.esh[(size_t)(2 * a) * S.Npad + 2 * j] + sg * out[vi * 16 + 2 * a];
+            const double ei = S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1] + sg * out[vi * 16 + 2 * a + 1];
             // (er + i ei) / (ar + i ai)
             x64[((size_t)s * 3 + a) * S.Npad + j] = Cx<double>{(er * ar + ei * ai) / den, (ei * ar - er * ai) / den};
         }
@@ -390,7 +398,7 @@ __global__ void k_record(const SampleDev* __restrict__ sd, const Cx<double>* __r
         for (int a = 0; a < 3; ++a) {
             const Cx<double> p = P[(size_t)a * S.Npad + j];
             const double lr = ar * p.re - ai * p.im, li = ar * p.im + ai * p.re;
-            const double inv = 1.0 / S.rscale;
+            const double inv = 1.0 / sample_sigma(S);
             resid[(size_t)(2 * a) * S.Npad + 2 * j] = (float)((lr - S.esh[(size_t)(2 * a) * S.Npad + 2 * j]) * inv);
             resid[(size_t)(2 * a) * S.Npad + 2 * j + 1] =
                 (float)((li - S.esh[(size_t)(2 * a) * S.Npad + 2 * j + 1]) * inv);
@@ -520,6 +528,11 @@ struct dda_nn {
     std::vector<DBuf> wf, wd;         // per layer BF16 operand layouts
     std::vector<DBuf> act;            // per layer output activations (bf16), act[0] = features
     DBuf out32, dA, dB, partials, lossacc, sdev;
+    // guess path: every sample's SampleDev and its (eps-1)/(eps+2), 1/alpha
+    // tables in one device buffer, uploaded from pinned staging in one copy
+    DBuf gsdev;
+    void* gstage = nullptr;
+    size_t gstage_n = 0;
     int ns_cap = 0;
     int adam_t = 0;
     std::vector<Sample> samples;
@@ -669,6 +682,7 @@ hipError_t nn_make_sample_dev(const NnSiteView& t, const dda_wave& w, const doub
     sd.rf = nullptr;
     sd.rscale = 1.0f;
     sd.pad_ = 0.0f;
+    sd.rn2 = nullptr;
     return hipSuccess;
 }
 
@@ -753,34 +767,76 @@ hipError_t nn_record_one(dda_nn* nn, const NnSiteView& tv, const dda_wave& w, co
 
 // Guesses P0 for nr right-hand sides of one target into x64 ([rhs][3][Npad] complex128).
 hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves, const double* ainv, int nr,
-                          const Cx<float>* esh, const Cx<float>* rf, const float* rscale, Cx<double>* x64,
+                          const Cx<float>* esh, const Cx<float>* rf, const double* rn2, Cx<double>* x64,
                           hipStream_t st) {
     if (t.n1 != t.n2 || t.n2 != t.n3 || t.n1 % 16) return hipErrorNotSupported;
     const int D = t.n1;
     const int chunk = 4;
     NCHK(nn_buffers(nn, D, chunk));
-    std::vector<SampleDev> sds(chunk);
-    std::vector<DBuf> kb(chunk);
     const size_t V = (size_t)D * D * D;
+    // one upload for all samples: their SampleDev records, then per sample
+    // (eps-1)/(eps+2) and 1/alpha per composition (4 ncomp doubles); the
+    // staging is pinned and kept, so the guess allocates and waits for nothing
+    const size_t tab = (size_t)4 * t.ncomp * sizeof(double);
+    const size_t bytes = (size_t)nr * (sizeof(SampleDev) + tab);
+    NCHK(nn->gsdev.ensure(bytes));
+    if (nn->gstage_n < bytes) {
+        // the previous guess's upload from the old staging has completed:
+        // every guess ends with the caller synchronizing on its timing event
+        if (nn->gstage) NCHK(hipHostFree(nn->gstage));
+        nn->gstage = nullptr;
+        nn->gstage_n = 0;
+        NCHK(hipHostMalloc(&nn->gstage, bytes, hipHostMallocDefault));
+        nn->gstage_n = bytes;
+    }
+    SampleDev* hs = reinterpret_cast<SampleDev*>(nn->gstage);
+    double* htab = reinterpret_cast<double*>(static_cast<char*>(nn->gstage) + (size_t)nr * sizeof(SampleDev));
+    const double* dtab = reinterpret_cast<const double*>(nn->gsdev.as<char>() + (size_t)nr * sizeof(SampleDev));
+    for (int k = 0; k < nr; ++k) {
+        SampleDev& sd = hs[k];
+        double* h = htab + (size_t)k * 4 * t.ncomp;
+        const double* ak = ainv + (size_t)k * 2 * t.ncomp;
+        for (int c = 0; c < t.ncomp; ++c) {
+            const double mr = t.m[2 * c], mi = t.m[2 * c + 1];
+            const double er = mr * mr - mi * mi, ei = 2 * mr * mi;
+            const double nre = er - 1, nim = ei, dr = er + 2, di = ei;
+            const double dd = dr * dr + di * di;
+            h[2 * c] = (nre * dr + nim * di) / dd;
+            h[2 * c + 1] = (nim * dr - nre * di) / dd;
+            h[2 * t.ncomp + 2 * c] = ak[2 * c];
+            h[2 * t.ncomp + 2 * c + 1] = ak[2 * c + 1];
+        }
+        for (int i = 0; i < 3; ++i) sd.khat[i] = waves[k].khat[i];
+        for (int i = 0; i < 6; ++i) sd.e[i] = waves[k].e0[i];
+        sd.kd = t.kd;
+        sd.ox = t.origin[0];
+        sd.oy = t.origin[1];
+        sd.oz = t.origin[2];
+        sd.N = t.N;
+        sd.Npad = t.Npad;
+        sd.site_xyz = t.site_xyz;
+        sd.site_comp = t.site_comp;
+        sd.kfac = dtab + (size_t)k * 4 * t.ncomp;
+        sd.ainv = sd.kfac + 2 * t.ncomp;
+        sd.resid = nullptr;
+        sd.esh = reinterpret_cast<const float*>(esh + (size_t)k * 3 * t.Npad);
+        sd.rf = reinterpret_cast<const float*>(rf + (size_t)k * 3 * t.Npad);
+        sd.rscale = 1.0f;
+        sd.pad_ = 0.0f;
+        sd.rn2 = rn2 + k;
+    }
+    NCHK(hipMemcpyAsync(nn->gsdev.p, nn->gstage, bytes, hipMemcpyHostToDevice, st));
+    const SampleDev* dsd = nn->gsdev.as<SampleDev>();
     for (int s0 = 0; s0 < nr; s0 += chunk) {
         const int nb = std::min(chunk, nr - s0);
-        for (int k = 0; k < nb; ++k) {
-            NCHK(nn_make_sample_dev(t, waves[s0 + k], ainv + (size_t)(s0 + k) * 2 * t.ncomp, sds[k], kb[k]));
-            sds[k].esh = reinterpret_cast<const float*>(esh + (size_t)(s0 + k) * 3 * t.Npad);
-            sds[k].rf = reinterpret_cast<const float*>(rf + (size_t)(s0 + k) * 3 * t.Npad);
-            sds[k].rscale = rscale[s0 + k];
-        }
-        NCHK(hipMemcpyAsync(nn->sdev.p, sds.data(), nb * sizeof(SampleDev), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, nn->act[0].as<uint16_t>(), V * nb * 16);
         NCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_features, dim3(256, nb), dim3(256), 0, st, nn->sdev.as<SampleDev>(), D,
-                           nn->act[0].as<uint16_t>());
+        hipLaunchKernelGGL(k_features, dim3(256, nb), dim3(256), 0, st, dsd + s0, D, nn->act[0].as<uint16_t>());
         NCHK(hipGetLastError());
         NCHK(nn_forward_any(nn, nb, st));
-        hipLaunchKernelGGL(k_guess, dim3(256, nb), dim3(256), 0, st, nn->sdev.as<SampleDev>(), D, nn->out32.as<float>(),
+        hipLaunchKernelGGL(k_guess, dim3(256, nb), dim3(256), 0, st, dsd + s0, D, nn->out32.as<float>(),
                            x64 + (size_t)s0 * 3 * t.Npad);
         NCHK(hipGetLastError());
-        NCHK(hipStreamSynchronize(st));  // sdev and kb are reused by the next chunk
     }
     return hipSuccess;
 }
@@ -843,6 +899,7 @@ dda_status dda_nn_destroy(dda_nn* nn) {
     if (!nn) return DDA_OK;
     (void)hipDeviceSynchronize();
     drop_store(nn);
+    if (nn->gstage) (void)hipHostFree(nn->gstage);
     delete nn;
     return DDA_OK;
 }
