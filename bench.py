@@ -91,7 +91,7 @@ def pass_names(P, ctx, n, prec_name="float"):
         zname = {0: f"k_zpass_ct<float, {n}, {sh['tx']}>", 1: f"k_zpass2_ct<float, {n}, {sh['tx']}, 8>",
                  2: f"k_zpass3_ct<float, {n}, {sh['tx']}>",
                  3: f"k_zpass4_ct<float, {n}, {sh['tx']}, {grp}>",
-                 4: f"k_zpass5_ct<{sh['tx']}>"}[sh["zrb"]]
+                 4: f"k_zpass5_ct<{sh['tx']}, {grp}>"}[sh["zrb"]]
         iname = "k_pinv3_ct" if sh["ct"] & 4 else "k_pinv_ct"
         return [f"k_pfwd_ct<float, {n}, 0|1|2|3, {grp}>", zname, f"{iname}<float, {n}, 0, 0|1|2|3, {grp}>"], sh
     return ["k_plane_fwd<float>", "k_zpass<float>", "k_plane_inv<float, 0>"], sh

@@ -119,10 +119,10 @@ struct Target {
     double aeff = 0;
     FftPlan plans[3];
     DevMem d_xyz, d_comp, d_pstart, d_cstart, d_perm, tw64, tw32, gh64, gh32;
-    DevMem gz64, gz32;  // n = 64: spectrum with components interleaved (two-factor z pass)
+    DevMem gz64, gz32;  // n = 64, 128: spectrum with components interleaved (two-factor z passes)
     DevMem gz64g, gz32g;  // the same with x columns in the class-grouped slab's group order
     DevMem zt16, zt32, zt16g;  // n = 64: z-pass tile order per XCD
-    DevMem zt8;                // n = 128: the same for 8-column tiles
+    DevMem zt8, zt8g;          // n = 128: the same for 8-column tiles (row and grouped layouts)
     bool have64 = false, have32 = false;
     MvShape sh32{}, sh64{};
     Geo geo() const {
@@ -140,6 +140,7 @@ struct Target {
         g.ztiles32 = zt32.as<int>();
         g.ztiles16g = zt16g.as<int>();
         g.ztiles8 = zt8.as<int>();
+        g.ztiles8g = zt8g.as<int>();
         g.site_xyz = d_xyz.as<uint32_t>();
         g.site_comp = d_comp.as<uint8_t>();
         return g;
@@ -356,11 +357,12 @@ MvShape default_shape(const Target& t, int tx_pref) {
         c.zrb = (c.ct & 2) ? 1 : 0;
         if (c.ct && matvec_shape_ok<T>(g, t.plans, c)) s = c;
         // n = 128, FP32: the two-factor 16 x 8 z pass with one frequency
-        // parity per block half
+        // parity per block half, on the class-grouped slab (one load per
+        // frequency in the inverse plane pass)
         if (std::is_same<T, float>::value && g.n1 == 128) {
             MvShape c5 = s;
             c5.tx = 8;
-            c5.ct = (ct_available<T>(g.n1, 8) & 3);
+            c5.ct = (ct_available<T>(g.n1, 8) & 11);
             c5.zrb = 4;
             if ((c5.ct & 3) == 3 && matvec_shape_ok<T>(g, t.plans, c5)) s = c5;
         }
@@ -524,11 +526,15 @@ dda_status build_target(dda_ctx* c, Target& t, const int32_t dims[3], const uint
     t.zt32.release();
     t.zt16g.release();
     t.zt8.release();
+    t.zt8g.release();
     if (n1 == 128 && n2 == 128 && n3 == 128) {
-        const std::vector<int> order = zpass_tile_order(128, 8, false);
-        if (order.empty()) return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "z-pass tile order unbalanced");
-        HCHK(c, t.zt8.ensure(order.size() * 4));
-        HCHK(c, hipMemcpy(t.zt8.p, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+        for (int v = 0; v < 2; ++v) {
+            const std::vector<int> order = zpass_tile_order(128, 8, v == 1);
+            if (order.empty()) return fail(c, DDA_ERR_UNSUPPORTED_DIMS, "z-pass tile order unbalanced");
+            DevMem& d = v ? t.zt8g : t.zt8;
+            HCHK(c, d.ensure(order.size() * 4));
+            HCHK(c, hipMemcpy(d.p, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+        }
     }
     if (n1 == 64 && n2 == 64 && n3 == 64) {
         for (int v = 0; v < 3; ++v) {
@@ -666,13 +672,17 @@ dda_status ensure_green(dda_ctx* c, Target& t, uint32_t prec) {
     const bool cube = t.n[0] == t.n[1] && t.n[1] == t.n[2];
     if (cube && (t.n[0] == 64 || t.n[0] == 128)) {
         // spectrum with the 6 components of a frequency adjacent (two-factor
-        // z passes); n = 64 also in the class-grouped column order
+        // z passes), also in the class-grouped column order (group half
+        // width n/2); at n = 128 only FP32 has a two-factor z pass
         const size_t cs = oct / 6;
-        for (int hx : {0, 32}) {
-            if (hx && t.n[0] != 64) continue;
+        const int hg = t.n[0] / 2;
+        for (int hx : {0, hg}) {
             DevMem& d64 = hx ? t.gz64g : t.gz64;
-            HCHK(c, d64.ensure(oct * sizeof(Cx<double>)));
-            HCHK(c, launch_green_interleave<double>(t.gh64.as<Cx<double>>(), d64.as<Cx<double>>(), cs, hx, c->stream));
+            if (t.n[0] == 64) {
+                HCHK(c, d64.ensure(oct * sizeof(Cx<double>)));
+                HCHK(c, launch_green_interleave<double>(t.gh64.as<Cx<double>>(), d64.as<Cx<double>>(), cs, hx,
+                                                        c->stream));
+            }
             if (t.gh32.p) {
                 DevMem& d32 = hx ? t.gz32g : t.gz32;
                 HCHK(c, d32.ensure(oct * sizeof(Cx<float>)));

@@ -27,8 +27,10 @@ struct Geo {
     const int* ztiles16;
     const int* ztiles32;
     const int* ztiles16g;
-    // n = 128: the same for 8-column tiles (two-factor 16 x 8 z pass)
+    // n = 128: the same for 8-column tiles (two-factor 16 x 8 z pass), in
+    // the row layout and in the class-grouped layout
     const int* ztiles8;
+    const int* ztiles8g;
 };
 
 // Twiddle tables of one target: f_i[k] = exp(-2 pi i k / n_i) (k < n_i) and

@@ -699,7 +699,14 @@ __device__ __forceinline__ Cx<float> row_xor8(Cx<float> v) { return {row_xor8(v.
 // so no twiddle beyond those eight per thread is held; that half hands its
 // output to the parity-0 half through LDS.  Block b runs on XCD b mod 8,
 // taking every rhs of one tile before the next tile of its XCD's list.
-template <int TX>
+//
+// G: class-grouped slab, as in the n = 64 pass: a tile of 8 columns holds
+// two partner groups (positions 2k, 2k + 1 of a row, whose columns fold onto
+// the same spectrum columns), partner (hy, hx) = (c >> 1 & 1, c & 1) of
+// group c >> 2 in lane c of a quad; the store replaces each group by its
+// 2 x 2 Hadamard transform, and the spectrum copy's x columns follow the
+// group order.
+template <int TX, bool G>
 __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3, 3))) k_zpass5_ct(Cx<float>* __restrict__ slab, const Cx<float>* __restrict__ gh,
                                                       Tw<float> tw, int nrhs, const int* __restrict__ active,
                                                       const int* __restrict__ tiles) {
@@ -731,10 +738,20 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
     const int q0 = tile * TX;
     const int par = q0 / (N * N), rem = q0 % (N * N);
     const int px = par & 1, py = par >> 1;
-    const int kyp = rem / N, kx0 = rem % N;
-    int sx, sy;
-    const int kxi = fold_idx(2 * (kx0 + c) + px, N, sx);
-    const int kyi = fold_idx(2 * kyp + py, N, sy);
+    int sx, sy, kxi, kyi;
+    if constexpr (G) {
+        constexpr int HN = N / 2;
+        const int gq = (rem >> 2) + (c >> 2);
+        const int kx = 2 * (grp_bx(gq % HN, px, HN) + (c & 1) * HN) + px;
+        const int fx = kx > N ? 2 * N - kx : kx;
+        sx = kx > N ? -1 : 1;
+        kxi = px * (HN + 1) + spec_xpos(fx >> 1, px, HN);
+        kyi = fold_idx(2 * (gq / HN + ((c >> 1) & 1) * HN) + py, N, sy);
+    } else {
+        const int kyp = rem / N, kx0 = rem % N;
+        kxi = fold_idx(2 * (kx0 + c) + px, N, sx);
+        kyi = fold_idx(2 * kyp + py, N, sy);
+    }
     const T sxy = (T)(sx * sy);
     Cx<T>* base = slab + (size_t)r * 3 * N * NCOL;
     const uint32_t o0 = (uint32_t)j * NCOL + q0 + c;
@@ -776,10 +793,11 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
     const int k2 = j >> 1, e = j & 1;
     const T sgn = e ? (T)-1 : (T)1;
     // spectrum index of inner frequency k = k2 + 8 (k1' + 8 e), kz = 2 k + pz (folded)
+    const uint32_t sp0 = (uint32_t)kyi * D + kxi;
     auto spec_at = [&](int k1p) -> uint32_t {
         const int kz = 2 * (k2 + R2 * (k1p + 8 * e)) + pz;
         const int kzf = kz > N ? 2 * N - kz : kz;
-        return ((uint32_t)(pz * H + (kzf >> 1)) * D + kyi) * D + kxi;
+        return (uint32_t)(pz * H + (kzf >> 1)) * (D * D) + sp0;
     };
     // the first frequency's spectrum is loaded before the barrier
     float4 g0[3];
@@ -865,8 +883,11 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int z2 = 0; z2 < R2; ++z2)
-            base[o0 + (uint32_t)(a * N + R1 * z2) * NCOL] = u[a][z2] + X1[xi(a, z2, j)];
+        for (int z2 = 0; z2 < R2; ++z2) {
+            Cx<T> v = u[a][z2] + X1[xi(a, z2, j)];
+            if constexpr (G) v = quad_hadamard(v, c);
+            base[o0 + (uint32_t)(a * N + R1 * z2) * NCOL] = v;
+        }
 }
 
 template <int TX>
@@ -1257,12 +1278,12 @@ void launch_pinv_g(int nblk, bool two_factor, const Geo& g, const Tw<T>& tw, int
                        slab, x, y, b, ainv, g, tw, nrhs, active, w, partials);
 }
 
-// grouped: class-grouped slab (n = 64 only)
+// grouped: class-grouped slab (n = 64 and 128)
 template <class T, int N, int MODE, int DOT>
 void launch_pinv(int nblk, bool two_factor, bool grouped, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x,
                  Cx<T>* y, const Cx<T>* b, const Cx<T>* slab, const Cx<T>* ainv, const int* active, const Cx<T>* w,
                  double* partials, hipStream_t st) {
-    if constexpr (N == 64)
+    if constexpr (N == 64 || N == 128)
         if (grouped)
             return launch_pinv_g<T, N, MODE, DOT, true>(nblk, two_factor, g, tw, nrhs, x, y, b, slab, ainv, active, w,
                                                         partials, st);
@@ -1272,7 +1293,7 @@ void launch_pinv(int nblk, bool two_factor, bool grouped, const Geo& g, const Tw
 template <class T, int N, int UPD>
 void launch_pfwd(int nblk, bool grouped, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* slab,
                  const int* active, const UpdArgs& ua, hipStream_t st) {
-    if constexpr (N == 64) {
+    if constexpr (N == 64 || N == 128) {
         if (grouped) {
             hipLaunchKernelGGL((k_pfwd_ct<T, N, UPD, true>), dim3(nblk), dim3(plane_threads<N>()), (plane_lds<T, N>()),
                                st, x, slab, g, tw, nrhs, active, ua);
@@ -1317,9 +1338,14 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
         if constexpr (N != 128 || !std::is_same<T, float>::value) {
             return hipErrorNotSupported;
         } else {
-            if (tx != 8 || !g.ztiles8) return hipErrorNotSupported;
-            hipLaunchKernelGGL((k_zpass5_ct<8>), dim3(nrhs * (ntile / 8)), dim3(8 * 32), (zpass5_lds<8>()), st, slab,
-                               ghat, tw, nrhs, active, g.ztiles8);
+            const int* tl = (ct & 8) ? g.ztiles8g : g.ztiles8;
+            if (tx != 8 || !tl) return hipErrorNotSupported;
+            if (ct & 8)
+                hipLaunchKernelGGL((k_zpass5_ct<8, true>), dim3(nrhs * (ntile / 8)), dim3(8 * 32), (zpass5_lds<8>()),
+                                   st, slab, ghat, tw, nrhs, active, tl);
+            else
+                hipLaunchKernelGGL((k_zpass5_ct<8, false>), dim3(nrhs * (ntile / 8)), dim3(8 * 32), (zpass5_lds<8>()),
+                                   st, slab, ghat, tw, nrhs, active, tl);
             return hipGetLastError();
         }
     }
@@ -1422,6 +1448,15 @@ hipError_t set_attrs_n() {
             for (const void* f : f3)
                 if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         }
+        if constexpr (N == 128) {
+            const void* fg[] = {
+                (const void*)k_pfwd_ct<T, N, 0, true>, (const void*)k_pfwd_ct<T, N, 2, true>,
+                (const void*)k_pinv_ct<T, N, MV_AX, 0, true>, (const void*)k_pinv_ct<T, N, MV_AX, 1, true>,
+                (const void*)k_pinv_ct<T, N, MV_AX, 2, true>, (const void*)k_pinv_ct<T, N, MV_AX, 3, true>,
+                (const void*)k_pinv_ct<T, N, MV_RESID, 0, true>};
+            for (const void* f : fg)
+                if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        }
     }
     if constexpr (zpass_lds<T, N, 8>() <= LDS_MAX && N % 8 == 0) {
         if (e == hipSuccess)
@@ -1443,7 +1478,9 @@ hipError_t set_attrs_n() {
     }
     if constexpr (N == 128 && std::is_same<T, float>::value) {
         if (e == hipSuccess)
-            e = set_lds_limit((const void*)k_zpass5_ct<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+            e = set_lds_limit((const void*)k_zpass5_ct<8, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = set_lds_limit((const void*)k_zpass5_ct<8, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     }
     if constexpr (N == 64) {
         if (e == hipSuccess)
@@ -1488,7 +1525,7 @@ bool ct_zpass_fits(int n, int tx, int zrb);
 
 // Which passes of a cubic box of side n have a specialised kernel in precision
 // T with z tile tx: bit 0 planes, bit 1 z pass, bit 2 two-factor inverse
-// plane pass, bit 3 class-grouped slab (with z pass variant 3 only).
+// plane pass, bit 3 class-grouped slab (with z pass variants 3 and 4 only).
 template <class T>
 int ct_available(int n, int tx) {
     auto planes = [](size_t lds) { return lds <= LDS_MAX; };
@@ -1497,7 +1534,7 @@ int ct_available(int n, int tx) {
     if (planes((size_t)(3 * n + n * (n + 1)) * sizeof(Cx<T>))) bits |= 1;  // as plane_lds
     if ((bits & 1) && n == 64) bits |= 4;  // two-factor inverse plane pass
     if (ct_zpass_fits<T>(n, tx, 0) || ct_zpass_fits<T>(n, tx, 2) || ct_zpass_fits<T>(n, tx, 4)) bits |= 2;
-    if ((bits & 3) == 3 && ct_zpass_fits<T>(n, tx, 3)) bits |= 8;  // class-grouped slab
+    if ((bits & 3) == 3 && (ct_zpass_fits<T>(n, tx, 3) || ct_zpass_fits<T>(n, tx, 4))) bits |= 8;  // class-grouped slab
     return bits;
 }
 

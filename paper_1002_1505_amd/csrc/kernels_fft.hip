@@ -471,7 +471,7 @@ bool matvec_shape_ok(const Geo& g, const FftPlan* plans, const MvShape& sh) {
         if ((sh.ct & av) != sh.ct) return false;
         if ((sh.ct & 2) && !ct_zpass_fits<T>(g.n1, sh.tx, sh.zrb)) return false;
         if ((sh.ct & 4) && !(sh.ct & 1)) return false;
-        if ((sh.ct & 8) && ((sh.ct & 3) != 3 || sh.zrb != 3)) return false;
+        if ((sh.ct & 8) && ((sh.ct & 3) != 3 || (sh.zrb != 3 && sh.zrb != 4))) return false;
         if ((sh.ct & 3) == 3) return true;
     }
     if (sh.tx <= 0 || (g.n1 % sh.tx) != 0) return false;

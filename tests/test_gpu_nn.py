@@ -162,3 +162,49 @@ def test_profile_hook_counts_flops_and_times():
         net.profile(24, 2, 1)  # box side not a multiple of 16
     net.close()
     ctx.close()
+
+
+def test_save_load_round_trip(tmp_path):
+    """dda_nn_save / dda_nn_load: a network loaded into a fresh one (other
+    seed) holds the same parameters bit for bit and gives the same forward
+    output bit for bit; a file of another shape, a truncated file and a
+    missing file are refused with the documented status."""
+    import paper_1002_1505_amd as P
+    from paper_1002_1505_amd import _lib as L
+
+    ctx = P.Context(0)
+    a = P.Net(ctx, width=16, depth=3, seed=3)
+    rng = np.random.default_rng(11)
+    params = [(bf16(rng.standard_normal((27, cin, cout)) * 0.1), (rng.standard_normal(cout) * 0.05).astype(np.float32))
+              for cin, cout, _ in a.layers()]
+    a.set_params(params)
+    x = bf16(rng.standard_normal((1, 16, 16, 16, 16)))
+    out_a, _, _ = a.forward_backward(x)
+    path = str(tmp_path / "net.bin")
+    a.save(path)
+    b = P.Net(ctx, width=16, depth=3, seed=9)
+    assert not all(np.array_equal(p[0], q[0]) for p, q in zip(b.get_params(), a.get_params()))
+    b.load(path)
+    for (wa, ba), (wb, bb) in zip(a.get_params(), b.get_params()):
+        assert np.array_equal(wa, wb) and np.array_equal(ba, bb)
+    out_b, _, _ = b.forward_backward(x)
+    assert np.array_equal(out_a, out_b)
+    other = P.Net(ctx, width=32, depth=3, seed=3)
+    with pytest.raises(P.DDAError) as e:
+        other.load(path)
+    assert e.value.status == L.DDA_ERR_INVALID_ARG
+    raw = open(path, "rb").read()
+    short = str(tmp_path / "short.bin")
+    open(short, "wb").write(raw[: len(raw) // 2])
+    with pytest.raises(P.DDAError) as e:
+        b.load(short)
+    assert e.value.status == L.DDA_ERR_IO
+    with pytest.raises(P.DDAError) as e:
+        b.load(str(tmp_path / "missing.bin"))
+    assert e.value.status == L.DDA_ERR_IO
+    # a refused load leaves the parameters as they were
+    for (wa, ba), (wb, bb) in zip(a.get_params(), b.get_params()):
+        assert np.array_equal(wa, wb) and np.array_equal(ba, bb)
+    for n in (a, b, other):
+        n.close()
+    ctx.close()

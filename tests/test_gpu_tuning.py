@@ -84,9 +84,11 @@ def test_autotune_cache_roundtrip(ctx, tmp_path):
 
 
 def test_two_factor_zpass_128_matches_lds_zpass_and_oracle(ctx):
-    """The 128^3 box's FP32 default z pass (variant 4: two-factor 16 x 8,
-    one frequency parity per block half, the 16-point step split over lane
-    pairs) against the LDS-line z pass (variant 1) on the full vectors,
+    """The 128^3 box's FP32 two-factor z pass (variant 4: 16 x 8, one
+    frequency parity per block half, the 16-point step split over lane pairs),
+    in the row slab layout and in the class-grouped layout (Hadamard of the
+    quadrant partners in the z pass, one load per frequency in the inverse
+    pass), against the LDS-line z pass (variant 1) on the full vectors,
     element by element, and against the oracle's direct sum on sampled rows."""
     import paper_1002_1505_amd as P
 
@@ -99,16 +101,22 @@ def test_two_factor_zpass_128_matches_lds_zpass_and_oracle(ctx):
     rng = np.random.default_rng(128)
     x = rng.standard_normal((2, len(r), 3)) + 1j * rng.standard_normal((2, len(r), 3))
     ainv = np.array([[2.0 + 0.3j], [1.0 - 0.2j]])
-    y4 = ctx.matvec(x, ainv=ainv, prec=P.DDA_FP32)
-    ctx.set_shape(dict(sh, zrb=1, tx=8), prec=P.DDA_FP32)
-    y1 = ctx.matvec(x, ainv=ainv, prec=P.DDA_FP32)
+    ys = {}
+    for name, shp in (("row", dict(sh, ct=sh["ct"] & ~8)), ("grouped", dict(sh, ct=sh["ct"] | 8)),
+                      ("lines", dict(sh, ct=sh["ct"] & ~8, zrb=1, tx=8))):
+        ctx.set_shape(shp, prec=P.DDA_FP32)
+        ys[name] = ctx.matvec(x, ainv=ainv, prec=P.DDA_FP32)
     ctx.set_shape(sh, prec=P.DDA_FP32)
     rows = np.concatenate([[0, len(r) - 1], rng.choice(len(r), 30, replace=False)])
-    for s in range(2):
-        d = np.abs(y4[s] - y1[s])
-        scale = np.sqrt(np.mean(np.abs(y1[s]) ** 2))
-        print(f"rhs {s}: rms diff {np.sqrt(np.mean(d ** 2)) / scale:.2e}, max diff {d.max() / scale:.2e}", flush=True)
-        assert np.sqrt(np.mean(d ** 2)) / scale < 2e-6 and d.max() / scale < 2e-5
-        ref = dda.matvec_rows(r, kd, np.full(len(r), ainv[s, 0]), x[s], rows)
-        err = np.abs(y4[s][rows] - ref).max() / np.sqrt(np.mean(np.abs(ref) ** 2))
-        assert err < 2e-5, err
+    y1 = ys["lines"]
+    for name in ("row", "grouped"):
+        y4 = ys[name]
+        for s in range(2):
+            d = np.abs(y4[s] - y1[s])
+            scale = np.sqrt(np.mean(np.abs(y1[s]) ** 2))
+            print(f"{name} rhs {s}: rms diff {np.sqrt(np.mean(d ** 2)) / scale:.2e}, max diff {d.max() / scale:.2e}",
+                  flush=True)
+            assert np.sqrt(np.mean(d ** 2)) / scale < 2e-6 and d.max() / scale < 2e-5
+            ref = dda.matvec_rows(r, kd, np.full(len(r), ainv[s, 0]), x[s], rows)
+            err = np.abs(y4[s][rows] - ref).max() / np.sqrt(np.mean(np.abs(ref) ** 2))
+            assert err < 2e-5, err
