@@ -140,11 +140,34 @@ template <class T, int DIR> __device__ __forceinline__ void bfly8(Cx<T>* v) {
     v[7] = e[3] - o3;
 }
 
+// 16 points: the 8-point transforms of the even and odd samples and one
+// radix-2 step with the twiddles w16^k = exp(DIR 2 pi i k / 16).
+template <class T, int DIR> __device__ __forceinline__ void bfly16(Cx<T>* v) {
+    Cx<T> e[8], o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        e[k] = v[2 * k];
+        o[k] = v[2 * k + 1];
+    }
+    bfly8<T, DIR>(e);
+    bfly8<T, DIR>(o);
+    const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, r = (T)0.70710678118654752440;
+    const Cx<T> w[8] = {{1, 0}, {c1, (T)DIR * s1}, {r, (T)DIR * r}, {s1, (T)DIR * c1},
+                        {0, (T)DIR}, {-s1, (T)DIR * c1}, {-r, (T)DIR * r}, {-c1, (T)DIR * s1}};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const Cx<T> t = k == 0 ? o[0] : (k == 4 ? mul_si<T, DIR>(o[4]) : w[k] * o[k]);
+        v[k] = e[k] + t;
+        v[k + 8] = e[k] - t;
+    }
+}
+
 template <class T, int DIR, int R> __device__ __forceinline__ void bfly(Cx<T>* v) {
     if constexpr (R == 2) bfly2<T, DIR>(v);
     else if constexpr (R == 3) bfly3<T, DIR>(v);
     else if constexpr (R == 4) bfly4<T, DIR>(v);
     else if constexpr (R == 5) bfly5<T, DIR>(v);
+    else if constexpr (R == 16) bfly16<T, DIR>(v);
     else bfly8<T, DIR>(v);
 }
 
@@ -331,7 +354,7 @@ template <> struct RadixPlan<32> { static constexpr int np = 2; static constexpr
 template <> struct RadixPlan<48> { static constexpr int np = 3; static constexpr int r[3] = {3, 4, 4}; };
 template <> struct RadixPlan<64> { static constexpr int np = 2; static constexpr int r[2] = {8, 8}; };
 template <> struct RadixPlan<96> { static constexpr int np = 3; static constexpr int r[3] = {3, 8, 4}; };
-template <> struct RadixPlan<128> { static constexpr int np = 3; static constexpr int r[3] = {8, 4, 4}; };
+template <> struct RadixPlan<128> { static constexpr int np = 2; static constexpr int r[2] = {16, 8}; };
 template <> struct RadixPlan<256> { static constexpr int np = 3; static constexpr int r[3] = {8, 8, 4}; };
 
 // Line l of the LDS batch starts at (l / LG) * LS1 + (l % LG) * LS0; its

@@ -185,21 +185,33 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     ct_fft<T, -1, N, N, NTH, N, PITCH, 0, 1>(buf, t1, tid);   // along x: lines are rows
     ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y: lines are columns
     Cx<T>* out = slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + par) * (size_t)(N * N);
-    if constexpr (G) {
-        // one lane per group: its four quadrant partners (y, x), (y, x + n/2),
-        // (y + n/2, x), (y + n/2, x + n/2) lie in one LDS bank, so the lane
-        // reads all four (lanes of one access hold different groups of a row)
-        // and stores them as 4 consecutive elements
+    if constexpr (G && sizeof(Cx<T>) == 8) {
+        // a group's four quadrant partners (y, x), (y, x + n/2), (y + n/2, x),
+        // (y + n/2, x + n/2) are 4 consecutive elements of the slab; lane l
+        // of a wave stores half l / 32 (rows y or y + n/2) of group l % 32 of
+        // the wave's 32 groups as one 16-byte store, so each store of the
+        // wave covers 1 KB without gaps.  The two halves of a group lie in
+        // one LDS bank, read by lanes of different half-waves
+        constexpr int HN = N / 2;
+        static_assert(NTH % 64 == 0, "whole waves");
+        float4* o4 = reinterpret_cast<float4*>(out);
+#pragma unroll 4
+        for (int h = tid; h < N * N / 2; h += NTH) {
+            const int gq = (h >> 6) * 32 + (h & 31), half = (h >> 5) & 1;
+            const Cx<T>* q = buf + (gq / HN + half * HN) * PITCH + grp_bx(gq % HN, px, HN);
+            const Cx<T> a0 = q[0], a1 = q[HN];
+            o4[2 * (size_t)gq + half] = make_float4(a0.re, a0.im, a1.re, a1.im);
+        }
+    } else if constexpr (G) {
+        // one lane per group (FP64): its four quadrant partners lie in one
+        // LDS bank, so the lane reads all four and stores them as 4
+        // consecutive elements
         constexpr int HN = N / 2;
 #pragma unroll 2
         for (int gq = tid; gq < N * N / 4; gq += NTH) {
             const Cx<T>* q = buf + (gq / HN) * PITCH + grp_bx(gq % HN, px, HN);
             const Cx<T> a0 = q[0], a1 = q[HN], a2 = q[HN * PITCH], a3 = q[HN * PITCH + HN];
-            if constexpr (sizeof(Cx<T>) == 8) {
-                float4* o4 = reinterpret_cast<float4*>(out) + 2 * (size_t)gq;
-                o4[0] = make_float4(a0.re, a0.im, a1.re, a1.im);
-                o4[1] = make_float4(a2.re, a2.im, a3.re, a3.im);
-            } else {
+            {
                 Cx<T>* o = out + 4 * (size_t)gq;
                 o[0] = a0;
                 o[1] = a1;
@@ -934,9 +946,11 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
         // grouped slab (one load per frequency): a thread keeps one column kx
         // (NTH is a multiple of n); all its loads are issued before the first
         // use, and the block-uniform class branches around the twiddles are
-        // scalar
-        const int kxp = tid % N, bx = kxp >> 1, px = kxp & 1;
-        const int gs = grp_pos(bx, px, HN) * 4 + q;
+        // scalar.  Lanes run along the group positions of one frequency
+        // parity px (t = px n/2 + position), so a load of the wave reads
+        // consecutive groups of one class plane
+        const int tpos = tid % N, px = tpos / HN, bx = grp_bx(tpos % HN, px, HN), kxp = 2 * bx + px;
+        const int gs = (tpos % HN) * 4 + q;
         Cx<T> hy[NI];
         if (qy) {
 #pragma unroll
