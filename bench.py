@@ -80,7 +80,17 @@ def parse():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--eval-targets", type=int, default=2)
     ap.add_argument("--sweep", type=int, default=32)
+    ap.add_argument("--solver", choices=["bicgstab", "bicgstab2"], default="bicgstab2",
+                    help="Krylov solver of the headline and mixed-batch legs (bicgstab2: BiCGstab(2), the "
+                         "guide's default PBCGS2)")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="only the headline target's FP32 matvec at 32 rhs (reps launches of each pass), for "
+                         "profiler runs; prints the per-pass times and exits")
+    ap.add_argument("--reps", type=int, default=5, help="launches per pass in --matvec-only")
     return ap.parse_args()
+
+
+SOLVERS = {"bicgstab": 0, "bicgstab2": 1}
 
 
 def pass_names(P, ctx, n, prec_name="float"):
@@ -120,6 +130,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ctx = P.Context(0, stream=stream.cuda_stream)
+    solver = SOLVERS[a.solver]
 
     # headline: the 128^3 sphere, 16 orientations x 2 polarizations
     n, x, m = 128, 20.0, 1.33 + 0.01j
@@ -132,6 +143,15 @@ def main():
     ctx.build_green_fft(P.DDA_FP32 | P.DDA_FP64)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
+    if a.matvec_only:
+        nr = 2 * a.orientations
+        ms, by = ctx.profile_matvec(0, nrhs=nr, prec=P.DDA_FP32, reps=a.reps)
+        names, sh = pass_names(P, ctx, n)
+        print(json.dumps({"matvec_only": True, "nrhs": nr, "reps": a.reps, "kernels": names, "shape": sh,
+                          "pass_ms": [round(float(v), 5) for v in ms], "bytes": [float(v) for v in by],
+                          "pass_GBs": [round(float(v), 1) for v in by / (ms * 1e-3) / 1e9]}), flush=True)
+        ctx.close()
+        return
     rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 4)
     ori = synth.uniform_orientations(a.orientations, rng)
     kh, e0, n_tf, e_tf = [], [], [], []
@@ -151,7 +171,7 @@ def main():
     ndir1 = len(thetas)
 
     def step():
-        _, st, status = ctx.solve(kh, e0, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE, want_p=False)
+        _, st, status = ctx.solve(kh, e0, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE, want_p=False, solver=solver)
         q = ctx.cross_sections(nrhs)
         f = ctx.amplitudes(nrhs, n_tf, e_tf)  # (rhs, all directions, 2)
         # each orientation's own 74 directions
@@ -198,8 +218,8 @@ def main():
         "config": {
             "workload": f"sphere in {n}^3 box (N={N}), FFT grid {2 * n}^3, m=1.33+0.01i, x={x}, LDR, "
                         f"{a.orientations} random orientations x 2 polarizations = {nrhs} rhs in one solve, "
-                        "FP32 matvec + FP64 refinement, tol 1e-5, cross sections and 74-direction amplitudes "
-                        "per orientation",
+                        f"{'BiCGstab(2)' if solver else 'BiCGstab'}, FP32 matvec + FP64 refinement, tol 1e-5, "
+                        "cross sections and 74-direction amplitudes per orientation",
             "global_batch": nrhs,
             "parallelism": "single GPU",
         },
@@ -224,6 +244,8 @@ def main():
                       "frac_hbm": round(float(mv[nr][1].sum() / (mv[nr][0].sum() * 1e-3) / 1e9) / HBM_PEAK_GBS, 4)}
             for nr in mv},
         "solve": {
+            "solver": a.solver,
+            "matvecs_mean": round(float(np.mean([s["matvecs"] for s in stats[-1]])), 2),
             "iters_mean": round(float(np.mean([s["iters"] for s in stats[-1]])), 2),
             "iters_max": int(max(s["iters"] for s in stats[-1])),
             "outer": sorted(set(s["outer"] for s in stats[-1])),
@@ -243,7 +265,7 @@ def main():
         kd64 = 10.0 / ((3.0 * int(occ64.sum()) / (4.0 * np.pi)) ** (1.0 / 3.0))
         out["orient_avg"] = orientation_average(P, ctx, a, occ64, kd64, 1.5 + 0.1j)
     if not a.no_c3:
-        out["c3"] = mixed_batch(P, ctx, synth, n_orient=a.c3_orientations)
+        out["c3"] = mixed_batch(P, ctx, synth, n_orient=a.c3_orientations, solver=solver)
     if not a.no_learned:
         out["learned"] = learned_vs_plain(P, ctx, a)
     if not a.no_cpu_baseline:
@@ -343,7 +365,7 @@ def sphere64(P, ctx, synth, a, steps=10):
     }
 
 
-def mixed_batch(P, ctx, synth, boxes=(32, 32, 32, 48, 48, 48, 64, 64), n_orient=64, max_iter=5000):
+def mixed_batch(P, ctx, synth, boxes=(32, 32, 32, 48, 48, 48, 64, 64), n_orient=64, max_iter=5000, solver=1):
     """Seeded random ellipsoids in 32^3, 48^3 and 64^3 boxes (axis ratios
     1 : U[1,2] : U[1,3], random rotation), Re m ~ U[1.2, 1.8], Im m ~
     log-U[0.001, 0.3], |m| k d ~ U[0.3, 0.8], LDR; n_orient uniform random
@@ -374,10 +396,10 @@ def mixed_batch(P, ctx, synth, boxes=(32, 32, 32, 48, 48, 48, 64, 64), n_orient=
         ctx.autotune(2 * n_orient, os.path.join(d, "tune.json"))
     tune_s = time.perf_counter() - t0
     # warm-up: workspaces and graphs, a few iterations
-    ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=8)
+    ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=8, solver=solver)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, st, _ = ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=max_iter)
+    _, st, _ = ctx.solve(kh, e0, targets=tg, tol=1e-5, want_p=False, max_iter=max_iter, solver=solver)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     sel = [[i for i in range(nrhs) if tg[i] == t] for t in range(len(tgt))]
@@ -385,14 +407,16 @@ def mixed_batch(P, ctx, synth, boxes=(32, 32, 32, 48, 48, 48, 64, 64), n_orient=
     iters = [float(np.mean([st[i]["iters"] for i in sel[t]])) for t in range(len(tgt))]
     return {
         "workload": f"{len(tgt)} random ellipsoids in boxes {list(boxes)}, {n_orient} orientations x 2 "
-                    "polarizations each, LDR, FP32 matvec + FP64 refinement, tol 1e-5, one solve call, "
-                    "autotuned launch shapes",
+                    f"polarizations each, LDR, {'BiCGstab(2)' if solver else 'BiCGstab'}, FP32 matvec + FP64 "
+                    "refinement, tol 1e-5, one solve call, autotuned launch shapes",
         "solves": nrhs,
         "converged": f"{conv}/{nrhs}",
         "solves_per_s": round(nrhs / dt, 2),
         "solve_s": round(dt, 3),
         "autotune_s": round(tune_s, 2),
         "mean_iters_by_target": [round(v, 1) for v in iters],
+        "mean_matvecs_by_target": [round(float(np.mean([st[i]["matvecs"] for i in sel[t]])), 1)
+                                   for t in range(len(tgt))],
         "median_target_iters": round(float(np.median(iters)), 1),
         "m_kd": [[round(m.real, 3), round(m.imag, 4), round(kd, 4), round(abs(m) * kd, 3)] for _, m, kd in tgt],
         "sites": [int(o.sum()) for o, _, _ in tgt],

@@ -732,11 +732,17 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
     constexpr int XS = 3 * R2 * R1 * TX;  // one exchange buffer [a][k2][z1][c]
     constexpr int PER_XCD = NCOL / TX / 8;
     static_assert(TX == 8, "lane layout: 8 columns, bit 3 of the lane is the parity of z1");
+    static_assert(PER_XCD % 2 == 0, "whole tile pairs per XCD");
     extern __shared__ unsigned char smem_raw[];
     const int b = blockIdx.x;
+    // consecutive blocks of an XCD take the two tiles of a list pair
+    // (entries 2i, 2i + 1: neighbouring tiles, whose 64-byte row segments
+    // share 128-byte lines) for one rhs, then the next rhs, so each line is
+    // fetched once while both halves are in use
     const int pos = b >> 3;
-    const int r = pos % nrhs;
-    const int tile = tiles[(b & 7) * PER_XCD + pos / nrhs];
+    const int pair = pos / (2 * nrhs), within = pos % (2 * nrhs);
+    const int r = within >> 1;
+    const int tile = tiles[(b & 7) * PER_XCD + 2 * pair + (within & 1)];
     if ((active && !active[r]) || tile < 0) return;
     const int tid = threadIdx.x;
     const int pz = __builtin_amdgcn_readfirstlane(tid / (TX * R1));
