@@ -687,6 +687,15 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
         }
 }
 
+// Non-temporal store of a slab value the z pass writes once per matvec.
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_stream(Cx<float>* p, Cx<float> v) {
+    f2v w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(p));
+}
+
 // Lane (lane ^ 8) of the same row of 16 lanes: a DPP row rotation by 8.
 // Every lane of the wave must be active.
 __device__ __forceinline__ float row_xor8(float v) {
@@ -904,7 +913,7 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
         for (int z2 = 0; z2 < R2; ++z2) {
             Cx<T> v = u[a][z2] + X1[xi(a, z2, j)];
             if constexpr (G) v = quad_hadamard(v, c);
-            base[o0 + (uint32_t)(a * N + R1 * z2) * NCOL] = v;
+            st_stream(base + o0 + (uint32_t)(a * N + R1 * z2) * NCOL, v);
         }
 }
 
