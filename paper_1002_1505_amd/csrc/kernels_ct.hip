@@ -40,6 +40,17 @@ __device__ __forceinline__ int fold_idx(int k, int n, int& sgn) {
     return (f & 1) * (n / 2 + 1) + (f >> 1);
 }
 
+// Non-temporal store of a slab value (the 128^3 z pass's output, which at
+// that size outgrows every cache before the inverse pass reads it; smaller
+// slabs stay in the last-level cache between passes and are stored normally).
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_stream(Cx<float>* p, Cx<float> v) {
+    f2v w;
+    w.x = v.re;
+    w.y = v.im;
+    __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(p));
+}
+
 // threads of the plane passes: 512 for n = 64 (8 waves per block; with 4
 // blocks per CU by LDS that is 32 waves, against 16 with 256 threads and no
 // room for 1024)
@@ -687,15 +698,6 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
         }
 }
 
-// Non-temporal store of a slab value the z pass writes once per matvec.
-typedef float f2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void st_stream(Cx<float>* p, Cx<float> v) {
-    f2v w;
-    w.x = v.re;
-    w.y = v.im;
-    __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(p));
-}
-
 // Lane (lane ^ 8) of the same row of 16 lanes: a DPP row rotation by 8.
 // Every lane of the wave must be active.
 __device__ __forceinline__ float row_xor8(float v) {
@@ -1042,22 +1044,37 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
             buf[kyp * PITCH + kxp] = v;
         }
     }
+    // the gather operands of the thread's first PF sites (site, composition,
+    // x, and the rhs or dot-product vector) are requested before the
+    // transforms, so that their latency overlaps them; the sites are visited
+    // in the order j0 + tid, j0 + tid + NTH, ... either way
+    constexpr int PF = 2;
+    const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
+    const Cx<T>* av = ainv + (size_t)rhs * g.ncomp;
+    uint32_t pf_s[PF];
+    int pf_c[PF];
+    Cx<T> pf_x[PF], pf_w[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        // an index past the class is clamped into it (an empty class reads
+        // site 0; neither value is used)
+        const int j = j1 > j0 ? min(j0 + tid + k * NTH, j1 - 1) : 0;
+        pf_s[k] = g.site_xyz[j];
+        pf_c[k] = g.site_comp[j];
+        pf_x[k] = x[vo + j];
+        if (MODE == MV_RESID) pf_w[k] = bvec[vo + j];
+        else if (DOT == 1 || DOT == 3) pf_w[k] = wv[vo + j];
+    }
     __syncthreads();
     ct_fft<T, +1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);    // along y, every column
     ct_fft<T, +1, N, HN, NTH, HN, PITCH, 0, 1>(buf, t1, tid);  // along x, rows y' < n/2
-    const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
-    const Cx<T>* av = ainv + (size_t)rhs * g.ncomp;
     double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0, a3r = 0, a3i = 0;
-#pragma unroll 2
-    for (int j = j0 + tid; j < j1; j += NTH) {
-        const uint32_t s = g.site_xyz[j];
+    auto visit = [&](int j, uint32_t s, int cj, Cx<T> xj, Cx<T> wj) {
         const int sx = s & 1023, sy = (s >> 10) & 1023;
-        const Cx<T> xj = x[vo + j];
-        Cx<T> v = buf[(sy >> 1) * PITCH + (sx >> 1)] + av[g.site_comp[j]] * xj;
-        if (MODE == MV_RESID) v = bvec[vo + j] - v;
+        Cx<T> v = buf[(sy >> 1) * PITCH + (sx >> 1)] + av[cj] * xj;
+        if (MODE == MV_RESID) v = wj - v;
         y[vo + j] = v;
         if (DOT == 1) {
-            const Cx<T> wj = wv[vo + j];
             a0r += (double)wj.re * v.re + (double)wj.im * v.im;
             a0i += (double)wj.re * v.im - (double)wj.im * v.re;
         } else if (DOT == 2 || DOT == 3) {
@@ -1065,7 +1082,6 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
             a0i += (double)v.re * xj.im - (double)v.im * xj.re;
             a1r += (double)v.re * v.re + (double)v.im * v.im;
             if (DOT == 3) {
-                const Cx<T> wj = wv[vo + j];
                 a1i += (double)xj.re * xj.re + (double)xj.im * xj.im;
                 a2r += (double)wj.re * xj.re + (double)wj.im * xj.im;
                 a2i += (double)wj.re * xj.im - (double)wj.im * xj.re;
@@ -1073,6 +1089,16 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
                 a3i += (double)wj.re * v.im - (double)wj.im * v.re;
             }
         }
+    };
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+        if (j0 + tid + k * NTH < j1) visit(j0 + tid + k * NTH, pf_s[k], pf_c[k], pf_x[k], pf_w[k]);
+#pragma unroll 2
+    for (int j = j0 + tid + PF * NTH; j < j1; j += NTH) {
+        Cx<T> wj = {0, 0};
+        if (MODE == MV_RESID) wj = bvec[vo + j];
+        else if (DOT == 1 || DOT == 3) wj = wv[vo + j];
+        visit(j, g.site_xyz[j], g.site_comp[j], x[vo + j], wj);
     }
     if (DOT) {
         __shared__ double sh[8 * 16];
