@@ -166,17 +166,15 @@ def main():
         n_tf.append(nt)
         e_tf.append(et)
     nrhs = len(kh)
-    n_tf = np.concatenate(n_tf)  # every orientation's 74 directions, in the target frame
-    e_tf = np.concatenate(e_tf)
-    ndir1 = len(thetas)
+    # each rhs's own orientation's 74 directions, in the target frame
+    n_tf = np.stack([n_tf[i // 2] for i in range(nrhs)])
+    e_tf = np.stack([e_tf[i // 2] for i in range(nrhs)])
 
     def step():
         _, st, status = ctx.solve(kh, e0, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE, want_p=False, solver=solver)
         q = ctx.cross_sections(nrhs)
-        f = ctx.amplitudes(nrhs, n_tf, e_tf)  # (rhs, all directions, 2)
-        # each orientation's own 74 directions
-        f_own = np.stack([f[i, (i // 2) * ndir1:(i // 2 + 1) * ndir1] for i in range(nrhs)])
-        return st, q, f_own
+        f = ctx.amplitudes_per_rhs(nrhs, n_tf, e_tf)  # (rhs, its orientation's 74 directions, 2)
+        return st, q, f
 
     for _ in range(a.warmup):
         step()

@@ -340,6 +340,15 @@ dda_status dda_cross_sections_phi(dda_ctx* ctx, int32_t npairs, int32_t ncomb, c
  * f: nrhs*ndir*2 complex128 (interleaved). */
 dda_status dda_amplitudes(dda_ctx* ctx, int32_t nrhs, int32_t ndir, const double* n_tf,
                           const double* e_tf, double* f);
+/* The same amplitudes with a direction set per right-hand side: rhs i of the
+ * last solve takes the ndir directions n_tf[i][0..ndir-1] (n_tf: nrhs x ndir
+ * x 3 doubles) with polarization vectors e_tf[i] (nrhs x ndir x 6 doubles),
+ * e.g. the lab-frame scattering directions of each orientation of a sweep
+ * expressed in the target frame.  f: nrhs*ndir*2 complex128, as above.
+ * DDA_ERR_INVALID_ARG for nrhs other than the last solve's or ndir <= 0;
+ * DDA_ERR_STATE before a solve. */
+dda_status dda_amplitudes_per_rhs(dda_ctx* ctx, int32_t nrhs, int32_t ndir, const double* n_tf, const double* e_tf,
+                                  double* f);
 
 /* Total E and B at npts points in or near the targets of the last solve
  * (guide, "Postprocessing: Calculating E and B In or Near the Target"): the

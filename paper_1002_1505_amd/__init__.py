@@ -240,6 +240,17 @@ class Context:
         f = f.reshape(nrhs, ndir, 2, 2)
         return f[..., 0] + 1j * f[..., 1]
 
+    def amplitudes_per_rhs(self, nrhs: int, n_tf, e_tf):
+        """Amplitudes with a direction set per rhs: n_tf (nrhs, ndir, 3), e_tf
+        (nrhs, ndir, 6); returns (nrhs, ndir, 2) complex (dda_amplitudes_per_rhs)."""
+        n_tf = np.ascontiguousarray(n_tf, dtype=np.float64).reshape(nrhs, -1, 3)
+        ndir = n_tf.shape[1]
+        e_tf = np.ascontiguousarray(e_tf, dtype=np.float64).reshape(nrhs, ndir, 6)
+        f = np.zeros(nrhs * ndir * 2 * 2)
+        _check(self.h, self.lib.dda_amplitudes_per_rhs(self.h, int(nrhs), ndir, _dptr(n_tf), _dptr(e_tf), _dptr(f)))
+        f = f.reshape(nrhs, ndir, 2, 2)
+        return f[..., 0] + 1j * f[..., 1]
+
     def near_field(self, nrhs: int, points, want_b=True):
         """Total E (and B) at points (npts, 3) in the target frame, lattice
         units from the target origin, for every rhs of the last solve

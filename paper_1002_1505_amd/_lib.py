@@ -99,6 +99,7 @@ SIGNATURES = {
     "dda_orientation_samples": (C.c_int32, [D, C.POINTER(C.c_int32), D, D, D, D]),
     "dda_phi_coefficients": (C.c_int32, [C.c_double, C.c_double, C.c_double, C.c_int32, D, D, D, D, D]),
     "dda_amplitudes": (C.c_int32, [P, C.c_int32, C.c_int32, D, D, D]),
+    "dda_amplitudes_per_rhs": (C.c_int32, [P, C.c_int32, C.c_int32, D, D, D]),
     "dda_near_field": (C.c_int32, [P, C.c_int32, C.c_int32, D, D, D]),
     "dda_polarization": (C.c_int32, [C.c_int32, D, C.c_double, D, D]),
     "dda_mueller": (C.c_int32, [C.c_int32, D, D, D, D, D, D]),

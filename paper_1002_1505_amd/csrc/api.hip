@@ -2086,32 +2086,48 @@ dda_status dda_scattering_moments(dda_ctx* c, int32_t nrhs, int32_t ndir, const 
     return DDA_OK;
 }
 
-dda_status dda_amplitudes(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* n_tf, const double* e_tf, double* f) {
+}  // extern "C"
+
+namespace {
+// Amplitudes of the last solve for directions shared by every rhs
+// (per_rhs = false, n_tf: ndir x 3) or per rhs (n_tf: nrhs x ndir x 3,
+// e_tf: nrhs x ndir x 6, rhs i taking block i).
+dda_status amplitudes_impl(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* n_tf, const double* e_tf, double* f,
+                           bool per_rhs) {
     SCHK(check_ctx(c));
     if (!c->have_solution) return fail(c, DDA_ERR_STATE, "amplitudes before a solve");
     if (nrhs != c->last_nrhs || ndir <= 0 || !n_tf || !e_tf || !f)
-        return fail(c, DDA_ERR_INVALID_ARG, "amplitudes: bad arguments");
+        return fail(c, DDA_ERR_INVALID_ARG, "amplitudes: bad arguments (nrhs must match the last solve)");
     hipStream_t st = c->stream;
-    DevMem &dn = c->scr[0], &dF = c->scr[1], &dP = c->scr[2];
-    HCHK(c, dn.ensure((size_t)ndir * 3 * sizeof(double)));
-    HCHK(c, hipMemcpyAsync(dn.p, n_tf, (size_t)ndir * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    DevMem &dn = c->scr[0], &dF = c->scr[1], &dP = c->scr[2], &dS = c->scr[3];
+    const size_t nset = per_rhs ? (size_t)nrhs : 1;
+    HCHK(c, dn.ensure(nset * ndir * 3 * sizeof(double)));
+    HCHK(c, hipMemcpyAsync(dn.p, n_tf, nset * ndir * 3 * sizeof(double), hipMemcpyHostToDevice, st));
     for (auto& gp : c->groups) {
         Group& g = *gp;
         Target& t = *c->tg[g.tgt];
         HCHK(c, dF.ensure((size_t)g.nr * ndir * 3 * sizeof(Cx<double>)));
         HCHK(c, dP.ensure((size_t)ampl_chunks(ndir, g.nr, t.N) * g.nr * ndir * 6 * sizeof(double)));
+        const int* dset = nullptr;
+        if (per_rhs) {
+            // direction block of each slot: its call-level rhs index
+            HCHK(c, dS.ensure((size_t)g.nr * sizeof(int)));
+            HCHK(c, hipMemcpyAsync(dS.p, g.idx.data(), (size_t)g.nr * sizeof(int), hipMemcpyHostToDevice, st));
+            dset = dS.as<int>();
+        }
         HCHK(c, launch_ampl(t.geo(), t.origin, t.kd, g.nr, g.x64.as<Cx<double>>(), ndir, dn.as<double>(),
-                            dF.as<Cx<double>>(), dP.as<double>(), st));
+                            dF.as<Cx<double>>(), dP.as<double>(), st, dset));
         std::vector<cd> F((size_t)g.nr * ndir * 3);
         HCHK(c, hipMemcpyAsync(F.data(), dF.p, F.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
         HCHK(c, hipStreamSynchronize(st));
         const double k3 = t.kd * t.kd * t.kd;
         for (int s = 0; s < g.nr; ++s) {
             const int i = g.idx[s];
+            const double* es = per_rhs ? e_tf + (size_t)i * ndir * 6 : e_tf;
             for (int d = 0; d < ndir; ++d) {
                 const cd* Fv = &F[((size_t)s * ndir + d) * 3];
                 for (int mm = 0; mm < 2; ++mm) {
-                    const double* e = e_tf + (size_t)d * 6 + 3 * mm;
+                    const double* e = es + (size_t)d * 6 + 3 * mm;
                     const cd v = k3 * (e[0] * Fv[0] + e[1] * Fv[1] + e[2] * Fv[2]);
                     f[(((size_t)i * ndir + d) * 2 + mm) * 2] = v.real();
                     f[(((size_t)i * ndir + d) * 2 + mm) * 2 + 1] = v.imag();
@@ -2120,6 +2136,18 @@ dda_status dda_amplitudes(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* 
         }
     }
     return DDA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+dda_status dda_amplitudes(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* n_tf, const double* e_tf, double* f) {
+    return amplitudes_impl(c, nrhs, ndir, n_tf, e_tf, f, false);
+}
+
+dda_status dda_amplitudes_per_rhs(dda_ctx* c, int32_t nrhs, int32_t ndir, const double* n_tf, const double* e_tf,
+                                  double* f) {
+    return amplitudes_impl(c, nrhs, ndir, n_tf, e_tf, f, true);
 }
 
 dda_status dda_near_field(dda_ctx* c, int32_t nrhs, int32_t npts, const double* pts, double* E, double* B) {

@@ -274,7 +274,8 @@ int ampl_chunks(int ndir, int nrhs, int N);
 hipError_t launch_near_field(const Geo& g, const double* o, int nrhs, const Cx<double>* P, const WaveDev* w,
                              const double* pts, int npts, double* out, hipStream_t st);
 hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const Cx<double>* P, int ndir,
-                       const double* ndirs, Cx<double>* F, double* partials, hipStream_t st);
+                       const double* ndirs, Cx<double>* F, double* partials, hipStream_t st,
+                       const int* dset = nullptr);
 
 hipError_t configure_fft_kernels();
 

@@ -838,20 +838,26 @@ __global__ void __launch_bounds__(256) k_xsec_pair(Geo g, const Cx<double>* __re
 // partials[((chunk * nrhs + rhs) * ndir + dir) * 6 + q].  On the lattice the
 // phase separates per axis, so the block evaluates n1 + n2 + n3 sincos for
 // its direction and each site takes two complex products of table entries.
+// PER = false: every rhs takes the same ndir directions, a block serves a
+// pair of rhs (same target, same phases).  PER = true: rhs slot r takes
+// directions dset[r] * ndir ... dset[r] * ndir + ndir - 1 of nd, one rhs per
+// block.
+template <bool PER>
 __global__ void __launch_bounds__(256) k_ampl(Geo g, double ox, double oy, double oz, double k,
                                               const Cx<double>* __restrict__ P, const double* __restrict__ nd,
-                                              double* __restrict__ partials, int ndir, int nrhs) {
+                                              double* __restrict__ partials, int ndir, int nrhs,
+                                              const int* __restrict__ dset) {
     __shared__ double sh[12 * 4];
     // the phase factors per axis, exp(-i k n_a (a - o_a)) for a = x, y, z at
     // every lattice coordinate of the box: [n1 | n2 | n3]
     extern __shared__ unsigned char smem_raw[];
     Cx<double>* T = reinterpret_cast<Cx<double>*>(smem_raw);
-    // a block serves a pair of rhs (same target, same phases)
-    const int dir = blockIdx.x, r0 = 2 * blockIdx.y, chunk = blockIdx.z;
-    const int nr = min(2, nrhs - r0);
+    const int dir = blockIdx.x, r0 = (PER ? 1 : 2) * blockIdx.y, chunk = blockIdx.z;
+    const int nr = PER ? 1 : min(2, nrhs - r0);
     const int per = (g.N + gridDim.z - 1) / gridDim.z;
     const int j0 = chunk * per, j1 = min(g.N, j0 + per);
-    const double nx = nd[3 * dir], ny = nd[3 * dir + 1], nz = nd[3 * dir + 2];
+    const size_t di = PER ? (size_t)dset[r0] * ndir + dir : (size_t)dir;
+    const double nx = nd[3 * di], ny = nd[3 * di + 1], nz = nd[3 * di + 2];
     const int n12 = g.n1 + g.n2, nt = n12 + g.n3;
     for (int i = threadIdx.x; i < nt; i += blockDim.x) {
         const double a = i < g.n1 ? nx * ((double)i - ox)
@@ -1421,11 +1427,15 @@ hipError_t launch_near_field(const Geo& g, const double* o, int nrhs, const Cx<d
     return hipGetLastError();
 }
 hipError_t launch_ampl(const Geo& g, const double* o, double k, int nrhs, const Cx<double>* P, int ndir,
-                       const double* ndirs, Cx<double>* F, double* partials, hipStream_t st) {
+                       const double* ndirs, Cx<double>* F, double* partials, hipStream_t st, const int* dset) {
     const int nc = ampl_chunks(ndir, nrhs, g.N);
     const size_t lds = (size_t)(g.n1 + g.n2 + g.n3) * sizeof(Cx<double>);  // at most 3 x 1023 entries
-    hipLaunchKernelGGL(k_ampl, dim3(ndir, (nrhs + 1) / 2, nc), dim3(256), lds, st, g, o[0], o[1], o[2], k, P, ndirs,
-                       partials, ndir, nrhs);
+    if (dset)
+        hipLaunchKernelGGL(k_ampl<true>, dim3(ndir, nrhs, nc), dim3(256), lds, st, g, o[0], o[1], o[2], k, P, ndirs,
+                           partials, ndir, nrhs, dset);
+    else
+        hipLaunchKernelGGL(k_ampl<false>, dim3(ndir, (nrhs + 1) / 2, nc), dim3(256), lds, st, g, o[0], o[1], o[2], k,
+                           P, ndirs, partials, ndir, nrhs, dset);
     HIP_TRY(hipGetLastError());
     const int n = nrhs * ndir * 6;
     hipLaunchKernelGGL(k_ampl_reduce, dim3((n + 255) / 256), dim3(256), 0, st, partials, nc, n,

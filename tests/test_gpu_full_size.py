@@ -166,3 +166,25 @@ def test_mixed_box_batch_vs_oracle(ctx):
         r, comp, _ = dda.sites_from_occupancy(occ)
         _check_solution(f"{name} pol {i % 2}", r, comp, [m], kd, kh[i], ee[i], Pg[i], st[i], q[i],
                         _gold(name, i % 2))
+
+
+def test_bicgstab2_box128_reaches_the_residual(ctx):
+    """BiCGstab(2) on the 128^3 sphere with the default launch shape (the
+    fused inner products of the grouped-slab passes feed the cycle's
+    scalars): full-vector FP64 residual by the oracle's FFT matvec, and the
+    efficiencies against BiCGstab's solution."""
+    import paper_1002_1505_amd as P
+
+    occ, r, comp, kd, m = _problem("box128_grid256")
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    khat, e0 = P.orientation_waves(0.4, 1.0, 0.3)
+    _, st1, status = ctx.solve(khat, e0, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE, want_p=False)
+    assert status == 0
+    q1 = ctx.cross_sections(2)
+    Pg, st2, status = ctx.solve(khat, e0, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE, solver=P.DDA_SOLVER_BICGSTAB2)
+    print(f"[box128 bicgstab2] stats {st2} (bicgstab {[s['iters'] for s in st1]})", flush=True)
+    assert status == 0
+    q2 = ctx.cross_sections(2)
+    for l in range(2):
+        _check_solution(f"box128 bicgstab2 pol {l}", r, comp, [m], kd, khat[l], e0[l], Pg[l], st2[l])
+        assert np.all(np.abs(q2[l] - q1[l]) <= 2e-4 * np.abs(q1[l]))
