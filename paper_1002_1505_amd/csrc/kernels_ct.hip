@@ -40,9 +40,11 @@ __device__ __forceinline__ int fold_idx(int k, int n, int& sgn) {
     return (f & 1) * (n / 2 + 1) + (f >> 1);
 }
 
-// Non-temporal store of a slab value (the 128^3 z pass's output, which at
-// that size outgrows every cache before the inverse pass reads it; smaller
-// slabs stay in the last-level cache between passes and are stored normally).
+// Non-temporal store of a slab value: the 128^3 z pass's output, which at
+// that size outgrows every cache before the inverse pass reads it and, stored
+// normally, would push the tensor spectrum that a z-pass block reuses for
+// every rhs out of the L2 (smaller slabs stay in the last-level cache between
+// passes and are stored normally).
 typedef float f2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void st_stream(Cx<float>* p, Cx<float> v) {
     f2v w;
@@ -720,8 +722,8 @@ __device__ __forceinline__ Cx<float> row_xor8(Cx<float> v) { return {row_xor8(v.
 // only the eight constants w_16^k1'.  The parity-1 half's shift h3[z] splits
 // into a constant per z2 and a factor per z1 that joins the outer twiddles,
 // so no twiddle beyond those eight per thread is held; that half hands its
-// output to the parity-0 half through LDS.  Block b runs on XCD b mod 8,
-// taking every rhs of one tile before the next tile of its XCD's list.
+// output to the parity-0 half through LDS.  Block b runs on XCD b mod 8 and
+// takes one tile of its XCD's list for every rhs in turn.
 //
 // G: class-grouped slab, as in the n = 64 pass: a tile of 8 columns holds
 // two partner groups (positions 2k, 2k + 1 of a row, whose columns fold onto
@@ -746,15 +748,14 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
     static_assert(PER_XCD % 2 == 0, "whole tile pairs per XCD");
     extern __shared__ unsigned char smem_raw[];
     const int b = blockIdx.x;
-    // consecutive blocks of an XCD take the two tiles of a list pair
-    // (entries 2i, 2i + 1: neighbouring tiles, whose 64-byte row segments
-    // share 128-byte lines) for one rhs, then the next rhs, so each line is
-    // fetched once while both halves are in use
-    const int pos = b >> 3;
-    const int pair = pos / (2 * nrhs), within = pos % (2 * nrhs);
-    const int r = within >> 1;
-    const int tile = tiles[(b & 7) * PER_XCD + 2 * pair + (within & 1)];
-    if ((active && !active[r]) || tile < 0) return;
+    // block b takes tile list entry b / 8 of XCD b mod 8 and every rhs in
+    // turn: the tile's spectrum columns, read again for each rhs within
+    // microseconds by the same block, stay in the XCD's L2, and the twiddles
+    // are loaded once.  Consecutive blocks of an XCD hold neighbouring tiles
+    // (list entries 2i, 2i + 1, whose 64-byte row segments share 128-byte
+    // lines) and walk the rhs in the same order.
+    const int tile = tiles[(b & 7) * PER_XCD + (b >> 3)];
+    if (tile < 0) return;
     const int tid = threadIdx.x;
     const int pz = __builtin_amdgcn_readfirstlane(tid / (TX * R1));
     const int tt = tid % (TX * R1);
@@ -782,8 +783,7 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
         kyi = fold_idx(2 * kyp + py, N, sy);
     }
     const T sxy = (T)(sx * sy);
-    Cx<T>* base = slab + (size_t)r * 3 * N * NCOL;
-    const uint32_t o0 = (uint32_t)j * NCOL + q0 + c;
+    const uint32_t o0_blk = (uint32_t)j * NCOL + q0 + c;
     // w_16^m = exp(-2 pi i m / 16), m < 8: the radix-2 twiddles of the inner
     // step and the z2-dependent part of the parity-1 half shift
     constexpr T C1 = (T)0.92387953251128675613, S1 = (T)0.38268343236508977173;
@@ -794,133 +794,150 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
     // shift h3[j + 16 z2] = w_256^j w_16^z2, giving w_256^(j (2 k2 + 1))
     // (from the h3 table, which holds w_256^q for q < 128, and
     // w_256^(q + 128) = -w_256^q); the factor w_16^z2 is a constant
-    Cx<T> w[R2];
-#pragma unroll
-    for (int m = 0; m < R2; ++m) {
-        if (pz) {
-            const int q = j * (2 * m + 1);
-            const Cx<T> hv = tw.h3[q & (N - 1)];
-            w[m] = (q & N) ? Cx<T>{-hv.re, -hv.im} : hv;
-        } else {
-            w[m] = tw.f3[j * m];
-        }
+    // held for the whole block in an LDS table WT[pz][m][z1] (thread tid
+    // writes entry tid), read where they are applied
+    Cx<T>* WT = reinterpret_cast<Cx<T>*>(smem_raw) + 2 * XS;
+    static_assert(TX * 32 == 2 * R2 * R1, "one table entry per thread");
+    {
+        const int tpz = tid >> 7, tm = (tid >> 4) & (R2 - 1), tj = tid & (R1 - 1);
+        const int q = tpz ? tj * (2 * tm + 1) : tj * tm;
+        const Cx<T> hv = (tpz ? tw.h3 : tw.f3)[q & (N - 1)];
+        WT[tid] = (q & N) ? Cx<T>{-hv.re, -hv.im} : hv;
     }
-    // forward, outer factor: thread (c, z1 = j)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        Cx<T> u[R2];
-#pragma unroll
-        for (int z2 = 0; z2 < R2; ++z2) u[z2] = base[o0 + (uint32_t)(a * N + R1 * z2) * NCOL];
-        if (pz) {
-#pragma unroll
-            for (int z2 = 1; z2 < R2; ++z2) u[z2] = w16[z2] * u[z2];
-        }
-        bfly<T, -1, R2>(u);
-#pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) X[xi(a, k2, j)] = (k2 || pz) ? u[k2] * w[k2] : u[k2];
-    }
+    const Cx<T>* w = WT + pz * R2 * R1 + j;  // w[m * R1]: factor m of thread z1 = j
     const int k2 = j >> 1, e = j & 1;
     const T sgn = e ? (T)-1 : (T)1;
     // spectrum index of inner frequency k = k2 + 8 (k1' + 8 e), kz = 2 k + pz (folded)
-    const uint32_t sp0 = (uint32_t)kyi * D + kxi;
+    const uint32_t sp0_blk = (uint32_t)kyi * D + kxi;
+    uint32_t sp0 = sp0_blk;
     auto spec_at = [&](int k1p) -> uint32_t {
         const int kz = 2 * (k2 + R2 * (k1p + 8 * e)) + pz;
         const int kzf = kz > N ? 2 * N - kz : kz;
         return (uint32_t)(pz * H + (kzf >> 1)) * (D * D) + sp0;
     };
-    // the first frequency's spectrum is loaded before the barrier
-    float4 g0[3];
-    {
-        const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)spec_at(0) * 3;
-        g0[0] = gp[0];
-        g0[1] = gp[1];
-        g0[2] = gp[2];
-    }
-    __syncthreads();
-    {
-        Cx<T> f[3][R2];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-#pragma unroll
-            for (int z1p = 0; z1p < R2; ++z1p) f[a][z1p] = X[xi(a, k2, e + 2 * z1p)];
-            bfly<T, -1, R2>(f[a]);
-            // radix-2 step across the lane pair: lane e contributes G_0 or
-            // w_16^k1' G_1 and keeps F[k1' + 8 e] = contribution of lane 0
-            // +/- that of lane 1
-#pragma unroll
-            for (int k1p = 0; k1p < R2; ++k1p) {
-                if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
-                const Cx<T> mine = (k1p && e) ? w16[k1p] * f[a][k1p] : f[a][k1p];
-                const Cx<T> other = row_xor8(mine);
-                f[a][k1p] = Cx<T>{fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
-            }
-        }
-#pragma unroll
-        for (int k1p = 0; k1p < R2; ++k1p) {
-            // at most two frequencies of spectrum loads in flight (registers)
-            if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
-            const int kz = 2 * (k2 + R2 * (k1p + 8 * e)) + pz;
-            const T sz = kz > N ? (T)-1 : (T)1;
-            const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)spec_at(k1p) * 3;
-            const float4 v0 = k1p ? gp[0] : g0[0], v1 = k1p ? gp[1] : g0[1], v2 = k1p ? gp[2] : g0[2];
-            const Cx<T> gxx = {v0.x, v0.y}, gxy = sxy * Cx<T>{v0.z, v0.w}, gxz = ((T)sx * sz) * Cx<T>{v1.x, v1.y};
-            const Cx<T> gyy = {v1.z, v1.w}, gyz = ((T)sy * sz) * Cx<T>{v2.x, v2.y}, gzz = {v2.z, v2.w};
-            const Cx<T> a0 = f[0][k1p], a1 = f[1][k1p], a2 = f[2][k1p];
-            f[0][k1p] = gxx * a0 + gxy * a1 + gxz * a2;
-            f[1][k1p] = gxy * a0 + gyy * a1 + gyz * a2;
-            f[2][k1p] = gxz * a0 + gyz * a1 + gzz * a2;
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            // inverse radix-2 step: lane e forms Y0 + Y1 (e = 0) or
-            // (Y0 - Y1) conj(w_16^k1') (e = 1) from its value and its partner's
-#pragma unroll
-            for (int k1p = 0; k1p < R2; ++k1p) {
-                if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
-                const Cx<T> mine = f[a][k1p];
-                const Cx<T> other = row_xor8(mine);
-                const Cx<T> s = {fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
-                f[a][k1p] = (k1p && e) ? cmulc(w16[k1p], s) : s;
-            }
-            bfly<T, +1, R2>(f[a]);
-            // each thread rewrites exactly the slots it read above
-#pragma unroll
-            for (int z1p = 0; z1p < R2; ++z1p) X[xi(a, k2, e + 2 * z1p)] = f[a][z1p];
-        }
-    }
-    __syncthreads();
-    // inverse, outer factor: thread (c, z1 = j), the conjugate twiddles; the
-    // parity-1 half finishes its half shift with conj(w_16^z2) and writes its
-    // output into the slots it has just read
-    Cx<T> u[3][R2];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int k2o = 0; k2o < R2; ++k2o) {
-            const Cx<T> v = X[xi(a, k2o, j)];
-            u[a][k2o] = (k2o || pz) ? cmulc(w[k2o], v) : v;
-        }
-        bfly<T, +1, R2>(u[a]);
-        if (pz) {
-#pragma unroll
-            for (int z2 = 0; z2 < R2; ++z2) X[xi(a, z2, j)] = z2 ? cmulc(w16[z2], u[a][z2]) : u[a][z2];
-        }
-    }
-    __syncthreads();
-    if (pz) return;
     const Cx<T>* X1 = reinterpret_cast<const Cx<T>*>(smem_raw) + XS;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int z2 = 0; z2 < R2; ++z2) {
-            Cx<T> v = u[a][z2] + X1[xi(a, z2, j)];
-            if constexpr (G) v = quad_hadamard(v, c);
-            st_stream(base + o0 + (uint32_t)(a * N + R1 * z2) * NCOL, v);
+#pragma unroll 1
+    for (int r = 0; r < nrhs; ++r) {
+        if (active && !active[r]) continue;  // block-uniform
+        Cx<T>* base = slab + (size_t)r * 3 * N * NCOL;
+        // the lane offsets pass through an empty asm statement, so that the
+        // addresses derived from them are formed inside the loop rather than
+        // kept in registers across it
+        uint32_t o0 = o0_blk;
+        sp0 = sp0_blk;
+        asm volatile("" : "+v"(o0), "+v"(sp0));
+        // the twiddle table is written (first rhs), and the parity-1 half
+        // rewrites the exchange buffer the parity-0 half read at the end of the
+        // previous rhs
+        __syncthreads();
+        // forward, outer factor: thread (c, z1 = j)
+    #pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Cx<T> u[R2];
+    #pragma unroll
+            for (int z2 = 0; z2 < R2; ++z2) u[z2] = base[o0 + (uint32_t)(a * N + R1 * z2) * NCOL];
+            if (pz) {
+    #pragma unroll
+                for (int z2 = 1; z2 < R2; ++z2) u[z2] = w16[z2] * u[z2];
+            }
+            bfly<T, -1, R2>(u);
+    #pragma unroll
+            for (int k2o = 0; k2o < R2; ++k2o) X[xi(a, k2o, j)] = (k2o || pz) ? u[k2o] * w[k2o * R1] : u[k2o];
         }
+        // the first frequency's spectrum is loaded before the barrier
+        float4 g0[3];
+        {
+            const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)spec_at(0) * 3;
+            g0[0] = gp[0];
+            g0[1] = gp[1];
+            g0[2] = gp[2];
+        }
+        __syncthreads();
+        {
+            Cx<T> f[3][R2];
+    #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+    #pragma unroll
+                for (int z1p = 0; z1p < R2; ++z1p) f[a][z1p] = X[xi(a, k2, e + 2 * z1p)];
+                bfly<T, -1, R2>(f[a]);
+                // radix-2 step across the lane pair: lane e contributes G_0 or
+                // w_16^k1' G_1 and keeps F[k1' + 8 e] = contribution of lane 0
+                // +/- that of lane 1
+    #pragma unroll
+                for (int k1p = 0; k1p < R2; ++k1p) {
+                    if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
+                    const Cx<T> mine = (k1p && e) ? w16[k1p] * f[a][k1p] : f[a][k1p];
+                    const Cx<T> other = row_xor8(mine);
+                    f[a][k1p] = Cx<T>{fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
+                }
+            }
+    #pragma unroll
+            for (int k1p = 0; k1p < R2; ++k1p) {
+                // at most two frequencies of spectrum loads in flight (registers)
+                if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
+                const int kz = 2 * (k2 + R2 * (k1p + 8 * e)) + pz;
+                const T sz = kz > N ? (T)-1 : (T)1;
+                const float4* gp = reinterpret_cast<const float4*>(gh) + (size_t)spec_at(k1p) * 3;
+                const float4 v0 = k1p ? gp[0] : g0[0], v1 = k1p ? gp[1] : g0[1], v2 = k1p ? gp[2] : g0[2];
+                const Cx<T> gxx = {v0.x, v0.y}, gxy = sxy * Cx<T>{v0.z, v0.w}, gxz = ((T)sx * sz) * Cx<T>{v1.x, v1.y};
+                const Cx<T> gyy = {v1.z, v1.w}, gyz = ((T)sy * sz) * Cx<T>{v2.x, v2.y}, gzz = {v2.z, v2.w};
+                const Cx<T> a0 = f[0][k1p], a1 = f[1][k1p], a2 = f[2][k1p];
+                f[0][k1p] = gxx * a0 + gxy * a1 + gxz * a2;
+                f[1][k1p] = gxy * a0 + gyy * a1 + gyz * a2;
+                f[2][k1p] = gxz * a0 + gyz * a1 + gzz * a2;
+            }
+    #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                // inverse radix-2 step: lane e forms Y0 + Y1 (e = 0) or
+                // (Y0 - Y1) conj(w_16^k1') (e = 1) from its value and its partner's
+    #pragma unroll
+                for (int k1p = 0; k1p < R2; ++k1p) {
+                    if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
+                    const Cx<T> mine = f[a][k1p];
+                    const Cx<T> other = row_xor8(mine);
+                    const Cx<T> s = {fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
+                    f[a][k1p] = (k1p && e) ? cmulc(w16[k1p], s) : s;
+                }
+                bfly<T, +1, R2>(f[a]);
+                // each thread rewrites exactly the slots it read above
+    #pragma unroll
+                for (int z1p = 0; z1p < R2; ++z1p) X[xi(a, k2, e + 2 * z1p)] = f[a][z1p];
+            }
+        }
+        __syncthreads();
+        // inverse, outer factor: thread (c, z1 = j), the conjugate twiddles; the
+        // parity-1 half finishes its half shift with conj(w_16^z2) and writes its
+        // output into the slots it has just read
+        Cx<T> u[3][R2];
+    #pragma unroll
+        for (int a = 0; a < 3; ++a) {
+    #pragma unroll
+            for (int k2o = 0; k2o < R2; ++k2o) {
+                const Cx<T> v = X[xi(a, k2o, j)];
+                u[a][k2o] = (k2o || pz) ? cmulc(w[k2o * R1], v) : v;
+            }
+            bfly<T, +1, R2>(u[a]);
+            if (pz) {
+    #pragma unroll
+                for (int z2 = 0; z2 < R2; ++z2) X[xi(a, z2, j)] = z2 ? cmulc(w16[z2], u[a][z2]) : u[a][z2];
+            }
+        }
+        __syncthreads();
+        if (!pz) {
+    #pragma unroll
+            for (int a = 0; a < 3; ++a)
+    #pragma unroll
+                for (int z2 = 0; z2 < R2; ++z2) {
+                    Cx<T> v = u[a][z2] + X1[xi(a, z2, j)];
+                    if constexpr (G) v = quad_hadamard(v, c);
+                    st_stream(base + o0 + (uint32_t)(a * N + R1 * z2) * NCOL, v);
+                }
+        }
+    }
 }
 
 template <int TX>
-constexpr size_t zpass5_lds() { return (size_t)2 * 3 * 8 * 16 * TX * sizeof(Cx<float>); }
+constexpr size_t zpass5_lds() { return (size_t)(2 * 3 * 8 * 16 * TX + 2 * 8 * 16) * sizeof(Cx<float>); }
 
 // DOT = 1: per-block partial sums of conj(w_j) . y_j (slot 0); DOT = 2:
 // conj(y_j) . x_j (slot 0) and |y_j|^2 (slot 1); DOT = 3: as DOT = 2 with
@@ -1396,11 +1413,11 @@ hipError_t pass_n(int which, int tx, int zrb, int ct, const Geo& g, const Tw<T>&
             const int* tl = (ct & 8) ? g.ztiles8g : g.ztiles8;
             if (tx != 8 || !tl) return hipErrorNotSupported;
             if (ct & 8)
-                hipLaunchKernelGGL((k_zpass5_ct<8, true>), dim3(nrhs * (ntile / 8)), dim3(8 * 32), (zpass5_lds<8>()),
-                                   st, slab, ghat, tw, nrhs, active, tl);
+                hipLaunchKernelGGL((k_zpass5_ct<8, true>), dim3(ntile / 8), dim3(8 * 32), (zpass5_lds<8>()), st, slab,
+                                   ghat, tw, nrhs, active, tl);
             else
-                hipLaunchKernelGGL((k_zpass5_ct<8, false>), dim3(nrhs * (ntile / 8)), dim3(8 * 32), (zpass5_lds<8>()),
-                                   st, slab, ghat, tw, nrhs, active, tl);
+                hipLaunchKernelGGL((k_zpass5_ct<8, false>), dim3(ntile / 8), dim3(8 * 32), (zpass5_lds<8>()), st, slab,
+                                   ghat, tw, nrhs, active, tl);
             return hipGetLastError();
         }
     }
