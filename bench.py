@@ -33,28 +33,45 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA
 METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM peak"
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
-# the counts of a 256 MiB device copy (FETCH x 1.9998, WRITE x 1.0); valid
-# only while the kernel source is the one measured (SHA-256 prefix of the file
-# that holds the kernel).  Keyed by kernel name and rhs count of the launch.
-MEASURED_TRAFFIC = {}
+# HBM bytes per launch from rocprofv3 counter runs of `bench.py
+# --matvec-only --matvec-box 128|64`: reads = 32, 64 and 128 bytes times the
+# L2's memory read requests of each size (TCC_EA0_RDREQ_32B/_64B/_128B),
+# writes = 64 bytes times TCC_EA0_WRREQ_64B plus 32 bytes times the other
+# write requests (median of 6 dispatches).  Valid only while the kernel's
+# sources are the ones measured (SHA-256 prefix of their concatenation).
+# Keyed by kernel name and rhs count of the launch; the summaries with the
+# commands are profiles/matvec_traffic_box128_grid256.md and
+# profiles/matvec_traffic_box64_grid128.md.
+_CT_SOURCES = ("paper_1002_1505_amd/csrc/kernels_ct.hip", "paper_1002_1505_amd/csrc/dda_device.h")
+MEASURED_TRAFFIC = {
+    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "b1ea19d1c4508988",
+                                   "read_bytes": 7906519968, "write_bytes": 8308759968},
+    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "b1ea19d1c4508988",
+                                               "read_bytes": 64460160, "write_bytes": 50331648},
+}
+
+
+def sources_digest(paths):
+    """SHA-256 prefix (16 hex digits) of the concatenated files, paths relative to this file; None if one is missing."""
+    import hashlib
+
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        for p in paths:
+            with open(os.path.join(root, p), "rb") as f:
+                h.update(f.read())
+    except OSError:
+        return None
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, nrhs: int):
-    """HBM bytes per launch of `kernel` if its source is unchanged since the counters were taken, else None."""
-    import hashlib
-
+    """HBM bytes per launch of `kernel` if its sources are unchanged since the counters were taken, else None."""
     m = MEASURED_TRAFFIC.get((kernel, nrhs))
-    if m is None:
+    if m is None or sources_digest(m["sources"]) != m["sha256"]:
         return None
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), m["source"])
-    try:
-        digest = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
-    except OSError:
-        return None
-    if digest != m["sha256"]:
-        return None
-    return round(1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]), 0)
+    return float(m["read_bytes"] + m["write_bytes"])
 
 
 def parse():
@@ -87,6 +104,8 @@ def parse():
                     help="only the headline target's FP32 matvec at 32 rhs (reps launches of each pass), for "
                          "profiler runs; prints the per-pass times and exits")
     ap.add_argument("--reps", type=int, default=5, help="launches per pass in --matvec-only")
+    ap.add_argument("--matvec-box", type=int, choices=[64, 128], default=128,
+                    help="--matvec-only target: the 128^3 sphere at 32 rhs or the 64^3 sphere at 2 rhs")
     return ap.parse_args()
 
 
@@ -134,6 +153,8 @@ def main():
 
     # headline: the 128^3 sphere, 16 orientations x 2 polarizations
     n, x, m = 128, 20.0, 1.33 + 0.01j
+    if a.matvec_only and a.matvec_box == 64:
+        n, x, m = 64, 10.0, 1.5 + 0.1j
     occ = synth.sphere_occupancy(n)
     N = int(occ.sum())
     aeff = (3.0 * N / (4.0 * np.pi)) ** (1.0 / 3.0)
@@ -144,7 +165,7 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     if a.matvec_only:
-        nr = 2 * a.orientations
+        nr = 2 * a.orientations if n == 128 else 2
         ms, by = ctx.profile_matvec(0, nrhs=nr, prec=P.DDA_FP32, reps=a.reps)
         names, sh = pass_names(P, ctx, n)
         print(json.dumps({"matvec_only": True, "nrhs": nr, "reps": a.reps, "kernels": names, "shape": sh,
