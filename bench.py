@@ -89,9 +89,11 @@ def parse():
     ap.add_argument("--c3-orientations", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run three plain 256 MiB device copies (reference kernel for HBM byte counters)")
-    ap.add_argument("--train-targets", type=int, default=16)
+    ap.add_argument("--train-targets", type=int, default=33,
+                    help="training targets; each sweep records (train-orient - 1) x 2 fields (33 x 31 x 2 = 2046)")
     ap.add_argument("--train-orient", type=int, default=32)
-    ap.add_argument("--nn-width", type=int, default=16)
+    ap.add_argument("--nn-width", type=int, default=16, choices=[16, 32, 64],
+                    help="hidden channels (width 64, depth 10: the 940k-parameter network)")
     ap.add_argument("--nn-depth", type=int, default=4)
     ap.add_argument("--history", type=int, default=3, help="solutions kept per slot for the least-squares guess")
     ap.add_argument("--epochs", type=int, default=20)
@@ -531,9 +533,14 @@ def learned_vs_plain(P, ctx, a):
             if i:
                 net.record()
     gen_s = time.perf_counter() - t0
+    print(f"[learned] {net.num_samples} training fields in {gen_s:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    loss0 = net.train(epochs=1, batch=4, lr=1e-3)
-    loss = net.train(epochs=a.epochs - 1, batch=4, lr=1e-3) if a.epochs > 1 else loss0
+    loss0 = loss = None
+    for ep in range(a.epochs):
+        loss = net.train(epochs=1, batch=4, lr=1e-3)
+        loss0 = loss if loss0 is None else loss0
+        print(f"[learned] epoch {ep + 1}/{a.epochs} loss {loss:.4f} ({time.perf_counter() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     net.attach()
@@ -565,6 +572,7 @@ def learned_vs_plain(P, ctx, a):
                     guess_ms[mode] += ctx.last_timing().get("ms_guess", 0.0)
             torch.cuda.synchronize()
             res[mode][1] += time.perf_counter() - t1
+            print(f"[learned] {mode}: {time.perf_counter() - t1:.2f} s", file=sys.stderr, flush=True)
     n_solves = 2 * a.sweep * a.eval_targets
     out = {
         "workload": f"porous aggregates in 64^3 box, {a.train_targets} training targets x {a.train_orient}-orientation "

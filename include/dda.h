@@ -512,7 +512,7 @@ dda_status dda_profile_matvec(dda_ctx* ctx, int32_t target, int32_t nrhs, uint32
 typedef struct dda_nn dda_nn;
 
 typedef struct {
-    int32_t width;      /* hidden channels: 16 or 32 */
+    int32_t width;      /* hidden channels: 16, 32 or 64 (width 64, depth 10: 940k parameters) */
     int32_t depth;      /* number of convolution layers, >= 2 */
     int32_t seed;       /* weight initialisation seed */
     int32_t reserved;

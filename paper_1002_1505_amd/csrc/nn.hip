@@ -56,68 +56,89 @@ __device__ __forceinline__ void offset_of(int o, int& dx, int& dy, int& dz) {
 
 enum { EPI_RELU = 0, EPI_F32 = 1, EPI_MASK = 2 };
 
+// Offsets per weight phase of the convolution: the block's weights
+// [27][NC][KC] are staged in LDS all at once up to NC x KC = 1024 (54 KB), one
+// plane of 9 offsets at a time above (74 KB at 64 x 64), so every block
+// computes all output channels of its voxels and reads its inputs once.
+__host__ __device__ constexpr int conv_ogl(int KC, int NC) { return KC * NC <= 1024 ? 27 : 9; }
+
 // Implicit-GEMM convolution.  X: [ns][V][KC] bf16.  Wb: [27][NC][KC] bf16 (the
 // B operand; for the data gradient the caller passes the weights with the
-// channel roles swapped and FLIP = 1, which negates the offsets).
+// channel roles swapped and FLIP = 1, which negates the offsets).  Block
+// (bx, s): voxels 64 bx .. 64 bx + 63 of sample s, 16 per wave.
 template <int KC, int NC, int FLIP, int EPI>
 __global__ void __launch_bounds__(256) k_conv(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wb,
                                               const float* __restrict__ bias, void* __restrict__ Y,
                                               const uint16_t* __restrict__ mask_act, int D, int dil) {
+    constexpr int NB = NC;
+    constexpr int OGL = conv_ogl(KC, NC);
+    static_assert(NC % 16 == 0 && KC % 16 == 0, "16-channel tiles");
     extern __shared__ unsigned char smem_raw[];
-    uint16_t* wl = reinterpret_cast<uint16_t*>(smem_raw);
+    uint16_t* wl = reinterpret_cast<uint16_t*>(smem_raw);  // [OGL][NC][KC]
     const int V = D * D * D;
     const int s = blockIdx.y;
     const int tid = threadIdx.x;
-    {
-        const uint4* src = reinterpret_cast<const uint4*>(Wb);
-        uint4* dst = reinterpret_cast<uint4*>(wl);
-        for (int i = tid; i < 27 * NC * KC / 8; i += 256) dst[i] = src[i];
-    }
-    __syncthreads();
     const int wave = tid >> 6, lane = tid & 63;
     const int i = lane & 15, kb = (lane >> 4) * 4;
     const int vb = blockIdx.x * 64 + wave * 16;
     const int v = vb + i;
     const int x = v % D, y = (v / D) % D, z = v / (D * D);
     const uint16_t* xs = X + (size_t)s * V * KC;
-    f4 acc[NC / 16];
+    f4 acc[NB / 16];
 #pragma unroll
-    for (int t = 0; t < NC / 16; ++t) acc[t] = f4{0, 0, 0, 0};
-    // the A operands of all 27 offsets are loaded first (independent loads in
-    // flight together), then consumed by the MFMAs
+    for (int t = 0; t < NB / 16; ++t) acc[t] = f4{0, 0, 0, 0};
+    // the A operands of OG offsets at a time are loaded first (independent
+    // loads in flight together), then consumed by the MFMAs: all 27 for up
+    // to 32 input channels, one plane of 9 offsets for 64
     constexpr int KCH = KC / 16;
-    s4 av[27][KCH];
+    constexpr int OG = KC <= 32 ? OGL : 9;
+    static_assert(OGL % OG == 0, "register groups within a weight phase");
+    s4 av[OG][KCH];
 #pragma unroll
-    for (int o = 0; o < 27; ++o) {
-        int dx, dy, dz;
-        offset_of(o, dx, dy, dz);
-        if (FLIP) {
-            dx = -dx;
-            dy = -dy;
-            dz = -dz;
+    for (int p0 = 0; p0 < 27; p0 += OGL) {
+        if (p0) __syncthreads();  // every wave is done with the previous phase
+        {
+            const uint4* src = reinterpret_cast<const uint4*>(Wb + (size_t)p0 * NC * KC);
+            uint4* dst = reinterpret_cast<uint4*>(wl);
+            for (int q = tid; q < OGL * NC * KC / 8; q += 256) dst[q] = src[q];
         }
-        const int xx = x + dil * dx, yy = y + dil * dy, zz = z + dil * dz;
-        const bool ok = (v < V) && xx >= 0 && xx < D && yy >= 0 && yy < D && zz >= 0 && zz < D;
-        const uint16_t* src = xs + ((size_t)(zz * D + yy) * D + xx) * KC;
+        __syncthreads();
 #pragma unroll
-        for (int kq = 0; kq < KCH; ++kq) {
-            av[o][kq] = s4{0, 0, 0, 0};
-            if (ok) av[o][kq] = *reinterpret_cast<const s4*>(src + kq * 16 + kb);
+        for (int o0 = p0; o0 < p0 + OGL; o0 += OG) {
+#pragma unroll
+            for (int oo = 0; oo < OG; ++oo) {
+                int dx, dy, dz;
+                offset_of(o0 + oo, dx, dy, dz);
+                if (FLIP) {
+                    dx = -dx;
+                    dy = -dy;
+                    dz = -dz;
+                }
+                const int xx = x + dil * dx, yy = y + dil * dy, zz = z + dil * dz;
+                const bool ok = (v < V) && xx >= 0 && xx < D && yy >= 0 && yy < D && zz >= 0 && zz < D;
+                const uint16_t* src = xs + ((size_t)(zz * D + yy) * D + xx) * KC;
+#pragma unroll
+                for (int kq = 0; kq < KCH; ++kq) {
+                    av[oo][kq] = s4{0, 0, 0, 0};
+                    if (ok) av[oo][kq] = *reinterpret_cast<const s4*>(src + kq * 16 + kb);
+                }
+            }
+#pragma unroll
+            for (int oo = 0; oo < OG; ++oo)
+#pragma unroll
+                for (int kq = 0; kq < KCH; ++kq)
+#pragma unroll
+                    for (int t = 0; t < NB / 16; ++t) {
+                        const s4 b = *reinterpret_cast<const s4*>(
+                            wl + (((o0 - p0 + oo) * NB) + t * 16 + i) * KC + kq * 16 + kb);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[oo][kq], b, acc[t], 0, 0, 0);
+                    }
         }
     }
-#pragma unroll
-    for (int o = 0; o < 27; ++o)
-#pragma unroll
-        for (int kq = 0; kq < KCH; ++kq)
-#pragma unroll
-            for (int t = 0; t < NC / 16; ++t) {
-                const s4 b = *reinterpret_cast<const s4*>(wl + ((o * NC) + t * 16 + i) * KC + kq * 16 + kb);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[o][kq], b, acc[t], 0, 0, 0);
-            }
     // D fragment: lane holds rows (lane >> 4) * 4 + r, column lane & 15
     const int i4 = (lane >> 4) * 4, j = lane & 15;
 #pragma unroll
-    for (int t = 0; t < NC / 16; ++t) {
+    for (int t = 0; t < NB / 16; ++t) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int vv = vb + i4 + r;
@@ -142,12 +163,20 @@ __global__ void __launch_bounds__(256) k_conv(const uint16_t* __restrict__ X, co
 // block of consecutive x-rows of one sample; partials[blk][27][KC][NC].
 // LDS: the 9 input rows around the output row, transposed to [ci][x + pad],
 // and the output-gradient row transposed to [co][x].
+// Tile groups of the weight gradient: at most 27 accumulator tiles per wave,
+// so the 432 tiles of a 64 x 64 layer take four blocks (blockIdx.z) per row
+// block, each staging the same rows.
+__host__ __device__ constexpr int wgrad_groups(int KC, int NC) { return (27 * (KC / 16) * (NC / 16) + 107) / 108; }
+
 template <int KC, int NC>
 __global__ void __launch_bounds__(256) k_wgrad(const uint16_t* __restrict__ X, const uint16_t* __restrict__ dY,
                                                float* __restrict__ partials, int D, int dil, int rows_per_block) {
     extern __shared__ unsigned char smem_raw[];
     constexpr int NT = 27 * (KC / 16) * (NC / 16);  // 16x16 tiles of dW
-    constexpr int TPW = (NT + 3) / 4;               // tiles per wave
+    constexpr int ZG = wgrad_groups(KC, NC);
+    constexpr int TPB = (NT + ZG - 1) / ZG;         // tiles per block
+    constexpr int TPW = (TPB + 3) / 4;              // tiles per wave
+    const int tile0 = blockIdx.z * TPB;
     const int pad = dil;
     const int XW = D + 2 * pad;
     uint16_t* xt = reinterpret_cast<uint16_t*>(smem_raw);  // [9][KC][XW]
@@ -165,24 +194,38 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t* __restrict__ X, c
         if (row >= D * D) break;
         const int y = row % D, z = row / D;
         __syncthreads();
-        // input rows (z + dil dz, y + dil dy), padded in x
-        for (int idx = tid; idx < 9 * KC * XW; idx += 256) {
-            const int xw = idx % XW, ci = (idx / XW) % KC, r9 = idx / (XW * KC);
+        // input rows (z + dil dz, y + dil dy), padded in x: 8 channels of a
+        // voxel per 16-byte load, transposed into [r9][ci][xw]
+        for (int idx = tid; idx < 9 * XW * (KC / 8); idx += 256) {
+            const int c8 = idx % (KC / 8), xw = (idx / (KC / 8)) % XW, r9 = idx / ((KC / 8) * XW);
             const int yy = y + dil * (r9 % 3 - 1), zz = z + dil * (r9 / 3 - 1), xx = xw - pad;
-            uint16_t val = 0;
+            uint4 val = {0, 0, 0, 0};
             if (xx >= 0 && xx < D && yy >= 0 && yy < D && zz >= 0 && zz < D)
-                val = X[((size_t)s * V + (size_t)(zz * D + yy) * D + xx) * KC + ci];
-            xt[idx] = val;
+                val = *reinterpret_cast<const uint4*>(X + ((size_t)s * V + (size_t)(zz * D + yy) * D + xx) * KC + c8 * 8);
+            const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+            uint16_t* d = xt + ((size_t)r9 * KC + c8 * 8) * XW + xw;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                d[(2 * q) * XW] = (uint16_t)(w4[q] & 0xffff);
+                d[(2 * q + 1) * XW] = (uint16_t)(w4[q] >> 16);
+            }
         }
-        for (int idx = tid; idx < NC * D; idx += 256) {
-            const int xx = idx % D, co = idx / D;
-            gt[idx] = dY[((size_t)s * V + (size_t)row * D + xx) * NC + co];
+        for (int idx = tid; idx < D * (NC / 8); idx += 256) {
+            const int c8 = idx % (NC / 8), xx = idx / (NC / 8);
+            const uint4 val = *reinterpret_cast<const uint4*>(dY + ((size_t)s * V + (size_t)row * D + xx) * NC + c8 * 8);
+            const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+            uint16_t* d = gt + (size_t)(c8 * 8) * D + xx;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                d[(2 * q) * D] = (uint16_t)(w4[q] & 0xffff);
+                d[(2 * q + 1) * D] = (uint16_t)(w4[q] >> 16);
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
-            const int tile = wave * TPW + t;
-            if (tile >= NT) break;
+            const int tl = wave * TPW + t, tile = tile0 + tl;
+            if (tl >= TPB || tile >= NT) break;
             const int o = tile / ((KC / 16) * (NC / 16));
             const int cit = (tile / (NC / 16)) % (KC / 16), cot = tile % (NC / 16);
             int dx, dy, dz;
@@ -204,14 +247,14 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t* __restrict__ X, c
             }
         }
     }
-    // write this block's partial: D[i = ci][j = co]
+    // write this block's tiles of its row block's partial: D[i = ci][j = co]
     const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
     float* out = partials + blk * 27 * KC * NC;
     const int i4 = (lane >> 4) * 4, j = lane & 15;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-        const int tile = wave * TPW + t;
-        if (tile >= NT) break;
+        const int tl = wave * TPW + t, tile = tile0 + tl;
+        if (tl >= TPB || tile >= NT) break;
         const int o = tile / ((KC / 16) * (NC / 16));
         const int cit = (tile / (NC / 16)) % (KC / 16), cot = tile % (NC / 16);
 #pragma unroll
@@ -224,6 +267,8 @@ __global__ void __launch_bounds__(256) k_wgrad(const uint16_t* __restrict__ X, c
 // adds its sum atomically (the order of the chunk sums is not fixed).
 // x-rows per weight-gradient block (enough blocks to fill the chip)
 constexpr int WG_ROWS = 8;
+// wide layers take more rows per block: fewer, larger partials to reduce
+__host__ __device__ constexpr int wgrad_rows(int KC, int NC) { return KC * NC >= 2048 ? 32 : WG_ROWS; }
 constexpr int RCH = 32;
 __global__ void k_reduce_partials(const float* __restrict__ partials, int nblk, int n, float* __restrict__ g) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -481,7 +526,7 @@ struct Sample {
     } while (0)
 
 template <int KC, int NC>
-size_t conv_lds() { return (size_t)27 * NC * KC * 2; }
+size_t conv_lds() { return (size_t)conv_ogl(KC, NC) * NC * KC * 2; }
 
 template <int KC, int NC, int FLIP, int EPI>
 hipError_t conv_launch(const uint16_t* X, const uint16_t* W, const float* b, void* Y, const uint16_t* mask, int D, int dil,
@@ -493,8 +538,8 @@ hipError_t conv_launch(const uint16_t* X, const uint16_t* W, const float* b, voi
                            160 * 1024));
         attr = true;
     }
-    hipLaunchKernelGGL((k_conv<KC, NC, FLIP, EPI>), dim3((V + 63) / 64, ns), dim3(256), (conv_lds<KC, NC>()), st, X, W, b,
-                       Y, mask, D, dil);
+    hipLaunchKernelGGL((k_conv<KC, NC, FLIP, EPI>), dim3((V + 63) / 64, ns), dim3(256), (conv_lds<KC, NC>()), st, X,
+                       W, b, Y, mask, D, dil);
     return hipGetLastError();
 }
 
@@ -508,7 +553,9 @@ hipError_t wgrad_launch(const uint16_t* X, const uint16_t* dY, float* partials, 
     }
     const int nbx = (D * D + rows_per_block - 1) / rows_per_block;
     const size_t lds = ((size_t)9 * KC * (D + 2 * dil) + (size_t)NC * D) * 2;
-    hipLaunchKernelGGL((k_wgrad<KC, NC>), dim3(nbx, ns), dim3(256), lds, st, X, dY, partials, D, dil, rows_per_block);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;  // rows of a box too wide for LDS
+    hipLaunchKernelGGL((k_wgrad<KC, NC>), dim3(nbx, ns, wgrad_groups(KC, NC)), dim3(256), lds, st, X, dY, partials, D,
+                       dil, rows_per_block);
     NCHK(hipGetLastError());
     const int n = 27 * KC * NC;
     hipLaunchKernelGGL(k_reduce_partials, dim3((n + 255) / 256, (nbx * ns + RCH - 1) / RCH), dim3(256), 0, st,
@@ -562,7 +609,12 @@ hipError_t nn_buffers(dda_nn* nn, int D, int ns) {
     const int wmax = std::max(nn->width, 16);
     NCHK(nn->dA.ensure(V * ns * wmax * 2));
     NCHK(nn->dB.ensure(V * ns * wmax * 2));
-    NCHK(nn->partials.ensure((size_t)ns * ((D * D + WG_ROWS - 1) / WG_ROWS) * 27 * wmax * wmax * 4));
+    size_t part = 0;
+    for (const Layer& L : nn->layers) {
+        const int rpb = wgrad_rows(L.cin, L.cout);
+        part = std::max(part, (size_t)ns * ((D * D + rpb - 1) / rpb) * 27 * L.cin * L.cout * 4);
+    }
+    NCHK(nn->partials.ensure(part));
     NCHK(nn->lossacc.ensure(ns * sizeof(double)));
     NCHK(nn->sdev.ensure(ns * sizeof(SampleDev)));
     nn->D = D;
@@ -598,13 +650,13 @@ hipError_t nn_backward(dda_nn* nn, int ns, hipStream_t st) {
     uint16_t* gcur = nn->dA.as<uint16_t>();
     uint16_t* gnext = nn->dB.as<uint16_t>();
     const int D = nn->D;
-    const int rpb = WG_ROWS;
     for (int l = (int)nn->layers.size() - 1; l >= 0; --l) {
         const Layer& L = nn->layers[l];
         const uint16_t* X = nn->act[l].as<uint16_t>();
         float* gw = nn->g.as<float>() + L.woff;
         float* gb = nn->g.as<float>() + L.boff;
         // weight and bias gradients
+        const int rpb = wgrad_rows(L.cin, L.cout);
         if (L.cin == 16 && L.cout == W) NCHK((wgrad_launch<16, W>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
         else if (L.cin == W && L.cout == W) NCHK((wgrad_launch<W, W>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
         else if (L.cin == W && L.cout == 16) NCHK((wgrad_launch<W, 16>(X, gcur, nn->partials.as<float>(), gw, D, L.dil, ns, rpb, st)));
@@ -628,10 +680,12 @@ hipError_t nn_backward(dda_nn* nn, int ns, hipStream_t st) {
 }
 
 hipError_t nn_forward_any(dda_nn* nn, int ns, hipStream_t st) {
+    if (nn->width == 64) return nn_forward<64>(nn, ns, st);
     if (nn->width == 32) return nn_forward<32>(nn, ns, st);
     return nn_forward<16>(nn, ns, st);
 }
 hipError_t nn_backward_any(dda_nn* nn, int ns, hipStream_t st) {
+    if (nn->width == 64) return nn_backward<64>(nn, ns, st);
     if (nn->width == 32) return nn_backward<32>(nn, ns, st);
     return nn_backward<16>(nn, ns, st);
 }
@@ -848,7 +902,7 @@ extern "C" {
 dda_status dda_nn_create(dda_ctx* ctx, const dda_nn_config* cfg, dda_nn** out) {
     (void)ctx;
     if (!cfg || !out) return DDA_ERR_INVALID_ARG;
-    if (!(cfg->width == 16 || cfg->width == 32) || cfg->depth < 2 || cfg->depth > 16)
+    if (!(cfg->width == 16 || cfg->width == 32 || cfg->width == 64) || cfg->depth < 2 || cfg->depth > 16)
         return DDA_ERR_INVALID_ARG;
     std::unique_ptr<dda_nn> nn(new dda_nn());
     nn->width = cfg->width;
@@ -1020,7 +1074,9 @@ dda_status dda_nn_train(dda_ctx* ctx, dda_nn* nn, const dda_nn_train_opts* o, do
     if (D == 0) return DDA_ERR_STATE;
     hipStream_t st = nullptr;
     if (nn_buffers(nn, D, B) != hipSuccess) return DDA_ERR_OOM;
-    std::mt19937 rng(nn->seed + 7);
+    // the sample order continues across calls (a call per epoch shuffles as
+    // one call over all epochs does not, but each call sees a fresh order)
+    std::mt19937 rng((uint32_t)(nn->seed + 7 + nn->adam_t));
     std::vector<int> order(ns_total);
     for (int i = 0; i < ns_total; ++i) order[i] = i;
     double last = 0;

@@ -23,8 +23,10 @@ def bf16(a):
     return u.astype(np.uint32).view(np.float32)
 
 
-@pytest.mark.parametrize("width,depth", [(16, 3), (32, 4)])
+@pytest.mark.parametrize("width,depth", [(16, 3), (32, 4), (64, 3)])
 def test_forward_and_gradients_match_oracle(width, depth):
+    """Width 64 runs the channel-split convolution (four 16-channel output
+    slices per voxel block) and the weight gradient in four tile groups."""
     import paper_1002_1505_amd as P
 
     ctx = P.Context(0)
@@ -161,6 +163,29 @@ def test_profile_hook_counts_flops_and_times():
     with pytest.raises(P.DDAError):
         net.profile(24, 2, 1)  # box side not a multiple of 16
     net.close()
+    ctx.close()
+
+
+def test_million_parameter_network_builds_and_runs():
+    """The learned-guess network at its full size: width 64, depth 10 holds
+    27 (16 x 64 + 8 x 64 x 64 + 64 x 16) weights and 9 x 64 + 16 biases
+    (940,624 parameters); its forward and backward passes run on a 64^3 box.
+    Widths other than 16, 32 and 64 are refused."""
+    import paper_1002_1505_amd as P
+    from paper_1002_1505_amd import _lib as L
+
+    ctx = P.Context(0)
+    net = P.Net(ctx, width=64, depth=10, seed=4)
+    assert net.num_params == 27 * (16 * 64 + 8 * 64 * 64 + 64 * 16) + 9 * 64 + 16
+    assert [l[:2] for l in net.layers()] == [(16, 64)] + [(64, 64)] * 8 + [(64, 16)]
+    f_ms, b_ms, gflop = net.profile(64, 2, 1)
+    print(f"[width 64 depth 10] forward {f_ms:.3f} ms backward {b_ms:.3f} ms for 2 samples of 64^3, "
+          f"{gflop / f_ms:.1f} TFLOP/s forward", flush=True)
+    assert f_ms > 0 and b_ms > 0
+    net.close()
+    with pytest.raises(P.DDAError) as e:
+        P.Net(ctx, width=48, depth=4, seed=1)
+    assert e.value.status == L.DDA_ERR_INVALID_ARG
     ctx.close()
 
 
