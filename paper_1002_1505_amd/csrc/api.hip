@@ -1062,14 +1062,17 @@ dda_status project_history(dda_ctx* c, Group& g, Target& t) {
     Cx<float>* W = g.pw32.as<Cx<float>>();
     HCHK(c, g.esh.ensure(ve * sizeof(Cx<float>)));
     HCHK(c, g.rf.ensure(ve * sizeof(Cx<float>)));
+    HistSrc src{};
+    src.h = h;
     for (int e = 0; e < h; ++e) {
-        const Cx<double>* px = from_last ? g.x64.as<Cx<double>>() : g.hx[e].as<Cx<double>>();
-        const Cx<double>* pa = from_last ? g.ainvprev.as<Cx<double>>() : g.hainvv[e].as<Cx<double>>();
-        const WaveDev* pw = from_last ? g.wprev.as<WaveDev>() : g.hwv[e].as<WaveDev>();
-        HCHK(c, launch_prev_shift(t.geo(), t.origin, nr, px, pa, g.ainv64.as<Cx<double>>(), pw, g.waves.as<WaveDev>(),
-                                  nullptr, nullptr, V + e * ve, st));
-        HCHK(c, matvec_group<float>(t, g, nr, V + e * ve, W + e * ve, nullptr, nullptr, MV_AX, st));
+        src.P[e] = from_last ? g.x64.as<Cx<double>>() : g.hx[e].as<Cx<double>>();
+        src.ainv[e] = from_last ? g.ainvprev.as<Cx<double>>() : g.hainvv[e].as<Cx<double>>();
+        src.w[e] = from_last ? g.wprev.as<WaveDev>() : g.hwv[e].as<WaveDev>();
     }
+    HCHK(c, launch_prev_shift_hist(t.geo(), t.origin, nr, src, g.ainv64.as<Cx<double>>(), g.waves.as<WaveDev>(), V, ve,
+                                   st));
+    for (int e = 0; e < h; ++e)
+        HCHK(c, matvec_group<float>(t, g, nr, V + e * ve, W + e * ve, nullptr, nullptr, MV_AX, st));
     // coefficients, combination, residual field and its norm on the device:
     // the guess takes no host round trip
     HCHK(c, launch_gram(t.Npad, nr, h, W, g.b64.as<Cx<double>>(), g.gpart.as<double>(), st));

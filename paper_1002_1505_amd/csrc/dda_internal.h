@@ -290,6 +290,18 @@ hipError_t launch_prev_shift(const Geo& g, const double* origin, int nrhs, const
 // triangle of the 4 x 4 matrix) then <W_e, b>; W, V are [h][nrhs][3][Npad].
 constexpr int HIST_MAX = 4;
 constexpr int HIST_NGRAM = HIST_MAX * (HIST_MAX + 1) / 2 + HIST_MAX;
+// the h stored solutions of a group, their 1/alpha tables and waves
+struct HistSrc {
+    const Cx<double>* P[HIST_MAX];
+    const Cx<double>* ainv[HIST_MAX];
+    const WaveDev* w[HIST_MAX];
+    int h;
+};
+// v32 + e ve = entry e carried to the new direction (as launch_prev_shift's
+// v32), all h entries in one launch
+hipError_t launch_prev_shift_hist(const Geo& g, const double* origin, int nrhs, const HistSrc& src,
+                                  const Cx<double>* ainv_new, const WaveDev* wnew, Cx<float>* v32, size_t ve,
+                                  hipStream_t st);
 int gram_blocks(int Npad);
 hipError_t launch_gram(int Npad, int nrhs, int h, const Cx<float>* W, const Cx<double>* b, double* partials,
                        hipStream_t st);

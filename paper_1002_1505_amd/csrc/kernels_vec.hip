@@ -990,12 +990,11 @@ __global__ void k_ampl_reduce(const double* __restrict__ partials, int nchunk, i
 // written (each output optional) as the field esh (FP32), as the guess
 // P0_j = esh_j / (1/alpha_new) in FP64 (p0) or in FP32 (v32).  p0 may alias
 // Pprev: every element is read and written by the same thread.
-__global__ void k_prev_shift(Geo g, double ox, double oy, double oz, const Cx<double>* Pprev,
-                             const Cx<double>* __restrict__ ainv_prev, const Cx<double>* __restrict__ ainv_new,
-                             const WaveDev* __restrict__ wprev, const WaveDev* __restrict__ wnew,
-                             Cx<float>* __restrict__ esh, Cx<double>* p0, Cx<float>* __restrict__ v32) {
-    const int rhs = blockIdx.y;
-    const WaveDev a = wprev[rhs], b = wnew[rhs];
+__device__ __forceinline__ void prev_shift_body(const Geo& g, double ox, double oy, double oz, int rhs,
+                                                const Cx<double>* Pprev, const Cx<double>* __restrict__ ainv_prev,
+                                                const Cx<double>* __restrict__ ainv_new, const WaveDev& a,
+                                                const WaveDev& b, Cx<float>* __restrict__ esh, Cx<double>* p0,
+                                                Cx<float>* __restrict__ v32) {
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < g.Npad; j += gridDim.x * blockDim.x) {
         Cx<double> ph = {0, 0};
         Cx<double> ap = {0, 0}, an = {1, 0};
@@ -1021,6 +1020,24 @@ __global__ void k_prev_shift(Geo g, double ox, double oy, double oz, const Cx<do
     }
 }
 
+__global__ void k_prev_shift(Geo g, double ox, double oy, double oz, const Cx<double>* Pprev,
+                             const Cx<double>* __restrict__ ainv_prev, const Cx<double>* __restrict__ ainv_new,
+                             const WaveDev* __restrict__ wprev, const WaveDev* __restrict__ wnew,
+                             Cx<float>* __restrict__ esh, Cx<double>* p0, Cx<float>* __restrict__ v32) {
+    const int rhs = blockIdx.y;
+    prev_shift_body(g, ox, oy, oz, rhs, Pprev, ainv_prev, ainv_new, wprev[rhs], wnew[rhs], esh, p0, v32);
+}
+
+// The history entries of the least-squares guess in one launch: entry e =
+// blockIdx.z carried to the new direction into v32 + e ve (FP32).
+__global__ void k_prev_shift_hist(Geo g, double ox, double oy, double oz, HistSrc src,
+                                  const Cx<double>* __restrict__ ainv_new, const WaveDev* __restrict__ wnew,
+                                  Cx<float>* __restrict__ v32, size_t ve) {
+    const int rhs = blockIdx.y, e = blockIdx.z;
+    prev_shift_body(g, ox, oy, oz, rhs, src.P[e], src.ainv[e], ainv_new, src.w[e][rhs], wnew[rhs], nullptr, nullptr,
+                    v32 + e * ve);
+}
+
 // Normal equations of min || b - sum_e c_e W_e || per rhs over h <= 4 basis
 // vectors: partial sums of <W_e, W_f> (e <= f) and <W_e, b> per block,
 // written to partials[rhs][blockIdx.x][14] complex.  W is [h][nrhs][V].
@@ -1033,9 +1050,7 @@ __global__ void __launch_bounds__(VT) k_gram_part(int V, int nrhs, int h, const 
 #pragma unroll
     for (int q = 0; q < NGRAM; ++q) acc[q] = double2{0, 0};
     const size_t es = (size_t)nrhs * V, o = (size_t)rhs * V;
-    for (int k = 0; k < VPT; ++k) {
-        const int i = blockIdx.x * VB + k * VT + threadIdx.x;
-        if (i >= V) continue;
+    for (int i = blockIdx.x * VT + threadIdx.x; i < V; i += gridDim.x * VT) {
         Cx<float> w[MAXH];
 #pragma unroll
         for (int e = 0; e < MAXH; ++e) w[e] = e < h ? W[e * es + o + i] : Cx<float>{0, 0};
@@ -1048,15 +1063,19 @@ __global__ void __launch_bounds__(VT) k_gram_part(int V, int nrhs, int h, const 
             acc_dot(acc[MAXH * (MAXH + 1) / 2 + e], Cx<double>{w[e].re, w[e].im}, bi);
         }
     }
-    __shared__ double sh[16];
+    // all 2 NGRAM sums with one barrier
+    __shared__ double sh[2 * NGRAM * (VT / 64)];
+    double v[2 * NGRAM];
+#pragma unroll
     for (int q = 0; q < NGRAM; ++q) {
-        const double re = block_sum(acc[q].x, sh);
-        const double im = block_sum(acc[q].y, sh);
-        if (threadIdx.x == 0) {
-            double* out = partials + (((size_t)rhs * gridDim.x + blockIdx.x) * NGRAM + q) * 2;
-            out[0] = re;
-            out[1] = im;
-        }
+        v[2 * q] = acc[q].x;
+        v[2 * q + 1] = acc[q].y;
+    }
+    block_sum_n<2 * NGRAM>(v, sh);
+    if (threadIdx.x == 0) {
+        double* out = partials + ((size_t)rhs * gridDim.x + blockIdx.x) * NGRAM * 2;
+#pragma unroll
+        for (int q = 0; q < 2 * NGRAM; ++q) out[q] = v[q];
     }
 }
 
@@ -1112,13 +1131,26 @@ hipError_t launch_prev_shift(const Geo& g, const double* origin, int nrhs, const
     return hipGetLastError();
 }
 
-int gram_blocks(int Npad) { return (3 * Npad + VB - 1) / VB; }
+hipError_t launch_prev_shift_hist(const Geo& g, const double* origin, int nrhs, const HistSrc& src,
+                                  const Cx<double>* ainv_new, const WaveDev* wnew, Cx<float>* v32, size_t ve,
+                                  hipStream_t st) {
+    if (src.h < 1 || src.h > HIST_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_prev_shift_hist, dim3((g.Npad + 255) / 256, nrhs, src.h), dim3(256), 0, st, g, origin[0],
+                       origin[1], origin[2], src, ainv_new, wnew, v32, ve);
+    return hipGetLastError();
+}
+
+// blocks of the Gram partial sums per rhs: enough to stream the vectors,
+// few enough that the coefficient kernel's reduction over them is short
+int gram_blocks(int Npad) { return std::min(256, (3 * Npad + VT - 1) / VT); }
 
 // Least-squares coefficients of the history guess on the device: sum the
 // Gram partials of one rhs over the blocks (one wave, fixed order), then solve
-// the h x h Hermitian normal equations G c = <W_e, b> by Gaussian elimination
-// with partial pivoting in FP64, the diagonal raised by 1e-12 of its largest
-// entry.  coef: [rhs][HIST_MAX] complex.
+// the h x h Hermitian normal equations G c = <W_e, b> in FP64 by a Cholesky
+// factorisation G = L L^H, the diagonal raised by 1e-12 of its largest entry
+// (positive definite).  Every loop runs to HIST_MAX with the indices known at
+// compile time, so the matrices stay in registers.  coef: [rhs][HIST_MAX]
+// complex.
 __global__ void __launch_bounds__(64) k_proj_coef(int nblk, int h, const double* __restrict__ partials,
                                                   Cx<double>* __restrict__ coef) {
     const int rhs = blockIdx.x;
@@ -1133,56 +1165,75 @@ __global__ void __launch_bounds__(64) k_proj_coef(int nblk, int h, const double*
 #pragma unroll
     for (int q = 0; q < 2 * NGRAM; ++q) acc[q] = wave_total(acc[q]);
     if (threadIdx.x != 0) return;
-    double2 A[MAXH][MAXH + 1];
-    int q = 0;
+    // G[e][f] = <W_e, W_f> for e <= f (row-major upper triangle), rhs <W_e, b>
+    double2 G[MAXH][MAXH], r[MAXH];
     double dmax = 0;
-    for (int e = 0; e < MAXH; ++e)
-        for (int f = e; f < MAXH; ++f) {
-            const double2 v = make_double2(acc[2 * q], acc[2 * q + 1]);
-            ++q;
-            if (e < h && f < h) {
-                A[e][f] = v;
-                A[f][e] = make_double2(v.x, -v.y);
-                if (e == f) dmax = fmax(dmax, sqrt(v.x * v.x + v.y * v.y));
+    {
+        int q = 0;
+#pragma unroll
+        for (int e = 0; e < MAXH; ++e)
+#pragma unroll
+            for (int f = e; f < MAXH; ++f) {
+                G[e][f] = make_double2(acc[2 * q], acc[2 * q + 1]);
+                ++q;
+                if (e == f && e < h) dmax = fmax(dmax, fabs(G[e][e].x));
             }
-        }
-    for (int e = 0; e < h; ++e) {
-        A[e][e].x += 1e-12 * dmax + 1e-300;
-        A[e][h] = make_double2(acc[2 * (q + e)], acc[2 * (q + e) + 1]);
+#pragma unroll
+        for (int e = 0; e < MAXH; ++e) r[e] = make_double2(acc[2 * (q + e)], acc[2 * (q + e) + 1]);
     }
-    for (int k = 0; k < h; ++k) {
-        int piv = k;
-        double best = A[k][k].x * A[k][k].x + A[k][k].y * A[k][k].y;
-        for (int i = k + 1; i < h; ++i) {
-            const double m2 = A[i][k].x * A[i][k].x + A[i][k].y * A[i][k].y;
-            if (m2 > best) {
-                best = m2;
-                piv = i;
+    // L (lower, real diagonal): L[i][j] for j <= i
+    double2 L[MAXH][MAXH];
+    double dg[MAXH];
+#pragma unroll
+    for (int j = 0; j < MAXH; ++j) {
+        if (j >= h) break;
+        double d = G[j][j].x + 1e-12 * dmax + 1e-300;
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= L[j][k].x * L[j][k].x + L[j][k].y * L[j][k].y;
+        dg[j] = sqrt(fmax(d, 1e-300));
+        const double inv = 1.0 / dg[j];
+#pragma unroll
+        for (int i = j + 1; i < MAXH; ++i) {
+            if (i >= h) break;
+            // G[i][j] = conj(G[j][i]); subtract sum_k L[i][k] conj(L[j][k])
+            double2 v = make_double2(G[j][i].x, -G[j][i].y);
+#pragma unroll
+            for (int k = 0; k < j; ++k) {
+                const double2 a = L[i][k], c = L[j][k];
+                v.x -= a.x * c.x + a.y * c.y;
+                v.y -= a.y * c.x - a.x * c.y;
             }
-        }
-        if (piv != k)
-            for (int j = 0; j <= h; ++j) {
-                const double2 tmp = A[k][j];
-                A[k][j] = A[piv][j];
-                A[piv][j] = tmp;
-            }
-        for (int i = k + 1; i < h; ++i) {
-            const double2 f = cdiv(A[i][k], A[k][k]);
-            for (int j = k; j <= h; ++j) {
-                const double2 fa = cmul2(f, A[k][j]);
-                A[i][j] = make_double2(A[i][j].x - fa.x, A[i][j].y - fa.y);
-            }
+            L[i][j] = make_double2(v.x * inv, v.y * inv);
         }
     }
-    double2 out[MAXH];
-    for (int k = h - 1; k >= 0; --k) {
-        double2 v = A[k][h];
-        for (int j = k + 1; j < h; ++j) {
-            const double2 aj = cmul2(A[k][j], out[j]);
-            v = make_double2(v.x - aj.x, v.y - aj.y);
+    // L y = r, then L^H c = y
+    double2 y[MAXH], out[MAXH];
+#pragma unroll
+    for (int i = 0; i < MAXH; ++i) {
+        if (i >= h) break;
+        double2 v = r[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+            const double2 a = cmul2(L[i][k], y[k]);
+            v = make_double2(v.x - a.x, v.y - a.y);
         }
-        out[k] = cdiv(v, A[k][k]);
+        y[i] = make_double2(v.x / dg[i], v.y / dg[i]);
     }
+#pragma unroll
+    for (int i = MAXH - 1; i >= 0; --i) {
+        if (i >= h) continue;
+        double2 v = y[i];
+#pragma unroll
+        for (int k = i + 1; k < MAXH; ++k) {
+            if (k >= h) break;
+            // conj(L[k][i]) * out[k]
+            const double2 a = L[k][i], o = out[k];
+            v.x -= a.x * o.x + a.y * o.y;
+            v.y -= a.x * o.y - a.y * o.x;
+        }
+        out[i] = make_double2(v.x / dg[i], v.y / dg[i]);
+    }
+#pragma unroll
     for (int e = 0; e < MAXH; ++e)
         coef[(size_t)rhs * MAXH + e] = e < h ? Cx<double>{out[e].x, out[e].y} : Cx<double>{0, 0};
 }

@@ -37,6 +37,8 @@
 
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 namespace nnk {
 
@@ -66,73 +68,128 @@ __host__ __device__ constexpr int conv_ogl(int KC, int NC) { return KC * NC <= 1
 // B operand; for the data gradient the caller passes the weights with the
 // channel roles swapped and FLIP = 1, which negates the offsets).  Block
 // (bx, s): voxels 64 bx .. 64 bx + 63 of sample s, 16 per wave.
+//
+// Each v_mfma_f32_16x16x32_bf16 reduces over 32 (tap, input channel) pairs:
+// lane group g = lane / 16 supplies 8 of them from one 16-byte load, for A
+// (voxel lane % 16) and B (output channel lane % 16) alike, so A and B agree
+// slot by slot whatever the instruction's internal order of its 32 products.
+// With 16 input channels one instruction takes two taps (groups 0, 1 the
+// first, 2, 3 the second; the 28th tap is empty); with 32 or 64 it takes 32
+// channels of one tap.
 template <int KC, int NC, int FLIP, int EPI>
 __global__ void __launch_bounds__(256) k_conv(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wb,
                                               const float* __restrict__ bias, void* __restrict__ Y,
                                               const uint16_t* __restrict__ mask_act, int D, int dil) {
     constexpr int NB = NC;
     constexpr int OGL = conv_ogl(KC, NC);
-    static_assert(NC % 16 == 0 && KC % 16 == 0, "16-channel tiles");
+    constexpr int CPR = KC / 8;  // 16-byte chunks per weight row
+    static_assert(NC % 16 == 0 && (KC == 16 || KC % 32 == 0), "channel tiles");
     extern __shared__ unsigned char smem_raw[];
     uint16_t* wl = reinterpret_cast<uint16_t*>(smem_raw);  // [OGL][NC][KC]
     const int V = D * D * D;
     const int s = blockIdx.y;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int i = lane & 15, kb = (lane >> 4) * 4;
+    const int i = lane & 15, g = lane >> 4;
     const int vb = blockIdx.x * 64 + wave * 16;
     const int v = vb + i;
     const int x = v % D, y = (v / D) % D, z = v / (D * D);
     const uint16_t* xs = X + (size_t)s * V * KC;
+    // per-axis validity of the taps at -dil, 0, +dil, and the lane's element
+    // index (voxel, first channel of its 8): a tap costs one add and selects
+    const bool vin = v < V;
+    const bool okx[3] = {x >= dil, true, x + dil < D};
+    const bool oky[3] = {y >= dil, true, y + dil < D};
+    const bool okz[3] = {z >= dil, true, z + dil < D};
+    const uint32_t ebase = (uint32_t)v * KC + (KC == 16 ? (g & 1) * 8 : g * 8);
+    const uint32_t esafe = vin ? ebase : (uint32_t)(g & 1) * 8;
+    // tap o of this lane: element index of its 8 channels, and validity
+    auto tap = [&](int o, bool& ok) -> uint32_t {
+        int dx, dy, dz;
+        offset_of(o, dx, dy, dz);
+        if (FLIP) {
+            dx = -dx;
+            dy = -dy;
+            dz = -dz;
+        }
+        ok = vin && okx[dx + 1] && oky[dy + 1] && okz[dz + 1];
+        return ok ? ebase + (uint32_t)(((dz * D + dy) * D + dx) * dil * KC) : esafe;
+    };
+    // weight row r of the current phase, 16-byte chunk c (swizzled as stored)
+    auto wrow = [&](int r, int c) -> bf8 {
+        const u4v w = *reinterpret_cast<const u4v*>(wl + r * KC + ((c ^ (r & (CPR - 1))) << 3));
+        return __builtin_bit_cast(bf8, w);
+    };
     f4 acc[NB / 16];
 #pragma unroll
     for (int t = 0; t < NB / 16; ++t) acc[t] = f4{0, 0, 0, 0};
-    // the A operands of OG offsets at a time are loaded first (independent
-    // loads in flight together), then consumed by the MFMAs: all 27 for up
-    // to 32 input channels, one plane of 9 offsets for 64
-    constexpr int KCH = KC / 16;
-    constexpr int OG = KC <= 32 ? OGL : 9;
-    static_assert(OGL % OG == 0, "register groups within a weight phase");
-    s4 av[OG][KCH];
+    const u4v zero = {0, 0, 0, 0};
 #pragma unroll
     for (int p0 = 0; p0 < 27; p0 += OGL) {
         if (p0) __syncthreads();  // every wave is done with the previous phase
         {
+            // 16-byte chunk c of weight row r goes to chunk c ^ (r mod CPR):
+            // the 16 rows a wave reads together then spread over the banks
             const uint4* src = reinterpret_cast<const uint4*>(Wb + (size_t)p0 * NC * KC);
             uint4* dst = reinterpret_cast<uint4*>(wl);
-            for (int q = tid; q < OGL * NC * KC / 8; q += 256) dst[q] = src[q];
+            for (int q = tid; q < OGL * NC * CPR; q += 256) {
+                const int r = q / CPR, c = q % CPR;
+                dst[r * CPR + (c ^ (r & (CPR - 1)))] = src[q];
+            }
         }
         __syncthreads();
+        if constexpr (KC == 16) {
+            // 14 instructions over the tap pairs (0, 1) .. (26, 27); all 27
+            // taps are in the one phase
+            constexpr int NP = 14;
+            const bool hi = g >= 2;
+            u4v av[NP];
 #pragma unroll
-        for (int o0 = p0; o0 < p0 + OGL; o0 += OG) {
-#pragma unroll
-            for (int oo = 0; oo < OG; ++oo) {
-                int dx, dy, dz;
-                offset_of(o0 + oo, dx, dy, dz);
-                if (FLIP) {
-                    dx = -dx;
-                    dy = -dy;
-                    dz = -dz;
-                }
-                const int xx = x + dil * dx, yy = y + dil * dy, zz = z + dil * dz;
-                const bool ok = (v < V) && xx >= 0 && xx < D && yy >= 0 && yy < D && zz >= 0 && zz < D;
-                const uint16_t* src = xs + ((size_t)(zz * D + yy) * D + xx) * KC;
-#pragma unroll
-                for (int kq = 0; kq < KCH; ++kq) {
-                    av[oo][kq] = s4{0, 0, 0, 0};
-                    if (ok) av[oo][kq] = *reinterpret_cast<const s4*>(src + kq * 16 + kb);
-                }
+            for (int q = 0; q < NP; ++q) {
+                bool oka, okb = false;
+                const uint32_t ea = tap(2 * q, oka);
+                const uint32_t eb = 2 * q + 1 < 27 ? tap(2 * q + 1, okb) : esafe;
+                const bool ok = hi ? okb : oka;
+                const u4v val = *reinterpret_cast<const u4v*>(xs + (hi ? eb : ea));
+                av[q] = ok ? val : zero;
             }
 #pragma unroll
-            for (int oo = 0; oo < OG; ++oo)
+            for (int q = 0; q < NP; ++q) {
+                const int o = hi ? (2 * q + 1 < 27 ? 2 * q + 1 : 26) : 2 * q;
 #pragma unroll
-                for (int kq = 0; kq < KCH; ++kq)
+                for (int t = 0; t < NB / 16; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, av[q]),
+                                                                     wrow(o * NB + t * 16 + i, g & 1), acc[t], 0, 0,
+                                                                     0);
+            }
+        } else {
+            // OG taps at a time, KQ instructions of 32 channels per tap
+            constexpr int KQ = KC / 32;
+            constexpr int OG = KC <= 32 ? OGL : 9;
+            static_assert(OGL % OG == 0, "register groups within a weight phase");
 #pragma unroll
-                    for (int t = 0; t < NB / 16; ++t) {
-                        const s4 b = *reinterpret_cast<const s4*>(
-                            wl + (((o0 - p0 + oo) * NB) + t * 16 + i) * KC + kq * 16 + kb);
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[oo][kq], b, acc[t], 0, 0, 0);
+            for (int o0 = p0; o0 < p0 + OGL; o0 += OG) {
+                u4v av[OG][KQ];
+#pragma unroll
+                for (int oo = 0; oo < OG; ++oo) {
+                    bool ok;
+                    const uint32_t e = tap(o0 + oo, ok);
+#pragma unroll
+                    for (int kq = 0; kq < KQ; ++kq) {
+                        const u4v val = *reinterpret_cast<const u4v*>(xs + e + kq * 32);
+                        av[oo][kq] = ok ? val : zero;
                     }
+                }
+#pragma unroll
+                for (int oo = 0; oo < OG; ++oo)
+#pragma unroll
+                    for (int kq = 0; kq < KQ; ++kq)
+#pragma unroll
+                        for (int t = 0; t < NB / 16; ++t)
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf8, av[oo][kq]), wrow((o0 - p0 + oo) * NB + t * 16 + i, kq * 4 + g),
+                                acc[t], 0, 0, 0);
+            }
         }
     }
     // D fragment: lane holds rows (lane >> 4) * 4 + r, column lane & 15
@@ -343,8 +400,11 @@ __device__ __forceinline__ double sample_sigma(const SampleDev& S) {
     return fmax(sqrt(*S.rn2 / (3.0 * S.N)), 1e-30);
 }
 
+// n bf16 values, n a multiple of 8 (16-byte stores)
 __global__ void k_zero16(uint16_t* __restrict__ p, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+    uint4* q = reinterpret_cast<uint4*>(p);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n / 8; i += (size_t)gridDim.x * blockDim.x)
+        q[i] = uint4{0, 0, 0, 0};
 }
 
 // Pseudo-random BF16 values in [-0.5, 0.5) (integer hash of index and seed),
@@ -379,8 +439,12 @@ __global__ void k_features(const SampleDev* __restrict__ sd, int D, uint16_t* __
         f[13] = (float)S.kfac[2 * c];
         f[14] = (float)S.kfac[2 * c + 1];
         f[15] = (float)S.kd;
-        uint16_t* o = X + ((size_t)s * V + (size_t)(z * D + y) * D + x) * 16;
-        for (int k = 0; k < 16; ++k) o[k] = f2bf(f[k]);
+        uint32_t wd[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wd[k] = (uint32_t)f2bf(f[2 * k]) | ((uint32_t)f2bf(f[2 * k + 1]) << 16);
+        uint4* o = reinterpret_cast<uint4*>(X + ((size_t)s * V + (size_t)(z * D + y) * D + x) * 16);
+        o[0] = uint4{wd[0], wd[1], wd[2], wd[3]};
+        o[1] = uint4{wd[4], wd[5], wd[6], wd[7]};
     }
 }
 
@@ -574,6 +638,11 @@ struct dda_nn {
     DBuf p, g, m, v;                  // FP32 master params, grads, Adam moments
     std::vector<DBuf> wf, wd;         // per layer BF16 operand layouts
     std::vector<DBuf> act;            // per layer output activations (bf16), act[0] = features
+    // act[0] holds zeros outside the sites of target feat_uid in its first
+    // feat_ns sample slots (the guess then rewrites the site voxels only);
+    // -1 after anything else wrote it
+    long long feat_uid = -1;
+    int feat_ns = 0;
     DBuf out32, dA, dB, partials, lossacc, sdev;
     // guess path: every sample's SampleDev and its (eps-1)/(eps+2), 1/alpha
     // tables in one device buffer, uploaded from pinned staging in one copy
@@ -604,6 +673,7 @@ hipError_t nn_buffers(dda_nn* nn, int D, int ns) {
     const size_t V = (size_t)D * D * D;
     nn->act.resize(nn->layers.size() + 1);
     NCHK(nn->act[0].ensure(V * ns * 16 * 2));
+    nn->feat_uid = -1;
     for (size_t l = 0; l < nn->layers.size(); ++l) NCHK(nn->act[l + 1].ensure(V * ns * nn->layers[l].cout * 2));
     NCHK(nn->out32.ensure(V * ns * 16 * 4));
     const int wmax = std::max(nn->width, 16);
@@ -883,8 +953,13 @@ hipError_t nn_guess_group(dda_nn* nn, const NnSiteView& t, const dda_wave* waves
     const SampleDev* dsd = nn->gsdev.as<SampleDev>();
     for (int s0 = 0; s0 < nr; s0 += chunk) {
         const int nb = std::min(chunk, nr - s0);
-        hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, nn->act[0].as<uint16_t>(), V * nb * 16);
-        NCHK(hipGetLastError());
+        // the voxels outside the target stay zero from an earlier guess on it
+        if (nn->feat_uid != t.uid || nn->feat_ns < nb) {
+            hipLaunchKernelGGL(k_zero16, dim3(1024), dim3(256), 0, st, nn->act[0].as<uint16_t>(), V * nb * 16);
+            NCHK(hipGetLastError());
+            nn->feat_uid = t.uid;
+            nn->feat_ns = nb;
+        }
         hipLaunchKernelGGL(k_features, dim3(256, nb), dim3(256), 0, st, dsd + s0, D, nn->act[0].as<uint16_t>());
         NCHK(hipGetLastError());
         NCHK(nn_forward_any(nn, nb, st));
@@ -986,6 +1061,7 @@ dda_status dda_nn_layer_info(const dda_nn* nn, int32_t* out3 /* depth x {cin, co
 
 dda_status dda_nn_profile(dda_nn* nn, int32_t D, int32_t ns, int32_t reps, double* ms_fwd, double* ms_bwd,
                           double* gflop_fwd) {
+    if (nn) nn->feat_uid = -1;  // act[0] is rewritten
     if (!nn || D < 16 || D % 16 || ns < 1 || ns > 8 || reps < 1) return DDA_ERR_INVALID_ARG;
     hipStream_t st = nullptr;
     if (nn_buffers(nn, D, ns) != hipSuccess) return DDA_ERR_OOM;
@@ -1024,6 +1100,7 @@ dda_status dda_nn_profile(dda_nn* nn, int32_t D, int32_t ns, int32_t reps, doubl
 
 dda_status dda_nn_forward_backward(dda_nn* nn, int32_t ns, int32_t D, const float* x_in, const float* target,
                                    const uint8_t* mask, int32_t nout, float* out, float* grads, double* loss) {
+    if (nn) nn->feat_uid = -1;  // act[0] is rewritten
     if (!nn || ns <= 0 || D < 16 || (D * D * D) % 64 || !x_in || nout < 1 || nout > 16) return DDA_ERR_INVALID_ARG;
     const size_t V = (size_t)D * D * D;
     hipStream_t st = nullptr;
@@ -1061,6 +1138,7 @@ dda_status dda_nn_forward_backward(dda_nn* nn, int32_t ns, int32_t D, const floa
 }
 
 dda_status dda_nn_train(dda_ctx* ctx, dda_nn* nn, const dda_nn_train_opts* o, double* loss_out) {
+    if (nn) nn->feat_uid = -1;  // act[0] is rewritten
     (void)ctx;
     if (!nn || !o) return DDA_ERR_INVALID_ARG;
     const int ns_total = (int)nn->samples.size();
