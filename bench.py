@@ -95,7 +95,7 @@ def parse():
     ap.add_argument("--nn-width", type=int, default=16, choices=[16, 32, 64],
                     help="hidden channels (width 64, depth 10: the 940k-parameter network)")
     ap.add_argument("--nn-depth", type=int, default=4)
-    ap.add_argument("--history", type=int, default=3, help="solutions kept per slot for the least-squares guess")
+    ap.add_argument("--history", type=int, default=4, help="solutions kept per slot for the least-squares guess (at most 4)")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--eval-targets", type=int, default=2)
     ap.add_argument("--sweep", type=int, default=32)
@@ -354,6 +354,10 @@ def sphere64(P, ctx, synth, a, steps=10):
     dom = int(np.argmax(ms))
     gbs = by / (ms * 1e-3) / 1e9
     ms64, by64 = ctx.profile_matvec(0, nrhs=2, prec=P.DDA_FP64, reps=5)
+    # the same FP32 passes at 8 and 32 rhs (one solve of a sweep or a batch)
+    by_nr = {2: (ms, by)}
+    for nr in (8, 32):
+        by_nr[nr] = ctx.profile_matvec(0, nrhs=nr, prec=P.DDA_FP32, reps=10)
     conv = sum(1 for s in st if s["status"] == 0 and s["rel_resid"] <= 1e-5)
     return {
         "workload": f"sphere in {n}^3 box (N={N}), FFT grid {2 * n}^3, m=1.5+0.1i, x={x}, LDR, 1 orientation x 2 "
@@ -370,7 +374,12 @@ def sphere64(P, ctx, synth, a, steps=10):
                    "GBs": round(float(by.sum() / (ms.sum() * 1e-3) / 1e9), 1),
                    "frac_hbm": round(float(by.sum() / (ms.sum() * 1e-3) / 1e9) / HBM_PEAK_GBS, 4),
                    "fp64_total_ms": round(float(ms64.sum()), 5),
-                   "fp64_GBs": round(float(by64.sum() / (ms64.sum() * 1e-3) / 1e9), 1)},
+                   "fp64_GBs": round(float(by64.sum() / (ms64.sum() * 1e-3) / 1e9), 1),
+                   "by_nrhs": {str(nr): {"pass_ms": [round(float(v), 5) for v in m_],
+                                         "total_ms": round(float(m_.sum()), 5),
+                                         "GBs": round(float(b_.sum() / (m_.sum() * 1e-3) / 1e9), 1),
+                                         "frac_hbm": round(float(b_.sum() / (m_.sum() * 1e-3) / 1e9) / HBM_PEAK_GBS, 4)}
+                               for nr, (m_, b_) in by_nr.items()}},
         "fp64_solve": {"solves_per_s": round(2 * k64 / dt64, 3), "iters": [s["iters"] for s in st64],
                        "max_rel_diff_Q_fp32refine_vs_fp64": q_rel},
         "Q": [list(map(float, qq)) for qq in q],
