@@ -71,10 +71,13 @@ __device__ __forceinline__ int spec_xpos(int u, int px, int H) { return u == H ?
 // 2 x 2 Hadamard transform over the four lanes of a quad, lane bits (hy, hx):
 // lane (qy, qx) returns sum over (hy, hx) of (-1)^(qx hx + qy hy) v(hy, hx).
 template <class T> __device__ __forceinline__ Cx<T> quad_hadamard(Cx<T> v, int lane) {
+    // lane bit set: partner minus own value, else own plus partner, as
+    // o + s v with s = -1 or +1 (one rounding either way, the same bits)
+    const T s1 = (lane & 1) ? (T)-1 : (T)1, s2 = (lane & 2) ? (T)-1 : (T)1;
     Cx<T> o = quad_xor<1>(v);
-    v = (lane & 1) ? o - v : v + o;
+    v = Cx<T>{s1 * v.re + o.re, s1 * v.im + o.im};
     o = quad_xor<2>(v);
-    return (lane & 2) ? o - v : v + o;
+    return Cx<T>{s2 * v.re + o.re, s2 * v.im + o.im};
 }
 
 // ---------------------------------------------------------------------------

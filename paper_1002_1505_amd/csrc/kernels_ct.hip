@@ -807,6 +807,10 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
     const Cx<T>* w = WT + pz * R2 * R1 + j;  // w[m * R1]: factor m of thread z1 = j
     const int k2 = j >> 1, e = j & 1;
     const T sgn = e ? (T)-1 : (T)1;
+    // w_16^m on lane e = 1 and 1 on lane e = 0 (a product with it replaces a
+    // product followed by a per-lane select)
+    const T fe = (T)e;
+    auto wsel = [&](int m) -> Cx<T> { return Cx<T>{fmaf(fe, w16[m].re - (T)1, (T)1), fe * w16[m].im}; };
     // spectrum index of inner frequency k = k2 + 8 (k1' + 8 e), kz = 2 k + pz (folded)
     const uint32_t sp0_blk = (uint32_t)kyi * D + kxi;
     uint32_t sp0 = sp0_blk;
@@ -866,7 +870,7 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
     #pragma unroll
                 for (int k1p = 0; k1p < R2; ++k1p) {
                     if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
-                    const Cx<T> mine = (k1p && e) ? w16[k1p] * f[a][k1p] : f[a][k1p];
+                    const Cx<T> mine = k1p ? wsel(k1p) * f[a][k1p] : f[a][k1p];
                     const Cx<T> other = row_xor8(mine);
                     f[a][k1p] = Cx<T>{fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
                 }
@@ -896,7 +900,7 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
                     const Cx<T> mine = f[a][k1p];
                     const Cx<T> other = row_xor8(mine);
                     const Cx<T> s = {fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
-                    f[a][k1p] = (k1p && e) ? cmulc(w16[k1p], s) : s;
+                    f[a][k1p] = k1p ? cmulc(wsel(k1p), s) : s;
                 }
                 bfly<T, +1, R2>(f[a]);
                 // each thread rewrites exactly the slots it read above
