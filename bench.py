@@ -44,10 +44,10 @@ METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM 
 # profiles/matvec_traffic_box64_grid128.md.
 _CT_SOURCES = ("paper_1002_1505_amd/csrc/kernels_ct.hip", "paper_1002_1505_amd/csrc/dda_device.h")
 MEASURED_TRAFFIC = {
-    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "b1ea19d1c4508988",
-                                   "read_bytes": 7906519968, "write_bytes": 8308759968},
-    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "b1ea19d1c4508988",
-                                               "read_bytes": 64460160, "write_bytes": 50331648},
+    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "66add46766a9bbda",
+                                   "read_bytes": 7896419872, "write_bytes": 8299033440},
+    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "66add46766a9bbda",
+                                               "read_bytes": 64453312, "write_bytes": 50331648},
 }
 
 
