@@ -108,6 +108,10 @@ struct MvDot {
 
 enum { MV_AX = 0, MV_RESID = 1 };
 
+// largest slab of one chunk of a batched matvec (fits the last-level cache
+// with the chunk's vectors and the spectrum)
+constexpr size_t MV_CHUNK_BYTES = (size_t)208 << 20;
+
 // ---- matvec / FFT launchers (kernels_fft.hip) ----
 template <class T>
 hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, const MvShape& sh, int nrhs,

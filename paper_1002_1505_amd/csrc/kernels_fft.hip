@@ -555,6 +555,34 @@ hipError_t launch_matvec(const Geo& g, const Tw<T>& tw, const FftPlan* plans, co
                          const Cx<T>* x, Cx<T>* y, const Cx<T>* b, Cx<T>* slab, const Cx<T>* ghat, const Cx<T>* ainv,
                          const int* active, int mode, hipStream_t st, MvDot dot, MvUpd upd) {
     if ((dot.dot || upd.mode) && !(sh.ct & 1)) return hipErrorNotSupported;
+    // A large batch of a small box runs its three passes chunk by chunk, the
+    // chunk's slab (at most MV_CHUNK_BYTES) staying in the 256 MB last-level
+    // cache from the pass that writes it to the pass that reads it.  Every
+    // per-rhs array keeps its stride (vectors 3 Npad, 1/alpha ncomp, fused
+    // partials 4 x 12 n complex, states and flags one), so a chunk is the
+    // same launch on offset pointers, and each rhs's arithmetic is unchanged.
+    const size_t slab_rhs = (size_t)12 * g.n1 * g.n2 * g.n3 * sizeof(Cx<T>);
+    const int chunk = (int)std::min<size_t>((size_t)nrhs, MV_CHUNK_BYTES / slab_rhs);
+    if (chunk >= 4 && chunk < nrhs) {
+        const size_t ve = (size_t)3 * g.Npad, ps = (size_t)4 * 12 * g.n1 * 2;
+        for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+            const int nr = std::min(chunk, nrhs - r0);
+            MvDot d = dot;
+            if (d.w) d.w = reinterpret_cast<const Cx<T>*>(d.w) + r0 * ve;
+            if (d.partials) d.partials += r0 * ps;
+            MvUpd u = upd;
+            if (u.r) u.r = reinterpret_cast<const Cx<T>*>(u.r) + r0 * ve;
+            if (u.v) u.v = reinterpret_cast<const Cx<T>*>(u.v) + r0 * ve;
+            if (u.pout) u.pout = reinterpret_cast<Cx<T>*>(u.pout) + r0 * ve;
+            if (u.st) u.st += r0;
+            if (u.part) u.part += r0 * ps;
+            for (int w = 0; w < 3; ++w)
+                HIP_TRY(launch_pass<T>(w, g, tw, plans, sh, nr, x + r0 * ve, y + r0 * ve, b ? b + r0 * ve : nullptr,
+                                       slab, ghat, ainv + (size_t)r0 * g.ncomp, active ? active + r0 : nullptr, mode,
+                                       st, d, u));
+        }
+        return hipSuccess;
+    }
     for (int w = 0; w < 3; ++w)
         HIP_TRY(launch_pass<T>(w, g, tw, plans, sh, nrhs, x, y, b, slab, ghat, ainv, active, mode, st, dot, upd));
     return hipSuccess;

@@ -227,6 +227,46 @@ def test_batched_uneven_targets_match_single_solves(ctx):
             assert np.all(np.abs(qb[i] - qs[k]) / np.abs(qs[k]) < 1e-4)
 
 
+def test_chunked_batch_matches_small_batches(ctx):
+    """A batch whose slab outgrows the matvec chunk runs the three passes
+    chunk by chunk on offset pointers: 24 rhs of a 48^3 sphere (FP32 slab
+    10.6 MB per rhs, chunks of 19; FP64 21.2 MB, chunks of 9).  The matvec
+    gives the same bits as three 8-rhs calls (which run whole), in FP32 and
+    FP64; 24-rhs solves (the fused inner products and updates of the chunked
+    passes, BiCGstab and BiCGstab(2)) match three 8-rhs solves."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.sphere_occupancy(48)
+    m, kd = 1.4 + 0.05j, 0.3
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    r, comp, _ = dda.sites_from_occupancy(occ)
+    rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 29)
+    x = rng.standard_normal((24, len(r), 3)) + 1j * rng.standard_normal((24, len(r), 3))
+    ainv = [[dda.inverse_polarizability(m, kd, dda.ALPHA_CM)]] * 24
+    for prec in (P.DDA_FP32, P.DDA_FP64):
+        y = ctx.matvec(x, ainv=ainv, prec=prec)
+        y8 = np.concatenate([ctx.matvec(x[i:i + 8], ainv=ainv[i:i + 8], prec=prec) for i in (0, 8, 16)])
+        assert np.array_equal(y, y8), prec
+    kh, ee = [], []
+    for b, th, ph in synth.uniform_orientations(12, rng):
+        k2, e2, _ = dda.waves_for_orientation(b, th, ph)
+        kh += [k2, k2]
+        ee += list(e2)
+    for solver in (P.DDA_SOLVER_BICGSTAB, P.DDA_SOLVER_BICGSTAB2):
+        Pb, sb, stb = ctx.solve(kh, ee, prec=P.DDA_SOLVE_FP32_REFINE, solver=solver)
+        assert stb == 0
+        qb = ctx.cross_sections(24)
+        for i0 in (0, 8, 16):
+            Ps, ss, sts = ctx.solve(kh[i0:i0 + 8], ee[i0:i0 + 8], prec=P.DDA_SOLVE_FP32_REFINE, solver=solver)
+            assert sts == 0
+            qs = ctx.cross_sections(8)
+            for k in range(8):
+                i = i0 + k
+                assert sb[i]["rel_resid"] <= 1e-5
+                assert _rel(Pb[i], Ps[k]) < 1e-6, (solver, i, sb[i], ss[k])
+                assert np.all(np.abs(qb[i] - qs[k]) <= 1e-6 * np.abs(qs[k]))
+
+
 def test_graph_and_eager_agree(ctx):
     import paper_1002_1505_amd as P
 
