@@ -103,6 +103,35 @@ def test_matvec_sampled_rows(ctx, name):
         assert err < tol and emax < 5 * tol
 
 
+@pytest.mark.parametrize("name,nrhs", [("box64_grid128", 2), ("box128_grid256", 32)])
+def test_matvec_sampled_rows_at_bench_batch(ctx, name, nrhs):
+    """The FP32 matvec at the batch size the bench times (2 rhs at 64^3,
+    32 at 128^3) and its default launch shape: for every rhs, sampled rows
+    (first, last and random sites) against the oracle's direct sum, rms and
+    max relative to the rms of the sampled reference.  Each rhs has its own
+    random field, so a slot mix-up between rhs shows as an O(1) error."""
+    import paper_1002_1505_amd as P
+
+    occ, r, comp, kd, m = _problem(name)
+    ctx.set_target(occ, [m], kd, P.DDA_ALPHA_LDR)
+    n = len(r)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((nrhs, n, 3)) + 1j * rng.standard_normal((nrhs, n, 3))
+    ainv = dda.inverse_polarizability(m, kd, dda.ALPHA_CM)
+    y = ctx.matvec(x, ainv=[[ainv]] * nrhs, prec=P.DDA_FP32)
+    per = 64 if nrhs <= 2 else 6
+    worst = (0.0, 0.0)
+    for k in range(nrhs):
+        rows = np.concatenate([[0, n - 1], rng.choice(n, per - 2, replace=False)])
+        ref = dda.matvec_rows(r, kd, np.full(n, ainv), x[k], rows)
+        scale = np.sqrt(np.mean(np.abs(ref) ** 2))
+        err = np.sqrt(np.mean(np.abs(y[k][rows] - ref) ** 2)) / scale
+        emax = np.abs(y[k][rows] - ref).max() / scale
+        worst = (max(worst[0], err), max(worst[1], emax))
+        assert err < 5e-6 and emax < 2.5e-5, (k, err, emax)
+    print(f"[{name} x {nrhs} rhs] sampled rel err worst rms {worst[0]:.3e} max {worst[1]:.3e}", flush=True)
+
+
 @pytest.mark.parametrize("name", list(WORKLOADS))
 def test_solve_full_residual_and_cross_sections(ctx, name):
     import paper_1002_1505_amd as P
