@@ -1617,9 +1617,10 @@ dda_status solve_impl(dda_ctx* c, int32_t nrhs, const dda_wave* waves, const dda
                 sc[s] = 1.0 / std::sqrt(rr);
                 double tin;
                 // inner target below the outer one by the drift the inner
-                // recursive residual can have from the FP64 residual: larger
-                // for FP32 vectors; a miss costs one short extra refinement
-                if (prec == DDA_SOLVE_FP32_REFINE) tin = std::min(0.5, std::max(2e-6, 0.6 * tol / rl));
+                // recursive residual can have from the FP64 residual (FP32
+                // vectors at 1e-5: well below a tenth of the tolerance); a
+                // miss costs one short extra refinement
+                if (prec == DDA_SOLVE_FP32_REFINE) tin = std::min(0.5, std::max(2e-6, 0.9 * tol / rl));
                 else tin = std::min(0.5, std::max(1e-15, 0.9 * tol / rl));
                 tr2[s] = tin * tin;
                 mi[s] = max_iter - iters[i];
