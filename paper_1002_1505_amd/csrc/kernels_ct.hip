@@ -72,19 +72,50 @@ struct UpdArgs {
     const double* part;
 };
 
+// n = 128, FP32, class-grouped slab: one forward block per plane and x
+// parity covers both y parities (the plane occupies the whole LDS, so a
+// block's transform phases cannot overlap another block's)
+template <class T, int N, bool G>
+constexpr bool pfwd_pair() { return N == 128 && G && sizeof(Cx<T>) == 8; }
+
+// Store of a transformed plane of x parity px into the class-grouped slab
+// (FP32): a group's four quadrant partners (y, x), (y, x + n/2),
+// (y + n/2, x), (y + n/2, x + n/2) are 4 consecutive elements of the slab;
+// lane l of a wave stores half l / 32 (rows y or y + n/2) of group l % 32 of
+// the wave's 32 groups as one 16-byte store, so each store of the wave
+// covers 1 KB without gaps.  The two halves of a group lie in one LDS bank,
+// read by lanes of different half-waves.
+template <int N, int NTH>
+__device__ __forceinline__ void store_plane(Cx<float>* out, const Cx<float>* buf, int px, int tid) {
+    constexpr int HN = N / 2, PITCH = N + 1;
+    static_assert(NTH % 64 == 0, "whole waves");
+    float4* o4 = reinterpret_cast<float4*>(out);
+#pragma unroll 4
+    for (int h = tid; h < N * N / 2; h += NTH) {
+        const int gq = (h >> 6) * 32 + (h & 31), half = (h >> 5) & 1;
+        const Cx<float>* q = buf + (gq / HN + half * HN) * PITCH + grp_bx(gq % HN, px, HN);
+        const Cx<float> a0 = q[0], a1 = q[HN];
+        o4[2 * (size_t)gq + half] = make_float4(a0.re, a0.im, a1.re, a1.im);
+    }
+}
+
 template <class T, int N, int UPD, bool G>
 __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __restrict__ x, Cx<T>* __restrict__ slab,
                                                                 Geo g, Tw<T> tw, int nrhs, const int* __restrict__ active,
                                                                 UpdArgs u) {
     constexpr int NTH = plane_threads<N>();
     constexpr int PITCH = N + 1;
+    constexpr bool PAIR = pfwd_pair<T, N, G>();
     extern __shared__ unsigned char smem_raw[];
     Cx<T>* t1 = reinterpret_cast<Cx<T>*>(smem_raw);
     Cx<T>* buf = t1 + N;
     const int nplanes = nrhs * 3 * N;
     const int b = blockIdx.x;
-    const int plane = ((b >> 3) >> 2) * 8 + (b & 7);
-    const int par = (b >> 3) & 3;
+    // the blocks of a plane are 8 apart, so they run on one XCD and share
+    // its L2 for the site values; PAIR: one block per x parity, both y
+    // parities
+    const int plane = PAIR ? ((b >> 3) >> 1) * 8 + (b & 7) : ((b >> 3) >> 2) * 8 + (b & 7);
+    const int par = PAIR ? (b >> 3) & 1 : (b >> 3) & 3;
     // every scalar of the exit test is loaded before it (the rhs clamped into
     // range for blocks past the last plane; a site range is never reversed),
     // so the loads overlap instead of following one another
@@ -196,25 +227,33 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
     }
     __syncthreads();
     ct_fft<T, -1, N, N, NTH, N, PITCH, 0, 1>(buf, t1, tid);   // along x: lines are rows
+    if constexpr (PAIR) {
+        // y parity 1 multiplies row y by h[y] before the transforms; that
+        // factor is constant along a row, so it can be applied after the x
+        // transform, which both y parities then share.  Each thread keeps
+        // the elements (y, x) it restores: x = tid % N, y = tid / N + k NTH / N
+        constexpr int KR = N * N / NTH, YS = NTH / N;
+        static_assert(N * N % NTH == 0 && NTH % N == 0, "whole rows per thread step");
+        Cx<T> keep[KR];
+#pragma unroll
+        for (int k = 0; k < KR; ++k) keep[k] = buf[(tid / N + k * YS) * PITCH + tid % N];
+        ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y, y parity 0
+        store_plane<N, NTH>(slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + par) * (size_t)(N * N), buf, px, tid);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int y = tid / N + k * YS;
+            buf[y * PITCH + tid % N] = keep[k] * th[N + y];
+        }
+        __syncthreads();
+        ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y, y parity 1
+        store_plane<N, NTH>(slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + 2 + par) * (size_t)(N * N), buf, px, tid);
+        return;
+    }
     ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y: lines are columns
     Cx<T>* out = slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + par) * (size_t)(N * N);
     if constexpr (G && sizeof(Cx<T>) == 8) {
-        // a group's four quadrant partners (y, x), (y, x + n/2), (y + n/2, x),
-        // (y + n/2, x + n/2) are 4 consecutive elements of the slab; lane l
-        // of a wave stores half l / 32 (rows y or y + n/2) of group l % 32 of
-        // the wave's 32 groups as one 16-byte store, so each store of the
-        // wave covers 1 KB without gaps.  The two halves of a group lie in
-        // one LDS bank, read by lanes of different half-waves
-        constexpr int HN = N / 2;
-        static_assert(NTH % 64 == 0, "whole waves");
-        float4* o4 = reinterpret_cast<float4*>(out);
-#pragma unroll 4
-        for (int h = tid; h < N * N / 2; h += NTH) {
-            const int gq = (h >> 6) * 32 + (h & 31), half = (h >> 5) & 1;
-            const Cx<T>* q = buf + (gq / HN + half * HN) * PITCH + grp_bx(gq % HN, px, HN);
-            const Cx<T> a0 = q[0], a1 = q[HN];
-            o4[2 * (size_t)gq + half] = make_float4(a0.re, a0.im, a1.re, a1.im);
-        }
+        store_plane<N, NTH>(out, buf, px, tid);
     } else if constexpr (G) {
         // one lane per group (FP64): its four quadrant partners lie in one
         // LDS bank, so the lane reads all four and stores them as 4
@@ -1371,6 +1410,9 @@ void launch_pfwd(int nblk, bool grouped, const Geo& g, const Tw<T>& tw, int nrhs
                  const int* active, const UpdArgs& ua, hipStream_t st) {
     if constexpr (N == 64 || N == 128) {
         if (grouped) {
+            // nblk counts 4 blocks per 8-plane group member; a paired block
+            // covers two of them
+            if constexpr (pfwd_pair<T, N, true>()) nblk /= 2;
             hipLaunchKernelGGL((k_pfwd_ct<T, N, UPD, true>), dim3(nblk), dim3(plane_threads<N>()), (plane_lds<T, N>()),
                                st, x, slab, g, tw, nrhs, active, ua);
             return;
