@@ -232,22 +232,31 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
         // factor is constant along a row, so it can be applied after the x
         // transform, which both y parities then share.  Each thread keeps
         // the elements (y, x) it restores: x = tid % N, y = tid / N + k NTH / N
+        // These are also the rows that the first radix-16 step of the y
+        // transform combines for column x (rows j + YS k, j = tid / N), so
+        // that step runs on the registers and writes rows KR j + k, where
+        // the second step reads them.
         constexpr int KR = N * N / NTH, YS = NTH / N;
         static_assert(N * N % NTH == 0 && NTH % N == 0, "whole rows per thread step");
+        static_assert(RadixPlan<N>::r[0] == KR && N / KR == YS, "first step over the thread's rows");
         Cx<T> keep[KR];
 #pragma unroll
         for (int k = 0; k < KR; ++k) keep[k] = buf[(tid / N + k * YS) * PITCH + tid % N];
-        ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y, y parity 0
-        store_plane<N, NTH>(slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + par) * (size_t)(N * N), buf, px, tid);
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < KR; ++k) {
-            const int y = tid / N + k * YS;
-            buf[y * PITCH + tid % N] = keep[k] * th[N + y];
+        for (int py = 0; py < 2; ++py) {
+            Cx<T> t[KR];
+#pragma unroll
+            for (int k = 0; k < KR; ++k) t[k] = py ? keep[k] * th[N + tid / N + k * YS] : keep[k];
+            bfly<T, -1, KR>(t);
+#pragma unroll
+            for (int k = 0; k < KR; ++k) buf[((tid / N) * KR + k) * PITCH + tid % N] = t[k];
+            __syncthreads();
+            ct_pass<T, -1, N, RadixPlan<N>::r[1], KR, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);  // y, second step
+            store_plane<N, NTH>(slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + 2 * py + par) * (size_t)(N * N), buf,
+                                px, tid);
+            if (py == 0) __syncthreads();
         }
-        __syncthreads();
-        ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y, y parity 1
-        store_plane<N, NTH>(slab + ((((size_t)rhs * 3 + c) * N + z) * 4 + 2 + par) * (size_t)(N * N), buf, px, tid);
         return;
     }
     ct_fft<T, -1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);   // along y: lines are columns
@@ -1188,6 +1197,183 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     }
 }
 
+// Inverse plane pass for n = 128, FP32, class-grouped slab: one block per
+// output class q and four consecutive planes z0 .. z0 + 3 (same rhs and
+// component) runs them in turn, as k_pinv_ct runs one plane.  The plane
+// fills the LDS, so one block runs per CU and nothing else hides a block's
+// slab loads; here the loads of the next plane are issued right after the
+// current plane's values are in LDS and arrive while it is transformed and
+// gathered.  The four class blocks of a plane group are 8 apart, so they run
+// on one XCD at about the same time and share the L2 lines of the grouped
+// slab (a 128-byte line holds four groups' values of all four classes).
+// Partial sums are written per plane and class, as k_pinv_ct writes them.
+template <int MODE, int DOT>
+__global__ void __launch_bounds__(1024) k_pinvq_ct(const Cx<float>* __restrict__ slab, const Cx<float>* __restrict__ x,
+                                                   Cx<float>* __restrict__ y, const Cx<float>* __restrict__ bvec,
+                                                   const Cx<float>* __restrict__ ainv, Geo g, Tw<float> tw, int nrhs,
+                                                   const int* __restrict__ active, const Cx<float>* __restrict__ wv,
+                                                   double* __restrict__ partials) {
+    using T = float;
+    constexpr int N = 128, NTH = 1024, PITCH = N + 1, NN = N * N, HN = N / 2, NI = NN / NTH, YS = NTH / N;
+    static_assert(NTH == plane_threads<N>() && NN % NTH == 0 && NTH % N == 0, "thread layout");
+    extern __shared__ unsigned char smem_raw[];
+    Cx<T>* t1 = reinterpret_cast<Cx<T>*>(smem_raw);
+    Cx<T>* buf = t1 + N;
+    Cx<T>* th = buf + N * PITCH;  // half-shift twiddles: x at [0, n), y at [n, 2n)
+    constexpr int NP = 4;  // planes per block
+    static_assert(N % NP == 0, "plane groups within one rhs and component");
+    const int nplanes = nrhs * 3 * N;
+    const int b = blockIdx.x;
+    const int q = (b >> 3) & 3;
+    const int plane0 = ((b >> 5) * 8 + (b & 7)) * NP;
+    const int rhs = min(plane0 / (3 * N), nrhs - 1);
+    const int c = (plane0 / N) % 3, z0 = plane0 % N;
+    const int on = active ? active[rhs] : 1;
+    if (plane0 >= nplanes || !on) return;
+    const int qx = q & 1, qy = q >> 1;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += NTH) {
+        t1[i] = tw.f1[i];
+        th[i] = tw.h1[i];
+        th[N + i] = tw.h2[i];
+    }
+    const Cx<T>* in = slab + (((size_t)rhs * 3 + c) * N + z0) * 4 * (size_t)NN;
+    // a thread keeps one column kx for every plane; lanes run along the group
+    // positions of one frequency parity px, so a load of the wave reads
+    // consecutive groups of one class plane
+    const int tpos = tid % N, px = tpos / HN, bx = grp_bx(tpos % HN, px, HN), kxp = 2 * bx + px;
+    // frequency row kyp = tid / n + i YS of element i: its parity is the
+    // thread's own (YS is even), so element i lies i (YS / 2) group rows
+    // past element 0 in the same parity-block plane.  The loads are buffer
+    // loads over the group's planes: one 32-bit byte offset of the thread
+    // plus a block-uniform offset (plane and element) in a scalar register,
+    // so no per-element address stays live across the transforms.  The
+    // buffer's extent is the NP planes' four parity blocks each, which
+    // bounds every load
+    static_assert(YS % 2 == 0, "one y parity per thread");
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<Cx<T>*>(in), (short)0, (int)(NP * 4 * NN * sizeof(Cx<T>)), 0x00020000);
+    const int boff = (((tid / N) & 1) * 2 + px) * NN * (int)sizeof(Cx<T>) +
+                     (((tid / N) >> 1) * HN * 4 + (tpos % HN) * 4) * (int)sizeof(Cx<T>);
+    Cx<T> v[NI];
+    auto load_plane = [&](int kp) {
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+            v[i] = __builtin_bit_cast(Cx<T>, __builtin_amdgcn_raw_buffer_load_b64(
+                                                 rs, boff, (kp * 4 * NN + q + i * (YS / 2) * HN * 4) * (int)sizeof(Cx<T>), 0));
+    };
+    load_plane(0);
+    const size_t vo = ((size_t)rhs * 3 + c) * g.Npad;
+    const Cx<T>* av = ainv + (size_t)rhs * g.ncomp;
+    __syncthreads();
+#pragma unroll 1
+    for (int kp = 0; kp < NP; ++kp) {
+        // the thread index passes through an empty asm statement, so the
+        // transforms' index arithmetic is redone per plane instead of being
+        // hoisted out of the loop and held in registers across it
+        int ltid = tid;
+        asm volatile("" : "+v"(ltid));
+        const int z = z0 + kp, plane = plane0 + kp;
+        const int j0 = g.class_start[4 * z + q], j1 = g.class_start[4 * z + q + 1];
+        {
+            // the first radix-16 step of the y transform runs on the
+            // registers: the thread's NI values are the rows kyp = j + YS i
+            // (j = tid / n) of its column, which that step combines; its
+            // outputs go to rows NI j + i, where the transform's second step
+            // reads them
+            static_assert(RadixPlan<N>::r[0] == NI && N / NI == YS, "first step over the thread's rows");
+            const Cx<T> hx = th[kxp];
+            Cx<T> t[NI];
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int kyp = tid / N + i * YS;
+                t[i] = v[i];
+                if (qx) t[i] = cmulc(hx, t[i]);
+                if (qy) t[i] = cmulc(th[N + kyp], t[i]);
+            }
+            bfly<T, +1, NI>(t);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) buf[((tid / N) * NI + i) * PITCH + kxp] = t[i];
+        }
+        // gather operands of the thread's first PF sites, then the next
+        // plane's slab values
+        constexpr int PF = 2;
+        uint32_t pf_s[PF];
+        int pf_c[PF];
+        Cx<T> pf_x[PF], pf_w[PF];
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int j = j1 > j0 ? min(j0 + ltid + k * NTH, j1 - 1) : 0;
+            pf_s[k] = g.site_xyz[j];
+            pf_c[k] = g.site_comp[j];
+            pf_x[k] = x[vo + j];
+            if (MODE == MV_RESID) pf_w[k] = bvec[vo + j];
+            else if (DOT == 1 || DOT == 3) pf_w[k] = wv[vo + j];
+        }
+        if (kp + 1 < NP) load_plane(kp + 1);
+        __syncthreads();
+        ct_pass<T, +1, N, RadixPlan<N>::r[1], NI, N, NTH, N, 1, 0, PITCH>(buf, t1, ltid);  // y, second step
+        ct_fft<T, +1, N, HN, NTH, HN, PITCH, 0, 1>(buf, t1, ltid);  // along x, rows y' < n/2
+        double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0, a3r = 0, a3i = 0;
+        auto visit = [&](int j, uint32_t s, int cj, Cx<T> xj, Cx<T> wj) {
+            const int sx = s & 1023, sy = (s >> 10) & 1023;
+            Cx<T> val = buf[(sy >> 1) * PITCH + (sx >> 1)] + av[cj] * xj;
+            if (MODE == MV_RESID) val = wj - val;
+            y[vo + j] = val;
+            if (DOT == 1) {
+                a0r += (double)wj.re * val.re + (double)wj.im * val.im;
+                a0i += (double)wj.re * val.im - (double)wj.im * val.re;
+            } else if (DOT == 2 || DOT == 3) {
+                a0r += (double)val.re * xj.re + (double)val.im * xj.im;
+                a0i += (double)val.re * xj.im - (double)val.im * xj.re;
+                a1r += (double)val.re * val.re + (double)val.im * val.im;
+                if (DOT == 3) {
+                    a1i += (double)xj.re * xj.re + (double)xj.im * xj.im;
+                    a2r += (double)wj.re * xj.re + (double)wj.im * xj.im;
+                    a2i += (double)wj.re * xj.im - (double)wj.im * xj.re;
+                    a3r += (double)wj.re * val.re + (double)wj.im * val.im;
+                    a3i += (double)wj.re * val.im - (double)wj.im * val.re;
+                }
+            }
+        };
+#pragma unroll
+        for (int k = 0; k < PF; ++k)
+            if (j0 + ltid + k * NTH < j1) visit(j0 + ltid + k * NTH, pf_s[k], pf_c[k], pf_x[k], pf_w[k]);
+#pragma unroll 2
+        for (int j = j0 + ltid + PF * NTH; j < j1; j += NTH) {
+            Cx<T> wj = {0, 0};
+            if (MODE == MV_RESID) wj = bvec[vo + j];
+            else if (DOT == 1 || DOT == 3) wj = wv[vo + j];
+            visit(j, g.site_xyz[j], g.site_comp[j], x[vo + j], wj);
+        }
+        if (DOT) {
+            __shared__ double sh[8 * 16];
+            const int nblk = 12 * N;
+            const int blk = (plane % (3 * N)) * 4 + q;
+            double red[8] = {a0r, a0i, a1r, a1i, a2r, a2i, a3r, a3i};
+            block_sum_n<DOT == 3 ? 8 : (DOT == 2 ? 3 : 2)>(red, sh);
+            if (ltid == 0) {
+                double* o = partials + ((size_t)rhs * 4 * nblk + blk) * 2;
+                o[0] = red[0];
+                o[1] = red[1];
+                if (DOT >= 2) {
+                    o[2 * nblk] = red[2];
+                    o[2 * nblk + 1] = DOT == 3 ? red[3] : 0;
+                }
+                if (DOT == 3) {
+                    o[4 * nblk] = red[4];
+                    o[4 * nblk + 1] = red[5];
+                    o[6 * nblk] = red[6];
+                    o[6 * nblk + 1] = red[7];
+                }
+            }
+        }
+        // every read of the plane (and of the partial-sum scratch) ends
+        // before the next plane is written
+        __syncthreads();
+    }
+}
+
 // Inverse plane pass for n = 64 as two-factor 8 x 8 transforms with one LDS
 // exchange per axis.  Block per (plane, output parity class q) as above; the
 // class pre-combination of the four quadrants feeds registers directly.
@@ -1382,6 +1568,15 @@ template <class T, int N, int MODE, int DOT, bool G>
 void launch_pinv_g(int nblk, bool two_factor, const Geo& g, const Tw<T>& tw, int nrhs, const Cx<T>* x, Cx<T>* y,
                    const Cx<T>* b, const Cx<T>* slab, const Cx<T>* ainv, const int* active, const Cx<T>* w,
                    double* partials, hipStream_t st) {
+    if constexpr (N == 128 && G && std::is_same<T, float>::value) {
+        // one block per class and group of 4 planes (nplanes is a multiple
+        // of 4), in groups of 8 blocks
+        const int ngrp = nrhs * 3 * N / 4;
+        hipLaunchKernelGGL((k_pinvq_ct<MODE, DOT>), dim3((ngrp + 7) / 8 * 8 * 4), dim3(plane_threads<N>()),
+                           (plane_lds<T, N>()), st,
+                           slab, x, y, b, ainv, g, tw, nrhs, active, w, partials);
+        return;
+    }
     if constexpr (N == 64) {
         if (two_factor) {
             hipLaunchKernelGGL((k_pinv3_ct<T, N, MODE, DOT, G>), dim3(nblk), dim3(256), (plane_lds<T, N>()), st, slab,
@@ -1574,6 +1769,13 @@ hipError_t set_attrs_n() {
                 (const void*)k_pinv_ct<T, N, MV_RESID, 0, true>};
             for (const void* f : fg)
                 if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+            if constexpr (std::is_same<T, float>::value) {
+                const void* fq[] = {(const void*)k_pinvq_ct<MV_AX, 0>, (const void*)k_pinvq_ct<MV_AX, 1>,
+                                    (const void*)k_pinvq_ct<MV_AX, 2>, (const void*)k_pinvq_ct<MV_AX, 3>,
+                                    (const void*)k_pinvq_ct<MV_RESID, 0>};
+                for (const void* f : fq)
+                    if (e == hipSuccess) e = set_lds_limit(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+            }
         }
     }
     if constexpr (zpass_lds<T, N, 8>() <= LDS_MAX && N % 8 == 0) {
