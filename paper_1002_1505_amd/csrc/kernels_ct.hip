@@ -72,11 +72,10 @@ struct UpdArgs {
     const double* part;
 };
 
-// n = 128, FP32, class-grouped slab: one forward block per plane and x
-// parity covers both y parities (the plane occupies the whole LDS, so a
-// block's transform phases cannot overlap another block's)
+// n = 64 and 128, FP32, class-grouped slab: one forward block per plane and
+// x parity covers both y parities
 template <class T, int N, bool G>
-constexpr bool pfwd_pair() { return N == 128 && G && sizeof(Cx<T>) == 8; }
+constexpr bool pfwd_pair() { return (N == 64 || N == 128) && G && sizeof(Cx<T>) == 8; }
 
 // Store of a transformed plane of x parity px into the class-grouped slab
 // (FP32): a group's four quadrant partners (y, x), (y, x + n/2),
