@@ -44,10 +44,10 @@ METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM 
 # profiles/matvec_traffic_box64_grid128.md.
 _CT_SOURCES = ("paper_1002_1505_amd/csrc/kernels_ct.hip", "paper_1002_1505_amd/csrc/dda_device.h")
 MEASURED_TRAFFIC = {
-    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "66add46766a9bbda",
-                                   "read_bytes": 7896419872, "write_bytes": 8299033440},
-    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "66add46766a9bbda",
-                                               "read_bytes": 64453312, "write_bytes": 50331648},
+    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "eed8ebc2d146989e",
+                                   "read_bytes": 7967868960, "write_bytes": 8286211136},
+    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "eed8ebc2d146989e",
+                                               "read_bytes": 64455744, "write_bytes": 50331648},
 }
 
 
@@ -123,8 +123,12 @@ def pass_names(P, ctx, n, prec_name="float"):
                  2: f"k_zpass3_ct<float, {n}, {sh['tx']}>",
                  3: f"k_zpass4_ct<float, {n}, {sh['tx']}, {grp}>",
                  4: f"k_zpass5_ct<{sh['tx']}, {grp}>"}[sh["zrb"]]
-        iname = "k_pinv3_ct" if sh["ct"] & 4 else "k_pinv_ct"
-        return [f"k_pfwd_ct<float, {n}, 0|1|2|3, {grp}>", zname, f"{iname}<float, {n}, 0, 0|1|2|3, {grp}>"], sh
+        if n == 128 and grp == "true":
+            iname = "k_pinvq_ct<0, 0|1|2|3>"  # four planes of one class per block
+        else:
+            iname = "k_pinv3_ct" if sh["ct"] & 4 else "k_pinv_ct"
+            iname = f"{iname}<float, {n}, 0, 0|1|2|3, {grp}>"
+        return [f"k_pfwd_ct<float, {n}, 0|2, {grp}>", zname, iname], sh
     return ["k_plane_fwd<float>", "k_zpass<float>", "k_plane_inv<float, 0>"], sh
 
 
