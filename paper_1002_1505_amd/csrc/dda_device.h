@@ -361,10 +361,14 @@ template <> struct RadixPlan<128> { static constexpr int np = 2; static constexp
 template <> struct RadixPlan<256> { static constexpr int np = 3; static constexpr int r[3] = {8, 8, 4}; };
 
 // Line l of the LDS batch starts at (l / LG) * LS1 + (l % LG) * LS0; its
-// elements are ES apart.
-template <class T, int DIR, int N, int R, int L, int NL, int NTH, int LG, int LS0, int LS1, int ES>
+// elements are ES apart.  KEEP < N (last step only): outputs KEEP .. N - 1
+// of each line are not written (nor, where the compiler can drop them,
+// computed); the last step writes output j + t L of its butterfly j, so
+// output t of every butterfly is kept iff t L < KEEP.
+template <class T, int DIR, int N, int R, int L, int NL, int NTH, int LG, int LS0, int LS1, int ES, int KEEP = N>
 __device__ __forceinline__ void ct_pass(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int tid) {
     constexpr int NB = N / R, TOT = NB * NL, MB = (TOT + NTH - 1) / NTH, TWS = N / (L * R);
+    static_assert(KEEP == N || (L * R == N && KEEP % L == 0 && KEEP < N), "pruned outputs only in the last step");
     Cx<T> v[MB][R];
 #pragma unroll
     for (int c = 0; c < MB; ++c) {
@@ -396,17 +400,30 @@ __device__ __forceinline__ void ct_pass(Cx<T>* __restrict__ buf, const Cx<T>* __
             const int k = j % L;
             const int ob = (j - k) * R + k;
 #pragma unroll
-            for (int t = 0; t < R; ++t) buf[base + (ob + t * L) * ES] = v[c][t];
+            for (int t = 0; t < R; ++t)
+                if (t * L < KEEP) buf[base + (ob + t * L) * ES] = v[c][t];
         }
     }
     __syncthreads();
 }
 
-template <class T, int DIR, int N, int NL, int NTH, int LG, int LS0, int LS1, int ES, int P = 0, int L = 1>
-__device__ __forceinline__ void ct_fft(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int tid) {
+template <class T, int DIR, int N, int NL, int NTH, int LG, int LS0, int LS1, int ES, int KEEP, int P, int L>
+__device__ __forceinline__ void ct_fft_steps(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int tid) {
     if constexpr (P < RadixPlan<N>::np) {
         constexpr int R = RadixPlan<N>::r[P];
-        ct_pass<T, DIR, N, R, L, NL, NTH, LG, LS0, LS1, ES>(buf, tw, tid);
-        ct_fft<T, DIR, N, NL, NTH, LG, LS0, LS1, ES, P + 1, L * R>(buf, tw, tid);
+        constexpr int K = (P + 1 == RadixPlan<N>::np) ? KEEP : N;
+        ct_pass<T, DIR, N, R, L, NL, NTH, LG, LS0, LS1, ES, K>(buf, tw, tid);
+        ct_fft_steps<T, DIR, N, NL, NTH, LG, LS0, LS1, ES, KEEP, P + 1, L * R>(buf, tw, tid);
     }
+}
+
+template <class T, int DIR, int N, int NL, int NTH, int LG, int LS0, int LS1, int ES>
+__device__ __forceinline__ void ct_fft(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int tid) {
+    ct_fft_steps<T, DIR, N, NL, NTH, LG, LS0, LS1, ES, N, 0, 1>(buf, tw, tid);
+}
+
+// As ct_fft, writing only outputs 0 .. KEEP - 1 of each line.
+template <class T, int DIR, int N, int NL, int NTH, int LG, int LS0, int LS1, int ES, int KEEP>
+__device__ __forceinline__ void ct_fft_keep(Cx<T>* __restrict__ buf, const Cx<T>* __restrict__ tw, int tid) {
+    ct_fft_steps<T, DIR, N, NL, NTH, LG, LS0, LS1, ES, KEEP, 0, 1>(buf, tw, tid);
 }

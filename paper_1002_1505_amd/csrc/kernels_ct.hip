@@ -1134,8 +1134,10 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
         else if (DOT == 1 || DOT == 3) pf_w[k] = wv[vo + j];
     }
     __syncthreads();
-    ct_fft<T, +1, N, N, NTH, N, 1, 0, PITCH>(buf, t1, tid);    // along y, every column
-    ct_fft<T, +1, N, HN, NTH, HN, PITCH, 0, 1>(buf, t1, tid);  // along x, rows y' < n/2
+    // only outputs below n/2 are read: rows y' < n/2 by the x transform,
+    // columns x' < n/2 by the gather
+    ct_fft_keep<T, +1, N, N, NTH, N, 1, 0, PITCH, HN>(buf, t1, tid);    // along y, every column
+    ct_fft_keep<T, +1, N, HN, NTH, HN, PITCH, 0, 1, HN>(buf, t1, tid);  // along x, rows y' < n/2
     double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0, a3r = 0, a3i = 0;
     auto visit = [&](int j, uint32_t s, int cj, Cx<T> xj, Cx<T> wj) {
         const int sx = s & 1023, sy = (s >> 10) & 1023;
@@ -1311,8 +1313,11 @@ __global__ void __launch_bounds__(1024) k_pinvq_ct(const Cx<float>* __restrict__
         }
         if (kp + 1 < NP) load_plane(kp + 1);
         __syncthreads();
-        ct_pass<T, +1, N, RadixPlan<N>::r[1], NI, N, NTH, N, 1, 0, PITCH>(buf, t1, ltid);  // y, second step
-        ct_fft<T, +1, N, HN, NTH, HN, PITCH, 0, 1>(buf, t1, ltid);  // along x, rows y' < n/2
+        // only outputs below n/2 are read: rows y' < n/2 by the x
+        // transform, columns x' < n/2 by the gather
+        static_assert(RadixPlan<N>::np == 2, "two steps");
+        ct_pass<T, +1, N, RadixPlan<N>::r[1], NI, N, NTH, N, 1, 0, PITCH, HN>(buf, t1, ltid);  // y, second step
+        ct_fft_keep<T, +1, N, HN, NTH, HN, PITCH, 0, 1, HN>(buf, t1, ltid);  // along x, rows y' < n/2
         double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0, a3r = 0, a3i = 0;
         auto visit = [&](int j, uint32_t s, int cj, Cx<T> xj, Cx<T> wj) {
             const int sx = s & 1023, sy = (s >> 10) & 1023;
