@@ -1027,6 +1027,11 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     const Cx<T>* in = slab + (((size_t)rhs * 3 + c) * N + z) * 4 * (size_t)NN;
     const T sgx = qx ? (T)-1 : (T)1, sgy = qy ? (T)-1 : (T)1;
     constexpr int NI = NN / NTH;  // frequencies per thread
+    // grouped slab with a two-step plan whose first radix is NI: a thread's
+    // NI rows are the ones the first step of the y transform combines for
+    // its column, so that step runs on its registers (see k_pinvq_ct)
+    constexpr bool REG1 = G && NN % NTH == 0 && NTH % N == 0 && RadixPlan<N>::np == 2 &&
+                          RadixPlan<N>::r[0] == NI && N / NI == NTH / N;
     if constexpr (G && NN % NTH == 0 && NTH % N == 0 && NI <= 16) {
         // grouped slab (one load per frequency): a thread keeps one column kx
         // (NTH is a multiple of n); all its loads are issued before the first
@@ -1057,8 +1062,14 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
 #pragma unroll
             for (int i = 0; i < NI; ++i) v[i] = cmulc(hy[i], v[i]);
         }
+        if constexpr (REG1) {
+            bfly<T, +1, NI>(v);
 #pragma unroll
-        for (int i = 0; i < NI; ++i) buf[((tid + i * NTH) / N) * PITCH + kxp] = v[i];
+            for (int i = 0; i < NI; ++i) buf[((tid / N) * NI + i) * PITCH + kxp] = v[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < NI; ++i) buf[((tid + i * NTH) / N) * PITCH + kxp] = v[i];
+        }
     } else if constexpr (!G && NN % NTH == 0 && NTH % N == 0) {
         // row layout (four quadrant loads per frequency): the same scheme in
         // batches of BI frequencies, which bounds the registers in flight
@@ -1136,8 +1147,11 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pinv_ct(const Cx<T>* __r
     __syncthreads();
     // only outputs below n/2 are read: rows y' < n/2 by the x transform,
     // columns x' < n/2 by the gather
-    ct_fft_keep<T, +1, N, N, NTH, N, 1, 0, PITCH, HN>(buf, t1, tid);    // along y, every column
-    ct_fft_keep<T, +1, N, HN, NTH, HN, PITCH, 0, 1, HN>(buf, t1, tid);  // along x, rows y' < n/2
+    if constexpr (REG1)
+        ct_pass<T, +1, N, RadixPlan<N>::r[1], NI, N, NTH, N, 1, 0, PITCH, HN>(buf, t1, tid);  // y, second step
+    else
+        ct_fft_keep<T, +1, N, N, NTH, N, 1, 0, PITCH, HN>(buf, t1, tid);  // along y, every column
+    ct_fft_keep<T, +1, N, HN, NTH, HN, PITCH, 0, 1, HN>(buf, t1, tid);    // along x, rows y' < n/2
     double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0, a3r = 0, a3i = 0;
     auto visit = [&](int j, uint32_t s, int cj, Cx<T> xj, Cx<T> wj) {
         const int sx = s & 1023, sy = (s >> 10) & 1023;
