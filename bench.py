@@ -44,10 +44,10 @@ METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM 
 # profiles/matvec_traffic_box64_grid128.md.
 _CT_SOURCES = ("paper_1002_1505_amd/csrc/kernels_ct.hip", "paper_1002_1505_amd/csrc/dda_device.h")
 MEASURED_TRAFFIC = {
-    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "eed8ebc2d146989e",
-                                   "read_bytes": 7967868960, "write_bytes": 8286211136},
-    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "eed8ebc2d146989e",
-                                               "read_bytes": 64455744, "write_bytes": 50331648},
+    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "0bd0c1300969339b",
+                                   "read_bytes": 7841742752, "write_bytes": 8294847584},
+    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "0bd0c1300969339b",
+                                               "read_bytes": 64456064, "write_bytes": 50331648},
 }
 
 
