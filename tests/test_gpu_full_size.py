@@ -132,6 +132,42 @@ def test_matvec_sampled_rows_at_bench_batch(ctx, name, nrhs):
     print(f"[{name} x {nrhs} rhs] sampled rel err worst rms {worst[0]:.3e} max {worst[1]:.3e}", flush=True)
 
 
+def test_matvec_box128_two_compositions_empty_planes(ctx):
+    """The 128^3 FP32 passes on a target that leaves planes, rows and whole
+    parity classes of planes empty and has two compositions: an axis-aligned
+    ellipsoid (diameters 70 x 110 x 36) whose x >= 64 half is composition 2,
+    3 rhs (plane groups of the inverse pass that span no padding).  Sampled
+    rows of every rhs (first and last site, the sites of the first and last
+    occupied planes, random ones) against the oracle's direct sum."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.ellipsoid_occupancy((128, 128, 128), (70, 110, 36))
+    occ[:, :, 64:] *= 2
+    m = [1.33 + 0.01j, 1.5 + 0.05j]
+    r, comp, idx = dda.sites_from_occupancy(occ)
+    kd = 10.0 / dda.effective_radius(len(r))
+    ctx.set_target(occ, m, kd, P.DDA_ALPHA_LDR)
+    sh = ctx.get_shape(0, P.DDA_FP32)
+    assert sh["ct"] & 8 and sh["zrb"] == 4, sh  # class-grouped 128^3 kernels
+    n, nrhs = len(r), 3
+    zs = idx[:, 2]
+    assert zs.min() > 0 and zs.max() < 127  # empty planes at both ends
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal((nrhs, n, 3)) + 1j * rng.standard_normal((nrhs, n, 3))
+    a_comp = [dda.inverse_polarizability(mm, kd, dda.ALPHA_CM) for mm in m]
+    ainv_site = np.asarray(a_comp)[comp - 1]
+    y = ctx.matvec(x, ainv=[a_comp] * nrhs, prec=P.DDA_FP32)
+    edge = np.concatenate([np.nonzero(zs == zs.min())[0][:4], np.nonzero(zs == zs.max())[0][-4:]])
+    for k in range(nrhs):
+        rows = np.unique(np.concatenate([[0, n - 1], edge, rng.choice(n, 22, replace=False)]))
+        ref = dda.matvec_rows(r, kd, ainv_site, x[k], rows)
+        scale = np.sqrt(np.mean(np.abs(ref) ** 2))
+        err = np.sqrt(np.mean(np.abs(y[k][rows] - ref) ** 2)) / scale
+        emax = np.abs(y[k][rows] - ref).max() / scale
+        print(f"[ellipsoid 128 rhs {k}] N={n} sampled rel err {err:.3e} max {emax:.3e}", flush=True)
+        assert err < 5e-6 and emax < 2.5e-5, (k, err, emax)
+
+
 @pytest.mark.parametrize("name", list(WORKLOADS))
 def test_solve_full_residual_and_cross_sections(ctx, name):
     import paper_1002_1505_amd as P
