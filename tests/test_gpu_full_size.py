@@ -138,7 +138,8 @@ def test_matvec_box128_two_compositions_empty_planes(ctx):
     ellipsoid (diameters 70 x 110 x 36) whose x >= 64 half is composition 2,
     3 rhs (plane groups of the inverse pass that span no padding).  Sampled
     rows of every rhs (first and last site, the sites of the first and last
-    occupied planes, random ones) against the oracle's direct sum."""
+    occupied planes, random ones) against the oracle's direct sum; then both
+    solvers to 1e-5, checked by the full-vector FP64 residual."""
     import paper_1002_1505_amd as P
 
     occ = synth.ellipsoid_occupancy((128, 128, 128), (70, 110, 36))
@@ -165,6 +166,50 @@ def test_matvec_box128_two_compositions_empty_planes(ctx):
         err = np.sqrt(np.mean(np.abs(y[k][rows] - ref) ** 2)) / scale
         emax = np.abs(y[k][rows] - ref).max() / scale
         print(f"[ellipsoid 128 rhs {k}] N={n} sampled rel err {err:.3e} max {emax:.3e}", flush=True)
+        assert err < 5e-6 and emax < 2.5e-5, (k, err, emax)
+    # BiCGstab and BiCGstab(2) solves (fused inner products of the inverse
+    # pass over empty classes): full-vector FP64 residual by the oracle
+    khat, e0 = P.orientation_waves(0.3, 0.8, 1.1)
+    for solver in (P.DDA_SOLVER_BICGSTAB, P.DDA_SOLVER_BICGSTAB2):
+        Pg, st, status = ctx.solve(khat, e0, tol=1e-5, prec=P.DDA_SOLVE_FP32_REFINE, solver=solver)
+        assert status == 0
+        q = ctx.cross_sections(2)
+        for l in range(2):
+            _check_solution(f"ellipsoid 128 solver {solver} pol {l}", r, comp, m, kd, khat[l], e0[l], Pg[l], st[l])
+            assert q[l, 1] > 0 and q[l, 2] > 0
+
+
+def test_matvec_box64_two_compositions_empty_planes(ctx):
+    """The 64^3 FP32 passes (paired forward blocks, inverse blocks with the
+    first y step on registers) on a two-composition ellipsoid that leaves
+    planes and classes empty, 5 rhs: sampled rows of every rhs against the
+    oracle's direct sum."""
+    import paper_1002_1505_amd as P
+
+    occ = synth.ellipsoid_occupancy((64, 64, 64), (40, 56, 18))
+    occ[:, 32:, :] *= 2
+    m = [1.5 + 0.1j, 1.2 + 0.02j]
+    r, comp, idx = dda.sites_from_occupancy(occ)
+    kd = 6.0 / dda.effective_radius(len(r))
+    ctx.set_target(occ, m, kd, P.DDA_ALPHA_LDR)
+    sh = ctx.get_shape(0, P.DDA_FP32)
+    assert sh["ct"] & 8, sh  # class-grouped 64^3 kernels
+    n, nrhs = len(r), 5
+    zs = idx[:, 2]
+    assert zs.min() > 0 and zs.max() < 63
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal((nrhs, n, 3)) + 1j * rng.standard_normal((nrhs, n, 3))
+    a_comp = [dda.inverse_polarizability(mm, kd, dda.ALPHA_CM) for mm in m]
+    ainv_site = np.asarray(a_comp)[comp - 1]
+    y = ctx.matvec(x, ainv=[a_comp] * nrhs, prec=P.DDA_FP32)
+    edge = np.concatenate([np.nonzero(zs == zs.min())[0][:4], np.nonzero(zs == zs.max())[0][-4:]])
+    for k in range(nrhs):
+        rows = np.unique(np.concatenate([[0, n - 1], edge, rng.choice(n, 22, replace=False)]))
+        ref = dda.matvec_rows(r, kd, ainv_site, x[k], rows)
+        scale = np.sqrt(np.mean(np.abs(ref) ** 2))
+        err = np.sqrt(np.mean(np.abs(y[k][rows] - ref) ** 2)) / scale
+        emax = np.abs(y[k][rows] - ref).max() / scale
+        print(f"[ellipsoid 64 rhs {k}] N={n} sampled rel err {err:.3e} max {emax:.3e}", flush=True)
         assert err < 5e-6 and emax < 2.5e-5, (k, err, emax)
 
 
