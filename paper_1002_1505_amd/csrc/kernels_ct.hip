@@ -747,19 +747,27 @@ __global__ void __launch_bounds__(TX * 16) k_zpass4_ct(Cx<T>* __restrict__ slab,
         }
 }
 
-// Lane (lane ^ 8) of the same row of 16 lanes: a DPP row rotation by 8.
-// Every lane of the wave must be active.
-__device__ __forceinline__ float row_xor8(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));
+// m + s * (m of lane ^ 8 in the same row of 16 lanes), both parts: one
+// v_fmac_f32 with a DPP row rotation by 8 per part (the compiler does not fold
+// a DPP move into an FMAC).  The s_nop gives the two wait states between a
+// VALU write of a register and a DPP read of it.  Every lane of the wave must
+// be active.
+__device__ __forceinline__ Cx<float> fma_row_xor8(Cx<float> m, float s) {
+    Cx<float> d = m;
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %2, %4 row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %3, %4 row_ror:8 row_mask:0xf bank_mask:0xf"
+        : "+v"(d.re), "+v"(d.im)
+        : "v"(m.re), "v"(m.im), "v"(s));
+    return d;
 }
-__device__ __forceinline__ Cx<float> row_xor8(Cx<float> v) { return {row_xor8(v.re), row_xor8(v.im)}; }
 
 // z pass of the n = 128 box (FP32) as a two-factor decomposition 128 = 16 x 8
 // with one frequency parity per block half.  With z = z1 + 16 z2 and
 // k = k2 + 8 k1, the forward DFT is an 8-point DFT over z2 (thread (c, z1),
 // 16 threads per column), a twiddle w_128^(z1 k2), one exchange through LDS
 // and a 16-point DFT over z1.  That 16-point DFT is split over a pair of
-// lanes (row_xor8 partners): thread (c, k2, e) with e the parity of z1 takes
+// lanes (8 apart in a row of 16): thread (c, k2, e) with e the parity of z1 takes
 // the 8-point DFT over z1 = e + 2 z1' and the pair finishes it with one
 // radix-2 step, F[k1' + 8 s] = G_0[k1'] + (-1)^s w_16^k1' G_1[k1'], lane e
 // keeping s = e; so each thread holds 8 frequencies k = k2 + 8 k1' + 64 e of
@@ -853,7 +861,7 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
     }
     const Cx<T>* w = WT + pz * R2 * R1 + j;  // w[m * R1]: factor m of thread z1 = j
     const int k2 = j >> 1, e = j & 1;
-    const T sgn = e ? (T)-1 : (T)1;
+    const T sgn = e ? (T)-1 : (T)1, nsgn = -sgn;
     // w_16^m on lane e = 1 and 1 on lane e = 0 (a product with it replaces a
     // product followed by a per-lane select)
     const T fe = (T)e;
@@ -912,14 +920,15 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
                 for (int z1p = 0; z1p < R2; ++z1p) f[a][z1p] = X[xi(a, k2, e + 2 * z1p)];
                 bfly<T, -1, R2>(f[a]);
                 // radix-2 step across the lane pair: lane e contributes G_0 or
-                // w_16^k1' G_1 and keeps F[k1' + 8 e] = contribution of lane 0
-                // +/- that of lane 1
+                // w_16^k1' G_1 and keeps its own contribution + (-1)^e that of
+                // its partner: F[k1'] on lane 0, -F[k1' + 8] on lane 1 (the
+                // sign is carried through the tensor product, which is
+                // linear, and taken back in the inverse step)
     #pragma unroll
                 for (int k1p = 0; k1p < R2; ++k1p) {
                     if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
                     const Cx<T> mine = k1p ? wsel(k1p) * f[a][k1p] : f[a][k1p];
-                    const Cx<T> other = row_xor8(mine);
-                    f[a][k1p] = Cx<T>{fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
+                    f[a][k1p] = fma_row_xor8(mine, sgn);
                 }
             }
     #pragma unroll
@@ -940,13 +949,13 @@ __global__ void __launch_bounds__(TX * 32) __attribute__((amdgpu_waves_per_eu(3,
     #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 // inverse radix-2 step: lane e forms Y0 + Y1 (e = 0) or
-                // (Y0 - Y1) conj(w_16^k1') (e = 1) from its value and its partner's
+                // (Y0 - Y1) conj(w_16^k1') (e = 1) from its value and its
+                // partner's; lane 1 holds -Y1, so that is its own value
+                // - (-1)^e times the partner's
     #pragma unroll
                 for (int k1p = 0; k1p < R2; ++k1p) {
                     if (k1p % 2 == 0) __builtin_amdgcn_sched_barrier(0);
-                    const Cx<T> mine = f[a][k1p];
-                    const Cx<T> other = row_xor8(mine);
-                    const Cx<T> s = {fmaf(sgn, mine.re, other.re), fmaf(sgn, mine.im, other.im)};
+                    const Cx<T> s = fma_row_xor8(f[a][k1p], nsgn);
                     f[a][k1p] = k1p ? cmulc(wsel(k1p), s) : s;
                 }
                 bfly<T, +1, R2>(f[a]);
