@@ -44,10 +44,10 @@ METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM 
 # profiles/matvec_traffic_box64_grid128.md.
 _CT_SOURCES = ("paper_1002_1505_amd/csrc/kernels_ct.hip", "paper_1002_1505_amd/csrc/dda_device.h")
 MEASURED_TRAFFIC = {
-    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "0bd0c1300969339b",
-                                   "read_bytes": 7841742752, "write_bytes": 8294847584},
-    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "0bd0c1300969339b",
-                                               "read_bytes": 64456064, "write_bytes": 50331648},
+    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "b55c36364439b26a",
+                                   "read_bytes": 8138509312, "write_bytes": 8247242112},
+    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "b55c36364439b26a",
+                                               "read_bytes": 64458048, "write_bytes": 50331648},
 }
 
 
