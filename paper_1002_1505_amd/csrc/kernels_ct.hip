@@ -1273,7 +1273,8 @@ __global__ void __launch_bounds__(1024) k_pinvq_ct(const Cx<float>* __restrict__
     // plus a block-uniform offset (plane and element) in a scalar register,
     // so no per-element address stays live across the transforms.  The
     // buffer's extent is the NP planes' four parity blocks each, which
-    // bounds every load
+    // bounds every load (an offset past it reads zero).  The last descriptor
+    // word selects 32-bit data for raw (untyped) loads on this chip family.
     static_assert(YS % 2 == 0, "one y parity per thread");
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<Cx<T>*>(in), (short)0, (int)(NP * 4 * NN * sizeof(Cx<T>)), 0x00020000);
