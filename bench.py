@@ -44,9 +44,9 @@ METRIC = "converged DDA solves/s at resid 1e-5 (learned vs plain); matvec % HBM 
 # profiles/matvec_traffic_box64_grid128.md.
 _CT_SOURCES = ("paper_1002_1505_amd/csrc/kernels_ct.hip", "paper_1002_1505_amd/csrc/dda_device.h")
 MEASURED_TRAFFIC = {
-    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "b3a345cf9772ebd6",
+    ("k_zpass5_ct<8, true>", 32): {"sources": _CT_SOURCES, "sha256": "446d6f046b54805c",
                                    "read_bytes": 8138509312, "write_bytes": 8247242112},
-    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "b3a345cf9772ebd6",
+    ("k_zpass4_ct<float, 64, 16, true>", 2): {"sources": _CT_SOURCES, "sha256": "446d6f046b54805c",
                                                "read_bytes": 64458048, "write_bytes": 50331648},
 }
 

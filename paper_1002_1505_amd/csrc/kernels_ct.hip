@@ -231,13 +231,14 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_pfwd_ct(const Cx<T>* __r
         // factor is constant along a row, so it can be applied after the x
         // transform, which both y parities then share.  Each thread keeps
         // the elements (y, x) it restores: x = tid % N, y = tid / N + k NTH / N
-        // These are also the rows that the first radix-16 step of the y
-        // transform combines for column x (rows j + YS k, j = tid / N), so
-        // that step runs on the registers and writes rows KR j + k, where
-        // the second step reads them.
+        // These are also the rows that the first step (radix KR: 16 at
+        // n = 128, 8 at n = 64) of the y transform combines for column x
+        // (rows j + YS k, j = tid / N), so that step runs on the registers
+        // and writes rows KR j + k, where the second and last step reads them.
         constexpr int KR = N * N / NTH, YS = NTH / N;
         static_assert(N * N % NTH == 0 && NTH % N == 0, "whole rows per thread step");
-        static_assert(RadixPlan<N>::r[0] == KR && N / KR == YS, "first step over the thread's rows");
+        static_assert(RadixPlan<N>::np == 2 && RadixPlan<N>::r[0] == KR && N / KR == YS,
+                      "two steps, the first over the thread's rows");
         Cx<T> keep[KR];
 #pragma unroll
         for (int k = 0; k < KR; ++k) keep[k] = buf[(tid / N + k * YS) * PITCH + tid % N];
