@@ -589,6 +589,103 @@ struct Sample {
         if (e_ != hipSuccess) return e_;          \
     } while (0)
 
+// Weight gradient for boxes whose side is a multiple of 16, with aligned
+// operand reads: sum_x X[x + dil dx][ci] dY[x][co] = sum_x X[x][ci]
+// dY[x - dil dx][co], so the block stages its 9 input rows unshifted
+// ([r9][ci][x]) and the output-gradient row in three shifted copies
+// ([dx + 1][co][x], zero where x - dil dx leaves the row).  Every operand of
+// v_mfma_f32_16x16x16_bf16 is then 4 consecutive x of one row at a multiple of
+// 4: one 8-byte LDS read instead of four 2-byte ones.
+template <int KC, int NC>
+__global__ void __launch_bounds__(256) k_wgrad_al(const uint16_t* __restrict__ X, const uint16_t* __restrict__ dY,
+                                                  float* __restrict__ partials, int D, int dil, int rows_per_block) {
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int NT = 27 * (KC / 16) * (NC / 16);  // 16x16 tiles of dW
+    constexpr int ZG = wgrad_groups(KC, NC);
+    constexpr int TPB = (NT + ZG - 1) / ZG;         // tiles per block
+    constexpr int TPW = (TPB + 3) / 4;              // tiles per wave
+    const int tile0 = blockIdx.z * TPB;
+    uint16_t* xt = reinterpret_cast<uint16_t*>(smem_raw);  // [9][KC][D]
+    uint16_t* gt = xt + 9 * KC * D;                         // [3][NC][D]
+    const int V = D * D * D;
+    const int s = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i = lane & 15, kb = (lane >> 4) * 4;
+    f4 acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = f4{0, 0, 0, 0};
+    const int row0 = blockIdx.x * rows_per_block;
+    for (int rr = 0; rr < rows_per_block; ++rr) {
+        const int row = row0 + rr;
+        if (row >= D * D) break;
+        const int y = row % D, z = row / D;
+        __syncthreads();
+        // input rows (z + dil dz, y + dil dy): 8 channels of a voxel per
+        // 16-byte load, transposed into [r9][ci][x]
+        for (int idx = tid; idx < 9 * D * (KC / 8); idx += 256) {
+            const int c8 = idx % (KC / 8), xx = (idx / (KC / 8)) % D, r9 = idx / ((KC / 8) * D);
+            const int yy = y + dil * (r9 % 3 - 1), zz = z + dil * (r9 / 3 - 1);
+            uint4 val = {0, 0, 0, 0};
+            if (yy >= 0 && yy < D && zz >= 0 && zz < D)
+                val = *reinterpret_cast<const uint4*>(X + ((size_t)s * V + (size_t)(zz * D + yy) * D + xx) * KC + c8 * 8);
+            const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+            uint16_t* d = xt + ((size_t)r9 * KC + c8 * 8) * D + xx;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                d[(2 * q) * D] = (uint16_t)(w4[q] & 0xffff);
+                d[(2 * q + 1) * D] = (uint16_t)(w4[q] >> 16);
+            }
+        }
+        // output-gradient row, copy dx + 1 at x holding dY[x - dil dx]
+        for (int idx = tid; idx < 3 * D * (NC / 8); idx += 256) {
+            const int c8 = idx % (NC / 8), xx = (idx / (NC / 8)) % D, cp = idx / ((NC / 8) * D);
+            const int xs = xx - dil * (cp - 1);
+            uint4 val = {0, 0, 0, 0};
+            if (xs >= 0 && xs < D)
+                val = *reinterpret_cast<const uint4*>(dY + ((size_t)s * V + (size_t)row * D + xs) * NC + c8 * 8);
+            const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+            uint16_t* d = gt + ((size_t)cp * NC + c8 * 8) * D + xx;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                d[(2 * q) * D] = (uint16_t)(w4[q] & 0xffff);
+                d[(2 * q + 1) * D] = (uint16_t)(w4[q] >> 16);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int tl = wave * TPW + t, tile = tile0 + tl;
+            if (tl >= TPB || tile >= NT) break;
+            const int o = tile / ((KC / 16) * (NC / 16));
+            const int cit = (tile / (NC / 16)) % (KC / 16), cot = tile % (NC / 16);
+            int dx, dy, dz;
+            offset_of(o, dx, dy, dz);
+            const int r9 = (dz + 1) * 3 + (dy + 1);
+            const uint16_t* arow = xt + ((size_t)r9 * KC + cit * 16 + i) * D + kb;
+            const uint16_t* brow = gt + ((size_t)(dx + 1) * NC + cot * 16 + i) * D + kb;
+            for (int x0 = 0; x0 < D; x0 += 16) {
+                const s4 a = *reinterpret_cast<const s4*>(arow + x0);
+                const s4 b = *reinterpret_cast<const s4*>(brow + x0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // write this block's tiles of its row block's partial: D[i = ci][j = co]
+    const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    float* out = partials + blk * 27 * KC * NC;
+    const int i4 = (lane >> 4) * 4, j = lane & 15;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int tl = wave * TPW + t, tile = tile0 + tl;
+        if (tl >= TPB || tile >= NT) break;
+        const int o = tile / ((KC / 16) * (NC / 16));
+        const int cit = (tile / (NC / 16)) % (KC / 16), cot = tile % (NC / 16);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            out[((size_t)o * KC + cit * 16 + i4 + r) * NC + cot * 16 + j] = acc[t][r];
+    }
+}
+
 template <int KC, int NC>
 size_t conv_lds() { return (size_t)conv_ogl(KC, NC) * NC * KC * 2; }
 
@@ -616,10 +713,22 @@ hipError_t wgrad_launch(const uint16_t* X, const uint16_t* dY, float* partials, 
         attr = true;
     }
     const int nbx = (D * D + rows_per_block - 1) / rows_per_block;
-    const size_t lds = ((size_t)9 * KC * (D + 2 * dil) + (size_t)NC * D) * 2;
-    if (lds > 160 * 1024) return hipErrorInvalidValue;  // rows of a box too wide for LDS
-    hipLaunchKernelGGL((k_wgrad<KC, NC>), dim3(nbx, ns, wgrad_groups(KC, NC)), dim3(256), lds, st, X, dY, partials, D,
-                       dil, rows_per_block);
+    const size_t lds_al = ((size_t)9 * KC + (size_t)3 * NC) * D * 2;
+    if (D % 16 == 0 && lds_al <= 160 * 1024) {
+        // aligned-operand kernel (rows of whole 16-voxel groups)
+        static bool aattr = false;
+        if (!aattr) {
+            NCHK(set_lds_limit((const void*)k_wgrad_al<KC, NC>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+            aattr = true;
+        }
+        hipLaunchKernelGGL((k_wgrad_al<KC, NC>), dim3(nbx, ns, wgrad_groups(KC, NC)), dim3(256), lds_al, st, X, dY,
+                           partials, D, dil, rows_per_block);
+    } else {
+        const size_t lds = ((size_t)9 * KC * (D + 2 * dil) + (size_t)NC * D) * 2;
+        if (lds > 160 * 1024) return hipErrorInvalidValue;  // rows of a box too wide for LDS
+        hipLaunchKernelGGL((k_wgrad<KC, NC>), dim3(nbx, ns, wgrad_groups(KC, NC)), dim3(256), lds, st, X, dY, partials,
+                           D, dil, rows_per_block);
+    }
     NCHK(hipGetLastError());
     const int n = 27 * KC * NC;
     hipLaunchKernelGGL(k_reduce_partials, dim3((n + 255) / 256, (nbx * ns + RCH - 1) / RCH), dim3(256), 0, st,
