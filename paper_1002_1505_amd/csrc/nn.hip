@@ -620,20 +620,26 @@ __global__ void __launch_bounds__(256) k_wgrad_al(const uint16_t* __restrict__ X
         if (row >= D * D) break;
         const int y = row % D, z = row / D;
         __syncthreads();
-        // input rows (z + dil dz, y + dil dy): 8 channels of a voxel per
-        // 16-byte load, transposed into [r9][ci][x]
-        for (int idx = tid; idx < 9 * D * (KC / 8); idx += 256) {
-            const int c8 = idx % (KC / 8), xx = (idx / (KC / 8)) % D, r9 = idx / ((KC / 8) * D);
+        // input rows (z + dil dz, y + dil dy), transposed into [r9][ci][x]:
+        // a thread takes 8 channels of 4 consecutive voxels (four 16-byte
+        // loads) and writes each channel's 4 values as one 8-byte store
+        for (int idx = tid; idx < 9 * (D / 4) * (KC / 8); idx += 256) {
+            const int c8 = idx % (KC / 8), xx = 4 * ((idx / (KC / 8)) % (D / 4)), r9 = idx / ((KC / 8) * (D / 4));
             const int yy = y + dil * (r9 % 3 - 1), zz = z + dil * (r9 / 3 - 1);
-            uint4 val = {0, 0, 0, 0};
-            if (yy >= 0 && yy < D && zz >= 0 && zz < D)
-                val = *reinterpret_cast<const uint4*>(X + ((size_t)s * V + (size_t)(zz * D + yy) * D + xx) * KC + c8 * 8);
-            const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
-            uint16_t* d = xt + ((size_t)r9 * KC + c8 * 8) * D + xx;
+            uint4 val[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+            if (yy >= 0 && yy < D && zz >= 0 && zz < D) {
+                const uint4* src =
+                    reinterpret_cast<const uint4*>(X + ((size_t)s * V + (size_t)(zz * D + yy) * D + xx) * KC + c8 * 8);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) val[v] = src[v * (KC / 8)];
+            }
+            uint2* d = reinterpret_cast<uint2*>(xt + ((size_t)r9 * KC + c8 * 8) * D + xx);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                d[(2 * q) * D] = (uint16_t)(w4[q] & 0xffff);
-                d[(2 * q + 1) * D] = (uint16_t)(w4[q] >> 16);
+                const uint32_t w0 = (&val[0].x)[q], w1 = (&val[1].x)[q], w2 = (&val[2].x)[q], w3 = (&val[3].x)[q];
+                // channel 2q: the low halves; channel 2q + 1: the high halves
+                d[(2 * q) * (D / 4)] = make_uint2((w0 & 0xffffu) | (w1 << 16), (w2 & 0xffffu) | (w3 << 16));
+                d[(2 * q + 1) * (D / 4)] = make_uint2((w0 >> 16) | (w1 & 0xffff0000u), (w2 >> 16) | (w3 & 0xffff0000u));
             }
         }
         // output-gradient row, copy dx + 1 at x holding dY[x - dil dx]
