@@ -23,10 +23,12 @@ def bf16(a):
     return u.astype(np.uint32).view(np.float32)
 
 
-@pytest.mark.parametrize("width,depth", [(16, 3), (32, 4), (64, 3)])
-def test_forward_and_gradients_match_oracle(width, depth):
+@pytest.mark.parametrize("width,depth,D", [(16, 3, 16), (32, 4, 16), (64, 3, 16), (16, 4, 32)])
+def test_forward_and_gradients_match_oracle(width, depth, D):
     """Width 64 runs the channel-split convolution (four 16-channel output
-    slices per voxel block) and the weight gradient in four tile groups."""
+    slices per voxel block) and the weight gradient in four tile groups; the
+    32^3 box runs rows of two 16-voxel groups and the dilated layers' shifted
+    output-gradient copies with more of each row inside the box."""
     import paper_1002_1505_amd as P
 
     ctx = P.Context(0)
@@ -38,7 +40,7 @@ def test_forward_and_gradients_match_oracle(width, depth):
         params.append((bf16(rng.standard_normal((27, cin, cout)) * np.sqrt(2.0 / (27 * cin))),
                        (rng.standard_normal(cout) * 0.05).astype(np.float32)))
     net.set_params(params)
-    D, ns = 16, 2
+    ns = 2
     x = bf16(rng.standard_normal((ns, D, D, D, 16)))
     mask = rng.random((ns, D, D, D)) < 0.4
     target = rng.standard_normal((ns, D, D, D, 16)).astype(np.float32)
